@@ -1,0 +1,212 @@
+"""ctypes binding of librjsmc (include/rjsmc.h).  Argument marshalling only.
+
+Every computation runs in the HIP library; torch provides device memory and the
+current stream.  If the library is not built, every entry point raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "librjsmc.so")
+
+RJSMC_OK, RJSMC_E_INVALID, RJSMC_E_DEVICE, RJSMC_E_NOMEM, RJSMC_E_CAPACITY, RJSMC_E_UNSUPPORTED = range(6)
+RJSMC_F64, RJSMC_F32 = 0, 1
+LAYOUT_DECOUPLED, LAYOUT_MERGED = 0, 1
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+class RJSMCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("rjsmc status %d: %s" % (status, msg))
+        self.status = status
+
+
+class System(ctypes.Structure):
+    _fields_ = [("loop_radius_m", ctypes.c_double), ("height_m", ctypes.c_double),
+                ("current_a", ctypes.c_double),
+                ("n_freq", ctypes.c_int32), ("freq_hz", _dp),
+                ("n_hankel", ctypes.c_int32), ("hankel_b", _dp), ("hankel_w", _dp),
+                ("n_gate", ctypes.c_int32), ("gate_open_s", _dp), ("gate_close_s", _dp),
+                ("eps_mn", ctypes.c_double), ("eps_an", _dp),
+                ("kmax_cond", ctypes.c_int32), ("kmax_charg", ctypes.c_int32),
+                ("z_max_m", ctypes.c_double), ("fwd_precision", ctypes.c_int32)]
+
+
+class Particles(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("stride", ctypes.c_int64), ("n_per_sounding", ctypes.c_int64),
+                ("layout", ctypes.c_int32),
+                ("kappa", ctypes.c_void_p), ("lambda_", ctypes.c_void_p),
+                ("phi_b", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("z_cond", ctypes.c_void_p),
+                ("m", ctypes.c_void_p), ("z_charg", ctypes.c_void_p),
+                ("log10_tau", ctypes.c_void_p), ("c", ctypes.c_void_p)]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "rjsmc_create": (ctypes.c_int, [ctypes.POINTER(System), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "rjsmc_destroy": (None, [ctypes.c_void_p]),
+    "rjsmc_last_error": (ctypes.c_char_p, []),
+    "rjsmc_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rjsmc_time_kernel": (ctypes.c_int, [ctypes.c_void_p, _dp]),
+    "rjsmc_build_time_kernel": (ctypes.c_int, [_dp, ctypes.c_int32, _dp, _dp, ctypes.c_int32, _dp]),
+    "rjsmc_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p,
+                                     ctypes.c_void_p]),
+    "rjsmc_loglik": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p]),
+    "rjsmc_loglik_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p]),
+}
+
+
+def lib():
+    """The loaded librjsmc.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librjsmc.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != RJSMC_OK:
+        raise RJSMCError(status, lib().rjsmc_last_error().decode())
+
+
+def _as_dp(a):
+    return a.ctypes.data_as(_dp)
+
+
+def build_time_kernel(freq_hz, gate_open_s, gate_close_s):
+    """Host-side frequency-to-time matrix of the library, [n_gate, n_freq]."""
+    f = np.ascontiguousarray(freq_hz, dtype=np.float64)
+    lo = np.ascontiguousarray(gate_open_s, dtype=np.float64)
+    hi = np.ascontiguousarray(gate_close_s, dtype=np.float64)
+    K = np.zeros((len(lo), len(f)))
+    _check(lib().rjsmc_build_time_kernel(_as_dp(f), len(f), _as_dp(lo), _as_dp(hi), len(lo), _as_dp(K)))
+    return K
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+_FLOAT_KEYS = ("phi_b", "phi", "z_cond", "m", "z_charg", "log10_tau", "c")
+
+
+def particles_to_device(p, device="cuda"):
+    """Copy a numpy SoA population (see workloads) to device tensors."""
+    import torch
+    out = {"layout": int(p["layout"]), "n_per_sounding": int(p.get("n_per_sounding", 0))}
+    out["kappa"] = torch.as_tensor(np.ascontiguousarray(p["kappa"], dtype=np.int32), device=device)
+    out["lambda_"] = torch.as_tensor(np.ascontiguousarray(p["lambda_"], dtype=np.int32), device=device)
+    for k in _FLOAT_KEYS:
+        out[k] = torch.as_tensor(np.ascontiguousarray(p[k], dtype=np.float64), device=device)
+    return out
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def particles_struct(p, n=None, stride=None):
+    """Particles struct viewing device tensors of dict p (rows [R, stride])."""
+    n_all = int(p["kappa"].shape[0])
+    n = n_all if n is None else n
+    stride = int(p["phi_b"].shape[-1]) if stride is None else stride
+    s = Particles()
+    s.n, s.stride, s.n_per_sounding, s.layout = n, stride, int(p.get("n_per_sounding", 0)), int(p["layout"])
+    s.kappa, s.lambda_ = _ptr(p["kappa"]), _ptr(p["lambda_"])
+    for k in _FLOAT_KEYS:
+        setattr(s, k, _ptr(p[k]))
+    return s
+
+
+class Context:
+    """A librjsmc context for one acquisition system on one device."""
+
+    def __init__(self, system, device=0, precision="f64"):
+        self._ptr = ctypes.c_void_p(0)
+        keep = {k: np.ascontiguousarray(system[k], dtype=np.float64)
+                for k in ("freq_hz", "hankel_b", "hankel_w", "gate_open_s", "gate_close_s", "eps_an")}
+        s = System()
+        s.loop_radius_m = system["loop_radius_m"]
+        s.height_m = system["height_m"]
+        s.current_a = system["current_a"]
+        s.n_freq, s.freq_hz = len(keep["freq_hz"]), _as_dp(keep["freq_hz"])
+        s.n_hankel, s.hankel_b, s.hankel_w = len(keep["hankel_b"]), _as_dp(keep["hankel_b"]), _as_dp(keep["hankel_w"])
+        s.n_gate, s.gate_open_s, s.gate_close_s = len(keep["gate_open_s"]), _as_dp(keep["gate_open_s"]), _as_dp(keep["gate_close_s"])
+        s.eps_mn, s.eps_an = system["eps_mn"], _as_dp(keep["eps_an"])
+        s.kmax_cond, s.kmax_charg = system["kmax_cond"], system["kmax_charg"]
+        s.z_max_m = system["z_max_m"]
+        s.fwd_precision = {"f64": RJSMC_F64, "f32": RJSMC_F32}[precision]
+        self.n_gate = s.n_gate
+        self.n_freq = s.n_freq
+        self.kmax_cond, self.kmax_charg = s.kmax_cond, s.kmax_charg
+        self.precision = precision
+        self.device = device
+        _check(lib().rjsmc_create(ctypes.byref(s), device, ctypes.byref(self._ptr)))
+
+    def close(self):
+        if self._ptr:
+            lib().rjsmc_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, stream=None):
+        _check(lib().rjsmc_check(self._ptr, _stream_handle(stream)))
+
+    def time_kernel(self):
+        K = np.zeros((self.n_gate, self.n_freq))
+        _check(lib().rjsmc_time_kernel(self._ptr, _as_dp(K)))
+        return K
+
+    # -- hot calls ---------------------------------------------------------------------
+    def forward(self, p, out=None, stream=None):
+        import torch
+        n = int(p["kappa"].shape[0])
+        if out is None:
+            out = torch.empty((n, self.n_gate), dtype=torch.float64, device=p["kappa"].device)
+        ps = particles_struct(p)
+        _check(lib().rjsmc_forward(self._ptr, ctypes.byref(ps), _ptr(out), _stream_handle(stream)))
+        return out
+
+    def loglik(self, p, y_obs, out=None, stream=None):
+        import torch
+        n = int(p["kappa"].shape[0])
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=p["kappa"].device)
+        ps = particles_struct(p)
+        _check(lib().rjsmc_loglik(self._ptr, ctypes.byref(ps), _ptr(y_obs), _ptr(out), _stream_handle(stream)))
+        return out
+
+    def loglik_grad(self, p, y_obs, stream=None):
+        import torch
+        n = int(p["kappa"].shape[0])
+        ll = torch.empty(n, dtype=torch.float64, device=p["kappa"].device)
+        g = {"layout": p["layout"], "kappa": p["kappa"], "lambda_": p["lambda_"]}
+        for k in _FLOAT_KEYS:
+            g[k] = torch.zeros_like(p[k])
+        ps = particles_struct(p)
+        gs = particles_struct(g)
+        _check(lib().rjsmc_loglik_grad(self._ptr, ctypes.byref(ps), _ptr(y_obs), _ptr(ll), ctypes.byref(gs),
+                                       _stream_handle(stream)))
+        return ll, {k: g[k] for k in _FLOAT_KEYS}

@@ -1,0 +1,215 @@
+// Fused forward model + Gaussian log-likelihood for gfx950.
+//
+// One wavefront evaluates one particle.  Its 64 lanes tile the (frequency, filter
+// abscissa) plane as 8 frequency groups x 8 abscissa groups: lane (g_w, g_l) handles
+// frequencies g_w + 8q and abscissae g_l + 8s, so 40 x 120 pairs give exactly 75 per
+// lane and the layer loop is uniform across the wave (one particle, one layer count).
+// Per pair the lane runs the TE reflection recursion in registers (the layer loop is
+// unrolled to a compile-time cap); partial Hankel sums of Im r_TE are reduced over the
+// 8 abscissa groups with xor shuffles, the 40 values go through LDS, and 20 lanes apply
+// the frequency-to-time matrix and the likelihood terms.  The kernel is bound by FP64
+// (or FP32) vector ALU work: ~24,000 layer steps per particle for 5 layers.
+#include <hip/hip_runtime.h>
+
+#include "cplx.h"
+#include "merge.h"
+#include "rjsmc_internal.h"
+
+namespace rjsmc {
+
+constexpr int kWavesPerBlock = 4;
+constexpr double kMu0 = 1.25663706143591729539e-06;   // 4 pi 1e-7
+constexpr double kTwoPi = 6.28318530717958647692;
+
+// TE reflection coefficient at the surface for wavenumber lam, layer wavenumbers
+// k2[l] = i w mu0 sigma_hat_l and thicknesses thk[l] (layers 0..L-1, the last one
+// infinite).  Bottom-up generalized reflection recursion with the interface terms
+//   R_{l,l+1} = (k2_l - k2_{l+1}) / (u_l + u_{l+1})^2,   R_air = -k2_0 / (lam + u_0)^2,
+//   r_l = (R_{l,l+1} + r_{l+1} E_{l+1}) / (1 + R_{l,l+1} r_{l+1} E_{l+1}),
+//   E_l = exp(-2 u_l h_l),  u_l = sqrt(lam^2 + k2_l), Re u_l > 0,
+// which never forms lam - u or u_l - u_{l+1} by subtraction.
+template <int LMAX, typename T>
+__device__ __forceinline__ cplx<T> reflection(T lam, const cplx<T> (&k2)[LMAX], const T (&thk)[LMAX],
+                                              int L) {
+  const T lam2 = lam * lam;
+  cplx<T> r = {T(0), T(0)};
+  cplx<T> u_below = {T(0), T(0)};
+#pragma unroll
+  for (int l = LMAX - 1; l >= 0; --l) {
+    if (l < L) {
+      const cplx<T> u = csqrt(cplx<T>{lam2 + k2[l].re, k2[l].im});
+      if (l < L - 1) {
+        const cplx<T> R = cdiv(k2[l] - k2[(l + 1 < LMAX) ? l + 1 : l], csq(u + u_below));
+        if (l < L - 2) {
+          const cplx<T> E = cexp(cplx<T>{T(-2) * thk[(l + 1 < LMAX) ? l + 1 : l] * u_below.re,
+                                         T(-2) * thk[(l + 1 < LMAX) ? l + 1 : l] * u_below.im});
+          const cplx<T> re = r * E;
+          r = cdiv(R + re, cplx<T>{T(1), T(0)} + R * re);
+        } else {
+          r = R;
+        }
+      }
+      u_below = u;
+    }
+  }
+  const cplx<T> R0 = cdiv(cplx<T>{-k2[0].re, -k2[0].im}, csq(cplx<T>{lam + u_below.re, u_below.im}));
+  if (L == 1) return R0;
+  const cplx<T> E0 = cexp(cplx<T>{T(-2) * thk[0] * u_below.re, T(-2) * thk[0] * u_below.im});
+  const cplx<T> re = r * E0;
+  return cdiv(R0 + re, cplx<T>{T(1), T(0)} + R0 * re);
+}
+
+template <typename T>
+__device__ __forceinline__ T to(double x) {
+  return static_cast<T>(x);
+}
+
+// resp != nullptr: write gate responses.  ll != nullptr: write the log-likelihood.
+template <int LMAX, typename T>
+__global__ __launch_bounds__(kWave * kWavesPerBlock) void forward_kernel(DevSystem s, DevParticles p, int kc,
+                                                                          int km, double *resp,
+                                                                          const double *y_obs, double *ll) {
+  __shared__ double s_lam[kMaxHankel];
+  __shared__ double s_ck[kMaxHankel];
+  __shared__ double s_omega[kMaxFreq];
+  __shared__ double s_K[kMaxGate * kMaxFreq];
+  __shared__ double s_eps2[kMaxGate];
+  __shared__ LayerStack s_stack[kWavesPerBlock];
+  __shared__ double s_imh[kWavesPerBlock][kMaxFreq];
+
+  const int nf = s.n_freq, ng = s.n_gate, nhp = s.n_hankel_pad;
+  for (int t = threadIdx.x; t < nhp; t += blockDim.x) {
+    s_lam[t] = s.lam[t];
+    s_ck[t] = s.ck[t];
+  }
+  for (int t = threadIdx.x; t < nf; t += blockDim.x) s_omega[t] = s.omega[t];
+  for (int t = threadIdx.x; t < nf * ng; t += blockDim.x) s_K[t] = s.K[t];
+  for (int t = threadIdx.x; t < ng; t += blockDim.x) s_eps2[t] = s.eps_an2[t];
+
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  const bool valid = i < p.n;
+  LayerStack *st = &s_stack[wave];
+  __syncthreads();
+  const int L = merge_particle(p, i, valid, kc, km, LMAX, st, s.flags);
+
+  if (L > 0) {
+    // per-particle Cole-Cole constants: (i w tau)^c = (w tau)^c (cos(pi c/2) + i sin(pi c/2))
+    const double c = p.c[i];
+    const double log_tau = p.log10_tau[i] * 2.302585092994045684;
+    double spc, cpc;
+    sincospi(0.5 * c, &spc, &cpc);
+
+    T thk[LMAX];
+    T sig[LMAX], mm[LMAX];
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) {
+      thk[l] = to<T>(l < L - 1 ? st->top[l + 1] - st->top[l] : 0.0);
+      sig[l] = to<T>(l < L ? st->sig[l] : 0.0);
+      mm[l] = to<T>(l < L ? st->m[l] : 0.0);
+    }
+
+    const int gl = lane & 7, gw = lane >> 3;
+    const int nhg = nhp >> 3;
+    const int nq = (nf + 7) >> 3;
+#pragma unroll 1
+    for (int q = 0; q < nq; ++q) {
+      const int jf = gw + 8 * q;
+      double acc = 0.0;
+      if (jf < nf) {
+        const double w = s_omega[jf];
+        // q_cc = 1 / (1 + (i w tau)^c)
+        const double pw = exp(c * (log(w) + log_tau));
+        const cplx<double> qcc = crcp(cplx<double>{1.0 + pw * cpc, pw * spc});
+        const T wmu = to<T>(w * kMu0);
+        const cplx<T> qt = {to<T>(qcc.re), to<T>(qcc.im)};
+        cplx<T> k2[LMAX];
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l) {
+          // sigma_hat = sigma_inf (1 - m q); k2 = i w mu0 sigma_hat
+          const cplx<T> sh = {sig[l] * (T(1) - mm[l] * qt.re), sig[l] * (-(mm[l] * qt.im))};
+          k2[l] = cplx<T>{-(wmu * sh.im), wmu * sh.re};
+        }
+#pragma unroll 1
+        for (int sidx = 0; sidx < nhg; ++sidx) {
+          const int k = gl + 8 * sidx;
+          const cplx<T> r = reflection<LMAX, T>(to<T>(s_lam[k]), k2, thk, L);
+          acc += s_ck[k] * static_cast<double>(r.im);
+        }
+        // reduce over the 8 abscissa groups (lane bits 0..2); all 8 lanes of a group
+        // share jf, so a group is either wholly active or wholly idle here
+        acc += __shfl_xor(acc, 1);
+        acc += __shfl_xor(acc, 2);
+        acc += __shfl_xor(acc, 4);
+        if (gl == 0) s_imh[wave][jf] = acc;
+      }
+    }
+  }
+  __syncthreads();
+  if (L > 0) {
+    double term = 0.0;
+    if (lane < ng) {
+      double y = 0.0;
+      for (int j = 0; j < nf; ++j) y += s_K[lane * nf + j] * s_imh[wave][j];
+      if (resp) resp[i * ng + lane] = y;
+      if (ll) {
+        const int64_t snd = p.n_per_sounding > 0 ? i / p.n_per_sounding : 0;
+        const double d = y_obs[snd * ng + lane];
+        const double e = s.eps_mn * y;
+        const double s2 = s_eps2[lane] + e * e;
+        const double r = d - y;
+        term = r * r / s2 + log(kTwoPi * s2);
+      }
+    }
+    if (ll) {
+      term += __shfl_xor(term, 1);
+      term += __shfl_xor(term, 2);
+      term += __shfl_xor(term, 4);
+      term += __shfl_xor(term, 8);
+      term += __shfl_xor(term, 16);
+      term += __shfl_xor(term, 32);
+      if (lane == 0) {
+        const double v = -0.5 * term;
+        ll[i] = (v == v && v != HUGE_VAL) ? v : -HUGE_VAL;   // NaN or +inf -> -inf
+      }
+    }
+  } else if (valid) {
+    // invalid particle: NaN responses, -inf log-likelihood
+    if (resp && lane < ng) resp[i * ng + lane] = __builtin_nan("");
+    if (ll && lane == 0) ll[i] = -HUGE_VAL;
+  }
+}
+
+template <int LMAX, typename T>
+static hipError_t launch_t(const DevSystem &s, const DevParticles &p, int kc, int km, double *resp,
+                           const double *y_obs, double *ll, hipStream_t stream) {
+  const int64_t blocks = (p.n + kWavesPerBlock - 1) / kWavesPerBlock;
+  hipLaunchKernelGGL((forward_kernel<LMAX, T>), dim3((unsigned)blocks), dim3(kWave * kWavesPerBlock), 0,
+                     stream, s, p, kc, km, resp, y_obs, ll);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_prec(int lcap, const DevSystem &s, const DevParticles &p, int kc, int km,
+                              double *resp, const double *y_obs, double *ll, hipStream_t stream) {
+  if (lcap <= 4) return launch_t<4, T>(s, p, kc, km, resp, y_obs, ll, stream);
+  if (lcap <= 8) return launch_t<8, T>(s, p, kc, km, resp, y_obs, ll, stream);
+  if (lcap <= 12) return launch_t<12, T>(s, p, kc, km, resp, y_obs, ll, stream);
+  return launch_t<16, T>(s, p, kc, km, resp, y_obs, ll, stream);
+}
+
+// Smallest compiled layer cap that holds every particle the context admits.
+int layer_cap(const DevParticles &p, int kc, int km) {
+  return p.layout == RJSMC_LAYOUT_DECOUPLED ? kc + km + 1 : kc + 1;
+}
+
+hipError_t launch_forward(const DevSystem &s, const DevParticles &p, int kc, int km, int precision,
+                          double *resp, const double *y_obs, double *ll, hipStream_t stream) {
+  if ((p.n + kWavesPerBlock - 1) / kWavesPerBlock > 0x7fffffff) return hipErrorInvalidValue;
+  const int lcap = layer_cap(p, kc, km);
+  if (precision == RJSMC_F32) return launch_prec<float>(lcap, s, p, kc, km, resp, y_obs, ll, stream);
+  return launch_prec<double>(lcap, s, p, kc, km, resp, y_obs, ll, stream);
+}
+
+}  // namespace rjsmc

@@ -1,0 +1,70 @@
+// Internal declarations shared by the host runtime and the HIP kernels of librjsmc.
+// Not part of the public ABI (include/rjsmc.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "rjsmc.h"
+
+namespace rjsmc {
+
+// Compile-time limits of the kernels.
+constexpr int kMaxFreq = 64;      // frequencies
+constexpr int kMaxHankel = 256;   // filter abscissae
+constexpr int kMaxGate = 32;      // gates
+constexpr int kMaxLayers = 16;    // merged layers per particle
+constexpr int kWave = 64;
+
+// Device flag bits raised by kernels, reported by rjsmc_check.
+constexpr int kFlagCapacity = 1;
+constexpr int kFlagUnsorted = 2;
+
+// Tables of one acquisition system, resident in device memory.
+struct DevSystem {
+  int n_freq, n_hankel, n_hankel_pad, n_gate;
+  double eps_mn;
+  double *omega;      // [n_freq] angular frequency
+  double *lam;        // [n_hankel_pad] filter wavenumbers b_k / a (padding: 1.0)
+  double *ck;         // [n_hankel_pad] (I/2) w_k lam_k exp(-2 lam_k h)  (padding: 0)
+  double *K;          // [n_gate][n_freq] frequency-to-time matrix
+  double *eps_an2;    // [n_gate] eps_an^2
+  int *flags;         // device flag word
+};
+
+// Particle pointers and sizes as the kernels see them.
+struct DevParticles {
+  int64_t n, stride, n_per_sounding;
+  int layout;
+  const int32_t *kappa, *lambda;
+  const double *phi_b, *phi, *z_cond, *m, *z_charg, *log10_tau, *c;
+};
+
+struct DevGrad {
+  double *phi_b, *phi, *z_cond, *m, *z_charg, *log10_tau, *c;
+};
+
+// Kernel launchers (forward.hip / adjoint.hip).  Return the launch's hipError_t.
+hipError_t launch_forward(const DevSystem &s, const DevParticles &p, int kmax_cond, int kmax_charg,
+                          int precision, double *resp, const double *y_obs, double *ll,
+                          hipStream_t stream);
+hipError_t launch_loglik_grad(const DevSystem &s, const DevParticles &p, int kmax_cond,
+                              int kmax_charg, const double *y_obs, double *ll, const DevGrad &g,
+                              hipStream_t stream);
+
+// Host-side construction of the frequency-to-time matrix (host.cpp).
+void build_time_kernel(const double *freq_hz, int n_freq, const double *t_open,
+                       const double *t_close, int n_gate, double *K_out);
+
+}  // namespace rjsmc
+
+struct rjsmc_ctx {
+  int device;
+  int kmax_cond, kmax_charg;
+  int precision;
+  double z_max;
+  rjsmc::DevSystem dev;
+  double *K_host;   // [n_gate][n_freq]
+};

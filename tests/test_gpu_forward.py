@@ -1,0 +1,207 @@
+"""GPU parity of the fused forward model + log-likelihood against the oracle.
+
+Tolerances (floating point; the forward model has no integer decisions):
+  FP64: |dy_g| <= 1e-9 max(|y_g|, s_g) with s_g the noise standard deviation at the
+        oracle response, and |dll| <= 1e-9 max(|ll|, 1).
+  FP32 recursion (Hankel sum, time transform and likelihood in FP64):
+        |dy_g| <= 1e-4 max(|y_g|, s_g); |dll| <= 1e-3 for particles within 50 nats of
+        the batch's best log-likelihood, else |dll| <= 1e-6 |ll| (1e-3 absolute is below
+        FP32 resolution for |ll| ~ 1e6).
+"""
+import numpy as np
+import pytest
+
+from paper_2109_00661_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2109_00661_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx64(B, system):
+    return B.Context(system, precision="f64")
+
+
+@pytest.fixture(scope="module")
+def ctx64_wide(B):
+    return B.Context(W.system(kmax_cond=7, kmax_charg=7), precision="f64")
+
+
+@pytest.fixture(scope="module")
+def ctx32(B, system):
+    return B.Context(system, precision="f32")
+
+
+def _noise_sd(system, y):
+    return np.sqrt(system["eps_an"] ** 2 + (system["eps_mn"] * y) ** 2)
+
+
+def _oracle(system, K, p, d, idx=None):
+    from oracle import em
+    y = em.forward(p, system, K, idx)
+    s2 = em.noise_variance(y, system["eps_an"][None, :], system["eps_mn"])
+    ll = -0.5 * np.sum((d[None, :] - y) ** 2 / s2 + np.log(2 * np.pi * s2), axis=1)
+    return y, ll
+
+
+def _run(B, ctx, p, d):
+    dp = B.particles_to_device(p)
+    y = ctx.forward(dp).cpu().numpy()
+    ll = ctx.loglik(dp, torch.as_tensor(d, device="cuda")).cpu().numpy()
+    ctx.check()
+    return y, ll
+
+
+def _assert_f64(system, y, ll, y_o, ll_o):
+    s = _noise_sd(system, y_o)
+    err_y = np.abs(y - y_o) / np.maximum(np.abs(y_o), s)
+    assert err_y.max() <= 1e-9, err_y.max()
+    err_ll = np.abs(ll - ll_o) / np.maximum(np.abs(ll_o), 1.0)
+    assert err_ll.max() <= 1e-9, err_ll.max()
+
+
+def test_merged_five_layer_fp64(B, ctx64, system, K_oracle, truth_data):
+    p = W.merged_population(99, 5, seed=2, kc=4)        # ragged tail over 4-particle blocks
+    y, ll = _run(B, ctx64, p, truth_data)
+    y_o, ll_o = _oracle(system, K_oracle, p, truth_data)
+    _assert_f64(system, y, ll, y_o, ll_o)
+
+
+def test_decoupled_uneven_fp64(B, ctx64_wide, system, K_oracle, truth_data):
+    p = W.decoupled_population(67, 7, 7, seed=3, min_sep=1.0)
+    y, ll = _run(B, ctx64_wide, p, truth_data)
+    y_o, ll_o = _oracle(system, K_oracle, p, truth_data)
+    _assert_f64(system, y, ll, y_o, ll_o)
+
+
+def test_truth_model_and_data(B, ctx64, system, K_oracle, truth_data):
+    p = W.truth_three_layer()
+    y, ll = _run(B, ctx64, p, truth_data)
+    y_o, ll_o = _oracle(system, K_oracle, p, truth_data)
+    _assert_f64(system, y, ll, y_o, ll_o)
+    assert y.min() < 0                       # IP sign reversal at late time
+
+
+def test_fp32_bounds(B, ctx32, system, K_oracle, truth_data):
+    p = W.merged_population(64, 5, seed=4, kc=4)
+    p = _with_near_truth(p)
+    y, ll = _run(B, ctx32, p, truth_data)
+    y_o, ll_o = _oracle(system, K_oracle, p, truth_data)
+    s = _noise_sd(system, y_o)
+    err_y = np.abs(y - y_o) / np.maximum(np.abs(y_o), s)
+    assert err_y.max() <= 1e-4, err_y.max()
+    near = ll_o >= ll_o.max() - 50.0
+    assert near.sum() >= 1
+    assert np.abs(ll - ll_o)[near].max() <= 1e-3
+    assert (np.abs(ll - ll_o)[~near] <= 1e-6 * np.abs(ll_o[~near])).all()
+
+
+def _with_near_truth(p):
+    """Put the merged equivalent of the three-layer truth (and small perturbations of
+    it) into the first particles so that some log-likelihoods are near the mode."""
+    rng = np.random.default_rng(9)
+    for i in range(4):
+        p["kappa"][i] = 2
+        p["phi_b"][i] = -2.0 + 0.01 * rng.standard_normal()
+        p["phi"][:2, i] = [-1.0, -3.0]
+        p["z_cond"][:2, i] = [20.0 + 0.1 * rng.standard_normal(), 40.0]
+        p["m"][:3, i] = [0.0, 0.4, 0.0]
+        p["log10_tau"][i] = -3.0
+        p["c"][i] = 0.5
+    return p
+
+
+def test_full_size_sampled(B, ctx64, system, K_oracle, truth_data):
+    """65,536 five-layer particles in the benchmark's launch; 48 sampled particles are
+    checked against the oracle, every particle for finiteness."""
+    p = W.merged_population(65536, 5, seed=2, kc=4)
+    y, ll = _run(B, ctx64, p, truth_data)
+    assert np.isfinite(y).all() and np.isfinite(ll).all()
+    idx = np.random.default_rng(0).choice(65536, 48, replace=False)
+    y_o, ll_o = _oracle(system, K_oracle, p, truth_data, idx)
+    _assert_f64(system, y[idx], ll[idx], y_o, ll_o)
+
+
+# ------------------------------------------------------------------------- edge cases
+def test_single_particle_halfspace_and_identical_layers(B, ctx64, system, K_oracle, truth_data):
+    p = W.merged_population(3, 5, seed=5, kc=4)
+    p["kappa"][0] = 0                                   # half-space
+    p["kappa"][1] = 4                                   # five identical layers
+    p["phi"][:, 1] = p["phi_b"][1]
+    p["m"][:, 1] = p["m"][0, 1]
+    p["kappa"][2] = 0
+    p["phi_b"][2] = p["phi_b"][1]
+    p["m"][0, 2] = p["m"][0, 1]
+    p["log10_tau"][2], p["c"][2] = p["log10_tau"][1], p["c"][1]
+    y, ll = _run(B, ctx64, p, truth_data)
+    y_o, ll_o = _oracle(system, K_oracle, p, truth_data)
+    _assert_f64(system, y, ll, y_o, ll_o)
+    assert np.array_equal(y[1], y[2])                   # R_{l,l+1} = 0 exactly
+    one = W.take(p, [0])
+    y1, ll1 = _run(B, ctx64, one, truth_data)
+    assert np.array_equal(y1[0], y[0])
+
+
+def test_zero_thickness_and_conductive_reduction(B, ctx64, system, K_oracle, truth_data):
+    p = W.decoupled_population(4, 4, 3, seed=6, kappa=np.array([2, 2, 3, 1]), lam=np.array([2, 0, 1, 3]))
+    p["z_charg"][0, 0] = p["z_cond"][0, 0]             # coincident interfaces
+    p["z_charg"][1, 0] = max(p["z_charg"][1, 0], p["z_cond"][0, 0])
+    p["m"][:, 1] = 0.0
+    p["z_charg"][:, 3] = [10.0, 10.0, 50.0]            # coincident within a partition
+    p["z_charg"][0, 2] = 0.0                           # interface at the surface
+    y, ll = _run(B, ctx64, p, truth_data)
+    y_o, ll_o = _oracle(system, K_oracle, p, truth_data)
+    _assert_f64(system, y, ll, y_o, ll_o)
+
+
+def test_invalid_particles_flagged(B, ctx64, system, truth_data):
+    p = W.merged_population(6, 5, seed=7, kc=4)
+    p["z_cond"][1, 2], p["z_cond"][2, 2] = 100.0, 50.0   # unsorted
+    dp = B.particles_to_device(p)
+    y = ctx64.forward(dp).cpu().numpy()
+    ll = ctx64.loglik(dp, torch.as_tensor(truth_data, device="cuda")).cpu().numpy()
+    with pytest.raises(B.RJSMCError) as e:
+        ctx64.check()
+    assert e.value.status == B.RJSMC_E_INVALID
+    assert np.isnan(y[2]).all() and ll[2] == -np.inf
+    assert np.isfinite(y[[0, 1, 3, 4, 5]]).all()
+    ctx64.check()                                        # flags were cleared
+    p["kappa"][4] = 7                                    # beyond the context's capacity
+    dp = B.particles_to_device(p)
+    ll = ctx64.loglik(dp, torch.as_tensor(truth_data, device="cuda")).cpu().numpy()
+    with pytest.raises(B.RJSMCError) as e:
+        ctx64.check()
+    assert e.value.status == B.RJSMC_E_CAPACITY
+    assert ll[4] == -np.inf
+
+
+def test_soundings_select_their_data(B, ctx64, system, K_oracle, truth_data):
+    p = W.merged_population(8, 5, seed=8, kc=4)
+    p["n_per_sounding"] = 4
+    d2 = np.stack([truth_data, 0.5 * truth_data])
+    dp = B.particles_to_device(p)
+    ll = ctx64.loglik(dp, torch.as_tensor(d2, device="cuda")).cpu().numpy()
+    _, ll_a = _oracle(system, K_oracle, p, d2[0], range(4))
+    _, ll_b = _oracle(system, K_oracle, p, d2[1], range(4, 8))
+    np.testing.assert_allclose(ll, np.concatenate([ll_a, ll_b]), rtol=1e-9)
+
+
+def test_host_rejects_before_launch(B, ctx64, truth_data):
+    p = W.merged_population(4, 5, seed=8, kc=4)
+    dp = B.particles_to_device(p)
+    s = B.particles_struct(dp)
+    s.n = 0
+    import ctypes
+    out = torch.empty(4, dtype=torch.float64, device="cuda")
+    st = B.lib().rjsmc_loglik(ctx64._ptr, ctypes.byref(s), B._ptr(torch.as_tensor(truth_data, device="cuda")),
+                              B._ptr(out), None)
+    assert st == B.RJSMC_E_INVALID
