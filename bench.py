@@ -35,11 +35,14 @@ def nominal_flop_per_eval(n_layers, n_freq=40, n_hankel=120):
     return n_freq * n_hankel * n_layers * FLOP_PER_LAYER_STEP
 
 
-def synth_data(ctx, system, torch):
+def synth_data(torch):
     """Synthetic sounding: the three-layer truth through the forward model plus noise
     with the standard deviation of the noise model at the response."""
     from paper_2109_00661_amd import binding as B
-    y = ctx.forward(B.particles_to_device(W.truth_three_layer())).cpu().numpy()[0]
+    system = W.system(kmax_cond=2, kmax_charg=0)
+    ctx = B.Context(system, precision="f64")
+    y = ctx.forward(B.particles_to_device(W.truth_three_layer_merged())).cpu().numpy()[0]
+    ctx.check()
     s = np.sqrt(system["eps_an"] ** 2 + (system["eps_mn"] * y) ** 2)
     return torch.as_tensor(y + s * W.data_noise(1), device="cuda")
 
@@ -97,7 +100,7 @@ def main():
 
     system = W.system(kmax_cond=N_LAYERS - 1, kmax_charg=0)
     ctx = B.Context(system, precision="f64")
-    d = synth_data(ctx, system, torch)
+    d = synth_data(torch)
     p = B.particles_to_device(W.merged_population(N_PARTICLES, N_LAYERS, seed=2, kc=N_LAYERS - 1))
     ll = torch.empty(N_PARTICLES, dtype=torch.float64, device="cuda")
 

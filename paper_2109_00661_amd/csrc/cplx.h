@@ -45,6 +45,49 @@ __device__ __forceinline__ cplx<T> crcp(cplx<T> b) {
   return {b.re * inv, -b.im * inv};
 }
 
+// 1/sqrt(x) and sqrt(x) for x > 0 (finite, normal): hardware estimate refined by two
+// Goldschmidt steps (relative error a few ulp).
+__device__ __forceinline__ void rsqrt_sqrt(double x, double &rs, double &sq) {
+  double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  sq = g;
+  rs = 2.0 * h;
+}
+__device__ __forceinline__ void rsqrt_sqrt(float x, float &rs, float &sq) {
+  rs = __builtin_amdgcn_rsqf(x);
+  sq = x * rs;
+}
+
+// 1/x for finite normal x != 0: hardware estimate and two Newton steps.
+__device__ __forceinline__ double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Principal square root for Im z != 0 or Re z > 0 (z never on the closed negative
+// real axis or at 0): both sqrt and its reciprocal from one refined estimate.
+template <typename T>
+__device__ __forceinline__ cplx<T> csqrt_fast(cplx<T> z) {
+  T rs, mag;
+  rsqrt_sqrt(z.re * z.re + z.im * z.im, rs, mag);
+  const T w = T(0.5) * (mag + (z.re >= T(0) ? z.re : -z.re));
+  T rt, t;
+  rsqrt_sqrt(w, rt, t);
+  const T o = T(0.5) * z.im * rt;
+  if (z.re >= T(0)) return {t, o};
+  return {o >= T(0) ? o : -o, z.im >= T(0) ? t : -t};
+}
+
 // Principal square root (Re >= 0), branch cut on the negative real axis.
 __device__ __forceinline__ cplx<double> csqrt(cplx<double> z) {
   const double mag = sqrt(z.re * z.re + z.im * z.im);

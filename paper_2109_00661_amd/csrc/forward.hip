@@ -21,42 +21,73 @@ constexpr int kWavesPerBlock = 4;
 constexpr double kMu0 = 1.25663706143591729539e-06;   // 4 pi 1e-7
 constexpr double kTwoPi = 6.28318530717958647692;
 
-// TE reflection coefficient at the surface for wavenumber lam, layer wavenumbers
-// k2[l] = i w mu0 sigma_hat_l and thicknesses thk[l] (layers 0..L-1, the last one
-// infinite).  Bottom-up generalized reflection recursion with the interface terms
+// Imaginary part of the TE reflection coefficient at the surface for wavenumber lam,
+// layer wavenumbers k2[l] = i w mu0 sigma_hat_l and thicknesses thk[l] (layers
+// 0..L-1, the last one infinite).  The generalized reflection recursion
 //   R_{l,l+1} = (k2_l - k2_{l+1}) / (u_l + u_{l+1})^2,   R_air = -k2_0 / (lam + u_0)^2,
 //   r_l = (R_{l,l+1} + r_{l+1} E_{l+1}) / (1 + R_{l,l+1} r_{l+1} E_{l+1}),
 //   E_l = exp(-2 u_l h_l),  u_l = sqrt(lam^2 + k2_l), Re u_l > 0,
-// which never forms lam - u or u_l - u_{l+1} by subtraction.
-template <int LMAX, typename T>
-__device__ __forceinline__ cplx<T> reflection(T lam, const cplx<T> (&k2)[LMAX], const T (&thk)[LMAX],
-                                              int L) {
+// is carried in projective form: with R = A/B (A = k2_l - k2_{l+1}, B = (u_l+u_{l+1})^2)
+// and r = N/D,
+//   N_l = A D_{l+1} + B N_{l+1} E_{l+1},   D_l = B D_{l+1} + A N_{l+1} E_{l+1},
+// so the whole stack needs one real division (Im r = Im(N conj D) / |D|^2) instead of
+// two complex divisions per layer.  No lam - u or u_l - u_{l+1} is ever formed.
+// FP64 keeps N, D unscaled (|D| stays within 1e-140 .. 1e30 for <= 16 layers of this
+// system); FP32 rescales by a power of two every layer.
+template <typename T>
+__device__ __forceinline__ void rescale(cplx<T> &N, cplx<T> &D) {}
+template <>
+__device__ __forceinline__ void rescale<float>(cplx<float> &N, cplx<float> &D) {
+  const float m = fabsf(D.re) + fabsf(D.im);
+  const int e = -__builtin_amdgcn_frexp_expf(m);
+  N = {ldexpf(N.re, e), ldexpf(N.im, e)};
+  D = {ldexpf(D.re, e), ldexpf(D.im, e)};
+}
+
+// k2[l] (layers 0..L-1) and thk[l] (l < L-1) are read from LDS: the layer loop is a
+// runtime loop whose carried state is N, D, u_{l+1} and k2_{l+1}.
+template <typename T>
+__device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const T *thk, int L) {
   const T lam2 = lam * lam;
-  cplx<T> r = {T(0), T(0)};
-  cplx<T> u_below = {T(0), T(0)};
-#pragma unroll
-  for (int l = LMAX - 1; l >= 0; --l) {
-    if (l < L) {
-      const cplx<T> u = csqrt(cplx<T>{lam2 + k2[l].re, k2[l].im});
-      if (l < L - 1) {
-        const cplx<T> R = cdiv(k2[l] - k2[(l + 1 < LMAX) ? l + 1 : l], csq(u + u_below));
-        if (l < L - 2) {
-          const cplx<T> E = cexp(cplx<T>{T(-2) * thk[(l + 1 < LMAX) ? l + 1 : l] * u_below.re,
-                                         T(-2) * thk[(l + 1 < LMAX) ? l + 1 : l] * u_below.im});
-          const cplx<T> re = r * E;
-          r = cdiv(R + re, cplx<T>{T(1), T(0)} + R * re);
-        } else {
-          r = R;
-        }
-      }
-      u_below = u;
+  cplx<T> k2b = k2[L - 1];
+  cplx<T> ub = csqrt_fast(cplx<T>{lam2 + k2b.re, k2b.im});
+  cplx<T> N, D;
+  if (L == 1) {
+    N = {-k2b.re, -k2b.im};
+    D = csq(cplx<T>{lam + ub.re, ub.im});
+  } else {
+    {
+      const cplx<T> kl = k2[L - 2];
+      const cplx<T> u = csqrt_fast(cplx<T>{lam2 + kl.re, kl.im});
+      N = kl - k2b;
+      D = csq(u + ub);
+      ub = u;
+      k2b = kl;
     }
+#pragma unroll 1
+    for (int l = L - 3; l >= 0; --l) {
+      const cplx<T> kl = k2[l];
+      const cplx<T> u = csqrt_fast(cplx<T>{lam2 + kl.re, kl.im});
+      const cplx<T> A = kl - k2b;
+      const cplx<T> B = csq(u + ub);
+      const T h2 = T(-2) * thk[l + 1];
+      const cplx<T> NE = N * cexp(cplx<T>{h2 * ub.re, h2 * ub.im});
+      const cplx<T> Nn = A * D + B * NE;
+      D = B * D + A * NE;
+      N = Nn;
+      rescale(N, D);
+      ub = u;
+      k2b = kl;
+    }
+    const cplx<T> A0 = {-k2b.re, -k2b.im};
+    const cplx<T> B0 = csq(cplx<T>{lam + ub.re, ub.im});
+    const T h2 = T(-2) * thk[0];
+    const cplx<T> NE = N * cexp(cplx<T>{h2 * ub.re, h2 * ub.im});
+    const cplx<T> Nn = A0 * D + B0 * NE;
+    D = B0 * D + A0 * NE;
+    N = Nn;
   }
-  const cplx<T> R0 = cdiv(cplx<T>{-k2[0].re, -k2[0].im}, csq(cplx<T>{lam + u_below.re, u_below.im}));
-  if (L == 1) return R0;
-  const cplx<T> E0 = cexp(cplx<T>{T(-2) * thk[0] * u_below.re, T(-2) * thk[0] * u_below.im});
-  const cplx<T> re = r * E0;
-  return cdiv(R0 + re, cplx<T>{T(1), T(0)} + R0 * re);
+  return (N.im * D.re - N.re * D.im) * fast_rcp(D.re * D.re + D.im * D.im);
 }
 
 template <typename T>
@@ -66,7 +97,7 @@ __device__ __forceinline__ T to(double x) {
 
 // resp != nullptr: write gate responses.  ll != nullptr: write the log-likelihood.
 template <int LMAX, typename T>
-__global__ __launch_bounds__(kWave * kWavesPerBlock) void forward_kernel(DevSystem s, DevParticles p, int kc,
+__global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevSystem s, DevParticles p, int kc,
                                                                           int km, double *resp,
                                                                           const double *y_obs, double *ll) {
   __shared__ double s_lam[kMaxHankel];
@@ -76,6 +107,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void forward_kernel(DevSyst
   __shared__ double s_eps2[kMaxGate];
   __shared__ LayerStack s_stack[kWavesPerBlock];
   __shared__ double s_imh[kWavesPerBlock][kMaxFreq];
+  __shared__ cplx<T> s_k2[kWavesPerBlock][8][kMaxLayers];
+  __shared__ T s_thk[kWavesPerBlock][kMaxLayers];
 
   const int nf = s.n_freq, ng = s.n_gate, nhp = s.n_hankel_pad;
   for (int t = threadIdx.x; t < nhp; t += blockDim.x) {
@@ -94,57 +127,52 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void forward_kernel(DevSyst
   __syncthreads();
   const int L = merge_particle(p, i, valid, kc, km, LMAX, st, s.flags);
 
+  // per-particle Cole-Cole constants: (i w tau)^c = (w tau)^c (cos(pi c/2) + i sin(pi c/2))
+  double c = 0.0, log_tau = 0.0, spc = 0.0, cpc = 1.0;
   if (L > 0) {
-    // per-particle Cole-Cole constants: (i w tau)^c = (w tau)^c (cos(pi c/2) + i sin(pi c/2))
-    const double c = p.c[i];
-    const double log_tau = p.log10_tau[i] * 2.302585092994045684;
-    double spc, cpc;
+    c = p.c[i];
+    log_tau = p.log10_tau[i] * 2.302585092994045684;
     sincospi(0.5 * c, &spc, &cpc);
-
-    T thk[LMAX];
-    T sig[LMAX], mm[LMAX];
-#pragma unroll
-    for (int l = 0; l < LMAX; ++l) {
-      thk[l] = to<T>(l < L - 1 ? st->top[l + 1] - st->top[l] : 0.0);
-      sig[l] = to<T>(l < L ? st->sig[l] : 0.0);
-      mm[l] = to<T>(l < L ? st->m[l] : 0.0);
-    }
-
-    const int gl = lane & 7, gw = lane >> 3;
-    const int nhg = nhp >> 3;
-    const int nq = (nf + 7) >> 3;
+    if (lane < L - 1) s_thk[wave][lane] = to<T>(st->top[lane + 1] - st->top[lane]);
+  }
+  const int gl = lane & 7, gw = lane >> 3;
+  const int nhg = nhp >> 3;
+  const int nq = (nf + 7) >> 3;
+  // every wave runs the same number of q iterations (block barriers inside)
 #pragma unroll 1
-    for (int q = 0; q < nq; ++q) {
-      const int jf = gw + 8 * q;
-      double acc = 0.0;
-      if (jf < nf) {
-        const double w = s_omega[jf];
-        // q_cc = 1 / (1 + (i w tau)^c)
-        const double pw = exp(c * (log(w) + log_tau));
-        const cplx<double> qcc = crcp(cplx<double>{1.0 + pw * cpc, pw * spc});
-        const T wmu = to<T>(w * kMu0);
-        const cplx<T> qt = {to<T>(qcc.re), to<T>(qcc.im)};
-        cplx<T> k2[LMAX];
-#pragma unroll
-        for (int l = 0; l < LMAX; ++l) {
-          // sigma_hat = sigma_inf (1 - m q); k2 = i w mu0 sigma_hat
-          const cplx<T> sh = {sig[l] * (T(1) - mm[l] * qt.re), sig[l] * (-(mm[l] * qt.im))};
-          k2[l] = cplx<T>{-(wmu * sh.im), wmu * sh.re};
-        }
-#pragma unroll 1
-        for (int sidx = 0; sidx < nhg; ++sidx) {
-          const int k = gl + 8 * sidx;
-          const cplx<T> r = reflection<LMAX, T>(to<T>(s_lam[k]), k2, thk, L);
-          acc += s_ck[k] * static_cast<double>(r.im);
-        }
-        // reduce over the 8 abscissa groups (lane bits 0..2); all 8 lanes of a group
-        // share jf, so a group is either wholly active or wholly idle here
-        acc += __shfl_xor(acc, 1);
-        acc += __shfl_xor(acc, 2);
-        acc += __shfl_xor(acc, 4);
-        if (gl == 0) s_imh[wave][jf] = acc;
+  for (int q = 0; q < nq; ++q) {
+    const int jf = gw + 8 * q;
+    const bool act = L > 0 && jf < nf;
+    if (act) {
+      const double w = s_omega[jf];
+      // q_cc = 1 / (1 + (i w tau)^c); k2 = i w mu0 sigma_inf (1 - m q_cc)
+      const double pw = exp(c * (log(w) + log_tau));
+      const cplx<double> qcc = crcp(cplx<double>{1.0 + pw * cpc, pw * spc});
+      const T wmu = to<T>(w * kMu0);
+      const cplx<T> qt = {to<T>(qcc.re), to<T>(qcc.im)};
+      for (int l = gl; l < L; l += 8) {
+        const T sg = to<T>(st->sig[l]), mg = to<T>(st->m[l]);
+        const cplx<T> sh = {sg * (T(1) - mg * qt.re), sg * (-(mg * qt.im))};
+        s_k2[wave][gw][l] = cplx<T>{-(wmu * sh.im), wmu * sh.re};
       }
     }
+    __syncthreads();
+    if (act) {
+      double acc = 0.0;
+#pragma unroll 1
+      for (int sidx = 0; sidx < nhg; ++sidx) {
+        const int k = gl + 8 * sidx;
+        const T rim = reflection_im<T>(to<T>(s_lam[k]), s_k2[wave][gw], s_thk[wave], L);
+        acc += s_ck[k] * static_cast<double>(rim);
+      }
+      // reduce over the 8 abscissa groups (lane bits 0..2); all 8 lanes of a group
+      // share jf, so a group is either wholly active or wholly idle here
+      acc += __shfl_xor(acc, 1);
+      acc += __shfl_xor(acc, 2);
+      acc += __shfl_xor(acc, 4);
+      if (gl == 0) s_imh[wave][jf] = acc;
+    }
+    __syncthreads();
   }
   __syncthreads();
   if (L > 0) {

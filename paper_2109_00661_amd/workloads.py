@@ -96,6 +96,19 @@ def truth_three_layer():
     return p
 
 
+def truth_three_layer_merged():
+    """The same three-layer truth in the merged layout (three layers, per-layer m)."""
+    p = empty_particles(1, 2, 0, LAYOUT_MERGED)
+    p["kappa"][0] = 2
+    p["phi_b"][0] = -2.0
+    p["phi"][:, 0] = [-1.0, -3.0]
+    p["z_cond"][:, 0] = [20.0, 40.0]
+    p["m"][:, 0] = [0.0, 0.4, 0.0]
+    p["log10_tau"][0] = -3.0
+    p["c"][0] = 0.5
+    return p
+
+
 def data_noise(seed=1):
     """Standard-normal draws that scale the data noise of the synthetic sounding."""
     return np.random.default_rng(seed).standard_normal(N_GATE)

@@ -290,14 +290,7 @@ def test_conductive_only_positive_and_ip_sign_reversal(system, K_oracle):
 def test_merged_and_decoupled_layouts_agree(system, K_oracle):
     """A decoupled particle and its merged equivalent give the same response."""
     d = W.truth_three_layer()
-    mg = W.empty_particles(1, 2, 0, W.LAYOUT_MERGED)
-    mg["kappa"][0] = 2
-    mg["phi_b"][0] = -2.0
-    mg["phi"][:, 0] = [-1.0, -3.0]
-    mg["z_cond"][:, 0] = [20.0, 40.0]
-    mg["m"][:, 0] = [0.0, 0.4, 0.0]
-    mg["log10_tau"][0] = -3.0
-    mg["c"][0] = 0.5
+    mg = W.truth_three_layer_merged()
     np.testing.assert_allclose(em.forward(mg, system, K_oracle), em.forward(d, system, K_oracle), rtol=1e-12)
 
 
