@@ -1,0 +1,184 @@
+"""Pins of the SMC oracle: published RNG vectors, closed-form evidence of a conjugate
+two-model problem, invariants of the tempering bisection and of systematic
+resampling, and prior invariance of the RJ-MCMC proposals."""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import smc
+from paper_2109_00661_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+PR = W.PRIOR
+
+
+def test_philox_known_answers():
+    for line in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(t, 16) for t in line.split()]
+        assert smc.philox4x32_10(v[:4], v[4:6]) == v[6:10]
+
+
+def test_uniforms_and_normals():
+    u = np.array([smc.uniform_pair(7, i, 3, 1, 0) for i in range(20000)]).ravel()
+    assert u.min() > 0 and u.max() < 1
+    assert stats.kstest(u, "uniform").pvalue > 1e-3
+    z = np.array([smc.normal_pair(*smc.uniform_pair(7, i, 3, 2, 0)) for i in range(20000)]).ravel()
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+
+
+# ------------------------------------------------------------------------- tempering
+def test_tess_limits_and_monotone():
+    rng = np.random.default_rng(0)
+    ll = rng.normal(-50, 20, 300)
+    models = rng.integers(0, 6, 300)
+    assert abs(smc.tess(ll, models, 0.0) - 300) < 1e-9
+    vals = [smc.tess(ll, models, g) for g in np.linspace(0, 1, 60)]
+    assert all(b <= a + 1e-9 for a, b in zip(vals, vals[1:]))
+
+
+def test_bisection_brackets_target():
+    rng = np.random.default_rng(1)
+    ll = rng.normal(-500, 200, 512)
+    models = rng.integers(0, 8, 512)
+    for gamma in (0.0, 0.3, 0.97):
+        dg = smc.next_dgamma(ll, models, gamma, 0.5)
+        assert 0 < dg <= 1 - gamma
+        assert smc.tess(ll, models, dg) >= 0.5 * 512
+        if dg < 1 - gamma:
+            assert smc.tess(ll, models, dg + 2.0 ** -50 * (1 - gamma)) < 0.5 * 512
+
+
+def test_constant_likelihood_single_step():
+    ll = np.full(64, -3.25)
+    kap = np.repeat([0, 1, 2, 3], 16)
+    lam = np.zeros(64, dtype=int)
+    g, lz, anc = smc.reweight_resample(ll, kap, lam, 4, 3, np.zeros(1), np.zeros((1, 20)), 0.5, 9, 1)
+    assert g[0] == 1.0
+    for k in range(4):
+        assert abs(lz[0, smc.model_id(k, 0, 3)] - (-3.25)) < 1e-14
+    assert np.array_equal(anc, np.arange(64))          # equal weights: every particle once
+
+
+# -------------------------------------------------------------------- resampling
+def test_systematic_counts_within_floor_ceil():
+    rng = np.random.default_rng(2)
+    for trial in range(20):
+        N = 200
+        models = rng.integers(0, 5, N)
+        W_ = np.zeros(N)
+        for k in range(5):
+            sel = models == k
+            w = rng.exponential(1.0, sel.sum()) ** 3
+            W_[sel] = w / w.sum()
+        U = [int(rng.integers(0, 2 ** 53)) for _ in range(5)]
+        anc = smc.systematic_within_model(W_, models, range(5), U)
+        assert np.all(models[anc] == models)           # within-model
+        counts = np.bincount(anc, minlength=N)
+        for k in range(5):
+            sel = np.nonzero(models == k)[0]
+            nk = len(sel)
+            expct = nk * W_[sel]
+            assert np.all(counts[sel] >= np.floor(expct - 1e-9)) and np.all(counts[sel] <= np.ceil(expct + 1e-9))
+            assert counts[sel].sum() == nk
+
+
+# --------------------------------------------------------------------- evidence (P12)
+@pytest.mark.slow
+def test_conjugate_two_model_evidence():
+    rng = np.random.default_rng(3)
+    x = np.linspace(-1, 1, 8)
+    y = 0.8 * x + 0.3 * x ** 2 + rng.normal(0, 0.3, 8)    # posterior odds about 0.71 : 0.29
+    toy = smc.NestedLinearGaussian(x, y, 0.09, 1.0)
+    exact = np.array([toy.log_evidence(0), toy.log_evidence(1)])
+    post = np.exp(exact - np.logaddexp(*exact))
+    assert 0.2 < post[1] < 0.8
+    lzs, fr = [], []
+    for seed in range(24):
+        lz, counts = smc.toy_rjsmc(toy, 300, 0.5, seed, n_moves=10)
+        lzs.append(lz)
+        fr.append(counts / counts.sum())
+    lzs, fr = np.array(lzs), np.array(fr)
+    ratio = np.exp(lzs - exact[None, :])                 # unbiased for 1
+    se = ratio.std(axis=0, ddof=1) / math.sqrt(len(ratio))
+    assert np.all(np.abs(ratio.mean(axis=0) - 1) <= 3 * se + 0.02), (ratio.mean(axis=0), se)
+    se_f = fr.std(axis=0, ddof=1) / math.sqrt(len(fr))
+    assert np.all(np.abs(fr.mean(axis=0) - post) <= 3 * se_f + 0.01), (fr.mean(0), post)
+
+
+def test_toy_tempered_evidence_closed_form_consistency():
+    """The closed form at g -> 0 is 0 and is concave increasing along the path's log."""
+    x = np.linspace(-1, 1, 8)
+    toy = smc.NestedLinearGaussian(x, np.sin(3 * x), 0.05, 2.0)
+    assert abs(toy.log_evidence(1, 0.0)) < 1e-12
+    # d/dg log Z_g = E_g[log L] and it is non-decreasing in g
+    gs = np.linspace(0.05, 1, 20)
+    lz = np.array([toy.log_evidence(1, g) for g in gs])
+    d = np.diff(lz) / np.diff(gs)
+    assert np.all(np.diff(d) >= -1e-6)
+
+
+# ------------------------------------------------------------------ prior and mutation
+def test_prior_draw_support():
+    p = smc.init_population(5, 500, 4, 3, PR)
+    assert set(np.unique(p["kappa"])) == set(range(5)) and set(np.unique(p["lambda_"])) == set(range(4))
+    for i in range(500):
+        th = smc.param_vector(p, i)
+        assert smc.in_support(th, int(p["kappa"][i]), int(p["lambda_"][i]), PR)
+
+
+def _q(probs=None):
+    return dict(move_prob=np.array(probs if probs is not None else [1, 1, 1, 1, 1, 1, 1, 0], float),
+                z_move_sd=0.05 * PR["z_max"], rw_scale=2.38)
+
+
+def test_mutation_preserves_the_prior_at_zero_temperature():
+    """With gamma = 0 the target is the prior: after many RJ moves the model counts stay
+    uniform and the depths and properties stay uniform (detailed balance of the
+    birth/death/move/within proposals with respect to the prior)."""
+    n = 3000
+    p = smc.init_population(11, n, 4, 3, PR)
+    ll = np.zeros(n)
+    fac = {}
+
+    def factor(i):
+        key = (int(p["kappa"][i]), int(p["lambda_"][i]))
+        if key not in fac:
+            fac[key] = np.diag(0.3 * smc.prior_sd(key[0], key[1], PR))
+        return fac[key]
+
+    st, _ = smc.mutate(p, ll, lambda pp, i: 0.0, lambda i: 0.0, 1, 13, _q(), PR, 4, 3, factor, 6)
+    assert st[1].sum() > 0.5 * st[0].sum()
+    ck = np.bincount(p["kappa"], minlength=5)
+    cl = np.bincount(p["lambda_"], minlength=4)
+    assert stats.chisquare(ck).pvalue > 1e-3 and stats.chisquare(cl).pvalue > 1e-3
+    zs = np.concatenate([p["z_cond"][:k, i] for i, k in enumerate(p["kappa"])])
+    assert stats.kstest(zs / PR["z_max"], "uniform").pvalue > 1e-3
+    phs = np.concatenate([[p["phi_b"][i]] + list(p["phi"][:k, i]) for i, k in enumerate(p["kappa"])])
+    assert stats.kstest((phs - PR["phi_lo"]) / (PR["phi_hi"] - PR["phi_lo"]), "uniform").pvalue > 1e-3
+
+
+def test_birth_inserts_sorted_and_death_removes():
+    p = W.truth_three_layer()
+    zc, ph = p["z_cond"][:2, 0], p["phi"][:2, 0]
+    z2, v2 = smc._birth(zc, ph, 30.0, -0.5, 4)
+    assert list(z2) == [20.0, 30.0, 40.0] and list(v2) == [-1.0, -0.5, -3.0]
+    assert smc._birth(np.arange(4.0), np.zeros(4), 1.5, 0.0, 4) is None
+
+
+def test_acceptance_uses_tempered_ratio():
+    """A particle whose proposals all have ll' = ll - 10 is accepted with probability
+    exp(-10 gamma)."""
+    n = 4000
+    p = smc.init_population(17, n, 4, 3, PR)
+    for g in (0.05, 0.2):
+        pp = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+        ll = np.zeros(n)
+        st, _ = smc.mutate(pp, ll, lambda q, i: float(ll[i]) - 10.0, lambda i: g, 2, 21, _q([0, 0, 0, 0, 0, 0, 1, 0]),
+                           PR, 4, 3, lambda i: np.diag(1e-6 * smc.prior_sd(int(pp["kappa"][i]), int(pp["lambda_"][i]), PR)), 1)
+        rate = st[1, 6] / st[0, 6]
+        assert abs(rate - math.exp(-10 * g)) < 4 * math.sqrt(math.exp(-10 * g) / n) + 0.01
