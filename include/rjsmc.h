@@ -74,6 +74,7 @@ typedef struct {
   int32_t kmax_charg;          /* capacity: chargeability interfaces per particle */
   double z_max_m;              /* prior depth bound of interfaces */
   int32_t fwd_precision;       /* rjsmc_precision */
+  int64_t max_particles;       /* workspace size of rjsmc_mutate (0: no mutation) */
 } rjsmc_system;
 
 /* Particle population in structure-of-arrays form, particle index fastest.  Every
@@ -152,6 +153,102 @@ rjsmc_status rjsmc_loglik(rjsmc_ctx *ctx, const rjsmc_particles *p, const double
  * FP64 only (RJSMC_E_UNSUPPORTED for an FP32 context). */
 rjsmc_status rjsmc_loglik_grad(rjsmc_ctx *ctx, const rjsmc_particles *p, const double *y_obs,
                                double *ll, rjsmc_particles *grad, rjsmc_stream stream);
+
+/* ------------------------------------------------------------------------------------
+ * SMC primitives (Algorithm 1).  All arithmetic on weights, temperatures and evidence
+ * is FP64.  Particles of one sounding are contiguous; n_sound soundings of
+ * n_per_sounding particles each (n_per_sounding = 0: one sounding of n).  Model index
+ * k = kappa (kmax_charg + 1) + lambda; n_models = (kmax_cond + 1)(kmax_charg + 1).
+ * Random numbers: Philox4x32-10 keyed by `seed`; particle i at step t, move r uses
+ * counters (i, t, r, slot); resampling of model k of sounding s uses (s, t, k, 2^31);
+ * prior draws use (i, 0, slot, 2^30).  Uniforms are (x + 0.5) 2^-53 for 53-bit x.
+ * ---------------------------------------------------------------------------------- */
+
+/* Bounds of the uniform priors (Section 2.3.1); depths are uniform on (0, z_max) of
+ * the context and the counts are uniform on 0..kmax of the context. */
+typedef struct {
+  double phi_lo, phi_hi;        /* log10 sigma_inf */
+  double m_lo, m_hi;            /* chargeability */
+  double ltau_lo, ltau_hi;      /* log10 tau */
+  double c_lo, c_hi;            /* Cole-Cole exponent */
+} rjsmc_prior;
+
+/* Draws every particle of `p` (DECOUPLED layout, device memory, counts and values
+ * written) from the prior (Algorithm 1 initialisation): kappa, lambda uniform on
+ * 0..kmax, properties uniform, depths sorted uniforms on (0, z_max). */
+rjsmc_status rjsmc_init_prior(rjsmc_ctx *ctx, rjsmc_particles *p, const rjsmc_prior *prior,
+                              uint64_t seed, rjsmc_stream stream);
+
+typedef struct {
+  double alpha_tess;            /* target fraction of the total effective sample size */
+  uint64_t seed;
+  int32_t step;                 /* t >= 1 */
+  int32_t n_sound;
+} rjsmc_reweight_args;
+
+/* Re-weight and re-sample every sounding (Algorithm 1; Section 3.2.1; Appendices C, D):
+ *  - the temperature increment dg is 1 - gamma if the total effective sample size
+ *    TESS(dg) = sum_k (sum_{i in k} w_i)^2 / sum_{i in k} w_i^2, w_i = exp(dg ll_i), stays
+ *    >= alpha N; otherwise 60 bisection steps on (0, 1 - gamma] keep the lower bracket;
+ *  - log_z[s][k] += logsumexp_{i in k}(dg ll_i) - ln N_k for every populated model;
+ *  - within each model, systematic resampling of its N_k members from the normalised
+ *    weights quantised to round(W_i 2^60); member j (by particle index) receives the
+ *    first member whose cumulative weight exceeds floor((j 2^53 + U) T / (N_k 2^53));
+ *  - out / ll_out receive the resampled population (out may not alias in).
+ * Soundings with gamma >= 1 are copied unchanged.  active[s] (device, may be NULL) is
+ * set to 1 if the sounding was re-weighted, else 0.  ancestors[n] (device) receives the
+ * global index of each particle's ancestor.  Requires n_per_sounding <= 2048 and
+ * n_models <= 128 (RJSMC_E_UNSUPPORTED otherwise). */
+rjsmc_status rjsmc_reweight_resample(rjsmc_ctx *ctx, const rjsmc_reweight_args *args,
+                                     const rjsmc_particles *in, const double *ll_in,
+                                     rjsmc_particles *out, double *ll_out, double *gamma,
+                                     double *log_z, int32_t *active, int32_t *ancestors,
+                                     rjsmc_stream stream);
+
+/* Proposal factors of the within-model move (Section 3.2.3).  For every (sounding,
+ * model) with more members than dimensions d = 3 + 2 kappa + 2 lambda:
+ * F = U diag(sqrt(Lambda)) from the eigen-decomposition of the members' sample
+ * covariance of theta = (phi_b, phi_1..kappa, z_1..kappa, m_1..lambda, zm_1..lambda,
+ * log10 tau, c); otherwise F = 0.1 diag(prior standard deviations).
+ * factors: device [n_sound][n_models][dmax][dmax], column r (direction r) contiguous:
+ * F[r][a] at offset r dmax + a; dmax = 3 + 2 kmax_cond + 2 kmax_charg. */
+rjsmc_status rjsmc_adapt(rjsmc_ctx *ctx, const rjsmc_particles *p, int32_t n_sound,
+                         const rjsmc_prior *prior, double *factors, rjsmc_stream stream);
+
+/* Move types of the RJ-MCMC kernel (Appendix E.1; Section 3.2.3). */
+enum {
+  RJSMC_MOVE_SIGMA_BIRTH = 0, RJSMC_MOVE_SIGMA_DEATH = 1, RJSMC_MOVE_SIGMA_MOVE = 2,
+  RJSMC_MOVE_M_BIRTH = 3, RJSMC_MOVE_M_DEATH = 4, RJSMC_MOVE_M_MOVE = 5,
+  RJSMC_MOVE_WITHIN_RW = 6, RJSMC_MOVE_WITHIN_MALA = 7, RJSMC_N_MOVES = 8
+};
+
+typedef struct {
+  uint64_t seed;
+  int32_t step;                 /* t */
+  int32_t n_moves;              /* R: sweeps of every particle */
+  int32_t n_sound;
+  double move_prob[8];          /* relative probability of each move type */
+  double z_move_sd;             /* sd of an interface move (m) */
+  double rw_scale;              /* within-model step along a principal direction */
+  double mala_eps;              /* gradient-informed step size */
+  const double *factors;        /* device, as written by rjsmc_adapt */
+  rjsmc_prior prior;
+} rjsmc_mutate_args;
+
+/* n_moves RJ-MCMC sweeps (Algorithm 1, mutation) targeting L^gamma(sounding) x prior.
+ * Per sweep every particle of an active sounding proposes one move of a type drawn from
+ * move_prob: birth (depth uniform on (0, z_max), property from its prior), death (a
+ * uniformly chosen interface), move (one depth + N(0, z_move_sd^2)), a within-model step
+ * theta + rw_scale xi F[:, r] along a uniformly chosen principal direction r, or a
+ * gradient-informed step (RJSMC_E_UNSUPPORTED in this build).  Proposals beyond the
+ * capacities or outside the prior support are rejected; the others are accepted when
+ * ln u < gamma (ll' - ll).  `scratch` and `ll_scratch` hold the proposals (same shapes as
+ * `state`).  n must not exceed the context's max_particles.  stats (device int64 [2][8], may be NULL) accumulates proposed / accepted
+ * counts per move type.  active (device [n_sound], NULL = all) selects soundings. */
+rjsmc_status rjsmc_mutate(rjsmc_ctx *ctx, const rjsmc_mutate_args *args, rjsmc_particles *state,
+                          double *ll, rjsmc_particles *scratch, double *ll_scratch,
+                          const double *gamma, const int32_t *active, const double *y_obs,
+                          int64_t *stats, rjsmc_stream stream);
 
 #ifdef __cplusplus
 }

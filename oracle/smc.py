@@ -317,7 +317,10 @@ def proposal_factor(p, members, k, l, pr):
     X = np.array([param_vector(p, i) for i in members])
     C = np.cov(X, rowvar=False, bias=False)
     lam_, U = np.linalg.eigh(C)
-    lam_ = np.clip(lam_, 0.0, None)
+    order = np.argsort(-lam_, kind="stable")                 # descending eigenvalues
+    lam_, U = np.clip(lam_[order], 0.0, None), U[:, order]
+    big = np.argmax(np.abs(U), axis=0)                       # largest component positive
+    U = U * np.where(U[big, np.arange(d)] < 0, -1.0, 1.0)[None, :]
     return U * np.sqrt(lam_)[None, :]
 
 

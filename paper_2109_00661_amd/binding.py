@@ -33,7 +33,8 @@ class System(ctypes.Structure):
                 ("n_gate", ctypes.c_int32), ("gate_open_s", _dp), ("gate_close_s", _dp),
                 ("eps_mn", ctypes.c_double), ("eps_an", _dp),
                 ("kmax_cond", ctypes.c_int32), ("kmax_charg", ctypes.c_int32),
-                ("z_max_m", ctypes.c_double), ("fwd_precision", ctypes.c_int32)]
+                ("z_max_m", ctypes.c_double), ("fwd_precision", ctypes.c_int32),
+                ("max_particles", ctypes.c_int64)]
 
 
 class Particles(ctypes.Structure):
@@ -43,6 +44,32 @@ class Particles(ctypes.Structure):
                 ("phi_b", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("z_cond", ctypes.c_void_p),
                 ("m", ctypes.c_void_p), ("z_charg", ctypes.c_void_p),
                 ("log10_tau", ctypes.c_void_p), ("c", ctypes.c_void_p)]
+
+
+class Prior(ctypes.Structure):
+    _fields_ = [("phi_lo", ctypes.c_double), ("phi_hi", ctypes.c_double), ("m_lo", ctypes.c_double),
+                ("m_hi", ctypes.c_double), ("ltau_lo", ctypes.c_double), ("ltau_hi", ctypes.c_double),
+                ("c_lo", ctypes.c_double), ("c_hi", ctypes.c_double)]
+
+
+class ReweightArgs(ctypes.Structure):
+    _fields_ = [("alpha_tess", ctypes.c_double), ("seed", ctypes.c_uint64), ("step", ctypes.c_int32),
+                ("n_sound", ctypes.c_int32)]
+
+
+N_MOVES = 8
+
+
+class MutateArgs(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("step", ctypes.c_int32), ("n_moves", ctypes.c_int32),
+                ("n_sound", ctypes.c_int32), ("move_prob", ctypes.c_double * N_MOVES),
+                ("z_move_sd", ctypes.c_double), ("rw_scale", ctypes.c_double), ("mala_eps", ctypes.c_double),
+                ("factors", ctypes.c_void_p), ("prior", Prior)]
+
+
+def make_prior(pr):
+    return Prior(pr["phi_lo"], pr["phi_hi"], pr["m_lo"], pr["m_hi"], pr["ltau_lo"], pr["ltau_hi"],
+                 pr["c_lo"], pr["c_hi"])
 
 
 _lib = None
@@ -61,6 +88,17 @@ _SIGS = {
                                     ctypes.c_void_p, ctypes.c_void_p]),
     "rjsmc_loglik_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p]),
+    "rjsmc_init_prior": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.POINTER(Prior),
+                                        ctypes.c_uint64, ctypes.c_void_p]),
+    "rjsmc_reweight_resample": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ReweightArgs), ctypes.POINTER(Particles),
+                                               ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p]),
+    "rjsmc_adapt": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_int32, ctypes.POINTER(Prior),
+                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "rjsmc_mutate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MutateArgs), ctypes.POINTER(Particles),
+                                    ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 
@@ -138,7 +176,7 @@ def particles_struct(p, n=None, stride=None):
 class Context:
     """A librjsmc context for one acquisition system on one device."""
 
-    def __init__(self, system, device=0, precision="f64"):
+    def __init__(self, system, device=0, precision="f64", max_particles=0):
         self._ptr = ctypes.c_void_p(0)
         keep = {k: np.ascontiguousarray(system[k], dtype=np.float64)
                 for k in ("freq_hz", "hankel_b", "hankel_w", "gate_open_s", "gate_close_s", "eps_an")}
@@ -153,6 +191,7 @@ class Context:
         s.kmax_cond, s.kmax_charg = system["kmax_cond"], system["kmax_charg"]
         s.z_max_m = system["z_max_m"]
         s.fwd_precision = {"f64": RJSMC_F64, "f32": RJSMC_F32}[precision]
+        s.max_particles = max_particles
         self.n_gate = s.n_gate
         self.n_freq = s.n_freq
         self.kmax_cond, self.kmax_charg = s.kmax_cond, s.kmax_charg
@@ -210,3 +249,56 @@ class Context:
         _check(lib().rjsmc_loglik_grad(self._ptr, ctypes.byref(ps), _ptr(y_obs), _ptr(ll), ctypes.byref(gs),
                                        _stream_handle(stream)))
         return ll, {k: g[k] for k in _FLOAT_KEYS}
+
+    # -- SMC primitives ----------------------------------------------------------------
+    def init_prior(self, p, prior, seed, stream=None):
+        ps = particles_struct(p)
+        pr = make_prior(prior)
+        _check(lib().rjsmc_init_prior(self._ptr, ctypes.byref(ps), ctypes.byref(pr), seed, _stream_handle(stream)))
+
+    def reweight_resample(self, p_in, ll_in, p_out, ll_out, gamma, log_z, active, anc, alpha, seed, step, n_sound,
+                          stream=None):
+        a = ReweightArgs(alpha, seed, step, n_sound)
+        si, so = particles_struct(p_in), particles_struct(p_out)
+        _check(lib().rjsmc_reweight_resample(self._ptr, ctypes.byref(a), ctypes.byref(si), _ptr(ll_in),
+                                             ctypes.byref(so), _ptr(ll_out), _ptr(gamma), _ptr(log_z), _ptr(active),
+                                             _ptr(anc), _stream_handle(stream)))
+
+    def adapt(self, p, n_sound, prior, factors, stream=None):
+        ps = particles_struct(p)
+        pr = make_prior(prior)
+        _check(lib().rjsmc_adapt(self._ptr, ctypes.byref(ps), n_sound, ctypes.byref(pr), _ptr(factors),
+                                 _stream_handle(stream)))
+
+    def mutate(self, state, ll, scratch, ll_scratch, gamma, active, y_obs, stats, *, seed, step, n_moves, n_sound,
+               prior, move_prob, z_move_sd, rw_scale, factors, mala_eps=0.0, stream=None):
+        a = MutateArgs()
+        a.seed, a.step, a.n_moves, a.n_sound = seed, step, n_moves, n_sound
+        for t in range(N_MOVES):
+            a.move_prob[t] = float(move_prob[t])
+        a.z_move_sd, a.rw_scale, a.mala_eps = z_move_sd, rw_scale, mala_eps
+        a.factors = _ptr(factors) if factors is not None else ctypes.c_void_p(0)
+        a.prior = make_prior(prior)
+        ss, sq = particles_struct(state), particles_struct(scratch)
+        _check(lib().rjsmc_mutate(self._ptr, ctypes.byref(a), ctypes.byref(ss), _ptr(ll), ctypes.byref(sq),
+                                  _ptr(ll_scratch), _ptr(gamma), _ptr(active), _ptr(y_obs), _ptr(stats),
+                                  _stream_handle(stream)))
+
+
+def empty_device_population(n, kmax_cond, kmax_charg, n_per_sounding=0, device="cuda"):
+    """Zeroed DECOUPLED population of device tensors."""
+    import torch
+    f = lambda *shape: torch.zeros(shape, dtype=torch.float64, device=device)
+    return {"layout": LAYOUT_DECOUPLED, "n_per_sounding": n_per_sounding,
+            "kappa": torch.zeros(n, dtype=torch.int32, device=device),
+            "lambda_": torch.zeros(n, dtype=torch.int32, device=device),
+            "phi_b": f(n), "phi": f(kmax_cond, n), "z_cond": f(kmax_cond, n), "m": f(kmax_charg, n),
+            "z_charg": f(kmax_charg, n), "log10_tau": f(n), "c": f(n)}
+
+
+def population_to_host(p):
+    out = {"layout": p["layout"], "n_per_sounding": p.get("n_per_sounding", 0)}
+    for k, v in p.items():
+        if hasattr(v, "cpu"):
+            out[k] = v.cpu().numpy()
+    return out

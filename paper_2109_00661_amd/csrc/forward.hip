@@ -123,9 +123,10 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + wave;
   const bool valid = i < p.n;
+  const bool skip = valid && p.mask && !p.mask[i];
   LayerStack *st = &s_stack[wave];
   __syncthreads();
-  const int L = merge_particle(p, i, valid, kc, km, LMAX, st, s.flags);
+  const int L = merge_particle(p, i, valid && !skip, kc, km, LMAX, st, s.flags);
 
   // per-particle Cole-Cole constants: (i w tau)^c = (w tau)^c (cos(pi c/2) + i sin(pi c/2))
   double c = 0.0, log_tau = 0.0, spc = 0.0, cpc = 1.0;
@@ -202,6 +203,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
         ll[i] = (v == v && v != HUGE_VAL) ? v : -HUGE_VAL;   // NaN or +inf -> -inf
       }
     }
+  } else if (skip) {
+    if (ll && lane == 0) ll[i] = -HUGE_VAL;
   } else if (valid) {
     // invalid particle: NaN responses, -inf log-likelihood
     if (resp && lane < ng) resp[i * ng + lane] = __builtin_nan("");

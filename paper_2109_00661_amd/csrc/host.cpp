@@ -268,11 +268,20 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
   }
   e = hipMalloc((void **)&d.flags, sizeof(int));
   if (e == hipSuccess) e = hipMemset(d.flags, 0, sizeof(int));
+  c->work_mask = nullptr;
+  c->work_type = nullptr;
+  c->work_n = s->max_particles > 0 ? s->max_particles : 0;
+  if (e == hipSuccess && c->work_n > 0) {
+    e = hipMalloc((void **)&c->work_mask, sizeof(int32_t) * c->work_n);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->work_type, sizeof(int32_t) * c->work_n);
+  }
   if (e != hipSuccess) {
+    if (c->work_mask) (void)hipFree(c->work_mask);
+    if (c->work_type) (void)hipFree(c->work_type);
     free_dev(d);
     delete[] c->K_host;
     delete c;
-    return hip_fail(e, "rjsmc_create: flag word");
+    return hip_fail(e, "rjsmc_create: workspace");
   }
   *out = c;
   return RJSMC_OK;
@@ -281,6 +290,8 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
 extern "C" void rjsmc_destroy(rjsmc_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  if (c->work_mask) (void)hipFree(c->work_mask);
+  if (c->work_type) (void)hipFree(c->work_type);
   free_dev(c->dev);
   delete[] c->K_host;
   delete c;
@@ -351,6 +362,7 @@ static rjsmc_status check_particles(const rjsmc_ctx *c, const rjsmc_particles *p
   dp->z_charg = p->z_charg;
   dp->log10_tau = p->log10_tau;
   dp->c = p->c;
+  dp->mask = nullptr;
   return RJSMC_OK;
 }
 
@@ -403,5 +415,161 @@ extern "C" rjsmc_status rjsmc_loglik_grad(rjsmc_ctx *c, const rjsmc_particles *p
     e = rjsmc::launch_loglik_grad(c->dev, dp, c->kmax_cond, c->kmax_charg, y_obs, ll, g,
                                   (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "rjsmc_loglik_grad: launch");
+  return RJSMC_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// SMC entry points
+// ---------------------------------------------------------------------------------
+static rjsmc::SmcShape smc_shape(const rjsmc_ctx *c) {
+  rjsmc::SmcShape sh;
+  sh.kc = c->kmax_cond;
+  sh.km = c->kmax_charg;
+  sh.n_models = (c->kmax_cond + 1) * (c->kmax_charg + 1);
+  sh.dmax = 3 + 2 * c->kmax_cond + 2 * c->kmax_charg;
+  sh.z_max = c->z_max;
+  return sh;
+}
+
+static rjsmc::DevParticlesW writable(const rjsmc::DevParticles &d) {
+  rjsmc::DevParticlesW w;
+  w.n = d.n;
+  w.stride = d.stride;
+  w.n_per_sounding = d.n_per_sounding;
+  w.layout = d.layout;
+  w.kappa = const_cast<int32_t *>(d.kappa);
+  w.lambda = const_cast<int32_t *>(d.lambda);
+  w.phi_b = const_cast<double *>(d.phi_b);
+  w.phi = const_cast<double *>(d.phi);
+  w.z_cond = const_cast<double *>(d.z_cond);
+  w.m = const_cast<double *>(d.m);
+  w.z_charg = const_cast<double *>(d.z_charg);
+  w.log10_tau = const_cast<double *>(d.log10_tau);
+  w.c = const_cast<double *>(d.c);
+  return w;
+}
+
+static rjsmc_status check_prior(const rjsmc_prior *pr, const char *who) {
+  if (!pr) return fail(RJSMC_E_INVALID, "%s: NULL prior", who);
+  if (!(pr->phi_lo < pr->phi_hi) || !(pr->m_lo < pr->m_hi) || !(pr->ltau_lo < pr->ltau_hi) ||
+      !(pr->c_lo < pr->c_hi) || !(pr->m_lo >= 0) || !(pr->m_hi < 1))
+    return fail(RJSMC_E_INVALID, "%s: bad prior bounds", who);
+  return RJSMC_OK;
+}
+
+// Soundings of a population: n_sound * n_per_sounding == n.
+static rjsmc_status check_soundings(const rjsmc_particles *p, int32_t n_sound, const char *who) {
+  const int64_t nps = p->n_per_sounding > 0 ? p->n_per_sounding : p->n;
+  if (n_sound < 1 || nps * (int64_t)n_sound != p->n)
+    return fail(RJSMC_E_INVALID, "%s: n_sound=%d does not tile n=%lld", who, n_sound, (long long)p->n);
+  if (nps > 2048)
+    return fail(RJSMC_E_UNSUPPORTED, "%s: %lld particles per sounding exceed 2048", who, (long long)nps);
+  return RJSMC_OK;
+}
+
+extern "C" rjsmc_status rjsmc_init_prior(rjsmc_ctx *c, rjsmc_particles *p, const rjsmc_prior *prior, uint64_t seed,
+                                         rjsmc_stream stream) {
+  if (!c) return fail(RJSMC_E_INVALID, "rjsmc_init_prior: NULL context");
+  rjsmc::DevParticles dp;
+  rjsmc_status st = check_particles(c, p, "rjsmc_init_prior", &dp);
+  if (st != RJSMC_OK) return st;
+  if (p->layout != RJSMC_LAYOUT_DECOUPLED) return fail(RJSMC_E_INVALID, "rjsmc_init_prior: DECOUPLED layout only");
+  if ((st = check_prior(prior, "rjsmc_init_prior")) != RJSMC_OK) return st;
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = rjsmc::launch_init_prior(writable(dp), smc_shape(c), *prior, seed, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "rjsmc_init_prior: launch");
+  return RJSMC_OK;
+}
+
+extern "C" rjsmc_status rjsmc_reweight_resample(rjsmc_ctx *c, const rjsmc_reweight_args *a, const rjsmc_particles *in,
+                                                const double *ll_in, rjsmc_particles *out, double *ll_out,
+                                                double *gamma, double *log_z, int32_t *active, int32_t *anc,
+                                                rjsmc_stream stream) {
+  const char *who = "rjsmc_reweight_resample";
+  if (!c || !a) return fail(RJSMC_E_INVALID, "%s: NULL argument", who);
+  rjsmc::DevParticles di, dout;
+  rjsmc_status st = check_particles(c, in, who, &di);
+  if (st == RJSMC_OK) st = check_particles(c, out, who, &dout);
+  if (st != RJSMC_OK) return st;
+  if (in->layout != out->layout || in->n != out->n || in->n_per_sounding != out->n_per_sounding)
+    return fail(RJSMC_E_INVALID, "%s: in and out populations differ in shape", who);
+  if (in->layout != RJSMC_LAYOUT_DECOUPLED) return fail(RJSMC_E_INVALID, "%s: DECOUPLED layout only", who);
+  if (in->kappa == out->kappa || in->phi_b == out->phi_b) return fail(RJSMC_E_INVALID, "%s: out aliases in", who);
+  if (!ll_in || !ll_out || !gamma || !log_z || !anc) return fail(RJSMC_E_INVALID, "%s: NULL array", who);
+  if (!(a->alpha_tess > 0 && a->alpha_tess < 1)) return fail(RJSMC_E_INVALID, "%s: alpha must be in (0,1)", who);
+  if ((st = check_soundings(in, a->n_sound, who)) != RJSMC_OK) return st;
+  const rjsmc::SmcShape sh = smc_shape(c);
+  if (sh.n_models > 128) return fail(RJSMC_E_UNSUPPORTED, "%s: %d models exceed 128", who, sh.n_models);
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess)
+    e = rjsmc::launch_reweight_resample(sh, *a, di, ll_in, writable(dout), ll_out, gamma, log_z, active, anc,
+                                        c->dev.flags, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "rjsmc_reweight_resample: launch");
+  return RJSMC_OK;
+}
+
+extern "C" rjsmc_status rjsmc_adapt(rjsmc_ctx *c, const rjsmc_particles *p, int32_t n_sound, const rjsmc_prior *prior,
+                                    double *factors, rjsmc_stream stream) {
+  const char *who = "rjsmc_adapt";
+  if (!c || !factors) return fail(RJSMC_E_INVALID, "%s: NULL argument", who);
+  rjsmc::DevParticles dp;
+  rjsmc_status st = check_particles(c, p, who, &dp);
+  if (st != RJSMC_OK) return st;
+  if (p->layout != RJSMC_LAYOUT_DECOUPLED) return fail(RJSMC_E_INVALID, "%s: DECOUPLED layout only", who);
+  if ((st = check_prior(prior, who)) != RJSMC_OK) return st;
+  if ((st = check_soundings(p, n_sound, who)) != RJSMC_OK) return st;
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = rjsmc::launch_adapt(smc_shape(c), dp, n_sound, *prior, factors, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "rjsmc_adapt: launch");
+  return RJSMC_OK;
+}
+
+extern "C" rjsmc_status rjsmc_mutate(rjsmc_ctx *c, const rjsmc_mutate_args *a, rjsmc_particles *state, double *ll,
+                                     rjsmc_particles *scratch, double *ll_scratch, const double *gamma,
+                                     const int32_t *active, const double *y_obs, int64_t *stats,
+                                     rjsmc_stream stream) {
+  const char *who = "rjsmc_mutate";
+  if (!c || !a) return fail(RJSMC_E_INVALID, "%s: NULL argument", who);
+  rjsmc::DevParticles ds, dq;
+  rjsmc_status st = check_particles(c, state, who, &ds);
+  if (st == RJSMC_OK) st = check_particles(c, scratch, who, &dq);
+  if (st != RJSMC_OK) return st;
+  if (state->layout != RJSMC_LAYOUT_DECOUPLED || scratch->layout != RJSMC_LAYOUT_DECOUPLED)
+    return fail(RJSMC_E_INVALID, "%s: DECOUPLED layout only", who);
+  if (scratch->n != state->n || scratch->n_per_sounding != state->n_per_sounding)
+    return fail(RJSMC_E_INVALID, "%s: scratch and state differ in shape", who);
+  if (state->n > c->work_n)
+    return fail(RJSMC_E_INVALID, "%s: n=%lld exceeds the context's max_particles=%lld", who, (long long)state->n,
+                (long long)c->work_n);
+  if (!ll || !ll_scratch || !gamma || !y_obs) return fail(RJSMC_E_INVALID, "%s: NULL array", who);
+  if ((st = check_prior(&a->prior, who)) != RJSMC_OK) return st;
+  if ((st = check_soundings(state, a->n_sound, who)) != RJSMC_OK) return st;
+  if (a->n_moves < 0) return fail(RJSMC_E_INVALID, "%s: negative n_moves", who);
+  double total = 0;
+  for (int t = 0; t < RJSMC_N_MOVES; ++t) {
+    if (!(a->move_prob[t] >= 0)) return fail(RJSMC_E_INVALID, "%s: negative move probability", who);
+    total += a->move_prob[t];
+  }
+  if (!(total > 0)) return fail(RJSMC_E_INVALID, "%s: move probabilities sum to zero", who);
+  if (a->move_prob[RJSMC_MOVE_WITHIN_MALA] > 0)
+    return fail(RJSMC_E_UNSUPPORTED, "%s: the gradient-informed move needs rjsmc_mutate_grad", who);
+  if (a->move_prob[RJSMC_MOVE_WITHIN_RW] > 0 && !a->factors)
+    return fail(RJSMC_E_INVALID, "%s: within-model moves need proposal factors", who);
+  if (!(a->z_move_sd >= 0) || !(a->rw_scale >= 0)) return fail(RJSMC_E_INVALID, "%s: bad step sizes", who);
+  const rjsmc::SmcShape sh = smc_shape(c);
+  hipError_t e = hipSetDevice(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  rjsmc::DevParticles prop = dq;
+  prop.mask = c->work_mask;
+  for (int r = 0; r < a->n_moves && e == hipSuccess; ++r) {
+    e = rjsmc::launch_propose(sh, *a, r, ds, writable(dq), c->work_mask, c->work_type, active, s);
+    if (e == hipSuccess)
+      e = rjsmc::launch_forward(c->dev, prop, c->kmax_cond, c->kmax_charg, c->precision, nullptr, y_obs, ll_scratch,
+                                s);
+    if (e == hipSuccess)
+      e = rjsmc::launch_accept(sh, *a, r, writable(ds), ll, dq, ll_scratch, c->work_mask, c->work_type, gamma, stats,
+                               s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "rjsmc_mutate: launch");
   return RJSMC_OK;
 }

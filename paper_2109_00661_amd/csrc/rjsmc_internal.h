@@ -36,10 +36,28 @@ struct DevSystem {
 
 // Particle pointers and sizes as the kernels see them.
 struct DevParticles {
-  int64_t n, stride, n_per_sounding;
-  int layout;
-  const int32_t *kappa, *lambda;
-  const double *phi_b, *phi, *z_cond, *m, *z_charg, *log10_tau, *c;
+  int64_t n = 0, stride = 0, n_per_sounding = 0;
+  int layout = 0;
+  const int32_t *kappa = nullptr, *lambda = nullptr;
+  const double *phi_b = nullptr, *phi = nullptr, *z_cond = nullptr, *m = nullptr, *z_charg = nullptr,
+               *log10_tau = nullptr, *c = nullptr;
+  const int32_t *mask = nullptr;   // optional: particles with mask[i] == 0 are skipped (ll = -inf)
+};
+
+// Writable view of a particle population.
+struct DevParticlesW {
+  int64_t n = 0, stride = 0, n_per_sounding = 0;
+  int layout = 0;
+  int32_t *kappa = nullptr, *lambda = nullptr;
+  double *phi_b = nullptr, *phi = nullptr, *z_cond = nullptr, *m = nullptr, *z_charg = nullptr,
+         *log10_tau = nullptr, *c = nullptr;
+};
+
+struct SmcShape {
+  int kc, km;          // capacities
+  int n_models;        // (kc+1)(km+1)
+  int dmax;            // 3 + 2 kc + 2 km
+  double z_max;
 };
 
 struct DevGrad {
@@ -54,6 +72,21 @@ hipError_t launch_loglik_grad(const DevSystem &s, const DevParticles &p, int kma
                               int kmax_charg, const double *y_obs, double *ll, const DevGrad &g,
                               hipStream_t stream);
 
+// SMC launchers (smc.hip).
+hipError_t launch_init_prior(const DevParticlesW &p, const SmcShape &sh, const rjsmc_prior &pr, uint64_t seed,
+                             hipStream_t stream);
+hipError_t launch_reweight_resample(const SmcShape &sh, const rjsmc_reweight_args &a, const DevParticles &in,
+                                    const double *ll_in, const DevParticlesW &out, double *ll_out, double *gamma,
+                                    double *log_z, int32_t *active, int32_t *anc, int *flags, hipStream_t stream);
+hipError_t launch_adapt(const SmcShape &sh, const DevParticles &p, int n_sound, const rjsmc_prior &pr,
+                        double *factors, hipStream_t stream);
+hipError_t launch_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticles &state,
+                          const DevParticlesW &prop, int32_t *mask, int32_t *type, const int32_t *active,
+                          hipStream_t stream);
+hipError_t launch_accept(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticlesW &state,
+                         double *ll, const DevParticles &prop, const double *ll_prop, const int32_t *mask,
+                         const int32_t *type, const double *gamma, int64_t *stats, hipStream_t stream);
+
 // Host-side construction of the frequency-to-time matrix (host.cpp).
 void build_time_kernel(const double *freq_hz, int n_freq, const double *t_open,
                        const double *t_close, int n_gate, double *K_out);
@@ -67,4 +100,7 @@ struct rjsmc_ctx {
   double z_max;
   rjsmc::DevSystem dev;
   double *K_host;   // [n_gate][n_freq]
+  int32_t *work_mask;   // [work_n] mutate scratch: proposal validity
+  int32_t *work_type;   // [work_n] mutate scratch: move type
+  int64_t work_n;
 };

@@ -1,0 +1,796 @@
+// SMC primitives of adaptive RJSMC (Algorithm 1) for gfx950: prior initialisation,
+// re-weighting with the tempering bisection and evidence update, within-model
+// systematic resampling, gather, per-model proposal adaptation, and the
+// propose / accept halves of the RJ-MCMC mutation (the likelihood of each proposal is
+// evaluated by the forward kernel in between).
+//
+// Weights, temperatures and evidence are FP64.  Resampling thresholds are exact
+// integer arithmetic on weights quantised to 2^-60, so ancestor choices do not depend
+// on summation order.  One workgroup owns one sounding for the reweight/resample step
+// (its particles, log-likelihoods, model ids and cumulative weights live in LDS).
+#include <hip/hip_runtime.h>
+
+#include "rjsmc_internal.h"
+
+namespace rjsmc {
+
+// ------------------------------------------------------------------ Philox4x32-10 ----
+// Counter-based generator of Salmon, Moraes, Dror and Shaw (SC'11): ten rounds of two
+// 32x32->64 multiplies with the Philox multipliers, with the key bumped by the Weyl
+// constants between rounds.
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u, kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u, kPhiloxW1 = 0xBB67AE85u;
+constexpr uint32_t kDomainInit = 0x40000000u, kDomainResample = 0x80000000u;
+
+__device__ __forceinline__ void philox10(uint32_t c[4], uint64_t seed) {
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += kPhiloxW0;
+      k1 += kPhiloxW1;
+    }
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * c[0];
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = (uint32_t)p1;
+    c[2] = n2;
+    c[3] = (uint32_t)p0;
+  }
+}
+
+__device__ __forceinline__ void bits53(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint64_t &x0, uint64_t &x1) {
+  uint32_t c[4] = {c0, c1, c2, c3};
+  philox10(c, seed);
+  x0 = ((uint64_t)c[0] << 21) | (c[1] >> 11);
+  x1 = ((uint64_t)c[2] << 21) | (c[3] >> 11);
+}
+
+// Two uniforms on (0, 1): (x + 0.5) 2^-53.
+__device__ __forceinline__ void uniforms(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                         double &u0, double &u1) {
+  uint64_t x0, x1;
+  bits53(seed, c0, c1, c2, c3, x0, x1);
+  u0 = ((double)x0 + 0.5) * 0x1.0p-53;
+  u1 = ((double)x1 + 0.5) * 0x1.0p-53;
+}
+
+// Box-Muller: first normal of the pair.
+__device__ __forceinline__ double normal0(double u1, double u2) {
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586477 * u2);
+}
+
+// lo + (hi - lo) u with each operation rounded separately (no fused multiply-add).
+__device__ __forceinline__ double affine(double lo, double hi, double u) {
+#pragma clang fp contract(off)
+  return lo + (hi - lo) * u;
+}
+
+// a + b c with the product rounded before the sum.
+__device__ __forceinline__ double madd_rn(double a, double b, double c) {
+#pragma clang fp contract(off)
+  return a + b * c;
+}
+
+// ------------------------------------------------------------------------ prior ------
+__global__ __launch_bounds__(256) void init_prior_kernel(DevParticlesW p, SmcShape sh, rjsmc_prior pr,
+                                                         uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const int64_t S = p.stride;
+  const int kc = sh.kc, km = sh.km;
+  auto u_at = [&](int idx) {
+    double a, b;
+    uniforms(seed, (uint32_t)i, 0u, (uint32_t)(idx >> 1), kDomainInit, a, b);
+    return (idx & 1) ? b : a;
+  };
+  int kap = (int)(u_at(0) * (double)(kc + 1));
+  kap = kap > kc ? kc : kap;
+  int lam = (int)(u_at(1) * (double)(km + 1));
+  lam = lam > km ? km : lam;
+  p.kappa[i] = kap;
+  p.lambda[i] = lam;
+  p.phi_b[i] = affine(pr.phi_lo, pr.phi_hi, u_at(2));
+  p.log10_tau[i] = affine(pr.ltau_lo, pr.ltau_hi, u_at(3));
+  p.c[i] = affine(pr.c_lo, pr.c_hi, u_at(4));
+  double z[kMaxLayers];
+  // conductivity interfaces: sorted depths, properties in draw order
+  for (int j = 0; j < kap; ++j) {
+    const double v = sh.z_max * u_at(6 + j);
+    int t = j;
+    while (t > 0 && z[t - 1] > v) {
+      z[t] = z[t - 1];
+      --t;
+    }
+    z[t] = v;
+  }
+  for (int j = 0; j < kc; ++j) {
+    p.z_cond[(int64_t)j * S + i] = j < kap ? z[j] : 0.0;
+    p.phi[(int64_t)j * S + i] = j < kap ? affine(pr.phi_lo, pr.phi_hi, u_at(6 + kc + j)) : 0.0;
+  }
+  const int base2 = 6 + 2 * kc;
+  for (int j = 0; j < lam; ++j) {
+    const double v = sh.z_max * u_at(base2 + j);
+    int t = j;
+    while (t > 0 && z[t - 1] > v) {
+      z[t] = z[t - 1];
+      --t;
+    }
+    z[t] = v;
+  }
+  for (int j = 0; j < km; ++j) {
+    p.z_charg[(int64_t)j * S + i] = j < lam ? z[j] : 0.0;
+    p.m[(int64_t)j * S + i] = j < lam ? affine(pr.m_lo, pr.m_hi, u_at(base2 + km + j)) : 0.0;
+  }
+}
+
+hipError_t launch_init_prior(const DevParticlesW &p, const SmcShape &sh, const rjsmc_prior &pr, uint64_t seed,
+                             hipStream_t stream) {
+  const int64_t blocks = (p.n + 255) / 256;
+  hipLaunchKernelGGL(init_prior_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, sh, pr, seed);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------- reweight / resample -----
+constexpr int kRwThreads = 512;
+constexpr int kRwWaves = kRwThreads / kWave;
+constexpr int kMaxPerSounding = 2048;
+constexpr int kMaxModels = 128;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+struct RwShared {
+  double ll[kMaxPerSounding];
+  uint64_t cum[kMaxPerSounding];
+  int16_t idx[kMaxPerSounding];     // particles sorted by (model, index)
+  uint8_t mod[kMaxPerSounding];
+  int cnt[kMaxModels], base[kMaxModels], off[kMaxModels];
+  double mx[kMaxModels], s1[kMaxModels], s2[kMaxModels];
+  uint64_t U[kMaxModels];
+  double tess;
+};
+
+// Per-model sums of w = exp(dg (ll - max_k)) and w^2, then TESS (all threads call).
+__device__ double eval_tess(RwShared &sm, double dg, int M) {
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  for (int m = wave; m < M; m += kRwWaves) {
+    const int n = sm.cnt[m];
+    if (n == 0) continue;
+    const double mx = sm.mx[m];
+    double a = 0.0, b = 0.0;
+    if (mx > -HUGE_VAL) {
+      for (int q = lane; q < n; q += kWave) {
+        const double w = exp(dg * (sm.ll[sm.idx[sm.base[m] + q]] - mx));
+        a += w;
+        b += w * w;
+      }
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+      sm.s1[m] = a;
+      sm.s2[m] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int m = 0; m < M; ++m)
+      if (sm.cnt[m] > 0 && sm.mx[m] > -HUGE_VAL) t += sm.s1[m] * sm.s1[m] / sm.s2[m];
+    sm.tess = t;
+  }
+  __syncthreads();
+  return sm.tess;
+}
+
+// floor(((j << 53) + U) * T / (n << 53)) for j < n <= 2048, U < 2^53, T < 2^62.
+__device__ __forceinline__ uint64_t sys_threshold(uint64_t j, uint64_t U, uint64_t T, uint64_t n) {
+  const uint64_t A = (j << 53) + U;
+  const uint64_t lo = A * T, hi = __umul64hi(A, T);
+  // P1 = floor(A T / 2^53) as (p_hi, p_lo)
+  const uint64_t p_lo = (hi << 11) | (lo >> 53);
+  const uint64_t p_hi = hi >> 53;
+  // long division of (p_hi, p_lo) by n in 32-bit digits
+  uint64_t r = p_hi % n;
+  uint64_t t1 = (r << 32) | (p_lo >> 32);
+  const uint64_t q1 = t1 / n;
+  r = t1 % n;
+  const uint64_t t2 = (r << 32) | (p_lo & 0xffffffffull);
+  const uint64_t q2 = t2 / n;
+  return (q1 << 32) | q2;
+}
+
+__global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape sh, rjsmc_reweight_args a,
+                                                                       DevParticles in, const double *ll_in,
+                                                                       double *gamma, double *log_z,
+                                                                       int32_t *active, int32_t *anc, int *flags) {
+  __shared__ RwShared sm;
+  const int s = blockIdx.x;
+  const int N = (int)(in.n_per_sounding > 0 ? in.n_per_sounding : in.n);
+  const int64_t off = (int64_t)s * N;
+  const int M = sh.n_models;
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
+  const double g0 = gamma[s];
+  if (!(g0 < 1.0)) {
+    for (int i = tid; i < N; i += kRwThreads) anc[off + i] = (int32_t)(off + i);
+    if (tid == 0 && active) active[s] = 0;
+    return;
+  }
+  for (int m = tid; m < M; m += kRwThreads) {
+    sm.cnt[m] = 0;
+    sm.mx[m] = -HUGE_VAL;
+  }
+  __syncthreads();
+  for (int i = tid; i < N; i += kRwThreads) {
+    const int kap = in.kappa[off + i], lam = in.lambda[off + i];
+    const bool okc = kap >= 0 && kap <= sh.kc && lam >= 0 && lam <= sh.km;
+    // a particle with counts outside the capacities is flagged and given -inf weight
+    sm.ll[i] = okc ? ll_in[off + i] : -HUGE_VAL;
+    if (!okc) atomicOr(flags, kFlagCapacity);
+    const int m = okc ? kap * (sh.km + 1) + lam : 0;
+    sm.mod[i] = (uint8_t)m;
+    atomicAdd(&sm.cnt[m], 1);
+  }
+  __syncthreads();
+  // stable counting sort by model: wave 0 walks 64-particle chunks in order
+  if (wave == 0) {
+    if (lane == 0) {
+      int acc = 0;
+      for (int m = 0; m < M; ++m) {
+        sm.base[m] = acc;
+        sm.off[m] = acc;
+        acc += sm.cnt[m];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    for (int c0 = 0; c0 < N; c0 += kWave) {
+      const int i = c0 + lane;
+      const int m = i < N ? sm.mod[i] : -1;
+      bool todo = i < N;
+      while (__any(todo)) {
+        const uint64_t pend = __ballot(todo);
+        const int leader = __ffsll((unsigned long long)pend) - 1;
+        const int lm = __shfl(m, leader);
+        const bool mine = todo && m == lm;
+        const uint64_t match = __ballot(mine);
+        const int rank = __popcll(match & ((1ull << lane) - 1));
+        const int basepos = sm.off[lm];
+        if (mine) {
+          sm.idx[basepos + rank] = (int16_t)i;
+          todo = false;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        if (lane == leader) sm.off[lm] = basepos + __popcll(match);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+  }
+  __syncthreads();
+  // per-model maxima and resampling uniforms
+  for (int m = wave; m < M; m += kRwWaves) {
+    const int n = sm.cnt[m];
+    double v = -HUGE_VAL;
+    for (int q = lane; q < n; q += kWave) v = fmax(v, sm.ll[sm.idx[sm.base[m] + q]]);
+    v = wave_max(v);
+    if (lane == 0) {
+      sm.mx[m] = v;
+      uint64_t x0, x1;
+      bits53(a.seed, (uint32_t)s, (uint32_t)a.step, (uint32_t)m, kDomainResample, x0, x1);
+      sm.U[m] = x0;
+    }
+  }
+  __syncthreads();
+  // temperature increment
+  const double target = a.alpha_tess * (double)N;
+  double hi = 1.0 - g0, dg;
+  bool full = eval_tess(sm, hi, M) >= target;
+  if (full) {
+    dg = hi;
+  } else {
+    double lo = 0.0;
+    for (int it = 0; it < 60; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (eval_tess(sm, mid, M) >= target)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    dg = lo;
+  }
+  eval_tess(sm, dg, M);   // s1 at the chosen increment
+  // evidence, quantised weights and per-model cumulative sums (wave per model)
+  for (int m = wave; m < M; m += kRwWaves) {
+    const int n = sm.cnt[m];
+    if (n == 0) continue;
+    const double mx = sm.mx[m];
+    const bool live = mx > -HUGE_VAL;
+    const double inv = live ? 1.0 / sm.s1[m] : 0.0;
+    if (lane == 0) {
+      double &lz = log_z[(int64_t)s * M + m];
+      lz = live ? lz + dg * mx + log(sm.s1[m]) - log((double)n) : -HUGE_VAL;
+    }
+    uint64_t carry = 0;
+    for (int q0 = 0; q0 < n; q0 += kWave) {
+      const int q = q0 + lane;
+      uint64_t v = 0;
+      if (q < n && live) {
+        const double w = exp(dg * (sm.ll[sm.idx[sm.base[m] + q]] - mx)) * inv;
+        v = (uint64_t)rint(w * 0x1.0p60);
+      }
+      // inclusive scan over the wave
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint64_t t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+      }
+      if (q < n) sm.cum[sm.base[m] + q] = carry + v;
+      carry += __shfl(v, kWave - 1);
+    }
+  }
+  __syncthreads();
+  // ancestors: member j of model m takes the first member whose cumulative weight
+  // exceeds the j-th systematic threshold
+  for (int pos = tid; pos < N; pos += kRwThreads) {
+    const int dest = sm.idx[pos];
+    if (dest < 0 || dest >= N) {       // cannot happen for a complete sort; never write outside
+      atomicOr(flags, kFlagUnsorted);
+      continue;
+    }
+    const int m = sm.mod[dest];
+    const int b = sm.base[m], n = sm.cnt[m];
+    const uint64_t T = sm.cum[b + n - 1];
+    int src = dest;
+    if (T > 0) {
+      const uint64_t thr = sys_threshold((uint64_t)(pos - b), sm.U[m], T, (uint64_t)n);
+      int lo = 0, hi2 = n - 1;       // first q with cum[q] > thr (exists: cum[n-1] = T > thr)
+      while (lo < hi2) {
+        const int mid = (lo + hi2) >> 1;
+        if (sm.cum[b + mid] > thr)
+          hi2 = mid;
+        else
+          lo = mid + 1;
+      }
+      src = sm.idx[b + lo];
+      if (src < 0 || src >= N) src = dest;
+    }
+    anc[off + dest] = (int32_t)(off + src);
+  }
+  if (tid == 0) {
+    gamma[s] = full ? 1.0 : g0 + dg;
+    if (active) active[s] = 1;
+  }
+}
+
+// out[i] = in[anc[i]] for every array of the population, ll_out[i] = ll_in[anc[i]].
+__global__ __launch_bounds__(256) void gather_kernel(DevParticles in, const double *ll_in, DevParticlesW out,
+                                                     double *ll_out, const int32_t *anc, int rows_c, int rows_m,
+                                                     int rows_zm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= in.n) return;
+  int64_t a = anc[i];
+  if (a < 0 || a >= in.n) a = i;
+  const int64_t Si = in.stride, So = out.stride;
+  out.kappa[i] = in.kappa[a];
+  if (out.lambda) out.lambda[i] = in.lambda ? in.lambda[a] : 0;
+  out.phi_b[i] = in.phi_b[a];
+  out.log10_tau[i] = in.log10_tau[a];
+  out.c[i] = in.c[a];
+  ll_out[i] = ll_in[a];
+  for (int r = 0; r < rows_c; ++r) {
+    out.phi[r * So + i] = in.phi[r * Si + a];
+    out.z_cond[r * So + i] = in.z_cond[r * Si + a];
+  }
+  for (int r = 0; r < rows_m; ++r) out.m[r * So + i] = in.m[r * Si + a];
+  for (int r = 0; r < rows_zm; ++r) out.z_charg[r * So + i] = in.z_charg[r * Si + a];
+}
+
+hipError_t launch_reweight_resample(const SmcShape &sh, const rjsmc_reweight_args &a, const DevParticles &in,
+                                    const double *ll_in, const DevParticlesW &out, double *ll_out, double *gamma,
+                                    double *log_z, int32_t *active, int32_t *anc, int *flags, hipStream_t stream) {
+  hipLaunchKernelGGL(reweight_resample_kernel, dim3((unsigned)a.n_sound), dim3(kRwThreads), 0, stream, sh, a, in,
+                     ll_in, gamma, log_z, active, anc, flags);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const bool dec = in.layout == RJSMC_LAYOUT_DECOUPLED;
+  const int64_t blocks = (in.n + 255) / 256;
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, in, ll_in, out, ll_out, anc, sh.kc,
+                     dec ? sh.km : sh.kc + 1, dec ? sh.km : 0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- parameter vectors --
+// theta = (phi_b, phi_1..k, z_1..k, m_1..l, zm_1..l, log10 tau, c) of a decoupled particle.
+__device__ __forceinline__ double theta_get(const DevParticles &p, int64_t i, int k, int l, int a) {
+  const int64_t S = p.stride;
+  if (a == 0) return p.phi_b[i];
+  a -= 1;
+  if (a < k) return p.phi[a * S + i];
+  a -= k;
+  if (a < k) return p.z_cond[a * S + i];
+  a -= k;
+  if (a < l) return p.m[a * S + i];
+  a -= l;
+  if (a < l) return p.z_charg[a * S + i];
+  a -= l;
+  return a == 0 ? p.log10_tau[i] : p.c[i];
+}
+
+__device__ __forceinline__ double prior_sd(const rjsmc_prior &pr, double zmax, int k, int l, int a) {
+  const double r12 = 0.28867513459481288225;   // 1/sqrt(12)
+  if (a <= k) return (pr.phi_hi - pr.phi_lo) * r12;
+  if (a <= 2 * k) return zmax * r12;
+  if (a <= 2 * k + l) return (pr.m_hi - pr.m_lo) * r12;
+  if (a <= 2 * k + 2 * l) return zmax * r12;
+  return a == 2 * k + 2 * l + 1 ? (pr.ltau_hi - pr.ltau_lo) * r12 : (pr.c_hi - pr.c_lo) * r12;
+}
+
+// ---------------------------------------------------------------------- adaptation ---
+// One wavefront per (sounding, model): member list, sample mean and covariance in LDS,
+// cyclic Jacobi eigen-decomposition, factor F = U diag(sqrt(Lambda)) with eigenvalues in
+// descending order and each direction signed so that its largest-magnitude component is
+// positive.
+constexpr int kDimMax = 3 + 2 * (kMaxLayers - 1);   // 33
+
+__global__ __launch_bounds__(kWave) void adapt_kernel(SmcShape sh, DevParticles p, rjsmc_prior pr, double *factors) {
+  __shared__ int16_t mem[kMaxPerSounding];
+  __shared__ double A[kDimMax][kDimMax + 1];
+  __shared__ double V[kDimMax][kDimMax + 1];
+  __shared__ double mu[kDimMax];
+  __shared__ double X[kWave][kDimMax + 1];
+  __shared__ int order[kDimMax];
+  const int lane = threadIdx.x;
+  const int M = sh.n_models;
+  const int s = blockIdx.x / M, m = blockIdx.x % M;
+  const int N = (int)(p.n_per_sounding > 0 ? p.n_per_sounding : p.n);
+  const int64_t off = (int64_t)s * N;
+  const int k = m / (sh.km + 1), l = m % (sh.km + 1);
+  const int d = 3 + 2 * k + 2 * l, D = sh.dmax;
+  double *F = factors + (int64_t)blockIdx.x * D * D;
+  // members in index order
+  int nm = 0;
+  for (int c0 = 0; c0 < N; c0 += kWave) {
+    const int i = c0 + lane;
+    const bool sel = i < N && p.kappa[off + i] == k && p.lambda[off + i] == l;
+    const uint64_t b = __ballot(sel);
+    if (sel) mem[nm + __popcll(b & ((1ull << lane) - 1))] = (int16_t)i;
+    nm += __popcll(b);
+  }
+  __syncthreads();
+  for (int t = lane; t < D * D; t += kWave) F[t] = 0.0;
+  if (nm <= d) {
+    for (int a = lane; a < d; a += kWave) F[a * D + a] = 0.1 * prior_sd(pr, sh.z_max, k, l, a);
+    return;
+  }
+  // mean
+  for (int a = lane; a < d; a += kWave) {
+    double acc = 0.0;
+    for (int q = 0; q < nm; ++q) acc += theta_get(p, off + mem[q], k, l, a);
+    mu[a] = acc / (double)nm;
+  }
+  for (int t = lane; t < d * d; t += kWave) A[t / d][t % d] = 0.0;
+  __syncthreads();
+  // covariance: stage 64 centred members at a time
+  for (int q0 = 0; q0 < nm; q0 += kWave) {
+    const int q = q0 + lane;
+    if (q < nm)
+      for (int a = 0; a < d; ++a) X[lane][a] = theta_get(p, off + mem[q], k, l, a) - mu[a];
+    __syncthreads();
+    const int nq = nm - q0 < kWave ? nm - q0 : kWave;
+    for (int t = lane; t < d * d; t += kWave) {
+      const int a = t / d, b = t % d;
+      if (b < a) continue;
+      double acc = A[a][b];
+      for (int r = 0; r < nq; ++r) acc += X[r][a] * X[r][b];
+      A[a][b] = acc;
+    }
+    __syncthreads();
+  }
+  for (int t = lane; t < d * d; t += kWave) {
+    const int a = t / d, b = t % d;
+    if (b >= a) {
+      const double v = A[a][b] / (double)(nm - 1);
+      A[a][b] = v;
+    }
+  }
+  __syncthreads();
+  for (int t = lane; t < d * d; t += kWave) {
+    const int a = t / d, b = t % d;
+    if (b < a) A[a][b] = A[b][a];
+    V[a][b] = a == b ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // cyclic Jacobi sweeps until the off-diagonal mass is negligible
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double offn = 0.0, diag = 0.0;
+    for (int t = lane; t < d * d; t += kWave) {
+      const int a = t / d, b = t % d;
+      if (a != b) offn += A[a][b] * A[a][b];
+      else diag += A[a][b] * A[a][b];
+    }
+    offn = wave_sum(offn);
+    diag = wave_sum(diag);
+    if (!(offn > 1e-30 * diag)) break;
+    for (int pp = 0; pp < d - 1; ++pp)
+      for (int qq = pp + 1; qq < d; ++qq) {
+        const double apq = A[pp][qq];
+        if (apq == 0.0) continue;
+        const double theta = (A[qq][qq] - A[pp][pp]) / (2.0 * apq);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double cth = 1.0 / sqrt(t * t + 1.0), sth = t * cth;
+        __syncthreads();
+        for (int r = lane; r < d; r += kWave) {
+          if (r != pp && r != qq) {
+            const double arp = A[r][pp], arq = A[r][qq];
+            A[r][pp] = cth * arp - sth * arq;
+            A[pp][r] = A[r][pp];
+            A[r][qq] = sth * arp + cth * arq;
+            A[qq][r] = A[r][qq];
+          }
+          const double vrp = V[r][pp], vrq = V[r][qq];
+          V[r][pp] = cth * vrp - sth * vrq;
+          V[r][qq] = sth * vrp + cth * vrq;
+        }
+        __syncthreads();
+        if (lane == 0) {
+          A[pp][pp] = A[pp][pp] - t * apq;
+          A[qq][qq] = A[qq][qq] + t * apq;
+          A[pp][qq] = 0.0;
+          A[qq][pp] = 0.0;
+        }
+        __syncthreads();
+      }
+  }
+  // descending eigenvalue order (stable selection by lane 0)
+  if (lane == 0) {
+    for (int a = 0; a < d; ++a) order[a] = a;
+    for (int a = 1; a < d; ++a) {
+      const int v = order[a];
+      int b = a;
+      while (b > 0 && A[order[b - 1]][order[b - 1]] < A[v][v]) {
+        order[b] = order[b - 1];
+        --b;
+      }
+      order[b] = v;
+    }
+  }
+  __syncthreads();
+  for (int r = lane; r < d; r += kWave) {
+    const int c = order[r];
+    const double ev = A[c][c] > 0.0 ? sqrt(A[c][c]) : 0.0;
+    int big = 0;
+    for (int a = 1; a < d; ++a)
+      if (fabs(V[a][c]) > fabs(V[big][c])) big = a;
+    const double sg = V[big][c] < 0.0 ? -1.0 : 1.0;
+    for (int a = 0; a < d; ++a) F[r * D + a] = sg * ev * V[a][c];
+  }
+}
+
+hipError_t launch_adapt(const SmcShape &sh, const DevParticles &p, int n_sound, const rjsmc_prior &pr,
+                        double *factors, hipStream_t stream) {
+  hipLaunchKernelGGL(adapt_kernel, dim3((unsigned)(n_sound * sh.n_models)), dim3(kWave), 0, stream, sh, p, pr,
+                     factors);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------ mutation ---
+__device__ __forceinline__ int draw_type(const rjsmc_mutate_args &a, double u0) {
+  double cum[RJSMC_N_MOVES];
+  double acc = 0.0;
+  for (int t = 0; t < RJSMC_N_MOVES; ++t) {
+    acc += a.move_prob[t];
+    cum[t] = acc;
+  }
+  const double x = u0 * acc;
+  for (int t = 0; t < RJSMC_N_MOVES; ++t)
+    if (x < cum[t]) return t;
+  return RJSMC_N_MOVES - 1;
+}
+
+__device__ __forceinline__ bool in_range(double v, double lo, double hi) { return v >= lo && v <= hi; }
+
+// Proposal of move `move` for every particle: the proposal is written to `prop`;
+// mask[i] = 1 if it needs a likelihood, type[i] = move type (-1: inactive sounding).
+__global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_args a, int move, DevParticles st,
+                                                      DevParticlesW prop, int32_t *mask, int32_t *type,
+                                                      const int32_t *active) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= st.n) return;
+  const int64_t snd = st.n_per_sounding > 0 ? i / st.n_per_sounding : 0;
+  const int64_t S = st.stride, So = prop.stride;
+  if (active && !active[snd]) {
+    mask[i] = 0;
+    type[i] = -1;
+    return;
+  }
+  const int kc = sh.kc, km = sh.km;
+  const rjsmc_prior &pr = a.prior;
+  double u0, ua, u1, u2, u3, u4;
+  uniforms(a.seed, (uint32_t)i, (uint32_t)a.step, (uint32_t)move, 0u, u0, ua);
+  uniforms(a.seed, (uint32_t)i, (uint32_t)a.step, (uint32_t)move, 1u, u1, u2);
+  uniforms(a.seed, (uint32_t)i, (uint32_t)a.step, (uint32_t)move, 2u, u3, u4);
+  const int t = draw_type(a, u0);
+  int k = st.kappa[i], l = st.lambda[i];
+  if (k < 0 || k > kc || l < 0 || l > km) {   // outside the capacities: left unchanged
+    mask[i] = 0;
+    type[i] = -1;
+    return;
+  }
+  double zc[kMaxLayers], ph[kMaxLayers], zm[kMaxLayers], mm[kMaxLayers];
+  for (int j = 0; j < k; ++j) {
+    zc[j] = st.z_cond[j * S + i];
+    ph[j] = st.phi[j * S + i];
+  }
+  for (int j = 0; j < l; ++j) {
+    zm[j] = st.z_charg[j * S + i];
+    mm[j] = st.m[j * S + i];
+  }
+  double phb = st.phi_b[i], lt = st.log10_tau[i], cc = st.c[i];
+  bool ok = false;
+  if (t == RJSMC_MOVE_SIGMA_BIRTH || t == RJSMC_MOVE_M_BIRTH) {
+    const bool sig = t == RJSMC_MOVE_SIGMA_BIRTH;
+    int &n = sig ? k : l;
+    double *z = sig ? zc : zm, *v = sig ? ph : mm;
+    if (n < (sig ? kc : km)) {
+      const double zn = sh.z_max * u1;
+      const double vn = sig ? affine(pr.phi_lo, pr.phi_hi, u2) : affine(pr.m_lo, pr.m_hi, u2);
+      int j = 0;
+      while (j < n && z[j] < zn) ++j;
+      for (int q = n; q > j; --q) {
+        z[q] = z[q - 1];
+        v[q] = v[q - 1];
+      }
+      z[j] = zn;
+      v[j] = vn;
+      ++n;
+      ok = true;
+    }
+  } else if (t == RJSMC_MOVE_SIGMA_DEATH || t == RJSMC_MOVE_M_DEATH) {
+    const bool sig = t == RJSMC_MOVE_SIGMA_DEATH;
+    int &n = sig ? k : l;
+    double *z = sig ? zc : zm, *v = sig ? ph : mm;
+    if (n > 0) {
+      int j = (int)(u1 * (double)n);
+      j = j > n - 1 ? n - 1 : j;
+      for (int q = j; q + 1 < n; ++q) {
+        z[q] = z[q + 1];
+        v[q] = v[q + 1];
+      }
+      --n;
+      ok = true;
+    }
+  } else if (t == RJSMC_MOVE_SIGMA_MOVE || t == RJSMC_MOVE_M_MOVE) {
+    const bool sig = t == RJSMC_MOVE_SIGMA_MOVE;
+    const int n = sig ? k : l;
+    double *z = sig ? zc : zm;
+    if (n > 0) {
+      int j = (int)(u1 * (double)n);
+      j = j > n - 1 ? n - 1 : j;
+      const double zn = madd_rn(z[j], a.z_move_sd, normal0(u2, u3));
+      const double lo = j > 0 ? z[j - 1] : 0.0;
+      const double hi = j + 1 < n ? z[j + 1] : sh.z_max;
+      if (lo < zn && zn < hi && zn > 0.0) {
+        z[j] = zn;
+        ok = true;
+      }
+    }
+  } else if (t == RJSMC_MOVE_WITHIN_RW) {
+    const int d = 3 + 2 * k + 2 * l;
+    int r = (int)(u1 * (double)d);
+    r = r > d - 1 ? d - 1 : r;
+    const int mdl = k * (km + 1) + l;
+    const double *Fr = a.factors + ((snd * sh.n_models + mdl) * (int64_t)sh.dmax + r) * sh.dmax;
+    const double step = a.rw_scale * normal0(u2, u3);
+    // theta' = theta + step F[:, r] in parameter-vector order
+    int q = 0;
+    phb = madd_rn(phb, step, Fr[q++]);
+    for (int j = 0; j < k; ++j) ph[j] = madd_rn(ph[j], step, Fr[q++]);
+    for (int j = 0; j < k; ++j) zc[j] = madd_rn(zc[j], step, Fr[q++]);
+    for (int j = 0; j < l; ++j) mm[j] = madd_rn(mm[j], step, Fr[q++]);
+    for (int j = 0; j < l; ++j) zm[j] = madd_rn(zm[j], step, Fr[q++]);
+    lt = madd_rn(lt, step, Fr[q++]);
+    cc = madd_rn(cc, step, Fr[q++]);
+    ok = in_range(phb, pr.phi_lo, pr.phi_hi) && in_range(lt, pr.ltau_lo, pr.ltau_hi) &&
+         in_range(cc, pr.c_lo, pr.c_hi);
+    for (int j = 0; j < k; ++j)
+      ok = ok && in_range(ph[j], pr.phi_lo, pr.phi_hi) && zc[j] > 0.0 && zc[j] < sh.z_max &&
+           (j == 0 || zc[j] > zc[j - 1]);
+    for (int j = 0; j < l; ++j)
+      ok = ok && in_range(mm[j], pr.m_lo, pr.m_hi) && zm[j] > 0.0 && zm[j] < sh.z_max &&
+           (j == 0 || zm[j] > zm[j - 1]);
+  }
+  mask[i] = ok ? 1 : 0;
+  type[i] = t;
+  if (!ok) return;
+  prop.kappa[i] = k;
+  prop.lambda[i] = l;
+  prop.phi_b[i] = phb;
+  prop.log10_tau[i] = lt;
+  prop.c[i] = cc;
+  for (int j = 0; j < kc; ++j) {
+    prop.z_cond[j * So + i] = j < k ? zc[j] : 0.0;
+    prop.phi[j * So + i] = j < k ? ph[j] : 0.0;
+  }
+  for (int j = 0; j < km; ++j) {
+    prop.z_charg[j * So + i] = j < l ? zm[j] : 0.0;
+    prop.m[j * So + i] = j < l ? mm[j] : 0.0;
+  }
+}
+
+// Metropolis-Hastings decision: accept when ln u < gamma (ll' - ll).
+__global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_args a, int move, DevParticlesW st,
+                                                     double *ll, DevParticles prop, const double *ll_prop,
+                                                     const int32_t *mask, const int32_t *type, const double *gamma,
+                                                     int64_t *stats) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = i < st.n;
+  const int t = in ? type[i] : -1;
+  bool acc = false;
+  if (in && t >= 0 && mask[i]) {
+    const int64_t snd = st.n_per_sounding > 0 ? i / st.n_per_sounding : 0;
+    double u0, ua;
+    uniforms(a.seed, (uint32_t)i, (uint32_t)a.step, (uint32_t)move, 0u, u0, ua);
+    const double margin = gamma[snd] * (ll_prop[i] - ll[i]) - log(ua);
+    acc = margin > 0.0;
+    if (acc) {
+      const int64_t S = st.stride, Sp = prop.stride;
+      st.kappa[i] = prop.kappa[i];
+      st.lambda[i] = prop.lambda[i];
+      st.phi_b[i] = prop.phi_b[i];
+      st.log10_tau[i] = prop.log10_tau[i];
+      st.c[i] = prop.c[i];
+      for (int j = 0; j < sh.kc; ++j) {
+        st.z_cond[j * S + i] = prop.z_cond[j * Sp + i];
+        st.phi[j * S + i] = prop.phi[j * Sp + i];
+      }
+      for (int j = 0; j < sh.km; ++j) {
+        st.z_charg[j * S + i] = prop.z_charg[j * Sp + i];
+        st.m[j * S + i] = prop.m[j * Sp + i];
+      }
+      ll[i] = ll_prop[i];
+    }
+  }
+  if (stats) {
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int q = 0; q < RJSMC_N_MOVES; ++q) {
+      const int np = __popcll(__ballot(t == q));
+      const int na = __popcll(__ballot(t == q && acc));
+      if (lane == 0 && np) atomicAdd((unsigned long long *)&stats[q], (unsigned long long)np);
+      if (lane == 0 && na) atomicAdd((unsigned long long *)&stats[RJSMC_N_MOVES + q], (unsigned long long)na);
+    }
+  }
+}
+
+hipError_t launch_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticles &state,
+                          const DevParticlesW &prop, int32_t *mask, int32_t *type, const int32_t *active,
+                          hipStream_t stream) {
+  const int64_t blocks = (state.n + 255) / 256;
+  hipLaunchKernelGGL(propose_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, sh, a, move, state, prop, mask,
+                     type, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_accept(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticlesW &state,
+                         double *ll, const DevParticles &prop, const double *ll_prop, const int32_t *mask,
+                         const int32_t *type, const double *gamma, int64_t *stats, hipStream_t stream) {
+  const int64_t blocks = (state.n + 255) / 256;
+  hipLaunchKernelGGL(accept_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, sh, a, move, state, ll, prop,
+                     ll_prop, mask, type, gamma, stats);
+  return hipGetLastError();
+}
+
+}  // namespace rjsmc

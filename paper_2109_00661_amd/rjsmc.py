@@ -1,0 +1,83 @@
+"""Algorithm 1 (adaptive RJSMC) driven through the C ABI.
+
+The loop below only sequences library calls and swaps buffers: initialisation from the
+prior, then, until every sounding reaches gamma = 1, re-weight + re-sample, adaptation of
+the within-model proposals, and R mutation sweeps.  Every arithmetic step runs in the
+HIP library; torch holds the device buffers.
+"""
+import numpy as np
+
+from . import binding as B
+from . import workloads as W
+
+UNIFORM_MOVES = (1, 1, 1, 1, 1, 1, 1, 0)     # birth/death/move x2 partitions + within-model RW
+
+
+class RJSMCRun:
+    def __init__(self, ctx, n_sound, n_per_sound, y_obs, *, prior=None, alpha=0.5, n_moves=5, seed=0,
+                 move_prob=UNIFORM_MOVES, z_move_frac=0.05, rw_scale=2.38, device="cuda"):
+        import torch
+        self.torch = torch
+        self.ctx = ctx
+        self.S, self.N = n_sound, n_per_sound
+        self.n = n_sound * n_per_sound
+        self.prior = dict(W.PRIOR) if prior is None else prior
+        self.alpha, self.n_moves, self.seed = alpha, n_moves, seed
+        self.move_prob = move_prob
+        self.z_move_sd = z_move_frac * self.prior["z_max"]
+        self.rw_scale = rw_scale
+        kc, km = ctx.kmax_cond, ctx.kmax_charg
+        self.M = (kc + 1) * (km + 1)
+        self.dmax = 3 + 2 * kc + 2 * km
+        nps = n_per_sound if n_sound > 1 else 0
+        self.bufs = [B.empty_device_population(self.n, kc, km, nps, device) for _ in range(2)]
+        self.lls = [torch.empty(self.n, dtype=torch.float64, device=device) for _ in range(2)]
+        self.cur = 0
+        self.gamma = torch.zeros(n_sound, dtype=torch.float64, device=device)
+        self.log_z = torch.zeros((n_sound, self.M), dtype=torch.float64, device=device)
+        self.active = torch.ones(n_sound, dtype=torch.int32, device=device)
+        self.anc = torch.empty(self.n, dtype=torch.int32, device=device)
+        self.factors = torch.zeros((n_sound, self.M, self.dmax, self.dmax), dtype=torch.float64, device=device)
+        self.stats = torch.zeros((2, B.N_MOVES), dtype=torch.int64, device=device)
+        self.y_obs = torch.as_tensor(np.asarray(y_obs, dtype=np.float64), device=device).reshape(n_sound, -1)
+        self.step = 0
+
+    @property
+    def state(self):
+        return self.bufs[self.cur]
+
+    @property
+    def ll(self):
+        return self.lls[self.cur]
+
+    def initialise(self):
+        self.ctx.init_prior(self.state, self.prior, self.seed)
+        self.ctx.loglik(self.state, self.y_obs, out=self.ll)
+
+    def advance(self):
+        """One iteration of the while-loop of Algorithm 1."""
+        self.step += 1
+        nxt = 1 - self.cur
+        self.ctx.reweight_resample(self.bufs[self.cur], self.lls[self.cur], self.bufs[nxt], self.lls[nxt], self.gamma,
+                                   self.log_z, self.active, self.anc, self.alpha, self.seed, self.step, self.S)
+        self.cur = nxt
+        self.ctx.adapt(self.state, self.S, self.prior, self.factors)
+        self.ctx.mutate(self.state, self.ll, self.bufs[1 - self.cur], self.lls[1 - self.cur], self.gamma, self.active,
+                        self.y_obs, self.stats, seed=self.seed, step=self.step, n_moves=self.n_moves,
+                        n_sound=self.S, prior=self.prior, move_prob=self.move_prob, z_move_sd=self.z_move_sd,
+                        rw_scale=self.rw_scale, factors=self.factors)
+
+    def run(self, max_steps=1000):
+        self.initialise()
+        while self.step < max_steps:
+            self.advance()
+            if bool((self.gamma >= 1.0).all()):
+                break
+        self.ctx.check()
+        return self
+
+    def model_probabilities(self):
+        """pi_T(k | y) = N_{T,k} / N per sounding (Section 3.2.1)."""
+        k = self.state["kappa"].cpu().numpy() * (self.ctx.kmax_charg + 1) + self.state["lambda_"].cpu().numpy()
+        k = k.reshape(self.S, self.N)
+        return np.stack([np.bincount(row, minlength=self.M) / self.N for row in k])

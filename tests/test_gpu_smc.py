@@ -1,0 +1,227 @@
+"""GPU parity of the SMC primitives against the oracle.
+
+Bars: integer outputs (counts, ancestors, move-type tallies) bit-exact; prior draws
+bit-exact (same uniforms, uncontracted arithmetic); temperatures, log-evidence and
+proposal factors within FP64 rounding of different summation orders; mutated states
+equal to the oracle's except where the oracle's accept margin gamma (ll' - ll) - ln u
+was within 1e-8 of zero (an accept decision that FP64 rounding may flip).
+"""
+import numpy as np
+import pytest
+
+from paper_2109_00661_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+PR = W.PRIOR
+KC, KM = PR["kmax_cond"], PR["kmax_charg"]
+M = (KC + 1) * (KM + 1)
+D = 3 + 2 * KC + 2 * KM
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2109_00661_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B, system):
+    return B.Context(system, precision="f64", max_particles=4096)
+
+
+def _host(B, p):
+    return B.population_to_host(p)
+
+
+def _assert_pop_equal(a, b, keys=("kappa", "lambda_", "phi_b", "phi", "z_cond", "m", "z_charg", "log10_tau", "c")):
+    for k in keys:
+        assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+
+
+def test_init_prior_bit_exact(B, ctx):
+    from oracle import smc
+    n = 777
+    dp = B.empty_device_population(n, KC, KM)
+    ctx.init_prior(dp, PR, seed=5)
+    ctx.check()
+    ref = smc.init_population(5, n, KC, KM, PR)
+    _assert_pop_equal(_host(B, dp), ref)
+
+
+def _population_with_ll(n_sound, nps, seed, ll_kind="heavy"):
+    from oracle import smc
+    p = smc.init_population(seed, n_sound * nps, KC, KM, PR)
+    p["n_per_sounding"] = nps if n_sound > 1 else 0
+    rng = np.random.default_rng(seed)
+    ll = -np.abs(rng.standard_cauchy(n_sound * nps)) * 50 - rng.uniform(0, 30, n_sound * nps)
+    return p, ll
+
+
+@pytest.mark.parametrize("n_sound,nps", [(1, 256), (3, 1024), (2, 2048), (4, 100)])
+def test_reweight_resample(B, ctx, n_sound, nps):
+    from oracle import smc
+    p, ll = _population_with_ll(n_sound, nps, 31 + nps)
+    gamma = np.linspace(0.0, 0.6, n_sound)
+    if n_sound >= 3:
+        gamma[-1] = 1.0                                  # finished sounding: copied through
+    if n_sound >= 2:
+        sel = (p["kappa"] == 2) & (np.arange(len(ll)) < nps)
+        ll[sel] = -np.inf                                # a dead model in sounding 0
+    log_z = np.random.default_rng(1).normal(0, 1, (n_sound, M))
+    g_ref, lz_ref, anc_ref = smc.reweight_resample(ll, p["kappa"], p["lambda_"], KC, KM, gamma, log_z, 0.5, 77, 3,
+                                                   nps if n_sound > 1 else None)
+    dp = B.particles_to_device(p)
+    out = B.empty_device_population(len(ll), KC, KM, p["n_per_sounding"])
+    ll_d = torch.as_tensor(ll, device="cuda")
+    ll_out = torch.empty_like(ll_d)
+    g_d = torch.as_tensor(gamma, device="cuda")
+    lz_d = torch.as_tensor(log_z, device="cuda")
+    act = torch.zeros(n_sound, dtype=torch.int32, device="cuda")
+    anc = torch.empty(len(ll), dtype=torch.int32, device="cuda")
+    ctx.reweight_resample(dp, ll_d, out, ll_out, g_d, lz_d, act, anc, 0.5, 77, 3, n_sound)
+    ctx.check()
+    g, lz, a = g_d.cpu().numpy(), lz_d.cpu().numpy(), anc.cpu().numpy()
+    np.testing.assert_allclose(g, g_ref, rtol=0, atol=1e-12)
+    fin = np.isfinite(lz_ref)
+    assert np.array_equal(fin, np.isfinite(lz))
+    np.testing.assert_allclose(lz[fin], lz_ref[fin], rtol=1e-11, atol=1e-11)
+    assert np.array_equal(a, anc_ref)
+    assert np.array_equal(act.cpu().numpy(), (gamma < 1).astype(np.int32))
+    _assert_pop_equal(_host(B, out), smc.gather(p, anc_ref))
+    assert np.array_equal(ll_out.cpu().numpy(), ll[anc_ref])
+
+
+def test_reweight_constant_likelihood_one_step(B, ctx):
+    from oracle import smc
+    p = smc.init_population(3, 512, KC, KM, PR)
+    dp = B.particles_to_device(p)
+    out = B.empty_device_population(512, KC, KM)
+    ll = torch.full((512,), -7.5, dtype=torch.float64, device="cuda")
+    g = torch.zeros(1, dtype=torch.float64, device="cuda")
+    lz = torch.zeros((1, M), dtype=torch.float64, device="cuda")
+    anc = torch.empty(512, dtype=torch.int32, device="cuda")
+    ctx.reweight_resample(dp, ll, out, torch.empty_like(ll), g, lz, None, anc, 0.5, 1, 1, 1)
+    ctx.check()
+    assert g.item() == 1.0
+    present = np.unique(smc.model_id(p["kappa"], p["lambda_"], KM))
+    np.testing.assert_allclose(lz.cpu().numpy()[0, present], -7.5, rtol=0, atol=1e-14)
+    assert np.array_equal(anc.cpu().numpy(), np.arange(512))
+
+
+def test_adapt_factors(B, ctx):
+    from oracle import smc
+    nps = 2048
+    p = smc.init_population(8, 2 * nps, KC, KM, PR)
+    p["n_per_sounding"] = nps
+    dp = B.particles_to_device(p)
+    F = torch.zeros((2, M, D, D), dtype=torch.float64, device="cuda")
+    ctx.adapt(dp, 2, PR, F)
+    ctx.check()
+    F = F.cpu().numpy()
+    models = smc.model_id(p["kappa"], p["lambda_"], KM)
+    for s in range(2):
+        for m in range(M):
+            k, l = m // (KM + 1), m % (KM + 1)
+            d = 3 + 2 * k + 2 * l
+            members = np.nonzero(models[s * nps:(s + 1) * nps] == m)[0] + s * nps
+            ref = smc.proposal_factor(p, members, k, l, PR)
+            got = F[s, m, :d, :d].T                      # device column r = direction r
+            assert np.all(F[s, m, d:, :] == 0) and np.all(F[s, m, :, d:] == 0)
+            if len(members) <= d:
+                assert np.array_equal(got, ref)
+                continue
+            C = ref @ ref.T
+            np.testing.assert_allclose(got @ got.T, C, rtol=0, atol=1e-10 * np.abs(C).max())
+            ev = np.sum(ref * ref, axis=0)
+            gap = np.min(np.abs(np.diff(ev))) / ev.max()
+            if gap > 1e-3:
+                np.testing.assert_allclose(got, ref, rtol=0, atol=1e-7 * np.abs(ref).max())
+
+
+def _device_factors(p, nps, n_sound, seed):
+    """Seeded proposal factors (any matrix is a valid factor) in both layouts."""
+    from oracle import smc
+    rng = np.random.default_rng(seed)
+    dev = np.zeros((n_sound, M, D, D))
+    host = {}
+    for s in range(n_sound):
+        for m in range(M):
+            k, l = m // (KM + 1), m % (KM + 1)
+            d = 3 + 2 * k + 2 * l
+            Fm = np.diag(0.05 * smc.prior_sd(k, l, PR)) @ (np.eye(d) + 0.3 * rng.standard_normal((d, d)))
+            host[(s, m)] = Fm
+            dev[s, m, :d, :d] = Fm.T
+    return dev, host
+
+
+@pytest.mark.parametrize("gamma", [0.002, 0.3])
+def test_mutate_against_oracle(B, ctx, system, K_oracle, truth_data, gamma):
+    from oracle import em, smc
+    n, n_moves, seed, step = 64, 3, 123, 4
+    p = smc.init_population(41, n, KC, KM, PR)
+    ll0 = em.loglik(p, system, K_oracle, truth_data)
+    q = dict(move_prob=np.array([1, 1, 1, 1, 1, 1, 1, 0], float), z_move_sd=0.05 * PR["z_max"], rw_scale=2.38)
+    fdev, fhost = _device_factors(p, n, 1, 5)
+    # oracle
+    po = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+    llo = ll0.copy()
+    models = lambda i: smc.model_id(int(po["kappa"][i]), int(po["lambda_"][i]), KM)
+    st_o, margins = smc.mutate(po, llo, lambda pp, i: em.loglik(pp, system, K_oracle, truth_data, [i])[0],
+                               lambda i: gamma, step, seed, q, PR, KC, KM, lambda i: fhost[(0, models(i))], n_moves)
+    # device
+    dp = B.particles_to_device(p)
+    scratch = B.empty_device_population(n, KC, KM)
+    ll_d = torch.as_tensor(ll0, device="cuda")
+    stats = torch.zeros((2, 8), dtype=torch.int64, device="cuda")
+    ctx.mutate(dp, ll_d, scratch, torch.empty_like(ll_d), torch.tensor([gamma], dtype=torch.float64, device="cuda"),
+               None, torch.as_tensor(truth_data, device="cuda"), stats, seed=seed, step=step, n_moves=n_moves,
+               n_sound=1, prior=PR, move_prob=q["move_prob"], z_move_sd=q["z_move_sd"], rw_scale=q["rw_scale"],
+               factors=torch.as_tensor(fdev, device="cuda"))
+    ctx.check()
+    got = _host(B, dp)
+    near = {i for i, r, mg in margins if abs(mg) < 1e-8}
+    ok = [i for i in range(n) if i not in near]
+    assert len(ok) >= n - 2
+    for k in ("kappa", "lambda_"):
+        assert np.array_equal(got[k][ok], po[k][ok]), k
+    for k in ("phi_b", "phi", "z_cond", "m", "z_charg", "log10_tau", "c"):
+        np.testing.assert_allclose(got[k][..., ok], po[k][..., ok], rtol=1e-12, atol=1e-12, err_msg=k)
+    lld = ll_d.cpu().numpy()
+    np.testing.assert_allclose(lld[ok], llo[ok], rtol=1e-9, atol=1e-9)
+    if not near:
+        assert np.array_equal(stats.cpu().numpy(), st_o)
+    assert st_o[1].sum() > 0                             # some moves were accepted
+
+
+def test_mutate_rejects_without_factors(B, ctx, truth_data):
+    dp = B.empty_device_population(8, KC, KM)
+    ctx.init_prior(dp, PR, seed=1)
+    ll = torch.zeros(8, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.RJSMCError):
+        ctx.mutate(dp, ll, B.empty_device_population(8, KC, KM), torch.empty_like(ll),
+                   torch.zeros(1, dtype=torch.float64, device="cuda"), None, torch.as_tensor(truth_data, device="cuda"),
+                   None, seed=1, step=1, n_moves=1, n_sound=1, prior=PR, move_prob=[0, 0, 0, 0, 0, 0, 1, 0],
+                   z_move_sd=15.0, rw_scale=2.38, factors=None)
+
+
+def test_rjsmc_end_to_end_single_sounding(B, system, truth_data):
+    """Algorithm 1 on the synthetic three-layer sounding: reaches gamma = 1, evidence
+    finite for populated models, model probabilities sum to one, a chargeable model
+    (lambda >= 1) is preferred for the chargeable truth."""
+    from paper_2109_00661_amd.rjsmc import RJSMCRun
+    ctx = B.Context(system, precision="f64", max_particles=256)
+    run = RJSMCRun(ctx, 1, 256, truth_data, seed=0).run(max_steps=400)
+    g = run.gamma.cpu().numpy()
+    assert g[0] == 1.0 and 2 <= run.step < 400
+    probs = run.model_probabilities()[0]
+    assert abs(probs.sum() - 1) < 1e-12
+    lz = run.log_z.cpu().numpy()[0]
+    assert np.all(np.isfinite(lz[probs > 0]))
+    lam = np.arange(M) % (KM + 1)
+    assert probs[lam >= 1].sum() > 0.5
+    st = run.stats.cpu().numpy()
+    assert st[1].sum() > 0 and np.all(st[1] <= st[0])
