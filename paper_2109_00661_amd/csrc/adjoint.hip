@@ -1,8 +1,391 @@
+// Log-likelihood and its gradient (reverse sweep) for gfx950.
+//
+// One wavefront per particle, lanes tiling (frequency, filter abscissa) as in the
+// forward kernel.  Phase A evaluates the forward model to obtain y, ll and
+// w_j = d ll / d Im H(w_j) = sum_g K_gj d ll / d y_g.  Phase B revisits every pair: it runs
+// the reflection recursion bottom-up in the classic form, keeping the generalized
+// reflection coefficients r_l of each layer in registers, then sweeps top-down through
+// the air interface and every layer, propagating the adjoint of c_k w_j Im r and
+// accumulating, per frequency, the complex adjoints of the layer wavenumbers
+// k2_l = i w mu0 sigma_hat_l and the adjoints of the thicknesses.  The u_l and E_l of the
+// recursion are recomputed in the sweep instead of stored.  Per frequency the adjoints
+// are mapped through the Cole-Cole terms to (log10 sigma_inf, m) of each merged layer and
+// to (log10 tau, c); after all frequencies the merged-layer gradients are routed back to
+// the particle's parameters through the merge (an interface moves the thickness above
+// and below it).
 #include <hip/hip_runtime.h>
+
+#include "cplx.h"
+#include "merge.h"
+#include "recursion.h"
 #include "rjsmc_internal.h"
+
 namespace rjsmc {
-hipError_t launch_loglik_grad(const DevSystem &, const DevParticles &, int, int, const double *, double *,
-                              const DevGrad &, hipStream_t) {
-  return hipErrorNotSupported;
+
+namespace {
+constexpr int kWavesA = 2;                               // particles per block
+constexpr double kMu0A = 1.25663706143591729539e-06;
+constexpr double kTwoPiA = 6.28318530717958647692;
+constexpr double kLn10 = 2.302585092994045684;
+constexpr double kHalfPi = 1.57079632679489661923;
+}  // namespace
+
+__device__ __forceinline__ cplx<double> crcp_fast(cplx<double> b) {
+  const double inv = fast_rcp(b.re * b.re + b.im * b.im);
+  return {b.re * inv, -b.im * inv};
 }
+__device__ __forceinline__ cplx<double> cdiv_fast(cplx<double> a, cplx<double> b) { return a * crcp_fast(b); }
+
+// Adds the adjoints of one (lam, w) pair with seed wt (the weight of Im r) to
+// G[l] (d(wt r)/d k2_l) and H[l] (Im d(wt r)/d h_l).
+template <int LMAX>
+__device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2, const double *thk, int L,
+                                             double wt, cplx<double> (&G)[LMAX], double (&H)[LMAX]) {
+  const double lam2 = lam * lam;
+  cplx<double> rt[LMAX];            // generalized reflection coefficient below interface l
+  // ---- bottom-up recursion, classic form
+  {
+    cplx<double> ub = csqrt_fast(cplx<double>{lam2 + k2[L - 1].re, k2[L - 1].im});
+#pragma unroll
+    for (int l = LMAX - 2; l >= 0; --l) {
+      if (l <= L - 2) {
+        const cplx<double> u = csqrt_fast(cplx<double>{lam2 + k2[l].re, k2[l].im});
+        const cplx<double> R = cdiv_fast(k2[l] - k2[l + 1], csq(u + ub));
+        if (l == L - 2) {
+          rt[l] = R;
+        } else {
+          const double h2 = -2.0 * thk[l + 1];
+          const cplx<double> E = cexp(cplx<double>{h2 * ub.re, h2 * ub.im});
+          const cplx<double> rho = rt[l + 1] * E;
+          rt[l] = cdiv_fast(R + rho, cplx<double>{1.0, 0.0} + R * rho);
+        }
+        ub = u;
+      }
+    }
+  }
+  // ---- top-down adjoint sweep
+  const cplx<double> one = {1.0, 0.0};
+  cplx<double> ul = csqrt_fast(cplx<double>{lam2 + k2[0].re, k2[0].im});   // u_0
+  const cplx<double> Bair = csq(cplx<double>{lam + ul.re, ul.im});
+  const cplx<double> Aair = {-k2[0].re, -k2[0].im};
+  const cplx<double> Rair = cdiv_fast(Aair, Bair);
+  cplx<double> Rbar_air, rtbar = {0.0, 0.0}, ubar = {0.0, 0.0};
+  const cplx<double> wb = {wt, 0.0};
+  if (L == 1) {
+    Rbar_air = wb;
+  } else {
+    const double h2 = -2.0 * thk[0];
+    const cplx<double> E = cexp(cplx<double>{h2 * ul.re, h2 * ul.im});
+    const cplx<double> rho = rt[0] * E;
+    const cplx<double> den = one + Rair * rho;
+    const cplx<double> iden2 = crcp_fast(csq(den));
+    Rbar_air = wb * (one - csq(rho)) * iden2;
+    const cplx<double> rhobar = wb * (one - csq(Rair)) * iden2;
+    rtbar = rhobar * E;
+    const cplx<double> Ebar = rhobar * rt[0];
+    ubar = Ebar * (h2 * E);                                       // dE/du = -2 h E
+    const cplx<double> hb = Ebar * (-2.0 * (ul * E));             // dE/dh = -2 u E
+    H[0] += hb.im;
+  }
+  // R_air = A / B, A = -k2_0, B = (lam + u_0)^2
+  const cplx<double> Abar_air = cdiv_fast(Rbar_air, Bair);
+  const cplx<double> Bbar_air = {-(Rbar_air * Rair).re, -(Rbar_air * Rair).im};
+  cplx<double> kbar = {-Abar_air.re, -Abar_air.im};               // adjoint of k2_0 (partial)
+  ubar = ubar + cdiv_fast(Bbar_air, Bair) * (2.0 * cplx<double>{lam + ul.re, ul.im});
+  if (L == 1) {
+    kbar = kbar + cdiv_fast(ubar, 2.0 * ul);                      // u_0 = sqrt(lam^2 + k2_0)
+    G[0] = G[0] + kbar;
+    return;
+  }
+#pragma unroll
+  for (int l = 0; l <= LMAX - 2; ++l) {
+    if (l <= L - 2) {
+      const cplx<double> un = csqrt_fast(cplx<double>{lam2 + k2[l + 1].re, k2[l + 1].im});   // u_{l+1}
+      const cplx<double> s = ul + un;
+      const cplx<double> B = csq(s);
+      const cplx<double> A = k2[l] - k2[l + 1];
+      const cplx<double> iB = crcp_fast(B);
+      const cplx<double> R = A * iB;
+      cplx<double> Rbar, rtbar_n = {0.0, 0.0}, ubar_n = {0.0, 0.0};
+      if (l == L - 2) {
+        Rbar = rtbar;
+      } else {
+        const double h2 = -2.0 * thk[l + 1];
+        const cplx<double> E = cexp(cplx<double>{h2 * un.re, h2 * un.im});
+        const cplx<double> rho = rt[l + 1] * E;
+        const cplx<double> iden2 = crcp_fast(csq(one + R * rho));
+        Rbar = rtbar * (one - csq(rho)) * iden2;
+        const cplx<double> rhobar = rtbar * (one - csq(R)) * iden2;
+        rtbar_n = rhobar * E;
+        const cplx<double> Ebar = rhobar * rt[l + 1];
+        ubar_n = Ebar * (h2 * E);
+        const cplx<double> hb = Ebar * (-2.0 * (un * E));
+        H[l + 1] += hb.im;
+      }
+      // R = A / B
+      const cplx<double> Abar = Rbar * iB;
+      const cplx<double> Bbar = {-(Abar * R).re, -(Abar * R).im};
+      const cplx<double> sb = Bbar * (2.0 * s);                   // B = s^2
+      kbar = kbar + Abar;                                          // A = k2_l - k2_{l+1}
+      ubar = ubar + sb;
+      ubar_n = ubar_n + sb;
+      kbar = kbar + cdiv_fast(ubar, 2.0 * ul);                     // u_l complete
+      G[l] = G[l] + kbar;
+      kbar = {-Abar.re, -Abar.im};                                 // partial adjoint of k2_{l+1}
+      ubar = ubar_n;
+      ul = un;
+      rtbar = rtbar_n;
+      if (l == L - 2) {                                            // basement complete
+        kbar = kbar + cdiv_fast(ubar, 2.0 * ul);
+        G[l + 1] = G[l + 1] + kbar;
+      }
+    }
+  }
+}
+
+// Gradient slots per frequency group: [layer sigma (LMAX)][layer m (LMAX)][thickness
+// (LMAX)][log10 tau][c].
+template <int LMAX>
+struct AdjShared {
+  double lam[kMaxHankel], ck[kMaxHankel], omega[kMaxFreq], K[kMaxGate * kMaxFreq], eps2[kMaxGate];
+  LayerStack stack[kWavesA];
+  double wbar[kWavesA][kMaxFreq];
+  double imh[kWavesA][kMaxFreq];
+  double ybar[kWavesA][kMaxGate];
+  cplx<double> k2[kWavesA][8][kMaxLayers];
+  double thk[kWavesA][kMaxLayers];
+  double slot[kWavesA][8][3 * LMAX + 2];
+  double gl[kWavesA][3 * LMAX + 2];
+  double ll[kWavesA];
+};
+
+template <int LMAX>
+__global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem s, DevParticles p, int kc, int km,
+                                                                       const double *y_obs, double *ll, DevGrad g) {
+  __shared__ AdjShared<LMAX> sm;
+  const int nf = s.n_freq, ng = s.n_gate, nhp = s.n_hankel_pad;
+  for (int t = threadIdx.x; t < nhp; t += blockDim.x) {
+    sm.lam[t] = s.lam[t];
+    sm.ck[t] = s.ck[t];
+  }
+  for (int t = threadIdx.x; t < nf; t += blockDim.x) sm.omega[t] = s.omega[t];
+  for (int t = threadIdx.x; t < nf * ng; t += blockDim.x) sm.K[t] = s.K[t];
+  for (int t = threadIdx.x; t < ng; t += blockDim.x) sm.eps2[t] = s.eps_an2[t];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int64_t i = (int64_t)blockIdx.x * kWavesA + wave;
+  const bool valid = i < p.n;
+  LayerStack *st = &sm.stack[wave];
+  constexpr int NS = 3 * LMAX + 2;
+  for (int t = lane; t < 8 * NS; t += kWave) sm.slot[wave][t / NS][t % NS] = 0.0;
+  __syncthreads();
+  const int L = merge_particle(p, i, valid, kc, km, LMAX, st, s.flags);
+
+  double c = 0.0, log_tau = 0.0, spc = 0.0, cpc = 1.0;
+  if (L > 0) {
+    c = p.c[i];
+    log_tau = p.log10_tau[i] * kLn10;
+    sincospi(0.5 * c, &spc, &cpc);
+    if (lane < L - 1) sm.thk[wave][lane] = st->top[lane + 1] - st->top[lane];
+  }
+  const int gl = lane & 7, gw = lane >> 3;
+  const int nhg = nhp >> 3;
+  const int nq = (nf + 7) >> 3;
+  // ---- phase A: forward model
+#pragma unroll 1
+  for (int q = 0; q < nq; ++q) {
+    const int jf = gw + 8 * q;
+    const bool act = L > 0 && jf < nf;
+    if (act) {
+      const double w = sm.omega[jf];
+      const double pw = exp(c * (log(w) + log_tau));
+      const cplx<double> qcc = crcp(cplx<double>{1.0 + pw * cpc, pw * spc});
+      const double wmu = w * kMu0A;
+      for (int l = gl; l < L; l += 8) {
+        const double sg = st->sig[l], mg = st->m[l];
+        const cplx<double> sh = {sg * (1.0 - mg * qcc.re), sg * (-(mg * qcc.im))};
+        sm.k2[wave][gw][l] = cplx<double>{-(wmu * sh.im), wmu * sh.re};
+      }
+    }
+    __syncthreads();
+    if (act) {
+      double acc = 0.0;
+#pragma unroll 1
+      for (int sidx = 0; sidx < nhg; ++sidx) {
+        const int k = gl + 8 * sidx;
+        acc += sm.ck[k] * reflection_im<double>(sm.lam[k], sm.k2[wave][gw], sm.thk[wave], L);
+      }
+      acc += __shfl_xor(acc, 1);
+      acc += __shfl_xor(acc, 2);
+      acc += __shfl_xor(acc, 4);
+      if (gl == 0) sm.imh[wave][jf] = acc;
+    }
+    __syncthreads();
+  }
+  // ---- gates, log-likelihood and its adjoint with respect to the gate responses
+  if (L > 0) {
+    double term = 0.0, ybar = 0.0;
+    if (lane < ng) {
+      double y = 0.0;
+      for (int j = 0; j < nf; ++j) y += sm.K[lane * nf + j] * sm.imh[wave][j];
+      const int64_t snd = p.n_per_sounding > 0 ? i / p.n_per_sounding : 0;
+      const double d = y_obs[snd * ng + lane];
+      const double e = s.eps_mn * y;
+      const double s2 = sm.eps2[lane] + e * e;
+      const double r = d - y;
+      term = r * r / s2 + log(kTwoPiA * s2);
+      // d ll / d y = r/s2 + (r^2/s2^2 - 1/s2) eps_mn^2 y
+      ybar = r / s2 + (r * r / (s2 * s2) - 1.0 / s2) * s.eps_mn * s.eps_mn * y;
+      sm.ybar[wave][lane] = ybar;
+    }
+    term += __shfl_xor(term, 1);
+    term += __shfl_xor(term, 2);
+    term += __shfl_xor(term, 4);
+    term += __shfl_xor(term, 8);
+    term += __shfl_xor(term, 16);
+    term += __shfl_xor(term, 32);
+    if (lane == 0) sm.ll[wave] = -0.5 * term;
+  }
+  __syncthreads();
+  if (L > 0 && lane < nf) {
+    double acc = 0.0;
+    for (int gg = 0; gg < ng; ++gg) acc += sm.K[gg * nf + lane] * sm.ybar[wave][gg];
+    sm.wbar[wave][lane] = acc;
+  }
+  __syncthreads();
+  // ---- phase B: reverse sweep per pair
+#pragma unroll 1
+  for (int q = 0; q < nq; ++q) {
+    const int jf = gw + 8 * q;
+    const bool act = L > 0 && jf < nf;
+    cplx<double> qcc = {0.0, 0.0}, zc = {0.0, 0.0};
+    double w = 0.0;
+    if (act) {
+      w = sm.omega[jf];
+      const double pw = exp(c * (log(w) + log_tau));
+      zc = cplx<double>{pw * cpc, pw * spc};
+      qcc = crcp(cplx<double>{1.0 + zc.re, zc.im});
+      const double wmu = w * kMu0A;
+      for (int l = gl; l < L; l += 8) {
+        const double sg = st->sig[l], mg = st->m[l];
+        const cplx<double> sh = {sg * (1.0 - mg * qcc.re), sg * (-(mg * qcc.im))};
+        sm.k2[wave][gw][l] = cplx<double>{-(wmu * sh.im), wmu * sh.re};
+      }
+    }
+    __syncthreads();
+    if (act) {
+      cplx<double> G[LMAX];
+      double H[LMAX];
+#pragma unroll
+      for (int l = 0; l < LMAX; ++l) {
+        G[l] = {0.0, 0.0};
+        H[l] = 0.0;
+      }
+      const double wj = sm.wbar[wave][jf];
+#pragma unroll 1
+      for (int sidx = 0; sidx < nhg; ++sidx) {
+        const int k = gl + 8 * sidx;
+        pair_adjoint<LMAX>(sm.lam[k], sm.k2[wave][gw], sm.thk[wave], L, sm.ck[k] * wj, G, H);
+      }
+#pragma unroll
+      for (int l = 0; l < LMAX; ++l) {
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) {
+          G[l].re += __shfl_xor(G[l].re, o);
+          G[l].im += __shfl_xor(G[l].im, o);
+          H[l] += __shfl_xor(H[l], o);
+        }
+      }
+      if (gl == 0) {
+        // Cole-Cole chain: k2 = i w mu0 sigma (1 - m q), q = 1/(1 + z), z = (i w tau)^c
+        const cplx<double> iwm = {0.0, w * kMu0A};
+        cplx<double> Gq = {0.0, 0.0};
+        double *sl = sm.slot[wave][gw];
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l) {
+          if (l < L) {
+            const double sg = st->sig[l], mg = st->m[l];
+            const cplx<double> dsig = iwm * (cplx<double>{1.0, 0.0} - mg * qcc);
+            sl[l] += (G[l] * dsig).im * kLn10 * sg;                       // d / d log10 sigma
+            sl[LMAX + l] += (G[l] * (iwm * (-sg * qcc))).im;              // d / d m
+            Gq = Gq + G[l] * (iwm * cplx<double>{-sg * mg, 0.0});
+            sl[2 * LMAX + l] += H[l];                                     // d / d thickness
+          }
+        }
+        const cplx<double> Gz = Gq * cplx<double>{-(csq(qcc)).re, -(csq(qcc)).im};   // dq/dz = -q^2
+        sl[3 * LMAX] += (Gz * (c * kLn10 * zc)).im;                                   // dz/dlog10 tau
+        sl[3 * LMAX + 1] += (Gz * (zc * cplx<double>{log(w) + log_tau, kHalfPi})).im; // dz/dc
+      }
+    }
+    __syncthreads();
+  }
+  // ---- merged-layer gradients -> particle parameters
+  if (L > 0) {
+    for (int t = lane; t < NS; t += kWave) {
+      double acc = 0.0;
+      for (int gq = 0; gq < 8; ++gq) acc += sm.slot[wave][gq][t];
+      sm.gl[wave][t] = acc;
+    }
+  }
+  __syncthreads();
+  if (valid && lane == 0) {
+    // one lane zeroes the particle's gradient slots and routes the merged-layer gradients
+    const int64_t S = p.stride;
+    const bool dec = p.layout == RJSMC_LAYOUT_DECOUPLED;
+    const int rows_m = dec ? km : kc + 1;
+    g.phi_b[i] = 0.0;
+    g.log10_tau[i] = L > 0 ? sm.gl[wave][3 * LMAX] : 0.0;
+    g.c[i] = L > 0 ? sm.gl[wave][3 * LMAX + 1] : 0.0;
+    for (int r = 0; r < kc; ++r) {
+      g.phi[r * S + i] = 0.0;
+      g.z_cond[r * S + i] = 0.0;
+    }
+    for (int r = 0; r < rows_m; ++r) g.m[r * S + i] = 0.0;
+    if (dec)
+      for (int r = 0; r < km; ++r) g.z_charg[r * S + i] = 0.0;
+    double llv = -HUGE_VAL;
+    if (L > 0) {
+      const double *gv = sm.gl[wave];
+      for (int l = 0; l < L; ++l) {
+        const int ss = st->src_sig[l];
+        if (ss < 0)
+          g.phi_b[i] += gv[l];
+        else
+          g.phi[ss * S + i] += gv[l];
+        const int sm_ = st->src_m[l];
+        if (sm_ >= 0) g.m[sm_ * S + i] += gv[LMAX + l];
+        if (l >= 1) {
+          // top_l moves the thickness of layer l-1 (+) and of layer l (-) unless l is the basement
+          const double dz = gv[2 * LMAX + l - 1] - (l <= L - 2 ? gv[2 * LMAX + l] : 0.0);
+          const int src = st->src_top[l];
+          if (src >= kMaxLayers)
+            g.z_charg[(src - kMaxLayers) * S + i] += dz;
+          else
+            g.z_cond[src * S + i] += dz;
+        }
+      }
+      llv = sm.ll[wave];
+      if (llv != llv) llv = -HUGE_VAL;
+    }
+    ll[i] = llv;
+  }
+}
+
+template <int LMAX>
+static hipError_t launch_g(const DevSystem &s, const DevParticles &p, int kc, int km, const double *y_obs, double *ll,
+                           const DevGrad &g, hipStream_t stream) {
+  const int64_t blocks = (p.n + kWavesA - 1) / kWavesA;
+  hipLaunchKernelGGL((loglik_grad_kernel<LMAX>), dim3((unsigned)blocks), dim3(kWave * kWavesA), 0, stream, s, p, kc,
+                     km, y_obs, ll, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_loglik_grad(const DevSystem &s, const DevParticles &p, int kc, int km, const double *y_obs,
+                              double *ll, const DevGrad &g, hipStream_t stream) {
+  if (s.n_gate > s.n_freq) return hipErrorInvalidValue;     // the ybar staging reuses the Im H slots
+  const int lcap = p.layout == RJSMC_LAYOUT_DECOUPLED ? kc + km + 1 : kc + 1;
+  if (lcap <= 4) return launch_g<4>(s, p, kc, km, y_obs, ll, g, stream);
+  if (lcap <= 8) return launch_g<8>(s, p, kc, km, y_obs, ll, g, stream);
+  return launch_g<16>(s, p, kc, km, y_obs, ll, g, stream);
+}
+
 }  // namespace rjsmc

@@ -1,0 +1,78 @@
+// Projective form of the layered-earth TE reflection recursion (shared by the forward
+// and adjoint kernels).
+#pragma once
+
+#include "cplx.h"
+
+namespace rjsmc {
+
+// Imaginary part of the TE reflection coefficient at the surface for wavenumber lam,
+// layer wavenumbers k2[l] = i w mu0 sigma_hat_l and thicknesses thk[l] (layers
+// 0..L-1, the last one infinite).  The generalized reflection recursion
+//   R_{l,l+1} = (k2_l - k2_{l+1}) / (u_l + u_{l+1})^2,   R_air = -k2_0 / (lam + u_0)^2,
+//   r_l = (R_{l,l+1} + r_{l+1} E_{l+1}) / (1 + R_{l,l+1} r_{l+1} E_{l+1}),
+//   E_l = exp(-2 u_l h_l),  u_l = sqrt(lam^2 + k2_l), Re u_l > 0,
+// is carried in projective form: with R = A/B (A = k2_l - k2_{l+1}, B = (u_l+u_{l+1})^2)
+// and r = N/D,
+//   N_l = A D_{l+1} + B N_{l+1} E_{l+1},   D_l = B D_{l+1} + A N_{l+1} E_{l+1},
+// so the whole stack needs one real division (Im r = Im(N conj D) / |D|^2) instead of
+// two complex divisions per layer.  No lam - u or u_l - u_{l+1} is ever formed.
+// FP64 keeps N, D unscaled (|D| stays within 1e-140 .. 1e30 for <= 16 layers of this
+// system); FP32 rescales by a power of two every layer.
+template <typename T>
+__device__ __forceinline__ void rescale(cplx<T> &N, cplx<T> &D) {}
+template <>
+__device__ __forceinline__ void rescale<float>(cplx<float> &N, cplx<float> &D) {
+  const float m = fabsf(D.re) + fabsf(D.im);
+  const int e = -__builtin_amdgcn_frexp_expf(m);
+  N = {ldexpf(N.re, e), ldexpf(N.im, e)};
+  D = {ldexpf(D.re, e), ldexpf(D.im, e)};
+}
+
+// k2[l] (layers 0..L-1) and thk[l] (l < L-1) are read from LDS: the layer loop is a
+// runtime loop whose carried state is N, D, u_{l+1} and k2_{l+1}.
+template <typename T>
+__device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const T *thk, int L) {
+  const T lam2 = lam * lam;
+  cplx<T> k2b = k2[L - 1];
+  cplx<T> ub = csqrt_fast(cplx<T>{lam2 + k2b.re, k2b.im});
+  cplx<T> N, D;
+  if (L == 1) {
+    N = {-k2b.re, -k2b.im};
+    D = csq(cplx<T>{lam + ub.re, ub.im});
+  } else {
+    {
+      const cplx<T> kl = k2[L - 2];
+      const cplx<T> u = csqrt_fast(cplx<T>{lam2 + kl.re, kl.im});
+      N = kl - k2b;
+      D = csq(u + ub);
+      ub = u;
+      k2b = kl;
+    }
+#pragma unroll 1
+    for (int l = L - 3; l >= 0; --l) {
+      const cplx<T> kl = k2[l];
+      const cplx<T> u = csqrt_fast(cplx<T>{lam2 + kl.re, kl.im});
+      const cplx<T> A = kl - k2b;
+      const cplx<T> B = csq(u + ub);
+      const T h2 = T(-2) * thk[l + 1];
+      const cplx<T> NE = N * cexp(cplx<T>{h2 * ub.re, h2 * ub.im});
+      const cplx<T> Nn = A * D + B * NE;
+      D = B * D + A * NE;
+      N = Nn;
+      rescale(N, D);
+      ub = u;
+      k2b = kl;
+    }
+    const cplx<T> A0 = {-k2b.re, -k2b.im};
+    const cplx<T> B0 = csq(cplx<T>{lam + ub.re, ub.im});
+    const T h2 = T(-2) * thk[0];
+    const cplx<T> NE = N * cexp(cplx<T>{h2 * ub.re, h2 * ub.im});
+    const cplx<T> Nn = A0 * D + B0 * NE;
+    D = B0 * D + A0 * NE;
+    N = Nn;
+  }
+  return (N.im * D.re - N.re * D.im) * fast_rcp(D.re * D.re + D.im * D.im);
+}
+
+}  // namespace rjsmc

@@ -1,0 +1,137 @@
+"""GPU parity of the reverse-sweep gradient of the log-likelihood.
+
+Against the oracle's forward-mode tangents (a different method): per particle
+|g_gpu - g_oracle| <= 1e-8 max|g_oracle| componentwise.  Against central finite
+differences of the GPU log-likelihood (step 1e-6 max(|x|, 1)): <= 1e-5 max|g|.
+Interfaces are kept at least 1 m apart (the gradient has kinks where a conductivity
+and a chargeability interface cross).
+"""
+import numpy as np
+import pytest
+
+from paper_2109_00661_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+FKEYS = ("phi_b", "phi", "z_cond", "m", "z_charg", "log10_tau", "c")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2109_00661_amd import binding
+    return binding
+
+
+def _grad_gpu(B, ctx, p, d):
+    dp = B.particles_to_device(p)
+    ll, g = ctx.loglik_grad(dp, torch.as_tensor(d, device="cuda"))
+    ll_plain = ctx.loglik(dp, torch.as_tensor(d, device="cuda"))
+    ctx.check()
+    return ll.cpu().numpy(), {k: v.cpu().numpy() for k, v in g.items()}, ll_plain.cpu().numpy()
+
+
+def _check_against_oracle(p, ll, g, ll_o, g_o, tol=1e-8):
+    np.testing.assert_allclose(ll, ll_o, rtol=1e-9, atol=1e-9)
+    n = len(ll)
+    for i in range(n):
+        gi = np.concatenate([np.atleast_1d(g[k][..., i]).ravel() for k in FKEYS])
+        go = np.concatenate([np.atleast_1d(g_o[k][..., i]).ravel() for k in FKEYS])
+        scale = max(np.abs(go).max(), 1e-300)
+        assert np.abs(gi - go).max() <= tol * scale, (i, np.abs(gi - go).max() / scale)
+
+
+def test_grad_merged_five_layer(B, system, K_oracle, truth_data):
+    from oracle import em
+    ctx = B.Context(system, precision="f64")
+    p = W.merged_population(21, 5, seed=12, kc=4)
+    ll, g, llp = _grad_gpu(B, ctx, p, truth_data)
+    np.testing.assert_allclose(ll, llp, rtol=1e-12, atol=0)
+    ll_o, g_o = em.loglik_grad(p, system, K_oracle, truth_data)
+    _check_against_oracle(p, ll, g, ll_o, g_o)
+
+
+def test_grad_decoupled_up_to_fifteen_layers(B, K_oracle, truth_data):
+    from oracle import em
+    system = W.system(kmax_cond=7, kmax_charg=7)
+    ctx = B.Context(system, precision="f64")
+    p = W.decoupled_population(13, 7, 7, seed=3, min_sep=1.0)
+    p["kappa"][0], p["lambda_"][0] = 0, 0                 # half-space
+    ll, g, llp = _grad_gpu(B, ctx, p, truth_data)
+    np.testing.assert_allclose(ll, llp, rtol=1e-12, atol=0)
+    ll_o, g_o = em.loglik_grad(p, system, K_oracle, truth_data)
+    _check_against_oracle(p, ll, g, ll_o, g_o)
+
+
+def test_grad_full_size_sampled(B, K_oracle, truth_data):
+    """65,536 decoupled particles with 1-8 segments per partition (the adjoint
+    workload); 6 sampled particles against the oracle, all finite."""
+    from oracle import em
+    system = W.system(kmax_cond=7, kmax_charg=7)
+    ctx = B.Context(system, precision="f64")
+    rng = np.random.default_rng(3)
+    n = 65536
+    p = W.empty_particles(n, 7, 7)
+    P = W.PRIOR
+    p["kappa"][:] = rng.integers(0, 8, n)
+    p["lambda_"][:] = rng.integers(0, 8, n)
+    p["phi_b"][:] = rng.uniform(-3, 0, n)
+    p["log10_tau"][:] = rng.uniform(-6, -1, n)
+    p["c"][:] = rng.uniform(0.1, 1, n)
+    zc = np.sort(rng.uniform(0, P["z_max"], (7, n)), axis=0)
+    zm = np.sort(rng.uniform(0, P["z_max"], (7, n)), axis=0)
+    for r in range(7):
+        p["z_cond"][r] = np.where(r < p["kappa"], zc[r], 0.0)
+        p["z_charg"][r] = np.where(r < p["lambda_"], zm[r], 0.0)
+    p["phi"][:] = rng.uniform(-3, 0, (7, n))
+    p["m"][:] = rng.uniform(0, 0.9, (7, n))
+    ll, g, llp = _grad_gpu(B, ctx, p, truth_data)
+    assert np.isfinite(ll).all() and all(np.isfinite(v).all() for v in g.values())
+    np.testing.assert_allclose(ll, llp, rtol=1e-12, atol=0)
+    # sampled particles whose interfaces are >= 1 m apart
+    sel = []
+    for i in np.random.default_rng(0).permutation(n):
+        z = np.sort(np.concatenate([[0.0], p["z_cond"][:p["kappa"][i], i], p["z_charg"][:p["lambda_"][i], i]]))
+        if np.all(np.diff(z) >= 1.0):
+            sel.append(i)
+        if len(sel) == 6:
+            break
+    sub = W.take(p, sel)
+    ll_o, g_o = em.loglik_grad(sub, system, K_oracle, truth_data)
+    _check_against_oracle(sub, ll[sel], {k: g[k][..., sel] for k in FKEYS}, ll_o, g_o)
+
+
+def test_grad_against_central_differences(B, system, truth_data):
+    ctx = B.Context(system, precision="f64")
+    p = W.decoupled_population(4, 4, 3, seed=21, min_sep=2.0, kappa=np.array([2, 4, 1, 3]),
+                               lam=np.array([1, 3, 0, 2]))
+    ll, g, _ = _grad_gpu(B, ctx, p, truth_data)
+    from oracle.em import particle_params
+    d = torch.as_tensor(truth_data, device="cuda")
+    for i in range(4):
+        names = particle_params(p, i)
+        gv = np.array([g[n][i] if r is None else g[n][r, i] for n, r in names])
+        fd = []
+        for n, r in names:
+            x0 = p[n][i] if r is None else p[n][r, i]
+            h = 1e-6 * max(abs(x0), 1.0)
+            vals = []
+            for sgn in (1, -1):
+                q = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+                if r is None:
+                    q[n][i] = x0 + sgn * h
+                else:
+                    q[n][r, i] = x0 + sgn * h
+                vals.append(ctx.loglik(B.particles_to_device(W.take(q, [i])), d).cpu().numpy()[0])
+            fd.append((vals[0] - vals[1]) / (2 * h))
+        fd = np.array(fd)
+        assert np.abs(gv - fd).max() <= 1e-5 * np.abs(gv).max(), (i, gv, fd)
+
+
+def test_grad_rejected_for_fp32(B, system, truth_data):
+    ctx = B.Context(system, precision="f32")
+    dp = B.particles_to_device(W.merged_population(2, 5, seed=1, kc=4))
+    with pytest.raises(B.RJSMCError) as e:
+        ctx.loglik_grad(dp, torch.as_tensor(truth_data, device="cuda"))
+    assert e.value.status == B.RJSMC_E_UNSUPPORTED
