@@ -240,15 +240,23 @@ typedef struct {
  * move_prob: birth (depth uniform on (0, z_max), property from its prior), death (a
  * uniformly chosen interface), move (one depth + N(0, z_move_sd^2)), a within-model step
  * theta + rw_scale xi F[:, r] along a uniformly chosen principal direction r, or a
- * gradient-informed step (RJSMC_E_UNSUPPORTED in this build).  Proposals beyond the
- * capacities or outside the prior support are rejected; the others are accepted when
- * ln u < gamma (ll' - ll).  `scratch` and `ll_scratch` hold the proposals (same shapes as
- * `state`).  n must not exceed the context's max_particles.  stats (device int64 [2][8], may be NULL) accumulates proposed / accepted
- * counts per move type.  active (device [n_sound], NULL = all) selects soundings. */
+ * gradient-informed (preconditioned Langevin) step
+ *   theta' = theta + mala_eps^2/2 F F^T gamma grad ll + mala_eps F xi
+ * whose acceptance includes the reverse-proposal correction
+ *   -|xi + mala_eps/2 F^T gamma (grad ll + grad' ll)|^2 / 2 + |xi|^2 / 2.
+ * Proposals beyond the capacities or outside the prior support are rejected; the others
+ * are accepted when ln u < gamma (ll' - ll) (+ the correction).  `scratch` and
+ * `ll_scratch` hold the proposals (same shapes as `state`).  grad_cur and grad_prop
+ * (device, particle-shaped, may be NULL unless move_prob[WITHIN_MALA] > 0) receive
+ * gradients of the current states and of the proposals; gradient-informed moves need an
+ * FP64 context.  n must not exceed the context's max_particles.  stats (device int64
+ * [2][8], may be NULL) accumulates proposed / accepted counts per move type.  active
+ * (device [n_sound], NULL = all) selects soundings. */
 rjsmc_status rjsmc_mutate(rjsmc_ctx *ctx, const rjsmc_mutate_args *args, rjsmc_particles *state,
                           double *ll, rjsmc_particles *scratch, double *ll_scratch,
                           const double *gamma, const int32_t *active, const double *y_obs,
-                          int64_t *stats, rjsmc_stream stream);
+                          rjsmc_particles *grad_cur, rjsmc_particles *grad_prop, int64_t *stats,
+                          rjsmc_stream stream);
 
 #ifdef __cplusplus
 }

@@ -25,6 +25,10 @@ readings where it is silent or loose:
   terms cancel).  Proposals beyond the capacity or outside the support are rejected.
   The within-model move steps along one principal direction of the model's particle
   covariance, scaled by the square root of its eigenvalue (Section 3.2.3).
+* The gradient-informed within-model move (the paper cites Langevin proposals as prior
+  art, Section 3) is a preconditioned Langevin step theta' = theta + eps^2/2 S grad +
+  eps F xi with S = F F^T, grad = gamma grad ll (flat prior inside the support) and a
+  Metropolis-Hastings correction with the reverse proposal density.
 """
 import math
 
@@ -373,6 +377,8 @@ def propose(p, i, step, move, seed, q, pr, kmax_cond, kmax_charg, factor):
             hi = z[j + 1] if j + 1 < len(z) else pr["z_max"]
             if lo < z[j] < hi and z[j] > 0.0:
                 new = dict(z_cond=z, phi=ph, z_charg=zm, m=mm) if t == 2 else dict(z_cond=zc, phi=ph, z_charg=z, m=mm)
+    elif t == 7:                                      # gradient-informed within-model step
+        new = dict(mala=True)
     elif t == 6:                                      # within-model step on one principal direction
         theta = param_vector(p, i)
         d = len(theta)
@@ -381,6 +387,29 @@ def propose(p, i, step, move, seed, q, pr, kmax_cond, kmax_charg, factor):
         if in_support(theta, k, l, pr):
             new = dict(theta=theta)
     return t, new, ua
+
+
+def mala_normals(seed, i, step, move, d):
+    """xi_0..xi_{d-1}: Box-Muller pairs from uniform slots 3, 4, ..."""
+    xi = []
+    slot = 3
+    while len(xi) < d:
+        xi.extend(normal_pair(*uniform_pair(seed, i, step, move, slot)))
+        slot += 1
+    return np.array(xi[:d])
+
+
+def mala_propose(theta, grad_ll, gamma, factor, eps, xi):
+    """theta' = theta + eps^2/2 S (gamma grad) + eps F xi, S = F F^T."""
+    g = gamma * grad_ll
+    return theta + 0.5 * eps * eps * (factor @ (factor.T @ g)) + eps * (factor @ xi)
+
+
+def mala_log_q_ratio(xi, grad_ll, grad_ll_new, gamma, factor, eps):
+    """log q(theta | theta') - log q(theta' | theta) for the preconditioned Langevin
+    proposal: -1/2 |xi + eps/2 F^T (g + g')|^2 + 1/2 |xi|^2 with g = gamma grad ll."""
+    v = xi + 0.5 * eps * (factor.T @ (gamma * (grad_ll + grad_ll_new)))
+    return -0.5 * (v @ v) + 0.5 * (xi @ xi)
 
 
 def apply_state(p, i, new):
@@ -403,7 +432,8 @@ def copy_particle(p, i):
     return {k: (v[..., i].copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
 
 
-def mutate(p, ll, loglik_fn, gamma_of, step, seed, q, pr, kmax_cond, kmax_charg, factors_of, n_moves):
+def mutate(p, ll, loglik_fn, gamma_of, step, seed, q, pr, kmax_cond, kmax_charg, factors_of, n_moves,
+           grad_fn=None):
     """n_moves RJ-MCMC sweeps over every particle (Algorithm 1, mutation).  loglik_fn
     evaluates one particle of a population; gamma_of(i) is its sounding's temperature;
     factors_of(i) the colouring factor of its model.  Acceptance: u < exp(gamma (ll' - ll))
@@ -420,9 +450,24 @@ def mutate(p, ll, loglik_fn, gamma_of, step, seed, q, pr, kmax_cond, kmax_charg,
                 margins.append((i, r, np.inf))
                 continue
             saved = copy_particle(p, i)
-            apply_state(p, i, new)
-            ll_new = loglik_fn(p, i)
-            margin = gamma_of(i) * (ll_new - ll[i]) - math.log(ua)
+            extra = 0.0
+            if "mala" in new:
+                k_, l_ = int(p["kappa"][i]), int(p["lambda_"][i])
+                F = factors_of(i)
+                theta = param_vector(p, i)
+                _, g0 = grad_fn(p, i)
+                xi = mala_normals(seed, i, step, r, len(theta))
+                th_new = mala_propose(theta, g0, gamma_of(i), F, q["mala_eps"], xi)
+                if not in_support(th_new, k_, l_, pr):
+                    margins.append((i, r, np.inf))
+                    continue
+                set_param_vector(p, i, th_new)
+                ll_new, g1 = grad_fn(p, i)
+                extra = mala_log_q_ratio(xi, g0, g1, gamma_of(i), F, q["mala_eps"])
+            else:
+                apply_state(p, i, new)
+                ll_new = loglik_fn(p, i)
+            margin = gamma_of(i) * (ll_new - ll[i]) + extra - math.log(ua)
             margins.append((i, r, margin))
             if margin > 0.0:
                 ll[i] = ll_new

@@ -98,7 +98,8 @@ _SIGS = {
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "rjsmc_mutate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MutateArgs), ctypes.POINTER(Particles),
                                     ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p, ctypes.c_void_p,
-                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Particles),
+                                    ctypes.POINTER(Particles), ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 
@@ -271,7 +272,8 @@ class Context:
                                  _stream_handle(stream)))
 
     def mutate(self, state, ll, scratch, ll_scratch, gamma, active, y_obs, stats, *, seed, step, n_moves, n_sound,
-               prior, move_prob, z_move_sd, rw_scale, factors, mala_eps=0.0, stream=None):
+               prior, move_prob, z_move_sd, rw_scale, factors, mala_eps=0.0, grad_cur=None, grad_prop=None,
+               stream=None):
         a = MutateArgs()
         a.seed, a.step, a.n_moves, a.n_sound = seed, step, n_moves, n_sound
         for t in range(N_MOVES):
@@ -280,8 +282,10 @@ class Context:
         a.factors = _ptr(factors) if factors is not None else ctypes.c_void_p(0)
         a.prior = make_prior(prior)
         ss, sq = particles_struct(state), particles_struct(scratch)
+        gc = ctypes.byref(particles_struct(grad_cur)) if grad_cur is not None else None
+        gp = ctypes.byref(particles_struct(grad_prop)) if grad_prop is not None else None
         _check(lib().rjsmc_mutate(self._ptr, ctypes.byref(a), ctypes.byref(ss), _ptr(ll), ctypes.byref(sq),
-                                  _ptr(ll_scratch), _ptr(gamma), _ptr(active), _ptr(y_obs), _ptr(stats),
+                                  _ptr(ll_scratch), _ptr(gamma), _ptr(active), _ptr(y_obs), gc, gp, _ptr(stats),
                                   _stream_handle(stream)))
 
 

@@ -174,11 +174,12 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int64_t i = (int64_t)blockIdx.x * kWavesA + wave;
   const bool valid = i < p.n;
+  const bool skip = valid && p.mask && p.mask[i] != p.mask_value;   // left untouched
   LayerStack *st = &sm.stack[wave];
   constexpr int NS = 3 * LMAX + 2;
   for (int t = lane; t < 8 * NS; t += kWave) sm.slot[wave][t / NS][t % NS] = 0.0;
   __syncthreads();
-  const int L = merge_particle(p, i, valid, kc, km, LMAX, st, s.flags);
+  const int L = merge_particle(p, i, valid && !skip, kc, km, LMAX, st, s.flags);
 
   double c = 0.0, log_tau = 0.0, spc = 0.0, cpc = 1.0;
   if (L > 0) {
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
     }
   }
   __syncthreads();
-  if (valid && lane == 0) {
+  if (valid && !skip && lane == 0) {
     // one lane zeroes the particle's gradient slots and routes the merged-layer gradients
     const int64_t S = p.stride;
     const bool dec = p.layout == RJSMC_LAYOUT_DECOUPLED;

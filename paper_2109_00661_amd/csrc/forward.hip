@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + wave;
   const bool valid = i < p.n;
-  const bool skip = valid && p.mask && !p.mask[i];
+  const bool skip = valid && p.mask && p.mask[i] != p.mask_value;
   LayerStack *st = &s_stack[wave];
   __syncthreads();
   const int L = merge_particle(p, i, valid && !skip, kc, km, LMAX, st, s.flags);
@@ -135,9 +135,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
         ll[i] = (v == v && v != HUGE_VAL) ? v : -HUGE_VAL;   // NaN or +inf -> -inf
       }
     }
-  } else if (skip) {
-    if (ll && lane == 0) ll[i] = -HUGE_VAL;
-  } else if (valid) {
+  } else if (valid && !skip) {
     // invalid particle: NaN responses, -inf log-likelihood
     if (resp && lane < ng) resp[i * ng + lane] = __builtin_nan("");
     if (ll && lane == 0) ll[i] = -HUGE_VAL;

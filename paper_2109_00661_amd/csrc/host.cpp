@@ -524,10 +524,25 @@ extern "C" rjsmc_status rjsmc_adapt(rjsmc_ctx *c, const rjsmc_particles *p, int3
   return RJSMC_OK;
 }
 
+static rjsmc_status grad_buffer(const rjsmc_ctx *c, const rjsmc_particles *g, const rjsmc_particles *like,
+                                const char *who, rjsmc::DevParticles *dp, rjsmc::DevGrad *dg) {
+  rjsmc_particles tmp = *g;
+  tmp.n = like->n;
+  tmp.n_per_sounding = like->n_per_sounding;
+  tmp.layout = like->layout;
+  tmp.kappa = like->kappa;
+  tmp.lambda = like->lambda;
+  rjsmc_status st = check_particles(c, &tmp, who, dp);
+  if (st != RJSMC_OK) return st;
+  if (g->stride != like->stride) return fail(RJSMC_E_INVALID, "%s: gradient stride differs from the state's", who);
+  *dg = rjsmc::DevGrad{g->phi_b, g->phi, g->z_cond, g->m, g->z_charg, g->log10_tau, g->c};
+  return RJSMC_OK;
+}
+
 extern "C" rjsmc_status rjsmc_mutate(rjsmc_ctx *c, const rjsmc_mutate_args *a, rjsmc_particles *state, double *ll,
                                      rjsmc_particles *scratch, double *ll_scratch, const double *gamma,
-                                     const int32_t *active, const double *y_obs, int64_t *stats,
-                                     rjsmc_stream stream) {
+                                     const int32_t *active, const double *y_obs, rjsmc_particles *grad_cur,
+                                     rjsmc_particles *grad_prop, int64_t *stats, rjsmc_stream stream) {
   const char *who = "rjsmc_mutate";
   if (!c || !a) return fail(RJSMC_E_INVALID, "%s: NULL argument", who);
   rjsmc::DevParticles ds, dq;
@@ -551,24 +566,45 @@ extern "C" rjsmc_status rjsmc_mutate(rjsmc_ctx *c, const rjsmc_mutate_args *a, r
     total += a->move_prob[t];
   }
   if (!(total > 0)) return fail(RJSMC_E_INVALID, "%s: move probabilities sum to zero", who);
-  if (a->move_prob[RJSMC_MOVE_WITHIN_MALA] > 0)
-    return fail(RJSMC_E_UNSUPPORTED, "%s: the gradient-informed move needs rjsmc_mutate_grad", who);
-  if (a->move_prob[RJSMC_MOVE_WITHIN_RW] > 0 && !a->factors)
+  const bool mala = a->move_prob[RJSMC_MOVE_WITHIN_MALA] > 0;
+  if ((a->move_prob[RJSMC_MOVE_WITHIN_RW] > 0 || mala) && !a->factors)
     return fail(RJSMC_E_INVALID, "%s: within-model moves need proposal factors", who);
-  if (!(a->z_move_sd >= 0) || !(a->rw_scale >= 0)) return fail(RJSMC_E_INVALID, "%s: bad step sizes", who);
+  if (!(a->z_move_sd >= 0) || !(a->rw_scale >= 0) || !(a->mala_eps >= 0))
+    return fail(RJSMC_E_INVALID, "%s: bad step sizes", who);
+  rjsmc::DevParticles gcd, gpd;
+  rjsmc::DevGrad gcw, gpw;
+  if (mala) {
+    if (c->precision != RJSMC_F64)
+      return fail(RJSMC_E_UNSUPPORTED, "%s: gradient-informed moves need an FP64 context", who);
+    if (!grad_cur || !grad_prop) return fail(RJSMC_E_INVALID, "%s: gradient-informed moves need gradient buffers", who);
+    if ((st = grad_buffer(c, grad_cur, state, who, &gcd, &gcw)) != RJSMC_OK) return st;
+    if ((st = grad_buffer(c, grad_prop, scratch, who, &gpd, &gpw)) != RJSMC_OK) return st;
+  }
   const rjsmc::SmcShape sh = smc_shape(c);
   hipError_t e = hipSetDevice(c->device);
   hipStream_t s = (hipStream_t)stream;
-  rjsmc::DevParticles prop = dq;
-  prop.mask = c->work_mask;
+  rjsmc::DevParticles prop1 = dq, prop2 = dq, cur2 = ds;
+  prop1.mask = c->work_mask;
+  prop1.mask_value = 1;
+  prop2.mask = c->work_mask;
+  prop2.mask_value = 2;
+  cur2.mask = c->work_mask;
+  cur2.mask_value = 2;
   for (int r = 0; r < a->n_moves && e == hipSuccess; ++r) {
-    e = rjsmc::launch_propose(sh, *a, r, ds, writable(dq), c->work_mask, c->work_type, active, s);
+    e = rjsmc::launch_draw_types(*a, r, ds, sh.kc, sh.km, c->work_mask, c->work_type, active, s);
+    if (e == hipSuccess && mala)   // gradients of the current states of the particles taking a Langevin step
+      e = rjsmc::launch_loglik_grad(c->dev, cur2, c->kmax_cond, c->kmax_charg, y_obs, ll_scratch, gcw, s);
     if (e == hipSuccess)
-      e = rjsmc::launch_forward(c->dev, prop, c->kmax_cond, c->kmax_charg, c->precision, nullptr, y_obs, ll_scratch,
+      e = rjsmc::launch_propose(sh, *a, r, ds, writable(dq), c->work_mask, c->work_type, gamma, mala ? &gcd : nullptr,
                                 s);
     if (e == hipSuccess)
-      e = rjsmc::launch_accept(sh, *a, r, writable(ds), ll, dq, ll_scratch, c->work_mask, c->work_type, gamma, stats,
-                               s);
+      e = rjsmc::launch_forward(c->dev, prop1, c->kmax_cond, c->kmax_charg, c->precision, nullptr, y_obs, ll_scratch,
+                                s);
+    if (e == hipSuccess && mala)
+      e = rjsmc::launch_loglik_grad(c->dev, prop2, c->kmax_cond, c->kmax_charg, y_obs, ll_scratch, gpw, s);
+    if (e == hipSuccess)
+      e = rjsmc::launch_accept(sh, *a, r, writable(ds), ll, dq, ll_scratch, c->work_mask, c->work_type, gamma,
+                               mala ? &gcd : nullptr, mala ? &gpd : nullptr, stats, s);
   }
   if (e != hipSuccess) return hip_fail(e, "rjsmc_mutate: launch");
   return RJSMC_OK;

@@ -41,7 +41,8 @@ struct DevParticles {
   const int32_t *kappa = nullptr, *lambda = nullptr;
   const double *phi_b = nullptr, *phi = nullptr, *z_cond = nullptr, *m = nullptr, *z_charg = nullptr,
                *log10_tau = nullptr, *c = nullptr;
-  const int32_t *mask = nullptr;   // optional: particles with mask[i] == 0 are skipped (ll = -inf)
+  const int32_t *mask = nullptr;   // optional: only particles with mask[i] == mask_value are
+  int mask_value = 1;              // evaluated; the others are left untouched
 };
 
 // Writable view of a particle population.
@@ -80,12 +81,15 @@ hipError_t launch_reweight_resample(const SmcShape &sh, const rjsmc_reweight_arg
                                     double *log_z, int32_t *active, int32_t *anc, int *flags, hipStream_t stream);
 hipError_t launch_adapt(const SmcShape &sh, const DevParticles &p, int n_sound, const rjsmc_prior &pr,
                         double *factors, hipStream_t stream);
+hipError_t launch_draw_types(const rjsmc_mutate_args &a, int move, const DevParticles &state, int kc, int km,
+                             int32_t *mask, int32_t *type, const int32_t *active, hipStream_t stream);
 hipError_t launch_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticles &state,
-                          const DevParticlesW &prop, int32_t *mask, int32_t *type, const int32_t *active,
-                          hipStream_t stream);
+                          const DevParticlesW &prop, int32_t *mask, const int32_t *type, const double *gamma,
+                          const DevParticles *grad_cur, hipStream_t stream);
 hipError_t launch_accept(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticlesW &state,
                          double *ll, const DevParticles &prop, const double *ll_prop, const int32_t *mask,
-                         const int32_t *type, const double *gamma, int64_t *stats, hipStream_t stream);
+                         const int32_t *type, const double *gamma, const DevParticles *grad_cur,
+                         const DevParticles *grad_prop, int64_t *stats, hipStream_t stream);
 
 // Host-side construction of the frequency-to-time matrix (host.cpp).
 void build_time_kernel(const double *freq_hz, int n_freq, const double *t_open,

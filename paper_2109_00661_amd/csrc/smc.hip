@@ -603,33 +603,61 @@ __device__ __forceinline__ int draw_type(const rjsmc_mutate_args &a, double u0) 
 
 __device__ __forceinline__ bool in_range(double v, double lo, double hi) { return v >= lo && v <= hi; }
 
-// Proposal of move `move` for every particle: the proposal is written to `prop`;
-// mask[i] = 1 if it needs a likelihood, type[i] = move type (-1: inactive sounding).
+// Move type of every particle for sweep `move` (-1: inactive sounding or counts outside
+// the capacities); mask = 2 marks the particles that take a gradient-informed step, whose
+// current gradient is needed before proposing.
+__global__ __launch_bounds__(256) void draw_types_kernel(rjsmc_mutate_args a, int move, DevParticles st, int kc,
+                                                         int km, int32_t *mask, int32_t *type,
+                                                         const int32_t *active) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= st.n) return;
+  const int64_t snd = st.n_per_sounding > 0 ? i / st.n_per_sounding : 0;
+  const int k = st.kappa[i], l = st.lambda[i];
+  int t = -1;
+  if ((!active || active[snd]) && k >= 0 && k <= kc && l >= 0 && l <= km) {
+    double u0, ua;
+    uniforms(a.seed, (uint32_t)i, (uint32_t)a.step, (uint32_t)move, 0u, u0, ua);
+    t = draw_type(a, u0);
+  }
+  type[i] = t;
+  mask[i] = t == RJSMC_MOVE_WITHIN_MALA ? 2 : 0;
+}
+
+// theta' = theta + F (eps^2/2 F^T (gamma grad) + eps xi) of the preconditioned Langevin step,
+// in parameter-vector order; xi from uniform slots 3, 4, ... (Box-Muller pairs).
+__device__ __forceinline__ void mala_normals(const rjsmc_mutate_args &a, int64_t i, int move, int d, double *xi) {
+  for (int r = 0; r < d; r += 2) {
+    double u1, u2;
+    uniforms(a.seed, (uint32_t)i, (uint32_t)a.step, (uint32_t)move, (uint32_t)(3 + r / 2), u1, u2);
+    const double rad = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincos(6.283185307179586477 * u2, &sn, &cs);
+    xi[r] = rad * cs;
+    if (r + 1 < d) xi[r + 1] = rad * sn;
+  }
+}
+
+// Proposal of move `move` for every particle (type from draw_types_kernel): written to
+// `prop`; mask[i] = 1 if the proposal needs a likelihood, 2 if it needs a likelihood and
+// a gradient, 0 if it is rejected outright.
 __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_args a, int move, DevParticles st,
-                                                      DevParticlesW prop, int32_t *mask, int32_t *type,
-                                                      const int32_t *active) {
+                                                      DevParticlesW prop, int32_t *mask, const int32_t *type,
+                                                      const double *gamma, DevParticles gcur) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= st.n) return;
   const int64_t snd = st.n_per_sounding > 0 ? i / st.n_per_sounding : 0;
   const int64_t S = st.stride, So = prop.stride;
-  if (active && !active[snd]) {
+  const int t = type[i];
+  if (t < 0) {
     mask[i] = 0;
-    type[i] = -1;
     return;
   }
   const int kc = sh.kc, km = sh.km;
   const rjsmc_prior &pr = a.prior;
-  double u0, ua, u1, u2, u3, u4;
-  uniforms(a.seed, (uint32_t)i, (uint32_t)a.step, (uint32_t)move, 0u, u0, ua);
+  double u1, u2, u3, u4;
   uniforms(a.seed, (uint32_t)i, (uint32_t)a.step, (uint32_t)move, 1u, u1, u2);
   uniforms(a.seed, (uint32_t)i, (uint32_t)a.step, (uint32_t)move, 2u, u3, u4);
-  const int t = draw_type(a, u0);
   int k = st.kappa[i], l = st.lambda[i];
-  if (k < 0 || k > kc || l < 0 || l > km) {   // outside the capacities: left unchanged
-    mask[i] = 0;
-    type[i] = -1;
-    return;
-  }
   double zc[kMaxLayers], ph[kMaxLayers], zm[kMaxLayers], mm[kMaxLayers];
   for (int j = 0; j < k; ++j) {
     zc[j] = st.z_cond[j * S + i];
@@ -712,9 +740,43 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
     for (int j = 0; j < l; ++j)
       ok = ok && in_range(mm[j], pr.m_lo, pr.m_hi) && zm[j] > 0.0 && zm[j] < sh.z_max &&
            (j == 0 || zm[j] > zm[j - 1]);
+  } else if (t == RJSMC_MOVE_WITHIN_MALA) {
+    const int d = 3 + 2 * k + 2 * l, D = sh.dmax;
+    const int mdl = k * (km + 1) + l;
+    const double *Fm = a.factors + (snd * sh.n_models + mdl) * (int64_t)D * D;   // F[a][r] = Fm[r D + a]
+    const double gam = gamma[snd];
+    double th[kDimMax], xi[kDimMax], cr[kDimMax];
+    for (int q = 0; q < d; ++q) th[q] = theta_get(st, i, k, l, q);
+    mala_normals(a, i, move, d, xi);
+    const double eps = a.mala_eps;
+    for (int r = 0; r < d; ++r) {          // cr = eps^2/2 F^T (gamma grad) + eps xi
+      double sr = 0.0;
+      for (int q = 0; q < d; ++q) sr += Fm[r * D + q] * (gam * theta_get(gcur, i, k, l, q));
+      cr[r] = 0.5 * eps * eps * sr + eps * xi[r];
+    }
+    for (int q = 0; q < d; ++q) {
+      double acc = 0.0;
+      for (int r = 0; r < d; ++r) acc += Fm[r * D + q] * cr[r];
+      th[q] += acc;
+    }
+    int q = 0;
+    phb = th[q++];
+    for (int j = 0; j < k; ++j) ph[j] = th[q++];
+    for (int j = 0; j < k; ++j) zc[j] = th[q++];
+    for (int j = 0; j < l; ++j) mm[j] = th[q++];
+    for (int j = 0; j < l; ++j) zm[j] = th[q++];
+    lt = th[q++];
+    cc = th[q++];
+    ok = in_range(phb, pr.phi_lo, pr.phi_hi) && in_range(lt, pr.ltau_lo, pr.ltau_hi) &&
+         in_range(cc, pr.c_lo, pr.c_hi);
+    for (int j = 0; j < k; ++j)
+      ok = ok && in_range(ph[j], pr.phi_lo, pr.phi_hi) && zc[j] > 0.0 && zc[j] < sh.z_max &&
+           (j == 0 || zc[j] > zc[j - 1]);
+    for (int j = 0; j < l; ++j)
+      ok = ok && in_range(mm[j], pr.m_lo, pr.m_hi) && zm[j] > 0.0 && zm[j] < sh.z_max &&
+           (j == 0 || zm[j] > zm[j - 1]);
   }
-  mask[i] = ok ? 1 : 0;
-  type[i] = t;
+  mask[i] = ok ? (t == RJSMC_MOVE_WITHIN_MALA ? 2 : 1) : 0;
   if (!ok) return;
   prop.kappa[i] = k;
   prop.lambda[i] = l;
@@ -735,7 +797,7 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
 __global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_args a, int move, DevParticlesW st,
                                                      double *ll, DevParticles prop, const double *ll_prop,
                                                      const int32_t *mask, const int32_t *type, const double *gamma,
-                                                     int64_t *stats) {
+                                                     DevParticles gcur, DevParticles gprop, int64_t *stats) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = i < st.n;
   const int t = in ? type[i] : -1;
@@ -744,7 +806,24 @@ __global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_a
     const int64_t snd = st.n_per_sounding > 0 ? i / st.n_per_sounding : 0;
     double u0, ua;
     uniforms(a.seed, (uint32_t)i, (uint32_t)a.step, (uint32_t)move, 0u, u0, ua);
-    const double margin = gamma[snd] * (ll_prop[i] - ll[i]) - log(ua);
+    double extra = 0.0;
+    if (t == RJSMC_MOVE_WITHIN_MALA) {
+      // log q(theta | theta') - log q(theta' | theta) = -|xi + eps/2 F^T gamma (g + g')|^2/2 + |xi|^2/2
+      const int k = st.kappa[i], l = st.lambda[i];
+      const int d = 3 + 2 * k + 2 * l, D = sh.dmax;
+      const double *Fm = a.factors + (snd * sh.n_models + (k * (sh.km + 1) + l)) * (int64_t)D * D;
+      const double gam = gamma[snd];
+      double xi[kDimMax];
+      mala_normals(a, i, move, d, xi);
+      for (int r = 0; r < d; ++r) {
+        double sr = 0.0;
+        for (int q = 0; q < d; ++q)
+          sr += Fm[r * D + q] * (gam * (theta_get(gcur, i, k, l, q) + theta_get(gprop, i, k, l, q)));
+        const double v = xi[r] + 0.5 * a.mala_eps * sr;
+        extra += -0.5 * v * v + 0.5 * xi[r] * xi[r];
+      }
+    }
+    const double margin = gamma[snd] * (ll_prop[i] - ll[i]) + extra - log(ua);
     acc = margin > 0.0;
     if (acc) {
       const int64_t S = st.stride, Sp = prop.stride;
@@ -775,21 +854,33 @@ __global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_a
   }
 }
 
-hipError_t launch_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticles &state,
-                          const DevParticlesW &prop, int32_t *mask, int32_t *type, const int32_t *active,
-                          hipStream_t stream) {
+hipError_t launch_draw_types(const rjsmc_mutate_args &a, int move, const DevParticles &state, int kc, int km,
+                             int32_t *mask, int32_t *type, const int32_t *active, hipStream_t stream) {
   const int64_t blocks = (state.n + 255) / 256;
-  hipLaunchKernelGGL(propose_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, sh, a, move, state, prop, mask,
+  hipLaunchKernelGGL(draw_types_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, a, move, state, kc, km, mask,
                      type, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticles &state,
+                          const DevParticlesW &prop, int32_t *mask, const int32_t *type, const double *gamma,
+                          const DevParticles *grad_cur, hipStream_t stream) {
+  const int64_t blocks = (state.n + 255) / 256;
+  const DevParticles g = grad_cur ? *grad_cur : DevParticles();
+  hipLaunchKernelGGL(propose_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, sh, a, move, state, prop, mask,
+                     type, gamma, g);
   return hipGetLastError();
 }
 
 hipError_t launch_accept(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticlesW &state,
                          double *ll, const DevParticles &prop, const double *ll_prop, const int32_t *mask,
-                         const int32_t *type, const double *gamma, int64_t *stats, hipStream_t stream) {
+                         const int32_t *type, const double *gamma, const DevParticles *grad_cur,
+                         const DevParticles *grad_prop, int64_t *stats, hipStream_t stream) {
   const int64_t blocks = (state.n + 255) / 256;
+  const DevParticles gc = grad_cur ? *grad_cur : DevParticles();
+  const DevParticles gp = grad_prop ? *grad_prop : DevParticles();
   hipLaunchKernelGGL(accept_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, sh, a, move, state, ll, prop,
-                     ll_prop, mask, type, gamma, stats);
+                     ll_prop, mask, type, gamma, gc, gp, stats);
   return hipGetLastError();
 }
 

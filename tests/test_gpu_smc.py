@@ -225,3 +225,52 @@ def test_rjsmc_end_to_end_single_sounding(B, system, truth_data):
     assert probs[lam >= 1].sum() > 0.5
     st = run.stats.cpu().numpy()
     assert st[1].sum() > 0 and np.all(st[1] <= st[0])
+
+
+@pytest.mark.parametrize("gamma", [0.01, 0.4])
+def test_mutate_gradient_informed_against_oracle(B, ctx, system, K_oracle, truth_data, gamma):
+    """Mixed sweeps including the preconditioned Langevin move (and RJ moves) against
+    the oracle, which evaluates gradients by forward-mode tangents."""
+    from oracle import em, smc
+    n, n_moves, seed, step = 32, 2, 321, 6
+    p = smc.init_population(43, n, KC, KM, PR)
+    ll0 = em.loglik(p, system, K_oracle, truth_data)
+    q = dict(move_prob=np.array([1, 1, 1, 1, 1, 1, 0, 4], float), z_move_sd=0.05 * PR["z_max"], rw_scale=2.38,
+             mala_eps=0.5)
+    fdev, fhost = _device_factors(p, n, 1, 9)
+
+    def grad_fn(pp, i):
+        one = W.take(pp, [i])
+        llv, g = em.loglik_grad(one, system, K_oracle, truth_data)
+        names = em.particle_params(one, 0)
+        return llv[0], np.array([g[nm][0] if r is None else g[nm][r, 0] for nm, r in names])
+
+    po = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+    llo = ll0.copy()
+    mdl = lambda i: smc.model_id(int(po["kappa"][i]), int(po["lambda_"][i]), KM)
+    st_o, margins = smc.mutate(po, llo, lambda pp, i: em.loglik(pp, system, K_oracle, truth_data, [i])[0],
+                               lambda i: gamma, step, seed, q, PR, KC, KM, lambda i: fhost[(0, mdl(i))], n_moves,
+                               grad_fn=grad_fn)
+    dp = B.particles_to_device(p)
+    scratch = B.empty_device_population(n, KC, KM)
+    gcur = B.empty_device_population(n, KC, KM)
+    gprop = B.empty_device_population(n, KC, KM)
+    ll_d = torch.as_tensor(ll0, device="cuda")
+    stats = torch.zeros((2, 8), dtype=torch.int64, device="cuda")
+    ctx.mutate(dp, ll_d, scratch, torch.empty_like(ll_d), torch.tensor([gamma], dtype=torch.float64, device="cuda"),
+               None, torch.as_tensor(truth_data, device="cuda"), stats, seed=seed, step=step, n_moves=n_moves,
+               n_sound=1, prior=PR, move_prob=q["move_prob"], z_move_sd=q["z_move_sd"], rw_scale=q["rw_scale"],
+               factors=torch.as_tensor(fdev, device="cuda"), mala_eps=q["mala_eps"], grad_cur=gcur, grad_prop=gprop)
+    ctx.check()
+    got = _host(B, dp)
+    near = {i for i, r, mg in margins if abs(mg) < 1e-7}
+    ok = [i for i in range(n) if i not in near]
+    assert len(ok) >= n - 2
+    for k in ("kappa", "lambda_"):
+        assert np.array_equal(got[k][ok], po[k][ok]), k
+    for k in ("phi_b", "phi", "z_cond", "m", "z_charg", "log10_tau", "c"):
+        np.testing.assert_allclose(got[k][..., ok], po[k][..., ok], rtol=1e-10, atol=1e-10, err_msg=k)
+    np.testing.assert_allclose(ll_d.cpu().numpy()[ok], llo[ok], rtol=1e-9, atol=1e-9)
+    if not near:
+        assert np.array_equal(stats.cpu().numpy(), st_o)
+    assert st_o[0, 7] > 0

@@ -182,3 +182,37 @@ def test_acceptance_uses_tempered_ratio():
                            PR, 4, 3, lambda i: np.diag(1e-6 * smc.prior_sd(int(pp["kappa"][i]), int(pp["lambda_"][i]), PR)), 1)
         rate = st[1, 6] / st[0, 6]
         assert abs(rate - math.exp(-10 * g)) < 4 * math.sqrt(math.exp(-10 * g) / n) + 0.01
+
+
+def test_mala_log_q_ratio_matches_gaussian_densities():
+    """The simplified Langevin correction equals the ratio of the two Gaussian proposal
+    densities N(theta; theta' + eps^2/2 S g', eps^2 S) / N(theta'; theta + eps^2/2 S g,
+    eps^2 S)."""
+    from scipy.stats import multivariate_normal as mvn
+    rng = np.random.default_rng(4)
+    for d in (3, 7, 11):
+        F = rng.standard_normal((d, d)) + 2 * np.eye(d)
+        S = F @ F.T
+        eps, gamma = 0.37, 0.6
+        theta = rng.standard_normal(d)
+        g0, g1 = rng.standard_normal(d), rng.standard_normal(d)
+        xi = rng.standard_normal(d)
+        th1 = smc.mala_propose(theta, g0, gamma, F, eps, xi)
+        fwd = mvn.logpdf(th1, theta + 0.5 * eps ** 2 * S @ (gamma * g0), eps ** 2 * S)
+        rev = mvn.logpdf(theta, th1 + 0.5 * eps ** 2 * S @ (gamma * g1), eps ** 2 * S)
+        assert abs(smc.mala_log_q_ratio(xi, g0, g1, gamma, F, eps) - (rev - fwd)) < 1e-9
+
+
+def test_mala_preserves_the_prior_at_zero_temperature():
+    n = 2000
+    p = smc.init_population(23, n, 4, 3, PR)
+    ll = np.zeros(n)
+    q = dict(move_prob=np.array([0, 0, 0, 0, 0, 0, 0, 1], float), z_move_sd=15.0, rw_scale=2.38, mala_eps=0.8)
+    fac = lambda i: np.diag(0.3 * smc.prior_sd(int(p["kappa"][i]), int(p["lambda_"][i]), PR))
+    grad = lambda pp, i: (0.0, np.zeros(3 + 2 * int(pp["kappa"][i]) + 2 * int(pp["lambda_"][i])))
+    st, _ = smc.mutate(p, ll, lambda pp, i: 0.0, lambda i: 0.0, 1, 29, q, PR, 4, 3, fac, 8, grad_fn=grad)
+    assert st[1, 7] > 0.3 * st[0, 7]
+    phs = np.array([p["phi_b"][i] for i in range(n)])
+    assert stats.kstest((phs - PR["phi_lo"]) / (PR["phi_hi"] - PR["phi_lo"]), "uniform").pvalue > 1e-3
+    cs = (p["c"] - PR["c_lo"]) / (PR["c_hi"] - PR["c_lo"])
+    assert stats.kstest(cs, "uniform").pvalue > 1e-3
