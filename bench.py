@@ -11,6 +11,7 @@ Prints one JSON line.  Options: --steps K --warmup W --gpus N (only 1 is support
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,6 +30,33 @@ N_LAYERS = 5
 FLOP_PER_LAYER_STEP = 66
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+# Sources of the headline kernel, and the committed hardware-counter summary of its HBM
+# traffic; the summary is used only while it was taken on these exact sources.
+KERNEL_SOURCES = ("forward.hip", "recursion.h", "cplx.h", "merge.h", "rjsmc_internal.h")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "forward_kernel_65536x5layer_fp64_hbm_traffic.txt")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2109_00661_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per headline launch (FETCH_SIZE + WRITE_SIZE, calibrated against a copy
+    of known size) from the committed counter summary, or None when the summary is
+    missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            fields = dict(line.split(":", 1) for line in f if re.match(r"^[a-z_0-9]+:", line))
+    except OSError:
+        return None
+    if fields.get("sources_sha256", "").strip() != kernel_sources_sha256():
+        return None
+    return float(fields["hbm_bytes_per_launch"])
 
 
 def nominal_flop_per_eval(n_layers, n_freq=40, n_hankel=120):
@@ -82,6 +110,69 @@ def cpu_baseline(system, d_np, budget_s=15.0):
                 sample="first %d of the 65,536 particles (numpy FP64, one thread), %.1f s" % (n_done, dt))
 
 
+def rjsmc_rate(torch, d, n_sound, n_per_sound, seed=0, move_prob=None):
+    """Soundings per second of complete Algorithm-1 runs (gamma 0 -> 1): n_sound copies
+    of the synthetic sounding, n_per_sound particles each, alpha = 0.5, 5 moves per step,
+    run together in the same launches.  Wall clock includes the per-step host check.
+    The spread over the replicate soundings of log Z of the best model and of the
+    posterior probability of a chargeable model measures Monte Carlo accuracy."""
+    from paper_2109_00661_amd import binding as B
+    from paper_2109_00661_amd.rjsmc import RJSMCRun, UNIFORM_MOVES
+    mp = UNIFORM_MOVES if move_prob is None else move_prob
+    ctx = B.Context(W.system(), precision="f64", max_particles=n_sound * n_per_sound)
+    y = np.tile(d.cpu().numpy(), (n_sound, 1))
+    RJSMCRun(ctx, n_sound, n_per_sound, y, seed=seed + 99, move_prob=mp).run()          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run = RJSMCRun(ctx, n_sound, n_per_sound, y, seed=seed, move_prob=mp).run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = run.stats.cpu().numpy()
+    probs = run.model_probabilities()
+    km = ctx.kmax_charg
+    p_ip = probs[:, (np.arange(probs.shape[1]) % (km + 1)) >= 1].sum(axis=1)
+    lz = run.log_z.cpu().numpy()
+    best = int(np.argmax(probs.mean(axis=0)))
+    out = {"soundings_per_s": n_sound / dt, "n_sound": n_sound, "particles_per_sounding": n_per_sound,
+           "steps": run.step, "seconds": dt, "proposals": int(st[0].sum()),
+           "acceptance": float(st[1].sum() / max(st[0].sum(), 1)),
+           "p_chargeable_mean": float(p_ip.mean()), "p_chargeable_sd": float(p_ip.std()),
+           "best_model": best}
+    if n_sound > 1:
+        out["log_z_best_sd"] = float(np.std(lz[:, best][np.isfinite(lz[:, best])]))
+    return out
+
+
+def adjoint_rate(torch, d, steps, warmup):
+    """Log-likelihood + gradient evaluations per second for 65,536 decoupled particles
+    with 1-8 segments per partition (merged layers up to 15)."""
+    from paper_2109_00661_amd import binding as B
+    system = W.system(kmax_cond=7, kmax_charg=7)
+    ctx = B.Context(system, precision="f64")
+    n = N_PARTICLES
+    rng = np.random.default_rng(3)
+    p = W.empty_particles(n, 7, 7)
+    p["kappa"][:] = rng.integers(0, 8, n)
+    p["lambda_"][:] = rng.integers(0, 8, n)
+    P = W.PRIOR
+    p["phi_b"][:] = rng.uniform(P["phi_lo"], P["phi_hi"], n)
+    p["log10_tau"][:] = rng.uniform(P["ltau_lo"], P["ltau_hi"], n)
+    p["c"][:] = rng.uniform(P["c_lo"], P["c_hi"], n)
+    zc = np.sort(rng.uniform(0, P["z_max"], (7, n)), axis=0)
+    zm = np.sort(rng.uniform(0, P["z_max"], (7, n)), axis=0)
+    for r in range(7):
+        p["z_cond"][r] = np.where(r < p["kappa"], zc[r], 0.0)
+        p["z_charg"][r] = np.where(r < p["lambda_"], zm[r], 0.0)
+    p["phi"][:] = rng.uniform(P["phi_lo"], P["phi_hi"], (7, n))
+    p["m"][:] = rng.uniform(P["m_lo"], P["m_hi"], (7, n))
+    dp = B.particles_to_device(p)
+    ms, _ = time_calls(lambda: ctx.loglik_grad(dp, d), steps, warmup, torch)
+    ms_f, _ = time_calls(lambda: ctx.loglik(dp, d), steps, warmup, torch)
+    ctx.check()
+    return {"grad_evals_per_s": n / (ms * 1e-3), "ms_per_launch": ms, "forward_ms_same_population": ms_f,
+            "grad_over_forward": ms / ms_f, "mean_merged_layers": float((p["kappa"] + p["lambda_"] + 1).mean())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +180,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extra", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the 65,536-particle forward+loglik launches (for profiling)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB before timing, as the "
+                         "reference for hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path runs on a single MI355X; "
@@ -104,6 +200,14 @@ def main():
     p = B.particles_to_device(W.merged_population(N_PARTICLES, N_LAYERS, seed=2, kc=N_LAYERS - 1))
     ll = torch.empty(N_PARTICLES, dtype=torch.float64, device="cuda")
 
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ms, wall = time_calls(lambda: ctx.loglik(p, d, out=ll), args.steps, args.warmup, torch)
     ctx.check()
     evals = N_PARTICLES / (ms * 1e-3)
@@ -118,14 +222,24 @@ def main():
                                "40 frequencies x 120-point J1 filter x 20 gates, FP64",
                    "particles": N_PARTICLES, "layers": N_LAYERS},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
+                     "traffic_unit": "HBM bytes per launch",
                      "kernel": "forward_kernel<8,double>", "flop_per_launch": flop},
         "wall_s_timed": wall,
     }
+    if args.headline_only:
+        print(json.dumps(out), flush=True)
+        return
     if args.extra:
         ctx32 = B.Context(system, precision="f32")
         ms32, _ = time_calls(lambda: ctx32.loglik(p, d, out=ll), args.steps, args.warmup, torch)
         out["fp32"] = {"evals_per_s": N_PARTICLES / (ms32 * 1e-3), "ms_per_step": ms32}
+    if args.extra:
+        out["adjoint"] = adjoint_rate(torch, d, max(3, args.steps // 4), 1)
+    from paper_2109_00661_amd.rjsmc import LANGEVIN_MOVES
+    out["rjsmc"] = {"single_sounding_256": rjsmc_rate(torch, d, 1, 256),
+                    "batched_64x256_rw": rjsmc_rate(torch, d, 64, 256),
+                    "batched_64x256_langevin": rjsmc_rate(torch, d, 64, 256, move_prob=LANGEVIN_MOVES)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(system, d.cpu().numpy())
     print(json.dumps(out), flush=True)

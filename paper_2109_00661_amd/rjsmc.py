@@ -11,11 +11,12 @@ from . import binding as B
 from . import workloads as W
 
 UNIFORM_MOVES = (1, 1, 1, 1, 1, 1, 1, 0)     # birth/death/move x2 partitions + within-model RW
+LANGEVIN_MOVES = (1, 1, 1, 1, 1, 1, 0, 1)    # the within-model move is the gradient-informed one
 
 
 class RJSMCRun:
     def __init__(self, ctx, n_sound, n_per_sound, y_obs, *, prior=None, alpha=0.5, n_moves=5, seed=0,
-                 move_prob=UNIFORM_MOVES, z_move_frac=0.05, rw_scale=2.38, device="cuda"):
+                 move_prob=UNIFORM_MOVES, z_move_frac=0.05, rw_scale=2.38, mala_eps=0.8, device="cuda"):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -26,6 +27,7 @@ class RJSMCRun:
         self.move_prob = move_prob
         self.z_move_sd = z_move_frac * self.prior["z_max"]
         self.rw_scale = rw_scale
+        self.mala_eps = mala_eps
         kc, km = ctx.kmax_cond, ctx.kmax_charg
         self.M = (kc + 1) * (km + 1)
         self.dmax = 3 + 2 * kc + 2 * km
@@ -40,6 +42,9 @@ class RJSMCRun:
         self.factors = torch.zeros((n_sound, self.M, self.dmax, self.dmax), dtype=torch.float64, device=device)
         self.stats = torch.zeros((2, B.N_MOVES), dtype=torch.int64, device=device)
         self.y_obs = torch.as_tensor(np.asarray(y_obs, dtype=np.float64), device=device).reshape(n_sound, -1)
+        self.grads = None
+        if move_prob[B.N_MOVES - 1] > 0:
+            self.grads = [B.empty_device_population(self.n, kc, km, nps, device) for _ in range(2)]
         self.step = 0
 
     @property
@@ -65,7 +70,9 @@ class RJSMCRun:
         self.ctx.mutate(self.state, self.ll, self.bufs[1 - self.cur], self.lls[1 - self.cur], self.gamma, self.active,
                         self.y_obs, self.stats, seed=self.seed, step=self.step, n_moves=self.n_moves,
                         n_sound=self.S, prior=self.prior, move_prob=self.move_prob, z_move_sd=self.z_move_sd,
-                        rw_scale=self.rw_scale, factors=self.factors)
+                        rw_scale=self.rw_scale, factors=self.factors, mala_eps=self.mala_eps,
+                        grad_cur=self.grads[0] if self.grads else None,
+                        grad_prop=self.grads[1] if self.grads else None)
 
     def run(self, max_steps=1000):
         self.initialise()
