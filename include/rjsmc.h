@@ -191,6 +191,8 @@ typedef struct {
  *    TESS(dg) = sum_k (sum_{i in k} w_i)^2 / sum_{i in k} w_i^2, w_i = exp(dg ll_i), stays
  *    >= alpha N; otherwise 60 bisection steps on (0, 1 - gamma] keep the lower bracket;
  *  - log_z[s][k] += logsumexp_{i in k}(dg ll_i) - ln N_k for every populated model;
+ *    a model with no member has an empty sum of incremental weights, so its estimate
+ *    (a product over steps) is 0 from then on: log_z[s][k] = -inf;
  *  - within each model, systematic resampling of its N_k members from the normalised
  *    weights quantised to round(W_i 2^60); member j (by particle index) receives the
  *    first member whose cumulative weight exceeds floor((j 2^53 + U) T / (N_k 2^53));

@@ -141,13 +141,16 @@ def next_dgamma(ll, models, gamma, alpha):
 
 def reweight(ll, models, dg, log_z, model_list):
     """Evidence update log Z_k += LSE_{i in k}(dg ll_i) - ln N_k (Algorithm 1,
-    Section 3.2.1) and the normalised within-model weights."""
+    Section 3.2.1) and the normalised within-model weights.  A model with no particle
+    at this step has an empty sum of incremental weights, so its estimate (a product
+    over steps) becomes 0, log Z_k = -inf, and stays there."""
     W = np.zeros(len(ll))
     log_z = np.array(log_z, dtype=np.float64)
     for k in model_list:
         sel = models == k
         nk = int(sel.sum())
         if nk == 0:
+            log_z[k] = -np.inf
             continue
         x = dg * ll[sel]
         lse = _logsumexp(x)

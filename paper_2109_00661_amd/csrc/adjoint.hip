@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
   for (int t = threadIdx.x; t < nf * ng; t += blockDim.x) sm.K[t] = s.K[t];
   for (int t = threadIdx.x; t < ng; t += blockDim.x) sm.eps2[t] = s.eps_an2[t];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int64_t i = (int64_t)blockIdx.x * kWavesA + wave;
+  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesA + wave;
   const bool valid = i < p.n;
   const bool skip = valid && p.mask && p.mask[i] != p.mask_value;   // left untouched
   LayerStack *st = &sm.stack[wave];
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
         sm.k2[wave][gw][l] = cplx<double>{-(wmu * sh.im), wmu * sh.re};
       }
     }
-    __syncthreads();
+    wave_lds_sync();
     if (act) {
       double acc = 0.0;
 #pragma unroll 1
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
       acc += __shfl_xor(acc, 4);
       if (gl == 0) sm.imh[wave][jf] = acc;
     }
-    __syncthreads();
+    wave_lds_sync();
   }
   // ---- gates, log-likelihood and its adjoint with respect to the gate responses
   if (L > 0) {
@@ -246,13 +246,13 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
     term += __shfl_xor(term, 32);
     if (lane == 0) sm.ll[wave] = -0.5 * term;
   }
-  __syncthreads();
+  wave_lds_sync();
   if (L > 0 && lane < nf) {
     double acc = 0.0;
     for (int gg = 0; gg < ng; ++gg) acc += sm.K[gg * nf + lane] * sm.ybar[wave][gg];
     sm.wbar[wave][lane] = acc;
   }
-  __syncthreads();
+  wave_lds_sync();
   // ---- phase B: reverse sweep per pair
 #pragma unroll 1
   for (int q = 0; q < nq; ++q) {
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
         sm.k2[wave][gw][l] = cplx<double>{-(wmu * sh.im), wmu * sh.re};
       }
     }
-    __syncthreads();
+    wave_lds_sync();
     if (act) {
       cplx<double> G[LMAX];
       double H[LMAX];
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
         sl[3 * LMAX + 1] += (Gz * (zc * cplx<double>{log(w) + log_tau, kHalfPi})).im; // dz/dc
       }
     }
-    __syncthreads();
+    wave_lds_sync();
   }
   // ---- merged-layer gradients -> particle parameters
   if (L > 0) {
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
       sm.gl[wave][t] = acc;
     }
   }
-  __syncthreads();
+  wave_lds_sync();
   if (valid && !skip && lane == 0) {
     // one lane zeroes the particle's gradient slots and routes the merged-layer gradients
     const int64_t S = p.stride;

@@ -104,17 +104,102 @@ __device__ __forceinline__ cplx<float> csqrt(cplx<float> z) {
   return z.re >= 0.0f ? cplx<float>{t, o} : cplx<float>{fabsf(o), copysignf(t, z.im)};
 }
 
-__device__ __forceinline__ cplx<double> cexp(cplx<double> z) {
-  const double e = exp(z.re);
-  double s, c;
-  sincos(z.im, &s, &c);
-  return {e * c, e * s};
+// exp(z) for the propagation factors exp(-2 h u), Re z <= 0 (Re z < -1000 gives 0;
+// NaN propagates).  Cody-Waite reduction and Taylor polynomials on the reduced range:
+//   exp(x) = 2^k exp(r),  k = rint(x / ln 2),  r = x - k ln 2,  |r| <= ln(2)/2,
+//   (cos y, sin y) = i^q (cos t, sin t),  q = rint(y 2/pi),  t = y - q pi/2,  |t| <= pi/4,
+// with ln 2 and pi/2 split into two and three doubles so that r and t are exact to a
+// few ulp for |y| < 2^20 (beyond that exp(x) underflows whenever |Im u| <= 3.2 Re u,
+// which the Cole-Cole layer wavenumbers guarantee for m < 1).  Truncation after r^12
+// (exp), t^15 (sin) and t^16 (cos) leaves remainders below 4e-16, 6e-17 and 2e-18.
+namespace detail {
+constexpr double kInvLn2 = 0x1.71547652b82fep+0;
+constexpr double kLn2Hi = 0x1.62e42fefa39efp-1, kLn2Lo = 0x1.abc9e3b39803fp-56;
+constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
+constexpr double kPio2A = 0x1.921fb54442d18p+0, kPio2B = 0x1.1a62633145c07p-54,
+                 kPio2C = -0x1.f1976b7ed8fbcp-110;
+// 1/n! for n = 0..16 (every n! here is exact in double: one rounding per entry)
+constexpr double kInvFact[17] = {1.0, 1.0, 1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0,
+    1.0 / 720.0, 1.0 / 5040.0, 1.0 / 40320.0, 1.0 / 362880.0, 1.0 / 3628800.0,
+    1.0 / 39916800.0, 1.0 / 479001600.0, 1.0 / 6227020800.0, 1.0 / 87178291200.0,
+    1.0 / 1307674368000.0, 1.0 / 20922789888000.0};
+template <int N>
+__device__ __forceinline__ double exp_taylor(double r) {   // sum_{n<=N} r^n / n!
+  double p = kInvFact[N];
+#pragma unroll
+  for (int n = N - 1; n >= 0; --n) p = fma(p, r, kInvFact[n]);
+  return p;
 }
+}  // namespace detail
+
+__device__ __forceinline__ cplx<double> cexp(cplx<double> z) {
+  using namespace detail;
+  const double x = z.re < -1000.0 ? -1000.0 : z.re;
+  const double kx = rint(x * kInvLn2);
+  double r = fma(kx, -kLn2Hi, x);
+  r = fma(kx, -kLn2Lo, r);
+  const double e = ldexp(exp_taylor<12>(r), (int)kx);
+
+  const double qy = rint(z.im * kTwoOverPi);
+  double t = fma(qy, -kPio2A, z.im);
+  t = fma(qy, -kPio2B, t);
+  t = fma(qy, -kPio2C, t);
+  // sin t = t P(-t^2), cos t = Q(-t^2) with P(x) = sum x^k / (2k+1)!, Q(x) = sum x^k / (2k)!:
+  // every coefficient is a positive 1/n!, the same constants as the exp polynomial
+  const double x2 = -(t * t);
+  double S = kInvFact[15];
+#pragma unroll
+  for (int n = 13; n >= 3; n -= 2) S = fma(S, x2, kInvFact[n]);
+  const double st = fma(t * x2, S, t);
+  double C = kInvFact[16];
+#pragma unroll
+  for (int n = 14; n >= 2; n -= 2) C = fma(C, x2, kInvFact[n]);
+  const double ct = fma(x2, C, 1.0);
+  const int q = (int)qy;
+  const double a = (q & 1) ? st : ct, b = (q & 1) ? ct : st;
+  const double cy = ((q + 1) & 2) ? -a : a, sy = (q & 2) ? -b : b;
+  return {e * cy, e * sy};
+}
+
+// FP32 variant: the same reductions, truncation after r^7, t^9 and t^10.
 __device__ __forceinline__ cplx<float> cexp(cplx<float> z) {
-  const float e = expf(z.re);
-  float s, c;
-  sincosf(z.im, &s, &c);
-  return {e * c, e * s};
+  constexpr float kInvLn2f = 0x1.715476p+0f, kLn2Hif = 0x1.62e430p-1f, kLn2Lof = -0x1.05c610p-29f;
+  constexpr float kTwoOverPif = 0x1.45f306p-1f;
+  constexpr float kPio2Af = 0x1.921fb6p+0f, kPio2Bf = -0x1.777a5cp-25f, kPio2Cf = -0x1.ee59dap-50f;
+  const float x = z.re < -110.0f ? -110.0f : z.re;
+  const float kx = rintf(x * kInvLn2f);
+  float r = fmaf(kx, -kLn2Hif, x);
+  r = fmaf(kx, -kLn2Lof, r);
+  float p = 1.0f / 5040.0f;
+  p = fmaf(p, r, 1.0f / 720.0f);
+  p = fmaf(p, r, 1.0f / 120.0f);
+  p = fmaf(p, r, 1.0f / 24.0f);
+  p = fmaf(p, r, 1.0f / 6.0f);
+  p = fmaf(p, r, 0.5f);
+  p = fmaf(p, r, 1.0f);
+  p = fmaf(p, r, 1.0f);
+  const float e = ldexpf(p, (int)kx);
+
+  const float qy = rintf(z.im * kTwoOverPif);
+  float t = fmaf(qy, -kPio2Af, z.im);
+  t = fmaf(qy, -kPio2Bf, t);
+  t = fmaf(qy, -kPio2Cf, t);
+  const float t2 = t * t;
+  float S = 1.0f / 362880.0f;
+  S = fmaf(S, t2, -1.0f / 5040.0f);
+  S = fmaf(S, t2, 1.0f / 120.0f);
+  S = fmaf(S, t2, -1.0f / 6.0f);
+  const float st = fmaf(t * t2, S, t);
+  float C = -1.0f / 3628800.0f;
+  C = fmaf(C, t2, 1.0f / 40320.0f);
+  C = fmaf(C, t2, -1.0f / 720.0f);
+  C = fmaf(C, t2, 1.0f / 24.0f);
+  C = fmaf(C, t2, -0.5f);
+  const float ct = fmaf(t2, C, 1.0f);
+  const int q = (int)qy;
+  const float a = (q & 1) ? st : ct, b = (q & 1) ? ct : st;
+  const float cy = ((q + 1) & 2) ? -a : a, sy = (q & 2) ? -b : b;
+  return {e * cy, e * sy};
 }
 
 }  // namespace rjsmc

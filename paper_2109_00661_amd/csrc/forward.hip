@@ -4,11 +4,13 @@
 // abscissa) plane as 8 frequency groups x 8 abscissa groups: lane (g_w, g_l) handles
 // frequencies g_w + 8q and abscissae g_l + 8s, so 40 x 120 pairs give exactly 75 per
 // lane and the layer loop is uniform across the wave (one particle, one layer count).
-// Per pair the lane runs the TE reflection recursion in registers (the layer loop is
-// unrolled to a compile-time cap); partial Hankel sums of Im r_TE are reduced over the
+// Per pair the lane runs the TE reflection recursion in registers (a runtime layer
+// loop over LDS-resident k^2 and thicknesses); partial Hankel sums of Im r_TE are reduced over the
 // 8 abscissa groups with xor shuffles, the 40 values go through LDS, and 20 lanes apply
-// the frequency-to-time matrix and the likelihood terms.  The kernel is bound by FP64
-// (or FP32) vector ALU work: ~24,000 layer steps per particle for 5 layers.
+// the frequency-to-time matrix and the likelihood terms.  After the workgroup stages the
+// shared tables in LDS its waves run independently (wave-level syncs only), so a
+// particle with few layers does not wait for a deeper neighbour.  The kernel is bound
+// by FP64 (or FP32) vector ALU work: ~24,000 layer steps per particle for 5 layers.
 #include <hip/hip_runtime.h>
 
 #include "cplx.h"
@@ -53,7 +55,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
 
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
   const bool valid = i < p.n;
   const bool skip = valid && p.mask && p.mask[i] != p.mask_value;
   LayerStack *st = &s_stack[wave];
@@ -71,7 +73,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
   const int gl = lane & 7, gw = lane >> 3;
   const int nhg = nhp >> 3;
   const int nq = (nf + 7) >> 3;
-  // every wave runs the same number of q iterations (block barriers inside)
+  // the waves of a workgroup run independently from here on (wave-level syncs only)
 #pragma unroll 1
   for (int q = 0; q < nq; ++q) {
     const int jf = gw + 8 * q;
@@ -89,7 +91,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
         s_k2[wave][gw][l] = cplx<T>{-(wmu * sh.im), wmu * sh.re};
       }
     }
-    __syncthreads();
+    wave_lds_sync();
     if (act) {
       double acc = 0.0;
 #pragma unroll 1
@@ -105,9 +107,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
       acc += __shfl_xor(acc, 4);
       if (gl == 0) s_imh[wave][jf] = acc;
     }
-    __syncthreads();
+    wave_lds_sync();
   }
-  __syncthreads();
   if (L > 0) {
     double term = 0.0;
     if (lane < ng) {

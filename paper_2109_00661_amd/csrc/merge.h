@@ -25,8 +25,8 @@ struct LayerStack {
   int L;                      // number of layers, 0 if the particle is invalid
 };
 
-// Lanes of one wavefront cooperate; `st` is this wave's LDS slot.  Every wave of the
-// block must call this (it contains two block barriers); waves without a particle pass
+// Lanes of one wavefront cooperate; `st` is this wave's LDS slot.  All 64 lanes of the
+// wave must call this (it syncs the wave twice); a wave without a particle passes
 // valid = false.  Returns L (>= 1) or 0 for no / an invalid particle (flags raised).
 // Property rule: a layer takes the conductivity segment below the last conductivity
 // interface at or above its top, and likewise for chargeability (zero above the first
@@ -85,7 +85,7 @@ __device__ __forceinline__ int merge_particle(const DevParticles &p, int64_t i, 
     }
   }
   const bool any_bad = __any(bad);
-  __syncthreads();
+  wave_lds_sync();
   if (ok && any_bad) {
     if (lane == 0) atomicOr(flags, kFlagUnsorted);
     ok = false;
@@ -110,7 +110,7 @@ __device__ __forceinline__ int merge_particle(const DevParticles &p, int64_t i, 
     }
   }
   if (ok && lane == 0) st->L = L;
-  __syncthreads();
+  wave_lds_sync();
   return ok ? L : 0;
 }
 

@@ -18,6 +18,25 @@ constexpr int kMaxGate = 32;      // gates
 constexpr int kMaxLayers = 16;    // merged layers per particle
 constexpr int kWave = 64;
 
+// Workgroups are dealt to the eight XCDs of the chip in turn (workgroup b runs on XCD
+// b mod 8), and each XCD has its own L2.  Kernels that give neighbouring particles to
+// neighbouring workgroups renumber them so that each XCD takes one contiguous range:
+// the particle columns' cache lines are then fetched by one L2 instead of several.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  const uint32_t per = nb / kXcds, rem = nb % kXcds;
+  const uint32_t x = b % kXcds, j = b / kXcds;
+  return x * per + (x < rem ? x : rem) + j;
+}
+
+// Orders a wave's LDS writes before later LDS reads of other lanes of the same wave
+// (a compiler barrier with wave-wide release/acquire; no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
 // Device flag bits raised by kernels, reported by rjsmc_check.
 constexpr int kFlagCapacity = 1;
 constexpr int kFlagUnsorted = 2;

@@ -316,7 +316,11 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
   // evidence, quantised weights and per-model cumulative sums (wave per model)
   for (int m = wave; m < M; m += kRwWaves) {
     const int n = sm.cnt[m];
-    if (n == 0) continue;
+    if (n == 0) {
+      // empty sum of incremental weights: the model's evidence estimate becomes 0
+      if (lane == 0) log_z[(int64_t)s * M + m] = -HUGE_VAL;
+      continue;
+    }
     const double mx = sm.mx[m];
     const bool live = mx > -HUGE_VAL;
     const double inv = live ? 1.0 / sm.s1[m] : 0.0;

@@ -59,8 +59,11 @@ def test_constant_likelihood_single_step():
     lam = np.zeros(64, dtype=int)
     g, lz, anc = smc.reweight_resample(ll, kap, lam, 4, 3, np.zeros(1), np.zeros((1, 20)), 0.5, 9, 1)
     assert g[0] == 1.0
-    for k in range(4):
-        assert abs(lz[0, smc.model_id(k, 0, 3)] - (-3.25)) < 1e-14
+    present = [smc.model_id(k, 0, 3) for k in range(4)]
+    for m in present:
+        assert abs(lz[0, m] - (-3.25)) < 1e-14
+    # models without particles: empty sum of incremental weights, estimate 0
+    assert all(lz[0, m] == -np.inf for m in range(20) if m not in present)
     assert np.array_equal(anc, np.arange(64))          # equal weights: every particle once
 
 
