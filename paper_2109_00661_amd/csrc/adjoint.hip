@@ -40,7 +40,8 @@ __device__ __forceinline__ cplx<double> cdiv_fast(cplx<double> a, cplx<double> b
 // G[l] (d(wt r)/d k2_l) and H[l] (Im d(wt r)/d h_l).
 template <int LMAX>
 __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2, const double *thk, int L,
-                                             double wt, cplx<double> (&G)[LMAX], double (&H)[LMAX]) {
+                                             double wt, cplx<double> (&G)[LMAX], double (&H)[LMAX],
+                                             const cplx<double> *phase, const double *e2) {
   const double lam2 = lam * lam;
   cplx<double> rt[LMAX];            // generalized reflection coefficient below interface l
   // ---- bottom-up recursion, classic form
@@ -55,7 +56,7 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
           rt[l] = R;
         } else {
           const double h2 = -2.0 * thk[l + 1];
-          const cplx<double> E = cexp(cplx<double>{h2 * ub.re, h2 * ub.im});
+          const cplx<double> E = cexp_tab(cplx<double>{h2 * ub.re, h2 * ub.im}, phase, e2);
           const cplx<double> rho = rt[l + 1] * E;
           rt[l] = cdiv_fast(R + rho, cplx<double>{1.0, 0.0} + R * rho);
         }
@@ -75,7 +76,7 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
     Rbar_air = wb;
   } else {
     const double h2 = -2.0 * thk[0];
-    const cplx<double> E = cexp(cplx<double>{h2 * ul.re, h2 * ul.im});
+    const cplx<double> E = cexp_tab(cplx<double>{h2 * ul.re, h2 * ul.im}, phase, e2);
     const cplx<double> rho = rt[0] * E;
     const cplx<double> den = one + Rair * rho;
     const cplx<double> iden2 = crcp_fast(csq(den));
@@ -111,7 +112,7 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
         Rbar = rtbar;
       } else {
         const double h2 = -2.0 * thk[l + 1];
-        const cplx<double> E = cexp(cplx<double>{h2 * un.re, h2 * un.im});
+        const cplx<double> E = cexp_tab(cplx<double>{h2 * un.re, h2 * un.im}, phase, e2);
         const cplx<double> rho = rt[l + 1] * E;
         const cplx<double> iden2 = crcp_fast(csq(one + R * rho));
         Rbar = rtbar * (one - csq(rho)) * iden2;
@@ -148,6 +149,8 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
 template <int LMAX>
 struct AdjShared {
   double lam[kMaxHankel], ck[kMaxHankel], omega[kMaxFreq], K[kMaxGate * kMaxFreq], eps2[kMaxGate];
+  cplx<double> phase[kPhaseN];
+  double exp2t[kExp2N];
   LayerStack stack[kWavesA];
   double wbar[kWavesA][kMaxFreq];
   double imh[kWavesA][kMaxFreq];
@@ -171,6 +174,9 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
   for (int t = threadIdx.x; t < nf; t += blockDim.x) sm.omega[t] = s.omega[t];
   for (int t = threadIdx.x; t < nf * ng; t += blockDim.x) sm.K[t] = s.K[t];
   for (int t = threadIdx.x; t < ng; t += blockDim.x) sm.eps2[t] = s.eps_an2[t];
+  for (int t = threadIdx.x; t < kPhaseN; t += blockDim.x)
+    sm.phase[t] = cplx<double>{s.phase[2 * t], s.phase[2 * t + 1]};
+  for (int t = threadIdx.x; t < kExp2N; t += blockDim.x) sm.exp2t[t] = s.exp2t[t];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesA + wave;
   const bool valid = i < p.n;
@@ -213,7 +219,7 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
 #pragma unroll 1
       for (int sidx = 0; sidx < nhg; ++sidx) {
         const int k = gl + 8 * sidx;
-        acc += sm.ck[k] * reflection_im<double>(sm.lam[k], sm.k2[wave][gw], sm.thk[wave], L);
+        acc += sm.ck[k] * reflection_im<double>(sm.lam[k], sm.k2[wave][gw], sm.thk[wave], L, sm.phase, sm.exp2t);
       }
       acc += __shfl_xor(acc, 1);
       acc += __shfl_xor(acc, 2);
@@ -285,7 +291,8 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
 #pragma unroll 1
       for (int sidx = 0; sidx < nhg; ++sidx) {
         const int k = gl + 8 * sidx;
-        pair_adjoint<LMAX>(sm.lam[k], sm.k2[wave][gw], sm.thk[wave], L, sm.ck[k] * wj, G, H);
+        pair_adjoint<LMAX>(sm.lam[k], sm.k2[wave][gw], sm.thk[wave], L, sm.ck[k] * wj, G, H, sm.phase,
+                           sm.exp2t);
       }
 #pragma unroll
       for (int l = 0; l < LMAX; ++l) {

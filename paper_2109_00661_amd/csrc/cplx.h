@@ -104,64 +104,64 @@ __device__ __forceinline__ cplx<float> csqrt(cplx<float> z) {
   return z.re >= 0.0f ? cplx<float>{t, o} : cplx<float>{fabsf(o), copysignf(t, z.im)};
 }
 
-// exp(z) for the propagation factors exp(-2 h u), Re z <= 0 (Re z < -1000 gives 0;
-// NaN propagates).  Cody-Waite reduction and Taylor polynomials on the reduced range:
-//   exp(x) = 2^k exp(r),  k = rint(x / ln 2),  r = x - k ln 2,  |r| <= ln(2)/2,
-//   (cos y, sin y) = i^q (cos t, sin t),  q = rint(y 2/pi),  t = y - q pi/2,  |t| <= pi/4,
-// with ln 2 and pi/2 split into two and three doubles so that r and t are exact to a
-// few ulp for |y| < 2^20 (beyond that exp(x) underflows whenever |Im u| <= 3.2 Re u,
-// which the Cole-Cole layer wavenumbers guarantee for m < 1).  Truncation after r^12
-// (exp), t^15 (sin) and t^16 (cos) leaves remainders below 4e-16, 6e-17 and 2e-18.
+// Constants of the Cody-Waite reductions of the propagation-factor exponentials: 1/ln 2,
+// ln 2 and pi/2 split into two and three doubles (so that k ln2 and q pi/2 subtract
+// exactly for the integer multiples that occur), 2/pi, and 1/n!.
 namespace detail {
 constexpr double kInvLn2 = 0x1.71547652b82fep+0;
 constexpr double kLn2Hi = 0x1.62e42fefa39efp-1, kLn2Lo = 0x1.abc9e3b39803fp-56;
 constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
 constexpr double kPio2A = 0x1.921fb54442d18p+0, kPio2B = 0x1.1a62633145c07p-54,
                  kPio2C = -0x1.f1976b7ed8fbcp-110;
-// 1/n! for n = 0..16 (every n! here is exact in double: one rounding per entry)
-constexpr double kInvFact[17] = {1.0, 1.0, 1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0,
-    1.0 / 720.0, 1.0 / 5040.0, 1.0 / 40320.0, 1.0 / 362880.0, 1.0 / 3628800.0,
-    1.0 / 39916800.0, 1.0 / 479001600.0, 1.0 / 6227020800.0, 1.0 / 87178291200.0,
-    1.0 / 1307674368000.0, 1.0 / 20922789888000.0};
-template <int N>
-__device__ __forceinline__ double exp_taylor(double r) {   // sum_{n<=N} r^n / n!
-  double p = kInvFact[N];
-#pragma unroll
-  for (int n = N - 1; n >= 0; --n) p = fma(p, r, kInvFact[n]);
-  return p;
-}
+// 1/n! for n = 0..8 (every n! here is exact in double: one rounding per entry)
+constexpr double kInvFact[9] = {1.0, 1.0, 1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0,
+                                1.0 / 720.0, 1.0 / 5040.0, 1.0 / 40320.0};
 }  // namespace detail
 
-__device__ __forceinline__ cplx<double> cexp(cplx<double> z) {
+// exp(z) for the propagation factors in FP64, Re z <= 0, with two small tables in LDS:
+// phase[j] = (cos, sin)(j pi/32) and e2[j] = 2^(j/64), j = 0..63.  With
+//   k = rint(64 x / ln 2), r = x - k ln2/64 (|r| <= ln2/128),
+//   j = rint(32 y / pi),   d = y - j pi/32   (|d| <= pi/64),
+//   exp(x + iy) = 2^floor(k/64) e2[k mod 64] e^r phase[j mod 64] (cos d + i sin d),
+// and Taylor polynomials of degree 5 (e^r), 7 (sin d) and 8 (cos d), whose remainders
+// are below 4e-17, 5e-18 and 3e-20.  Re z < -1000 gives 0; a NaN real part is clamped
+// too (the recursion still propagates it through u), a NaN imaginary part gives NaN.
+__device__ __forceinline__ cplx<double> cexp_tab(cplx<double> z, const cplx<double> *phase,
+                                                 const double *e2) {
   using namespace detail;
-  const double x = z.re < -1000.0 ? -1000.0 : z.re;
-  const double kx = rint(x * kInvLn2);
-  double r = fma(kx, -kLn2Hi, x);
-  r = fma(kx, -kLn2Lo, r);
-  const double e = ldexp(exp_taylor<12>(r), (int)kx);
+  const double x = fmax(z.re, -1000.0);
+  const double kx = rint(x * (64.0 * kInvLn2));
+  double r = fma(kx, -(kLn2Hi / 64.0), x);
+  r = fma(kx, -(kLn2Lo / 64.0), r);
+  double p = fma(r, kInvFact[5], kInvFact[4]);
+  p = fma(p, r, kInvFact[3]);
+  p = fma(p, r, kInvFact[2]);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  const int ki = (int)kx;
+  const double e = ldexp(p * e2[ki & 63], ki >> 6);   // ki >> 6 = floor(ki / 64)
 
-  const double qy = rint(z.im * kTwoOverPi);
-  double t = fma(qy, -kPio2A, z.im);
-  t = fma(qy, -kPio2B, t);
-  t = fma(qy, -kPio2C, t);
-  // sin t = t P(-t^2), cos t = Q(-t^2) with P(x) = sum x^k / (2k+1)!, Q(x) = sum x^k / (2k)!:
-  // every coefficient is a positive 1/n!, the same constants as the exp polynomial
-  const double x2 = -(t * t);
-  double S = kInvFact[15];
-#pragma unroll
-  for (int n = 13; n >= 3; n -= 2) S = fma(S, x2, kInvFact[n]);
-  const double st = fma(t * x2, S, t);
-  double C = kInvFact[16];
-#pragma unroll
-  for (int n = 14; n >= 2; n -= 2) C = fma(C, x2, kInvFact[n]);
-  const double ct = fma(x2, C, 1.0);
-  const int q = (int)qy;
-  const double a = (q & 1) ? st : ct, b = (q & 1) ? ct : st;
-  const double cy = ((q + 1) & 2) ? -a : a, sy = (q & 2) ? -b : b;
-  return {e * cy, e * sy};
+  const double jy = rint(z.im * (16.0 * kTwoOverPi));
+  double d = fma(jy, -(kPio2A / 16.0), z.im);
+  d = fma(jy, -(kPio2B / 16.0), d);
+  d = fma(jy, -(kPio2C / 16.0), d);
+  const double x2 = -(d * d);
+  double S = fma(x2, kInvFact[7], kInvFact[5]);
+  S = fma(S, x2, kInvFact[3]);
+  const double sd = fma(d * x2, S, d);
+  double C = fma(x2, kInvFact[8], kInvFact[6]);
+  C = fma(C, x2, kInvFact[4]);
+  C = fma(C, x2, kInvFact[2]);
+  const double cd = fma(x2, C, 1.0);
+  const cplx<double> t = phase[(int)jy & 63];
+  return {e * (t.re * cd - t.im * sd), e * (t.im * cd + t.re * sd)};
 }
 
-// FP32 variant: the same reductions, truncation after r^7, t^9 and t^10.
+// exp(z) for the propagation factors in FP32, Re z <= 0 (Re z < -110 gives 0):
+//   exp(x) = 2^k exp(r),  k = rint(x / ln 2),  r = x - k ln 2,  |r| <= ln(2)/2,
+//   (cos y, sin y) = i^q (cos t, sin t),  q = rint(y 2/pi),  t = y - q pi/2,  |t| <= pi/4,
+// with ln 2 and pi/2 split into two and three floats, and Taylor polynomials truncated
+// after r^7 (exp), t^9 (sin) and t^10 (cos): remainders below 7e-9, 2e-9 and 2e-10.
 __device__ __forceinline__ cplx<float> cexp(cplx<float> z) {
   constexpr float kInvLn2f = 0x1.715476p+0f, kLn2Hif = 0x1.62e430p-1f, kLn2Lof = -0x1.05c610p-29f;
   constexpr float kTwoOverPif = 0x1.45f306p-1f;

@@ -39,6 +39,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
   __shared__ double s_omega[kMaxFreq];
   __shared__ double s_K[kMaxGate * kMaxFreq];
   __shared__ double s_eps2[kMaxGate];
+  __shared__ cplx<double> s_phase[kPhaseN];
+  __shared__ double s_exp2[kExp2N];
   __shared__ LayerStack s_stack[kWavesPerBlock];
   __shared__ double s_imh[kWavesPerBlock][kMaxFreq];
   __shared__ cplx<T> s_k2[kWavesPerBlock][8][kMaxLayers];
@@ -52,6 +54,9 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
   for (int t = threadIdx.x; t < nf; t += blockDim.x) s_omega[t] = s.omega[t];
   for (int t = threadIdx.x; t < nf * ng; t += blockDim.x) s_K[t] = s.K[t];
   for (int t = threadIdx.x; t < ng; t += blockDim.x) s_eps2[t] = s.eps_an2[t];
+  for (int t = threadIdx.x; t < kPhaseN; t += blockDim.x)
+    s_phase[t] = cplx<double>{s.phase[2 * t], s.phase[2 * t + 1]};
+  for (int t = threadIdx.x; t < kExp2N; t += blockDim.x) s_exp2[t] = s.exp2t[t];
 
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
@@ -97,7 +102,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
 #pragma unroll 1
       for (int sidx = 0; sidx < nhg; ++sidx) {
         const int k = gl + 8 * sidx;
-        const T rim = reflection_im<T>(to<T>(s_lam[k]), s_k2[wave][gw], s_thk[wave], L);
+        const T rim = reflection_im<T>(to<T>(s_lam[k]), s_k2[wave][gw], s_thk[wave], L, s_phase, s_exp2);
         acc += s_ck[k] * static_cast<double>(rim);
       }
       // reduce over the 8 abscissa groups (lane bits 0..2); all 8 lanes of a group

@@ -186,7 +186,7 @@ using rjsmc::DevParticles;
 extern "C" const char *rjsmc_last_error(void) { return g_last_error.c_str(); }
 
 static void free_dev(rjsmc::DevSystem &d) {
-  void *ptrs[] = {d.omega, d.lam, d.ck, d.K, d.eps_an2, d.flags};
+  void *ptrs[] = {d.omega, d.lam, d.ck, d.K, d.eps_an2, d.phase, d.exp2t, d.flags};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   memset(&d, 0, sizeof d);
@@ -244,6 +244,14 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
     ck[k] = 0.5 * s->current_a * s->hankel_w[k] * lam[k] * std::exp(-2.0 * lam[k] * s->height_m);
   }
   for (int g = 0; g < ng; ++g) eps2[g] = s->eps_an[g] * s->eps_an[g];
+  // tables of the propagation-factor exponential, from extended-precision libm
+  std::vector<double> phase(2 * rjsmc::kPhaseN), exp2t(rjsmc::kExp2N);
+  const long double pil = acosl(-1.0L);
+  for (int j = 0; j < rjsmc::kPhaseN; ++j) {
+    phase[2 * j] = (double)cosl(pil * j / 32);
+    phase[2 * j + 1] = (double)sinl(pil * j / 32);
+  }
+  for (int j = 0; j < rjsmc::kExp2N; ++j) exp2t[j] = (double)exp2l(j / 64.0L);
   c->K_host = new double[(size_t)ng * nf];
   rjsmc::build_time_kernel(s->freq_hz, nf, s->gate_open_s, s->gate_close_s, ng, c->K_host);
 
@@ -255,7 +263,9 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
              {&d.lam, lam.data(), (size_t)nhp},
              {&d.ck, ck.data(), (size_t)nhp},
              {&d.K, c->K_host, (size_t)ng * nf},
-             {&d.eps_an2, eps2.data(), (size_t)ng}};
+             {&d.eps_an2, eps2.data(), (size_t)ng},
+             {&d.phase, phase.data(), phase.size()},
+             {&d.exp2t, exp2t.data(), exp2t.size()}};
   for (auto &u : ups) {
     e = hipMalloc((void **)u.dst, u.n * sizeof(double));
     if (e == hipSuccess) e = hipMemcpy(*u.dst, u.src, u.n * sizeof(double), hipMemcpyHostToDevice);

@@ -29,10 +29,21 @@ __device__ __forceinline__ void rescale<float>(cplx<float> &N, cplx<float> &D) {
   D = {ldexpf(D.re, e), ldexpf(D.im, e)};
 }
 
+// Propagation factor exp(-2 h u): table-assisted in FP64, polynomial in FP32.
+__device__ __forceinline__ cplx<double> prop_exp(cplx<double> z, const cplx<double> *phase,
+                                                 const double *e2) {
+  return cexp_tab(z, phase, e2);
+}
+__device__ __forceinline__ cplx<float> prop_exp(cplx<float> z, const cplx<double> *, const double *) {
+  return cexp(z);
+}
+
 // k2[l] (layers 0..L-1) and thk[l] (l < L-1) are read from LDS: the layer loop is a
-// runtime loop whose carried state is N, D, u_{l+1} and k2_{l+1}.
+// runtime loop whose carried state is N, D, u_{l+1} and k2_{l+1}.  phase / e2 are the
+// LDS copies of the exponential's tables (used in FP64).
 template <typename T>
-__device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const T *thk, int L) {
+__device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const T *thk, int L,
+                                           const cplx<double> *phase, const double *e2) {
   const T lam2 = lam * lam;
   cplx<T> k2b = k2[L - 1];
   cplx<T> ub = csqrt_fast(cplx<T>{lam2 + k2b.re, k2b.im});
@@ -56,7 +67,7 @@ __device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const T *th
       const cplx<T> A = kl - k2b;
       const cplx<T> B = csq(u + ub);
       const T h2 = T(-2) * thk[l + 1];
-      const cplx<T> NE = N * cexp(cplx<T>{h2 * ub.re, h2 * ub.im});
+      const cplx<T> NE = N * prop_exp(cplx<T>{h2 * ub.re, h2 * ub.im}, phase, e2);
       const cplx<T> Nn = A * D + B * NE;
       D = B * D + A * NE;
       N = Nn;
@@ -67,7 +78,7 @@ __device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const T *th
     const cplx<T> A0 = {-k2b.re, -k2b.im};
     const cplx<T> B0 = csq(cplx<T>{lam + ub.re, ub.im});
     const T h2 = T(-2) * thk[0];
-    const cplx<T> NE = N * cexp(cplx<T>{h2 * ub.re, h2 * ub.im});
+    const cplx<T> NE = N * prop_exp(cplx<T>{h2 * ub.re, h2 * ub.im}, phase, e2);
     const cplx<T> Nn = A0 * D + B0 * NE;
     D = B0 * D + A0 * NE;
     N = Nn;
