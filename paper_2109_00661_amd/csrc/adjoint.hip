@@ -156,7 +156,9 @@ struct AdjShared {
   double imh[kWavesA][kMaxFreq];
   double ybar[kWavesA][kMaxGate];
   cplx<double> k2[kWavesA][8][kMaxLayers];
+  cplx<double> dk2[kWavesA][8][kMaxLayers];
   double thk[kWavesA][kMaxLayers];
+  double h2[kWavesA][kMaxLayers];
   double slot[kWavesA][8][3 * LMAX + 2];
   double gl[kWavesA][3 * LMAX + 2];
   double ll[kWavesA];
@@ -192,7 +194,10 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
     c = p.c[i];
     log_tau = p.log10_tau[i] * kLn10;
     sincospi(0.5 * c, &spc, &cpc);
-    if (lane < L - 1) sm.thk[wave][lane] = st->top[lane + 1] - st->top[lane];
+    if (lane < L - 1) {
+      sm.thk[wave][lane] = st->top[lane + 1] - st->top[lane];
+      sm.h2[wave][lane] = -2.0 * (st->top[lane + 1] - st->top[lane]);
+    }
   }
   const int gl = lane & 7, gw = lane >> 3;
   const int nhg = nhp >> 3;
@@ -207,10 +212,15 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
       const double pw = exp(c * (log(w) + log_tau));
       const cplx<double> qcc = crcp(cplx<double>{1.0 + pw * cpc, pw * spc});
       const double wmu = w * kMu0A;
-      for (int l = gl; l < L; l += 8) {
+      auto k2_of = [&](int l) {
         const double sg = st->sig[l], mg = st->m[l];
         const cplx<double> sh = {sg * (1.0 - mg * qcc.re), sg * (-(mg * qcc.im))};
-        sm.k2[wave][gw][l] = cplx<double>{-(wmu * sh.im), wmu * sh.re};
+        return cplx<double>{-(wmu * sh.im), wmu * sh.re};
+      };
+      for (int l = gl; l < L; l += 8) {
+        const cplx<double> kl = k2_of(l);
+        sm.k2[wave][gw][l] = kl;
+        if (l + 1 < L) sm.dk2[wave][gw][l] = kl - k2_of(l + 1);
       }
     }
     wave_lds_sync();
@@ -219,7 +229,8 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
 #pragma unroll 1
       for (int sidx = 0; sidx < nhg; ++sidx) {
         const int k = gl + 8 * sidx;
-        acc += sm.ck[k] * reflection_im<double>(sm.lam[k], sm.k2[wave][gw], sm.thk[wave], L, sm.phase, sm.exp2t);
+        acc += sm.ck[k] * reflection_im<double>(sm.lam[k], sm.k2[wave][gw], sm.dk2[wave][gw], sm.h2[wave], L,
+                                      sm.phase, sm.exp2t);
       }
       acc += __shfl_xor(acc, 1);
       acc += __shfl_xor(acc, 2);

@@ -45,23 +45,22 @@ __device__ __forceinline__ cplx<T> crcp(cplx<T> b) {
   return {b.re * inv, -b.im * inv};
 }
 
-// 1/sqrt(x) and sqrt(x) for x > 0 (finite, normal): hardware estimate refined by two
-// Goldschmidt steps (relative error a few ulp).
-__device__ __forceinline__ void rsqrt_sqrt(double x, double &rs, double &sq) {
-  double y = __builtin_amdgcn_rsq(x);
+// sqrt(x) and 1/(2 sqrt(x)) for x > 0 (finite, normal): hardware reciprocal-square-root
+// estimate refined by two Goldschmidt steps (relative error a few ulp).
+__device__ __forceinline__ void sqrt_hrsqrt(double x, double &sq, double &hrs) {
+  const double y = __builtin_amdgcn_rsq(x);
   double g = x * y, h = 0.5 * y;
   double r = fma(-g, h, 0.5);
   g = fma(g, r, g);
   h = fma(h, r, h);
   r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  h = fma(h, r, h);
-  sq = g;
-  rs = 2.0 * h;
+  sq = fma(g, r, g);
+  hrs = fma(h, r, h);
 }
-__device__ __forceinline__ void rsqrt_sqrt(float x, float &rs, float &sq) {
-  rs = __builtin_amdgcn_rsqf(x);
-  sq = x * rs;
+__device__ __forceinline__ void sqrt_hrsqrt(float x, float &sq, float &hrs) {
+  const float y = __builtin_amdgcn_rsqf(x);
+  sq = x * y;
+  hrs = 0.5f * y;
 }
 
 // 1/x for finite normal x != 0: hardware estimate and two Newton steps.
@@ -78,14 +77,14 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 // real axis or at 0): both sqrt and its reciprocal from one refined estimate.
 template <typename T>
 __device__ __forceinline__ cplx<T> csqrt_fast(cplx<T> z) {
-  T rs, mag;
-  rsqrt_sqrt(z.re * z.re + z.im * z.im, rs, mag);
-  const T w = T(0.5) * (mag + (z.re >= T(0) ? z.re : -z.re));
-  T rt, t;
-  rsqrt_sqrt(w, rt, t);
-  const T o = T(0.5) * z.im * rt;
-  if (z.re >= T(0)) return {t, o};
-  return {o >= T(0) ? o : -o, z.im >= T(0) ? t : -t};
+  T mag, hm;
+  sqrt_hrsqrt(z.re * z.re + z.im * z.im, mag, hm);
+  const T w = T(0.5) * (mag + fabs(z.re));
+  T t, ht;
+  sqrt_hrsqrt(w, t, ht);
+  const T o = z.im * ht;   // Im z / (2 t)
+  const bool right = z.re >= T(0);
+  return {right ? t : fabs(o), right ? o : copysign(t, z.im)};
 }
 
 // Principal square root (Re >= 0), branch cut on the negative real axis.
@@ -113,48 +112,49 @@ constexpr double kLn2Hi = 0x1.62e42fefa39efp-1, kLn2Lo = 0x1.abc9e3b39803fp-56;
 constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
 constexpr double kPio2A = 0x1.921fb54442d18p+0, kPio2B = 0x1.1a62633145c07p-54,
                  kPio2C = -0x1.f1976b7ed8fbcp-110;
-// 1/n! for n = 0..8 (every n! here is exact in double: one rounding per entry)
-constexpr double kInvFact[9] = {1.0, 1.0, 1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0,
-                                1.0 / 720.0, 1.0 / 5040.0, 1.0 / 40320.0};
+// 1/n! for n = 0..6 (every n! here is exact in double: one rounding per entry)
+constexpr double kInvFact[7] = {1.0, 1.0, 1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0};
 }  // namespace detail
 
-// exp(z) for the propagation factors in FP64, Re z <= 0, with two small tables in LDS:
-// phase[j] = (cos, sin)(j pi/32) and e2[j] = 2^(j/64), j = 0..63.  With
-//   k = rint(64 x / ln 2), r = x - k ln2/64 (|r| <= ln2/128),
-//   j = rint(32 y / pi),   d = y - j pi/32   (|d| <= pi/64),
-//   exp(x + iy) = 2^floor(k/64) e2[k mod 64] e^r phase[j mod 64] (cos d + i sin d),
-// and Taylor polynomials of degree 5 (e^r), 7 (sin d) and 8 (cos d), whose remainders
-// are below 4e-17, 5e-18 and 3e-20.  Re z < -1000 gives 0; a NaN real part is clamped
-// too (the recursion still propagates it through u), a NaN imaginary part gives NaN.
+// exp(z) for the propagation factors in FP64, Re z <= 0, with two tables in LDS:
+// phase[j] = (cos, sin)(j pi/128) and e2[j] = 2^(j/256), j = 0..255.  With
+//   k = round(256 x / ln 2), r = x - k ln2/256 (|r| <= ln2/512),
+//   j = round(128 y / pi),   d = y - j pi/128  (|d| <= pi/256),
+//   exp(x + iy) = 2^floor(k/256) e2[k mod 256] e^r phase[j mod 256] (cos d + i sin d),
+// and Taylor polynomials of degree 4 (e^r), 5 (sin d) and 6 (cos d), whose remainders
+// are below 4e-17, 9e-18 and 2e-20.  k and j are rounded by adding 1.5 2^52, which
+// leaves them as integers in the low word.  Re z < -1000 gives 0; a NaN real part is
+// clamped too (the recursion still propagates it through u), a NaN imaginary part
+// gives NaN.
 __device__ __forceinline__ cplx<double> cexp_tab(cplx<double> z, const cplx<double> *phase,
                                                  const double *e2) {
   using namespace detail;
+  constexpr double kRound = 0x1.8p52;
   const double x = fmax(z.re, -1000.0);
-  const double kx = rint(x * (64.0 * kInvLn2));
-  double r = fma(kx, -(kLn2Hi / 64.0), x);
-  r = fma(kx, -(kLn2Lo / 64.0), r);
-  double p = fma(r, kInvFact[5], kInvFact[4]);
-  p = fma(p, r, kInvFact[3]);
+  const double kr = fma(x, 256.0 * kInvLn2, kRound);
+  const int ki = __double2loint(kr);
+  const double kx = kr - kRound;
+  double r = fma(kx, -(kLn2Hi / 256.0), x);
+  r = fma(kx, -(kLn2Lo / 256.0), r);
+  double p = fma(r, kInvFact[4], kInvFact[3]);
   p = fma(p, r, kInvFact[2]);
   p = fma(p, r, 1.0);
   p = fma(p, r, 1.0);
-  const int ki = (int)kx;
-  const double e = ldexp(p * e2[ki & 63], ki >> 6);   // ki >> 6 = floor(ki / 64)
+  const double e = ldexp(p * e2[ki & 255], ki >> 8);   // ki >> 8 = floor(ki / 256)
 
-  const double jy = rint(z.im * (16.0 * kTwoOverPi));
-  double d = fma(jy, -(kPio2A / 16.0), z.im);
-  d = fma(jy, -(kPio2B / 16.0), d);
-  d = fma(jy, -(kPio2C / 16.0), d);
+  const double jr = fma(z.im, 64.0 * kTwoOverPi, kRound);
+  const int ji = __double2loint(jr);
+  const double jy = jr - kRound;
+  double d = fma(jy, -(kPio2A / 64.0), z.im);
+  d = fma(jy, -(kPio2B / 64.0), d);
+  d = fma(jy, -(kPio2C / 64.0), d);
   const double x2 = -(d * d);
-  double S = fma(x2, kInvFact[7], kInvFact[5]);
-  S = fma(S, x2, kInvFact[3]);
-  const double sd = fma(d * x2, S, d);
-  double C = fma(x2, kInvFact[8], kInvFact[6]);
-  C = fma(C, x2, kInvFact[4]);
+  const double sd = fma(d * x2, fma(x2, kInvFact[5], kInvFact[3]), d);
+  double C = fma(x2, kInvFact[6], kInvFact[4]);
   C = fma(C, x2, kInvFact[2]);
   const double cd = fma(x2, C, 1.0);
-  const cplx<double> t = phase[(int)jy & 63];
-  return {e * (t.re * cd - t.im * sd), e * (t.im * cd + t.re * sd)};
+  const cplx<double> t = phase[ji & 255];
+  return {e * fma(t.re, cd, -(t.im * sd)), e * fma(t.im, cd, t.re * sd)};
 }
 
 // exp(z) for the propagation factors in FP32, Re z <= 0 (Re z < -110 gives 0):

@@ -37,14 +37,15 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
   __shared__ double s_lam[kMaxHankel];
   __shared__ double s_ck[kMaxHankel];
   __shared__ double s_omega[kMaxFreq];
-  __shared__ double s_K[kMaxGate * kMaxFreq];
   __shared__ double s_eps2[kMaxGate];
   __shared__ cplx<double> s_phase[kPhaseN];
   __shared__ double s_exp2[kExp2N];
   __shared__ LayerStack s_stack[kWavesPerBlock];
   __shared__ double s_imh[kWavesPerBlock][kMaxFreq];
-  __shared__ cplx<T> s_k2[kWavesPerBlock][8][kMaxLayers];
-  __shared__ T s_thk[kWavesPerBlock][kMaxLayers];
+  __shared__ cplx<T> s_k2[kWavesPerBlock][8][LMAX];
+  __shared__ cplx<T> s_dk2[kWavesPerBlock][8][LMAX];
+  __shared__ T s_h2[kWavesPerBlock][LMAX];
+  extern __shared__ double s_K[];   // [n_gate][n_freq], dynamic
 
   const int nf = s.n_freq, ng = s.n_gate, nhp = s.n_hankel_pad;
   for (int t = threadIdx.x; t < nhp; t += blockDim.x) {
@@ -73,7 +74,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
     c = p.c[i];
     log_tau = p.log10_tau[i] * 2.302585092994045684;
     sincospi(0.5 * c, &spc, &cpc);
-    if (lane < L - 1) s_thk[wave][lane] = to<T>(st->top[lane + 1] - st->top[lane]);
+    if (lane < L - 1) s_h2[wave][lane] = T(-2) * to<T>(st->top[lane + 1] - st->top[lane]);
   }
   const int gl = lane & 7, gw = lane >> 3;
   const int nhg = nhp >> 3;
@@ -90,10 +91,15 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
       const cplx<double> qcc = crcp(cplx<double>{1.0 + pw * cpc, pw * spc});
       const T wmu = to<T>(w * kMu0);
       const cplx<T> qt = {to<T>(qcc.re), to<T>(qcc.im)};
-      for (int l = gl; l < L; l += 8) {
+      auto k2_of = [&](int l) {
         const T sg = to<T>(st->sig[l]), mg = to<T>(st->m[l]);
         const cplx<T> sh = {sg * (T(1) - mg * qt.re), sg * (-(mg * qt.im))};
-        s_k2[wave][gw][l] = cplx<T>{-(wmu * sh.im), wmu * sh.re};
+        return cplx<T>{-(wmu * sh.im), wmu * sh.re};
+      };
+      for (int l = gl; l < L; l += 8) {
+        const cplx<T> kl = k2_of(l);
+        s_k2[wave][gw][l] = kl;
+        if (l + 1 < L) s_dk2[wave][gw][l] = kl - k2_of(l + 1);
       }
     }
     wave_lds_sync();
@@ -102,7 +108,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
 #pragma unroll 1
       for (int sidx = 0; sidx < nhg; ++sidx) {
         const int k = gl + 8 * sidx;
-        const T rim = reflection_im<T>(to<T>(s_lam[k]), s_k2[wave][gw], s_thk[wave], L, s_phase, s_exp2);
+        const T rim = reflection_im<T>(to<T>(s_lam[k]), s_k2[wave][gw], s_dk2[wave][gw], s_h2[wave], L,
+                                         s_phase, s_exp2);
         acc += s_ck[k] * static_cast<double>(rim);
       }
       // reduce over the 8 abscissa groups (lane bits 0..2); all 8 lanes of a group
@@ -152,7 +159,8 @@ template <int LMAX, typename T>
 static hipError_t launch_t(const DevSystem &s, const DevParticles &p, int kc, int km, double *resp,
                            const double *y_obs, double *ll, hipStream_t stream) {
   const int64_t blocks = (p.n + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL((forward_kernel<LMAX, T>), dim3((unsigned)blocks), dim3(kWave * kWavesPerBlock), 0,
+  const size_t dyn = sizeof(double) * s.n_freq * s.n_gate;
+  hipLaunchKernelGGL((forward_kernel<LMAX, T>), dim3((unsigned)blocks), dim3(kWave * kWavesPerBlock), dyn,
                      stream, s, p, kc, km, resp, y_obs, ll);
   return hipGetLastError();
 }

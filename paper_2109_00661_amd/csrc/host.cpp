@@ -248,10 +248,10 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
   std::vector<double> phase(2 * rjsmc::kPhaseN), exp2t(rjsmc::kExp2N);
   const long double pil = acosl(-1.0L);
   for (int j = 0; j < rjsmc::kPhaseN; ++j) {
-    phase[2 * j] = (double)cosl(pil * j / 32);
-    phase[2 * j + 1] = (double)sinl(pil * j / 32);
+    phase[2 * j] = (double)cosl(pil * j / 128);
+    phase[2 * j + 1] = (double)sinl(pil * j / 128);
   }
-  for (int j = 0; j < rjsmc::kExp2N; ++j) exp2t[j] = (double)exp2l(j / 64.0L);
+  for (int j = 0; j < rjsmc::kExp2N; ++j) exp2t[j] = (double)exp2l(j / 256.0L);
   c->K_host = new double[(size_t)ng * nf];
   rjsmc::build_time_kernel(s->freq_hz, nf, s->gate_open_s, s->gate_close_s, ng, c->K_host);
 

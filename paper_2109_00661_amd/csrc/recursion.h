@@ -29,6 +29,13 @@ __device__ __forceinline__ void rescale<float>(cplx<float> &N, cplx<float> &D) {
   D = {ldexpf(D.re, e), ldexpf(D.im, e)};
 }
 
+// a b + c d with one multiplication and three fused multiply-adds per component.
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul2add(cplx<T> a, cplx<T> b, cplx<T> c, cplx<T> d) {
+  return {fma(a.re, b.re, fma(-a.im, b.im, fma(c.re, d.re, -(c.im * d.im)))),
+          fma(a.re, b.im, fma(a.im, b.re, fma(c.re, d.im, c.im * d.re)))};
+}
+
 // Propagation factor exp(-2 h u): table-assisted in FP64, polynomial in FP32.
 __device__ __forceinline__ cplx<double> prop_exp(cplx<double> z, const cplx<double> *phase,
                                                  const double *e2) {
@@ -38,49 +45,49 @@ __device__ __forceinline__ cplx<float> prop_exp(cplx<float> z, const cplx<double
   return cexp(z);
 }
 
-// k2[l] (layers 0..L-1) and thk[l] (l < L-1) are read from LDS: the layer loop is a
-// runtime loop whose carried state is N, D, u_{l+1} and k2_{l+1}.  phase / e2 are the
+// Per-(frequency, layer) terms are read from LDS: k2[l] (layers 0..L-1), the interface
+// numerators dk2[l] = k2[l] - k2[l+1] (l < L-1) and h2[l] = -2 h_l (l < L-1).  The layer
+// loop is a runtime loop whose carried state is N, D and u_{l+1}.  phase / e2 are the
 // LDS copies of the exponential's tables (used in FP64).
 template <typename T>
-__device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const T *thk, int L,
+__device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const cplx<T> *dk2, const T *h2, int L,
                                            const cplx<double> *phase, const double *e2) {
   const T lam2 = lam * lam;
-  cplx<T> k2b = k2[L - 1];
-  cplx<T> ub = csqrt_fast(cplx<T>{lam2 + k2b.re, k2b.im});
+  const cplx<T> kb = k2[L - 1];
+  cplx<T> ub = csqrt_fast(cplx<T>{lam2 + kb.re, kb.im});
   cplx<T> N, D;
   if (L == 1) {
-    N = {-k2b.re, -k2b.im};
+    N = {-kb.re, -kb.im};
     D = csq(cplx<T>{lam + ub.re, ub.im});
   } else {
     {
       const cplx<T> kl = k2[L - 2];
       const cplx<T> u = csqrt_fast(cplx<T>{lam2 + kl.re, kl.im});
-      N = kl - k2b;
+      N = dk2[L - 2];
       D = csq(u + ub);
       ub = u;
-      k2b = kl;
     }
 #pragma unroll 1
     for (int l = L - 3; l >= 0; --l) {
       const cplx<T> kl = k2[l];
       const cplx<T> u = csqrt_fast(cplx<T>{lam2 + kl.re, kl.im});
-      const cplx<T> A = kl - k2b;
+      const cplx<T> A = dk2[l];
       const cplx<T> B = csq(u + ub);
-      const T h2 = T(-2) * thk[l + 1];
-      const cplx<T> NE = N * prop_exp(cplx<T>{h2 * ub.re, h2 * ub.im}, phase, e2);
-      const cplx<T> Nn = A * D + B * NE;
-      D = B * D + A * NE;
+      const T hh = h2[l + 1];
+      const cplx<T> NE = N * prop_exp(cplx<T>{hh * ub.re, hh * ub.im}, phase, e2);
+      const cplx<T> Nn = cmul2add(A, D, B, NE);
+      D = cmul2add(B, D, A, NE);
       N = Nn;
       rescale(N, D);
       ub = u;
-      k2b = kl;
     }
-    const cplx<T> A0 = {-k2b.re, -k2b.im};
+    const cplx<T> k0 = k2[0];
+    const cplx<T> A0 = {-k0.re, -k0.im};
     const cplx<T> B0 = csq(cplx<T>{lam + ub.re, ub.im});
-    const T h2 = T(-2) * thk[0];
-    const cplx<T> NE = N * prop_exp(cplx<T>{h2 * ub.re, h2 * ub.im}, phase, e2);
-    const cplx<T> Nn = A0 * D + B0 * NE;
-    D = B0 * D + A0 * NE;
+    const T hh = h2[0];
+    const cplx<T> NE = N * prop_exp(cplx<T>{hh * ub.re, hh * ub.im}, phase, e2);
+    const cplx<T> Nn = cmul2add(A0, D, B0, NE);
+    D = cmul2add(B0, D, A0, NE);
     N = Nn;
   }
   return (N.im * D.re - N.re * D.im) * fast_rcp(D.re * D.re + D.im * D.im);

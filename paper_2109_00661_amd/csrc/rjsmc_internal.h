@@ -38,8 +38,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Sizes of the tables of the propagation-factor exponential (see cexp_tab).
-constexpr int kPhaseN = 64;
-constexpr int kExp2N = 64;
+constexpr int kPhaseN = 256;
+constexpr int kExp2N = 256;
 
 // Device flag bits raised by kernels, reported by rjsmc_check.
 constexpr int kFlagCapacity = 1;
@@ -54,8 +54,8 @@ struct DevSystem {
   double *ck;         // [n_hankel_pad] (I/2) w_k lam_k exp(-2 lam_k h)  (padding: 0)
   double *K;          // [n_gate][n_freq] frequency-to-time matrix
   double *eps_an2;    // [n_gate] eps_an^2
-  double *phase;      // [kPhaseN][2] (cos, sin)(j pi/32), j = 0..63
-  double *exp2t;      // [kExp2N] 2^(j/64), j = 0..63
+  double *phase;      // [kPhaseN][2] (cos, sin)(j pi/128), j = 0..255
+  double *exp2t;      // [kExp2N] 2^(j/256), j = 0..255
   int *flags;         // device flag word
 };
 
