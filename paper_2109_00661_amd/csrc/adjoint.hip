@@ -4,9 +4,11 @@
 // forward kernel.  Phase A evaluates the forward model to obtain y, ll and
 // w_j = d ll / d Im H(w_j) = sum_g K_gj d ll / d y_g.  Phase B revisits every pair: it runs
 // the reflection recursion bottom-up in the classic form, keeping the generalized
-// reflection coefficients r_l of each layer in registers, then sweeps top-down through
-// the air interface and every layer, propagating the adjoint of c_k w_j Im r and
-// accumulating, per frequency, the complex adjoints of the layer wavenumbers
+// reflection coefficients r_l of each layer in a per-lane array (runtime layer loops:
+// the arrays live in the wave's private memory, which keeps the register count low
+// enough for two waves per SIMD), then sweeps top-down through the air interface and
+// every layer, propagating the adjoint of c_k w_j Im r and accumulating, per lane and
+// frequency, the complex adjoints of the layer wavenumbers
 // k2_l = i w mu0 sigma_hat_l and the adjoints of the thicknesses.  The u_l and E_l of the
 // recursion are recomputed in the sweep instead of stored.  Per frequency the adjoints
 // are mapped through the Cole-Cole terms to (log10 sigma_inf, m) of each merged layer and
@@ -37,7 +39,7 @@ __device__ __forceinline__ cplx<double> crcp_fast(cplx<double> b) {
 __device__ __forceinline__ cplx<double> cdiv_fast(cplx<double> a, cplx<double> b) { return a * crcp_fast(b); }
 
 // Adds the adjoints of one (lam, w) pair with seed wt (the weight of Im r) to
-// G[l] (d(wt r)/d k2_l) and H[l] (Im d(wt r)/d h_l).
+// G[l] (d(wt r)/d k2_l) and H[l] (Im d(wt r)/d h_l); runtime layer loops.
 template <int LMAX>
 __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2, const double *thk, int L,
                                              double wt, cplx<double> (&G)[LMAX], double (&H)[LMAX],
@@ -47,9 +49,9 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
   // ---- bottom-up recursion, classic form
   {
     cplx<double> ub = csqrt_fast(cplx<double>{lam2 + k2[L - 1].re, k2[L - 1].im});
-#pragma unroll
-    for (int l = LMAX - 2; l >= 0; --l) {
-      if (l <= L - 2) {
+#pragma unroll 1
+    for (int l = L - 2; l >= 0; --l) {
+      {
         const cplx<double> u = csqrt_fast(cplx<double>{lam2 + k2[l].re, k2[l].im});
         const cplx<double> R = cdiv_fast(k2[l] - k2[l + 1], csq(u + ub));
         if (l == L - 2) {
@@ -98,9 +100,9 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
     G[0] = G[0] + kbar;
     return;
   }
-#pragma unroll
-  for (int l = 0; l <= LMAX - 2; ++l) {
-    if (l <= L - 2) {
+#pragma unroll 1
+  for (int l = 0; l <= L - 2; ++l) {
+    {
       const cplx<double> un = csqrt_fast(cplx<double>{lam2 + k2[l + 1].re, k2[l + 1].im});   // u_{l+1}
       const cplx<double> s = ul + un;
       const cplx<double> B = csq(s);
@@ -148,7 +150,7 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
 // (LMAX)][log10 tau][c].
 template <int LMAX>
 struct AdjShared {
-  double lam[kMaxHankel], ck[kMaxHankel], omega[kMaxFreq], K[kMaxGate * kMaxFreq], eps2[kMaxGate];
+  double lam[kMaxHankel], ck[kMaxHankel], omega[kMaxFreq], eps2[kMaxGate];
   cplx<double> phase[kPhaseN];
   double exp2t[kExp2N];
   LayerStack stack[kWavesA];
@@ -168,13 +170,14 @@ template <int LMAX>
 __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem s, DevParticles p, int kc, int km,
                                                                        const double *y_obs, double *ll, DevGrad g) {
   __shared__ AdjShared<LMAX> sm;
+  extern __shared__ double sK[];   // [n_gate][n_freq], dynamic
   const int nf = s.n_freq, ng = s.n_gate, nhp = s.n_hankel_pad;
   for (int t = threadIdx.x; t < nhp; t += blockDim.x) {
     sm.lam[t] = s.lam[t];
     sm.ck[t] = s.ck[t];
   }
   for (int t = threadIdx.x; t < nf; t += blockDim.x) sm.omega[t] = s.omega[t];
-  for (int t = threadIdx.x; t < nf * ng; t += blockDim.x) sm.K[t] = s.K[t];
+  for (int t = threadIdx.x; t < nf * ng; t += blockDim.x) sK[t] = s.K[t];
   for (int t = threadIdx.x; t < ng; t += blockDim.x) sm.eps2[t] = s.eps_an2[t];
   for (int t = threadIdx.x; t < kPhaseN; t += blockDim.x)
     sm.phase[t] = cplx<double>{s.phase[2 * t], s.phase[2 * t + 1]};
@@ -244,7 +247,7 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
     double term = 0.0, ybar = 0.0;
     if (lane < ng) {
       double y = 0.0;
-      for (int j = 0; j < nf; ++j) y += sm.K[lane * nf + j] * sm.imh[wave][j];
+      for (int j = 0; j < nf; ++j) y += sK[lane * nf + j] * sm.imh[wave][j];
       const int64_t snd = p.n_per_sounding > 0 ? i / p.n_per_sounding : 0;
       const double d = y_obs[snd * ng + lane];
       const double e = s.eps_mn * y;
@@ -266,7 +269,7 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
   wave_lds_sync();
   if (L > 0 && lane < nf) {
     double acc = 0.0;
-    for (int gg = 0; gg < ng; ++gg) acc += sm.K[gg * nf + lane] * sm.ybar[wave][gg];
+    for (int gg = 0; gg < ng; ++gg) acc += sK[gg * nf + lane] * sm.ybar[wave][gg];
     sm.wbar[wave][lane] = acc;
   }
   wave_lds_sync();
@@ -393,8 +396,9 @@ template <int LMAX>
 static hipError_t launch_g(const DevSystem &s, const DevParticles &p, int kc, int km, const double *y_obs, double *ll,
                            const DevGrad &g, hipStream_t stream) {
   const int64_t blocks = (p.n + kWavesA - 1) / kWavesA;
-  hipLaunchKernelGGL((loglik_grad_kernel<LMAX>), dim3((unsigned)blocks), dim3(kWave * kWavesA), 0, stream, s, p, kc,
-                     km, y_obs, ll, g);
+  const size_t dyn = sizeof(double) * s.n_freq * s.n_gate;
+  hipLaunchKernelGGL((loglik_grad_kernel<LMAX>), dim3((unsigned)blocks), dim3(kWave * kWavesA), dyn, stream, s, p,
+                     kc, km, y_obs, ll, g);
   return hipGetLastError();
 }
 
