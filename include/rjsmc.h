@@ -260,6 +260,35 @@ rjsmc_status rjsmc_mutate(rjsmc_ctx *ctx, const rjsmc_mutate_args *args, rjsmc_p
                           rjsmc_particles *grad_cur, rjsmc_particles *grad_prop, int64_t *stats,
                           rjsmc_stream stream);
 
+/* ------------------------------------------------------------------------------------
+ * Tile shape of the forward kernel.  Not part of the method: it decides how the
+ * particles of a launch are packed into workgroups, never what is computed (results are
+ * identical for every shape).
+ * ---------------------------------------------------------------------------------- */
+typedef struct {
+  int32_t waves_per_block;  /* particles (one wavefront each) per workgroup: 2, 4 or 8 */
+  int32_t layer_sort;       /* 1: evaluate particles in descending order of layer capacity
+                               (kappa + lambda + 1), computed on the device before each
+                               launch; used only when n <= max_particles of the context */
+} rjsmc_tuning;
+
+#define RJSMC_TUNING_CANDIDATES 6   /* waves_per_block {2,4,8} x layer_sort {0,1} */
+
+/* Sets / reads the tile shape used by rjsmc_forward, rjsmc_loglik and the proposal
+ * likelihoods of rjsmc_mutate (default {4, 0}).  RJSMC_E_INVALID for other values. */
+rjsmc_status rjsmc_set_tuning(rjsmc_ctx *ctx, const rjsmc_tuning *tuning);
+rjsmc_status rjsmc_get_tuning(const rjsmc_ctx *ctx, rjsmc_tuning *tuning);
+
+/* Autotuner: times rjsmc_loglik on population p (device, as for rjsmc_loglik; ll is
+ * overwritten) for every candidate tile shape, `reps` launches each after one warm-up,
+ * with HIP events on `stream`; keeps the fastest in the context and writes it to *best
+ * (may be NULL).  times_ms (host float[RJSMC_TUNING_CANDIDATES], may be NULL) receives
+ * the mean launch time of candidate k = 2 * index(waves_per_block) + layer_sort, or -1
+ * for a candidate that needs more workspace than max_particles.  Synchronizes `stream`.
+ * RJSMC_E_INVALID for bad arguments or reps outside 1..1000. */
+rjsmc_status rjsmc_autotune(rjsmc_ctx *ctx, const rjsmc_particles *p, const double *y_obs, double *ll,
+                            int32_t reps, rjsmc_tuning *best, float *times_ms, rjsmc_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,13 @@ class MutateArgs(ctypes.Structure):
                 ("factors", ctypes.c_void_p), ("prior", Prior)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("waves_per_block", ctypes.c_int32), ("layer_sort", ctypes.c_int32)]
+
+
+TUNING_CANDIDATES = 6
+
+
 def make_prior(pr):
     return Prior(pr["phi_lo"], pr["phi_hi"], pr["m_lo"], pr["m_hi"], pr["ltau_lo"], pr["ltau_hi"],
                  pr["c_lo"], pr["c_hi"])
@@ -100,6 +107,11 @@ _SIGS = {
                                     ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Particles),
                                     ctypes.POINTER(Particles), ctypes.c_void_p, ctypes.c_void_p]),
+    "rjsmc_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
+    "rjsmc_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
+    "rjsmc_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_float),
+                                      ctypes.c_void_p]),
 }
 
 
@@ -218,6 +230,28 @@ class Context:
         K = np.zeros((self.n_gate, self.n_freq))
         _check(lib().rjsmc_time_kernel(self._ptr, _as_dp(K)))
         return K
+
+    # -- tile shape --------------------------------------------------------------------
+    def set_tuning(self, waves_per_block, layer_sort):
+        t = Tuning(int(waves_per_block), int(layer_sort))
+        _check(lib().rjsmc_set_tuning(self._ptr, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(lib().rjsmc_get_tuning(self._ptr, ctypes.byref(t)))
+        return {"waves_per_block": t.waves_per_block, "layer_sort": t.layer_sort}
+
+    def autotune(self, p, y_obs, reps=3, stream=None):
+        """Times every tile shape on p, keeps the fastest; returns (best, times_ms)."""
+        import torch
+        n = int(p["kappa"].shape[0])
+        ll = torch.empty(n, dtype=torch.float64, device=p["kappa"].device)
+        best = Tuning()
+        times = (ctypes.c_float * TUNING_CANDIDATES)()
+        ps = particles_struct(p)
+        _check(lib().rjsmc_autotune(self._ptr, ctypes.byref(ps), _ptr(y_obs), _ptr(ll), int(reps), ctypes.byref(best),
+                                    times, _stream_handle(stream)))
+        return ({"waves_per_block": best.waves_per_block, "layer_sort": best.layer_sort}, list(times))
 
     # -- hot calls ---------------------------------------------------------------------
     def forward(self, p, out=None, stream=None):

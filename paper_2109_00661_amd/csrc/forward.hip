@@ -20,7 +20,6 @@
 
 namespace rjsmc {
 
-constexpr int kWavesPerBlock = 4;
 constexpr double kMu0 = 1.25663706143591729539e-06;   // 4 pi 1e-7
 constexpr double kTwoPi = 6.28318530717958647692;
 
@@ -30,10 +29,15 @@ __device__ __forceinline__ T to(double x) {
 }
 
 // resp != nullptr: write gate responses.  ll != nullptr: write the log-likelihood.
-template <int LMAX, typename T>
-__global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevSystem s, DevParticles p, int kc,
-                                                                          int km, double *resp,
-                                                                          const double *y_obs, double *ll) {
+// WPB particles (one wave each) per workgroup.  perm != nullptr: slot j of the grid
+// evaluates particle perm[j] (workgroups in launch order, dealt round-robin to the XCDs);
+// otherwise slot j is particle j (workgroups renumbered XCD-contiguous).
+template <typename T, int WPB>
+__global__ __launch_bounds__(kWave * WPB, 16 / WPB) void forward_kernel(DevSystem s, DevParticles p, int kc, int km,
+                                                                       double *resp, const double *y_obs,
+                                                                       double *ll, const int32_t *perm) {
+  constexpr int LMAX = kMaxLayers;
+  constexpr int kWavesPerBlock = WPB;
   __shared__ double s_lam[kMaxHankel];
   __shared__ double s_ck[kMaxHankel];
   __shared__ double s_omega[kMaxFreq];
@@ -61,7 +65,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
 
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wave;
+  const int64_t slot = (int64_t)(perm ? blockIdx.x : xcd_block(blockIdx.x, gridDim.x)) * kWavesPerBlock + wave;
+  const int64_t i = perm ? (slot < p.n ? (int64_t)perm[slot] : p.n) : slot;
   const bool valid = i < p.n;
   const bool skip = valid && p.mask && p.mask[i] != p.mask_value;
   LayerStack *st = &s_stack[wave];
@@ -155,36 +160,100 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock, 2) void forward_kernel(DevS
   }
 }
 
-template <int LMAX, typename T>
+template <typename T, int WPB>
 static hipError_t launch_t(const DevSystem &s, const DevParticles &p, int kc, int km, double *resp,
-                           const double *y_obs, double *ll, hipStream_t stream) {
-  const int64_t blocks = (p.n + kWavesPerBlock - 1) / kWavesPerBlock;
+                           const double *y_obs, double *ll, const int32_t *perm, hipStream_t stream) {
+  const int64_t blocks = (p.n + WPB - 1) / WPB;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   const size_t dyn = sizeof(double) * s.n_freq * s.n_gate;
-  hipLaunchKernelGGL((forward_kernel<LMAX, T>), dim3((unsigned)blocks), dim3(kWave * kWavesPerBlock), dyn,
-                     stream, s, p, kc, km, resp, y_obs, ll);
+  hipLaunchKernelGGL((forward_kernel<T, WPB>), dim3((unsigned)blocks), dim3(kWave * WPB), dyn, stream, s, p, kc, km,
+                     resp, y_obs, ll, perm);
   return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t launch_prec(int lcap, const DevSystem &s, const DevParticles &p, int kc, int km,
+static hipError_t launch_prec(const ForwardTiles &t, const DevSystem &s, const DevParticles &p, int kc, int km,
                               double *resp, const double *y_obs, double *ll, hipStream_t stream) {
-  if (lcap <= 4) return launch_t<4, T>(s, p, kc, km, resp, y_obs, ll, stream);
-  if (lcap <= 8) return launch_t<8, T>(s, p, kc, km, resp, y_obs, ll, stream);
-  if (lcap <= 12) return launch_t<12, T>(s, p, kc, km, resp, y_obs, ll, stream);
-  return launch_t<16, T>(s, p, kc, km, resp, y_obs, ll, stream);
-}
-
-// Smallest compiled layer cap that holds every particle the context admits.
-int layer_cap(const DevParticles &p, int kc, int km) {
-  return p.layout == RJSMC_LAYOUT_DECOUPLED ? kc + km + 1 : kc + 1;
+  if (t.waves_per_block == 2) return launch_t<T, 2>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
+  if (t.waves_per_block == 8) return launch_t<T, 8>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
+  return launch_t<T, 4>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
 }
 
 hipError_t launch_forward(const DevSystem &s, const DevParticles &p, int kc, int km, int precision,
-                          double *resp, const double *y_obs, double *ll, hipStream_t stream) {
-  if ((p.n + kWavesPerBlock - 1) / kWavesPerBlock > 0x7fffffff) return hipErrorInvalidValue;
-  const int lcap = layer_cap(p, kc, km);
-  if (precision == RJSMC_F32) return launch_prec<float>(lcap, s, p, kc, km, resp, y_obs, ll, stream);
-  return launch_prec<double>(lcap, s, p, kc, km, resp, y_obs, ll, stream);
+                          double *resp, const double *y_obs, double *ll, hipStream_t stream,
+                          const ForwardTiles &tiles) {
+  if (precision == RJSMC_F32) return launch_prec<float>(tiles, s, p, kc, km, resp, y_obs, ll, stream);
+  return launch_prec<double>(tiles, s, p, kc, km, resp, y_obs, ll, stream);
+}
+
+// ---- ordering of particles by layer capacity (counting sort, descending capacity)
+// cnt[0..kCapBins) counts, cnt[kCapBins..2 kCapBins) cursors.  Bin b holds capacity
+// kMaxLayers - b, so bin 0 (the deepest particles) is evaluated first.
+namespace {
+constexpr int kCapBins = kMaxLayers;
+
+__device__ __forceinline__ int cap_bin(const DevParticles &p, int64_t i) {
+  const int lam = p.layout == RJSMC_LAYOUT_DECOUPLED ? p.lambda[i] : 0;
+  int cap = p.kappa[i] + lam + 1;
+  cap = cap < 1 ? 1 : (cap > kMaxLayers ? kMaxLayers : cap);   // invalid counts: anywhere
+  return kMaxLayers - cap;
+}
+
+__global__ void sort_zero_kernel(int *cnt) {
+  if (threadIdx.x < 2 * kCapBins) cnt[threadIdx.x] = 0;
+}
+
+// Per wave: one ballot and one atomic per bin present.
+__global__ __launch_bounds__(256) void sort_count_kernel(DevParticles p, int *cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int bin = i < p.n ? cap_bin(p, i) : -1;
+  uint64_t todo = __ballot(bin >= 0);
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const int b = __shfl(bin, leader);
+    const uint64_t same = __ballot(bin == b);
+    if (lane == leader) atomicAdd(&cnt[b], __popcll(same));
+    todo &= ~same;
+  }
+}
+
+__global__ void sort_scan_kernel(int *cnt) {
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int b = 0; b < kCapBins; ++b) {
+      cnt[kCapBins + b] = acc;
+      acc += cnt[b];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void sort_scatter_kernel(DevParticles p, int *cnt, int32_t *perm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int bin = i < p.n ? cap_bin(p, i) : -1;
+  uint64_t todo = __ballot(bin >= 0);
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const int b = __shfl(bin, leader);
+    const uint64_t same = __ballot(bin == b);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&cnt[kCapBins + b], __popcll(same));
+    base = __shfl(base, leader);
+    if (bin == b) perm[base + __popcll(same & ((1ull << lane) - 1))] = (int32_t)i;
+    todo &= ~same;
+  }
+}
+}  // namespace
+
+hipError_t launch_layer_sort(const DevParticles &p, int *cnt, int32_t *perm, hipStream_t stream) {
+  const int64_t blocks = (p.n + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sort_zero_kernel, dim3(1), dim3(64), 0, stream, cnt);
+  hipLaunchKernelGGL(sort_count_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, cnt);
+  hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(64), 0, stream, cnt);
+  hipLaunchKernelGGL(sort_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, cnt, perm);
+  return hipGetLastError();
 }
 
 }  // namespace rjsmc

@@ -280,14 +280,22 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
   if (e == hipSuccess) e = hipMemset(d.flags, 0, sizeof(int));
   c->work_mask = nullptr;
   c->work_type = nullptr;
+  c->work_perm = nullptr;
+  c->work_cnt = nullptr;
+  c->tuning.waves_per_block = 4;
+  c->tuning.layer_sort = 0;
   c->work_n = s->max_particles > 0 ? s->max_particles : 0;
   if (e == hipSuccess && c->work_n > 0) {
     e = hipMalloc((void **)&c->work_mask, sizeof(int32_t) * c->work_n);
     if (e == hipSuccess) e = hipMalloc((void **)&c->work_type, sizeof(int32_t) * c->work_n);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->work_perm, sizeof(int32_t) * c->work_n);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->work_cnt, sizeof(int) * 2 * rjsmc::kMaxLayers);
   }
   if (e != hipSuccess) {
     if (c->work_mask) (void)hipFree(c->work_mask);
     if (c->work_type) (void)hipFree(c->work_type);
+    if (c->work_perm) (void)hipFree(c->work_perm);
+    if (c->work_cnt) (void)hipFree(c->work_cnt);
     free_dev(d);
     delete[] c->K_host;
     delete c;
@@ -302,6 +310,8 @@ extern "C" void rjsmc_destroy(rjsmc_ctx *c) {
   (void)hipSetDevice(c->device);
   if (c->work_mask) (void)hipFree(c->work_mask);
   if (c->work_type) (void)hipFree(c->work_type);
+  if (c->work_perm) (void)hipFree(c->work_perm);
+  if (c->work_cnt) (void)hipFree(c->work_cnt);
   free_dev(c->dev);
   delete[] c->K_host;
   delete c;
@@ -376,6 +386,30 @@ static rjsmc_status check_particles(const rjsmc_ctx *c, const rjsmc_particles *p
   return RJSMC_OK;
 }
 
+// Tile shape of a forward launch over dp from the context's tuning; a layer-capacity
+// order is computed first (on the same stream) when the tuning asks for one and the
+// workspace holds dp.n particles.
+static hipError_t forward_tiles(const rjsmc_ctx *c, const rjsmc::DevParticles &dp, const rjsmc_tuning &t,
+                                hipStream_t stream, rjsmc::ForwardTiles *tiles) {
+  tiles->waves_per_block = t.waves_per_block;
+  tiles->perm = nullptr;
+  if (t.layer_sort && c->work_perm && dp.n <= c->work_n && dp.n > 0) {
+    const hipError_t e = rjsmc::launch_layer_sort(dp, c->work_cnt, c->work_perm, stream);
+    if (e != hipSuccess) return e;
+    tiles->perm = c->work_perm;
+  }
+  return hipSuccess;
+}
+
+static hipError_t run_forward(const rjsmc_ctx *c, const rjsmc::DevParticles &dp, const rjsmc_tuning &t, double *resp,
+                              const double *y_obs, double *ll, hipStream_t stream) {
+  rjsmc::ForwardTiles tiles;
+  hipError_t e = forward_tiles(c, dp, t, stream, &tiles);
+  if (e == hipSuccess)
+    e = rjsmc::launch_forward(c->dev, dp, c->kmax_cond, c->kmax_charg, c->precision, resp, y_obs, ll, stream, tiles);
+  return e;
+}
+
 extern "C" rjsmc_status rjsmc_forward(rjsmc_ctx *c, const rjsmc_particles *p, double *resp,
                                       rjsmc_stream stream) {
   if (!c) return fail(RJSMC_E_INVALID, "rjsmc_forward: NULL context");
@@ -385,8 +419,7 @@ extern "C" rjsmc_status rjsmc_forward(rjsmc_ctx *c, const rjsmc_particles *p, do
   if (!resp) return fail(RJSMC_E_INVALID, "rjsmc_forward: NULL resp");
   hipError_t e = hipSetDevice(c->device);
   if (e == hipSuccess)
-    e = rjsmc::launch_forward(c->dev, dp, c->kmax_cond, c->kmax_charg, c->precision, resp, nullptr,
-                              nullptr, (hipStream_t)stream);
+    e = run_forward(c, dp, c->tuning, resp, nullptr, nullptr, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "rjsmc_forward: launch");
   return RJSMC_OK;
 }
@@ -400,8 +433,7 @@ extern "C" rjsmc_status rjsmc_loglik(rjsmc_ctx *c, const rjsmc_particles *p, con
   if (!y_obs || !ll) return fail(RJSMC_E_INVALID, "rjsmc_loglik: NULL y_obs or ll");
   hipError_t e = hipSetDevice(c->device);
   if (e == hipSuccess)
-    e = rjsmc::launch_forward(c->dev, dp, c->kmax_cond, c->kmax_charg, c->precision, nullptr, y_obs,
-                              ll, (hipStream_t)stream);
+    e = run_forward(c, dp, c->tuning, nullptr, y_obs, ll, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "rjsmc_loglik: launch");
   return RJSMC_OK;
 }
@@ -608,8 +640,7 @@ extern "C" rjsmc_status rjsmc_mutate(rjsmc_ctx *c, const rjsmc_mutate_args *a, r
       e = rjsmc::launch_propose(sh, *a, r, ds, writable(dq), c->work_mask, c->work_type, gamma, mala ? &gcd : nullptr,
                                 s);
     if (e == hipSuccess)
-      e = rjsmc::launch_forward(c->dev, prop1, c->kmax_cond, c->kmax_charg, c->precision, nullptr, y_obs, ll_scratch,
-                                s);
+      e = run_forward(c, prop1, c->tuning, nullptr, y_obs, ll_scratch, s);
     if (e == hipSuccess && mala)
       e = rjsmc::launch_loglik_grad(c->dev, prop2, c->kmax_cond, c->kmax_charg, y_obs, ll_scratch, gpw, s);
     if (e == hipSuccess)
@@ -617,5 +648,71 @@ extern "C" rjsmc_status rjsmc_mutate(rjsmc_ctx *c, const rjsmc_mutate_args *a, r
                                mala ? &gcd : nullptr, mala ? &gpd : nullptr, stats, s);
   }
   if (e != hipSuccess) return hip_fail(e, "rjsmc_mutate: launch");
+  return RJSMC_OK;
+}
+
+// ---------------------------------------------------------------------------- tuning
+static bool valid_tuning(const rjsmc_tuning &t) {
+  return (t.waves_per_block == 2 || t.waves_per_block == 4 || t.waves_per_block == 8) &&
+         (t.layer_sort == 0 || t.layer_sort == 1);
+}
+
+extern "C" rjsmc_status rjsmc_set_tuning(rjsmc_ctx *c, const rjsmc_tuning *t) {
+  if (!c || !t) return fail(RJSMC_E_INVALID, "rjsmc_set_tuning: NULL argument");
+  if (!valid_tuning(*t))
+    return fail(RJSMC_E_INVALID, "rjsmc_set_tuning: waves_per_block must be 2, 4 or 8 and layer_sort 0 or 1");
+  c->tuning = *t;
+  return RJSMC_OK;
+}
+
+extern "C" rjsmc_status rjsmc_get_tuning(const rjsmc_ctx *c, rjsmc_tuning *t) {
+  if (!c || !t) return fail(RJSMC_E_INVALID, "rjsmc_get_tuning: NULL argument");
+  *t = c->tuning;
+  return RJSMC_OK;
+}
+
+extern "C" rjsmc_status rjsmc_autotune(rjsmc_ctx *c, const rjsmc_particles *p, const double *y_obs, double *ll,
+                                       int32_t reps, rjsmc_tuning *best, float *times_ms, rjsmc_stream stream) {
+  const char *who = "rjsmc_autotune";
+  if (!c) return fail(RJSMC_E_INVALID, "%s: NULL context", who);
+  rjsmc::DevParticles dp;
+  rjsmc_status st = check_particles(c, p, who, &dp);
+  if (st != RJSMC_OK) return st;
+  if (!y_obs || !ll) return fail(RJSMC_E_INVALID, "%s: NULL y_obs or ll", who);
+  if (reps < 1 || reps > 1000) return fail(RJSMC_E_INVALID, "%s: reps=%d outside 1..1000", who, reps);
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "rjsmc_autotune: hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  e = hipEventCreate(&ev0);
+  if (e == hipSuccess) e = hipEventCreate(&ev1);
+  const int wpb[3] = {2, 4, 8};
+  rjsmc_tuning bt = c->tuning;
+  float bms = -1.0f;
+  for (int k = 0; k < RJSMC_TUNING_CANDIDATES && e == hipSuccess; ++k) {
+    const rjsmc_tuning t = {wpb[k / 2], k % 2};
+    float ms = -1.0f;
+    if (!t.layer_sort || (c->work_perm && dp.n <= c->work_n)) {
+      e = run_forward(c, dp, t, nullptr, y_obs, ll, s);   // warm-up
+      if (e == hipSuccess) e = hipEventRecord(ev0, s);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = run_forward(c, dp, t, nullptr, y_obs, ll, s);
+      if (e == hipSuccess) e = hipEventRecord(ev1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(ev1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+      if (e == hipSuccess) {
+        ms /= (float)reps;
+        if (bms < 0 || ms < bms) {
+          bms = ms;
+          bt = t;
+        }
+      }
+    }
+    if (times_ms) times_ms[k] = ms;
+  }
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (e != hipSuccess) return hip_fail(e, "rjsmc_autotune");
+  c->tuning = bt;
+  if (best) *best = bt;
   return RJSMC_OK;
 }

@@ -90,10 +90,20 @@ struct DevGrad {
   double *phi_b, *phi, *z_cond, *m, *z_charg, *log10_tau, *c;
 };
 
+// Tile shape of one forward launch: particles per workgroup and an optional evaluation
+// order (a permutation of the particle indices).
+struct ForwardTiles {
+  int waves_per_block = 4;
+  const int32_t *perm = nullptr;
+};
+
 // Kernel launchers (forward.hip / adjoint.hip).  Return the launch's hipError_t.
 hipError_t launch_forward(const DevSystem &s, const DevParticles &p, int kmax_cond, int kmax_charg,
                           int precision, double *resp, const double *y_obs, double *ll,
-                          hipStream_t stream);
+                          hipStream_t stream, const ForwardTiles &tiles);
+// perm[0..n) = particle indices in descending order of layer capacity (kappa + lambda + 1);
+// cnt: 2 kMaxLayers ints of device scratch.
+hipError_t launch_layer_sort(const DevParticles &p, int *cnt, int32_t *perm, hipStream_t stream);
 hipError_t launch_loglik_grad(const DevSystem &s, const DevParticles &p, int kmax_cond,
                               int kmax_charg, const double *y_obs, double *ll, const DevGrad &g,
                               hipStream_t stream);
@@ -131,5 +141,8 @@ struct rjsmc_ctx {
   double *K_host;   // [n_gate][n_freq]
   int32_t *work_mask;   // [work_n] mutate scratch: proposal validity
   int32_t *work_type;   // [work_n] mutate scratch: move type
+  int32_t *work_perm;   // [work_n] evaluation order by layer capacity
+  int *work_cnt;        // [2 kMaxLayers] counting-sort scratch
   int64_t work_n;
+  rjsmc_tuning tuning;  // forward tile shape
 };

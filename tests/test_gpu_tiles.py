@@ -1,0 +1,106 @@
+"""Tile shapes of the forward kernel (workgroup size, layer-capacity evaluation order)
+and the autotuner.  A tile shape only changes how particles are packed into
+workgroups, so every shape must give bit-identical responses and log-likelihoods; the
+default shape is itself checked against the oracle in test_gpu_forward."""
+import numpy as np
+import pytest
+
+from paper_2109_00661_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SHAPES = [(w, s) for w in (2, 4, 8) for s in (0, 1)]
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2109_00661_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def uneven():
+    # conductivity layers 1-8 and chargeability interfaces 0-4, mixed; n not a multiple
+    # of any workgroup size
+    return W.decoupled_population(1003, 7, 4, seed=21, min_sep=1.0)
+
+
+def _data(B, truth_data):
+    return torch.as_tensor(truth_data, device="cuda")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_every_shape_bit_identical(B, uneven, truth_data, prec):
+    ctx = B.Context(W.system(kmax_cond=7, kmax_charg=4), precision=prec, max_particles=2048)
+    dp = B.particles_to_device(uneven)
+    d = _data(B, truth_data)
+    assert ctx.get_tuning() == {"waves_per_block": 4, "layer_sort": 0}
+    ref_y = ctx.forward(dp).cpu().numpy()
+    ref_ll = ctx.loglik(dp, d).cpu().numpy()
+    ctx.check()
+    assert np.all(np.isfinite(ref_ll))
+    for w, s in SHAPES:
+        ctx.set_tuning(w, s)
+        y = ctx.forward(dp).cpu().numpy()
+        ll = ctx.loglik(dp, d).cpu().numpy()
+        ctx.check()
+        assert np.array_equal(y, ref_y), (w, s)
+        assert np.array_equal(ll, ref_ll), (w, s)
+
+
+def test_sort_skipped_beyond_workspace(B, uneven, truth_data):
+    """layer_sort needs max_particles >= n; beyond it the index order is used."""
+    ctx = B.Context(W.system(kmax_cond=7, kmax_charg=4), precision="f64", max_particles=100)
+    dp = B.particles_to_device(uneven)
+    d = _data(B, truth_data)
+    ref = ctx.loglik(dp, d).cpu().numpy()
+    ctx.set_tuning(8, 1)
+    assert np.array_equal(ctx.loglik(dp, d).cpu().numpy(), ref)
+    ctx.check()
+
+
+def test_masked_mutation_under_sorted_shape(B, truth_data):
+    """The proposal likelihoods of rjsmc_mutate use the tuned shape: a sorted, 8-wave
+    shape gives the same chain as the default shape."""
+    from paper_2109_00661_amd.rjsmc import RJSMCRun
+    runs = []
+    for shape in ((4, 0), (8, 1)):
+        ctx = B.Context(W.system(), precision="f64", max_particles=512)
+        ctx.set_tuning(*shape)
+        run = RJSMCRun(ctx, 2, 256, np.tile(truth_data, (2, 1)), seed=5)
+        run.initialise()
+        for _ in range(3):
+            run.advance()
+        ctx.check()
+        runs.append((run.ll.cpu().numpy(), run.log_z.cpu().numpy(), run.gamma.cpu().numpy()))
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+
+
+def test_autotune_picks_a_timed_shape(B, uneven, truth_data):
+    ctx = B.Context(W.system(kmax_cond=7, kmax_charg=4), precision="f64", max_particles=2048)
+    dp = B.particles_to_device(uneven)
+    d = _data(B, truth_data)
+    ref = ctx.loglik(dp, d).cpu().numpy()
+    best, times = ctx.autotune(dp, d, reps=2)
+    assert len(times) == 6 and all(t > 0 for t in times)
+    k = 2 * (2, 4, 8).index(best["waves_per_block"]) + best["layer_sort"]
+    assert times[k] == min(times)
+    assert ctx.get_tuning() == best
+    assert np.array_equal(ctx.loglik(dp, d).cpu().numpy(), ref)
+    small = B.Context(W.system(kmax_cond=7, kmax_charg=4), precision="f64")   # no workspace
+    best2, times2 = small.autotune(dp, d, reps=1)
+    assert [t < 0 for t in times2] == [False, True] * 3 and best2["layer_sort"] == 0
+    ctx.check()
+
+
+def test_bad_tuning_rejected(B):
+    ctx = B.Context(W.system(), precision="f64")
+    for w, s in ((3, 0), (4, 2), (0, 0)):
+        with pytest.raises(B.RJSMCError):
+            ctx.set_tuning(w, s)
+    assert ctx.get_tuning() == {"waves_per_block": 4, "layer_sort": 0}
