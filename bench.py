@@ -63,14 +63,20 @@ def nominal_flop_per_eval(n_layers, n_freq=40, n_hankel=120):
     return n_freq * n_hankel * n_layers * FLOP_PER_LAYER_STEP
 
 
+def synth_response():
+    """Gate responses of the three-layer truth (device forward model)."""
+    from paper_2109_00661_amd import binding as B
+    ctx = B.Context(W.system(kmax_cond=2, kmax_charg=0), precision="f64")
+    y = ctx.forward(B.particles_to_device(W.truth_three_layer_merged())).cpu().numpy()[0]
+    ctx.check()
+    return y
+
+
 def synth_data(torch):
     """Synthetic sounding: the three-layer truth through the forward model plus noise
     with the standard deviation of the noise model at the response."""
-    from paper_2109_00661_amd import binding as B
     system = W.system(kmax_cond=2, kmax_charg=0)
-    ctx = B.Context(system, precision="f64")
-    y = ctx.forward(B.particles_to_device(W.truth_three_layer_merged())).cpu().numpy()[0]
-    ctx.check()
+    y = synth_response()
     s = np.sqrt(system["eps_an"] ** 2 + (system["eps_mn"] * y) ** 2)
     return torch.as_tensor(y + s * W.data_noise(1), device="cuda")
 
@@ -110,36 +116,56 @@ def cpu_baseline(system, d_np, budget_s=15.0):
                 sample="first %d of the 65,536 particles (numpy FP64, one thread), %.1f s" % (n_done, dt))
 
 
-def rjsmc_rate(torch, d, n_sound, n_per_sound, seed=0, move_prob=None):
-    """Soundings per second of complete Algorithm-1 runs (gamma 0 -> 1): n_sound copies
-    of the synthetic sounding, n_per_sound particles each, alpha = 0.5, 5 moves per step,
-    run together in the same launches.  Wall clock includes the per-step host check.
-    The spread over the replicate soundings of log Z of the best model and of the
-    posterior probability of a chargeable model measures Monte Carlo accuracy."""
+def rjsmc_rate(torch, d, n_sound, n_per_sound, seed=0, move_prob=None, graph=False, kmax=None, noise=False,
+               tune=False):
+    """Soundings per second of complete Algorithm-1 runs (gamma 0 -> 1): n_sound soundings
+    of n_per_sound particles each, alpha = 0.5, 5 moves per step, run together in the
+    same launches (graph=True: one captured HIP graph per step).  The soundings are copies
+    of the synthetic sounding, or (noise=True) independent noise realisations of its
+    response.  Wall clock includes the per-step host check.  The spread over the replicate
+    soundings of log Z of the best model and of the posterior probability of a chargeable
+    model measures Monte Carlo accuracy."""
     from paper_2109_00661_amd import binding as B
     from paper_2109_00661_amd.rjsmc import RJSMCRun, UNIFORM_MOVES
     mp = UNIFORM_MOVES if move_prob is None else move_prob
-    ctx = B.Context(W.system(), precision="f64", max_particles=n_sound * n_per_sound)
-    y = np.tile(d.cpu().numpy(), (n_sound, 1))
-    RJSMCRun(ctx, n_sound, n_per_sound, y, seed=seed + 99, move_prob=mp).run()          # warm-up
+    kc, km = kmax if kmax is not None else (W.PRIOR["kmax_cond"], W.PRIOR["kmax_charg"])
+    system = W.system(kmax_cond=kc, kmax_charg=km)
+    ctx = B.Context(system, precision="f64", max_particles=n_sound * n_per_sound)
+    d0 = d.cpu().numpy()
+    if noise:
+        y_true = synth_response()
+        s = np.sqrt(system["eps_an"] ** 2 + (system["eps_mn"] * y_true) ** 2)
+        y = np.stack([y_true + s * W.data_noise(1000 + i) for i in range(n_sound)])
+    else:
+        y = np.tile(d0, (n_sound, 1))
+    tuned = None
+    if tune:
+        warm = RJSMCRun(ctx, n_sound, n_per_sound, y, seed=seed + 99, move_prob=mp)
+        warm.initialise()
+        tuned, _ = ctx.autotune(warm.state, warm.y_obs, reps=3)
+    RJSMCRun(ctx, n_sound, n_per_sound, y, seed=seed + 99, move_prob=mp, graph=graph).run()          # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run = RJSMCRun(ctx, n_sound, n_per_sound, y, seed=seed, move_prob=mp).run()
+    run = RJSMCRun(ctx, n_sound, n_per_sound, y, seed=seed, move_prob=mp, graph=graph).run()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = run.stats.cpu().numpy()
     probs = run.model_probabilities()
-    km = ctx.kmax_charg
     p_ip = probs[:, (np.arange(probs.shape[1]) % (km + 1)) >= 1].sum(axis=1)
     lz = run.log_z.cpu().numpy()
     best = int(np.argmax(probs.mean(axis=0)))
     out = {"soundings_per_s": n_sound / dt, "n_sound": n_sound, "particles_per_sounding": n_per_sound,
-           "steps": run.step, "seconds": dt, "proposals": int(st[0].sum()),
+           "steps": run.step, "seconds": dt, "graph": graph,
+           "proposals_per_sounding": float(st[0].sum() / n_sound),
            "acceptance": float(st[1].sum() / max(st[0].sum(), 1)),
            "p_chargeable_mean": float(p_ip.mean()), "p_chargeable_sd": float(p_ip.std()),
            "best_model": best}
+    if tuned is not None:
+        out["tuning"] = tuned
     if n_sound > 1:
-        out["log_z_best_sd"] = float(np.std(lz[:, best][np.isfinite(lz[:, best])]))
+        fin = np.isfinite(lz[:, best])
+        out["log_z_best_sd"] = float(np.std(lz[fin, best])) if fin.any() else None
+        out["log_z_best_finite"] = int(fin.sum())
     return out
 
 
@@ -238,8 +264,11 @@ def main():
         out["adjoint"] = adjoint_rate(torch, d, max(3, args.steps // 4), 1)
     from paper_2109_00661_amd.rjsmc import LANGEVIN_MOVES
     out["rjsmc"] = {"single_sounding_256": rjsmc_rate(torch, d, 1, 256),
-                    "batched_64x256_rw": rjsmc_rate(torch, d, 64, 256),
-                    "batched_64x256_langevin": rjsmc_rate(torch, d, 64, 256, move_prob=LANGEVIN_MOVES)}
+                    "single_sounding_256_graph": rjsmc_rate(torch, d, 1, 256, graph=True),
+                    "batched_64x256_rw": rjsmc_rate(torch, d, 64, 256, graph=True),
+                    "batched_64x256_langevin": rjsmc_rate(torch, d, 64, 256, move_prob=LANGEVIN_MOVES, graph=True),
+                    "uneven_512x1024_rw": rjsmc_rate(torch, d, 512, 1024, graph=True, kmax=(7, 4), noise=True,
+                                                     tune=True)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(system, d.cpu().numpy())
     print(json.dumps(out), flush=True)

@@ -184,6 +184,8 @@ typedef struct {
   uint64_t seed;
   int32_t step;                 /* t >= 1 */
   int32_t n_sound;
+  const int32_t *step_dev;      /* device, may be NULL: when set, t is read from *step_dev
+                                   when the kernels run (for replayed HIP graphs) */
 } rjsmc_reweight_args;
 
 /* Re-weight and re-sample every sounding (Algorithm 1; Section 3.2.1; Appendices C, D):
@@ -235,6 +237,7 @@ typedef struct {
   double mala_eps;              /* gradient-informed step size */
   const double *factors;        /* device, as written by rjsmc_adapt */
   rjsmc_prior prior;
+  const int32_t *step_dev;      /* device, may be NULL: when set, t is read from *step_dev */
 } rjsmc_mutate_args;
 
 /* n_moves RJ-MCMC sweeps (Algorithm 1, mutation) targeting L^gamma(sounding) x prior.
@@ -259,6 +262,11 @@ rjsmc_status rjsmc_mutate(rjsmc_ctx *ctx, const rjsmc_mutate_args *args, rjsmc_p
                           const double *gamma, const int32_t *active, const double *y_obs,
                           rjsmc_particles *grad_cur, rjsmc_particles *grad_prop, int64_t *stats,
                           rjsmc_stream stream);
+
+/* *counter += delta on the device, in stream order (one thread).  With step_dev in the
+ * argument structs above, a whole SMC step (re-weight/re-sample, adapt, mutate, this
+ * increment) can be captured once into a HIP graph and replayed step after step. */
+rjsmc_status rjsmc_counter_add(rjsmc_ctx *ctx, int32_t *counter, int32_t delta, rjsmc_stream stream);
 
 /* ------------------------------------------------------------------------------------
  * Tile shape of the forward kernel.  Not part of the method: it decides how the

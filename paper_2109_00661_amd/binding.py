@@ -54,7 +54,7 @@ class Prior(ctypes.Structure):
 
 class ReweightArgs(ctypes.Structure):
     _fields_ = [("alpha_tess", ctypes.c_double), ("seed", ctypes.c_uint64), ("step", ctypes.c_int32),
-                ("n_sound", ctypes.c_int32)]
+                ("n_sound", ctypes.c_int32), ("step_dev", ctypes.c_void_p)]
 
 
 N_MOVES = 8
@@ -64,7 +64,7 @@ class MutateArgs(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("step", ctypes.c_int32), ("n_moves", ctypes.c_int32),
                 ("n_sound", ctypes.c_int32), ("move_prob", ctypes.c_double * N_MOVES),
                 ("z_move_sd", ctypes.c_double), ("rw_scale", ctypes.c_double), ("mala_eps", ctypes.c_double),
-                ("factors", ctypes.c_void_p), ("prior", Prior)]
+                ("factors", ctypes.c_void_p), ("prior", Prior), ("step_dev", ctypes.c_void_p)]
 
 
 class Tuning(ctypes.Structure):
@@ -107,6 +107,7 @@ _SIGS = {
                                     ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Particles),
                                     ctypes.POINTER(Particles), ctypes.c_void_p, ctypes.c_void_p]),
+    "rjsmc_counter_add": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "rjsmc_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "rjsmc_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "rjsmc_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p, ctypes.c_void_p,
@@ -231,6 +232,9 @@ class Context:
         _check(lib().rjsmc_time_kernel(self._ptr, _as_dp(K)))
         return K
 
+    def counter_add(self, counter, delta=1, stream=None):
+        _check(lib().rjsmc_counter_add(self._ptr, _ptr(counter), int(delta), _stream_handle(stream)))
+
     # -- tile shape --------------------------------------------------------------------
     def set_tuning(self, waves_per_block, layer_sort):
         t = Tuning(int(waves_per_block), int(layer_sort))
@@ -292,8 +296,8 @@ class Context:
         _check(lib().rjsmc_init_prior(self._ptr, ctypes.byref(ps), ctypes.byref(pr), seed, _stream_handle(stream)))
 
     def reweight_resample(self, p_in, ll_in, p_out, ll_out, gamma, log_z, active, anc, alpha, seed, step, n_sound,
-                          stream=None):
-        a = ReweightArgs(alpha, seed, step, n_sound)
+                          stream=None, step_dev=None):
+        a = ReweightArgs(alpha, seed, step, n_sound, _ptr(step_dev) if step_dev is not None else None)
         si, so = particles_struct(p_in), particles_struct(p_out)
         _check(lib().rjsmc_reweight_resample(self._ptr, ctypes.byref(a), ctypes.byref(si), _ptr(ll_in),
                                              ctypes.byref(so), _ptr(ll_out), _ptr(gamma), _ptr(log_z), _ptr(active),
@@ -307,7 +311,7 @@ class Context:
 
     def mutate(self, state, ll, scratch, ll_scratch, gamma, active, y_obs, stats, *, seed, step, n_moves, n_sound,
                prior, move_prob, z_move_sd, rw_scale, factors, mala_eps=0.0, grad_cur=None, grad_prop=None,
-               stream=None):
+               stream=None, step_dev=None):
         a = MutateArgs()
         a.seed, a.step, a.n_moves, a.n_sound = seed, step, n_moves, n_sound
         for t in range(N_MOVES):
@@ -315,6 +319,7 @@ class Context:
         a.z_move_sd, a.rw_scale, a.mala_eps = z_move_sd, rw_scale, mala_eps
         a.factors = _ptr(factors) if factors is not None else ctypes.c_void_p(0)
         a.prior = make_prior(prior)
+        a.step_dev = _ptr(step_dev) if step_dev is not None else None
         ss, sq = particles_struct(state), particles_struct(scratch)
         gc = ctypes.byref(particles_struct(grad_cur)) if grad_cur is not None else None
         gp = ctypes.byref(particles_struct(grad_prop)) if grad_prop is not None else None

@@ -716,3 +716,11 @@ extern "C" rjsmc_status rjsmc_autotune(rjsmc_ctx *c, const rjsmc_particles *p, c
   if (best) *best = bt;
   return RJSMC_OK;
 }
+
+extern "C" rjsmc_status rjsmc_counter_add(rjsmc_ctx *c, int32_t *counter, int32_t delta, rjsmc_stream stream) {
+  if (!c || !counter) return fail(RJSMC_E_INVALID, "rjsmc_counter_add: NULL argument");
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = rjsmc::launch_counter_add(counter, delta, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "rjsmc_counter_add: launch");
+  return RJSMC_OK;
+}

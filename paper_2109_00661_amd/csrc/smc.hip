@@ -14,6 +14,22 @@
 
 namespace rjsmc {
 
+// The step t of a re-weight or mutate call: from device memory when the caller keeps it
+// there (replayed graphs), else the value passed.
+template <typename A>
+__device__ __forceinline__ int32_t step_of(const A &a) {
+  return a.step_dev ? *a.step_dev : a.step;
+}
+
+__global__ void counter_add_kernel(int32_t *counter, int32_t delta) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter += delta;
+}
+
+hipError_t launch_counter_add(int32_t *counter, int32_t delta, hipStream_t stream) {
+  hipLaunchKernelGGL(counter_add_kernel, dim3(1), dim3(64), 0, stream, counter, delta);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ Philox4x32-10 ----
 // Counter-based generator of Salmon, Moraes, Dror and Shaw (SC'11): ten rounds of two
 // 32x32->64 multiplies with the Philox multipliers, with the key bumped by the Weyl
@@ -290,7 +306,7 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
     if (lane == 0) {
       sm.mx[m] = v;
       uint64_t x0, x1;
-      bits53(a.seed, (uint32_t)s, (uint32_t)a.step, (uint32_t)m, kDomainResample, x0, x1);
+      bits53(a.seed, (uint32_t)s, (uint32_t)step_of(a), (uint32_t)m, kDomainResample, x0, x1);
       sm.U[m] = x0;
     }
   }
@@ -620,7 +636,7 @@ __global__ __launch_bounds__(256) void draw_types_kernel(rjsmc_mutate_args a, in
   int t = -1;
   if ((!active || active[snd]) && k >= 0 && k <= kc && l >= 0 && l <= km) {
     double u0, ua;
-    uniforms(a.seed, (uint32_t)i, (uint32_t)a.step, (uint32_t)move, 0u, u0, ua);
+    uniforms(a.seed, (uint32_t)i, (uint32_t)step_of(a), (uint32_t)move, 0u, u0, ua);
     t = draw_type(a, u0);
   }
   type[i] = t;
@@ -632,7 +648,7 @@ __global__ __launch_bounds__(256) void draw_types_kernel(rjsmc_mutate_args a, in
 __device__ __forceinline__ void mala_normals(const rjsmc_mutate_args &a, int64_t i, int move, int d, double *xi) {
   for (int r = 0; r < d; r += 2) {
     double u1, u2;
-    uniforms(a.seed, (uint32_t)i, (uint32_t)a.step, (uint32_t)move, (uint32_t)(3 + r / 2), u1, u2);
+    uniforms(a.seed, (uint32_t)i, (uint32_t)step_of(a), (uint32_t)move, (uint32_t)(3 + r / 2), u1, u2);
     const double rad = sqrt(-2.0 * log(u1));
     double sn, cs;
     sincos(6.283185307179586477 * u2, &sn, &cs);
@@ -659,8 +675,8 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
   const int kc = sh.kc, km = sh.km;
   const rjsmc_prior &pr = a.prior;
   double u1, u2, u3, u4;
-  uniforms(a.seed, (uint32_t)i, (uint32_t)a.step, (uint32_t)move, 1u, u1, u2);
-  uniforms(a.seed, (uint32_t)i, (uint32_t)a.step, (uint32_t)move, 2u, u3, u4);
+  uniforms(a.seed, (uint32_t)i, (uint32_t)step_of(a), (uint32_t)move, 1u, u1, u2);
+  uniforms(a.seed, (uint32_t)i, (uint32_t)step_of(a), (uint32_t)move, 2u, u3, u4);
   int k = st.kappa[i], l = st.lambda[i];
   double zc[kMaxLayers], ph[kMaxLayers], zm[kMaxLayers], mm[kMaxLayers];
   for (int j = 0; j < k; ++j) {
@@ -809,7 +825,7 @@ __global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_a
   if (in && t >= 0 && mask[i]) {
     const int64_t snd = st.n_per_sounding > 0 ? i / st.n_per_sounding : 0;
     double u0, ua;
-    uniforms(a.seed, (uint32_t)i, (uint32_t)a.step, (uint32_t)move, 0u, u0, ua);
+    uniforms(a.seed, (uint32_t)i, (uint32_t)step_of(a), (uint32_t)move, 0u, u0, ua);
     double extra = 0.0;
     if (t == RJSMC_MOVE_WITHIN_MALA) {
       // log q(theta | theta') - log q(theta' | theta) = -|xi + eps/2 F^T gamma (g + g')|^2/2 + |xi|^2/2

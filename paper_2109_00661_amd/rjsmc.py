@@ -15,8 +15,15 @@ LANGEVIN_MOVES = (1, 1, 1, 1, 1, 1, 0, 1)    # the within-model move is the grad
 
 
 class RJSMCRun:
+    """One RJSMC run over n_sound soundings of n_per_sound particles each.
+
+    graph=True captures one whole step (re-weight/re-sample, adapt, R mutation sweeps and
+    the device step counter) into a HIP graph per ping-pong direction and replays it, so
+    a step costs one graph launch instead of tens of kernel launches from Python."""
+
     def __init__(self, ctx, n_sound, n_per_sound, y_obs, *, prior=None, alpha=0.5, n_moves=5, seed=0,
-                 move_prob=UNIFORM_MOVES, z_move_frac=0.05, rw_scale=2.38, mala_eps=0.8, device="cuda"):
+                 move_prob=UNIFORM_MOVES, z_move_frac=0.05, rw_scale=2.38, mala_eps=0.8, device="cuda",
+                 graph=False):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -46,6 +53,9 @@ class RJSMCRun:
         if move_prob[B.N_MOVES - 1] > 0:
             self.grads = [B.empty_device_population(self.n, kc, km, nps, device) for _ in range(2)]
         self.step = 0
+        self.use_graph = graph
+        self.graphs = None
+        self.step_dev = None
 
     @property
     def state(self):
@@ -59,12 +69,13 @@ class RJSMCRun:
         self.ctx.init_prior(self.state, self.prior, self.seed)
         self.ctx.loglik(self.state, self.y_obs, out=self.ll)
 
-    def advance(self):
-        """One iteration of the while-loop of Algorithm 1."""
-        self.step += 1
+    def _launch_step(self, step_dev=None):
+        """Enqueues one iteration of the while-loop of Algorithm 1 (step self.step, or the
+        value in step_dev when the kernels run) and flips the ping-pong buffers."""
         nxt = 1 - self.cur
         self.ctx.reweight_resample(self.bufs[self.cur], self.lls[self.cur], self.bufs[nxt], self.lls[nxt], self.gamma,
-                                   self.log_z, self.active, self.anc, self.alpha, self.seed, self.step, self.S)
+                                   self.log_z, self.active, self.anc, self.alpha, self.seed, self.step, self.S,
+                                   step_dev=step_dev)
         self.cur = nxt
         self.ctx.adapt(self.state, self.S, self.prior, self.factors)
         self.ctx.mutate(self.state, self.ll, self.bufs[1 - self.cur], self.lls[1 - self.cur], self.gamma, self.active,
@@ -72,7 +83,40 @@ class RJSMCRun:
                         n_sound=self.S, prior=self.prior, move_prob=self.move_prob, z_move_sd=self.z_move_sd,
                         rw_scale=self.rw_scale, factors=self.factors, mala_eps=self.mala_eps,
                         grad_cur=self.grads[0] if self.grads else None,
-                        grad_prop=self.grads[1] if self.grads else None)
+                        grad_prop=self.grads[1] if self.grads else None, step_dev=step_dev)
+        if step_dev is not None:
+            self.ctx.counter_add(step_dev, 1)
+
+    def _capture(self):
+        """Captures the step from each buffer into a graph; the device counter holds the
+        step the next replay runs."""
+        torch = self.torch
+        self.step_dev = torch.full((1,), self.step + 1, dtype=torch.int32, device=self.gamma.device)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        cur0 = self.cur
+        self.graphs = {}
+        for start in (cur0, 1 - cur0):
+            self.cur = start
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                self._launch_step(self.step_dev)
+            self.graphs[start] = g
+        self.cur = cur0
+        torch.cuda.current_stream().wait_stream(side)
+
+    def advance(self):
+        """One iteration of the while-loop of Algorithm 1."""
+        self.step += 1
+        if not self.use_graph:
+            self._launch_step()
+            return
+        if self.graphs is None:
+            self.step -= 1
+            self._capture()
+            self.step += 1
+        self.graphs[self.cur].replay()
+        self.cur = 1 - self.cur
 
     def run(self, max_steps=1000):
         self.initialise()

@@ -276,3 +276,35 @@ def test_mutate_gradient_informed_against_oracle(B, ctx, system, K_oracle, truth
     if not near:
         assert np.array_equal(stats.cpu().numpy(), st_o)
     assert st_o[0, 7] > 0
+
+
+@pytest.mark.parametrize("moves", ["rw", "langevin"])
+def test_graph_replay_matches_eager(B, truth_data, moves):
+    """A whole step captured once into a HIP graph per ping-pong direction and replayed
+    (device step counter) gives bit-identical states, log-likelihoods, evidence,
+    temperatures and move counts to the eager calls, after every step."""
+    from paper_2109_00661_amd.rjsmc import RJSMCRun, UNIFORM_MOVES, LANGEVIN_MOVES
+    mp = UNIFORM_MOVES if moves == "rw" else LANGEVIN_MOVES
+    y = np.tile(truth_data, (2, 1))
+    runs = []
+    for graph in (False, True):
+        ctx = B.Context(W.system(), precision="f64", max_particles=512)
+        run = RJSMCRun(ctx, 2, 256, y, seed=9, move_prob=mp, graph=graph)
+        run.initialise()
+        runs.append(run)
+    eager, graphed = runs
+    for step in range(40):
+        eager.advance()
+        graphed.advance()
+        assert np.array_equal(eager.ll.cpu().numpy(), graphed.ll.cpu().numpy()), step
+        assert np.array_equal(eager.gamma.cpu().numpy(), graphed.gamma.cpu().numpy()), step
+        assert np.array_equal(eager.log_z.cpu().numpy(), graphed.log_z.cpu().numpy()), step
+        if bool((eager.gamma >= 1.0).all()):
+            break
+    assert bool((graphed.gamma >= 1.0).all())
+    for k in ("kappa", "lambda_", "phi_b", "phi", "z_cond", "m", "z_charg", "log10_tau", "c"):
+        assert np.array_equal(eager.state[k].cpu().numpy(), graphed.state[k].cpu().numpy()), k
+    assert np.array_equal(eager.stats.cpu().numpy(), graphed.stats.cpu().numpy())
+    assert int(graphed.step_dev.item()) == graphed.step + 1
+    eager.ctx.check()
+    graphed.ctx.check()
