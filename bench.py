@@ -264,9 +264,10 @@ def main():
         out["adjoint"] = adjoint_rate(torch, d, max(3, args.steps // 4), 1)
     from paper_2109_00661_amd.rjsmc import LANGEVIN_MOVES
     out["rjsmc"] = {"single_sounding_256": rjsmc_rate(torch, d, 1, 256),
-                    "single_sounding_256_graph": rjsmc_rate(torch, d, 1, 256, graph=True),
-                    "batched_64x256_rw": rjsmc_rate(torch, d, 64, 256, graph=True),
-                    "batched_64x256_langevin": rjsmc_rate(torch, d, 64, 256, move_prob=LANGEVIN_MOVES, graph=True),
+                    "single_sounding_256_tuned_graph": rjsmc_rate(torch, d, 1, 256, graph=True, tune=True),
+                    "batched_64x256_rw": rjsmc_rate(torch, d, 64, 256, graph=True, tune=True),
+                    "batched_64x256_langevin": rjsmc_rate(torch, d, 64, 256, move_prob=LANGEVIN_MOVES, graph=True,
+                                                          tune=True),
                     "uneven_512x1024_rw": rjsmc_rate(torch, d, 512, 1024, graph=True, kmax=(7, 4), noise=True,
                                                      tune=True)}
     if not args.no_cpu:

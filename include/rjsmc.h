@@ -274,16 +274,22 @@ rjsmc_status rjsmc_counter_add(rjsmc_ctx *ctx, int32_t *counter, int32_t delta, 
  * identical for every shape).
  * ---------------------------------------------------------------------------------- */
 typedef struct {
-  int32_t waves_per_block;  /* particles (one wavefront each) per workgroup: 2, 4 or 8 */
-  int32_t layer_sort;       /* 1: evaluate particles in descending order of layer capacity
-                               (kappa + lambda + 1), computed on the device before each
-                               launch; used only when n <= max_particles of the context */
+  int32_t waves_per_block;    /* particles per workgroup */
+  int32_t layer_sort;         /* 1: evaluate particles in descending order of layer capacity
+                                 (kappa + lambda + 1), computed on the device before each
+                                 launch; used only when n <= max_particles of the context */
+  int32_t waves_per_particle; /* wavefronts sharing one particle's frequency groups (more
+                                 than one shortens the latency of small batches) */
 } rjsmc_tuning;
 
-#define RJSMC_TUNING_CANDIDATES 6   /* waves_per_block {2,4,8} x layer_sort {0,1} */
+/* The tile shapes, as (waves_per_block, waves_per_particle):
+ *   (2,1) (4,1) (8,1) (2,2) (1,4) (1,8),
+ * each with layer_sort 0 and 1: candidate k = 2 * shape index + layer_sort. */
+#define RJSMC_TUNING_CANDIDATES 12
 
 /* Sets / reads the tile shape used by rjsmc_forward, rjsmc_loglik and the proposal
- * likelihoods of rjsmc_mutate (default {4, 0}).  RJSMC_E_INVALID for other values. */
+ * likelihoods of rjsmc_mutate (default {4, 0, 1}).  RJSMC_E_INVALID for a shape not in
+ * the list above. */
 rjsmc_status rjsmc_set_tuning(rjsmc_ctx *ctx, const rjsmc_tuning *tuning);
 rjsmc_status rjsmc_get_tuning(const rjsmc_ctx *ctx, rjsmc_tuning *tuning);
 
@@ -291,8 +297,8 @@ rjsmc_status rjsmc_get_tuning(const rjsmc_ctx *ctx, rjsmc_tuning *tuning);
  * overwritten) for every candidate tile shape, `reps` launches each after one warm-up,
  * with HIP events on `stream`; keeps the fastest in the context and writes it to *best
  * (may be NULL).  times_ms (host float[RJSMC_TUNING_CANDIDATES], may be NULL) receives
- * the mean launch time of candidate k = 2 * index(waves_per_block) + layer_sort, or -1
- * for a candidate that needs more workspace than max_particles.  Synchronizes `stream`.
+ * the mean launch time of candidate k, or -1 for a candidate that needs more workspace
+ * than max_particles.  Synchronizes `stream`.
  * RJSMC_E_INVALID for bad arguments or reps outside 1..1000. */
 rjsmc_status rjsmc_autotune(rjsmc_ctx *ctx, const rjsmc_particles *p, const double *y_obs, double *ll,
                             int32_t reps, rjsmc_tuning *best, float *times_ms, rjsmc_stream stream);

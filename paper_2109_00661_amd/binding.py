@@ -68,10 +68,12 @@ class MutateArgs(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("waves_per_block", ctypes.c_int32), ("layer_sort", ctypes.c_int32)]
+    _fields_ = [("waves_per_block", ctypes.c_int32), ("layer_sort", ctypes.c_int32),
+                ("waves_per_particle", ctypes.c_int32)]
 
 
-TUNING_CANDIDATES = 6
+TUNING_CANDIDATES = 12
+TILE_SHAPES = ((2, 1), (4, 1), (8, 1), (2, 2), (1, 4), (1, 8))   # (waves_per_block, waves_per_particle)
 
 
 def make_prior(pr):
@@ -236,14 +238,15 @@ class Context:
         _check(lib().rjsmc_counter_add(self._ptr, _ptr(counter), int(delta), _stream_handle(stream)))
 
     # -- tile shape --------------------------------------------------------------------
-    def set_tuning(self, waves_per_block, layer_sort):
-        t = Tuning(int(waves_per_block), int(layer_sort))
+    def set_tuning(self, waves_per_block, layer_sort, waves_per_particle=1):
+        t = Tuning(int(waves_per_block), int(layer_sort), int(waves_per_particle))
         _check(lib().rjsmc_set_tuning(self._ptr, ctypes.byref(t)))
 
     def get_tuning(self):
         t = Tuning()
         _check(lib().rjsmc_get_tuning(self._ptr, ctypes.byref(t)))
-        return {"waves_per_block": t.waves_per_block, "layer_sort": t.layer_sort}
+        return {"waves_per_block": t.waves_per_block, "layer_sort": t.layer_sort,
+                "waves_per_particle": t.waves_per_particle}
 
     def autotune(self, p, y_obs, reps=3, stream=None):
         """Times every tile shape on p, keeps the fastest; returns (best, times_ms)."""
@@ -255,7 +258,8 @@ class Context:
         ps = particles_struct(p)
         _check(lib().rjsmc_autotune(self._ptr, ctypes.byref(ps), _ptr(y_obs), _ptr(ll), int(reps), ctypes.byref(best),
                                     times, _stream_handle(stream)))
-        return ({"waves_per_block": best.waves_per_block, "layer_sort": best.layer_sort}, list(times))
+        return ({"waves_per_block": best.waves_per_block, "layer_sort": best.layer_sort,
+                 "waves_per_particle": best.waves_per_particle}, list(times))
 
     # -- hot calls ---------------------------------------------------------------------
     def forward(self, p, out=None, stream=None):

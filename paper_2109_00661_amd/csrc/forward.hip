@@ -29,15 +29,18 @@ __device__ __forceinline__ T to(double x) {
 }
 
 // resp != nullptr: write gate responses.  ll != nullptr: write the log-likelihood.
-// WPB particles (one wave each) per workgroup.  perm != nullptr: slot j of the grid
-// evaluates particle perm[j] (workgroups in launch order, dealt round-robin to the XCDs);
+// WPB particles per workgroup, P waves per particle: wave q0 of a particle takes the
+// frequency groups q0, q0 + P, ... (P = 1: the whole particle; P > 1 shortens the
+// latency of small batches), and the particle's first wave applies the gates and the
+// likelihood after a workgroup barrier.  perm != nullptr: slot j of the grid evaluates
+// particle perm[j] (workgroups in launch order, dealt round-robin to the XCDs);
 // otherwise slot j is particle j (workgroups renumbered XCD-contiguous).
-template <typename T, int WPB>
-__global__ __launch_bounds__(kWave * WPB, 16 / WPB) void forward_kernel(DevSystem s, DevParticles p, int kc, int km,
-                                                                       double *resp, const double *y_obs,
-                                                                       double *ll, const int32_t *perm) {
+template <typename T, int WPB, int P>
+__global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P) : 1) void forward_kernel(
+    DevSystem s, DevParticles p, int kc, int km, double *resp, const double *y_obs, double *ll,
+    const int32_t *perm) {
   constexpr int LMAX = kMaxLayers;
-  constexpr int kWavesPerBlock = WPB;
+  constexpr int kWavesPerBlock = WPB * P;
   __shared__ double s_lam[kMaxHankel];
   __shared__ double s_ck[kMaxHankel];
   __shared__ double s_omega[kMaxFreq];
@@ -45,7 +48,7 @@ __global__ __launch_bounds__(kWave * WPB, 16 / WPB) void forward_kernel(DevSyste
   __shared__ cplx<double> s_phase[kPhaseN];
   __shared__ double s_exp2[kExp2N];
   __shared__ LayerStack s_stack[kWavesPerBlock];
-  __shared__ double s_imh[kWavesPerBlock][kMaxFreq];
+  __shared__ double s_imh[WPB][kMaxFreq];
   __shared__ cplx<T> s_k2[kWavesPerBlock][8][LMAX];
   __shared__ cplx<T> s_dk2[kWavesPerBlock][8][LMAX];
   __shared__ T s_h2[kWavesPerBlock][LMAX];
@@ -65,7 +68,9 @@ __global__ __launch_bounds__(kWave * WPB, 16 / WPB) void forward_kernel(DevSyste
 
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t slot = (int64_t)(perm ? blockIdx.x : xcd_block(blockIdx.x, gridDim.x)) * kWavesPerBlock + wave;
+  const int pw = wave / P;           // particle of this wave within the workgroup
+  const int q0 = wave % P;           // first frequency group of this wave
+  const int64_t slot = (int64_t)(perm ? blockIdx.x : xcd_block(blockIdx.x, gridDim.x)) * WPB + pw;
   const int64_t i = perm ? (slot < p.n ? (int64_t)perm[slot] : p.n) : slot;
   const bool valid = i < p.n;
   const bool skip = valid && p.mask && p.mask[i] != p.mask_value;
@@ -86,7 +91,7 @@ __global__ __launch_bounds__(kWave * WPB, 16 / WPB) void forward_kernel(DevSyste
   const int nq = (nf + 7) >> 3;
   // the waves of a workgroup run independently from here on (wave-level syncs only)
 #pragma unroll 1
-  for (int q = 0; q < nq; ++q) {
+  for (int q = q0; q < nq; q += P) {
     const int jf = gw + 8 * q;
     const bool act = L > 0 && jf < nf;
     if (act) {
@@ -122,15 +127,19 @@ __global__ __launch_bounds__(kWave * WPB, 16 / WPB) void forward_kernel(DevSyste
       acc += __shfl_xor(acc, 1);
       acc += __shfl_xor(acc, 2);
       acc += __shfl_xor(acc, 4);
-      if (gl == 0) s_imh[wave][jf] = acc;
+      if (gl == 0) s_imh[pw][jf] = acc;
     }
     wave_lds_sync();
+  }
+  if (P > 1) {
+    __syncthreads();                 // every wave of the particle has written its Im H
+    if (q0 != 0) return;
   }
   if (L > 0) {
     double term = 0.0;
     if (lane < ng) {
       double y = 0.0;
-      for (int j = 0; j < nf; ++j) y += s_K[lane * nf + j] * s_imh[wave][j];
+      for (int j = 0; j < nf; ++j) y += s_K[lane * nf + j] * s_imh[pw][j];
       if (resp) resp[i * ng + lane] = y;
       if (ll) {
         const int64_t snd = p.n_per_sounding > 0 ? i / p.n_per_sounding : 0;
@@ -160,23 +169,28 @@ __global__ __launch_bounds__(kWave * WPB, 16 / WPB) void forward_kernel(DevSyste
   }
 }
 
-template <typename T, int WPB>
+template <typename T, int WPB, int P>
 static hipError_t launch_t(const DevSystem &s, const DevParticles &p, int kc, int km, double *resp,
                            const double *y_obs, double *ll, const int32_t *perm, hipStream_t stream) {
   const int64_t blocks = (p.n + WPB - 1) / WPB;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   const size_t dyn = sizeof(double) * s.n_freq * s.n_gate;
-  hipLaunchKernelGGL((forward_kernel<T, WPB>), dim3((unsigned)blocks), dim3(kWave * WPB), dyn, stream, s, p, kc, km,
-                     resp, y_obs, ll, perm);
+  hipLaunchKernelGGL((forward_kernel<T, WPB, P>), dim3((unsigned)blocks), dim3(kWave * WPB * P), dyn, stream, s, p,
+                     kc, km, resp, y_obs, ll, perm);
   return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t launch_prec(const ForwardTiles &t, const DevSystem &s, const DevParticles &p, int kc, int km,
                               double *resp, const double *y_obs, double *ll, hipStream_t stream) {
-  if (t.waves_per_block == 2) return launch_t<T, 2>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
-  if (t.waves_per_block == 8) return launch_t<T, 8>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
-  return launch_t<T, 4>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
+  const int w = t.waves_per_block, q = t.waves_per_particle;
+  if (q == 2 && w == 2) return launch_t<T, 2, 2>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
+  if (q == 4 && w == 1) return launch_t<T, 1, 4>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
+  if (q == 8 && w == 1) return launch_t<T, 1, 8>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
+  if (q != 1) return hipErrorInvalidValue;
+  if (w == 2) return launch_t<T, 2, 1>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
+  if (w == 8) return launch_t<T, 8, 1>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
+  return launch_t<T, 4, 1>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
 }
 
 hipError_t launch_forward(const DevSystem &s, const DevParticles &p, int kc, int km, int precision,

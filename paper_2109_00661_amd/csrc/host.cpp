@@ -284,6 +284,7 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
   c->work_cnt = nullptr;
   c->tuning.waves_per_block = 4;
   c->tuning.layer_sort = 0;
+  c->tuning.waves_per_particle = 1;
   c->work_n = s->max_particles > 0 ? s->max_particles : 0;
   if (e == hipSuccess && c->work_n > 0) {
     e = hipMalloc((void **)&c->work_mask, sizeof(int32_t) * c->work_n);
@@ -392,6 +393,7 @@ static rjsmc_status check_particles(const rjsmc_ctx *c, const rjsmc_particles *p
 static hipError_t forward_tiles(const rjsmc_ctx *c, const rjsmc::DevParticles &dp, const rjsmc_tuning &t,
                                 hipStream_t stream, rjsmc::ForwardTiles *tiles) {
   tiles->waves_per_block = t.waves_per_block;
+  tiles->waves_per_particle = t.waves_per_particle;
   tiles->perm = nullptr;
   if (t.layer_sort && c->work_perm && dp.n <= c->work_n && dp.n > 0) {
     const hipError_t e = rjsmc::launch_layer_sort(dp, c->work_cnt, c->work_perm, stream);
@@ -652,15 +654,21 @@ extern "C" rjsmc_status rjsmc_mutate(rjsmc_ctx *c, const rjsmc_mutate_args *a, r
 }
 
 // ---------------------------------------------------------------------------- tuning
+// (waves_per_block, waves_per_particle) of the compiled tile shapes.
+static const int kShapes[RJSMC_TUNING_CANDIDATES / 2][2] = {{2, 1}, {4, 1}, {8, 1}, {2, 2}, {1, 4}, {1, 8}};
+
 static bool valid_tuning(const rjsmc_tuning &t) {
-  return (t.waves_per_block == 2 || t.waves_per_block == 4 || t.waves_per_block == 8) &&
-         (t.layer_sort == 0 || t.layer_sort == 1);
+  if (t.layer_sort != 0 && t.layer_sort != 1) return false;
+  for (const auto &sh : kShapes)
+    if (t.waves_per_block == sh[0] && t.waves_per_particle == sh[1]) return true;
+  return false;
 }
 
 extern "C" rjsmc_status rjsmc_set_tuning(rjsmc_ctx *c, const rjsmc_tuning *t) {
   if (!c || !t) return fail(RJSMC_E_INVALID, "rjsmc_set_tuning: NULL argument");
   if (!valid_tuning(*t))
-    return fail(RJSMC_E_INVALID, "rjsmc_set_tuning: waves_per_block must be 2, 4 or 8 and layer_sort 0 or 1");
+    return fail(RJSMC_E_INVALID, "rjsmc_set_tuning: (%d, %d, %d) is not a compiled tile shape", t->waves_per_block,
+                t->layer_sort, t->waves_per_particle);
   c->tuning = *t;
   return RJSMC_OK;
 }
@@ -686,11 +694,10 @@ extern "C" rjsmc_status rjsmc_autotune(rjsmc_ctx *c, const rjsmc_particles *p, c
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   e = hipEventCreate(&ev0);
   if (e == hipSuccess) e = hipEventCreate(&ev1);
-  const int wpb[3] = {2, 4, 8};
   rjsmc_tuning bt = c->tuning;
   float bms = -1.0f;
   for (int k = 0; k < RJSMC_TUNING_CANDIDATES && e == hipSuccess; ++k) {
-    const rjsmc_tuning t = {wpb[k / 2], k % 2};
+    const rjsmc_tuning t = {kShapes[k / 2][0], k % 2, kShapes[k / 2][1]};
     float ms = -1.0f;
     if (!t.layer_sort || (c->work_perm && dp.n <= c->work_n)) {
       e = run_forward(c, dp, t, nullptr, y_obs, ll, s);   // warm-up

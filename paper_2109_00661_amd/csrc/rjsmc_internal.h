@@ -93,7 +93,8 @@ struct DevGrad {
 // Tile shape of one forward launch: particles per workgroup and an optional evaluation
 // order (a permutation of the particle indices).
 struct ForwardTiles {
-  int waves_per_block = 4;
+  int waves_per_block = 4;     // particles per workgroup
+  int waves_per_particle = 1;  // waves sharing one particle's frequency groups
   const int32_t *perm = nullptr;
 };
 

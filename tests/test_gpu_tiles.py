@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-SHAPES = [(w, s) for w in (2, 4, 8) for s in (0, 1)]
+SHAPES = [(w, s, q) for (w, q) in ((2, 1), (4, 1), (8, 1), (2, 2), (1, 4), (1, 8)) for s in (0, 1)]
 
 
 @pytest.fixture(scope="module")
@@ -38,18 +38,18 @@ def test_every_shape_bit_identical(B, uneven, truth_data, prec):
     ctx = B.Context(W.system(kmax_cond=7, kmax_charg=4), precision=prec, max_particles=2048)
     dp = B.particles_to_device(uneven)
     d = _data(B, truth_data)
-    assert ctx.get_tuning() == {"waves_per_block": 4, "layer_sort": 0}
+    assert ctx.get_tuning() == {"waves_per_block": 4, "layer_sort": 0, "waves_per_particle": 1}
     ref_y = ctx.forward(dp).cpu().numpy()
     ref_ll = ctx.loglik(dp, d).cpu().numpy()
     ctx.check()
     assert np.all(np.isfinite(ref_ll))
-    for w, s in SHAPES:
-        ctx.set_tuning(w, s)
+    for w, s, q in SHAPES:
+        ctx.set_tuning(w, s, q)
         y = ctx.forward(dp).cpu().numpy()
         ll = ctx.loglik(dp, d).cpu().numpy()
         ctx.check()
-        assert np.array_equal(y, ref_y), (w, s)
-        assert np.array_equal(ll, ref_ll), (w, s)
+        assert np.array_equal(y, ref_y), (w, s, q)
+        assert np.array_equal(ll, ref_ll), (w, s, q)
 
 
 def test_sort_skipped_beyond_workspace(B, uneven, truth_data):
@@ -64,11 +64,11 @@ def test_sort_skipped_beyond_workspace(B, uneven, truth_data):
 
 
 def test_masked_mutation_under_sorted_shape(B, truth_data):
-    """The proposal likelihoods of rjsmc_mutate use the tuned shape: a sorted, 8-wave
-    shape gives the same chain as the default shape."""
+    """The proposal likelihoods of rjsmc_mutate use the tuned shape: sorted and
+    multi-wave shapes give the same chain as the default shape."""
     from paper_2109_00661_amd.rjsmc import RJSMCRun
     runs = []
-    for shape in ((4, 0), (8, 1)):
+    for shape in ((4, 0, 1), (8, 1, 1), (1, 1, 8)):
         ctx = B.Context(W.system(), precision="f64", max_particles=512)
         ctx.set_tuning(*shape)
         run = RJSMCRun(ctx, 2, 256, np.tile(truth_data, (2, 1)), seed=5)
@@ -77,8 +77,9 @@ def test_masked_mutation_under_sorted_shape(B, truth_data):
             run.advance()
         ctx.check()
         runs.append((run.ll.cpu().numpy(), run.log_z.cpu().numpy(), run.gamma.cpu().numpy()))
-    for a, b in zip(*runs):
-        assert np.array_equal(a, b)
+    for other in runs[1:]:
+        for a, b in zip(runs[0], other):
+            assert np.array_equal(a, b)
 
 
 def test_autotune_picks_a_timed_shape(B, uneven, truth_data):
@@ -87,20 +88,20 @@ def test_autotune_picks_a_timed_shape(B, uneven, truth_data):
     d = _data(B, truth_data)
     ref = ctx.loglik(dp, d).cpu().numpy()
     best, times = ctx.autotune(dp, d, reps=2)
-    assert len(times) == 6 and all(t > 0 for t in times)
-    k = 2 * (2, 4, 8).index(best["waves_per_block"]) + best["layer_sort"]
+    assert len(times) == 12 and all(t > 0 for t in times)
+    k = 2 * B.TILE_SHAPES.index((best["waves_per_block"], best["waves_per_particle"])) + best["layer_sort"]
     assert times[k] == min(times)
     assert ctx.get_tuning() == best
     assert np.array_equal(ctx.loglik(dp, d).cpu().numpy(), ref)
     small = B.Context(W.system(kmax_cond=7, kmax_charg=4), precision="f64")   # no workspace
     best2, times2 = small.autotune(dp, d, reps=1)
-    assert [t < 0 for t in times2] == [False, True] * 3 and best2["layer_sort"] == 0
+    assert [t < 0 for t in times2] == [False, True] * 6 and best2["layer_sort"] == 0
     ctx.check()
 
 
 def test_bad_tuning_rejected(B):
     ctx = B.Context(W.system(), precision="f64")
-    for w, s in ((3, 0), (4, 2), (0, 0)):
+    for w, s, q in ((3, 0, 1), (4, 2, 1), (0, 0, 1), (4, 0, 2), (1, 0, 5)):
         with pytest.raises(B.RJSMCError):
-            ctx.set_tuning(w, s)
-    assert ctx.get_tuning() == {"waves_per_block": 4, "layer_sort": 0}
+            ctx.set_tuning(w, s, q)
+    assert ctx.get_tuning() == {"waves_per_block": 4, "layer_sort": 0, "waves_per_particle": 1}
