@@ -250,7 +250,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
                      "traffic_unit": "HBM bytes per launch",
-                     "kernel": "forward_kernel<8,double>", "flop_per_launch": flop},
+                     "kernel": "forward_kernel<double,4,1>", "flop_per_launch": flop},
         "wall_s_timed": wall,
     }
     if args.headline_only:
