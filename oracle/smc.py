@@ -436,17 +436,20 @@ def copy_particle(p, i):
 
 
 def mutate(p, ll, loglik_fn, gamma_of, step, seed, q, pr, kmax_cond, kmax_charg, factors_of, n_moves,
-           grad_fn=None):
+           grad_fn=None, indices=None):
     """n_moves RJ-MCMC sweeps over every particle (Algorithm 1, mutation).  loglik_fn
     evaluates one particle of a population; gamma_of(i) is its sounding's temperature;
     factors_of(i) the colouring factor of its model.  Acceptance: u < exp(gamma (ll' - ll))
     (the prior and proposal terms cancel for these moves).  Returns the per-type
-    (proposed, accepted) counts and the accept margins gamma (ll' - ll) - ln u."""
+    (proposed, accepted) counts and the accept margins gamma (ll' - ll) - ln u.
+    indices: the particles to move (default all); each particle's chain depends only on
+    its own state and random counters, so a subset moves exactly as in the full sweep."""
     n = len(ll)
+    which = range(n) if indices is None else list(indices)
     stats = np.zeros((2, N_MOVE_TYPES), dtype=np.int64)
     margins = []
     for r in range(n_moves):
-        for i in range(n):
+        for i in which:
             t, new, ua = propose(p, i, step, r, seed, q, pr, kmax_cond, kmax_charg, factors_of(i))
             stats[0, t] += 1
             if new is None:

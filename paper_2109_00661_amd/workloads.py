@@ -161,6 +161,34 @@ def decoupled_population(n, kmax_cond, kmax_charg, seed=3, min_sep=0.0, kappa=No
     return p
 
 
+def prior_population(n, kmax_cond, kmax_charg, seed=3, n_per_sounding=0):
+    """Decoupled-layout particles from the prior drawn in bulk (vectorised; large
+    batches): kappa ~ U{0..kmax_cond}, lambda ~ U{0..kmax_charg}, sorted U(0, z_max)
+    interfaces in the used rows (zeros beyond), properties from the prior ranges."""
+    rng = np.random.default_rng(seed)
+    P = PRIOR
+    p = empty_particles(n, kmax_cond, kmax_charg)
+    p["n_per_sounding"] = n_per_sounding
+    p["kappa"][:] = rng.integers(0, kmax_cond + 1, n)
+    p["lambda_"][:] = rng.integers(0, kmax_charg + 1, n)
+    p["phi_b"][:] = rng.uniform(P["phi_lo"], P["phi_hi"], n)
+    p["log10_tau"][:] = rng.uniform(P["ltau_lo"], P["ltau_hi"], n)
+    p["c"][:] = rng.uniform(P["c_lo"], P["c_hi"], n)
+    for key, kmax, cnt in (("z_cond", kmax_cond, p["kappa"]), ("z_charg", kmax_charg, p["lambda_"])):
+        if kmax == 0:
+            continue
+        z = rng.uniform(0.0, P["z_max"], (kmax, n))
+        rows = np.arange(kmax)[:, None]
+        z = np.where(rows < cnt[None, :], z, np.inf)
+        z = np.sort(z, axis=0)
+        p[key][:] = np.where(np.isfinite(z), z, 0.0)
+    if kmax_cond:
+        p["phi"][:] = rng.uniform(P["phi_lo"], P["phi_hi"], (kmax_cond, n))
+    if kmax_charg:
+        p["m"][:] = rng.uniform(P["m_lo"], P["m_hi"], (kmax_charg, n))
+    return p
+
+
 def take(p, idx):
     """Sub-population with the particles at positions idx (a copy)."""
     idx = np.asarray(idx)
