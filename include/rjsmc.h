@@ -263,6 +263,33 @@ rjsmc_status rjsmc_mutate(rjsmc_ctx *ctx, const rjsmc_mutate_args *args, rjsmc_p
                           rjsmc_particles *grad_cur, rjsmc_particles *grad_prop, int64_t *stats,
                           rjsmc_stream stream);
 
+/* Posterior summaries of a population (Section 2.3.3 and the case studies), per sounding:
+ *  - model_count[s][k]: particles in model k (pi_T(k | y) = count / N, Section 3.2.1);
+ *  - log_bfipd[s]: log of the grouped Bayes factor of chargeable (lambda >= 1) versus
+ *    conductive-only (lambda = 0) models with the uniform model prior,
+ *      log[(n_charg / |M_charg|) / (n_cond / |M_cond|)]
+ *        = log n_charg - log n_cond - log kmax_charg,
+ *    +inf when no particle is conductive-only, -inf when none is chargeable, NaN for the
+ *    MERGED layout or kmax_charg = 0;
+ *  - at each depth z of depth_m: the model-averaged mean of log10 sigma_inf(z) and of
+ *    m(z), and the fraction of particles with m(z) > 0 (a property applies from its
+ *    interface down, as in the merge).
+ * Output pointers are device memory and may be NULL (that output is skipped).
+ * Sums run over the particles in index order (reproducible). */
+typedef struct {
+  int32_t n_sound;
+  int32_t n_depth;              /* 0 .. 65536 */
+  const double *depth_m;        /* device [n_depth] */
+  int32_t *model_count;         /* device [n_sound][n_models] */
+  double *log_bfipd;            /* device [n_sound] */
+  double *mean_log10_sigma;     /* device [n_sound][n_depth] */
+  double *mean_m;               /* device [n_sound][n_depth] */
+  double *p_chargeable;         /* device [n_sound][n_depth] */
+} rjsmc_summary_args;
+
+rjsmc_status rjsmc_summarize(rjsmc_ctx *ctx, const rjsmc_particles *p, const rjsmc_summary_args *args,
+                             rjsmc_stream stream);
+
 /* *counter += delta on the device, in stream order (one thread).  With step_dev in the
  * argument structs above, a whole SMC step (re-weight/re-sample, adapt, mutate, this
  * increment) can be captured once into a HIP graph and replayed step after step. */

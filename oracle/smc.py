@@ -559,3 +559,51 @@ def toy_rjsmc(toy, N, alpha, seed, n_moves=5, rw_scale=2.38):
                 if math.log(ua) < log_a:
                     k[i], th[i], ll[i] = kn, tn, lln
     return log_z, np.bincount(k, minlength=2)
+
+
+# ------------------------------------------------------------ posterior summaries (O-12)
+def posterior_summary(p, kmax_cond, kmax_charg, n_sound, depths):
+    """Per sounding: model counts, the BFIPD statistic and model-averaged depth profiles.
+
+    BFIPD (Section 2.3.3) is the grouped Bayes factor of chargeable (lambda >= 1) versus
+    conductive-only (lambda = 0) models: the mean over chargeable models of
+    pi_T(k | y) / p(k), divided by the same mean over conductive models, with
+    pi_T(k | y) = N_k / N (Section 3.2.1) and the uniform model prior p(k).  Profiles:
+    at each depth, the mean over particles of log10 sigma_inf(z) and of m(z), and the
+    fraction with m(z) > 0, a property applying from its interface down (Section 2.2).
+    Returns dict(model_count [S][M], log_bfipd [S], mean_log10_sigma, mean_m,
+    p_chargeable [S][n_depth])."""
+    n = len(p["kappa"])
+    N = n // n_sound
+    M = n_models(kmax_cond, kmax_charg)
+    prior_k = np.full(M, 1.0 / M)
+    charg = np.array([k % (kmax_charg + 1) >= 1 for k in range(M)])
+    depths = np.asarray(depths, dtype=np.float64)
+    out = {k: [] for k in ("model_count", "log_bfipd", "mean_log10_sigma", "mean_m", "p_chargeable")}
+    for s in range(n_sound):
+        idx = range(s * N, (s + 1) * N)
+        models = np.array([model_id(int(p["kappa"][i]), int(p["lambda_"][i]), kmax_charg) for i in idx])
+        cnt = np.bincount(models, minlength=M)
+        post = cnt / N
+        ratio = post / prior_k
+        if kmax_charg == 0:
+            lb = np.nan
+        else:
+            num, den = ratio[charg].mean(), ratio[~charg].mean()
+            with np.errstate(divide="ignore"):
+                lb = np.log(num) - np.log(den)
+        phi = np.zeros((N, len(depths)))
+        m = np.zeros((N, len(depths)))
+        for q, i in enumerate(idx):
+            k, l = int(p["kappa"][i]), int(p["lambda_"][i])
+            for d, z in enumerate(depths):
+                ic = sum(1 for r in range(k) if p["z_cond"][r, i] <= z)
+                im = sum(1 for r in range(l) if p["z_charg"][r, i] <= z)
+                phi[q, d] = p["phi_b"][i] if ic == 0 else p["phi"][ic - 1, i]
+                m[q, d] = 0.0 if im == 0 else p["m"][im - 1, i]
+        out["model_count"].append(cnt)
+        out["log_bfipd"].append(lb)
+        out["mean_log10_sigma"].append(phi.mean(axis=0))
+        out["mean_m"].append(m.mean(axis=0))
+        out["p_chargeable"].append((m > 0).mean(axis=0))
+    return {k: np.array(v) for k, v in out.items()}

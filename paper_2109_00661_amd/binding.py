@@ -67,6 +67,12 @@ class MutateArgs(ctypes.Structure):
                 ("factors", ctypes.c_void_p), ("prior", Prior), ("step_dev", ctypes.c_void_p)]
 
 
+class SummaryArgs(ctypes.Structure):
+    _fields_ = [("n_sound", ctypes.c_int32), ("n_depth", ctypes.c_int32), ("depth_m", ctypes.c_void_p),
+                ("model_count", ctypes.c_void_p), ("log_bfipd", ctypes.c_void_p),
+                ("mean_log10_sigma", ctypes.c_void_p), ("mean_m", ctypes.c_void_p), ("p_chargeable", ctypes.c_void_p)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int32), ("layer_sort", ctypes.c_int32),
                 ("waves_per_particle", ctypes.c_int32)]
@@ -110,6 +116,8 @@ _SIGS = {
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Particles),
                                     ctypes.POINTER(Particles), ctypes.c_void_p, ctypes.c_void_p]),
     "rjsmc_counter_add": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "rjsmc_summarize": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.POINTER(SummaryArgs),
+                                       ctypes.c_void_p]),
     "rjsmc_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "rjsmc_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "rjsmc_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p, ctypes.c_void_p,
@@ -233,6 +241,25 @@ class Context:
         K = np.zeros((self.n_gate, self.n_freq))
         _check(lib().rjsmc_time_kernel(self._ptr, _as_dp(K)))
         return K
+
+    def summarize(self, p, n_sound, depth_m=None, stream=None):
+        """Model counts [S][M], log BFIPD [S] and, on the depth grid (device tensor),
+        the model-averaged mean log10 sigma, mean m and P(m > 0) [S][n_depth]."""
+        import torch
+        dev = p["kappa"].device
+        M = (self.kmax_cond + 1) * (self.kmax_charg + 1)
+        nd = 0 if depth_m is None else int(depth_m.numel())
+        out = {"model_count": torch.empty((n_sound, M), dtype=torch.int32, device=dev),
+               "log_bfipd": torch.empty(n_sound, dtype=torch.float64, device=dev),
+               "mean_log10_sigma": torch.empty((n_sound, nd), dtype=torch.float64, device=dev),
+               "mean_m": torch.empty((n_sound, nd), dtype=torch.float64, device=dev),
+               "p_chargeable": torch.empty((n_sound, nd), dtype=torch.float64, device=dev)}
+        a = SummaryArgs(n_sound, nd, _ptr(depth_m) if nd else None, _ptr(out["model_count"]), _ptr(out["log_bfipd"]),
+                        _ptr(out["mean_log10_sigma"]) if nd else None, _ptr(out["mean_m"]) if nd else None,
+                        _ptr(out["p_chargeable"]) if nd else None)
+        ps = particles_struct(p)
+        _check(lib().rjsmc_summarize(self._ptr, ctypes.byref(ps), ctypes.byref(a), _stream_handle(stream)))
+        return out
 
     def counter_add(self, counter, delta=1, stream=None):
         _check(lib().rjsmc_counter_add(self._ptr, _ptr(counter), int(delta), _stream_handle(stream)))

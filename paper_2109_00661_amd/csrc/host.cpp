@@ -731,3 +731,19 @@ extern "C" rjsmc_status rjsmc_counter_add(rjsmc_ctx *c, int32_t *counter, int32_
   if (e != hipSuccess) return hip_fail(e, "rjsmc_counter_add: launch");
   return RJSMC_OK;
 }
+
+extern "C" rjsmc_status rjsmc_summarize(rjsmc_ctx *c, const rjsmc_particles *p, const rjsmc_summary_args *a,
+                                        rjsmc_stream stream) {
+  const char *who = "rjsmc_summarize";
+  if (!c || !a) return fail(RJSMC_E_INVALID, "%s: NULL argument", who);
+  rjsmc::DevParticles dp;
+  rjsmc_status st = check_particles(c, p, who, &dp);
+  if (st != RJSMC_OK) return st;
+  if ((st = check_soundings(p, a->n_sound, who)) != RJSMC_OK) return st;
+  if (a->n_depth < 0 || a->n_depth > 65536) return fail(RJSMC_E_INVALID, "%s: n_depth=%d outside 0..65536", who, a->n_depth);
+  if (a->n_depth > 0 && !a->depth_m) return fail(RJSMC_E_INVALID, "%s: NULL depth grid", who);
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = rjsmc::launch_summary(smc_shape(c), dp, *a, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "rjsmc_summarize: launch");
+  return RJSMC_OK;
+}

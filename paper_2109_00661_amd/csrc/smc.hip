@@ -904,4 +904,77 @@ hipError_t launch_accept(const SmcShape &sh, const rjsmc_mutate_args &a, int mov
   return hipGetLastError();
 }
 
+// -------------------------------------------------------------- posterior summaries ---
+// Grid (sounding, item block): item j < M counts the particles of model j; item M the
+// chargeable-versus-conductive Bayes factor; items M + 1 + d the depth profiles at
+// depth d.  Each item walks the sounding's particles in index order (deterministic sums).
+__global__ __launch_bounds__(256) void summary_kernel(SmcShape sh, DevParticles p, rjsmc_summary_args a) {
+  const int s = blockIdx.x;
+  const int j = blockIdx.y * blockDim.x + threadIdx.x;
+  const int M = sh.n_models;
+  if (j >= M + 1 + a.n_depth) return;
+  const int64_t N = p.n_per_sounding > 0 ? p.n_per_sounding : p.n;
+  const int64_t off = (int64_t)s * N, S = p.stride;
+  const bool dec = p.layout == RJSMC_LAYOUT_DECOUPLED;
+  if (j < M) {
+    if (!a.model_count) return;
+    int cnt = 0;
+    for (int64_t q = 0; q < N; ++q) {
+      const int64_t i = off + q;
+      const int lam = dec ? p.lambda[i] : 0;
+      cnt += p.kappa[i] * (sh.km + 1) + lam == j;
+    }
+    a.model_count[(int64_t)s * M + j] = cnt;
+    return;
+  }
+  if (j == M) {
+    if (!a.log_bfipd) return;
+    if (!dec || sh.km == 0) {
+      a.log_bfipd[s] = __builtin_nan("");
+      return;
+    }
+    int64_t non = 0;
+    for (int64_t q = 0; q < N; ++q) non += p.lambda[off + q] == 0;
+    // (mean posterior-to-prior ratio over chargeable models) / (the same over conductive
+    // models), uniform model prior: (n_charg / n_cond) |M_cond| / |M_charg|, with
+    // |M_cond| = kmax_cond + 1 and |M_charg| = (kmax_cond + 1) kmax_charg
+    a.log_bfipd[s] = log((double)(N - non)) - log((double)non) - log((double)sh.km);
+    return;
+  }
+  const int d = j - M - 1;
+  const double z = a.depth_m[d];
+  double sphi = 0.0, sm = 0.0;
+  int64_t npos = 0;
+  for (int64_t q = 0; q < N; ++q) {
+    const int64_t i = off + q;
+    const int kap = p.kappa[i];
+    int ic = 0;
+    for (int r = 0; r < kap; ++r) ic += p.z_cond[r * S + i] <= z;
+    const double phi = ic == 0 ? p.phi_b[i] : p.phi[(int64_t)(ic - 1) * S + i];
+    double m;
+    if (dec) {
+      const int lam = p.lambda[i];
+      int im = 0;
+      for (int r = 0; r < lam; ++r) im += p.z_charg[r * S + i] <= z;
+      m = im == 0 ? 0.0 : p.m[(int64_t)(im - 1) * S + i];
+    } else {
+      m = p.m[(int64_t)ic * S + i];
+    }
+    sphi += phi;
+    sm += m;
+    npos += m > 0.0;
+  }
+  const int64_t o = (int64_t)s * a.n_depth + d;
+  if (a.mean_log10_sigma) a.mean_log10_sigma[o] = sphi / (double)N;
+  if (a.mean_m) a.mean_m[o] = sm / (double)N;
+  if (a.p_chargeable) a.p_chargeable[o] = (double)npos / (double)N;
+}
+
+hipError_t launch_summary(const SmcShape &sh, const DevParticles &p, const rjsmc_summary_args &a, hipStream_t stream) {
+  const int items = sh.n_models + 1 + a.n_depth;
+  hipLaunchKernelGGL(summary_kernel, dim3((unsigned)a.n_sound, (unsigned)((items + 255) / 256)), dim3(256), 0, stream,
+                     sh, p, a);
+  return hipGetLastError();
+}
+
 }  // namespace rjsmc

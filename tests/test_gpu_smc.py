@@ -308,3 +308,23 @@ def test_graph_replay_matches_eager(B, truth_data, moves):
     assert int(graphed.step_dev.item()) == graphed.step + 1
     eager.ctx.check()
     graphed.ctx.check()
+
+
+def test_posterior_summary_against_oracle(B, ctx):
+    """Model counts (exact), log BFIPD and the depth profiles of three soundings."""
+    from oracle import smc
+    S, nps = 3, 400
+    p = W.prior_population(S * nps, KC, KM, seed=44, n_per_sounding=nps)
+    p["lambda_"][nps:2 * nps] = 0                 # a sounding with no chargeable particle
+    p["lambda_"][2 * nps:] = np.maximum(p["lambda_"][2 * nps:], 1)
+    p["lambda_"][2 * nps:2 * nps + 5] = 0         # and one that is almost all chargeable
+    depths = np.concatenate([np.linspace(0.0, 300.0, 61), [1000.0]])
+    ref = smc.posterior_summary(p, KC, KM, S, depths)
+    out = ctx.summarize(B.particles_to_device(p), S, torch.as_tensor(depths, device="cuda"))
+    ctx.check()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    assert np.array_equal(got["model_count"], ref["model_count"])
+    assert got["log_bfipd"][1] == -np.inf
+    np.testing.assert_allclose(got["log_bfipd"], ref["log_bfipd"], rtol=1e-13, atol=0)
+    for k in ("mean_log10_sigma", "mean_m", "p_chargeable"):
+        np.testing.assert_allclose(got[k], ref[k], rtol=1e-12, atol=1e-14, err_msg=k)

@@ -219,3 +219,57 @@ def test_mala_preserves_the_prior_at_zero_temperature():
     assert stats.kstest((phs - PR["phi_lo"]) / (PR["phi_hi"] - PR["phi_lo"]), "uniform").pvalue > 1e-3
     cs = (p["c"] - PR["c_lo"]) / (PR["c_hi"] - PR["c_lo"])
     assert stats.kstest(cs, "uniform").pvalue > 1e-3
+
+
+# ----------------------------------------------------------------- posterior summaries
+def _population(counts_kl, kc=4, km=3, seed=0):
+    """Decoupled population with the given (kappa, lambda) per particle."""
+    from paper_2109_00661_amd import workloads as W
+    n = len(counts_kl)
+    p = W.prior_population(n, kc, km, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    for i, (k, l) in enumerate(counts_kl):
+        p["kappa"][i], p["lambda_"][i] = k, l
+        p["z_cond"][:, i] = np.concatenate([np.sort(rng.uniform(0, 300, k)), np.zeros(kc - k)])
+        p["z_charg"][:, i] = np.concatenate([np.sort(rng.uniform(0, 300, l)), np.zeros(km - l)])
+    return p
+
+
+def test_bfipd_is_one_when_the_posterior_equals_the_prior():
+    """Every model equally populated: posterior model probabilities equal the uniform
+    prior, so the Bayes factor of any grouping is 1."""
+    kl = [(k, l) for k in range(5) for l in range(4)] * 3
+    out = smc.posterior_summary(_population(kl), 4, 3, 1, [])
+    assert out["model_count"][0].tolist() == [3] * 20
+    assert abs(out["log_bfipd"][0]) < 1e-14
+
+
+def test_bfipd_limits_and_posterior_odds():
+    kl = [(1, 2)] * 10
+    assert smc.posterior_summary(_population(kl), 4, 3, 1, [])["log_bfipd"][0] == np.inf
+    kl = [(3, 0)] * 10
+    assert smc.posterior_summary(_population(kl), 4, 3, 1, [])["log_bfipd"][0] == -np.inf
+    # a Bayes factor is posterior odds over prior odds; prior odds of chargeability = 15:5
+    rng = np.random.default_rng(4)
+    kl = list(zip(rng.integers(0, 5, 300), rng.integers(0, 4, 300)))
+    out = smc.posterior_summary(_population(kl), 4, 3, 1, [])
+    pc = np.mean([l >= 1 for _, l in kl])
+    assert abs(out["log_bfipd"][0] - (np.log(pc / (1 - pc)) - np.log(15 / 5))) < 1e-12
+
+
+def test_profiles_match_the_merged_stack():
+    """Depth profiles from interface counting equal the merged layer stack of the forward
+    model (layer tops from cumulative thicknesses), particle by particle."""
+    from oracle import em
+    rng = np.random.default_rng(9)
+    kl = list(zip(rng.integers(0, 5, 40), rng.integers(0, 4, 40)))
+    p = _population(kl, seed=9)
+    depths = np.linspace(0.5, 299.5, 37)
+    out = smc.posterior_summary(p, 4, 3, 40, depths)      # one particle per sounding
+    for i in range(40):
+        sig, ms, thick = em.merged_stack(p, i)
+        tops = np.concatenate([[0.0], np.cumsum(thick)])
+        layer = np.searchsorted(tops, depths, side="right") - 1
+        np.testing.assert_allclose(out["mean_log10_sigma"][i], np.log10(np.array(sig))[layer], rtol=0, atol=1e-12)
+        np.testing.assert_array_equal(out["mean_m"][i], np.array(ms)[layer])
+        np.testing.assert_array_equal(out["p_chargeable"][i], (np.array(ms)[layer] > 0).astype(float))
