@@ -169,6 +169,64 @@ def rjsmc_rate(torch, d, n_sound, n_per_sound, seed=0, move_prob=None, graph=Fal
     return out
 
 
+def survey_run(torch, precision, move_prob, n_per_sound=2048, seed=0):
+    """Complete RJSMC runs over the synthetic survey (2,000 soundings on 10 lines): wall
+    clock, and how well the per-sounding log BFIPD separates the stations above the
+    chargeable body (should be > 0) from the others (< 0)."""
+    from paper_2109_00661_amd import binding as B
+    from paper_2109_00661_amd.rjsmc import RJSMCRun
+    truth, body, _, _ = W.survey()
+    S = len(body)
+    system = W.system()
+    ref = B.Context(system, precision="f64")
+    y_true = ref.forward(B.particles_to_device(truth)).cpu().numpy()
+    ref.check()
+    sd = np.sqrt(system["eps_an"][None, :] ** 2 + (system["eps_mn"] * y_true) ** 2)
+    noise = np.stack([np.random.default_rng(5000 + i).standard_normal(y_true.shape[1]) for i in range(S)])
+    y = y_true + sd * noise
+    ctx = B.Context(system, precision=precision, max_particles=S * n_per_sound)
+    run = RJSMCRun(ctx, S, n_per_sound, y, seed=seed, move_prob=move_prob, graph=True)
+    run.initialise()
+    tuned, _ = ctx.autotune(run.state, run.y_obs, reps=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run.run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    summ = ctx.summarize(run.state, S)
+    lb = summ["log_bfipd"].cpu().numpy()
+    lz = run.log_z.cpu().numpy()
+    km = ctx.kmax_charg
+    true_model = truth["kappa"] * (km + 1) + truth["lambda_"]
+    lz_true = lz[np.arange(S), true_model]
+    st = run.stats.cpu().numpy()
+    return {"precision": precision, "soundings": S, "particles_per_sounding": n_per_sound,
+            "soundings_per_s": S / dt, "seconds": dt, "steps": run.step, "tuning": tuned,
+            "acceptance": float(st[1].sum() / max(st[0].sum(), 1)),
+            "detect_true_positive": float(np.mean(lb[body] > 0)),
+            "detect_true_negative": float(np.mean(lb[~body] < 0)),
+            "log_bfipd_median_body": float(np.median(lb[body])),
+            "log_bfipd_median_outside": float(np.median(lb[~body])),
+            "log_z_true_model_finite": int(np.isfinite(lz_true).sum()),
+            "_log_bfipd": lb, "_log_z_true": lz_true}
+
+
+def survey(torch):
+    from paper_2109_00661_amd.rjsmc import UNIFORM_MOVES, LANGEVIN_MOVES
+    runs = {"fp64_rw": survey_run(torch, "f64", UNIFORM_MOVES),
+            "fp32_forward_rw": survey_run(torch, "f32", UNIFORM_MOVES),
+            "fp64_langevin": survey_run(torch, "f64", LANGEVIN_MOVES)}
+    a, b = runs["fp64_rw"]["_log_bfipd"], runs["fp32_forward_rw"]["_log_bfipd"]
+    fin = np.isfinite(a) & np.isfinite(b)
+    za, zb = runs["fp64_rw"]["_log_z_true"], runs["fp32_forward_rw"]["_log_z_true"]
+    zf = np.isfinite(za) & np.isfinite(zb)
+    out = {k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")} for k, v in runs.items()}
+    out["fp32_vs_fp64"] = {"bfipd_sign_agreement": float(np.mean(np.sign(a) == np.sign(b))),
+                           "log_bfipd_median_abs_diff": float(np.median(np.abs(a[fin] - b[fin]))) if fin.any() else None,
+                           "log_z_true_median_abs_diff": float(np.median(np.abs(za[zf] - zb[zf]))) if zf.any() else None}
+    return out
+
+
 def adjoint_rate(torch, d, steps, warmup):
     """Log-likelihood + gradient evaluations per second for 65,536 decoupled particles
     with 1-8 segments per partition (merged layers up to 15)."""
@@ -206,6 +264,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extra", action="store_true")
+    ap.add_argument("--survey", action="store_true",
+                    help="also run the 2,000-sounding synthetic survey (FP64, FP32-forward, Langevin; minutes)")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the 65,536-particle forward+loglik launches (for profiling)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -270,6 +330,8 @@ def main():
                                                           tune=True),
                     "uneven_512x1024_rw": rjsmc_rate(torch, d, 512, 1024, graph=True, kmax=(7, 4), noise=True,
                                                      tune=True)}
+    if args.survey:
+        out["survey"] = survey(torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(system, d.cpu().numpy())
     print(json.dumps(out), flush=True)

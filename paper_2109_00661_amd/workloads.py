@@ -189,6 +189,44 @@ def prior_population(n, kmax_cond, kmax_charg, seed=3, n_per_sounding=0):
     return p
 
 
+def survey(n_lines=10, n_stations=200, station_m=25.0, line_m=100.0):
+    """Synthetic airborne survey standing in for a flight-line dataset: n_lines parallel
+    lines of n_stations soundings.  Every station's truth is a three-layer model with
+    smoothly varying conductivities and interface depths; an elliptical chargeable body
+    (about 40% of the stations of the default grid) makes the second layer chargeable with
+    m up to 0.6 (tapering to the body's edge), tau from 1e-4 s to 1e-2 s across it and
+    c = 0.5.  Returns (truth particles in the decoupled layout with capacities
+    kmax_cond = 4, kmax_charg = 3, body mask [S], x [S], y [S])."""
+    x = np.tile(np.arange(n_stations) * station_m, n_lines)
+    y = np.repeat(np.arange(n_lines) * line_m, n_stations)
+    S = n_lines * n_stations
+    xs, ys = x.max() if S > 1 else 1.0, y.max() if n_lines > 1 else 1.0
+    two_pi = 2.0 * np.pi
+    phi1 = -2.0 + 0.3 * np.sin(two_pi * x / 2000.0) + 0.2 * np.cos(two_pi * y / 700.0)
+    phi2 = -1.0 + 0.3 * np.cos(two_pi * x / 1300.0)
+    phi3 = -2.5 + 0.3 * np.sin(two_pi * y / 900.0)
+    z1 = 20.0 + 10.0 * np.sin(two_pi * (x + y) / 1500.0)
+    z2 = z1 + 20.0
+    cx, cy = 0.5 * xs, 0.5 * ys
+    ax, ay = 0.30 * xs, 0.50 * max(ys, 1.0)
+    r2 = ((x - cx) / ax) ** 2 + ((y - cy) / ay) ** 2
+    body = r2 < 1.0
+    p = empty_particles(S, PRIOR["kmax_cond"], PRIOR["kmax_charg"])
+    p["kappa"][:] = 2
+    p["phi_b"][:] = phi1
+    p["phi"][0] = phi2
+    p["phi"][1] = phi3
+    p["z_cond"][0] = z1
+    p["z_cond"][1] = z2
+    p["lambda_"][:] = np.where(body, 2, 0)
+    p["z_charg"][0] = np.where(body, z1, 0.0)
+    p["z_charg"][1] = np.where(body, z2, 0.0)
+    p["m"][0] = np.where(body, 0.6 * np.sqrt(np.clip(1.0 - r2, 0.0, 1.0)), 0.0)
+    p["log10_tau"][:] = -4.0 + 2.0 * np.clip((x - (cx - ax)) / (2.0 * ax), 0.0, 1.0)
+    p["c"][:] = 0.5
+    return p, body, x, y
+
+
 def take(p, idx):
     """Sub-population with the particles at positions idx (a copy)."""
     idx = np.asarray(idx)
