@@ -511,10 +511,26 @@ class NestedLinearGaussian:
                 + 0.5 * bvec @ np.linalg.solve(A, bvec) - 0.5 * logdetA - 0.5 * d * math.log(self.v))
 
 
-def toy_rjsmc(toy, N, alpha, seed, n_moves=5, rw_scale=2.38):
+def mutation_count(acceptance, c, r_max):
+    """Number of mutation sweeps for the next step (Section 3.2.4, after Drovandi and
+    Pettitt): with p_min the smallest acceptance rate over the proposal types,
+    R = ceil(log c / log(1 - p_min)), so that every particle moves with probability at
+    least 1 - c under the least-accepted proposal; at least 1, at most r_max (also when
+    p_min = 0)."""
+    p_min = min(acceptance)
+    if p_min <= 0.0:
+        return r_max
+    if p_min >= 1.0:
+        return 1
+    return int(min(max(math.ceil(math.log(c) / math.log(1.0 - p_min)), 1), r_max))
+
+
+def toy_rjsmc(toy, N, alpha, seed, n_moves=5, rw_scale=2.38, adapt_c=None, r_max=100):
     """Algorithm 1 on the toy with the oracle's reweight/resample primitives; RJ birth /
     death between M1 and M2 draws b from its prior, within-model moves are Gaussian
-    random walks scaled by the model's particle spread.  Returns (log Z [2], counts)."""
+    random walks scaled by the model's particle spread.  adapt_c: the number of sweeps of
+    each step follows the previous step's acceptance rates (mutation_count), starting
+    from n_moves.  Returns (log Z [2], counts)."""
     rng_key = seed
     k = np.zeros(N, dtype=np.int64)
     th = np.zeros((N, 2))
@@ -535,6 +551,7 @@ def toy_rjsmc(toy, N, alpha, seed, n_moves=5, rw_scale=2.38):
         anc = systematic_within_model(W, k, range(2), U)
         k, th, ll = k[anc], th[anc], ll[anc]
         sd = [np.std(th[k == m], axis=0) + 1e-3 for m in range(2)]
+        tried, taken = np.zeros(2), np.zeros(2)
         for r in range(n_moves):
             for i in range(N):
                 u0, ua = uniform_pair(seed, i, step, r, 0)
@@ -556,8 +573,13 @@ def toy_rjsmc(toy, N, alpha, seed, n_moves=5, rw_scale=2.38):
                     log_a = gamma * (lln - ll[i]) + lp(tn, kn) - lp(th[i], k[i])
                 else:
                     log_a = gamma * (lln - ll[i])              # prior-draw birth: prior terms cancel
+                kind = 0 if u0 < 0.5 else 1
+                tried[kind] += 1
                 if math.log(ua) < log_a:
                     k[i], th[i], ll[i] = kn, tn, lln
+                    taken[kind] += 1
+        if adapt_c is not None:
+            n_moves = mutation_count([taken[j] / tried[j] for j in range(2) if tried[j] > 0], adapt_c, r_max)
     return log_z, np.bincount(k, minlength=2)
 
 

@@ -14,6 +14,17 @@ UNIFORM_MOVES = (1, 1, 1, 1, 1, 1, 1, 0)     # birth/death/move x2 partitions + 
 LANGEVIN_MOVES = (1, 1, 1, 1, 1, 1, 0, 1)    # the within-model move is the gradient-informed one
 
 
+def mutation_count(rates, c, r_max):
+    """Sweeps for the next step from the last step's acceptance rates per move type
+    (Section 3.2.4): the least R with (1 - p_min)^R <= c, clamped to 1 .. r_max."""
+    p = min(rates)
+    if p <= 0.0:
+        return int(r_max)
+    if p >= 1.0:
+        return 1
+    return int(min(max(np.ceil(np.log(c) / np.log1p(-p)), 1), r_max))
+
+
 class RJSMCRun:
     """One RJSMC run over n_sound soundings of n_per_sound particles each.
 
@@ -23,7 +34,7 @@ class RJSMCRun:
 
     def __init__(self, ctx, n_sound, n_per_sound, y_obs, *, prior=None, alpha=0.5, n_moves=5, seed=0,
                  move_prob=UNIFORM_MOVES, z_move_frac=0.05, rw_scale=2.38, mala_eps=0.8, device="cuda",
-                 graph=False):
+                 graph=False, adapt_c=None, r_max=100):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -53,6 +64,9 @@ class RJSMCRun:
         if move_prob[B.N_MOVES - 1] > 0:
             self.grads = [B.empty_device_population(self.n, kc, km, nps, device) for _ in range(2)]
         self.step = 0
+        self.adapt_c, self.r_max = adapt_c, r_max
+        self.moves_per_step = []
+        self._stats_prev = None
         self.use_graph = graph
         self.graphs = None
         self.step_dev = None
@@ -87,36 +101,49 @@ class RJSMCRun:
         if step_dev is not None:
             self.ctx.counter_add(step_dev, 1)
 
-    def _capture(self):
-        """Captures the step from each buffer into a graph; the device counter holds the
-        step the next replay runs."""
+    def _capture(self, start):
+        """Captures the step from buffer `start` with the current number of sweeps into a
+        graph; the device counter holds the step that a replay runs."""
         torch = self.torch
-        self.step_dev = torch.full((1,), self.step + 1, dtype=torch.int32, device=self.gamma.device)
+        if self.step_dev is None:
+            self.step_dev = torch.full((1,), self.step + 1, dtype=torch.int32, device=self.gamma.device)
+            self.graphs = {}
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         cur0 = self.cur
-        self.graphs = {}
-        for start in (cur0, 1 - cur0):
-            self.cur = start
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=side):
-                self._launch_step(self.step_dev)
-            self.graphs[start] = g
+        self.cur = start
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            self._launch_step(self.step_dev)
+        self.graphs[(start, self.n_moves)] = g
         self.cur = cur0
         torch.cuda.current_stream().wait_stream(side)
+
+    def _adapt_sweeps(self):
+        """Next step's number of sweeps from this step's acceptance rates."""
+        st = self.stats.cpu().numpy()
+        prev = self._stats_prev if self._stats_prev is not None else np.zeros_like(st)
+        self._stats_prev = st
+        tried, taken = st[0] - prev[0], st[1] - prev[1]
+        rates = [taken[t] / tried[t] for t in range(B.N_MOVES) if self.move_prob[t] > 0 and tried[t] > 0]
+        if rates:
+            self.n_moves = mutation_count(rates, self.adapt_c, self.r_max)
 
     def advance(self):
         """One iteration of the while-loop of Algorithm 1."""
         self.step += 1
+        self.moves_per_step.append(self.n_moves)
         if not self.use_graph:
             self._launch_step()
-            return
-        if self.graphs is None:
-            self.step -= 1
-            self._capture()
-            self.step += 1
-        self.graphs[self.cur].replay()
-        self.cur = 1 - self.cur
+        else:
+            if self.graphs is None or (self.cur, self.n_moves) not in self.graphs:
+                self.step -= 1
+                self._capture(self.cur)
+                self.step += 1
+            self.graphs[(self.cur, self.n_moves)].replay()
+            self.cur = 1 - self.cur
+        if self.adapt_c is not None:
+            self._adapt_sweeps()
 
     def run(self, max_steps=1000):
         self.initialise()

@@ -328,3 +328,30 @@ def test_posterior_summary_against_oracle(B, ctx):
     np.testing.assert_allclose(got["log_bfipd"], ref["log_bfipd"], rtol=1e-13, atol=0)
     for k in ("mean_log10_sigma", "mean_m", "p_chargeable"):
         np.testing.assert_allclose(got[k], ref[k], rtol=1e-12, atol=1e-14, err_msg=k)
+
+
+def test_adaptive_sweeps_graph_and_eager(B, truth_data):
+    """Adaptive R_t: each step's sweep count follows the previous step's acceptance
+    rates, and graph replay (one graph per sweep count) matches the eager calls."""
+    from paper_2109_00661_amd.rjsmc import RJSMCRun, mutation_count
+    y = np.tile(truth_data, (2, 1))
+    runs = []
+    for graph in (False, True):
+        ctx = B.Context(W.system(), precision="f64", max_particles=512)
+        run = RJSMCRun(ctx, 2, 256, y, seed=13, n_moves=2, graph=graph, adapt_c=0.2, r_max=12)
+        run.initialise()
+        prev = np.zeros((2, 8), dtype=np.int64)
+        for _ in range(5):
+            run.advance()
+            st = run.stats.cpu().numpy()
+            rates = [(st[1, t] - prev[1, t]) / (st[0, t] - prev[0, t]) for t in range(8)
+                     if run.move_prob[t] > 0 and st[0, t] > prev[0, t]]
+            assert run.n_moves == mutation_count(rates, 0.2, 12)
+            prev = st
+        ctx.check()
+        runs.append(run)
+    a, b = runs
+    assert a.moves_per_step == b.moves_per_step and len(set(a.moves_per_step)) > 1
+    assert np.array_equal(a.ll.cpu().numpy(), b.ll.cpu().numpy())
+    assert np.array_equal(a.log_z.cpu().numpy(), b.log_z.cpu().numpy())
+    assert np.array_equal(a.stats.cpu().numpy(), b.stats.cpu().numpy())

@@ -273,3 +273,46 @@ def test_profiles_match_the_merged_stack():
         np.testing.assert_allclose(out["mean_log10_sigma"][i], np.log10(np.array(sig))[layer], rtol=0, atol=1e-12)
         np.testing.assert_array_equal(out["mean_m"][i], np.array(ms)[layer])
         np.testing.assert_array_equal(out["p_chargeable"][i], (np.array(ms)[layer] > 0).astype(float))
+
+
+# ------------------------------------------------------------- adaptive mutation count
+def test_mutation_count_is_the_smallest_sufficient_count():
+    """R is the smallest number of sweeps with (1 - p_min)^R <= c (brute force)."""
+    rng = np.random.default_rng(12)
+    for _ in range(2000):
+        acc = rng.uniform(0.001, 0.999, rng.integers(1, 6)).tolist()
+        c = 10 ** rng.uniform(-4, -0.5)
+        p = min(acc)
+        R = 1
+        while (1 - p) ** R > c:
+            R += 1
+        assert smc.mutation_count(acc, c, 10 ** 6) == R
+    assert smc.mutation_count([0.5, 0.0], 0.01, 77) == 77
+    assert smc.mutation_count([1.0], 0.01, 77) == 1
+    assert smc.mutation_count([1e-6], 0.01, 50) == 50
+    assert smc.mutation_count([0.5], 0.01, 100) == 7                 # 0.5^7 < 0.01 < 0.5^6
+
+
+@pytest.mark.slow
+def test_conjugate_evidence_with_adaptive_mutation_count():
+    """Adapting R from the acceptance rates keeps the evidence estimate unbiased."""
+    rng = np.random.default_rng(3)
+    x = np.linspace(-1, 1, 8)
+    y = 0.8 * x + 0.3 * x ** 2 + rng.normal(0, 0.3, 8)
+    toy = smc.NestedLinearGaussian(x, y, 0.09, 1.0)
+    exact = np.array([toy.log_evidence(0), toy.log_evidence(1)])
+    lzs = np.array([smc.toy_rjsmc(toy, 300, 0.5, seed, n_moves=3, adapt_c=0.05, r_max=20)[0] for seed in range(16)])
+    ratio = np.exp(lzs - exact[None, :])
+    se = ratio.std(axis=0, ddof=1) / math.sqrt(len(ratio))
+    assert np.all(np.abs(ratio.mean(axis=0) - 1) <= 3 * se + 0.02), (ratio.mean(axis=0), se)
+
+
+def test_driver_mutation_count_matches_the_oracle():
+    from paper_2109_00661_amd.rjsmc import mutation_count
+    rng = np.random.default_rng(13)
+    for _ in range(2000):
+        acc = rng.uniform(0.0, 1.0, rng.integers(1, 8)).tolist()
+        if rng.uniform() < 0.05:
+            acc.append(0.0)
+        c, r_max = 10 ** rng.uniform(-4, -0.3), int(rng.integers(1, 300))
+        assert mutation_count(acc, c, r_max) == smc.mutation_count(acc, c, r_max)
