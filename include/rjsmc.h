@@ -238,6 +238,13 @@ typedef struct {
   const double *factors;        /* device, as written by rjsmc_adapt */
   rjsmc_prior prior;
   const int32_t *step_dev;      /* device, may be NULL: when set, t is read from *step_dev */
+  const double *rw_scale_dev;   /* device [n_sound], may be NULL: per-sounding within-model
+                                   step (overrides rw_scale) */
+  int64_t *stats_sound;         /* device [n_sound][2], may be NULL: within-model random-walk
+                                   proposals / acceptances per sounding (accumulated) */
+  int32_t trial;                /* 0: the sweeps of Algorithm 1.  b >= 1: trial proposals
+                                   (Section 3.2.3) decided and counted but never kept, with
+                                   random-number move index b * 2^20 + r */
 } rjsmc_mutate_args;
 
 /* n_moves RJ-MCMC sweeps (Algorithm 1, mutation) targeting L^gamma(sounding) x prior.
@@ -289,6 +296,25 @@ typedef struct {
 
 rjsmc_status rjsmc_summarize(rjsmc_ctx *ctx, const rjsmc_particles *p, const rjsmc_summary_args *args,
                              rjsmc_stream stream);
+
+/* One bisection step per sounding on log(scale) of the within-model random walk, from
+ * trial proposals at the bracket's midpoint (Section 3.2.3: the step is scaled to reach a
+ * target acceptance rate).  init = 1 starts the bracket [log lo0, log hi0]; otherwise a
+ * sounding whose trials were accepted at a rate above `target` raises the lower end to
+ * the midpoint, else lowers the upper end (no trials: unchanged).  Then scale =
+ * exp(midpoint) and stats_sound is zeroed for the next trials.  Device arrays; no host
+ * synchronisation, so it can sit inside a captured step. */
+typedef struct {
+  int32_t n_sound;
+  int32_t init;
+  double target;
+  double lo0, hi0;              /* initial bracket of the scale, 0 < lo0 < hi0 */
+  double *log_lo, *log_hi;      /* device [n_sound] */
+  double *scale;                /* device [n_sound] */
+  int64_t *stats_sound;         /* device [n_sound][2] */
+} rjsmc_bisect_args;
+
+rjsmc_status rjsmc_scale_bisect(rjsmc_ctx *ctx, const rjsmc_bisect_args *args, rjsmc_stream stream);
 
 /* *counter += delta on the device, in stream order (one thread).  With step_dev in the
  * argument structs above, a whole SMC step (re-weight/re-sample, adapt, mutate, this

@@ -386,7 +386,8 @@ def propose(p, i, step, move, seed, q, pr, kmax_cond, kmax_charg, factor):
         theta = param_vector(p, i)
         d = len(theta)
         r = min(int(u1 * d), d - 1)
-        theta = theta + q["rw_scale"] * normal_pair(u2, u3)[0] * factor[:, r]
+        scale = q["rw_scale"](i) if callable(q["rw_scale"]) else q["rw_scale"]
+        theta = theta + scale * normal_pair(u2, u3)[0] * factor[:, r]
         if in_support(theta, k, l, pr):
             new = dict(theta=theta)
     return t, new, ua
@@ -435,22 +436,29 @@ def copy_particle(p, i):
     return {k: (v[..., i].copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
 
 
+TRIAL_STRIDE = 1 << 20      # random-number move index of trial sweep b: b * TRIAL_STRIDE + r
+
+
 def mutate(p, ll, loglik_fn, gamma_of, step, seed, q, pr, kmax_cond, kmax_charg, factors_of, n_moves,
-           grad_fn=None, indices=None):
+           grad_fn=None, indices=None, trial=0):
     """n_moves RJ-MCMC sweeps over every particle (Algorithm 1, mutation).  loglik_fn
     evaluates one particle of a population; gamma_of(i) is its sounding's temperature;
     factors_of(i) the colouring factor of its model.  Acceptance: u < exp(gamma (ll' - ll))
     (the prior and proposal terms cancel for these moves).  Returns the per-type
     (proposed, accepted) counts and the accept margins gamma (ll' - ll) - ln u.
     indices: the particles to move (default all); each particle's chain depends only on
-    its own state and random counters, so a subset moves exactly as in the full sweep."""
+    its own state and random counters, so a subset moves exactly as in the full sweep.
+    q["rw_scale"] may be a function of the particle index.  trial = b >= 1: trial
+    proposals (Section 3.2.3) that draw from their own counters (move index
+    b * TRIAL_STRIDE + r) and are decided but never kept."""
     n = len(ll)
     which = range(n) if indices is None else list(indices)
     stats = np.zeros((2, N_MOVE_TYPES), dtype=np.int64)
     margins = []
     for r in range(n_moves):
+        mv = trial * TRIAL_STRIDE + r
         for i in which:
-            t, new, ua = propose(p, i, step, r, seed, q, pr, kmax_cond, kmax_charg, factors_of(i))
+            t, new, ua = propose(p, i, step, mv, seed, q, pr, kmax_cond, kmax_charg, factors_of(i))
             stats[0, t] += 1
             if new is None:
                 margins.append((i, r, np.inf))
@@ -462,7 +470,7 @@ def mutate(p, ll, loglik_fn, gamma_of, step, seed, q, pr, kmax_cond, kmax_charg,
                 F = factors_of(i)
                 theta = param_vector(p, i)
                 _, g0 = grad_fn(p, i)
-                xi = mala_normals(seed, i, step, r, len(theta))
+                xi = mala_normals(seed, i, step, mv, len(theta))
                 th_new = mala_propose(theta, g0, gamma_of(i), F, q["mala_eps"], xi)
                 if not in_support(th_new, k_, l_, pr):
                     margins.append((i, r, np.inf))
@@ -475,7 +483,12 @@ def mutate(p, ll, loglik_fn, gamma_of, step, seed, q, pr, kmax_cond, kmax_charg,
                 ll_new = loglik_fn(p, i)
             margin = gamma_of(i) * (ll_new - ll[i]) + extra - math.log(ua)
             margins.append((i, r, margin))
-            if margin > 0.0:
+            if margin > 0.0 and trial > 0:
+                stats[1, t] += 1
+                for key, v in saved.items():
+                    if isinstance(p[key], np.ndarray):
+                        p[key][..., i] = v
+            elif margin > 0.0:
                 ll[i] = ll_new
                 stats[1, t] += 1
             else:
@@ -509,6 +522,19 @@ class NestedLinearGaussian:
         _, logdetA = np.linalg.slogdet(A)
         return (-0.5 * g * n * math.log(2 * math.pi * self.s2) - 0.5 * g * (self.y @ self.y) / self.s2
                 + 0.5 * bvec @ np.linalg.solve(A, bvec) - 0.5 * logdetA - 0.5 * d * math.log(self.v))
+
+
+def scale_bisection(log_lo, log_hi, tried, accepted, target):
+    """One bisection step on log(scale) of the within-model random walk from trial
+    proposals made at the bracket's midpoint (Section 3.2.3): a higher acceptance than
+    the target allows a larger step.  Returns (log_lo, log_hi, next scale)."""
+    if tried > 0:
+        mid = 0.5 * (log_lo + log_hi)
+        if accepted / tried > target:
+            log_lo = mid
+        else:
+            log_hi = mid
+    return log_lo, log_hi, math.exp(0.5 * (log_lo + log_hi))
 
 
 def mutation_count(acceptance, c, r_max):

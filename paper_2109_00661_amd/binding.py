@@ -64,7 +64,14 @@ class MutateArgs(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("step", ctypes.c_int32), ("n_moves", ctypes.c_int32),
                 ("n_sound", ctypes.c_int32), ("move_prob", ctypes.c_double * N_MOVES),
                 ("z_move_sd", ctypes.c_double), ("rw_scale", ctypes.c_double), ("mala_eps", ctypes.c_double),
-                ("factors", ctypes.c_void_p), ("prior", Prior), ("step_dev", ctypes.c_void_p)]
+                ("factors", ctypes.c_void_p), ("prior", Prior), ("step_dev", ctypes.c_void_p),
+                ("rw_scale_dev", ctypes.c_void_p), ("stats_sound", ctypes.c_void_p), ("trial", ctypes.c_int32)]
+
+
+class BisectArgs(ctypes.Structure):
+    _fields_ = [("n_sound", ctypes.c_int32), ("init", ctypes.c_int32), ("target", ctypes.c_double),
+                ("lo0", ctypes.c_double), ("hi0", ctypes.c_double), ("log_lo", ctypes.c_void_p),
+                ("log_hi", ctypes.c_void_p), ("scale", ctypes.c_void_p), ("stats_sound", ctypes.c_void_p)]
 
 
 class SummaryArgs(ctypes.Structure):
@@ -116,6 +123,7 @@ _SIGS = {
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Particles),
                                     ctypes.POINTER(Particles), ctypes.c_void_p, ctypes.c_void_p]),
     "rjsmc_counter_add": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "rjsmc_scale_bisect": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BisectArgs), ctypes.c_void_p]),
     "rjsmc_summarize": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.POINTER(SummaryArgs),
                                        ctypes.c_void_p]),
     "rjsmc_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
@@ -261,6 +269,11 @@ class Context:
         _check(lib().rjsmc_summarize(self._ptr, ctypes.byref(ps), ctypes.byref(a), _stream_handle(stream)))
         return out
 
+    def scale_bisect(self, n_sound, init, target, lo0, hi0, log_lo, log_hi, scale, stats_sound, stream=None):
+        a = BisectArgs(n_sound, int(init), target, lo0, hi0, _ptr(log_lo), _ptr(log_hi), _ptr(scale),
+                       _ptr(stats_sound))
+        _check(lib().rjsmc_scale_bisect(self._ptr, ctypes.byref(a), _stream_handle(stream)))
+
     def counter_add(self, counter, delta=1, stream=None):
         _check(lib().rjsmc_counter_add(self._ptr, _ptr(counter), int(delta), _stream_handle(stream)))
 
@@ -342,7 +355,7 @@ class Context:
 
     def mutate(self, state, ll, scratch, ll_scratch, gamma, active, y_obs, stats, *, seed, step, n_moves, n_sound,
                prior, move_prob, z_move_sd, rw_scale, factors, mala_eps=0.0, grad_cur=None, grad_prop=None,
-               stream=None, step_dev=None):
+               stream=None, step_dev=None, rw_scale_dev=None, stats_sound=None, trial=0):
         a = MutateArgs()
         a.seed, a.step, a.n_moves, a.n_sound = seed, step, n_moves, n_sound
         for t in range(N_MOVES):
@@ -351,6 +364,9 @@ class Context:
         a.factors = _ptr(factors) if factors is not None else ctypes.c_void_p(0)
         a.prior = make_prior(prior)
         a.step_dev = _ptr(step_dev) if step_dev is not None else None
+        a.rw_scale_dev = _ptr(rw_scale_dev) if rw_scale_dev is not None else None
+        a.stats_sound = _ptr(stats_sound) if stats_sound is not None else None
+        a.trial = int(trial)
         ss, sq = particles_struct(state), particles_struct(scratch)
         gc = ctypes.byref(particles_struct(grad_cur)) if grad_cur is not None else None
         gp = ctypes.byref(particles_struct(grad_prop)) if grad_prop is not None else None

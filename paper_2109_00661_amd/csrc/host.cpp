@@ -634,7 +634,9 @@ extern "C" rjsmc_status rjsmc_mutate(rjsmc_ctx *c, const rjsmc_mutate_args *a, r
   prop2.mask_value = 2;
   cur2.mask = c->work_mask;
   cur2.mask_value = 2;
-  for (int r = 0; r < a->n_moves && e == hipSuccess; ++r) {
+  if (a->trial < 0 || a->trial > 1000) return fail(RJSMC_E_INVALID, "%s: trial=%d outside 0..1000", who, a->trial);
+  for (int r0 = 0; r0 < a->n_moves && e == hipSuccess; ++r0) {
+    const int r = a->trial * (1 << 20) + r0;   // random-number move index
     e = rjsmc::launch_draw_types(*a, r, ds, sh.kc, sh.km, c->work_mask, c->work_type, active, s);
     if (e == hipSuccess && mala)   // gradients of the current states of the particles taking a Langevin step
       e = rjsmc::launch_loglik_grad(c->dev, cur2, c->kmax_cond, c->kmax_charg, y_obs, ll_scratch, gcw, s);
@@ -745,5 +747,19 @@ extern "C" rjsmc_status rjsmc_summarize(rjsmc_ctx *c, const rjsmc_particles *p, 
   hipError_t e = hipSetDevice(c->device);
   if (e == hipSuccess) e = rjsmc::launch_summary(smc_shape(c), dp, *a, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "rjsmc_summarize: launch");
+  return RJSMC_OK;
+}
+
+extern "C" rjsmc_status rjsmc_scale_bisect(rjsmc_ctx *c, const rjsmc_bisect_args *a, rjsmc_stream stream) {
+  const char *who = "rjsmc_scale_bisect";
+  if (!c || !a) return fail(RJSMC_E_INVALID, "%s: NULL argument", who);
+  if (a->n_sound < 1) return fail(RJSMC_E_INVALID, "%s: n_sound < 1", who);
+  if (!a->log_lo || !a->log_hi || !a->scale || !a->stats_sound) return fail(RJSMC_E_INVALID, "%s: NULL array", who);
+  if (a->init && !(a->lo0 > 0 && a->hi0 > a->lo0 && std::isfinite(a->hi0)))
+    return fail(RJSMC_E_INVALID, "%s: bad initial bracket", who);
+  if (!(a->target > 0 && a->target < 1)) return fail(RJSMC_E_INVALID, "%s: target outside (0, 1)", who);
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = rjsmc::launch_scale_bisect(*a, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "rjsmc_scale_bisect: launch");
   return RJSMC_OK;
 }

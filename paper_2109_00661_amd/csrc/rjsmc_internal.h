@@ -111,6 +111,7 @@ hipError_t launch_loglik_grad(const DevSystem &s, const DevParticles &p, int kma
 
 // SMC launchers (smc.hip).
 hipError_t launch_counter_add(int32_t *counter, int32_t delta, hipStream_t stream);
+hipError_t launch_scale_bisect(const rjsmc_bisect_args &a, hipStream_t stream);
 hipError_t launch_summary(const SmcShape &sh, const DevParticles &p, const rjsmc_summary_args &a, hipStream_t stream);
 hipError_t launch_init_prior(const DevParticlesW &p, const SmcShape &sh, const rjsmc_prior &pr, uint64_t seed,
                              hipStream_t stream);

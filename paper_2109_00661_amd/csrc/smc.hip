@@ -742,7 +742,7 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
     r = r > d - 1 ? d - 1 : r;
     const int mdl = k * (km + 1) + l;
     const double *Fr = a.factors + ((snd * sh.n_models + mdl) * (int64_t)sh.dmax + r) * sh.dmax;
-    const double step = a.rw_scale * normal0(u2, u3);
+    const double step = (a.rw_scale_dev ? a.rw_scale_dev[snd] : a.rw_scale) * normal0(u2, u3);
     // theta' = theta + step F[:, r] in parameter-vector order
     int q = 0;
     phb = madd_rn(phb, step, Fr[q++]);
@@ -845,7 +845,7 @@ __global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_a
     }
     const double margin = gamma[snd] * (ll_prop[i] - ll[i]) + extra - log(ua);
     acc = margin > 0.0;
-    if (acc) {
+    if (acc && a.trial == 0) {
       const int64_t S = st.stride, Sp = prop.stride;
       st.kappa[i] = prop.kappa[i];
       st.lambda[i] = prop.lambda[i];
@@ -862,6 +862,11 @@ __global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_a
       }
       ll[i] = ll_prop[i];
     }
+  }
+  if (a.stats_sound && t == RJSMC_MOVE_WITHIN_RW) {   // every drawn random-walk proposal counts
+    const int64_t snd = st.n_per_sounding > 0 ? i / st.n_per_sounding : 0;
+    atomicAdd((unsigned long long *)&a.stats_sound[2 * snd], 1ull);
+    if (acc) atomicAdd((unsigned long long *)&a.stats_sound[2 * snd + 1], 1ull);
   }
   if (stats) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -974,6 +979,38 @@ hipError_t launch_summary(const SmcShape &sh, const DevParticles &p, const rjsmc
   const int items = sh.n_models + 1 + a.n_depth;
   hipLaunchKernelGGL(summary_kernel, dim3((unsigned)a.n_sound, (unsigned)((items + 255) / 256)), dim3(256), 0, stream,
                      sh, p, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ step-size bisection ---
+__global__ void scale_bisect_kernel(rjsmc_bisect_args a) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n_sound) return;
+  double lo, hi;
+  if (a.init) {
+    lo = log(a.lo0);
+    hi = log(a.hi0);
+  } else {
+    lo = a.log_lo[s];
+    hi = a.log_hi[s];
+    const int64_t tried = a.stats_sound[2 * s], taken = a.stats_sound[2 * s + 1];
+    if (tried > 0) {
+      const double mid = 0.5 * (lo + hi);
+      if ((double)taken / (double)tried > a.target)
+        lo = mid;
+      else
+        hi = mid;
+    }
+  }
+  a.log_lo[s] = lo;
+  a.log_hi[s] = hi;
+  a.scale[s] = exp(0.5 * (lo + hi));
+  a.stats_sound[2 * s] = 0;
+  a.stats_sound[2 * s + 1] = 0;
+}
+
+hipError_t launch_scale_bisect(const rjsmc_bisect_args &a, hipStream_t stream) {
+  hipLaunchKernelGGL(scale_bisect_kernel, dim3((unsigned)((a.n_sound + 255) / 256)), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 

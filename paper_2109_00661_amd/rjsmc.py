@@ -12,6 +12,7 @@ from . import workloads as W
 
 UNIFORM_MOVES = (1, 1, 1, 1, 1, 1, 1, 0)     # birth/death/move x2 partitions + within-model RW
 LANGEVIN_MOVES = (1, 1, 1, 1, 1, 1, 0, 1)    # the within-model move is the gradient-informed one
+RW_ONLY = (0, 0, 0, 0, 0, 0, 1, 0)           # trial proposals of the step-size bisection
 
 
 def mutation_count(rates, c, r_max):
@@ -34,7 +35,8 @@ class RJSMCRun:
 
     def __init__(self, ctx, n_sound, n_per_sound, y_obs, *, prior=None, alpha=0.5, n_moves=5, seed=0,
                  move_prob=UNIFORM_MOVES, z_move_frac=0.05, rw_scale=2.38, mala_eps=0.8, device="cuda",
-                 graph=False, adapt_c=None, r_max=100):
+                 graph=False, adapt_c=None, r_max=100, tune_scale=False, scale_target=0.44, n_bisect=6,
+                 scale_bracket=(0.05, 20.0)):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -65,6 +67,13 @@ class RJSMCRun:
             self.grads = [B.empty_device_population(self.n, kc, km, nps, device) for _ in range(2)]
         self.step = 0
         self.adapt_c, self.r_max = adapt_c, r_max
+        self.tune_scale, self.scale_target, self.n_bisect, self.scale_bracket = (tune_scale, scale_target, n_bisect,
+                                                                                 scale_bracket)
+        if tune_scale:
+            self.log_lo = torch.zeros(n_sound, dtype=torch.float64, device=device)
+            self.log_hi = torch.zeros(n_sound, dtype=torch.float64, device=device)
+            self.scale = torch.full((n_sound,), rw_scale, dtype=torch.float64, device=device)
+            self.stats_sound = torch.zeros((n_sound, 2), dtype=torch.int64, device=device)
         self.moves_per_step = []
         self._stats_prev = None
         self.use_graph = graph
@@ -92,12 +101,23 @@ class RJSMCRun:
                                    step_dev=step_dev)
         self.cur = nxt
         self.ctx.adapt(self.state, self.S, self.prior, self.factors)
+        common = dict(seed=self.seed, step=self.step, n_sound=self.S, prior=self.prior, z_move_sd=self.z_move_sd,
+                      rw_scale=self.rw_scale, factors=self.factors, mala_eps=self.mala_eps, step_dev=step_dev)
+        if self.tune_scale:
+            # bisection on the random-walk scale from trial proposals (never kept)
+            bis = dict(target=self.scale_target, lo0=self.scale_bracket[0], hi0=self.scale_bracket[1],
+                       log_lo=self.log_lo, log_hi=self.log_hi, scale=self.scale, stats_sound=self.stats_sound)
+            self.ctx.scale_bisect(self.S, 1, **bis)
+            for b in range(1, self.n_bisect + 1):
+                self.ctx.mutate(self.state, self.ll, self.bufs[1 - self.cur], self.lls[1 - self.cur], self.gamma,
+                                self.active, self.y_obs, None, n_moves=1, move_prob=RW_ONLY, rw_scale_dev=self.scale,
+                                stats_sound=self.stats_sound, trial=b, **common)
+                self.ctx.scale_bisect(self.S, 0, **bis)
         self.ctx.mutate(self.state, self.ll, self.bufs[1 - self.cur], self.lls[1 - self.cur], self.gamma, self.active,
-                        self.y_obs, self.stats, seed=self.seed, step=self.step, n_moves=self.n_moves,
-                        n_sound=self.S, prior=self.prior, move_prob=self.move_prob, z_move_sd=self.z_move_sd,
-                        rw_scale=self.rw_scale, factors=self.factors, mala_eps=self.mala_eps,
+                        self.y_obs, self.stats, n_moves=self.n_moves, move_prob=self.move_prob,
                         grad_cur=self.grads[0] if self.grads else None,
-                        grad_prop=self.grads[1] if self.grads else None, step_dev=step_dev)
+                        grad_prop=self.grads[1] if self.grads else None,
+                        rw_scale_dev=self.scale if self.tune_scale else None, **common)
         if step_dev is not None:
             self.ctx.counter_add(step_dev, 1)
 

@@ -355,3 +355,86 @@ def test_adaptive_sweeps_graph_and_eager(B, truth_data):
     assert np.array_equal(a.ll.cpu().numpy(), b.ll.cpu().numpy())
     assert np.array_equal(a.log_z.cpu().numpy(), b.log_z.cpu().numpy())
     assert np.array_equal(a.stats.cpu().numpy(), b.stats.cpu().numpy())
+
+
+def test_trial_mutation_against_oracle(B, ctx, system, K_oracle, truth_data):
+    """Trial proposals with per-sounding scales: the population and its log-likelihoods
+    are untouched, and the per-sounding random-walk counts equal the oracle's decisions."""
+    from oracle import em, smc
+    S, nps, trial, seed, step = 2, 32, 3, 55, 7
+    n = S * nps
+    p = smc.init_population(61, n, KC, KM, PR)
+    p["n_per_sounding"] = nps
+    ll0 = em.loglik(p, system, K_oracle, truth_data)
+    scales = np.array([0.4, 1.7])
+    fdev, fhost = _device_factors(p, nps, S, 8)
+    q = dict(move_prob=np.array([0, 0, 0, 0, 0, 0, 1, 0], float), z_move_sd=0.05 * PR["z_max"],
+             rw_scale=lambda i: scales[i // nps])
+    po = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+    llo = ll0.copy()
+    models = lambda i: smc.model_id(int(po["kappa"][i]), int(po["lambda_"][i]), KM)
+    _, margins = smc.mutate(po, llo, lambda pp, i: em.loglik(pp, system, K_oracle, truth_data, [i])[0],
+                            lambda i: 0.2, step, seed, q, PR, KC, KM, lambda i: fhost[(i // nps, models(i))], 1,
+                            trial=trial)
+    dp = B.particles_to_device(p)
+    ll_d = torch.as_tensor(ll0, device="cuda")
+    stats_sound = torch.zeros((S, 2), dtype=torch.int64, device="cuda")
+    ctx.mutate(dp, ll_d, B.empty_device_population(n, KC, KM, nps), torch.empty_like(ll_d),
+               torch.full((S,), 0.2, dtype=torch.float64, device="cuda"), None,
+               torch.as_tensor(np.tile(truth_data, (S, 1)), device="cuda"), None, seed=seed, step=step, n_moves=1,
+               n_sound=S, prior=PR, move_prob=q["move_prob"], z_move_sd=q["z_move_sd"], rw_scale=9.9,
+               factors=torch.as_tensor(fdev, device="cuda"), rw_scale_dev=torch.as_tensor(scales, device="cuda"),
+               stats_sound=stats_sound, trial=trial)
+    ctx.check()
+    _assert_pop_equal(_host(B, dp), p)
+    assert np.array_equal(ll_d.cpu().numpy(), ll0)
+    near = [mg for _, _, mg in margins if abs(mg) < 1e-8]
+    assert not near
+    acc = np.zeros(S, dtype=np.int64)
+    for i, _, mg in margins:
+        acc[i // nps] += 0 < mg < np.inf
+    got = stats_sound.cpu().numpy()
+    assert np.array_equal(got[:, 0], [nps, nps]) and np.array_equal(got[:, 1], acc)
+
+
+def test_scale_bisect_kernel(B, ctx):
+    from oracle import smc
+    rng = np.random.default_rng(5)
+    S = 300
+    lo = torch.zeros(S, dtype=torch.float64, device="cuda")
+    hi = torch.zeros(S, dtype=torch.float64, device="cuda")
+    sc = torch.zeros(S, dtype=torch.float64, device="cuda")
+    st = torch.zeros((S, 2), dtype=torch.int64, device="cuda")
+    ctx.scale_bisect(S, 1, 0.44, 0.05, 20.0, lo, hi, sc, st)
+    ref = [(np.log(0.05), np.log(20.0))] * S
+    for it in range(5):
+        tried = rng.integers(0, 50, S)
+        taken = rng.integers(0, tried + 1)
+        st.copy_(torch.as_tensor(np.stack([tried, taken], axis=1), device="cuda"))
+        ctx.scale_bisect(S, 0, 0.44, 0.05, 20.0, lo, hi, sc, st)
+        new = [smc.scale_bisection(a, b, int(t), int(k), 0.44) for (a, b), t, k in zip(ref, tried, taken)]
+        ref = [(a, b) for a, b, _ in new]
+        np.testing.assert_array_equal(lo.cpu().numpy(), [a for a, _ in ref])
+        np.testing.assert_array_equal(hi.cpu().numpy(), [b for _, b in ref])
+        np.testing.assert_allclose(sc.cpu().numpy(), [x for _, _, x in new], rtol=1e-15)
+        assert int(st.abs().sum()) == 0
+    ctx.check()
+
+
+def test_tuned_scale_run_graph_and_eager(B, truth_data):
+    from paper_2109_00661_amd.rjsmc import RJSMCRun
+    y = np.tile(truth_data, (2, 1))
+    runs = []
+    for graph in (False, True):
+        ctx = B.Context(W.system(), precision="f64", max_particles=512)
+        run = RJSMCRun(ctx, 2, 256, y, seed=21, graph=graph, tune_scale=True, n_bisect=5)
+        run.initialise()
+        for _ in range(4):
+            run.advance()
+        ctx.check()
+        runs.append(run)
+    a, b = runs
+    for k in ("ll", "log_z", "gamma", "scale", "stats"):
+        assert np.array_equal(getattr(a, k).cpu().numpy(), getattr(b, k).cpu().numpy()), k
+    sc = a.scale.cpu().numpy()
+    assert np.all((sc > 0.05) & (sc < 20.0))

@@ -316,3 +316,34 @@ def test_driver_mutation_count_matches_the_oracle():
             acc.append(0.0)
         c, r_max = 10 ** rng.uniform(-4, -0.3), int(rng.integers(1, 300))
         assert mutation_count(acc, c, r_max) == smc.mutation_count(acc, c, r_max)
+
+
+# ------------------------------------------------------------- step-size bisection
+def test_scale_bisection_finds_the_gaussian_random_walk_scale():
+    """For a standard normal target, a random walk x + s xi is accepted at rate
+    (2/pi) arctan(2/s); bisecting to 0.44 must give s = 2/tan(0.22 pi) ~ 2.42."""
+    rate = lambda s: 2.0 / math.pi * math.atan(2.0 / s)
+    lo, hi = math.log(0.05), math.log(20.0)
+    s = math.exp(0.5 * (lo + hi))
+    for _ in range(40):
+        tried = 10 ** 9
+        lo, hi, s = smc.scale_bisection(lo, hi, tried, round(rate(s) * tried), 0.44)
+    assert abs(s - 2.0 / math.tan(0.22 * math.pi)) < 1e-6
+    assert smc.scale_bisection(0.0, 1.0, 0, 0, 0.44) == (0.0, 1.0, math.exp(0.5))   # no trials: unchanged
+
+
+def test_trial_proposals_keep_the_population(system, K_oracle, truth_data):
+    from oracle import em
+    p = smc.init_population(8, 24, PR["kmax_cond"], PR["kmax_charg"], PR)
+    ll = em.loglik(p, system, K_oracle, truth_data)
+    p0 = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+    ll0 = ll.copy()
+    q = dict(move_prob=np.array([0, 0, 0, 0, 0, 0, 1, 0], float), z_move_sd=15.0, rw_scale=lambda i: 0.5 + 0.1 * i)
+    F = lambda i: np.diag(0.05 * smc.prior_sd(int(p["kappa"][i]), int(p["lambda_"][i]), PR))
+    st, margins = smc.mutate(p, ll, lambda pp, i: em.loglik(pp, system, K_oracle, truth_data, [i])[0],
+                             lambda i: 0.3, 4, 99, q, PR, PR["kmax_cond"], PR["kmax_charg"], F, 1, trial=2)
+    for k, v in p0.items():
+        if isinstance(v, np.ndarray):
+            assert np.array_equal(p[k], v), k
+    assert np.array_equal(ll, ll0)
+    assert st[0, 6] == 24 and st[1, 6] == sum(1 for _, _, m in margins if 0 < m < np.inf)
