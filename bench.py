@@ -117,7 +117,7 @@ def cpu_baseline(system, d_np, budget_s=15.0):
 
 
 def rjsmc_rate(torch, d, n_sound, n_per_sound, seed=0, move_prob=None, graph=False, kmax=None, noise=False,
-               tune=False):
+               tune=False, **run_kw):
     """Soundings per second of complete Algorithm-1 runs (gamma 0 -> 1): n_sound soundings
     of n_per_sound particles each, alpha = 0.5, 5 moves per step, run together in the
     same launches (graph=True: one captured HIP graph per step).  The soundings are copies
@@ -143,10 +143,10 @@ def rjsmc_rate(torch, d, n_sound, n_per_sound, seed=0, move_prob=None, graph=Fal
         warm = RJSMCRun(ctx, n_sound, n_per_sound, y, seed=seed + 99, move_prob=mp)
         warm.initialise()
         tuned, _ = ctx.autotune(warm.state, warm.y_obs, reps=3)
-    RJSMCRun(ctx, n_sound, n_per_sound, y, seed=seed + 99, move_prob=mp, graph=graph).run()          # warm-up
+    RJSMCRun(ctx, n_sound, n_per_sound, y, seed=seed + 99, move_prob=mp, graph=graph, **run_kw).run()   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run = RJSMCRun(ctx, n_sound, n_per_sound, y, seed=seed, move_prob=mp, graph=graph).run()
+    run = RJSMCRun(ctx, n_sound, n_per_sound, y, seed=seed, move_prob=mp, graph=graph, **run_kw).run()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = run.stats.cpu().numpy()
@@ -159,7 +159,10 @@ def rjsmc_rate(torch, d, n_sound, n_per_sound, seed=0, move_prob=None, graph=Fal
            "proposals_per_sounding": float(st[0].sum() / n_sound),
            "acceptance": float(st[1].sum() / max(st[0].sum(), 1)),
            "p_chargeable_mean": float(p_ip.mean()), "p_chargeable_sd": float(p_ip.std()),
-           "best_model": best}
+           "best_model": best,
+           "ll_max_median": float(np.median(run.ll.cpu().numpy().reshape(n_sound, n_per_sound).max(axis=1)))}
+    if run_kw:
+        out["sweeps_per_step_mean"] = float(np.mean(run.moves_per_step))
     if tuned is not None:
         out["tuning"] = tuned
     if n_sound > 1:
@@ -328,6 +331,8 @@ def main():
                     "batched_64x256_rw": rjsmc_rate(torch, d, 64, 256, graph=True, tune=True),
                     "batched_64x256_langevin": rjsmc_rate(torch, d, 64, 256, move_prob=LANGEVIN_MOVES, graph=True,
                                                           tune=True),
+                    "batched_64x256_adaptive_sweeps_tuned_scale": rjsmc_rate(
+                        torch, d, 64, 256, graph=True, tune=True, adapt_c=0.05, r_max=40, tune_scale=True),
                     "uneven_512x1024_rw": rjsmc_rate(torch, d, 512, 1024, graph=True, kmax=(7, 4), noise=True,
                                                      tune=True)}
     if args.survey:
