@@ -47,7 +47,8 @@ __device__ __forceinline__ cplx<float> prop_exp(cplx<float> z, const cplx<double
 
 // Per-(frequency, layer) terms are read from LDS: k2[l] (layers 0..L-1), the interface
 // numerators dk2[l] = k2[l] - k2[l+1] (l < L-1) and h2[l] = -2 h_l (l < L-1).  The layer
-// loop is a runtime loop whose carried state is N, D and u_{l+1}.  phase / e2 are the
+// loop is a runtime loop (unrolled by two, which removes the register rotation of the
+// carried u and stays within 128 VGPRs) whose carried state is N, D and u_{l+1}.  phase / e2 are the
 // LDS copies of the exponential's tables (used in FP64).
 template <typename T>
 __device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const cplx<T> *dk2, const T *h2, int L,
@@ -67,7 +68,7 @@ __device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const cplx<
       D = csq(u + ub);
       ub = u;
     }
-#pragma unroll 1
+#pragma unroll 2
     for (int l = L - 3; l >= 0; --l) {
       const cplx<T> kl = k2[l];
       const cplx<T> u = csqrt_fast(cplx<T>{lam2 + kl.re, kl.im});
