@@ -172,6 +172,13 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
   __shared__ AdjShared<LMAX> sm;
   extern __shared__ double sK[];   // [n_gate][n_freq], dynamic
   const int nf = s.n_freq, ng = s.n_gate, nhp = s.n_hankel_pad;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesA + wave;
+  const bool valid = i < p.n;
+  const bool skip = valid && p.mask && p.mask[i] != p.mask_value;   // left untouched
+  // a masked launch (the Langevin proposals of a sweep) leaves most workgroups without
+  // work: they leave before staging the tables
+  if (!__syncthreads_or(valid && !skip)) return;
   for (int t = threadIdx.x; t < nhp; t += blockDim.x) {
     sm.lam[t] = s.lam[t];
     sm.ck[t] = s.ck[t];
@@ -182,10 +189,6 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
   for (int t = threadIdx.x; t < kPhaseN; t += blockDim.x)
     sm.phase[t] = cplx<double>{s.phase[2 * t], s.phase[2 * t + 1]};
   for (int t = threadIdx.x; t < kExp2N; t += blockDim.x) sm.exp2t[t] = s.exp2t[t];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesA + wave;
-  const bool valid = i < p.n;
-  const bool skip = valid && p.mask && p.mask[i] != p.mask_value;   // left untouched
   LayerStack *st = &sm.stack[wave];
   constexpr int NS = 3 * LMAX + 2;
   for (int t = lane; t < 8 * NS; t += kWave) sm.slot[wave][t / NS][t % NS] = 0.0;

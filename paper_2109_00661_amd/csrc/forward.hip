@@ -55,6 +55,16 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
   extern __shared__ double s_K[];   // [n_gate][n_freq], dynamic
 
   const int nf = s.n_freq, ng = s.n_gate, nhp = s.n_hankel_pad;
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int pw = wave / P;           // particle of this wave within the workgroup
+  const int q0 = wave % P;           // first frequency group of this wave
+  const int64_t slot = (int64_t)(perm ? blockIdx.x : xcd_block(blockIdx.x, gridDim.x)) * WPB + pw;
+  const int64_t i = perm ? (slot < p.n ? (int64_t)perm[slot] : p.n) : slot;
+  const bool valid = i < p.n;
+  const bool skip = valid && p.mask && p.mask[i] != p.mask_value;
+  // workgroups with no particle to evaluate (masked launches) leave before staging
+  if (!__syncthreads_or(valid && !skip)) return;
   for (int t = threadIdx.x; t < nhp; t += blockDim.x) {
     s_lam[t] = s.lam[t];
     s_ck[t] = s.ck[t];
@@ -65,15 +75,6 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
   for (int t = threadIdx.x; t < kPhaseN; t += blockDim.x)
     s_phase[t] = cplx<double>{s.phase[2 * t], s.phase[2 * t + 1]};
   for (int t = threadIdx.x; t < kExp2N; t += blockDim.x) s_exp2[t] = s.exp2t[t];
-
-  const int wave = threadIdx.x / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int pw = wave / P;           // particle of this wave within the workgroup
-  const int q0 = wave % P;           // first frequency group of this wave
-  const int64_t slot = (int64_t)(perm ? blockIdx.x : xcd_block(blockIdx.x, gridDim.x)) * WPB + pw;
-  const int64_t i = perm ? (slot < p.n ? (int64_t)perm[slot] : p.n) : slot;
-  const bool valid = i < p.n;
-  const bool skip = valid && p.mask && p.mask[i] != p.mask_value;
   LayerStack *st = &s_stack[wave];
   __syncthreads();
   const int L = merge_particle(p, i, valid && !skip, kc, km, LMAX, st, s.flags);

@@ -282,6 +282,7 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
   c->work_type = nullptr;
   c->work_perm = nullptr;
   c->work_cnt = nullptr;
+  c->work_gvalid = nullptr;
   c->tuning.waves_per_block = 4;
   c->tuning.layer_sort = 0;
   c->tuning.waves_per_particle = 1;
@@ -290,6 +291,7 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
     e = hipMalloc((void **)&c->work_mask, sizeof(int32_t) * c->work_n);
     if (e == hipSuccess) e = hipMalloc((void **)&c->work_type, sizeof(int32_t) * c->work_n);
     if (e == hipSuccess) e = hipMalloc((void **)&c->work_perm, sizeof(int32_t) * c->work_n);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->work_gvalid, sizeof(int32_t) * c->work_n);
     if (e == hipSuccess) e = hipMalloc((void **)&c->work_cnt, sizeof(int) * 2 * rjsmc::kMaxLayers);
   }
   if (e != hipSuccess) {
@@ -297,6 +299,7 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
     if (c->work_type) (void)hipFree(c->work_type);
     if (c->work_perm) (void)hipFree(c->work_perm);
     if (c->work_cnt) (void)hipFree(c->work_cnt);
+    if (c->work_gvalid) (void)hipFree(c->work_gvalid);
     free_dev(d);
     delete[] c->K_host;
     delete c;
@@ -313,6 +316,7 @@ extern "C" void rjsmc_destroy(rjsmc_ctx *c) {
   if (c->work_type) (void)hipFree(c->work_type);
   if (c->work_perm) (void)hipFree(c->work_perm);
   if (c->work_cnt) (void)hipFree(c->work_cnt);
+  if (c->work_gvalid) (void)hipFree(c->work_gvalid);
   free_dev(c->dev);
   delete[] c->K_host;
   delete c;
@@ -635,21 +639,26 @@ extern "C" rjsmc_status rjsmc_mutate(rjsmc_ctx *c, const rjsmc_mutate_args *a, r
   cur2.mask = c->work_mask;
   cur2.mask_value = 2;
   if (a->trial < 0 || a->trial > 1000) return fail(RJSMC_E_INVALID, "%s: trial=%d outside 0..1000", who, a->trial);
+  // Langevin moves keep each particle's current gradient from sweep to sweep until an
+  // accepted move of another type changes the state
+  int32_t *gvalid = mala ? c->work_gvalid : nullptr;
+  rjsmc::DevParticlesW gcw_state = mala ? writable(gcd) : rjsmc::DevParticlesW();
+  if (e == hipSuccess && gvalid) e = rjsmc::launch_fill_i32(gvalid, ds.n, 0, s);
   for (int r0 = 0; r0 < a->n_moves && e == hipSuccess; ++r0) {
     const int r = a->trial * (1 << 20) + r0;   // random-number move index
-    e = rjsmc::launch_draw_types(*a, r, ds, sh.kc, sh.km, c->work_mask, c->work_type, active, s);
+    e = rjsmc::launch_draw_types(*a, r, ds, sh.kc, sh.km, c->work_mask, c->work_type, active, gvalid, s);
     if (e == hipSuccess && mala)   // gradients of the current states of the particles taking a Langevin step
       e = rjsmc::launch_loglik_grad(c->dev, cur2, c->kmax_cond, c->kmax_charg, y_obs, ll_scratch, gcw, s);
     if (e == hipSuccess)
       e = rjsmc::launch_propose(sh, *a, r, ds, writable(dq), c->work_mask, c->work_type, gamma, mala ? &gcd : nullptr,
-                                s);
+                                gvalid, s);
     if (e == hipSuccess)
       e = run_forward(c, prop1, c->tuning, nullptr, y_obs, ll_scratch, s);
     if (e == hipSuccess && mala)
       e = rjsmc::launch_loglik_grad(c->dev, prop2, c->kmax_cond, c->kmax_charg, y_obs, ll_scratch, gpw, s);
     if (e == hipSuccess)
       e = rjsmc::launch_accept(sh, *a, r, writable(ds), ll, dq, ll_scratch, c->work_mask, c->work_type, gamma,
-                               mala ? &gcd : nullptr, mala ? &gpd : nullptr, stats, s);
+                               mala ? &gcw_state : nullptr, mala ? &gpd : nullptr, gvalid, stats, s);
   }
   if (e != hipSuccess) return hip_fail(e, "rjsmc_mutate: launch");
   return RJSMC_OK;

@@ -121,14 +121,16 @@ hipError_t launch_reweight_resample(const SmcShape &sh, const rjsmc_reweight_arg
 hipError_t launch_adapt(const SmcShape &sh, const DevParticles &p, int n_sound, const rjsmc_prior &pr,
                         double *factors, hipStream_t stream);
 hipError_t launch_draw_types(const rjsmc_mutate_args &a, int move, const DevParticles &state, int kc, int km,
-                             int32_t *mask, int32_t *type, const int32_t *active, hipStream_t stream);
+                             int32_t *mask, int32_t *type, const int32_t *active, const int32_t *gvalid,
+                             hipStream_t stream);
 hipError_t launch_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticles &state,
                           const DevParticlesW &prop, int32_t *mask, const int32_t *type, const double *gamma,
-                          const DevParticles *grad_cur, hipStream_t stream);
+                          const DevParticles *grad_cur, int32_t *gvalid, hipStream_t stream);
 hipError_t launch_accept(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticlesW &state,
                          double *ll, const DevParticles &prop, const double *ll_prop, const int32_t *mask,
-                         const int32_t *type, const double *gamma, const DevParticles *grad_cur,
-                         const DevParticles *grad_prop, int64_t *stats, hipStream_t stream);
+                         const int32_t *type, const double *gamma, const DevParticlesW *grad_cur,
+                         const DevParticles *grad_prop, int32_t *gvalid, int64_t *stats, hipStream_t stream);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t stream);
 
 // Host-side construction of the frequency-to-time matrix (host.cpp).
 void build_time_kernel(const double *freq_hz, int n_freq, const double *t_open,
@@ -145,6 +147,7 @@ struct rjsmc_ctx {
   double *K_host;   // [n_gate][n_freq]
   int32_t *work_mask;   // [work_n] mutate scratch: proposal validity
   int32_t *work_type;   // [work_n] mutate scratch: move type
+  int32_t *work_gvalid; // [work_n] mutate scratch: the current state's gradient is up to date
   int32_t *work_perm;   // [work_n] evaluation order by layer capacity
   int *work_cnt;        // [2 kMaxLayers] counting-sort scratch
   int64_t work_n;

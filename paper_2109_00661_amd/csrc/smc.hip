@@ -435,6 +435,24 @@ hipError_t launch_reweight_resample(const SmcShape &sh, const rjsmc_reweight_arg
 
 // ---------------------------------------------------------------- parameter vectors --
 // theta = (phi_b, phi_1..k, z_1..k, m_1..l, zm_1..l, log10 tau, c) of a decoupled particle.
+__device__ __forceinline__ DevParticles readonly(const DevParticlesW &w) {
+  DevParticles r;
+  r.n = w.n;
+  r.stride = w.stride;
+  r.n_per_sounding = w.n_per_sounding;
+  r.layout = w.layout;
+  r.kappa = w.kappa;
+  r.lambda = w.lambda;
+  r.phi_b = w.phi_b;
+  r.phi = w.phi;
+  r.z_cond = w.z_cond;
+  r.m = w.m;
+  r.z_charg = w.z_charg;
+  r.log10_tau = w.log10_tau;
+  r.c = w.c;
+  return r;
+}
+
 __device__ __forceinline__ double theta_get(const DevParticles &p, int64_t i, int k, int l, int a) {
   const int64_t S = p.stride;
   if (a == 0) return p.phi_b[i];
@@ -624,11 +642,11 @@ __device__ __forceinline__ int draw_type(const rjsmc_mutate_args &a, double u0) 
 __device__ __forceinline__ bool in_range(double v, double lo, double hi) { return v >= lo && v <= hi; }
 
 // Move type of every particle for sweep `move` (-1: inactive sounding or counts outside
-// the capacities); mask = 2 marks the particles that take a gradient-informed step, whose
-// current gradient is needed before proposing.
+// the capacities); mask = 2 marks the particles that take a gradient-informed step and
+// whose current gradient is not already up to date (gvalid) from an earlier sweep.
 __global__ __launch_bounds__(256) void draw_types_kernel(rjsmc_mutate_args a, int move, DevParticles st, int kc,
                                                          int km, int32_t *mask, int32_t *type,
-                                                         const int32_t *active) {
+                                                         const int32_t *active, const int32_t *gvalid) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= st.n) return;
   const int64_t snd = st.n_per_sounding > 0 ? i / st.n_per_sounding : 0;
@@ -640,7 +658,7 @@ __global__ __launch_bounds__(256) void draw_types_kernel(rjsmc_mutate_args a, in
     t = draw_type(a, u0);
   }
   type[i] = t;
-  mask[i] = t == RJSMC_MOVE_WITHIN_MALA ? 2 : 0;
+  mask[i] = t == RJSMC_MOVE_WITHIN_MALA && !(gvalid && gvalid[i]) ? 2 : 0;
 }
 
 // theta' = theta + F (eps^2/2 F^T (gamma grad) + eps xi) of the preconditioned Langevin step,
@@ -662,7 +680,7 @@ __device__ __forceinline__ void mala_normals(const rjsmc_mutate_args &a, int64_t
 // a gradient, 0 if it is rejected outright.
 __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_args a, int move, DevParticles st,
                                                       DevParticlesW prop, int32_t *mask, const int32_t *type,
-                                                      const double *gamma, DevParticles gcur) {
+                                                      const double *gamma, DevParticles gcur, int32_t *gvalid) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= st.n) return;
   const int64_t snd = st.n_per_sounding > 0 ? i / st.n_per_sounding : 0;
@@ -672,6 +690,7 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
     mask[i] = 0;
     return;
   }
+  if (t == RJSMC_MOVE_WITHIN_MALA && gvalid) gvalid[i] = 1;   // computed just before, or kept
   const int kc = sh.kc, km = sh.km;
   const rjsmc_prior &pr = a.prior;
   double u1, u2, u3, u4;
@@ -817,7 +836,8 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
 __global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_args a, int move, DevParticlesW st,
                                                      double *ll, DevParticles prop, const double *ll_prop,
                                                      const int32_t *mask, const int32_t *type, const double *gamma,
-                                                     DevParticles gcur, DevParticles gprop, int64_t *stats) {
+                                                     DevParticlesW gcur, DevParticles gprop, int32_t *gvalid,
+                                                     int64_t *stats) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = i < st.n;
   const int t = in ? type[i] : -1;
@@ -838,7 +858,7 @@ __global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_a
       for (int r = 0; r < d; ++r) {
         double sr = 0.0;
         for (int q = 0; q < d; ++q)
-          sr += Fm[r * D + q] * (gam * (theta_get(gcur, i, k, l, q) + theta_get(gprop, i, k, l, q)));
+          sr += Fm[r * D + q] * (gam * (theta_get(readonly(gcur), i, k, l, q) + theta_get(gprop, i, k, l, q)));
         const double v = xi[r] + 0.5 * a.mala_eps * sr;
         extra += -0.5 * v * v + 0.5 * xi[r] * xi[r];
       }
@@ -861,6 +881,26 @@ __global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_a
         st.m[j * S + i] = prop.m[j * Sp + i];
       }
       ll[i] = ll_prop[i];
+      if (gvalid) {
+        // a Langevin proposal brings its own gradient; any other accepted move leaves the
+        // cached gradient stale
+        if (t == RJSMC_MOVE_WITHIN_MALA) {
+          const int64_t Sg = gcur.stride, Sq = gprop.stride;
+          gcur.phi_b[i] = gprop.phi_b[i];
+          gcur.log10_tau[i] = gprop.log10_tau[i];
+          gcur.c[i] = gprop.c[i];
+          for (int j = 0; j < sh.kc; ++j) {
+            gcur.phi[j * Sg + i] = gprop.phi[j * Sq + i];
+            gcur.z_cond[j * Sg + i] = gprop.z_cond[j * Sq + i];
+          }
+          for (int j = 0; j < sh.km; ++j) {
+            gcur.m[j * Sg + i] = gprop.m[j * Sq + i];
+            gcur.z_charg[j * Sg + i] = gprop.z_charg[j * Sq + i];
+          }
+        } else {
+          gvalid[i] = 0;
+        }
+      }
     }
   }
   if (a.stats_sound && t == RJSMC_MOVE_WITHIN_RW) {   // every drawn random-walk proposal counts
@@ -880,32 +920,43 @@ __global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_a
 }
 
 hipError_t launch_draw_types(const rjsmc_mutate_args &a, int move, const DevParticles &state, int kc, int km,
-                             int32_t *mask, int32_t *type, const int32_t *active, hipStream_t stream) {
+                             int32_t *mask, int32_t *type, const int32_t *active, const int32_t *gvalid,
+                             hipStream_t stream) {
   const int64_t blocks = (state.n + 255) / 256;
   hipLaunchKernelGGL(draw_types_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, a, move, state, kc, km, mask,
-                     type, active);
+                     type, active, gvalid);
+  return hipGetLastError();
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t stream) {
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n, v);
   return hipGetLastError();
 }
 
 hipError_t launch_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticles &state,
                           const DevParticlesW &prop, int32_t *mask, const int32_t *type, const double *gamma,
-                          const DevParticles *grad_cur, hipStream_t stream) {
+                          const DevParticles *grad_cur, int32_t *gvalid, hipStream_t stream) {
   const int64_t blocks = (state.n + 255) / 256;
   const DevParticles g = grad_cur ? *grad_cur : DevParticles();
   hipLaunchKernelGGL(propose_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, sh, a, move, state, prop, mask,
-                     type, gamma, g);
+                     type, gamma, g, gvalid);
   return hipGetLastError();
 }
 
 hipError_t launch_accept(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticlesW &state,
                          double *ll, const DevParticles &prop, const double *ll_prop, const int32_t *mask,
-                         const int32_t *type, const double *gamma, const DevParticles *grad_cur,
-                         const DevParticles *grad_prop, int64_t *stats, hipStream_t stream) {
+                         const int32_t *type, const double *gamma, const DevParticlesW *grad_cur,
+                         const DevParticles *grad_prop, int32_t *gvalid, int64_t *stats, hipStream_t stream) {
   const int64_t blocks = (state.n + 255) / 256;
-  const DevParticles gc = grad_cur ? *grad_cur : DevParticles();
+  const DevParticlesW gc = grad_cur ? *grad_cur : DevParticlesW();
   const DevParticles gp = grad_prop ? *grad_prop : DevParticles();
   hipLaunchKernelGGL(accept_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, sh, a, move, state, ll, prop,
-                     ll_prop, mask, type, gamma, gc, gp, stats);
+                     ll_prop, mask, type, gamma, gc, gp, grad_cur ? gvalid : nullptr, stats);
   return hipGetLastError();
 }
 
