@@ -167,6 +167,12 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// A bisection round evaluates the TESS at the 7 midpoints that three successive halvings
+// of the bracket can visit, then takes the same three decisions: 20 rounds give the 60
+// halvings, with the evaluation points and decisions of a plain bisection bit for bit
+// but a third of the sequential rounds.
+constexpr int kBisectK = 7;
+
 struct RwShared {
   double ll[kMaxPerSounding];
   uint64_t cum[kMaxPerSounding];
@@ -176,6 +182,8 @@ struct RwShared {
   double mx[kMaxModels], s1[kMaxModels], s2[kMaxModels];
   uint64_t U[kMaxModels];
   double tess;
+  double ess[kBisectK][kMaxModels];   // per-model ESS at the candidates of a bisection round
+  double tessk[kBisectK];
 };
 
 // Per-model sums of w = exp(dg (ll - max_k)) and w^2, then TESS (all threads call).
@@ -209,6 +217,53 @@ __device__ double eval_tess(RwShared &sm, double dg, int M) {
   }
   __syncthreads();
   return sm.tess;
+}
+
+// TESS at kBisectK increments at once (all threads call); sm.tessk[c] holds TESS(dg[c]).
+// Each model's wave forms the sums of every candidate, reduces them together (the
+// candidates' reductions overlap), and lane c stores the model's ESS for candidate c;
+// lane c of the first wave then adds the models in order.  Same arithmetic and order
+// as eval_tess for every candidate.
+__device__ void eval_tess_k(RwShared &sm, const double (&dg)[kBisectK], int M) {
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  for (int m = wave; m < M; m += kRwWaves) {
+    const int n = sm.cnt[m];
+    const double mx = sm.mx[m];
+    const bool live = n > 0 && mx > -HUGE_VAL;
+    double a[kBisectK], b[kBisectK];
+#pragma unroll
+    for (int c = 0; c < kBisectK; ++c) {
+      a[c] = 0.0;
+      b[c] = 0.0;
+    }
+    if (live) {
+      for (int q = lane; q < n; q += kWave) {
+        const double x = sm.ll[sm.idx[sm.base[m] + q]] - mx;
+#pragma unroll
+        for (int c = 0; c < kBisectK; ++c) {
+          const double w = exp(dg[c] * x);
+          a[c] += w;
+          b[c] += w * w;
+        }
+      }
+    }
+    double e = 0.0;
+#pragma unroll
+    for (int c = 0; c < kBisectK; ++c) {
+      a[c] = wave_sum(a[c]);
+      b[c] = wave_sum(b[c]);
+      const double ec = live ? a[c] * a[c] / b[c] : 0.0;
+      e = lane == c ? ec : e;
+    }
+    if (lane < kBisectK) sm.ess[lane][m] = e;
+  }
+  __syncthreads();
+  if (threadIdx.x < kBisectK) {
+    double t = 0.0;
+    for (int m = 0; m < M; ++m) t += sm.ess[threadIdx.x][m];
+    sm.tessk[threadIdx.x] = t;
+  }
+  __syncthreads();
 }
 
 // floor(((j << 53) + U) * T / (n << 53)) for j < n <= 2048, U < 2^53, T < 2^62.
@@ -319,12 +374,29 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
     dg = hi;
   } else {
     double lo = 0.0;
-    for (int it = 0; it < 60; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (eval_tess(sm, mid, M) >= target)
-        lo = mid;
-      else
-        hi = mid;
+    for (int round = 0; round < 60 / 3; ++round) {
+      // the points three halvings of (lo, hi) can visit, formed as the halvings form them
+      double c[kBisectK];
+      c[3] = 0.5 * (lo + hi);
+      c[1] = 0.5 * (lo + c[3]);
+      c[5] = 0.5 * (c[3] + hi);
+      c[0] = 0.5 * (lo + c[1]);
+      c[2] = 0.5 * (c[1] + c[3]);
+      c[4] = 0.5 * (c[3] + c[5]);
+      c[6] = 0.5 * (c[5] + hi);
+      eval_tess_k(sm, c, M);
+      int node = 3;
+#pragma unroll
+      for (int level = 0; level < 3; ++level) {
+        const int step = 2 >> level;          // 2, 1, 0: distance to the next level's point
+        if (sm.tessk[node] >= target) {
+          lo = c[node];
+          node += level < 2 ? step : 0;
+        } else {
+          hi = c[node];
+          node -= level < 2 ? step : 0;
+        }
+      }
     }
     dg = lo;
   }
@@ -479,18 +551,32 @@ __device__ __forceinline__ double prior_sd(const rjsmc_prior &pr, double zmax, i
 
 // ---------------------------------------------------------------------- adaptation ---
 // One wavefront per (sounding, model): member list, sample mean and covariance in LDS,
-// cyclic Jacobi eigen-decomposition, factor F = U diag(sqrt(Lambda)) with eigenvalues in
+// Jacobi eigen-decomposition, factor F = U diag(sqrt(Lambda)) with eigenvalues in
 // descending order and each direction signed so that its largest-magnitude component is
 // positive.
+//
+// The Jacobi sweeps use the round-robin (tournament) ordering: a sweep is nn - 1 rounds
+// of nn/2 disjoint index pairs (nn = d rounded up to even), so every pair of a round is
+// rotated at once, A <- J^T A J with J the product of the round's rotations (a column
+// pass into a second buffer, then a row pass back).  Each pair's 2x2 block is touched by
+// its own rotation only, so its diagonal takes the classical update and its off-diagonal
+// entry is set to zero.  A sweep then costs nn - 1 wave-synchronous rounds instead of
+// d (d - 1) / 2 sequential rotations.
 constexpr int kDimMax = 3 + 2 * (kMaxLayers - 1);   // 33
+constexpr int kLd = kDimMax + 1;                    // LDS row stride
 
 __global__ __launch_bounds__(kWave) void adapt_kernel(SmcShape sh, DevParticles p, rjsmc_prior pr, double *factors) {
   __shared__ int16_t mem[kMaxPerSounding];
-  __shared__ double A[kDimMax][kDimMax + 1];
-  __shared__ double V[kDimMax][kDimMax + 1];
+  __shared__ double A[kDimMax][kLd];
+  __shared__ double V0[kDimMax][kLd];
+  // member staging (64 rows) during the moments; column-pass buffers of A and V after
+  __shared__ double T[2][kDimMax][kLd];
   __shared__ double mu[kDimMax];
-  __shared__ double X[kWave][kDimMax + 1];
+  __shared__ double rc[kLd], rs[kLd];
+  __shared__ int partner[kLd];
   __shared__ int order[kDimMax];
+  static_assert(kWave * kLd <= 2 * kDimMax * kLd, "staging fits the column-pass buffers");
+  double (*X)[kLd] = reinterpret_cast<double (*)[kLd]>(&T[0][0][0]);
   const int lane = threadIdx.x;
   const int M = sh.n_models;
   const int s = blockIdx.x / M, m = blockIdx.x % M;
@@ -508,26 +594,33 @@ __global__ __launch_bounds__(kWave) void adapt_kernel(SmcShape sh, DevParticles 
     if (sel) mem[nm + __popcll(b & ((1ull << lane) - 1))] = (int16_t)i;
     nm += __popcll(b);
   }
-  __syncthreads();
+  wave_lds_sync();
   for (int t = lane; t < D * D; t += kWave) F[t] = 0.0;
   if (nm <= d) {
     for (int a = lane; a < d; a += kWave) F[a * D + a] = 0.1 * prior_sd(pr, sh.z_max, k, l, a);
     return;
   }
-  // mean
-  for (int a = lane; a < d; a += kWave) {
-    double acc = 0.0;
-    for (int q = 0; q < nm; ++q) acc += theta_get(p, off + mem[q], k, l, a);
-    mu[a] = acc / (double)nm;
+  // mean: members staged 64 at a time, summed in index order by lane a
+  double acc_mu = 0.0;
+  for (int q0 = 0; q0 < nm; q0 += kWave) {
+    const int q = q0 + lane;
+    if (q < nm)
+      for (int a = 0; a < d; ++a) X[lane][a] = theta_get(p, off + mem[q], k, l, a);
+    wave_lds_sync();
+    const int nq = nm - q0 < kWave ? nm - q0 : kWave;
+    if (lane < d)
+      for (int r = 0; r < nq; ++r) acc_mu += X[r][lane];
+    wave_lds_sync();
   }
+  if (lane < d) mu[lane] = acc_mu / (double)nm;
   for (int t = lane; t < d * d; t += kWave) A[t / d][t % d] = 0.0;
-  __syncthreads();
+  wave_lds_sync();
   // covariance: stage 64 centred members at a time
   for (int q0 = 0; q0 < nm; q0 += kWave) {
     const int q = q0 + lane;
     if (q < nm)
       for (int a = 0; a < d; ++a) X[lane][a] = theta_get(p, off + mem[q], k, l, a) - mu[a];
-    __syncthreads();
+    wave_lds_sync();
     const int nq = nm - q0 < kWave ? nm - q0 : kWave;
     for (int t = lane; t < d * d; t += kWave) {
       const int a = t / d, b = t % d;
@@ -536,23 +629,23 @@ __global__ __launch_bounds__(kWave) void adapt_kernel(SmcShape sh, DevParticles 
       for (int r = 0; r < nq; ++r) acc += X[r][a] * X[r][b];
       A[a][b] = acc;
     }
-    __syncthreads();
+    wave_lds_sync();
   }
   for (int t = lane; t < d * d; t += kWave) {
     const int a = t / d, b = t % d;
-    if (b >= a) {
-      const double v = A[a][b] / (double)(nm - 1);
-      A[a][b] = v;
-    }
+    if (b >= a) A[a][b] = A[a][b] / (double)(nm - 1);
   }
-  __syncthreads();
+  wave_lds_sync();
   for (int t = lane; t < d * d; t += kWave) {
     const int a = t / d, b = t % d;
     if (b < a) A[a][b] = A[b][a];
-    V[a][b] = a == b ? 1.0 : 0.0;
+    V0[a][b] = a == b ? 1.0 : 0.0;
   }
-  __syncthreads();
-  // cyclic Jacobi sweeps until the off-diagonal mass is negligible
+  wave_lds_sync();
+  double (*Vc)[kLd] = V0;        // current eigenvector estimate
+  double (*Vn)[kLd] = T[1];      // its column-pass buffer
+  double (*B)[kLd] = T[0];       // column-pass buffer of A
+  const int nn = (d + 1) & ~1, np = nn / 2;
   for (int sweep = 0; sweep < 40; ++sweep) {
     double offn = 0.0, diag = 0.0;
     for (int t = lane; t < d * d; t += kWave) {
@@ -563,35 +656,68 @@ __global__ __launch_bounds__(kWave) void adapt_kernel(SmcShape sh, DevParticles 
     offn = wave_sum(offn);
     diag = wave_sum(diag);
     if (!(offn > 1e-30 * diag)) break;
-    for (int pp = 0; pp < d - 1; ++pp)
-      for (int qq = pp + 1; qq < d; ++qq) {
-        const double apq = A[pp][qq];
-        if (apq == 0.0) continue;
-        const double theta = (A[qq][qq] - A[pp][pp]) / (2.0 * apq);
-        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        const double cth = 1.0 / sqrt(t * t + 1.0), sth = t * cth;
-        __syncthreads();
-        for (int r = lane; r < d; r += kWave) {
-          if (r != pp && r != qq) {
-            const double arp = A[r][pp], arq = A[r][qq];
-            A[r][pp] = cth * arp - sth * arq;
-            A[pp][r] = A[r][pp];
-            A[r][qq] = sth * arp + cth * arq;
-            A[qq][r] = A[r][qq];
+    for (int round = 0; round < nn - 1; ++round) {
+      // pair `lane` of this round: (nn-1, round) and ((round + j) mod (nn-1), (round - j) mod (nn-1))
+      int pp = 0, qq = 0;
+      double app = 0.0, aqq = 0.0, apq = 0.0, tt = 0.0;
+      bool rot = false;
+      if (lane < np) {
+        int x = lane == 0 ? nn - 1 : (round + lane) % (nn - 1);
+        int y = lane == 0 ? round : (round - lane + (nn - 1)) % (nn - 1);
+        pp = x < y ? x : y;
+        qq = x < y ? y : x;
+        double cth = 1.0, sth = 0.0;
+        if (qq < d) {
+          apq = A[pp][qq];
+          if (apq != 0.0) {
+            app = A[pp][pp];
+            aqq = A[qq][qq];
+            const double theta = (aqq - app) / (2.0 * apq);
+            tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            cth = 1.0 / sqrt(tt * tt + 1.0);
+            sth = tt * cth;
+            rot = true;
           }
-          const double vrp = V[r][pp], vrq = V[r][qq];
-          V[r][pp] = cth * vrp - sth * vrq;
-          V[r][qq] = sth * vrp + cth * vrq;
+          partner[pp] = qq;
+          partner[qq] = pp;
+          rc[pp] = cth;
+          rs[pp] = -sth;
+          rc[qq] = cth;
+          rs[qq] = sth;
+        } else if (pp < d) {           // paired with the padding index: untouched
+          partner[pp] = pp;
+          rc[pp] = 1.0;
+          rs[pp] = 0.0;
         }
-        __syncthreads();
-        if (lane == 0) {
-          A[pp][pp] = A[pp][pp] - t * apq;
-          A[qq][qq] = A[qq][qq] + t * apq;
-          A[pp][qq] = 0.0;
-          A[qq][pp] = 0.0;
-        }
-        __syncthreads();
       }
+      wave_lds_sync();
+      // column pass: B = A J, Vn = Vc J
+      for (int t = lane; t < d * d; t += kWave) {
+        const int i = t / d, x = t % d;
+        const int y = partner[x];
+        const double c_ = rc[x], s_ = rs[x];
+        B[i][x] = c_ * A[i][x] + s_ * A[i][y];
+        Vn[i][x] = c_ * Vc[i][x] + s_ * Vc[i][y];
+      }
+      wave_lds_sync();
+      // row pass: A = J^T B
+      for (int t = lane; t < d * d; t += kWave) {
+        const int x = t / d, j = t % d;
+        const int y = partner[x];
+        A[x][j] = rc[x] * B[x][j] + rs[x] * B[y][j];
+      }
+      wave_lds_sync();
+      if (rot) {
+        A[pp][pp] = app - tt * apq;
+        A[qq][qq] = aqq + tt * apq;
+        A[pp][qq] = 0.0;
+        A[qq][pp] = 0.0;
+      }
+      double (*sw)[kLd] = Vc;
+      Vc = Vn;
+      Vn = sw;
+      wave_lds_sync();
+    }
   }
   // descending eigenvalue order (stable selection by lane 0)
   if (lane == 0) {
@@ -606,15 +732,15 @@ __global__ __launch_bounds__(kWave) void adapt_kernel(SmcShape sh, DevParticles 
       order[b] = v;
     }
   }
-  __syncthreads();
+  wave_lds_sync();
   for (int r = lane; r < d; r += kWave) {
     const int c = order[r];
     const double ev = A[c][c] > 0.0 ? sqrt(A[c][c]) : 0.0;
     int big = 0;
     for (int a = 1; a < d; ++a)
-      if (fabs(V[a][c]) > fabs(V[big][c])) big = a;
-    const double sg = V[big][c] < 0.0 ? -1.0 : 1.0;
-    for (int a = 0; a < d; ++a) F[r * D + a] = sg * ev * V[a][c];
+      if (fabs(Vc[a][c]) > fabs(Vc[big][c])) big = a;
+    const double sg = Vc[big][c] < 0.0 ? -1.0 : 1.0;
+    for (int a = 0; a < d; ++a) F[r * D + a] = sg * ev * Vc[a][c];
   }
 }
 
