@@ -29,6 +29,16 @@ readings where it is silent or loose:
   art, Section 3) is a preconditioned Langevin step theta' = theta + eps^2/2 S grad +
   eps F xi with S = F F^T, grad = gamma grad ll (flat prior inside the support) and a
   Metropolis-Hastings correction with the reverse proposal density.
+* Particle recycling for the proposal adaptation (Section 3.2.5): the members of model
+  k in the populations of steps l = 0..t (each approximating the model-conditional
+  power posterior at gamma_l) are pooled and weighted by the deterministic mixture
+  nu = L^gamma_t / sum_l N_{l,k} L^gamma_l / Z_{l,k}, N_{l,k} the number of model-k
+  members contributed by step l.  With equal counts this is the paper's nu up to a
+  constant; with unequal counts it is the mixture the pool is actually drawn from.
+  Steps without model-k members (or with Z_{l,k} = 0) are not mixture components.
+  The prior density cancels.  L^0 = 1, also where L = 0.  The weighted covariance is
+  sum w (theta - mu)(theta - mu)^T / (1 - sum w^2) with normalised weights w, which is
+  the sample covariance when the weights are equal.
 """
 import math
 
@@ -322,13 +332,69 @@ def proposal_factor(p, members, k, l, pr):
     if len(members) <= d:
         return np.diag(0.1 * prior_sd(k, l, pr))
     X = np.array([param_vector(p, i) for i in members])
-    C = np.cov(X, rowvar=False, bias=False)
+    return factor_of_covariance(np.cov(X, rowvar=False, bias=False))
+
+
+def factor_of_covariance(C):
+    """F = U diag(sqrt Lambda) of a covariance, eigenvalues descending, each direction
+    signed so that its largest-magnitude component is positive."""
+    d = C.shape[0]
     lam_, U = np.linalg.eigh(C)
     order = np.argsort(-lam_, kind="stable")                 # descending eigenvalues
     lam_, U = np.clip(lam_[order], 0.0, None), U[:, order]
     big = np.argmax(np.abs(U), axis=0)                       # largest component positive
     U = U * np.where(U[big, np.arange(d)] < 0, -1.0, 1.0)[None, :]
     return U * np.sqrt(lam_)[None, :]
+
+
+# ------------------------------------------------------------ particle recycling (O-15)
+def _tempered(g, ll):
+    """log L^g = g ll, with L^0 = 1 also where L = 0 (ll = -inf)."""
+    ll = np.asarray(ll, dtype=np.float64)
+    if g == 0.0:
+        return np.zeros_like(ll)
+    return g * ll
+
+
+def recycled_log_weights(ll, gamma_hist, log_z_hist, count_hist, gamma_t):
+    """Unnormalised log deterministic-mixture weights (Section 3.2.5) of pooled members
+    of one model with log-likelihoods `ll`: gamma_t ll - log sum_l N_l exp(gamma_l ll -
+    log Z_l) over the steps l whose population holds N_l > 0 members of the model and
+    whose evidence estimate log Z_l is finite."""
+    ll = np.asarray(ll, dtype=np.float64)
+    comps = [q for q in range(len(gamma_hist)) if count_hist[q] > 0 and np.isfinite(log_z_hist[q])]
+    terms = np.stack([math.log(count_hist[q]) + _tempered(gamma_hist[q], ll) - log_z_hist[q] for q in comps])
+    num = _tempered(gamma_t, ll)
+    m = np.max(terms, axis=0)
+    live = (num > -np.inf) & (m > -np.inf)
+    mm = np.where(live, m, 0.0)
+    with np.errstate(divide="ignore", invalid="ignore"):   # dead members, masked below
+        den = mm + np.log(np.sum(np.exp(terms - mm[None, :]), axis=0))
+        return np.where(live, num - den, -np.inf)           # L = 0: weight 0
+
+
+def weighted_covariance(X, log_w):
+    """Self-normalised weighted mean and covariance sum w (x - mu)(x - mu)^T / (1 - sum
+    w^2) of the rows of X."""
+    w = np.exp(log_w - np.max(log_w))
+    w = w / np.sum(w)
+    mu = w @ X
+    Xc = X - mu[None, :]
+    return mu, (Xc * w[:, None]).T @ Xc / (1.0 - np.sum(w * w))
+
+
+def recycled_proposal_factor(thetas, log_w, k, l, pr):
+    """Colouring factor of model (k, l) from the pooled members' parameter vectors
+    (rows of `thetas`) and their recycling log-weights; the prior-scaled diagonal when
+    no more members than dimensions carry weight."""
+    d = 3 + 2 * k + 2 * l
+    thetas = np.asarray(thetas, dtype=np.float64).reshape(-1, d)
+    log_w = np.asarray(log_w, dtype=np.float64)
+    if np.sum(log_w > -np.inf) <= d:
+        return np.diag(0.1 * prior_sd(k, l, pr))
+    live = log_w > -np.inf
+    _, C = weighted_covariance(thetas[live], log_w[live])
+    return factor_of_covariance(C)
 
 
 # ---------------------------------------------------------------------- mutation (O-11)

@@ -347,3 +347,99 @@ def test_trial_proposals_keep_the_population(system, K_oracle, truth_data):
             assert np.array_equal(p[k], v), k
     assert np.array_equal(ll, ll0)
     assert st[0, 6] == 24 and st[1, 6] == sum(1 for _, _, m in margins if 0 < m < np.inf)
+
+
+# ------------------------------------------------------------------- particle recycling
+def _norm_w(lw):
+    w = np.exp(lw - np.max(lw))
+    return w / w.sum()
+
+
+def test_recycled_factor_of_one_population_is_the_plain_factor():
+    """A pool holding only the current population has equal weights: the recycled factor
+    is the factor of the sample covariance (Section 3.2.3)."""
+    p = smc.init_population(4, 600, PR["kmax_cond"], PR["kmax_charg"], PR)
+    models = smc.model_id(p["kappa"], p["lambda_"], PR["kmax_charg"])
+    k, l = 2, 1
+    members = np.nonzero(models == k * (PR["kmax_charg"] + 1) + l)[0]
+    thetas = np.array([smc.param_vector(p, i) for i in members])
+    ll = np.random.default_rng(0).normal(-80, 5, len(members))
+    lw = smc.recycled_log_weights(ll, [0.3], [-12.0], [len(members)], 0.3)
+    np.testing.assert_allclose(_norm_w(lw), 1.0 / len(members), rtol=1e-12)
+    F = smc.recycled_proposal_factor(thetas, lw, k, l, PR)
+    F0 = smc.proposal_factor(p, members, k, l, PR)
+    np.testing.assert_allclose(F @ F.T, F0 @ F0.T, rtol=0, atol=1e-12 * np.abs(F0 @ F0.T).max())
+
+
+def test_recycled_weights_with_equal_counts_are_the_papers_weights():
+    """With the same number of members from every step the count-weighted mixture gives
+    the normalised weights of the paper's nu = L^g_t p / (1/t sum_l L^g_l p / Z_l)."""
+    rng = np.random.default_rng(2)
+    ll = rng.normal(-40, 15, 500)
+    gam = np.array([0.0, 0.01, 0.07, 0.3, 0.55])
+    lz = np.array([0.0, -0.4, -2.5, -9.0, -15.0])
+    lw = smc.recycled_log_weights(ll, gam, lz, [100] * 5, gam[-1])
+    nu = np.exp(gam[-1] * ll) / (np.sum([np.exp(g * ll - z) for g, z in zip(gam, lz)], axis=0) / (len(gam) - 1))
+    np.testing.assert_allclose(_norm_w(lw), nu / nu.sum(), rtol=1e-10)
+
+
+def test_recycled_weights_invariances_and_dead_members():
+    rng = np.random.default_rng(3)
+    ll = rng.normal(-30, 10, 200)
+    ll[5] = -np.inf
+    gam, lz, cnt = [0.0, 0.1, 0.4], [0.0, -3.0, -11.0], [50, 20, 130]
+    w = _norm_w(smc.recycled_log_weights(ll, gam, lz, cnt, 0.4))
+    assert w[5] == 0.0 and np.all(np.isfinite(w))
+    # a common shift of every log Z, or a common factor on every count, leaves them alone
+    np.testing.assert_allclose(_norm_w(smc.recycled_log_weights(ll, gam, np.array(lz) + 7.0, cnt, 0.4)), w, rtol=1e-12)
+    np.testing.assert_allclose(_norm_w(smc.recycled_log_weights(ll, gam, lz, np.array(cnt) * 3, 0.4)), w, rtol=1e-12)
+    # steps without members are not mixture components
+    np.testing.assert_allclose(_norm_w(smc.recycled_log_weights(ll, gam + [0.2], lz + [-np.inf], cnt + [0], 0.4)),
+                               w, rtol=1e-12)
+
+
+def test_recycled_moments_match_the_tempered_gaussian():
+    """Exact draws from the power posteriors of a Gaussian prior and likelihood, with
+    unequal counts per step and the closed-form normalising constants: the recycled
+    weighted mean and covariance recover the current power posterior.  Plausible
+    mistakes (counts dropped, evidence dropped or sign-flipped, gamma_t in the mixture)
+    miss it by far more than the tolerance."""
+    rng = np.random.default_rng(1)
+    d, s0, s = 3, 2.0, 0.5
+    m = np.array([1.5, -1.0, 0.5])
+    gam = np.array([0.0, 0.002, 0.01, 0.05, 0.25])
+    cnt = np.array([30000, 800, 3000, 600, 5000])
+
+    def post(g):
+        P = 1.0 / s0 ** 2 + g / s ** 2
+        return (g / s ** 2) * m / P, 1.0 / P
+
+    def log_z(g):
+        a, b = s0 ** 2, g / s ** 2
+        return float(np.sum(-0.5 * np.log1p(a * b) - b * m ** 2 / (2.0 * (1.0 + a * b))))
+
+    X, LL = [], []
+    for g, n in zip(gam, cnt):
+        mu, v = post(g)
+        x = mu + math.sqrt(v) * rng.standard_normal((n, d))
+        X.append(x)
+        LL.append(-0.5 * np.sum((x - m) ** 2, axis=1) / s ** 2)
+    X, LL = np.concatenate(X), np.concatenate(LL)
+    lz = np.array([log_z(g) for g in gam])
+    mu_t, v_t = post(gam[-1])
+
+    def miss(lw):
+        mu, C = smc.weighted_covariance(X, lw)
+        return max(np.abs(mu - mu_t).max() / math.sqrt(v_t), np.abs(np.diag(C) / v_t - 1.0).max(),
+                   np.abs(C - np.diag(np.diag(C))).max() / v_t)
+
+    assert miss(smc.recycled_log_weights(LL, gam, lz, cnt, gam[-1])) < 0.04
+    assert miss(smc.recycled_log_weights(LL, gam, lz, np.ones_like(cnt), gam[-1])) > 0.07
+    assert miss(smc.recycled_log_weights(LL, gam, np.zeros_like(lz), cnt, gam[-1])) > 0.07
+    assert miss(smc.recycled_log_weights(LL, gam, -lz, cnt, gam[-1])) > 0.07
+    assert miss(smc.recycled_log_weights(LL, np.full_like(gam, gam[-1]), lz, cnt, gam[-1])) > 0.07
+
+
+def test_recycled_weight_of_a_dead_member_without_a_prior_component_is_zero():
+    lw = smc.recycled_log_weights(np.array([-np.inf, -3.0]), [0.2, 0.5], [-1.0, -2.0], [4, 4], 0.5)
+    assert lw[0] == -np.inf and np.isfinite(lw[1])
