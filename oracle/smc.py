@@ -386,13 +386,17 @@ def weighted_covariance(X, log_w):
 def recycled_proposal_factor(thetas, log_w, k, l, pr):
     """Colouring factor of model (k, l) from the pooled members' parameter vectors
     (rows of `thetas`) and their recycling log-weights; the prior-scaled diagonal when
-    no more members than dimensions carry weight."""
+    the weights' effective sample size (sum w)^2 / sum w^2 is not above the dimension
+    (with equal weights: no more members than dimensions, as without recycling)."""
     d = 3 + 2 * k + 2 * l
     thetas = np.asarray(thetas, dtype=np.float64).reshape(-1, d)
     log_w = np.asarray(log_w, dtype=np.float64)
-    if np.sum(log_w > -np.inf) <= d:
-        return np.diag(0.1 * prior_sd(k, l, pr))
     live = log_w > -np.inf
+    if not live.any():
+        return np.diag(0.1 * prior_sd(k, l, pr))
+    w = np.exp(log_w[live] - np.max(log_w[live]))
+    if np.sum(w) ** 2 / np.sum(w * w) <= d:
+        return np.diag(0.1 * prior_sd(k, l, pr))
     _, C = weighted_covariance(thetas[live], log_w[live])
     return factor_of_covariance(C)
 

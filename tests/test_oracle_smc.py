@@ -443,3 +443,17 @@ def test_recycled_moments_match_the_tempered_gaussian():
 def test_recycled_weight_of_a_dead_member_without_a_prior_component_is_zero():
     lw = smc.recycled_log_weights(np.array([-np.inf, -3.0]), [0.2, 0.5], [-1.0, -2.0], [4, 4], 0.5)
     assert lw[0] == -np.inf and np.isfinite(lw[1])
+
+
+def test_recycled_factor_falls_back_when_the_weights_concentrate():
+    k, l = 1, 0
+    d = 3 + 2 * k
+    X = np.random.default_rng(5).normal(size=(40, d))
+    lw = np.full(40, -1e3)
+    lw[:3] = 0.0                                     # effective sample size 3 <= d = 5
+    F = smc.recycled_proposal_factor(X, lw, k, l, PR)
+    np.testing.assert_array_equal(F, np.diag(0.1 * smc.prior_sd(k, l, PR)))
+    lw[:8] = 0.0
+    F = smc.recycled_proposal_factor(X, lw, k, l, PR)
+    _, C = smc.weighted_covariance(X[:8], np.zeros(8))
+    np.testing.assert_allclose(F @ F.T, np.cov(X[:8], rowvar=False), rtol=1e-12, atol=1e-14)
