@@ -39,6 +39,20 @@ readings where it is silent or loose:
   The prior density cancels.  L^0 = 1, also where L = 0.  The weighted covariance is
   sum w (theta - mu)(theta - mu)^T / (1 - sum w^2) with normalised weights w, which is
   the sample covariance when the weights are equal.
+* Adaptive birth (Appendix E.2), optional: the new interface depth u_d ~ U(0, z_max)
+  fixes the insertion index r; the split segment's property is copied to the new
+  segment below the interface (the top segment of the chargeability partition is not
+  chargeable: its value is the constant 0); every component of the larger model's
+  vector except the new depth is then shifted by S[i, :] u_p, u_p ~ N(0, 1), with S the
+  symmetric (ZCA) square root of the larger model's proposal covariance and i the new
+  property's component.  |det J| = |S[i, new] - S[i, source]| (S[i, source] = 0 for the
+  constant top segment): the printed determinant's indices are read this way, which
+  the elimination of the duplicated row gives.  The death of interface r inverts the
+  map with the same S: u_p = (theta[new] - theta[source]) / (S[i, new] - S[i, source]),
+  and is rejected unless the recovered smaller state is in the support with u_d at
+  index r (so that the pair is a bijection).  Acceptance, with equal birth and death
+  probabilities and the uniform model prior: gamma (ll' - ll) + log|J| - log(range of
+  the property) - log phi(u_p) for a birth, the negative of the correction for a death.
 """
 import math
 
@@ -363,6 +377,8 @@ def recycled_log_weights(ll, gamma_hist, log_z_hist, count_hist, gamma_t):
     whose evidence estimate log Z_l is finite."""
     ll = np.asarray(ll, dtype=np.float64)
     comps = [q for q in range(len(gamma_hist)) if count_hist[q] > 0 and np.isfinite(log_z_hist[q])]
+    if not comps:
+        return np.full(ll.shape, -np.inf)
     terms = np.stack([math.log(count_hist[q]) + _tempered(gamma_hist[q], ll) - log_z_hist[q] for q in comps])
     num = _tempered(gamma_t, ll)
     m = np.max(terms, axis=0)
@@ -401,6 +417,91 @@ def recycled_proposal_factor(thetas, log_w, k, l, pr):
     return factor_of_covariance(C)
 
 
+# ------------------------------------------------------------ adaptive birth (O-16)
+def zca_row(F, i):
+    """Row i of the symmetric square root S = U Lambda^1/2 U^T of the covariance F F^T,
+    from its factor F = U Lambda^1/2 (columns f_r = u_r sqrt(lambda_r)):
+    S = sum_r f_r f_r^T / |f_r| over the nonzero columns, added in column order with
+    separately rounded products."""
+    d = F.shape[0]
+    row = np.zeros(d)
+    for r in range(d):
+        col = F[:, r]
+        n2 = 0.0
+        for a in range(d):
+            n2 += float(col[a]) * float(col[a])
+        if n2 > 0.0:
+            w = float(F[i, r]) / math.sqrt(n2)
+            row = row + w * col
+    return row
+
+
+def _log_normal_pdf(x):
+    return -0.5 * x * x - 0.5 * math.log(2.0 * math.pi)
+
+
+def _zca_indices(k, l, part, r):
+    """(new property component, source component or None, new depth component) in the
+    vector of the larger model (k, l) for the interface at index r of partition `part`
+    (0 conductivity, 1 chargeability)."""
+    if part == 0:
+        return r + 1, r, 1 + k + r
+    jn = 1 + 2 * k + r
+    return jn, (jn - 1 if r >= 1 else None), 1 + 2 * k + l + r
+
+
+def zca_birth(theta, k, l, part, zn, up, F_big, pr):
+    """Adaptive birth of an interface at depth zn in partition `part` of model (k, l)
+    (Appendix E.2): (theta', k', l', log proposal correction) or None."""
+    theta = np.asarray(theta, dtype=np.float64)
+    if part == 0:
+        z = theta[1 + k:1 + 2 * k]
+        r = int(np.searchsorted(z, zn, side="left"))
+        src = theta[r]                                   # phi_b for r = 0
+        base = np.concatenate([theta[:r + 1], [src], theta[r + 1:1 + k + r], [zn], theta[1 + k + r:]])
+        kb, lb = k + 1, l
+        dv = pr["phi_hi"] - pr["phi_lo"]
+    else:
+        zm = theta[1 + 2 * k + l:1 + 2 * k + 2 * l]
+        r = int(np.searchsorted(zm, zn, side="left"))
+        src = theta[1 + 2 * k + r - 1] if r >= 1 else 0.0
+        mo, zo = 1 + 2 * k, 1 + 2 * k + l
+        base = np.concatenate([theta[:mo + r], [src], theta[mo + r:zo + r], [zn], theta[zo + r:]])
+        kb, lb = k, l + 1
+        dv = pr["m_hi"] - pr["m_lo"]
+    jn, js, jz = _zca_indices(kb, lb, part, r)
+    S = zca_row(F_big, jn)
+    shift = S * up
+    shift[jz] = 0.0
+    th = base + shift
+    J = S[jn] - (S[js] if js is not None else 0.0)
+    if J == 0.0:
+        return None
+    return th, kb, lb, math.log(abs(J)) - math.log(dv) - _log_normal_pdf(up)
+
+
+def zca_death(theta, k, l, part, r, F_cur, pr):
+    """Adaptive death of interface r of partition `part` of model (k, l), the inverse of
+    zca_birth with the current model's S: (theta', k', l', log correction) or None."""
+    theta = np.asarray(theta, dtype=np.float64)
+    jn, js, jz = _zca_indices(k, l, part, r)
+    S = zca_row(F_cur, jn)
+    J = S[jn] - (S[js] if js is not None else 0.0)
+    if J == 0.0:
+        return None
+    up = (theta[jn] - (theta[js] if js is not None else 0.0)) / J
+    th = theta - S * up
+    th[jz] = theta[jz]
+    ud = theta[jz]
+    small = np.delete(th, [jn, jz])
+    ks, ls = (k - 1, l) if part == 0 else (k, l - 1)
+    zs = small[1 + ks:1 + 2 * ks] if part == 0 else small[1 + 2 * ks + ls:1 + 2 * ks + 2 * ls]
+    if int(np.searchsorted(zs, ud, side="left")) != r or np.any(zs == ud):
+        return None
+    dv = (pr["phi_hi"] - pr["phi_lo"]) if part == 0 else (pr["m_hi"] - pr["m_lo"])
+    return small, ks, ls, -(math.log(abs(J)) - math.log(dv) - _log_normal_pdf(up))
+
+
 # ---------------------------------------------------------------------- mutation (O-11)
 def _birth(z, v, zn, vn, cap):
     if len(z) >= cap:
@@ -423,6 +524,20 @@ def propose(p, i, step, move, seed, q, pr, kmax_cond, kmax_charg, factor):
     zc, ph = p["z_cond"][:k, i].copy(), p["phi"][:k, i].copy()
     zm, mm = p["z_charg"][:l, i].copy(), p["m"][:l, i].copy()
     new = None
+    if q.get("zca") and t in (0, 1, 3, 4):            # adaptive birth / death (Appendix E.2)
+        part = 0 if t in (0, 1) else 1
+        theta = param_vector(p, i)
+        res = None
+        if t in (0, 3) and (k < kmax_cond if part == 0 else l < kmax_charg):
+            kb, lb = (k + 1, l) if part == 0 else (k, l + 1)
+            res = zca_birth(theta, k, l, part, pr["z_max"] * u1, normal_pair(u2, u3)[0],
+                            q["factor_of_model"](i, kb, lb), pr)
+        elif t in (1, 4) and (k if part == 0 else l) > 0:
+            n_if = k if part == 0 else l
+            res = zca_death(theta, k, l, part, min(int(u1 * n_if), n_if - 1), q["factor_of_model"](i, k, l), pr)
+        if res is not None and in_support(res[0], res[1], res[2], pr):
+            new = dict(kappa=res[1], lambda_=res[2], theta=res[0], log_q=res[3])
+        return t, new, ua
     if t in (0, 3):                                   # birth
         zn = pr["z_max"] * u1
         if t == 0:
@@ -488,6 +603,10 @@ def mala_log_q_ratio(xi, grad_ll, grad_ll_new, gamma, factor, eps):
 
 def apply_state(p, i, new):
     if "theta" in new:
+        if "kappa" in new:                            # a move between models
+            p["kappa"][i], p["lambda_"][i] = new["kappa"], new["lambda_"]
+            for key in ("z_cond", "phi", "z_charg", "m"):
+                p[key][:, i] = 0.0
         set_param_vector(p, i, new["theta"])
         return
     k, l = len(new["z_cond"]), len(new["z_charg"])
@@ -551,6 +670,7 @@ def mutate(p, ll, loglik_fn, gamma_of, step, seed, q, pr, kmax_cond, kmax_charg,
             else:
                 apply_state(p, i, new)
                 ll_new = loglik_fn(p, i)
+                extra = new.get("log_q", 0.0)
             margin = gamma_of(i) * (ll_new - ll[i]) + extra - math.log(ua)
             margins.append((i, r, margin))
             if margin > 0.0 and trial > 0:

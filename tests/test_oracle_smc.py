@@ -457,3 +457,104 @@ def test_recycled_factor_falls_back_when_the_weights_concentrate():
     F = smc.recycled_proposal_factor(X, lw, k, l, PR)
     _, C = smc.weighted_covariance(X[:8], np.zeros(8))
     np.testing.assert_allclose(F @ F.T, np.cov(X[:8], rowvar=False), rtol=1e-12, atol=1e-14)
+
+
+# -------------------------------------------------------------------- adaptive birth
+def _random_factor(d, seed, scale=None):
+    rng = np.random.default_rng(seed)
+    A = rng.normal(size=(d, d)) * (scale if scale is not None else 1.0)
+    return np.linalg.qr(A)[0] * rng.uniform(0.05, 0.6, d)[None, :]
+
+
+def test_zca_row_is_the_symmetric_square_root():
+    F = _random_factor(9, 1)
+    F[:, 4] = 0.0                                    # a zero direction contributes nothing
+    S = np.array([smc.zca_row(F, i) for i in range(9)])
+    np.testing.assert_allclose(S, S.T, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(S @ S, F @ F.T, rtol=0, atol=1e-14)
+    assert np.all(np.linalg.eigvalsh(S) > -1e-15)
+    D = np.diag([0.3, 2.0, 0.0, 5.0])
+    np.testing.assert_array_equal(np.array([smc.zca_row(D, i) for i in range(4)]), D)
+
+
+@pytest.mark.parametrize("part", [0, 1])
+def test_zca_birth_then_death_is_the_identity(part):
+    """The death of the interface a birth inserted, with the same covariance root,
+    recovers the smaller state and negates the log proposal correction."""
+    rng = np.random.default_rng(7 + part)
+    p = smc.init_population(31 + part, 400, 4, 3, PR)
+    done = 0
+    for i in range(400):
+        k, l = int(p["kappa"][i]), int(p["lambda_"][i])
+        if (part == 0 and k == 4) or (part == 1 and l == 3):
+            continue
+        kb, lb = (k + 1, l) if part == 0 else (k, l + 1)
+        F = _random_factor(3 + 2 * kb + 2 * lb, i) * 0.05
+        theta = smc.param_vector(p, i)
+        zn, up = rng.uniform(0, PR["z_max"]), rng.normal()
+        res = smc.zca_birth(theta, k, l, part, zn, up, F, PR)
+        if res is None or not smc.in_support(res[0], res[1], res[2], PR):
+            continue
+        th1, k1, l1, lq = res
+        z1 = th1[1 + k1:1 + 2 * k1] if part == 0 else th1[1 + 2 * k1 + l1:1 + 2 * k1 + 2 * l1]
+        r = int(np.nonzero(z1 == zn)[0][0])
+        back = smc.zca_death(th1, k1, l1, part, r, F, PR)
+        assert back is not None
+        np.testing.assert_allclose(back[0], theta, rtol=1e-12, atol=1e-12)
+        assert (back[1], back[2]) == (k, l)
+        assert abs(back[3] + lq) < 1e-9
+        done += 1
+    assert done > 100
+
+
+def _zca_invariance(monkeypatch=None, drop_jacobian=False, n=3000, sweeps=10):
+    p = smc.init_population(17, n, 4, 3, PR)
+    ll = np.zeros(n)
+    facs = {}
+
+    def factor_of_model(i, k, l):
+        if (k, l) not in facs:
+            d = 3 + 2 * k + 2 * l
+            R = np.random.default_rng(100 + 10 * k + l).normal(size=(d, d))
+            facs[(k, l)] = np.diag(smc.prior_sd(k, l, PR)) @ (np.eye(d) + 0.3 * R)
+        return facs[(k, l)]
+
+    if drop_jacobian:
+        orig = smc.zca_birth
+
+        def no_jacobian(theta, k, l, part, zn, up, F_big, pr):
+            res = orig(theta, k, l, part, zn, up, F_big, pr)
+            if res is None:
+                return None
+            jn, js, _ = smc._zca_indices(res[1], res[2], part, 0)
+            S = smc.zca_row(F_big, jn)
+            return res[0], res[1], res[2], res[3] - math.log(abs(S[jn] - (S[js] if js is not None else 0.0)))
+        monkeypatch.setattr(smc, "zca_birth", no_jacobian)
+    q = _q([1, 1, 0, 1, 1, 0, 1, 0])
+    q["zca"] = True
+    q["factor_of_model"] = factor_of_model
+    fac = lambda i: factor_of_model(i, int(p["kappa"][i]), int(p["lambda_"][i]))
+    st, _ = smc.mutate(p, ll, lambda pp, i: 0.0, lambda i: 0.0, 1, 19, q, PR, 4, 3, fac, sweeps)
+    return p, st
+
+
+@pytest.mark.slow
+def test_zca_moves_preserve_the_prior_at_zero_temperature(monkeypatch):
+    """With gamma = 0 the adaptive birth and death (with random covariance roots per
+    model) leave the prior invariant: uniform model counts and uniform properties and
+    depths.  The same chain without the Jacobian term drifts away from it."""
+    p, st = _zca_invariance()
+    assert st[1, 0] > 0.05 * st[0, 0] and st[1, 1] > 0.05 * st[0, 1]
+    ck = np.bincount(p["kappa"], minlength=5)
+    cl = np.bincount(p["lambda_"], minlength=4)
+    assert stats.chisquare(ck).pvalue > 1e-3 and stats.chisquare(cl).pvalue > 1e-3, (ck, cl)
+    zs = np.concatenate([p["z_cond"][:k, i] for i, k in enumerate(p["kappa"])])
+    assert stats.kstest(zs / PR["z_max"], "uniform").pvalue > 1e-3
+    phs = np.concatenate([[p["phi_b"][i]] + list(p["phi"][:k, i]) for i, k in enumerate(p["kappa"])])
+    assert stats.kstest((phs - PR["phi_lo"]) / (PR["phi_hi"] - PR["phi_lo"]), "uniform").pvalue > 1e-3
+    ms = np.concatenate([p["m"][:l, i] for i, l in enumerate(p["lambda_"])])
+    assert stats.kstest((ms - PR["m_lo"]) / (PR["m_hi"] - PR["m_lo"]), "uniform").pvalue > 1e-3
+    p2, _ = _zca_invariance(monkeypatch, drop_jacobian=True)
+    ck2 = np.bincount(p2["kappa"], minlength=5)
+    cl2 = np.bincount(p2["lambda_"], minlength=4)
+    assert min(stats.chisquare(ck2).pvalue, stats.chisquare(cl2).pvalue) < 1e-6, (ck2, cl2)
