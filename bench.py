@@ -169,7 +169,35 @@ def rjsmc_rate(torch, d, n_sound, n_per_sound, seed=0, move_prob=None, graph=Fal
         fin = np.isfinite(lz[:, best])
         out["log_z_best_sd"] = float(np.std(lz[fin, best])) if fin.any() else None
         out["log_z_best_finite"] = int(fin.sum())
+        # marginal evidence log p(y) = log (1/M) sum_k Z_k (uniform model prior), per replicate
+        mx = np.max(np.where(np.isfinite(lz), lz, -np.inf), axis=1)
+        lpy = mx + np.log(np.sum(np.exp(np.where(np.isfinite(lz), lz - mx[:, None], -np.inf)), axis=1)) - np.log(
+            lz.shape[1])
+        out["log_evidence_mean"] = float(np.mean(lpy))
+        out["log_evidence_sd"] = float(np.std(lpy))
+        out["p_best_model_mean"] = float(np.mean(probs[:, best]))
+        out["p_best_model_sd"] = float(np.std(probs[:, best]))
     return out
+
+
+def accuracy_comparison(torch, d, sizes=(256, 512, 1024), reps=32, adapt_c=0.01, r_max=40):
+    """Random-walk against gradient-informed (Langevin) within-model moves on the same
+    GPU: `reps` replicate runs of the synthetic sounding (batched) for each particle count,
+    with the adaptive number of sweeps (c = 0.01: every particle moves with probability
+    0.99) and tuned tiles.  The spread over replicates of the marginal log-evidence and of
+    the best model's posterior probability measures accuracy; soundings/s the cost."""
+    from paper_2109_00661_amd.rjsmc import UNIFORM_MOVES, LANGEVIN_MOVES
+    rows = []
+    for name, mp in (("random_walk", UNIFORM_MOVES), ("langevin", LANGEVIN_MOVES)):
+        for n in sizes:
+            r = rjsmc_rate(torch, d, reps, n, move_prob=mp, graph=True, tune=True, adapt_c=adapt_c, r_max=r_max)
+            row = {"moves": name, "particles_per_sounding": n}
+            row.update({k: r[k] for k in ("soundings_per_s", "steps", "sweeps_per_step_mean", "acceptance",
+                                          "log_evidence_mean", "log_evidence_sd", "best_model", "p_best_model_mean",
+                                          "p_best_model_sd", "ll_max_median")})
+            print(json.dumps(row), file=sys.stderr, flush=True)
+            rows.append(row)
+    return rows
 
 
 def survey_run(torch, precision, move_prob, n_per_sound=2048, seed=0):
@@ -269,6 +297,8 @@ def main():
     ap.add_argument("--extra", action="store_true")
     ap.add_argument("--survey", action="store_true",
                     help="also run the 2,000-sounding synthetic survey (FP64, FP32-forward, Langevin; minutes)")
+    ap.add_argument("--compare", action="store_true",
+                    help="also compare random-walk and Langevin moves at several particle counts (minutes)")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the 65,536-particle forward+loglik launches (for profiling)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -337,6 +367,8 @@ def main():
                                                      tune=True)}
     if args.survey:
         out["survey"] = survey(torch)
+    if args.compare:
+        out["moves_accuracy_comparison"] = accuracy_comparison(torch, d)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(system, d.cpu().numpy())
     print(json.dumps(out), flush=True)

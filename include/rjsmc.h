@@ -219,6 +219,48 @@ rjsmc_status rjsmc_reweight_resample(rjsmc_ctx *ctx, const rjsmc_reweight_args *
 rjsmc_status rjsmc_adapt(rjsmc_ctx *ctx, const rjsmc_particles *p, int32_t n_sound,
                          const rjsmc_prior *prior, double *factors, rjsmc_stream stream);
 
+/* Archive of earlier populations for particle recycling (Section 3.2.5).  Slot h holds
+ * the population of an earlier step, in the layout of the current one (n = n_sound
+ * n_per_sounding particles, soundings contiguous):
+ *   particle i of slot h is column h n + i of `pop` (pop.n = n_slots n, pop.stride >=
+ *   pop.n; its n_per_sounding is ignored), its log-likelihood ll[h n + i];
+ *   gamma[h n_sound + s] is the temperature that slot's population targets and
+ *   log_z[(h n_sound + s) n_models + k] the evidence estimate log Z_{h,k} of model k
+ *   at that temperature.
+ * Slots 0 .. n_used - 1 are read; n_used <= n_slots <= RJSMC_MAX_ARCHIVE.  All arrays
+ * are device memory owned by the caller. */
+#define RJSMC_MAX_ARCHIVE 64
+typedef struct {
+  rjsmc_particles pop;
+  double *ll;
+  double *gamma;
+  double *log_z;
+  int32_t n_slots, n_used;
+} rjsmc_archive;
+
+/* Copies population p (n particles, its ll, and the per-sounding gamma[n_sound] and
+ * log_z[n_sound][n_models]) into slot `slot` of the archive (0 <= slot < n_slots).
+ * RJSMC_E_INVALID on shape mismatch; does not change n_used. */
+rjsmc_status rjsmc_archive_store(rjsmc_ctx *ctx, const rjsmc_particles *p, const double *ll,
+                                 const double *gamma, const double *log_z, int32_t n_sound,
+                                 rjsmc_archive *archive, int32_t slot, rjsmc_stream stream);
+
+/* Proposal factors from recycled particles (Section 3.2.5 with Section 3.2.3).  For
+ * each (sounding s, model k) the members of model k in the current population p (with
+ * log-likelihoods ll, temperature gamma[s], evidence log_z[s][k]) and in the archive's
+ * used slots are pooled and weighted by the deterministic mixture
+ *   nu = L^gamma_t / sum_l N_l L^gamma_l / Z_{l,k}
+ * over the sources l (slots and the current population) that hold N_l > 0 members of
+ * model k and a finite log Z_{l,k} (L^0 = 1; the prior density cancels).  F is the
+ * factor (as in rjsmc_adapt) of the weighted covariance sum w (theta - mu)(theta -
+ * mu)^T / (1 - sum w^2), normalised weights w; 0.1 diag(prior sd) when the weights'
+ * effective sample size (sum w)^2 / sum w^2 is not above d.  With an empty archive the
+ * weights are equal and F is that of rjsmc_adapt (up to rounding). */
+rjsmc_status rjsmc_adapt_recycled(rjsmc_ctx *ctx, const rjsmc_particles *p, const double *ll,
+                                  const double *gamma, const double *log_z, int32_t n_sound,
+                                  const rjsmc_archive *archive, const rjsmc_prior *prior,
+                                  double *factors, rjsmc_stream stream);
+
 /* Move types of the RJ-MCMC kernel (Appendix E.1; Section 3.2.3). */
 enum {
   RJSMC_MOVE_SIGMA_BIRTH = 0, RJSMC_MOVE_SIGMA_DEATH = 1, RJSMC_MOVE_SIGMA_MOVE = 2,
@@ -245,6 +287,20 @@ typedef struct {
   int32_t trial;                /* 0: the sweeps of Algorithm 1.  b >= 1: trial proposals
                                    (Section 3.2.3) decided and counted but never kept, with
                                    random-number move index b * 2^20 + r */
+  int32_t zca_birth;            /* 0: a birth draws the new property from its prior.  1: the
+                                   adaptive birth and death of Appendix E.2: the new depth
+                                   u_d = z_max u fixes the insertion index r, the split
+                                   segment's property (0 above the first chargeability
+                                   interface) is copied below the new interface, and every
+                                   other component of the larger model's vector is shifted
+                                   by S[i, :] u_p, u_p ~ N(0, 1), with S = sum_r f_r f_r^T /
+                                   |f_r| the symmetric root of the larger model's F F^T
+                                   (from `factors`) and i the new property's component;
+                                   the MH ratio gains log|S[i, new] - S[i, source]| -
+                                   log(prior range) - log phi(u_p) (its negative for the
+                                   death, which inverts the map with the same S and is
+                                   rejected unless the recovered state is in the support
+                                   with u_d at index r) */
 } rjsmc_mutate_args;
 
 /* n_moves RJ-MCMC sweeps (Algorithm 1, mutation) targeting L^gamma(sounding) x prior.

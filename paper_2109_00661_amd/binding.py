@@ -65,7 +65,8 @@ class MutateArgs(ctypes.Structure):
                 ("n_sound", ctypes.c_int32), ("move_prob", ctypes.c_double * N_MOVES),
                 ("z_move_sd", ctypes.c_double), ("rw_scale", ctypes.c_double), ("mala_eps", ctypes.c_double),
                 ("factors", ctypes.c_void_p), ("prior", Prior), ("step_dev", ctypes.c_void_p),
-                ("rw_scale_dev", ctypes.c_void_p), ("stats_sound", ctypes.c_void_p), ("trial", ctypes.c_int32)]
+                ("rw_scale_dev", ctypes.c_void_p), ("stats_sound", ctypes.c_void_p), ("trial", ctypes.c_int32),
+                ("zca_birth", ctypes.c_int32)]
 
 
 class BisectArgs(ctypes.Structure):
@@ -78,6 +79,14 @@ class SummaryArgs(ctypes.Structure):
     _fields_ = [("n_sound", ctypes.c_int32), ("n_depth", ctypes.c_int32), ("depth_m", ctypes.c_void_p),
                 ("model_count", ctypes.c_void_p), ("log_bfipd", ctypes.c_void_p),
                 ("mean_log10_sigma", ctypes.c_void_p), ("mean_m", ctypes.c_void_p), ("p_chargeable", ctypes.c_void_p)]
+
+
+class Archive(ctypes.Structure):
+    _fields_ = [("pop", Particles), ("ll", ctypes.c_void_p), ("gamma", ctypes.c_void_p), ("log_z", ctypes.c_void_p),
+                ("n_slots", ctypes.c_int32), ("n_used", ctypes.c_int32)]
+
+
+MAX_ARCHIVE = 64
 
 
 class Tuning(ctypes.Structure):
@@ -118,6 +127,12 @@ _SIGS = {
                                                ctypes.c_void_p]),
     "rjsmc_adapt": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_int32, ctypes.POINTER(Prior),
                                    ctypes.c_void_p, ctypes.c_void_p]),
+    "rjsmc_archive_store": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Archive),
+                                           ctypes.c_int32, ctypes.c_void_p]),
+    "rjsmc_adapt_recycled": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Archive),
+                                            ctypes.POINTER(Prior), ctypes.c_void_p, ctypes.c_void_p]),
     "rjsmc_mutate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MutateArgs), ctypes.POINTER(Particles),
                                     ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Particles),
@@ -353,9 +368,22 @@ class Context:
         _check(lib().rjsmc_adapt(self._ptr, ctypes.byref(ps), n_sound, ctypes.byref(pr), _ptr(factors),
                                  _stream_handle(stream)))
 
+    def archive_store(self, p, ll, gamma, log_z, n_sound, archive, slot, stream=None):
+        ps = particles_struct(p)
+        a = archive.struct()
+        _check(lib().rjsmc_archive_store(self._ptr, ctypes.byref(ps), _ptr(ll), _ptr(gamma), _ptr(log_z), n_sound,
+                                         ctypes.byref(a), int(slot), _stream_handle(stream)))
+
+    def adapt_recycled(self, p, ll, gamma, log_z, n_sound, archive, prior, factors, stream=None):
+        ps = particles_struct(p)
+        a = archive.struct()
+        pr = make_prior(prior)
+        _check(lib().rjsmc_adapt_recycled(self._ptr, ctypes.byref(ps), _ptr(ll), _ptr(gamma), _ptr(log_z), n_sound,
+                                          ctypes.byref(a), ctypes.byref(pr), _ptr(factors), _stream_handle(stream)))
+
     def mutate(self, state, ll, scratch, ll_scratch, gamma, active, y_obs, stats, *, seed, step, n_moves, n_sound,
                prior, move_prob, z_move_sd, rw_scale, factors, mala_eps=0.0, grad_cur=None, grad_prop=None,
-               stream=None, step_dev=None, rw_scale_dev=None, stats_sound=None, trial=0):
+               stream=None, step_dev=None, rw_scale_dev=None, stats_sound=None, trial=0, zca_birth=False):
         a = MutateArgs()
         a.seed, a.step, a.n_moves, a.n_sound = seed, step, n_moves, n_sound
         for t in range(N_MOVES):
@@ -367,6 +395,7 @@ class Context:
         a.rw_scale_dev = _ptr(rw_scale_dev) if rw_scale_dev is not None else None
         a.stats_sound = _ptr(stats_sound) if stats_sound is not None else None
         a.trial = int(trial)
+        a.zca_birth = 1 if zca_birth else 0
         ss, sq = particles_struct(state), particles_struct(scratch)
         gc = ctypes.byref(particles_struct(grad_cur)) if grad_cur is not None else None
         gp = ctypes.byref(particles_struct(grad_prop)) if grad_prop is not None else None
@@ -384,6 +413,26 @@ def empty_device_population(n, kmax_cond, kmax_charg, n_per_sounding=0, device="
             "lambda_": torch.zeros(n, dtype=torch.int32, device=device),
             "phi_b": f(n), "phi": f(kmax_cond, n), "z_cond": f(kmax_cond, n), "m": f(kmax_charg, n),
             "z_charg": f(kmax_charg, n), "log10_tau": f(n), "c": f(n)}
+
+
+class DeviceArchive:
+    """Device buffers of a particle archive of n_slots populations of n particles
+    (n_sound soundings); n_used slots are read by Context.adapt_recycled."""
+
+    def __init__(self, n_slots, n, n_sound, kmax_cond, kmax_charg, device="cuda"):
+        import torch
+        if not 1 <= n_slots <= MAX_ARCHIVE:
+            raise ValueError("n_slots must be in 1..%d" % MAX_ARCHIVE)
+        M = (kmax_cond + 1) * (kmax_charg + 1)
+        self.n_slots, self.n, self.n_sound, self.n_used = n_slots, n, n_sound, 0
+        self.pop = empty_device_population(n_slots * n, kmax_cond, kmax_charg, 0, device)
+        self.ll = torch.zeros(n_slots * n, dtype=torch.float64, device=device)
+        self.gamma = torch.zeros((n_slots, n_sound), dtype=torch.float64, device=device)
+        self.log_z = torch.zeros((n_slots, n_sound, M), dtype=torch.float64, device=device)
+
+    def struct(self):
+        return Archive(particles_struct(self.pop), _ptr(self.ll), _ptr(self.gamma), _ptr(self.log_z), self.n_slots,
+                       self.n_used)
 
 
 def population_to_host(p):

@@ -283,6 +283,7 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
   c->work_perm = nullptr;
   c->work_cnt = nullptr;
   c->work_gvalid = nullptr;
+  c->work_lq = nullptr;
   c->tuning.waves_per_block = 4;
   c->tuning.layer_sort = 0;
   c->tuning.waves_per_particle = 1;
@@ -292,6 +293,7 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
     if (e == hipSuccess) e = hipMalloc((void **)&c->work_type, sizeof(int32_t) * c->work_n);
     if (e == hipSuccess) e = hipMalloc((void **)&c->work_perm, sizeof(int32_t) * c->work_n);
     if (e == hipSuccess) e = hipMalloc((void **)&c->work_gvalid, sizeof(int32_t) * c->work_n);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->work_lq, sizeof(double) * c->work_n);
     if (e == hipSuccess) e = hipMalloc((void **)&c->work_cnt, sizeof(int) * 2 * rjsmc::kMaxLayers);
   }
   if (e != hipSuccess) {
@@ -300,6 +302,7 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
     if (c->work_perm) (void)hipFree(c->work_perm);
     if (c->work_cnt) (void)hipFree(c->work_cnt);
     if (c->work_gvalid) (void)hipFree(c->work_gvalid);
+    if (c->work_lq) (void)hipFree(c->work_lq);
     free_dev(d);
     delete[] c->K_host;
     delete c;
@@ -317,6 +320,7 @@ extern "C" void rjsmc_destroy(rjsmc_ctx *c) {
   if (c->work_perm) (void)hipFree(c->work_perm);
   if (c->work_cnt) (void)hipFree(c->work_cnt);
   if (c->work_gvalid) (void)hipFree(c->work_gvalid);
+  if (c->work_lq) (void)hipFree(c->work_lq);
   free_dev(c->dev);
   delete[] c->K_host;
   delete c;
@@ -572,6 +576,74 @@ extern "C" rjsmc_status rjsmc_adapt(rjsmc_ctx *c, const rjsmc_particles *p, int3
   return RJSMC_OK;
 }
 
+// Archive of a current population p (n particles): shapes, slots and arrays.
+static rjsmc_status check_archive(const rjsmc_ctx *c, const rjsmc_archive *ar, const rjsmc_particles *p,
+                                  const char *who, rjsmc::DevParticles *dpop) {
+  if (!ar) return fail(RJSMC_E_INVALID, "%s: NULL archive", who);
+  if (ar->n_slots < 1 || ar->n_slots > RJSMC_MAX_ARCHIVE)
+    return fail(RJSMC_E_INVALID, "%s: n_slots=%d outside 1..%d", who, ar->n_slots, RJSMC_MAX_ARCHIVE);
+  if (ar->n_used < 0 || ar->n_used > ar->n_slots)
+    return fail(RJSMC_E_INVALID, "%s: n_used=%d outside 0..n_slots", who, ar->n_used);
+  const rjsmc_status st = check_particles(c, &ar->pop, who, dpop);
+  if (st != RJSMC_OK) return st;
+  if (ar->pop.layout != p->layout) return fail(RJSMC_E_INVALID, "%s: archive layout differs", who);
+  if (ar->pop.n != (int64_t)ar->n_slots * p->n)
+    return fail(RJSMC_E_INVALID, "%s: archive holds %lld particles, not n_slots x %lld", who, (long long)ar->pop.n,
+                (long long)p->n);
+  if (!ar->ll || !ar->gamma || !ar->log_z) return fail(RJSMC_E_INVALID, "%s: NULL archive array", who);
+  return RJSMC_OK;
+}
+
+extern "C" rjsmc_status rjsmc_archive_store(rjsmc_ctx *c, const rjsmc_particles *p, const double *ll,
+                                            const double *gamma, const double *log_z, int32_t n_sound,
+                                            rjsmc_archive *ar, int32_t slot, rjsmc_stream stream) {
+  const char *who = "rjsmc_archive_store";
+  if (!c || !ll || !gamma || !log_z) return fail(RJSMC_E_INVALID, "%s: NULL argument", who);
+  rjsmc::DevParticles dp, dpop;
+  rjsmc_status st = check_particles(c, p, who, &dp);
+  if (st != RJSMC_OK) return st;
+  if (p->layout != RJSMC_LAYOUT_DECOUPLED) return fail(RJSMC_E_INVALID, "%s: DECOUPLED layout only", who);
+  if ((st = check_soundings(p, n_sound, who)) != RJSMC_OK) return st;
+  if ((st = check_archive(c, ar, p, who, &dpop)) != RJSMC_OK) return st;
+  if (slot < 0 || slot >= ar->n_slots) return fail(RJSMC_E_INVALID, "%s: slot %d outside 0..%d", who, slot,
+                                                   ar->n_slots - 1);
+  const rjsmc::SmcShape sh = smc_shape(c);
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess)
+    e = rjsmc::launch_archive_store(dp, ll, gamma, log_z, n_sound, sh.n_models, writable(dpop), ar->ll, ar->gamma,
+                                    ar->log_z, slot, c->kmax_cond, c->kmax_charg, c->kmax_charg,
+                                    (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "rjsmc_archive_store: launch");
+  return RJSMC_OK;
+}
+
+extern "C" rjsmc_status rjsmc_adapt_recycled(rjsmc_ctx *c, const rjsmc_particles *p, const double *ll,
+                                             const double *gamma, const double *log_z, int32_t n_sound,
+                                             const rjsmc_archive *ar, const rjsmc_prior *prior, double *factors,
+                                             rjsmc_stream stream) {
+  const char *who = "rjsmc_adapt_recycled";
+  if (!c || !factors || !ll || !gamma || !log_z) return fail(RJSMC_E_INVALID, "%s: NULL argument", who);
+  rjsmc::DevParticles dp, dpop;
+  rjsmc_status st = check_particles(c, p, who, &dp);
+  if (st != RJSMC_OK) return st;
+  if (p->layout != RJSMC_LAYOUT_DECOUPLED) return fail(RJSMC_E_INVALID, "%s: DECOUPLED layout only", who);
+  if ((st = check_prior(prior, who)) != RJSMC_OK) return st;
+  if ((st = check_soundings(p, n_sound, who)) != RJSMC_OK) return st;
+  if ((st = check_archive(c, ar, p, who, &dpop)) != RJSMC_OK) return st;
+  rjsmc::ArchiveView av;
+  av.pop = dpop;
+  av.ll = ar->ll;
+  av.gamma = ar->gamma;
+  av.log_z = ar->log_z;
+  av.n_used = ar->n_used;
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess)
+    e = rjsmc::launch_adapt_recycled(smc_shape(c), dp, ll, gamma, log_z, n_sound, av, *prior, factors,
+                                     (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "rjsmc_adapt_recycled: launch");
+  return RJSMC_OK;
+}
+
 static rjsmc_status grad_buffer(const rjsmc_ctx *c, const rjsmc_particles *g, const rjsmc_particles *like,
                                 const char *who, rjsmc::DevParticles *dp, rjsmc::DevGrad *dg) {
   rjsmc_particles tmp = *g;
@@ -617,6 +689,8 @@ extern "C" rjsmc_status rjsmc_mutate(rjsmc_ctx *c, const rjsmc_mutate_args *a, r
   const bool mala = a->move_prob[RJSMC_MOVE_WITHIN_MALA] > 0;
   if ((a->move_prob[RJSMC_MOVE_WITHIN_RW] > 0 || mala) && !a->factors)
     return fail(RJSMC_E_INVALID, "%s: within-model moves need proposal factors", who);
+  if (a->zca_birth != 0 && a->zca_birth != 1) return fail(RJSMC_E_INVALID, "%s: zca_birth must be 0 or 1", who);
+  if (a->zca_birth && !a->factors) return fail(RJSMC_E_INVALID, "%s: adaptive births need proposal factors", who);
   if (!(a->z_move_sd >= 0) || !(a->rw_scale >= 0) || !(a->mala_eps >= 0))
     return fail(RJSMC_E_INVALID, "%s: bad step sizes", who);
   rjsmc::DevParticles gcd, gpd;
@@ -651,14 +725,14 @@ extern "C" rjsmc_status rjsmc_mutate(rjsmc_ctx *c, const rjsmc_mutate_args *a, r
       e = rjsmc::launch_loglik_grad(c->dev, cur2, c->kmax_cond, c->kmax_charg, y_obs, ll_scratch, gcw, s);
     if (e == hipSuccess)
       e = rjsmc::launch_propose(sh, *a, r, ds, writable(dq), c->work_mask, c->work_type, gamma, mala ? &gcd : nullptr,
-                                gvalid, s);
+                                gvalid, c->work_lq, s);
     if (e == hipSuccess)
       e = run_forward(c, prop1, c->tuning, nullptr, y_obs, ll_scratch, s);
     if (e == hipSuccess && mala)
       e = rjsmc::launch_loglik_grad(c->dev, prop2, c->kmax_cond, c->kmax_charg, y_obs, ll_scratch, gpw, s);
     if (e == hipSuccess)
       e = rjsmc::launch_accept(sh, *a, r, writable(ds), ll, dq, ll_scratch, c->work_mask, c->work_type, gamma,
-                               mala ? &gcw_state : nullptr, mala ? &gpd : nullptr, gvalid, stats, s);
+                               mala ? &gcw_state : nullptr, mala ? &gpd : nullptr, gvalid, stats, c->work_lq, s);
   }
   if (e != hipSuccess) return hip_fail(e, "rjsmc_mutate: launch");
   return RJSMC_OK;

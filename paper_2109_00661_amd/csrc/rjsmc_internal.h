@@ -120,16 +120,32 @@ hipError_t launch_reweight_resample(const SmcShape &sh, const rjsmc_reweight_arg
                                     double *log_z, int32_t *active, int32_t *anc, int *flags, hipStream_t stream);
 hipError_t launch_adapt(const SmcShape &sh, const DevParticles &p, int n_sound, const rjsmc_prior &pr,
                         double *factors, hipStream_t stream);
+
+// Used slots of a particle archive: slot h is columns h n .. h n + n - 1 of pop (n the
+// current population's size), ll likewise, gamma [slot][n_sound], log_z [slot][n_sound][M].
+constexpr int kMaxArchive = RJSMC_MAX_ARCHIVE;
+struct ArchiveView {
+  DevParticles pop;
+  const double *ll = nullptr, *gamma = nullptr, *log_z = nullptr;
+  int n_used = 0;
+};
+hipError_t launch_adapt_recycled(const SmcShape &sh, const DevParticles &p, const double *ll, const double *gamma,
+                                 const double *log_z, int n_sound, const ArchiveView &ar, const rjsmc_prior &pr,
+                                 double *factors, hipStream_t stream);
+hipError_t launch_archive_store(const DevParticles &src, const double *ll, const double *gamma, const double *log_z,
+                                int n_sound, int n_models, const DevParticlesW &dst, double *ll_dst, double *gamma_dst,
+                                double *log_z_dst, int slot, int rows_c, int rows_m, int rows_zm, hipStream_t stream);
 hipError_t launch_draw_types(const rjsmc_mutate_args &a, int move, const DevParticles &state, int kc, int km,
                              int32_t *mask, int32_t *type, const int32_t *active, const int32_t *gvalid,
                              hipStream_t stream);
 hipError_t launch_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticles &state,
                           const DevParticlesW &prop, int32_t *mask, const int32_t *type, const double *gamma,
-                          const DevParticles *grad_cur, int32_t *gvalid, hipStream_t stream);
+                          const DevParticles *grad_cur, int32_t *gvalid, double *lq, hipStream_t stream);
 hipError_t launch_accept(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticlesW &state,
                          double *ll, const DevParticles &prop, const double *ll_prop, const int32_t *mask,
                          const int32_t *type, const double *gamma, const DevParticlesW *grad_cur,
-                         const DevParticles *grad_prop, int32_t *gvalid, int64_t *stats, hipStream_t stream);
+                         const DevParticles *grad_prop, int32_t *gvalid, int64_t *stats, const double *lq,
+                         hipStream_t stream);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t stream);
 
 // Host-side construction of the frequency-to-time matrix (host.cpp).
@@ -148,6 +164,7 @@ struct rjsmc_ctx {
   int32_t *work_mask;   // [work_n] mutate scratch: proposal validity
   int32_t *work_type;   // [work_n] mutate scratch: move type
   int32_t *work_gvalid; // [work_n] mutate scratch: the current state's gradient is up to date
+  double *work_lq;      // [work_n] mutate scratch: log proposal correction of an adaptive birth/death
   int32_t *work_perm;   // [work_n] evaluation order by layer capacity
   int *work_cnt;        // [2 kMaxLayers] counting-sort scratch
   int64_t work_n;

@@ -167,103 +167,149 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// A bisection round evaluates the TESS at the 7 midpoints that three successive halvings
-// of the bracket can visit, then takes the same three decisions: 20 rounds give the 60
-// halvings, with the evaluation points and decisions of a plain bisection bit for bit
-// but a third of the sequential rounds.
+// The temperature search evaluates the TESS at the 2^LV - 1 midpoints that LV successive
+// halvings of the bracket can visit, then takes the same LV decisions: 60 / LV rounds give
+// the 60 halvings of a plain bisection, with its evaluation points and decisions, in a
+// fraction of its sequential rounds.  LV = 3 up to 512 particles per sounding, 2 up to
+// 1194 and 1 above (the exponentials of a round are staged in LDS: (2^LV - 1) N values).
 constexpr int kBisectK = 7;
+constexpr int kStageMax = kBisectK * 512;
+// Work items of the sums: up to 64 consecutive members of one model (sorted order).
+constexpr int kMaxItems = kMaxPerSounding / kWave + kMaxModels;
+// (item, candidate) sums: at most (512/64 + 128) x 7, (1194/64 + 128) x 3 or 160 x 1
+constexpr int kPartMax = 1024;
+static_assert((512 / kWave + kMaxModels) * 7 <= kPartMax && (kStageMax / 3 / kWave + 1 + kMaxModels) * 3 <= kPartMax &&
+                  kMaxItems <= kPartMax, "item sums fit");
 
 struct RwShared {
-  double ll[kMaxPerSounding];
-  uint64_t cum[kMaxPerSounding];
+  union {
+    double ll[kMaxPerSounding];                       // particle order, until x is formed
+    double w[kStageMax];                              // exponentials of a search round
+    uint64_t cum[kMaxPerSounding];                    // cumulative weights, after the search
+  } u;
+  double x[kMaxPerSounding];        // sorted order: ll - max of the model (-inf: dead model)
+  double part_a[kPartMax], part_b[kPartMax];     // per (item, candidate) sums
   int16_t idx[kMaxPerSounding];     // particles sorted by (model, index)
   uint8_t mod[kMaxPerSounding];
   int cnt[kMaxModels], base[kMaxModels], off[kMaxModels];
   double mx[kMaxModels], s1[kMaxModels], s2[kMaxModels];
   uint64_t U[kMaxModels];
-  double tess;
-  double ess[kBisectK][kMaxModels];   // per-model ESS at the candidates of a bisection round
+  int16_t item_m[kMaxItems], item_q0[kMaxItems];
+  int item_base[kMaxModels + 1];
+  int n_items;
   double tessk[kBisectK];
 };
 
-// Per-model sums of w = exp(dg (ll - max_k)) and w^2, then TESS (all threads call).
-__device__ double eval_tess(RwShared &sm, double dg, int M) {
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  for (int m = wave; m < M; m += kRwWaves) {
-    const int n = sm.cnt[m];
-    if (n == 0) continue;
-    const double mx = sm.mx[m];
+// TESS at K increments at once (all threads call): sm.tessk[c] = TESS(dg[c]) and
+// sm.s1/s2[m] = sum over model m of w and w^2, w = exp(dg[0] (ll - max_m)).
+//   1. every thread forms exponentials of (candidate, position) pairs;
+//   2. one thread per (item, candidate) adds the item's members in order;
+//   3. one lane per (model, candidate) adds the model's items in order and forms its ESS;
+//      lane c then adds the models in order.
+template <int K>
+__device__ __forceinline__ void eval_tess(RwShared &sm, const double (&dg)[K], int M, int N) {
+  double *W = sm.u.w;
+  for (int t = threadIdx.x; t < K * N; t += kRwThreads) {
+    const int c = K == 1 ? 0 : t / N;
+    // dg[c] as a sum of exact zeros and one term (a select chain would become an
+    // indexed private array)
+    double d = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) d += (c == j ? 1.0 : 0.0) * dg[j];
+    W[t] = exp(d * sm.x[t - c * N]);
+  }
+  __syncthreads();
+  const int ni = sm.n_items;
+  for (int t = threadIdx.x; t < ni * K; t += kRwThreads) {
+    const int it = K == 1 ? t : t / K, c = t - it * K;
+    const int m = sm.item_m[it];
+    const int p0 = sm.base[m] + sm.item_q0[it];
+    const int rem = sm.cnt[m] - sm.item_q0[it];
+    const int p1 = p0 + (rem < kWave ? rem : kWave);
+    const double *w = W + c * N;
     double a = 0.0, b = 0.0;
-    if (mx > -HUGE_VAL) {
-      for (int q = lane; q < n; q += kWave) {
-        const double w = exp(dg * (sm.ll[sm.idx[sm.base[m] + q]] - mx));
-        a += w;
-        b += w * w;
+    for (int pos = p0; pos < p1; ++pos) {
+      const double v = w[pos];
+      a += v;
+      b += v * v;
+    }
+    sm.part_a[t] = a;                 // t = it K + c
+    sm.part_b[t] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    for (int t = threadIdx.x; t < M * K; t += kWave) {
+      const int m = K == 1 ? t : t / K, c = t - m * K;
+      const int i0 = sm.item_base[m], i1 = sm.item_base[m + 1];
+      double A = 0.0, B = 0.0;
+      for (int it = i0; it < i1; ++it) {
+        A += sm.part_a[it * K + c];
+        B += sm.part_b[it * K + c];
+      }
+      W[c * M + m] = i1 > i0 ? A * A / B : 0.0;   // per-model ESS (the exponentials are spent)
+      if (c == 0) {
+        sm.s1[m] = A;
+        sm.s2[m] = B;
       }
     }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    if (lane == 0) {
-      sm.s1[m] = a;
-      sm.s2[m] = b;
+    wave_lds_sync();
+    if (threadIdx.x < K) {
+      double t = 0.0;
+      for (int m = 0; m < M; ++m) t += W[threadIdx.x * M + m];
+      sm.tessk[threadIdx.x] = t;
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int m = 0; m < M; ++m)
-      if (sm.cnt[m] > 0 && sm.mx[m] > -HUGE_VAL) t += sm.s1[m] * sm.s1[m] / sm.s2[m];
-    sm.tess = t;
-  }
-  __syncthreads();
-  return sm.tess;
 }
 
-// TESS at kBisectK increments at once (all threads call); sm.tessk[c] holds TESS(dg[c]).
-// Each model's wave forms the sums of every candidate, reduces them together (the
-// candidates' reductions overlap), and lane c stores the model's ESS for candidate c;
-// lane c of the first wave then adds the models in order.  Same arithmetic and order
-// as eval_tess for every candidate.
-__device__ void eval_tess_k(RwShared &sm, const double (&dg)[kBisectK], int M) {
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  for (int m = wave; m < M; m += kRwWaves) {
-    const int n = sm.cnt[m];
-    const double mx = sm.mx[m];
-    const bool live = n > 0 && mx > -HUGE_VAL;
-    double a[kBisectK], b[kBisectK];
+// The 2^LV - 1 points that LV halvings of (lo, hi) can visit, in order, each formed from
+// its two neighbours exactly as a halving forms it.
+template <int K>
+__device__ __forceinline__ void nested_midpoints(double (&c)[K], double lo, double hi) {
+  static_assert(K == 1 || K == 3 || K == 7, "one, two or three halvings");
+  if constexpr (K == 1) {
+    c[0] = 0.5 * (lo + hi);
+  } else if constexpr (K == 3) {
+    c[1] = 0.5 * (lo + hi);
+    c[0] = 0.5 * (lo + c[1]);
+    c[2] = 0.5 * (c[1] + hi);
+  } else {
+    c[3] = 0.5 * (lo + hi);
+    c[1] = 0.5 * (lo + c[3]);
+    c[5] = 0.5 * (c[3] + hi);
+    c[0] = 0.5 * (lo + c[1]);
+    c[2] = 0.5 * (c[1] + c[3]);
+    c[4] = 0.5 * (c[3] + c[5]);
+    c[6] = 0.5 * (c[5] + hi);
+  }
+}
+
+// 60 halvings of (0, hi) keeping the lower end where TESS >= target.
+template <int LV>
+__device__ __forceinline__ double bisect_increment(RwShared &sm, double hi, double target, int M, int N) {
+  constexpr int K = (1 << LV) - 1;
+  double lo = 0.0;
+  for (int round = 0; round < 60 / LV; ++round) {
+    double c[K];
+    nested_midpoints<K>(c, lo, hi);
+    eval_tess<K>(sm, c, M, N);
+    int node = K / 2, step = (K + 1) / 4;
 #pragma unroll
-    for (int c = 0; c < kBisectK; ++c) {
-      a[c] = 0.0;
-      b[c] = 0.0;
-    }
-    if (live) {
-      for (int q = lane; q < n; q += kWave) {
-        const double x = sm.ll[sm.idx[sm.base[m] + q]] - mx;
+    for (int level = 0; level < LV; ++level) {
+      double cn = 0.0;                      // c[node], kept out of an indexed private array
 #pragma unroll
-        for (int c = 0; c < kBisectK; ++c) {
-          const double w = exp(dg[c] * x);
-          a[c] += w;
-          b[c] += w * w;
-        }
+      for (int j = 0; j < K; ++j) cn += (node == j ? 1.0 : 0.0) * c[j];
+      if (sm.tessk[node] >= target) {
+        lo = cn;
+        node += step;
+      } else {
+        hi = cn;
+        node -= step;
       }
+      step >>= 1;
     }
-    double e = 0.0;
-#pragma unroll
-    for (int c = 0; c < kBisectK; ++c) {
-      a[c] = wave_sum(a[c]);
-      b[c] = wave_sum(b[c]);
-      const double ec = live ? a[c] * a[c] / b[c] : 0.0;
-      e = lane == c ? ec : e;
-    }
-    if (lane < kBisectK) sm.ess[lane][m] = e;
   }
-  __syncthreads();
-  if (threadIdx.x < kBisectK) {
-    double t = 0.0;
-    for (int m = 0; m < M; ++m) t += sm.ess[threadIdx.x][m];
-    sm.tessk[threadIdx.x] = t;
-  }
-  __syncthreads();
+  return lo;
 }
 
 // floor(((j << 53) + U) * T / (n << 53)) for j < n <= 2048, U < 2^53, T < 2^62.
@@ -308,7 +354,7 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
     const int kap = in.kappa[off + i], lam = in.lambda[off + i];
     const bool okc = kap >= 0 && kap <= sh.kc && lam >= 0 && lam <= sh.km;
     // a particle with counts outside the capacities is flagged and given -inf weight
-    sm.ll[i] = okc ? ll_in[off + i] : -HUGE_VAL;
+    sm.u.ll[i] = okc ? ll_in[off + i] : -HUGE_VAL;
     if (!okc) atomicOr(flags, kFlagCapacity);
     const int m = okc ? kap * (sh.km + 1) + lam : 0;
     sm.mod[i] = (uint8_t)m;
@@ -356,7 +402,7 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
   for (int m = wave; m < M; m += kRwWaves) {
     const int n = sm.cnt[m];
     double v = -HUGE_VAL;
-    for (int q = lane; q < n; q += kWave) v = fmax(v, sm.ll[sm.idx[sm.base[m] + q]]);
+    for (int q = lane; q < n; q += kWave) v = fmax(v, sm.u.ll[sm.idx[sm.base[m] + q]]);
     v = wave_max(v);
     if (lane == 0) {
       sm.mx[m] = v;
@@ -366,41 +412,45 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
     }
   }
   __syncthreads();
+  // x in sorted order (the particle-order ll is not needed after this)
+  for (int pos = tid; pos < N; pos += kRwThreads) {
+    const int m = sm.mod[sm.idx[pos]];
+    const double mx = sm.mx[m];
+    sm.x[pos] = mx > -HUGE_VAL ? sm.u.ll[sm.idx[pos]] - mx : -HUGE_VAL;
+  }
+  // work items: 64 consecutive members of a model whose maximum is finite
+  if (tid == 0) {
+    int it = 0;
+    for (int m = 0; m < M; ++m) {
+      sm.item_base[m] = it;
+      if (sm.cnt[m] > 0 && sm.mx[m] > -HUGE_VAL)
+        for (int q0 = 0; q0 < sm.cnt[m]; q0 += kWave) {
+          sm.item_m[it] = (int16_t)m;
+          sm.item_q0[it] = (int16_t)q0;
+          ++it;
+        }
+    }
+    sm.item_base[M] = it;
+    sm.n_items = it;
+  }
+  __syncthreads();
   // temperature increment
   const double target = a.alpha_tess * (double)N;
-  double hi = 1.0 - g0, dg;
-  bool full = eval_tess(sm, hi, M) >= target;
-  if (full) {
-    dg = hi;
-  } else {
-    double lo = 0.0;
-    for (int round = 0; round < 60 / 3; ++round) {
-      // the points three halvings of (lo, hi) can visit, formed as the halvings form them
-      double c[kBisectK];
-      c[3] = 0.5 * (lo + hi);
-      c[1] = 0.5 * (lo + c[3]);
-      c[5] = 0.5 * (c[3] + hi);
-      c[0] = 0.5 * (lo + c[1]);
-      c[2] = 0.5 * (c[1] + c[3]);
-      c[4] = 0.5 * (c[3] + c[5]);
-      c[6] = 0.5 * (c[5] + hi);
-      eval_tess_k(sm, c, M);
-      int node = 3;
-#pragma unroll
-      for (int level = 0; level < 3; ++level) {
-        const int step = 2 >> level;          // 2, 1, 0: distance to the next level's point
-        if (sm.tessk[node] >= target) {
-          lo = c[node];
-          node += level < 2 ? step : 0;
-        } else {
-          hi = c[node];
-          node -= level < 2 ? step : 0;
-        }
-      }
-    }
-    dg = lo;
+  const double hi = 1.0 - g0;
+  const double full_dg[1] = {hi};
+  eval_tess<1>(sm, full_dg, M, N);
+  const bool full = sm.tessk[0] >= target;
+  double dg = hi;
+  if (!full) {
+    if (N <= kStageMax / 7)
+      dg = bisect_increment<3>(sm, hi, target, M, N);
+    else if (N <= kStageMax / 3)
+      dg = bisect_increment<2>(sm, hi, target, M, N);
+    else
+      dg = bisect_increment<1>(sm, hi, target, M, N);
   }
-  eval_tess(sm, dg, M);   // s1 at the chosen increment
+  const double chosen[1] = {dg};
+  eval_tess<1>(sm, chosen, M, N);   // s1 at the chosen increment
   // evidence, quantised weights and per-model cumulative sums (wave per model)
   for (int m = wave; m < M; m += kRwWaves) {
     const int n = sm.cnt[m];
@@ -421,7 +471,7 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
       const int q = q0 + lane;
       uint64_t v = 0;
       if (q < n && live) {
-        const double w = exp(dg * (sm.ll[sm.idx[sm.base[m] + q]] - mx)) * inv;
+        const double w = exp(dg * sm.x[sm.base[m] + q]) * inv;
         v = (uint64_t)rint(w * 0x1.0p60);
       }
       // inclusive scan over the wave
@@ -430,7 +480,7 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
         const uint64_t t = __shfl_up(v, o);
         if (lane >= o) v += t;
       }
-      if (q < n) sm.cum[sm.base[m] + q] = carry + v;
+      if (q < n) sm.u.cum[sm.base[m] + q] = carry + v;
       carry += __shfl(v, kWave - 1);
     }
   }
@@ -445,14 +495,14 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
     }
     const int m = sm.mod[dest];
     const int b = sm.base[m], n = sm.cnt[m];
-    const uint64_t T = sm.cum[b + n - 1];
+    const uint64_t T = sm.u.cum[b + n - 1];
     int src = dest;
     if (T > 0) {
       const uint64_t thr = sys_threshold((uint64_t)(pos - b), sm.U[m], T, (uint64_t)n);
       int lo = 0, hi2 = n - 1;       // first q with cum[q] > thr (exists: cum[n-1] = T > thr)
       while (lo < hi2) {
         const int mid = (lo + hi2) >> 1;
-        if (sm.cum[b + mid] > thr)
+        if (sm.u.cum[b + mid] > thr)
           hi2 = mid;
         else
           lo = mid + 1;
@@ -550,20 +600,167 @@ __device__ __forceinline__ double prior_sd(const rjsmc_prior &pr, double zmax, i
 }
 
 // ---------------------------------------------------------------------- adaptation ---
-// One wavefront per (sounding, model): member list, sample mean and covariance in LDS,
-// Jacobi eigen-decomposition, factor F = U diag(sqrt(Lambda)) with eigenvalues in
-// descending order and each direction signed so that its largest-magnitude component is
-// positive.
-//
-// The Jacobi sweeps use the round-robin (tournament) ordering: a sweep is nn - 1 rounds
-// of nn/2 disjoint index pairs (nn = d rounded up to even), so every pair of a round is
-// rotated at once, A <- J^T A J with J the product of the round's rotations (a column
-// pass into a second buffer, then a row pass back).  Each pair's 2x2 block is touched by
-// its own rotation only, so its diagonal takes the classical update and its off-diagonal
-// entry is set to zero.  A sweep then costs nn - 1 wave-synchronous rounds instead of
-// d (d - 1) / 2 sequential rotations.
+// One wavefront per (sounding, model): member list, mean and covariance in LDS, then the
+// factor of the covariance (eigen_factor).
 constexpr int kDimMax = 3 + 2 * (kMaxLayers - 1);   // 33
 constexpr int kLd = kDimMax + 1;                    // LDS row stride
+
+// Jacobi eigen-decomposition of the symmetric d x d matrix A (LDS, overwritten; V0 holds
+// the identity, T two spare d x d buffers) and the factor F = U diag(sqrt Lambda) into
+// F[r D + a] (direction r), eigenvalues descending, each direction signed so that its
+// largest-magnitude component is positive.  One wavefront.
+//
+// The sweeps use the round-robin (tournament) ordering: a sweep is nn - 1 rounds of nn/2
+// disjoint index pairs (nn = d rounded up to even), so every pair of a round is rotated
+// at once, A <- J^T A J with J the product of the round's rotations.  Each pair's 2x2
+// block is touched by its own rotation only, so its diagonal takes the classical update
+// and its off-diagonal entry is set to zero.
+__device__ __forceinline__ void eigen_factor(double (*A)[kLd], double (*V0)[kLd], double (*T)[kDimMax][kLd],
+                                             double *rc, double *rs, double *shift, int *order, int d, int D,
+                                             double *F) {
+  const int lane = threadIdx.x & (kWave - 1);
+  double (*Vc)[kLd] = V0;         // current eigenvector estimate
+  double (*Vn)[kLd] = T[1];       // its next-round buffer
+  double (*B)[kLd] = T[0];        // A J of a round
+  const int nn = (d + 1) & ~1, np = nn / 2;
+  const int dd = d * d;
+  // element t = lane + 64 it of the d x d matrix as (row, column), stepped without division
+  const int r0 = lane / d, c0 = lane % d, rstep = kWave / d, cstep = kWave % d;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double offn = 0.0, diag = 0.0, dmax = 0.0;
+    for (int t = lane, x = r0, y = c0; t < dd; t += kWave) {
+      const double v = A[x][y] * A[x][y];
+      offn += x != y ? v : 0.0;
+      diag += x == y ? v : 0.0;
+      dmax = x == y ? fmax(dmax, fabs(A[x][x])) : dmax;
+      x += rstep;
+      y += cstep;
+      if (y >= d) {
+        y -= d;
+        ++x;
+      }
+    }
+    offn = wave_sum(offn);
+    diag = wave_sum(diag);
+    dmax = wave_max(dmax);
+    if (!(offn > 1e-30 * diag)) break;
+    // an off-diagonal entry below 1e-16 sqrt(|a_pp a_qq|), or below 1e-18 of the largest
+    // diagonal entry, is rounding noise: it is set to zero without a rotation, and a
+    // sweep without any rotation ends the iteration
+    const double floor_abs = 1e-18 * dmax;
+    bool any_rot = false;
+    for (int round = 0; round < nn - 1; ++round) {
+      // partner of index x in this round: pairs (nn-1, round) and (round + i, round - i)
+      // mod nn-1, i = 1 .. nn/2 - 1; a partner beyond d (the padding index) leaves x alone
+      auto partner_of = [&](int x) {
+        int y;
+        if (x == nn - 1)
+          y = round;
+        else if (x == round)
+          y = nn - 1;
+        else {
+          y = 2 * round - x;
+          if (y < 0) y += nn - 1;
+          if (y >= nn - 1) y -= nn - 1;
+        }
+        return y < d ? y : x;
+      };
+      bool rot = false;
+      if (lane < np) {
+        int x = lane == 0 ? nn - 1 : round + lane;
+        if (lane != 0 && x >= nn - 1) x -= nn - 1;
+        int y = lane == 0 ? round : round - lane;
+        if (y < 0) y += nn - 1;
+        const int pp = x < y ? x : y, qq = x < y ? y : x;
+        if (qq < d) {
+          const double apq = A[pp][qq], app = A[pp][pp], aqq = A[qq][qq];
+          double cth = 1.0, sth = 0.0, tt = 0.0;
+          rot = fabs(apq) > fmax(1e-16 * sqrt(fabs(app * aqq)), floor_abs);
+          if (rot) {
+            const double theta = (aqq - app) / (2.0 * apq);
+            tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            cth = 1.0 / sqrt(tt * tt + 1.0);
+            sth = tt * cth;
+          }
+          rc[pp] = cth;
+          rs[pp] = -sth;
+          rc[qq] = cth;
+          rs[qq] = sth;
+          shift[pp] = -(tt * apq);
+          shift[qq] = tt * apq;
+        } else if (pp < d) {           // paired with the padding index: untouched
+          rc[pp] = 1.0;
+          rs[pp] = 0.0;
+          shift[pp] = 0.0;
+        }
+      }
+      any_rot = any_rot || __any(rot);
+      wave_lds_sync();
+      // column pass: B = A J, Vn = Vc J
+      for (int t = lane, i = r0, x = c0; t < dd; t += kWave) {
+        const int y = partner_of(x);
+        const double c_ = rc[x], s_ = rs[x];
+        B[i][x] = c_ * A[i][x] + s_ * A[i][y];
+        Vn[i][x] = c_ * Vc[i][x] + s_ * Vc[i][y];
+        i += rstep;
+        x += cstep;
+        if (x >= d) {
+          x -= d;
+          ++i;
+        }
+      }
+      wave_lds_sync();
+      // row pass: A = J^T B; a pair's 2x2 block takes the classical diagonal update
+      // (from the round's A) and a zero off-diagonal
+      for (int t = lane, x = r0, j = c0; t < dd; t += kWave) {
+        const int y = partner_of(x);
+        double v;
+        if (x == j)
+          v = A[x][x] + shift[x];
+        else if (y == j)
+          v = 0.0;
+        else
+          v = rc[x] * B[x][j] + rs[x] * B[y][j];
+        A[x][j] = v;
+        x += rstep;
+        j += cstep;
+        if (j >= d) {
+          j -= d;
+          ++x;
+        }
+      }
+      wave_lds_sync();
+      double (*sw)[kLd] = Vc;
+      Vc = Vn;
+      Vn = sw;
+    }
+    if (!any_rot) break;
+  }
+  double (*Ac)[kLd] = A;
+  // descending eigenvalue order (stable selection by lane 0)
+  if (lane == 0) {
+    for (int a = 0; a < d; ++a) order[a] = a;
+    for (int a = 1; a < d; ++a) {
+      const int v = order[a];
+      int b = a;
+      while (b > 0 && Ac[order[b - 1]][order[b - 1]] < Ac[v][v]) {
+        order[b] = order[b - 1];
+        --b;
+      }
+      order[b] = v;
+    }
+  }
+  wave_lds_sync();
+  for (int r = lane; r < d; r += kWave) {
+    const int c = order[r];
+    const double ev = Ac[c][c] > 0.0 ? sqrt(Ac[c][c]) : 0.0;
+    int big = 0;
+    for (int a = 1; a < d; ++a)
+      if (fabs(Vc[a][c]) > fabs(Vc[big][c])) big = a;
+    const double sg = Vc[big][c] < 0.0 ? -1.0 : 1.0;
+    for (int a = 0; a < d; ++a) F[r * D + a] = sg * ev * Vc[a][c];
+  }
+}
 
 __global__ __launch_bounds__(kWave) void adapt_kernel(SmcShape sh, DevParticles p, rjsmc_prior pr, double *factors) {
   __shared__ int16_t mem[kMaxPerSounding];
@@ -572,8 +769,7 @@ __global__ __launch_bounds__(kWave) void adapt_kernel(SmcShape sh, DevParticles 
   // member staging (64 rows) during the moments; column-pass buffers of A and V after
   __shared__ double T[2][kDimMax][kLd];
   __shared__ double mu[kDimMax];
-  __shared__ double rc[kLd], rs[kLd];
-  __shared__ int partner[kLd];
+  __shared__ double rc[kLd], rs[kLd], shift[kLd];
   __shared__ int order[kDimMax];
   static_assert(kWave * kLd <= 2 * kDimMax * kLd, "staging fits the column-pass buffers");
   double (*X)[kLd] = reinterpret_cast<double (*)[kLd]>(&T[0][0][0]);
@@ -642,112 +838,213 @@ __global__ __launch_bounds__(kWave) void adapt_kernel(SmcShape sh, DevParticles 
     V0[a][b] = a == b ? 1.0 : 0.0;
   }
   wave_lds_sync();
-  double (*Vc)[kLd] = V0;        // current eigenvector estimate
-  double (*Vn)[kLd] = T[1];      // its column-pass buffer
-  double (*B)[kLd] = T[0];       // column-pass buffer of A
-  const int nn = (d + 1) & ~1, np = nn / 2;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    double offn = 0.0, diag = 0.0;
-    for (int t = lane; t < d * d; t += kWave) {
-      const int a = t / d, b = t % d;
-      if (a != b) offn += A[a][b] * A[a][b];
-      else diag += A[a][b] * A[a][b];
-    }
-    offn = wave_sum(offn);
-    diag = wave_sum(diag);
-    if (!(offn > 1e-30 * diag)) break;
-    for (int round = 0; round < nn - 1; ++round) {
-      // pair `lane` of this round: (nn-1, round) and ((round + j) mod (nn-1), (round - j) mod (nn-1))
-      int pp = 0, qq = 0;
-      double app = 0.0, aqq = 0.0, apq = 0.0, tt = 0.0;
-      bool rot = false;
-      if (lane < np) {
-        int x = lane == 0 ? nn - 1 : (round + lane) % (nn - 1);
-        int y = lane == 0 ? round : (round - lane + (nn - 1)) % (nn - 1);
-        pp = x < y ? x : y;
-        qq = x < y ? y : x;
-        double cth = 1.0, sth = 0.0;
-        if (qq < d) {
-          apq = A[pp][qq];
-          if (apq != 0.0) {
-            app = A[pp][pp];
-            aqq = A[qq][qq];
-            const double theta = (aqq - app) / (2.0 * apq);
-            tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            cth = 1.0 / sqrt(tt * tt + 1.0);
-            sth = tt * cth;
-            rot = true;
-          }
-          partner[pp] = qq;
-          partner[qq] = pp;
-          rc[pp] = cth;
-          rs[pp] = -sth;
-          rc[qq] = cth;
-          rs[qq] = sth;
-        } else if (pp < d) {           // paired with the padding index: untouched
-          partner[pp] = pp;
-          rc[pp] = 1.0;
-          rs[pp] = 0.0;
-        }
-      }
-      wave_lds_sync();
-      // column pass: B = A J, Vn = Vc J
-      for (int t = lane; t < d * d; t += kWave) {
-        const int i = t / d, x = t % d;
-        const int y = partner[x];
-        const double c_ = rc[x], s_ = rs[x];
-        B[i][x] = c_ * A[i][x] + s_ * A[i][y];
-        Vn[i][x] = c_ * Vc[i][x] + s_ * Vc[i][y];
-      }
-      wave_lds_sync();
-      // row pass: A = J^T B
-      for (int t = lane; t < d * d; t += kWave) {
-        const int x = t / d, j = t % d;
-        const int y = partner[x];
-        A[x][j] = rc[x] * B[x][j] + rs[x] * B[y][j];
-      }
-      wave_lds_sync();
-      if (rot) {
-        A[pp][pp] = app - tt * apq;
-        A[qq][qq] = aqq + tt * apq;
-        A[pp][qq] = 0.0;
-        A[qq][pp] = 0.0;
-      }
-      double (*sw)[kLd] = Vc;
-      Vc = Vn;
-      Vn = sw;
-      wave_lds_sync();
-    }
-  }
-  // descending eigenvalue order (stable selection by lane 0)
-  if (lane == 0) {
-    for (int a = 0; a < d; ++a) order[a] = a;
-    for (int a = 1; a < d; ++a) {
-      const int v = order[a];
-      int b = a;
-      while (b > 0 && A[order[b - 1]][order[b - 1]] < A[v][v]) {
-        order[b] = order[b - 1];
-        --b;
-      }
-      order[b] = v;
-    }
-  }
-  wave_lds_sync();
-  for (int r = lane; r < d; r += kWave) {
-    const int c = order[r];
-    const double ev = A[c][c] > 0.0 ? sqrt(A[c][c]) : 0.0;
-    int big = 0;
-    for (int a = 1; a < d; ++a)
-      if (fabs(Vc[a][c]) > fabs(Vc[big][c])) big = a;
-    const double sg = Vc[big][c] < 0.0 ? -1.0 : 1.0;
-    for (int a = 0; a < d; ++a) F[r * D + a] = sg * ev * Vc[a][c];
-  }
+  eigen_factor(A, V0, T, rc, rs, shift, order, d, D, F);
 }
 
 hipError_t launch_adapt(const SmcShape &sh, const DevParticles &p, int n_sound, const rjsmc_prior &pr,
                         double *factors, hipStream_t stream) {
   hipLaunchKernelGGL(adapt_kernel, dim3((unsigned)(n_sound * sh.n_models)), dim3(kWave), 0, stream, sh, p, pr,
                      factors);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- particle recycling ---
+// One wavefront per (sounding, model) pools the model's members of the current
+// population and of the archive's used slots, weighted by the deterministic mixture of
+// the sources (Section 3.2.5):
+//   log nu = gamma_t ll - log sum_c exp(log N_c - log Z_c + gamma_c ll)
+// over the sources c with N_c > 0 members and a finite log Z_c (L^0 = 1).  Four passes
+// over the sources (member list rebuilt per source): counts, the largest log nu, the
+// weight sums and weighted mean, the weighted covariance; then eigen_factor.
+__global__ __launch_bounds__(kWave) void adapt_recycled_kernel(SmcShape sh, DevParticles p, const double *ll,
+                                                               const double *gamma, const double *log_z,
+                                                               ArchiveView ar, rjsmc_prior pr, double *factors) {
+  __shared__ int16_t mem[kMaxPerSounding];
+  __shared__ double A[kDimMax][kLd];
+  __shared__ double V0[kDimMax][kLd];
+  __shared__ double T[2][kDimMax][kLd];
+  __shared__ double mu[kDimMax];
+  __shared__ double rc[kLd], rs[kLd], shift[kLd];
+  __shared__ int order[kDimMax];
+  __shared__ double wst[kWave];
+  __shared__ double comp_lc[kMaxArchive + 1], comp_g[kMaxArchive + 1];
+  double (*X)[kLd] = reinterpret_cast<double (*)[kLd]>(&T[0][0][0]);
+  const int lane = threadIdx.x;
+  const int M = sh.n_models;
+  const int n_sound = (int)(gridDim.x / M);
+  const int s = blockIdx.x / M, m = blockIdx.x % M;
+  const int N = (int)(p.n_per_sounding > 0 ? p.n_per_sounding : p.n);
+  const int64_t n_total = p.n;
+  const int k = m / (sh.km + 1), l = m % (sh.km + 1);
+  const int d = 3 + 2 * k + 2 * l, D = sh.dmax;
+  double *F = factors + (int64_t)blockIdx.x * D * D;
+  const int Q = ar.n_used + 1;            // sources: archive slots 0 .. n_used - 1, then the current population
+  const double g_t = gamma[s];
+  // member list of source q (particle offsets within that source's sounding s)
+  auto members = [&](int q) {
+    const DevParticles &P = q < ar.n_used ? ar.pop : p;
+    const int64_t off = (q < ar.n_used ? (int64_t)q * n_total : 0) + (int64_t)s * N;
+    int nm = 0;
+    for (int c0 = 0; c0 < N; c0 += kWave) {
+      const int i = c0 + lane;
+      const bool sel = i < N && P.kappa[off + i] == k && P.lambda[off + i] == l;
+      const uint64_t b = __ballot(sel);
+      if (sel) mem[nm + __popcll(b & ((1ull << lane) - 1))] = (int16_t)i;
+      nm += __popcll(b);
+    }
+    wave_lds_sync();
+    return nm;
+  };
+  auto src_ll = [&](int q, int i) {
+    return q < ar.n_used ? ar.ll[(int64_t)q * n_total + (int64_t)s * N + i] : ll[(int64_t)s * N + i];
+  };
+  // 1. mixture components
+  int nc = 0;
+  for (int q = 0; q < Q; ++q) {
+    const int nm = members(q);
+    const double gq = q < ar.n_used ? ar.gamma[(int64_t)q * n_sound + s] : g_t;
+    const double lz = q < ar.n_used ? ar.log_z[((int64_t)q * n_sound + s) * M + m] : log_z[(int64_t)s * M + m];
+    if (nm > 0 && lz > -HUGE_VAL && lz < HUGE_VAL) {
+      if (lane == 0) {
+        comp_lc[nc] = log((double)nm) - lz;
+        comp_g[nc] = gq;
+      }
+      ++nc;
+    }
+    wave_lds_sync();
+  }
+  auto log_nu = [&](double x) {
+    const double num = g_t == 0.0 ? 0.0 : g_t * x;
+    double mx = -HUGE_VAL;
+    for (int c = 0; c < nc; ++c) mx = fmax(mx, comp_lc[c] + (comp_g[c] == 0.0 ? 0.0 : comp_g[c] * x));
+    if (!(num > -HUGE_VAL) || !(mx > -HUGE_VAL)) return -HUGE_VAL;   // L = 0: weight 0
+    double sum = 0.0;
+    for (int c = 0; c < nc; ++c) sum += exp(comp_lc[c] + (comp_g[c] == 0.0 ? 0.0 : comp_g[c] * x) - mx);
+    return num - (mx + log(sum));
+  };
+  // 2. largest log weight
+  double lmax = -HUGE_VAL;
+  for (int q = 0; q < Q; ++q) {
+    const int nm = members(q);
+    for (int r = lane; r < nm; r += kWave) lmax = fmax(lmax, log_nu(src_ll(q, mem[r])));
+    wave_lds_sync();
+  }
+  lmax = wave_max(lmax);
+  for (int t = lane; t < D * D; t += kWave) F[t] = 0.0;
+  // 3. weight sums and weighted mean: members staged 64 at a time, lane a adds in order
+  double acc_mu = 0.0, sw = 0.0, sw2 = 0.0;
+  if (lmax > -HUGE_VAL) {
+    for (int q = 0; q < Q; ++q) {
+      const int nm = members(q);
+      const DevParticles &P = q < ar.n_used ? ar.pop : p;
+      const int64_t off = (q < ar.n_used ? (int64_t)q * n_total : 0) + (int64_t)s * N;
+      for (int q0 = 0; q0 < nm; q0 += kWave) {
+        const int r = q0 + lane;
+        if (r < nm) {
+          const double w = exp(log_nu(src_ll(q, mem[r])) - lmax);
+          wst[lane] = w;
+          sw += w;
+          sw2 += w * w;
+          for (int a = 0; a < d; ++a) X[lane][a] = theta_get(P, off + mem[r], k, l, a);
+        }
+        wave_lds_sync();
+        const int nq = nm - q0 < kWave ? nm - q0 : kWave;
+        if (lane < d)
+          for (int rr = 0; rr < nq; ++rr) acc_mu += wst[rr] * X[rr][lane];
+        wave_lds_sync();
+      }
+    }
+  }
+  sw = wave_sum(sw);
+  sw2 = wave_sum(sw2);
+  if (!(lmax > -HUGE_VAL) || !(sw * sw > (double)d * sw2)) {      // effective sample size <= d
+    for (int a = lane; a < d; a += kWave) F[a * D + a] = 0.1 * prior_sd(pr, sh.z_max, k, l, a);
+    return;
+  }
+  if (lane < d) mu[lane] = acc_mu / sw;
+  for (int t = lane; t < d * d; t += kWave) A[t / d][t % d] = 0.0;
+  wave_lds_sync();
+  // 4. weighted covariance sum w (theta - mu)(theta - mu)^T, then / (sw - sw2 / sw)
+  for (int q = 0; q < Q; ++q) {
+    const int nm = members(q);
+    const DevParticles &P = q < ar.n_used ? ar.pop : p;
+    const int64_t off = (q < ar.n_used ? (int64_t)q * n_total : 0) + (int64_t)s * N;
+    for (int q0 = 0; q0 < nm; q0 += kWave) {
+      const int r = q0 + lane;
+      if (r < nm) {
+        wst[lane] = exp(log_nu(src_ll(q, mem[r])) - lmax);
+        for (int a = 0; a < d; ++a) X[lane][a] = theta_get(P, off + mem[r], k, l, a) - mu[a];
+      }
+      wave_lds_sync();
+      const int nq = nm - q0 < kWave ? nm - q0 : kWave;
+      for (int t = lane; t < d * d; t += kWave) {
+        const int a = t / d, b = t % d;
+        if (b < a) continue;
+        double acc = A[a][b];
+        for (int rr = 0; rr < nq; ++rr) acc += wst[rr] * X[rr][a] * X[rr][b];
+        A[a][b] = acc;
+      }
+      wave_lds_sync();
+    }
+  }
+  const double norm = sw - sw2 / sw;      // sum w (1 - sum w~^2)
+  for (int t = lane; t < d * d; t += kWave) {
+    const int a = t / d, b = t % d;
+    if (b >= a) A[a][b] = A[a][b] / norm;
+  }
+  wave_lds_sync();
+  for (int t = lane; t < d * d; t += kWave) {
+    const int a = t / d, b = t % d;
+    if (b < a) A[a][b] = A[b][a];
+    V0[a][b] = a == b ? 1.0 : 0.0;
+  }
+  wave_lds_sync();
+  eigen_factor(A, V0, T, rc, rs, shift, order, d, D, F);
+}
+
+hipError_t launch_adapt_recycled(const SmcShape &sh, const DevParticles &p, const double *ll, const double *gamma,
+                                 const double *log_z, int n_sound, const ArchiveView &ar, const rjsmc_prior &pr,
+                                 double *factors, hipStream_t stream) {
+  hipLaunchKernelGGL(adapt_recycled_kernel, dim3((unsigned)(n_sound * sh.n_models)), dim3(kWave), 0, stream, sh, p,
+                     ll, gamma, log_z, ar, pr, factors);
+  return hipGetLastError();
+}
+
+// Slot `slot` of the archive := population src (every row), its ll, gamma and log_z.
+__global__ __launch_bounds__(256) void archive_store_kernel(DevParticles src, const double *ll, const double *gamma,
+                                                            const double *log_z, int n_sound, int n_models,
+                                                            DevParticlesW dst, double *ll_dst, double *gamma_dst,
+                                                            double *log_z_dst, int slot, int rows_c, int rows_m,
+                                                            int rows_zm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = src.n, Si = src.stride, So = dst.stride;
+  const int64_t o = (int64_t)slot * n + i;
+  if (i < n) {
+    dst.kappa[o] = src.kappa[i];
+    dst.lambda[o] = src.lambda[i];
+    dst.phi_b[o] = src.phi_b[i];
+    dst.log10_tau[o] = src.log10_tau[i];
+    dst.c[o] = src.c[i];
+    ll_dst[o] = ll[i];
+    for (int r = 0; r < rows_c; ++r) {
+      dst.phi[r * So + o] = src.phi[r * Si + i];
+      dst.z_cond[r * So + o] = src.z_cond[r * Si + i];
+    }
+    for (int r = 0; r < rows_m; ++r) dst.m[r * So + o] = src.m[r * Si + i];
+    for (int r = 0; r < rows_zm; ++r) dst.z_charg[r * So + o] = src.z_charg[r * Si + i];
+  }
+  if (i < n_sound) gamma_dst[(int64_t)slot * n_sound + i] = gamma[i];
+  if (i < (int64_t)n_sound * n_models) log_z_dst[(int64_t)slot * n_sound * n_models + i] = log_z[i];
+}
+
+hipError_t launch_archive_store(const DevParticles &src, const double *ll, const double *gamma, const double *log_z,
+                                int n_sound, int n_models, const DevParticlesW &dst, double *ll_dst, double *gamma_dst,
+                                double *log_z_dst, int slot, int rows_c, int rows_m, int rows_zm, hipStream_t stream) {
+  int64_t work = src.n;
+  if ((int64_t)n_sound * n_models > work) work = (int64_t)n_sound * n_models;
+  const int64_t blocks = (work + 255) / 256;
+  hipLaunchKernelGGL(archive_store_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, src, ll, gamma, log_z, n_sound,
+                     n_models, dst, ll_dst, gamma_dst, log_z_dst, slot, rows_c, rows_m, rows_zm);
   return hipGetLastError();
 }
 
@@ -801,12 +1098,115 @@ __device__ __forceinline__ void mala_normals(const rjsmc_mutate_args &a, int64_t
   }
 }
 
+// ------------------------------------------------------------ adaptive birth ---
+// a - b c with the product rounded before the difference.
+__device__ __forceinline__ double msub_rn(double a, double b, double c) {
+#pragma clang fp contract(off)
+  return a - b * c;
+}
+
+// Row i of the symmetric root S = sum_r f_r f_r^T / |f_r| of F F^T (F[a][r] = Fm[r D + a],
+// the nonzero columns), the columns added in order with separately rounded products.
+__device__ void zca_row(const double *Fm, int D, int d, int i, double *row) {
+#pragma clang fp contract(off)
+  for (int j = 0; j < d; ++j) row[j] = 0.0;
+  for (int r = 0; r < d; ++r) {
+    const double *col = Fm + (int64_t)r * D;
+    double n2 = 0.0;
+    for (int q = 0; q < d; ++q) n2 = n2 + col[q] * col[q];
+    if (n2 > 0.0) {
+      const double w = col[i] / sqrt(n2);
+      for (int j = 0; j < d; ++j) row[j] = row[j] + w * col[j];
+    }
+  }
+}
+
+// Adaptive birth (Appendix E.2) of an interface at depth zn in partition `part` (0
+// conductivity, 1 chargeability) of the parameter vector th of model (k, l), or the
+// death of interface r, the inverse map with the same covariance root (that of the
+// larger model).  th is rewritten in place (kDimMax + 2 entries); false when the
+// proposal is rejected outright; lq receives the log proposal correction.
+__device__ bool zca_move(double *th, int &k, int &l, bool birth, int part, double u1, double up,
+                         const rjsmc_mutate_args &a, const SmcShape &sh, int64_t snd, double &lq) {
+  const int D = sh.dmax;
+  const rjsmc_prior &pr = a.prior;
+  const double dv = part == 0 ? pr.phi_hi - pr.phi_lo : pr.m_hi - pr.m_lo;
+  const double log_norm = 0.91893853320467274178;   // log sqrt(2 pi)
+  double S[kDimMax + 2];
+  if (birth) {
+    const int d = 3 + 2 * k + 2 * l;
+    const double zn = sh.z_max * u1;
+    int r = 0, ia, ib;
+    double src;
+    if (part == 0) {
+      while (r < k && th[1 + k + r] < zn) ++r;
+      ia = r + 1;                      // the new property's component
+      ib = 1 + k + r;                  // the new depth goes to ib + 1
+      src = th[r];
+    } else {
+      const int mo = 1 + 2 * k, zo = 1 + 2 * k + l;
+      while (r < l && th[zo + r] < zn) ++r;
+      ia = mo + r;
+      ib = zo + r;
+      src = r >= 1 ? th[mo + r - 1] : 0.0;
+    }
+    for (int q = d - 1; q >= ib; --q) th[q + 2] = th[q];
+    th[ib + 1] = zn;
+    for (int q = ib - 1; q >= ia; --q) th[q + 1] = th[q];
+    th[ia] = src;
+    const int kb = part == 0 ? k + 1 : k, lb = part == 0 ? l : l + 1, db = d + 2;
+    const int jn = ia, jz = ib + 1, js = (part == 0 || r >= 1) ? ia - 1 : -1;
+    const double *Fm = a.factors + (snd * sh.n_models + kb * (sh.km + 1) + lb) * (int64_t)D * D;
+    zca_row(Fm, D, db, jn, S);
+    for (int j = 0; j < db; ++j)
+      if (j != jz) th[j] = madd_rn(th[j], S[j], up);
+    const double J = S[jn] - (js >= 0 ? S[js] : 0.0);
+    if (J == 0.0) return false;
+    lq = log(fabs(J)) - log(dv) + (0.5 * up * up + log_norm);
+    k = kb;
+    l = lb;
+    return true;
+  }
+  const int n_if = part == 0 ? k : l;
+  if (n_if < 1) return false;
+  int r = (int)(u1 * (double)n_if);
+  r = r > n_if - 1 ? n_if - 1 : r;
+  const int d = 3 + 2 * k + 2 * l;
+  const int jn = part == 0 ? r + 1 : 1 + 2 * k + r;
+  const int js = part == 0 ? r : (r >= 1 ? jn - 1 : -1);
+  const int jz = part == 0 ? 1 + k + r : 1 + 2 * k + l + r;
+  const double *Fm = a.factors + (snd * sh.n_models + k * (sh.km + 1) + l) * (int64_t)D * D;
+  zca_row(Fm, D, d, jn, S);
+  const double J = S[jn] - (js >= 0 ? S[js] : 0.0);
+  if (J == 0.0) return false;
+  const double upd = (th[jn] - (js >= 0 ? th[js] : 0.0)) / J;
+  const double ud = th[jz];
+  for (int j = 0; j < d; ++j)
+    if (j != jz) th[j] = msub_rn(th[j], S[j], upd);
+  int w = jn;                          // drop components jn and jz (jn < jz)
+  for (int q = jn + 1; q < d; ++q)
+    if (q != jz) th[w++] = th[q];
+  const int ks = part == 0 ? k - 1 : k, ls = part == 0 ? l : l - 1;
+  const int z0 = part == 0 ? 1 + ks : 1 + 2 * ks + ls, nz = part == 0 ? ks : ls;
+  int below = 0;
+  for (int q = 0; q < nz; ++q) {
+    if (th[z0 + q] == ud) return false;
+    below += th[z0 + q] < ud ? 1 : 0;
+  }
+  if (below != r) return false;        // u_d would not be inserted at index r: no bijection
+  lq = -(log(fabs(J)) - log(dv) + (0.5 * upd * upd + log_norm));
+  k = ks;
+  l = ls;
+  return true;
+}
+
 // Proposal of move `move` for every particle (type from draw_types_kernel): written to
 // `prop`; mask[i] = 1 if the proposal needs a likelihood, 2 if it needs a likelihood and
 // a gradient, 0 if it is rejected outright.
 __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_args a, int move, DevParticles st,
                                                       DevParticlesW prop, int32_t *mask, const int32_t *type,
-                                                      const double *gamma, DevParticles gcur, int32_t *gvalid) {
+                                                      const double *gamma, DevParticles gcur, int32_t *gvalid,
+                                                      double *lq) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= st.n) return;
   const int64_t snd = st.n_per_sounding > 0 ? i / st.n_per_sounding : 0;
@@ -834,7 +1234,43 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
   }
   double phb = st.phi_b[i], lt = st.log10_tau[i], cc = st.c[i];
   bool ok = false;
-  if (t == RJSMC_MOVE_SIGMA_BIRTH || t == RJSMC_MOVE_M_BIRTH) {
+  const bool jump = t == RJSMC_MOVE_SIGMA_BIRTH || t == RJSMC_MOVE_M_BIRTH || t == RJSMC_MOVE_SIGMA_DEATH ||
+                    t == RJSMC_MOVE_M_DEATH;
+  if (lq) lq[i] = 0.0;
+  if (a.zca_birth && jump) {
+    const bool birth = t == RJSMC_MOVE_SIGMA_BIRTH || t == RJSMC_MOVE_M_BIRTH;
+    const int part = t == RJSMC_MOVE_SIGMA_BIRTH || t == RJSMC_MOVE_SIGMA_DEATH ? 0 : 1;
+    if (!birth || (part == 0 ? k < kc : l < km)) {
+      double th[kDimMax + 2], corr = 0.0;
+      int q = 0;
+      th[q++] = phb;
+      for (int j = 0; j < k; ++j) th[q++] = ph[j];
+      for (int j = 0; j < k; ++j) th[q++] = zc[j];
+      for (int j = 0; j < l; ++j) th[q++] = mm[j];
+      for (int j = 0; j < l; ++j) th[q++] = zm[j];
+      th[q++] = lt;
+      th[q++] = cc;
+      if (zca_move(th, k, l, birth, part, u1, normal0(u2, u3), a, sh, snd, corr)) {
+        q = 0;
+        phb = th[q++];
+        for (int j = 0; j < k; ++j) ph[j] = th[q++];
+        for (int j = 0; j < k; ++j) zc[j] = th[q++];
+        for (int j = 0; j < l; ++j) mm[j] = th[q++];
+        for (int j = 0; j < l; ++j) zm[j] = th[q++];
+        lt = th[q++];
+        cc = th[q++];
+        ok = in_range(phb, pr.phi_lo, pr.phi_hi) && in_range(lt, pr.ltau_lo, pr.ltau_hi) &&
+             in_range(cc, pr.c_lo, pr.c_hi);
+        for (int j = 0; j < k; ++j)
+          ok = ok && in_range(ph[j], pr.phi_lo, pr.phi_hi) && zc[j] > 0.0 && zc[j] < sh.z_max &&
+               (j == 0 || zc[j] > zc[j - 1]);
+        for (int j = 0; j < l; ++j)
+          ok = ok && in_range(mm[j], pr.m_lo, pr.m_hi) && zm[j] > 0.0 && zm[j] < sh.z_max &&
+               (j == 0 || zm[j] > zm[j - 1]);
+        if (lq) lq[i] = corr;
+      }
+    }
+  } else if (t == RJSMC_MOVE_SIGMA_BIRTH || t == RJSMC_MOVE_M_BIRTH) {
     const bool sig = t == RJSMC_MOVE_SIGMA_BIRTH;
     int &n = sig ? k : l;
     double *z = sig ? zc : zm, *v = sig ? ph : mm;
@@ -963,7 +1399,7 @@ __global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_a
                                                      double *ll, DevParticles prop, const double *ll_prop,
                                                      const int32_t *mask, const int32_t *type, const double *gamma,
                                                      DevParticlesW gcur, DevParticles gprop, int32_t *gvalid,
-                                                     int64_t *stats) {
+                                                     int64_t *stats, const double *lq) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = i < st.n;
   const int t = in ? type[i] : -1;
@@ -989,6 +1425,10 @@ __global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_a
         extra += -0.5 * v * v + 0.5 * xi[r] * xi[r];
       }
     }
+    if (a.zca_birth && lq &&
+        (t == RJSMC_MOVE_SIGMA_BIRTH || t == RJSMC_MOVE_M_BIRTH || t == RJSMC_MOVE_SIGMA_DEATH ||
+         t == RJSMC_MOVE_M_DEATH))
+      extra += lq[i];                     // adaptive birth / death: proposal and Jacobian terms
     const double margin = gamma[snd] * (ll_prop[i] - ll[i]) + extra - log(ua);
     acc = margin > 0.0;
     if (acc && a.trial == 0) {
@@ -1066,23 +1506,24 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t stream)
 
 hipError_t launch_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticles &state,
                           const DevParticlesW &prop, int32_t *mask, const int32_t *type, const double *gamma,
-                          const DevParticles *grad_cur, int32_t *gvalid, hipStream_t stream) {
+                          const DevParticles *grad_cur, int32_t *gvalid, double *lq, hipStream_t stream) {
   const int64_t blocks = (state.n + 255) / 256;
   const DevParticles g = grad_cur ? *grad_cur : DevParticles();
   hipLaunchKernelGGL(propose_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, sh, a, move, state, prop, mask,
-                     type, gamma, g, gvalid);
+                     type, gamma, g, gvalid, lq);
   return hipGetLastError();
 }
 
 hipError_t launch_accept(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticlesW &state,
                          double *ll, const DevParticles &prop, const double *ll_prop, const int32_t *mask,
                          const int32_t *type, const double *gamma, const DevParticlesW *grad_cur,
-                         const DevParticles *grad_prop, int32_t *gvalid, int64_t *stats, hipStream_t stream) {
+                         const DevParticles *grad_prop, int32_t *gvalid, int64_t *stats, const double *lq,
+                         hipStream_t stream) {
   const int64_t blocks = (state.n + 255) / 256;
   const DevParticlesW gc = grad_cur ? *grad_cur : DevParticlesW();
   const DevParticles gp = grad_prop ? *grad_prop : DevParticles();
   hipLaunchKernelGGL(accept_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, sh, a, move, state, ll, prop,
-                     ll_prop, mask, type, gamma, gc, gp, grad_cur ? gvalid : nullptr, stats);
+                     ll_prop, mask, type, gamma, gc, gp, grad_cur ? gvalid : nullptr, stats, lq);
   return hipGetLastError();
 }
 

@@ -36,7 +36,7 @@ class RJSMCRun:
     def __init__(self, ctx, n_sound, n_per_sound, y_obs, *, prior=None, alpha=0.5, n_moves=5, seed=0,
                  move_prob=UNIFORM_MOVES, z_move_frac=0.05, rw_scale=2.38, mala_eps=0.8, device="cuda",
                  graph=False, adapt_c=None, r_max=100, tune_scale=False, scale_target=0.44, n_bisect=6,
-                 scale_bracket=(0.05, 20.0)):
+                 scale_bracket=(0.05, 20.0), recycle=0, zca_birth=False):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -76,6 +76,15 @@ class RJSMCRun:
             self.stats_sound = torch.zeros((n_sound, 2), dtype=torch.int64, device=device)
         self.moves_per_step = []
         self._stats_prev = None
+        # particle recycling (Section 3.2.5): the proposals adapt to the current population
+        # pooled with the populations of up to `recycle` earlier steps (a ring)
+        if recycle and graph:
+            raise ValueError("particle recycling runs eagerly (the archive slot changes every step)")
+        if not 0 <= recycle <= B.MAX_ARCHIVE:
+            raise ValueError("recycle must be in 0..%d" % B.MAX_ARCHIVE)
+        self.archive = B.DeviceArchive(recycle, self.n, n_sound, kc, km, device) if recycle else None
+        # births and deaths by the adaptive construction of Appendix E.2
+        self.zca_birth = bool(zca_birth)
         self.use_graph = graph
         self.graphs = None
         self.step_dev = None
@@ -91,6 +100,15 @@ class RJSMCRun:
     def initialise(self):
         self.ctx.init_prior(self.state, self.prior, self.seed)
         self.ctx.loglik(self.state, self.y_obs, out=self.ll)
+        if self.archive is not None:
+            self.archive.n_used = 0
+            self._archive_current()
+
+    def _archive_current(self):
+        """Stores the current population (step self.step) in its ring slot."""
+        a = self.archive
+        self.ctx.archive_store(self.state, self.ll, self.gamma, self.log_z, self.S, a, self.step % a.n_slots)
+        a.n_used = min(a.n_used + 1, a.n_slots)
 
     def _launch_step(self, step_dev=None):
         """Enqueues one iteration of the while-loop of Algorithm 1 (step self.step, or the
@@ -100,9 +118,14 @@ class RJSMCRun:
                                    self.log_z, self.active, self.anc, self.alpha, self.seed, self.step, self.S,
                                    step_dev=step_dev)
         self.cur = nxt
-        self.ctx.adapt(self.state, self.S, self.prior, self.factors)
+        if self.archive is not None:
+            self.ctx.adapt_recycled(self.state, self.ll, self.gamma, self.log_z, self.S, self.archive, self.prior,
+                                    self.factors)
+        else:
+            self.ctx.adapt(self.state, self.S, self.prior, self.factors)
         common = dict(seed=self.seed, step=self.step, n_sound=self.S, prior=self.prior, z_move_sd=self.z_move_sd,
-                      rw_scale=self.rw_scale, factors=self.factors, mala_eps=self.mala_eps, step_dev=step_dev)
+                      rw_scale=self.rw_scale, factors=self.factors, mala_eps=self.mala_eps, step_dev=step_dev,
+                      zca_birth=self.zca_birth)
         if self.tune_scale:
             # bisection on the random-walk scale from trial proposals (never kept)
             bis = dict(target=self.scale_target, lo0=self.scale_bracket[0], hi0=self.scale_bracket[1],
@@ -118,6 +141,8 @@ class RJSMCRun:
                         grad_cur=self.grads[0] if self.grads else None,
                         grad_prop=self.grads[1] if self.grads else None,
                         rw_scale_dev=self.scale if self.tune_scale else None, **common)
+        if self.archive is not None:
+            self._archive_current()
         if step_dev is not None:
             self.ctx.counter_add(step_dev, 1)
 

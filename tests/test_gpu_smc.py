@@ -143,7 +143,7 @@ def test_adapt_factors(B, ctx):
                 np.testing.assert_allclose(got, ref, rtol=0, atol=1e-7 * np.abs(ref).max())
 
 
-def _device_factors(p, nps, n_sound, seed):
+def _device_factors(p, nps, n_sound, seed, scale=0.05):
     """Seeded proposal factors (any matrix is a valid factor) in both layouts."""
     from oracle import smc
     rng = np.random.default_rng(seed)
@@ -153,7 +153,7 @@ def _device_factors(p, nps, n_sound, seed):
         for m in range(M):
             k, l = m // (KM + 1), m % (KM + 1)
             d = 3 + 2 * k + 2 * l
-            Fm = np.diag(0.05 * smc.prior_sd(k, l, PR)) @ (np.eye(d) + 0.3 * rng.standard_normal((d, d)))
+            Fm = np.diag(scale * smc.prior_sd(k, l, PR)) @ (np.eye(d) + 0.3 * rng.standard_normal((d, d)))
             host[(s, m)] = Fm
             dev[s, m, :d, :d] = Fm.T
     return dev, host
@@ -438,3 +438,162 @@ def test_tuned_scale_run_graph_and_eager(B, truth_data):
         assert np.array_equal(getattr(a, k).cpu().numpy(), getattr(b, k).cpu().numpy()), k
     sc = a.scale.cpu().numpy()
     assert np.all((sc > 0.05) & (sc < 20.0))
+
+
+# ------------------------------------------------------------------- particle recycling
+def _recycle_case(B, ctx, n_sound, nps, n_used, seed):
+    """Archive of n_used earlier populations plus a current one, with random
+    log-likelihoods, increasing temperatures (the first slot the prior's) and evidence
+    estimates including an empty-evidence component; GPU factors and the oracle's."""
+    from oracle import smc
+    rng = np.random.default_rng(seed)
+    n = n_sound * nps
+    pops = []
+    for h in range(n_used + 1):                          # the last one is the current population
+        q = smc.init_population(seed + 10 * h, n, KC, KM, PR)
+        q["n_per_sounding"] = nps if n_sound > 1 else 0
+        pops.append(q)
+    lls = [-np.abs(rng.standard_cauchy(n)) * 20 - rng.uniform(0, 30, n) for _ in pops]
+    gam = np.sort(rng.uniform(0.0, 0.5, (n_used + 1, n_sound)), axis=0)
+    lz = rng.normal(0.0, 3.0, (n_used + 1, n_sound, M))
+    if n_used:
+        gam[0], lz[0] = 0.0, 0.0
+    if n_used > 1:
+        lz[1, 0, 3] = -np.inf
+    arch = B.DeviceArchive(max(n_used, 1) + 1, n, n_sound, KC, KM)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    for h in range(n_used):
+        ctx.archive_store(B.particles_to_device(pops[h]), dev(lls[h]), dev(gam[h]), dev(lz[h]), n_sound, arch, h)
+    arch.n_used = n_used
+    F = torch.zeros((n_sound, M, D, D), dtype=torch.float64, device="cuda")
+    ctx.adapt_recycled(B.particles_to_device(pops[-1]), dev(lls[-1]), dev(gam[-1]), dev(lz[-1]), n_sound, arch, PR, F)
+    ctx.check()
+    F = F.cpu().numpy()
+    refs = {}
+    for s in range(n_sound):
+        for m in range(M):
+            k, l = m // (KM + 1), m % (KM + 1)
+            thetas, llp, cnt = [], [], []
+            for q, (pq, lq) in enumerate(zip(pops, lls)):
+                models = smc.model_id(pq["kappa"], pq["lambda_"], KM)
+                mem = np.nonzero(models[s * nps:(s + 1) * nps] == m)[0] + s * nps
+                thetas += [smc.param_vector(pq, i) for i in mem]
+                llp.append(lq[mem])
+                cnt.append(len(mem))
+            lw = smc.recycled_log_weights(np.concatenate(llp), gam[:, s], lz[:, s, m], cnt, gam[-1, s])
+            refs[(s, m)] = smc.recycled_proposal_factor(np.array(thetas).reshape(-1, 3 + 2 * k + 2 * l), lw, k, l, PR)
+    return F, refs, pops, lls, gam, lz, arch
+
+
+def _check_factors(F, refs):
+    for (s, m), ref in refs.items():
+        k, l = m // (KM + 1), m % (KM + 1)
+        d = 3 + 2 * k + 2 * l
+        got = F[s, m, :d, :d].T
+        assert np.all(F[s, m, d:, :] == 0) and np.all(F[s, m, :, d:] == 0)
+        C = ref @ ref.T
+        np.testing.assert_allclose(got @ got.T, C, rtol=0, atol=1e-10 * np.abs(C).max(), err_msg=str((s, m)))
+
+
+@pytest.mark.parametrize("n_sound,nps,n_used", [(1, 256, 3), (2, 1024, 5), (3, 100, 1)])
+def test_adapt_recycled_against_oracle(B, ctx, n_sound, nps, n_used):
+    F, refs, *_ = _recycle_case(B, ctx, n_sound, nps, n_used, 40 + n_used)
+    _check_factors(F, refs)
+
+
+def test_adapt_recycled_with_an_empty_archive_is_adapt(B, ctx):
+    from oracle import smc
+    F, refs, pops, lls, gam, lz, arch = _recycle_case(B, ctx, 2, 512, 0, 7)
+    _check_factors(F, refs)
+    F0 = torch.zeros((2, M, D, D), dtype=torch.float64, device="cuda")
+    ctx.adapt(B.particles_to_device(pops[-1]), 2, PR, F0)
+    F0 = F0.cpu().numpy()
+    for s in range(2):
+        for m in range(M):
+            a, b = F[s, m], F0[s, m]
+            np.testing.assert_allclose(a.T @ a, b.T @ b, rtol=0, atol=1e-10 * max(np.abs(b.T @ b).max(), 1e-300))
+
+
+def test_archive_store_copies_every_row(B, ctx):
+    _, _, pops, lls, gam, lz, arch = _recycle_case(B, ctx, 2, 128, 2, 3)
+    n = 256
+    got = B.population_to_host(arch.pop)
+    for h in range(2):
+        for key in ("kappa", "lambda_", "phi_b", "phi", "z_cond", "m", "z_charg", "log10_tau", "c"):
+            np.testing.assert_array_equal(got[key][..., h * n:(h + 1) * n], pops[h][key], err_msg=key)
+        np.testing.assert_array_equal(arch.ll.cpu().numpy()[h * n:(h + 1) * n], lls[h])
+        np.testing.assert_array_equal(arch.gamma.cpu().numpy()[h], gam[h])
+        np.testing.assert_array_equal(arch.log_z.cpu().numpy()[h], lz[h])
+
+
+def test_rjsmc_run_with_recycling(B, truth_data):
+    from paper_2109_00661_amd import workloads as W2
+    from paper_2109_00661_amd.rjsmc import RJSMCRun
+    ctx = B.Context(W2.system(), precision="f64", max_particles=512)
+    y = np.stack([truth_data, truth_data])
+    run = RJSMCRun(ctx, 2, 256, y, seed=21, n_moves=2, recycle=6).run()
+    assert bool((run.gamma >= 1.0).all())
+    assert run.archive.n_used == 6
+    lz = run.log_z.cpu().numpy()
+    assert np.isfinite(lz.max(axis=1)).all()
+    with pytest.raises(ValueError):
+        RJSMCRun(ctx, 2, 256, y, seed=21, graph=True, recycle=4)
+
+
+@pytest.mark.parametrize("gamma", [0.003, 0.2])
+def test_mutate_adaptive_birth_against_oracle(B, ctx, system, K_oracle, truth_data, gamma):
+    """Adaptive birth and death (Appendix E.2) with seeded covariance roots per model:
+    states, likelihoods and tallies as the oracle's (decisions within 1e-8 of the
+    threshold excepted)."""
+    from oracle import em, smc
+    n, n_moves, seed, step = 128, 4, 321, 6
+    p = smc.init_population(43, n, KC, KM, PR)
+    ll0 = em.loglik(p, system, K_oracle, truth_data)
+    q = dict(move_prob=np.array([1, 1, 0, 1, 1, 0, 1, 0], float), z_move_sd=0.05 * PR["z_max"], rw_scale=2.38)
+    fdev, fhost = _device_factors(p, n, 1, 9, scale=0.5)
+    q["zca"] = True
+    q["factor_of_model"] = lambda i, k, l: fhost[(0, smc.model_id(k, l, KM))]
+    po = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+    llo = ll0.copy()
+    models = lambda i: smc.model_id(int(po["kappa"][i]), int(po["lambda_"][i]), KM)
+    st_o, margins = smc.mutate(po, llo, lambda pp, i: em.loglik(pp, system, K_oracle, truth_data, [i])[0],
+                               lambda i: gamma, step, seed, q, PR, KC, KM, lambda i: fhost[(0, models(i))], n_moves)
+    dp = B.particles_to_device(p)
+    scratch = B.empty_device_population(n, KC, KM)
+    ll_d = torch.as_tensor(ll0, device="cuda")
+    stats = torch.zeros((2, 8), dtype=torch.int64, device="cuda")
+    ctx.mutate(dp, ll_d, scratch, torch.empty_like(ll_d), torch.tensor([gamma], dtype=torch.float64, device="cuda"),
+               None, torch.as_tensor(truth_data, device="cuda"), stats, seed=seed, step=step, n_moves=n_moves,
+               n_sound=1, prior=PR, move_prob=q["move_prob"], z_move_sd=q["z_move_sd"], rw_scale=q["rw_scale"],
+               factors=torch.as_tensor(fdev, device="cuda"), zca_birth=True)
+    ctx.check()
+    got = _host(B, dp)
+    near = {i for i, r, mg in margins if abs(mg) < 1e-8}
+    ok = [i for i in range(n) if i not in near]
+    assert len(ok) >= n - 2
+    for k in ("kappa", "lambda_"):
+        assert np.array_equal(got[k][ok], po[k][ok]), k
+    for k in ("phi_b", "phi", "z_cond", "m", "z_charg", "log10_tau", "c"):
+        np.testing.assert_allclose(got[k][..., ok], po[k][..., ok], rtol=1e-12, atol=1e-12, err_msg=k)
+    np.testing.assert_allclose(ll_d.cpu().numpy()[ok], llo[ok], rtol=1e-9, atol=1e-9)
+    if not near:
+        assert np.array_equal(stats.cpu().numpy(), st_o)
+    assert st_o[1, [0, 1, 3, 4]].sum() > 0                # some adaptive births or deaths were accepted
+
+
+def test_rjsmc_run_with_adaptive_birth(B, truth_data):
+    """Algorithm 1 with the adaptive birth/death of Appendix E.2, eager and as step graphs
+    (identical), reaches gamma = 1 with finite evidence for the populated models."""
+    from paper_2109_00661_amd import workloads as W2
+    from paper_2109_00661_amd.rjsmc import RJSMCRun
+    ctx = B.Context(W2.system(), precision="f64", max_particles=512)
+    y = np.stack([truth_data, truth_data])
+    runs = [RJSMCRun(ctx, 2, 256, y, seed=5, n_moves=2, zca_birth=True, graph=g).run() for g in (False, True)]
+    for r in runs:
+        assert bool((r.gamma >= 1.0).all())
+        st = r.stats.cpu().numpy()
+        assert st[1, [0, 1, 3, 4]].sum() > 0
+    a, b = (B.population_to_host(r.state) for r in runs)
+    for key in ("kappa", "lambda_", "phi_b", "phi", "z_cond", "m", "z_charg", "log10_tau", "c"):
+        np.testing.assert_array_equal(a[key], b[key], err_msg=key)
+    np.testing.assert_array_equal(runs[0].log_z.cpu().numpy(), runs[1].log_z.cpu().numpy())
