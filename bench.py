@@ -184,19 +184,26 @@ def accuracy_comparison(torch, d, sizes=(256, 512, 1024), reps=32, adapt_c=0.01,
     """Random-walk against gradient-informed (Langevin) within-model moves on the same
     GPU: `reps` replicate runs of the synthetic sounding (batched) for each particle count,
     with the adaptive number of sweeps (c = 0.01: every particle moves with probability
-    0.99) and tuned tiles.  The spread over replicates of the marginal log-evidence and of
-    the best model's posterior probability measures accuracy; soundings/s the cost."""
+    0.99) and tuned tiles; then the random walk at 512 particles with the adaptive birth
+    and with particle recycling (8 populations, eager).  The spread over replicates of
+    the marginal log-evidence and of the best model's posterior probability measures
+    accuracy; soundings/s the cost."""
     from paper_2109_00661_amd.rjsmc import UNIFORM_MOVES, LANGEVIN_MOVES
     rows = []
-    for name, mp in (("random_walk", UNIFORM_MOVES), ("langevin", LANGEVIN_MOVES)):
-        for n in sizes:
-            r = rjsmc_rate(torch, d, reps, n, move_prob=mp, graph=True, tune=True, adapt_c=adapt_c, r_max=r_max)
-            row = {"moves": name, "particles_per_sounding": n}
-            row.update({k: r[k] for k in ("soundings_per_s", "steps", "sweeps_per_step_mean", "acceptance",
-                                          "log_evidence_mean", "log_evidence_sd", "best_model", "p_best_model_mean",
-                                          "p_best_model_sd", "ll_max_median")})
-            print(json.dumps(row), file=sys.stderr, flush=True)
-            rows.append(row)
+    cases = [(name, mp, n, True, {}) for name, mp in (("random_walk", UNIFORM_MOVES), ("langevin", LANGEVIN_MOVES))
+             for n in sizes]
+    # the paper's adaptive machinery on the random-walk sampler at 512 particles
+    cases += [("random_walk_adaptive_birth", UNIFORM_MOVES, 512, True, {"zca_birth": True}),
+              ("random_walk_recycling_8", UNIFORM_MOVES, 512, False, {"recycle": 8})]
+    for name, mp, n, graph, extra in cases:
+        r = rjsmc_rate(torch, d, reps, n, move_prob=mp, graph=graph, tune=True, adapt_c=adapt_c, r_max=r_max,
+                       **extra)
+        row = {"moves": name, "particles_per_sounding": n, "graph": graph}
+        row.update({k: r[k] for k in ("soundings_per_s", "steps", "sweeps_per_step_mean", "acceptance",
+                                      "log_evidence_mean", "log_evidence_sd", "best_model", "p_best_model_mean",
+                                      "p_best_model_sd", "ll_max_median")})
+        print(json.dumps(row), file=sys.stderr, flush=True)
+        rows.append(row)
     return rows
 
 

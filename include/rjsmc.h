@@ -392,9 +392,11 @@ typedef struct {
 } rjsmc_tuning;
 
 /* The tile shapes, as (waves_per_block, waves_per_particle):
- *   (2,1) (4,1) (8,1) (2,2) (1,4) (1,8),
- * each with layer_sort 0 and 1: candidate k = 2 * shape index + layer_sort. */
-#define RJSMC_TUNING_CANDIDATES 12
+ *   (2,1) (4,1) (8,1) (2,2) (1,4) (1,8) (1,16),
+ * each with layer_sort 0 and 1: candidate k = 2 * shape index + layer_sort.  With more
+ * waves per particle than groups of 8 frequencies, each group's filter abscissae are
+ * split among the waves as well (the sums keep the same order). */
+#define RJSMC_TUNING_CANDIDATES 14
 
 /* Sets / reads the tile shape used by rjsmc_forward, rjsmc_loglik and the proposal
  * likelihoods of rjsmc_mutate (default {4, 0, 1}).  RJSMC_E_INVALID for a shape not in

@@ -94,8 +94,8 @@ class Tuning(ctypes.Structure):
                 ("waves_per_particle", ctypes.c_int32)]
 
 
-TUNING_CANDIDATES = 12
-TILE_SHAPES = ((2, 1), (4, 1), (8, 1), (2, 2), (1, 4), (1, 8))   # (waves_per_block, waves_per_particle)
+TUNING_CANDIDATES = 14
+TILE_SHAPES = ((2, 1), (4, 1), (8, 1), (2, 2), (1, 4), (1, 8), (1, 16))   # (waves_per_block, waves_per_particle)
 
 
 def make_prior(pr):

@@ -90,9 +90,16 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
   const int gl = lane & 7, gw = lane >> 3;
   const int nhg = nhp >> 3;
   const int nq = (nf + 7) >> 3;
+  // With more waves per particle than frequency chunks, each chunk's abscissa groups are
+  // split into A parts (work unit = chunk x part); the parts store their reflection
+  // terms and the particle's first wave adds them in the order of the A == 1 path, so
+  // every tile shape gives the same sums.
+  const int A = (P > 1 && P > nq) ? P / nq : 1;
+  double *s_rim = s_K + nf * ng + pw * nf * nhp;   // [nf][nhp] reflection terms when A > 1
   // the waves of a workgroup run independently from here on (wave-level syncs only)
 #pragma unroll 1
-  for (int q = q0; q < nq; q += P) {
+  for (int u = q0; u < nq * A; u += P) {
+    const int q = A == 1 ? u : u / A, part = u - q * A;
     const int jf = gw + 8 * q;
     const bool act = L > 0 && jf < nf;
     if (act) {
@@ -114,14 +121,14 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
       }
     }
     wave_lds_sync();
-    if (act) {
+    if (act && A == 1) {
       double acc = 0.0;
 #pragma unroll 1
       for (int sidx = 0; sidx < nhg; ++sidx) {
         const int k = gl + 8 * sidx;
         const T rim = reflection_im<T>(to<T>(s_lam[k]), s_k2[wave][gw], s_dk2[wave][gw], s_h2[wave], L,
                                          s_phase, s_exp2);
-        acc += s_ck[k] * static_cast<double>(rim);
+        acc = __builtin_fma(s_ck[k], static_cast<double>(rim), acc);
       }
       // reduce over the 8 abscissa groups (lane bits 0..2); all 8 lanes of a group
       // share jf, so a group is either wholly active or wholly idle here
@@ -129,12 +136,37 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
       acc += __shfl_xor(acc, 2);
       acc += __shfl_xor(acc, 4);
       if (gl == 0) s_imh[pw][jf] = acc;
+    } else if (act) {
+#pragma unroll 1
+      for (int sidx = part * nhg / A; sidx < (part + 1) * nhg / A; ++sidx) {
+        const int k = gl + 8 * sidx;
+        s_rim[jf * nhp + k] = static_cast<double>(reflection_im<T>(to<T>(s_lam[k]), s_k2[wave][gw],
+                                                                   s_dk2[wave][gw], s_h2[wave], L, s_phase,
+                                                                   s_exp2));
+      }
     }
     wave_lds_sync();
   }
   if (P > 1) {
-    __syncthreads();                 // every wave of the particle has written its Im H
+    __syncthreads();                 // every wave of the particle has written its terms or Im H
     if (q0 != 0) return;
+  }
+  if (A > 1 && L > 0) {
+    // Im H from the stored terms, added in the order of the A == 1 path
+    for (int qq = 0; qq < nq; ++qq) {
+      const int jf = gw + 8 * qq;
+      double acc = 0.0;
+      if (jf < nf)
+        for (int sidx = 0; sidx < nhg; ++sidx) {
+          const int k = gl + 8 * sidx;
+          acc = __builtin_fma(s_ck[k], s_rim[jf * nhp + k], acc);
+        }
+      acc += __shfl_xor(acc, 1);
+      acc += __shfl_xor(acc, 2);
+      acc += __shfl_xor(acc, 4);
+      if (gl == 0 && jf < nf) s_imh[pw][jf] = acc;
+    }
+    wave_lds_sync();
   }
   if (L > 0) {
     double term = 0.0;
@@ -175,7 +207,10 @@ static hipError_t launch_t(const DevSystem &s, const DevParticles &p, int kc, in
                            const double *y_obs, double *ll, const int32_t *perm, hipStream_t stream) {
   const int64_t blocks = (p.n + WPB - 1) / WPB;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  const size_t dyn = sizeof(double) * s.n_freq * s.n_gate;
+  const int nq = (s.n_freq + 7) / 8;
+  const int A = (P > 1 && P > nq) ? P / nq : 1;
+  const size_t dyn =
+      sizeof(double) * (s.n_freq * s.n_gate + (A > 1 ? (size_t)WPB * s.n_freq * s.n_hankel_pad : 0));
   hipLaunchKernelGGL((forward_kernel<T, WPB, P>), dim3((unsigned)blocks), dim3(kWave * WPB * P), dyn, stream, s, p,
                      kc, km, resp, y_obs, ll, perm);
   return hipGetLastError();
@@ -188,6 +223,7 @@ static hipError_t launch_prec(const ForwardTiles &t, const DevSystem &s, const D
   if (q == 2 && w == 2) return launch_t<T, 2, 2>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
   if (q == 4 && w == 1) return launch_t<T, 1, 4>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
   if (q == 8 && w == 1) return launch_t<T, 1, 8>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
+  if (q == 16 && w == 1) return launch_t<T, 1, 16>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
   if (q != 1) return hipErrorInvalidValue;
   if (w == 2) return launch_t<T, 2, 1>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
   if (w == 8) return launch_t<T, 8, 1>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);

@@ -720,12 +720,14 @@ extern "C" rjsmc_status rjsmc_mutate(rjsmc_ctx *c, const rjsmc_mutate_args *a, r
   if (e == hipSuccess && gvalid) e = rjsmc::launch_fill_i32(gvalid, ds.n, 0, s);
   for (int r0 = 0; r0 < a->n_moves && e == hipSuccess; ++r0) {
     const int r = a->trial * (1 << 20) + r0;   // random-number move index
-    e = rjsmc::launch_draw_types(*a, r, ds, sh.kc, sh.km, c->work_mask, c->work_type, active, gvalid, s);
-    if (e == hipSuccess && mala)   // gradients of the current states of the particles taking a Langevin step
-      e = rjsmc::launch_loglik_grad(c->dev, cur2, c->kmax_cond, c->kmax_charg, y_obs, ll_scratch, gcw, s);
-    if (e == hipSuccess)
+    if (mala) {
+      e = rjsmc::launch_draw_types(*a, r, ds, sh.kc, sh.km, c->work_mask, c->work_type, active, gvalid, s);
+      if (e == hipSuccess)   // gradients of the current states of the particles taking a Langevin step
+        e = rjsmc::launch_loglik_grad(c->dev, cur2, c->kmax_cond, c->kmax_charg, y_obs, ll_scratch, gcw, s);
+    }
+    if (e == hipSuccess)   // without gradient moves the proposal kernel draws the types itself
       e = rjsmc::launch_propose(sh, *a, r, ds, writable(dq), c->work_mask, c->work_type, gamma, mala ? &gcd : nullptr,
-                                gvalid, c->work_lq, s);
+                                gvalid, c->work_lq, active, !mala, s);
     if (e == hipSuccess)
       e = run_forward(c, prop1, c->tuning, nullptr, y_obs, ll_scratch, s);
     if (e == hipSuccess && mala)
@@ -740,7 +742,7 @@ extern "C" rjsmc_status rjsmc_mutate(rjsmc_ctx *c, const rjsmc_mutate_args *a, r
 
 // ---------------------------------------------------------------------------- tuning
 // (waves_per_block, waves_per_particle) of the compiled tile shapes.
-static const int kShapes[RJSMC_TUNING_CANDIDATES / 2][2] = {{2, 1}, {4, 1}, {8, 1}, {2, 2}, {1, 4}, {1, 8}};
+static const int kShapes[RJSMC_TUNING_CANDIDATES / 2][2] = {{2, 1}, {4, 1}, {8, 1}, {2, 2}, {1, 4}, {1, 8}, {1, 16}};
 
 static bool valid_tuning(const rjsmc_tuning &t) {
   if (t.layer_sort != 0 && t.layer_sort != 1) return false;

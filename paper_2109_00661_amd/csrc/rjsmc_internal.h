@@ -138,9 +138,12 @@ hipError_t launch_archive_store(const DevParticles &src, const double *ll, const
 hipError_t launch_draw_types(const rjsmc_mutate_args &a, int move, const DevParticles &state, int kc, int km,
                              int32_t *mask, int32_t *type, const int32_t *active, const int32_t *gvalid,
                              hipStream_t stream);
+// draw = true: the kernel also draws the move types (runs without gradient moves, which
+// need the types before the current-state gradients)
 hipError_t launch_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticles &state,
-                          const DevParticlesW &prop, int32_t *mask, const int32_t *type, const double *gamma,
-                          const DevParticles *grad_cur, int32_t *gvalid, double *lq, hipStream_t stream);
+                          const DevParticlesW &prop, int32_t *mask, int32_t *type, const double *gamma,
+                          const DevParticles *grad_cur, int32_t *gvalid, double *lq, const int32_t *active,
+                          bool draw, hipStream_t stream);
 hipError_t launch_accept(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticlesW &state,
                          double *ll, const DevParticles &prop, const double *ll_prop, const int32_t *mask,
                          const int32_t *type, const double *gamma, const DevParticlesW *grad_cur,

@@ -197,6 +197,7 @@ struct RwShared {
   int16_t item_m[kMaxItems], item_q0[kMaxItems];
   int item_base[kMaxModels + 1];
   int n_items;
+  int16_t anc_l[kMaxPerSounding];   // ancestor of each particle (index within the sounding)
   double tessk[kBisectK];
 };
 
@@ -329,11 +330,35 @@ __device__ __forceinline__ uint64_t sys_threshold(uint64_t j, uint64_t U, uint64
   return (q1 << 32) | q2;
 }
 
+// out[i] = in[src] for every row of the population and ll_out[i] = ll_in[src].
+__device__ __forceinline__ void copy_particle(const DevParticles &in, const double *ll_in, const DevParticlesW &out,
+                                              double *ll_out, int64_t i, int64_t src, int rows_c, int rows_m,
+                                              int rows_zm) {
+  const int64_t Si = in.stride, So = out.stride;
+  out.kappa[i] = in.kappa[src];
+  if (out.lambda) out.lambda[i] = in.lambda ? in.lambda[src] : 0;
+  out.phi_b[i] = in.phi_b[src];
+  out.log10_tau[i] = in.log10_tau[src];
+  out.c[i] = in.c[src];
+  ll_out[i] = ll_in[src];
+  for (int r = 0; r < rows_c; ++r) {
+    out.phi[r * So + i] = in.phi[r * Si + src];
+    out.z_cond[r * So + i] = in.z_cond[r * Si + src];
+  }
+  for (int r = 0; r < rows_m; ++r) out.m[r * So + i] = in.m[r * Si + src];
+  for (int r = 0; r < rows_zm; ++r) out.z_charg[r * So + i] = in.z_charg[r * Si + src];
+}
+
+// One workgroup per sounding: re-weight, evidence, within-model resampling, and the
+// resampled population written to out (each particle copied from its ancestor).
 __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape sh, rjsmc_reweight_args a,
                                                                        DevParticles in, const double *ll_in,
+                                                                       DevParticlesW out, double *ll_out,
                                                                        double *gamma, double *log_z,
                                                                        int32_t *active, int32_t *anc, int *flags) {
   __shared__ RwShared sm;
+  const bool dec = in.layout == RJSMC_LAYOUT_DECOUPLED;
+  const int rows_c = sh.kc, rows_m = dec ? sh.km : sh.kc + 1, rows_zm = dec ? sh.km : 0;
   const int s = blockIdx.x;
   const int N = (int)(in.n_per_sounding > 0 ? in.n_per_sounding : in.n);
   const int64_t off = (int64_t)s * N;
@@ -341,7 +366,10 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
   const double g0 = gamma[s];
   if (!(g0 < 1.0)) {
-    for (int i = tid; i < N; i += kRwThreads) anc[off + i] = (int32_t)(off + i);
+    for (int i = tid; i < N; i += kRwThreads) {
+      anc[off + i] = (int32_t)(off + i);
+      copy_particle(in, ll_in, out, ll_out, off + i, off + i, rows_c, rows_m, rows_zm);
+    }
     if (tid == 0 && active) active[s] = 0;
     return;
   }
@@ -487,6 +515,8 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
   __syncthreads();
   // ancestors: member j of model m takes the first member whose cumulative weight
   // exceeds the j-th systematic threshold
+  for (int i = tid; i < N; i += kRwThreads) sm.anc_l[i] = (int16_t)i;
+  __syncthreads();
   for (int pos = tid; pos < N; pos += kRwThreads) {
     const int dest = sm.idx[pos];
     if (dest < 0 || dest >= N) {       // cannot happen for a complete sort; never write outside
@@ -510,7 +540,14 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
       src = sm.idx[b + lo];
       if (src < 0 || src >= N) src = dest;
     }
-    anc[off + dest] = (int32_t)(off + src);
+    sm.anc_l[dest] = (int16_t)src;
+  }
+  __syncthreads();
+  // the resampled population, in particle order (coalesced writes)
+  for (int i = tid; i < N; i += kRwThreads) {
+    const int src = sm.anc_l[i];
+    anc[off + i] = (int32_t)(off + src);
+    copy_particle(in, ll_in, out, ll_out, off + i, off + src, rows_c, rows_m, rows_zm);
   }
   if (tid == 0) {
     gamma[s] = full ? 1.0 : g0 + dg;
@@ -518,40 +555,11 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
   }
 }
 
-// out[i] = in[anc[i]] for every array of the population, ll_out[i] = ll_in[anc[i]].
-__global__ __launch_bounds__(256) void gather_kernel(DevParticles in, const double *ll_in, DevParticlesW out,
-                                                     double *ll_out, const int32_t *anc, int rows_c, int rows_m,
-                                                     int rows_zm) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= in.n) return;
-  int64_t a = anc[i];
-  if (a < 0 || a >= in.n) a = i;
-  const int64_t Si = in.stride, So = out.stride;
-  out.kappa[i] = in.kappa[a];
-  if (out.lambda) out.lambda[i] = in.lambda ? in.lambda[a] : 0;
-  out.phi_b[i] = in.phi_b[a];
-  out.log10_tau[i] = in.log10_tau[a];
-  out.c[i] = in.c[a];
-  ll_out[i] = ll_in[a];
-  for (int r = 0; r < rows_c; ++r) {
-    out.phi[r * So + i] = in.phi[r * Si + a];
-    out.z_cond[r * So + i] = in.z_cond[r * Si + a];
-  }
-  for (int r = 0; r < rows_m; ++r) out.m[r * So + i] = in.m[r * Si + a];
-  for (int r = 0; r < rows_zm; ++r) out.z_charg[r * So + i] = in.z_charg[r * Si + a];
-}
-
 hipError_t launch_reweight_resample(const SmcShape &sh, const rjsmc_reweight_args &a, const DevParticles &in,
                                     const double *ll_in, const DevParticlesW &out, double *ll_out, double *gamma,
                                     double *log_z, int32_t *active, int32_t *anc, int *flags, hipStream_t stream) {
   hipLaunchKernelGGL(reweight_resample_kernel, dim3((unsigned)a.n_sound), dim3(kRwThreads), 0, stream, sh, a, in,
-                     ll_in, gamma, log_z, active, anc, flags);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const bool dec = in.layout == RJSMC_LAYOUT_DECOUPLED;
-  const int64_t blocks = (in.n + 255) / 256;
-  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, in, ll_in, out, ll_out, anc, sh.kc,
-                     dec ? sh.km : sh.kc + 1, dec ? sh.km : 0);
+                     ll_in, out, ll_out, gamma, log_z, active, anc, flags);
   return hipGetLastError();
 }
 
@@ -604,6 +612,7 @@ __device__ __forceinline__ double prior_sd(const rjsmc_prior &pr, double zmax, i
 // factor of the covariance (eigen_factor).
 constexpr int kDimMax = 3 + 2 * (kMaxLayers - 1);   // 33
 constexpr int kLd = kDimMax + 1;                    // LDS row stride
+constexpr int kAdaptThreads = 512;                 // workgroup of the adaptation kernels
 
 // Jacobi eigen-decomposition of the symmetric d x d matrix A (LDS, overwritten; V0 holds
 // the identity, T two spare d x d buffers) and the factor F = U diag(sqrt Lambda) into
@@ -615,130 +624,112 @@ constexpr int kLd = kDimMax + 1;                    // LDS row stride
 // at once, A <- J^T A J with J the product of the round's rotations.  Each pair's 2x2
 // block is touched by its own rotation only, so its diagonal takes the classical update
 // and its off-diagonal entry is set to zero.
+template <int NT>
 __device__ __forceinline__ void eigen_factor(double (*A)[kLd], double (*V0)[kLd], double (*T)[kDimMax][kLd],
-                                             double *rc, double *rs, double *shift, int *order, int d, int D,
-                                             double *F) {
-  const int lane = threadIdx.x & (kWave - 1);
-  double (*Vc)[kLd] = V0;         // current eigenvector estimate
-  double (*Vn)[kLd] = T[1];       // its next-round buffer
-  double (*B)[kLd] = T[0];        // A J of a round
+                                             double *rc, double *rs, int *order, int d, int D, double *F) {
+  const int tid = threadIdx.x;
+  auto sync = [] {
+    if (NT > kWave)
+      __syncthreads();
+    else
+      wave_lds_sync();
+  };
+  __shared__ int partner[kLd];
+  __shared__ double red[2][NT / kWave];
+  double (*Vc)[kLd] = V0;        // current eigenvector estimate
+  double (*Vn)[kLd] = T[1];      // its column-pass buffer
+  double (*B)[kLd] = T[0];       // column-pass buffer of A
   const int nn = (d + 1) & ~1, np = nn / 2;
-  const int dd = d * d;
-  // element t = lane + 64 it of the d x d matrix as (row, column), stepped without division
-  const int r0 = lane / d, c0 = lane % d, rstep = kWave / d, cstep = kWave % d;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    double offn = 0.0, diag = 0.0, dmax = 0.0;
-    for (int t = lane, x = r0, y = c0; t < dd; t += kWave) {
-      const double v = A[x][y] * A[x][y];
-      offn += x != y ? v : 0.0;
-      diag += x == y ? v : 0.0;
-      dmax = x == y ? fmax(dmax, fabs(A[x][x])) : dmax;
-      x += rstep;
-      y += cstep;
-      if (y >= d) {
-        y -= d;
-        ++x;
-      }
+    double offn = 0.0, diag = 0.0;
+    for (int t = tid; t < d * d; t += NT) {
+      const int a = t / d, b = t % d;
+      if (a != b) offn += A[a][b] * A[a][b];
+      else diag += A[a][b] * A[a][b];
     }
     offn = wave_sum(offn);
     diag = wave_sum(diag);
-    dmax = wave_max(dmax);
+    if (NT > kWave) {                  // the waves' sums, added in wave order
+      if ((tid & (kWave - 1)) == 0) {
+        red[0][tid / kWave] = offn;
+        red[1][tid / kWave] = diag;
+      }
+      __syncthreads();
+      offn = 0.0;
+      diag = 0.0;
+      for (int w = 0; w < NT / kWave; ++w) {
+        offn += red[0][w];
+        diag += red[1][w];
+      }
+      __syncthreads();
+    }
     if (!(offn > 1e-30 * diag)) break;
-    // an off-diagonal entry below 1e-16 sqrt(|a_pp a_qq|), or below 1e-18 of the largest
-    // diagonal entry, is rounding noise: it is set to zero without a rotation, and a
-    // sweep without any rotation ends the iteration
-    const double floor_abs = 1e-18 * dmax;
-    bool any_rot = false;
     for (int round = 0; round < nn - 1; ++round) {
-      // partner of index x in this round: pairs (nn-1, round) and (round + i, round - i)
-      // mod nn-1, i = 1 .. nn/2 - 1; a partner beyond d (the padding index) leaves x alone
-      auto partner_of = [&](int x) {
-        int y;
-        if (x == nn - 1)
-          y = round;
-        else if (x == round)
-          y = nn - 1;
-        else {
-          y = 2 * round - x;
-          if (y < 0) y += nn - 1;
-          if (y >= nn - 1) y -= nn - 1;
-        }
-        return y < d ? y : x;
-      };
+      // pair `tid` of this round: (nn-1, round) and ((round + j) mod (nn-1), (round - j) mod (nn-1))
+      int pp = 0, qq = 0;
+      double app = 0.0, aqq = 0.0, apq = 0.0, tt = 0.0;
       bool rot = false;
-      if (lane < np) {
-        int x = lane == 0 ? nn - 1 : round + lane;
-        if (lane != 0 && x >= nn - 1) x -= nn - 1;
-        int y = lane == 0 ? round : round - lane;
-        if (y < 0) y += nn - 1;
-        const int pp = x < y ? x : y, qq = x < y ? y : x;
+      if (tid < np) {
+        int x = tid == 0 ? nn - 1 : (round + tid) % (nn - 1);
+        int y = tid == 0 ? round : (round - tid + (nn - 1)) % (nn - 1);
+        pp = x < y ? x : y;
+        qq = x < y ? y : x;
+        double cth = 1.0, sth = 0.0;
         if (qq < d) {
-          const double apq = A[pp][qq], app = A[pp][pp], aqq = A[qq][qq];
-          double cth = 1.0, sth = 0.0, tt = 0.0;
-          rot = fabs(apq) > fmax(1e-16 * sqrt(fabs(app * aqq)), floor_abs);
-          if (rot) {
+          apq = A[pp][qq];
+          if (apq != 0.0) {
+            app = A[pp][pp];
+            aqq = A[qq][qq];
             const double theta = (aqq - app) / (2.0 * apq);
             tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
             cth = 1.0 / sqrt(tt * tt + 1.0);
             sth = tt * cth;
+            rot = true;
           }
+          partner[pp] = qq;
+          partner[qq] = pp;
           rc[pp] = cth;
           rs[pp] = -sth;
           rc[qq] = cth;
           rs[qq] = sth;
-          shift[pp] = -(tt * apq);
-          shift[qq] = tt * apq;
         } else if (pp < d) {           // paired with the padding index: untouched
+          partner[pp] = pp;
           rc[pp] = 1.0;
           rs[pp] = 0.0;
-          shift[pp] = 0.0;
         }
       }
-      any_rot = any_rot || __any(rot);
-      wave_lds_sync();
+      sync();
       // column pass: B = A J, Vn = Vc J
-      for (int t = lane, i = r0, x = c0; t < dd; t += kWave) {
-        const int y = partner_of(x);
+      for (int t = tid; t < d * d; t += NT) {
+        const int i = t / d, x = t % d;
+        const int y = partner[x];
         const double c_ = rc[x], s_ = rs[x];
         B[i][x] = c_ * A[i][x] + s_ * A[i][y];
         Vn[i][x] = c_ * Vc[i][x] + s_ * Vc[i][y];
-        i += rstep;
-        x += cstep;
-        if (x >= d) {
-          x -= d;
-          ++i;
-        }
       }
-      wave_lds_sync();
-      // row pass: A = J^T B; a pair's 2x2 block takes the classical diagonal update
-      // (from the round's A) and a zero off-diagonal
-      for (int t = lane, x = r0, j = c0; t < dd; t += kWave) {
-        const int y = partner_of(x);
-        double v;
-        if (x == j)
-          v = A[x][x] + shift[x];
-        else if (y == j)
-          v = 0.0;
-        else
-          v = rc[x] * B[x][j] + rs[x] * B[y][j];
-        A[x][j] = v;
-        x += rstep;
-        j += cstep;
-        if (j >= d) {
-          j -= d;
-          ++x;
-        }
+      sync();
+      // row pass: A = J^T B
+      for (int t = tid; t < d * d; t += NT) {
+        const int x = t / d, j = t % d;
+        const int y = partner[x];
+        A[x][j] = rc[x] * B[x][j] + rs[x] * B[y][j];
       }
-      wave_lds_sync();
+      sync();
+      if (rot) {
+        A[pp][pp] = app - tt * apq;
+        A[qq][qq] = aqq + tt * apq;
+        A[pp][qq] = 0.0;
+        A[qq][pp] = 0.0;
+      }
       double (*sw)[kLd] = Vc;
       Vc = Vn;
       Vn = sw;
+      sync();
     }
-    if (!any_rot) break;
   }
   double (*Ac)[kLd] = A;
-  // descending eigenvalue order (stable selection by lane 0)
-  if (lane == 0) {
+  // descending eigenvalue order (stable selection by one thread)
+  if (tid == 0) {
     for (int a = 0; a < d; ++a) order[a] = a;
     for (int a = 1; a < d; ++a) {
       const int v = order[a];
@@ -750,8 +741,8 @@ __device__ __forceinline__ void eigen_factor(double (*A)[kLd], double (*V0)[kLd]
       order[b] = v;
     }
   }
-  wave_lds_sync();
-  for (int r = lane; r < d; r += kWave) {
+  sync();
+  for (int r = tid; r < d; r += NT) {
     const int c = order[r];
     const double ev = Ac[c][c] > 0.0 ? sqrt(Ac[c][c]) : 0.0;
     int big = 0;
@@ -762,18 +753,19 @@ __device__ __forceinline__ void eigen_factor(double (*A)[kLd], double (*V0)[kLd]
   }
 }
 
-__global__ __launch_bounds__(kWave) void adapt_kernel(SmcShape sh, DevParticles p, rjsmc_prior pr, double *factors) {
+__global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(SmcShape sh, DevParticles p, rjsmc_prior pr, double *factors) {
   __shared__ int16_t mem[kMaxPerSounding];
   __shared__ double A[kDimMax][kLd];
   __shared__ double V0[kDimMax][kLd];
   // member staging (64 rows) during the moments; column-pass buffers of A and V after
   __shared__ double T[2][kDimMax][kLd];
   __shared__ double mu[kDimMax];
-  __shared__ double rc[kLd], rs[kLd], shift[kLd];
+  __shared__ double rc[kLd], rs[kLd];
+  __shared__ int s_ready;
   __shared__ int order[kDimMax];
   static_assert(kWave * kLd <= 2 * kDimMax * kLd, "staging fits the column-pass buffers");
   double (*X)[kLd] = reinterpret_cast<double (*)[kLd]>(&T[0][0][0]);
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int M = sh.n_models;
   const int s = blockIdx.x / M, m = blockIdx.x % M;
   const int N = (int)(p.n_per_sounding > 0 ? p.n_per_sounding : p.n);
@@ -781,70 +773,80 @@ __global__ __launch_bounds__(kWave) void adapt_kernel(SmcShape sh, DevParticles 
   const int k = m / (sh.km + 1), l = m % (sh.km + 1);
   const int d = 3 + 2 * k + 2 * l, D = sh.dmax;
   double *F = factors + (int64_t)blockIdx.x * D * D;
-  // members in index order
-  int nm = 0;
-  for (int c0 = 0; c0 < N; c0 += kWave) {
-    const int i = c0 + lane;
-    const bool sel = i < N && p.kappa[off + i] == k && p.lambda[off + i] == l;
-    const uint64_t b = __ballot(sel);
-    if (sel) mem[nm + __popcll(b & ((1ull << lane) - 1))] = (int16_t)i;
-    nm += __popcll(b);
-  }
-  wave_lds_sync();
-  for (int t = lane; t < D * D; t += kWave) F[t] = 0.0;
-  if (nm <= d) {
-    for (int a = lane; a < d; a += kWave) F[a * D + a] = 0.1 * prior_sd(pr, sh.z_max, k, l, a);
-    return;
-  }
-  // mean: members staged 64 at a time, summed in index order by lane a
-  double acc_mu = 0.0;
-  for (int q0 = 0; q0 < nm; q0 += kWave) {
-    const int q = q0 + lane;
-    if (q < nm)
-      for (int a = 0; a < d; ++a) X[lane][a] = theta_get(p, off + mem[q], k, l, a);
-    wave_lds_sync();
-    const int nq = nm - q0 < kWave ? nm - q0 : kWave;
-    if (lane < d)
-      for (int r = 0; r < nq; ++r) acc_mu += X[r][lane];
-    wave_lds_sync();
-  }
-  if (lane < d) mu[lane] = acc_mu / (double)nm;
-  for (int t = lane; t < d * d; t += kWave) A[t / d][t % d] = 0.0;
-  wave_lds_sync();
-  // covariance: stage 64 centred members at a time
-  for (int q0 = 0; q0 < nm; q0 += kWave) {
-    const int q = q0 + lane;
-    if (q < nm)
-      for (int a = 0; a < d; ++a) X[lane][a] = theta_get(p, off + mem[q], k, l, a) - mu[a];
-    wave_lds_sync();
-    const int nq = nm - q0 < kWave ? nm - q0 : kWave;
-    for (int t = lane; t < d * d; t += kWave) {
-      const int a = t / d, b = t % d;
-      if (b < a) continue;
-      double acc = A[a][b];
-      for (int r = 0; r < nq; ++r) acc += X[r][a] * X[r][b];
-      A[a][b] = acc;
+  // members, mean and covariance on the first wave; the workgroup then decomposes
+  auto moments = [&]() -> bool {
+    // members in index order
+    int nm = 0;
+    for (int c0 = 0; c0 < N; c0 += kWave) {
+      const int i = c0 + lane;
+      const bool sel = i < N && p.kappa[off + i] == k && p.lambda[off + i] == l;
+      const uint64_t b = __ballot(sel);
+      if (sel) mem[nm + __popcll(b & ((1ull << lane) - 1))] = (int16_t)i;
+      nm += __popcll(b);
     }
     wave_lds_sync();
+    for (int t = lane; t < D * D; t += kWave) F[t] = 0.0;
+    if (nm <= d) {
+      for (int a = lane; a < d; a += kWave) F[a * D + a] = 0.1 * prior_sd(pr, sh.z_max, k, l, a);
+      return false;
+    }
+    // mean: members staged 64 at a time, summed in index order by lane a
+    double acc_mu = 0.0;
+    for (int q0 = 0; q0 < nm; q0 += kWave) {
+      const int q = q0 + lane;
+      if (q < nm)
+        for (int a = 0; a < d; ++a) X[lane][a] = theta_get(p, off + mem[q], k, l, a);
+      wave_lds_sync();
+      const int nq = nm - q0 < kWave ? nm - q0 : kWave;
+      if (lane < d)
+        for (int r = 0; r < nq; ++r) acc_mu += X[r][lane];
+      wave_lds_sync();
+    }
+    if (lane < d) mu[lane] = acc_mu / (double)nm;
+    for (int t = lane; t < d * d; t += kWave) A[t / d][t % d] = 0.0;
+    wave_lds_sync();
+    // covariance: stage 64 centred members at a time
+    for (int q0 = 0; q0 < nm; q0 += kWave) {
+      const int q = q0 + lane;
+      if (q < nm)
+        for (int a = 0; a < d; ++a) X[lane][a] = theta_get(p, off + mem[q], k, l, a) - mu[a];
+      wave_lds_sync();
+      const int nq = nm - q0 < kWave ? nm - q0 : kWave;
+      for (int t = lane; t < d * d; t += kWave) {
+        const int a = t / d, b = t % d;
+        if (b < a) continue;
+        double acc = A[a][b];
+        for (int r = 0; r < nq; ++r) acc += X[r][a] * X[r][b];
+        A[a][b] = acc;
+      }
+      wave_lds_sync();
+    }
+    for (int t = lane; t < d * d; t += kWave) {
+      const int a = t / d, b = t % d;
+      if (b >= a) A[a][b] = A[a][b] / (double)(nm - 1);
+    }
+    wave_lds_sync();
+    for (int t = lane; t < d * d; t += kWave) {
+      const int a = t / d, b = t % d;
+      if (b < a) A[a][b] = A[b][a];
+      V0[a][b] = a == b ? 1.0 : 0.0;
+    }
+    wave_lds_sync();
+    return true;
+  };
+  if (wave == 0) {
+    const bool ok = moments();
+    if (lane == 0) s_ready = ok ? 1 : 0;
   }
-  for (int t = lane; t < d * d; t += kWave) {
-    const int a = t / d, b = t % d;
-    if (b >= a) A[a][b] = A[a][b] / (double)(nm - 1);
-  }
-  wave_lds_sync();
-  for (int t = lane; t < d * d; t += kWave) {
-    const int a = t / d, b = t % d;
-    if (b < a) A[a][b] = A[b][a];
-    V0[a][b] = a == b ? 1.0 : 0.0;
-  }
-  wave_lds_sync();
-  eigen_factor(A, V0, T, rc, rs, shift, order, d, D, F);
+  __syncthreads();
+  if (!s_ready) return;
+  eigen_factor<kAdaptThreads>(A, V0, T, rc, rs, order, d, D, F);
 }
 
 hipError_t launch_adapt(const SmcShape &sh, const DevParticles &p, int n_sound, const rjsmc_prior &pr,
                         double *factors, hipStream_t stream) {
-  hipLaunchKernelGGL(adapt_kernel, dim3((unsigned)(n_sound * sh.n_models)), dim3(kWave), 0, stream, sh, p, pr,
-                     factors);
+  hipLaunchKernelGGL(adapt_kernel, dim3((unsigned)(n_sound * sh.n_models)), dim3(kAdaptThreads), 0, stream, sh, p,
+                     pr, factors);
   return hipGetLastError();
 }
 
@@ -856,7 +858,7 @@ hipError_t launch_adapt(const SmcShape &sh, const DevParticles &p, int n_sound, 
 // over the sources c with N_c > 0 members and a finite log Z_c (L^0 = 1).  Four passes
 // over the sources (member list rebuilt per source): counts, the largest log nu, the
 // weight sums and weighted mean, the weighted covariance; then eigen_factor.
-__global__ __launch_bounds__(kWave) void adapt_recycled_kernel(SmcShape sh, DevParticles p, const double *ll,
+__global__ __launch_bounds__(kAdaptThreads) void adapt_recycled_kernel(SmcShape sh, DevParticles p, const double *ll,
                                                                const double *gamma, const double *log_z,
                                                                ArchiveView ar, rjsmc_prior pr, double *factors) {
   __shared__ int16_t mem[kMaxPerSounding];
@@ -864,12 +866,13 @@ __global__ __launch_bounds__(kWave) void adapt_recycled_kernel(SmcShape sh, DevP
   __shared__ double V0[kDimMax][kLd];
   __shared__ double T[2][kDimMax][kLd];
   __shared__ double mu[kDimMax];
-  __shared__ double rc[kLd], rs[kLd], shift[kLd];
+  __shared__ double rc[kLd], rs[kLd];
+  __shared__ int s_ready;
   __shared__ int order[kDimMax];
   __shared__ double wst[kWave];
   __shared__ double comp_lc[kMaxArchive + 1], comp_g[kMaxArchive + 1];
   double (*X)[kLd] = reinterpret_cast<double (*)[kLd]>(&T[0][0][0]);
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int M = sh.n_models;
   const int n_sound = (int)(gridDim.x / M);
   const int s = blockIdx.x / M, m = blockIdx.x % M;
@@ -880,60 +883,93 @@ __global__ __launch_bounds__(kWave) void adapt_recycled_kernel(SmcShape sh, DevP
   double *F = factors + (int64_t)blockIdx.x * D * D;
   const int Q = ar.n_used + 1;            // sources: archive slots 0 .. n_used - 1, then the current population
   const double g_t = gamma[s];
-  // member list of source q (particle offsets within that source's sounding s)
-  auto members = [&](int q) {
-    const DevParticles &P = q < ar.n_used ? ar.pop : p;
-    const int64_t off = (q < ar.n_used ? (int64_t)q * n_total : 0) + (int64_t)s * N;
-    int nm = 0;
-    for (int c0 = 0; c0 < N; c0 += kWave) {
-      const int i = c0 + lane;
-      const bool sel = i < N && P.kappa[off + i] == k && P.lambda[off + i] == l;
-      const uint64_t b = __ballot(sel);
-      if (sel) mem[nm + __popcll(b & ((1ull << lane) - 1))] = (int16_t)i;
-      nm += __popcll(b);
-    }
-    wave_lds_sync();
-    return nm;
-  };
-  auto src_ll = [&](int q, int i) {
-    return q < ar.n_used ? ar.ll[(int64_t)q * n_total + (int64_t)s * N + i] : ll[(int64_t)s * N + i];
-  };
-  // 1. mixture components
-  int nc = 0;
-  for (int q = 0; q < Q; ++q) {
-    const int nm = members(q);
-    const double gq = q < ar.n_used ? ar.gamma[(int64_t)q * n_sound + s] : g_t;
-    const double lz = q < ar.n_used ? ar.log_z[((int64_t)q * n_sound + s) * M + m] : log_z[(int64_t)s * M + m];
-    if (nm > 0 && lz > -HUGE_VAL && lz < HUGE_VAL) {
-      if (lane == 0) {
-        comp_lc[nc] = log((double)nm) - lz;
-        comp_g[nc] = gq;
+  // weights, mean and covariance on the first wave; the workgroup then decomposes
+  auto moments = [&]() -> bool {
+    // member list of source q (particle offsets within that source's sounding s)
+    auto members = [&](int q) {
+      const DevParticles &P = q < ar.n_used ? ar.pop : p;
+      const int64_t off = (q < ar.n_used ? (int64_t)q * n_total : 0) + (int64_t)s * N;
+      int nm = 0;
+      for (int c0 = 0; c0 < N; c0 += kWave) {
+        const int i = c0 + lane;
+        const bool sel = i < N && P.kappa[off + i] == k && P.lambda[off + i] == l;
+        const uint64_t b = __ballot(sel);
+        if (sel) mem[nm + __popcll(b & ((1ull << lane) - 1))] = (int16_t)i;
+        nm += __popcll(b);
       }
-      ++nc;
+      wave_lds_sync();
+      return nm;
+    };
+    auto src_ll = [&](int q, int i) {
+      return q < ar.n_used ? ar.ll[(int64_t)q * n_total + (int64_t)s * N + i] : ll[(int64_t)s * N + i];
+    };
+    // 1. mixture components
+    int nc = 0;
+    for (int q = 0; q < Q; ++q) {
+      const int nm = members(q);
+      const double gq = q < ar.n_used ? ar.gamma[(int64_t)q * n_sound + s] : g_t;
+      const double lz = q < ar.n_used ? ar.log_z[((int64_t)q * n_sound + s) * M + m] : log_z[(int64_t)s * M + m];
+      if (nm > 0 && lz > -HUGE_VAL && lz < HUGE_VAL) {
+        if (lane == 0) {
+          comp_lc[nc] = log((double)nm) - lz;
+          comp_g[nc] = gq;
+        }
+        ++nc;
+      }
+      wave_lds_sync();
     }
+    auto log_nu = [&](double x) {
+      const double num = g_t == 0.0 ? 0.0 : g_t * x;
+      double mx = -HUGE_VAL;
+      for (int c = 0; c < nc; ++c) mx = fmax(mx, comp_lc[c] + (comp_g[c] == 0.0 ? 0.0 : comp_g[c] * x));
+      if (!(num > -HUGE_VAL) || !(mx > -HUGE_VAL)) return -HUGE_VAL;   // L = 0: weight 0
+      double sum = 0.0;
+      for (int c = 0; c < nc; ++c) sum += exp(comp_lc[c] + (comp_g[c] == 0.0 ? 0.0 : comp_g[c] * x) - mx);
+      return num - (mx + log(sum));
+    };
+    // 2. largest log weight
+    double lmax = -HUGE_VAL;
+    for (int q = 0; q < Q; ++q) {
+      const int nm = members(q);
+      for (int r = lane; r < nm; r += kWave) lmax = fmax(lmax, log_nu(src_ll(q, mem[r])));
+      wave_lds_sync();
+    }
+    lmax = wave_max(lmax);
+    for (int t = lane; t < D * D; t += kWave) F[t] = 0.0;
+    // 3. weight sums and weighted mean: members staged 64 at a time, lane a adds in order
+    double acc_mu = 0.0, sw = 0.0, sw2 = 0.0;
+    if (lmax > -HUGE_VAL) {
+      for (int q = 0; q < Q; ++q) {
+        const int nm = members(q);
+        const DevParticles &P = q < ar.n_used ? ar.pop : p;
+        const int64_t off = (q < ar.n_used ? (int64_t)q * n_total : 0) + (int64_t)s * N;
+        for (int q0 = 0; q0 < nm; q0 += kWave) {
+          const int r = q0 + lane;
+          if (r < nm) {
+            const double w = exp(log_nu(src_ll(q, mem[r])) - lmax);
+            wst[lane] = w;
+            sw += w;
+            sw2 += w * w;
+            for (int a = 0; a < d; ++a) X[lane][a] = theta_get(P, off + mem[r], k, l, a);
+          }
+          wave_lds_sync();
+          const int nq = nm - q0 < kWave ? nm - q0 : kWave;
+          if (lane < d)
+            for (int rr = 0; rr < nq; ++rr) acc_mu += wst[rr] * X[rr][lane];
+          wave_lds_sync();
+        }
+      }
+    }
+    sw = wave_sum(sw);
+    sw2 = wave_sum(sw2);
+    if (!(lmax > -HUGE_VAL) || !(sw * sw > (double)d * sw2)) {      // effective sample size <= d
+      for (int a = lane; a < d; a += kWave) F[a * D + a] = 0.1 * prior_sd(pr, sh.z_max, k, l, a);
+      return false;
+    }
+    if (lane < d) mu[lane] = acc_mu / sw;
+    for (int t = lane; t < d * d; t += kWave) A[t / d][t % d] = 0.0;
     wave_lds_sync();
-  }
-  auto log_nu = [&](double x) {
-    const double num = g_t == 0.0 ? 0.0 : g_t * x;
-    double mx = -HUGE_VAL;
-    for (int c = 0; c < nc; ++c) mx = fmax(mx, comp_lc[c] + (comp_g[c] == 0.0 ? 0.0 : comp_g[c] * x));
-    if (!(num > -HUGE_VAL) || !(mx > -HUGE_VAL)) return -HUGE_VAL;   // L = 0: weight 0
-    double sum = 0.0;
-    for (int c = 0; c < nc; ++c) sum += exp(comp_lc[c] + (comp_g[c] == 0.0 ? 0.0 : comp_g[c] * x) - mx);
-    return num - (mx + log(sum));
-  };
-  // 2. largest log weight
-  double lmax = -HUGE_VAL;
-  for (int q = 0; q < Q; ++q) {
-    const int nm = members(q);
-    for (int r = lane; r < nm; r += kWave) lmax = fmax(lmax, log_nu(src_ll(q, mem[r])));
-    wave_lds_sync();
-  }
-  lmax = wave_max(lmax);
-  for (int t = lane; t < D * D; t += kWave) F[t] = 0.0;
-  // 3. weight sums and weighted mean: members staged 64 at a time, lane a adds in order
-  double acc_mu = 0.0, sw = 0.0, sw2 = 0.0;
-  if (lmax > -HUGE_VAL) {
+    // 4. weighted covariance sum w (theta - mu)(theta - mu)^T, then / (sw - sw2 / sw)
     for (int q = 0; q < Q; ++q) {
       const int nm = members(q);
       const DevParticles &P = q < ar.n_used ? ar.pop : p;
@@ -941,72 +977,49 @@ __global__ __launch_bounds__(kWave) void adapt_recycled_kernel(SmcShape sh, DevP
       for (int q0 = 0; q0 < nm; q0 += kWave) {
         const int r = q0 + lane;
         if (r < nm) {
-          const double w = exp(log_nu(src_ll(q, mem[r])) - lmax);
-          wst[lane] = w;
-          sw += w;
-          sw2 += w * w;
-          for (int a = 0; a < d; ++a) X[lane][a] = theta_get(P, off + mem[r], k, l, a);
+          wst[lane] = exp(log_nu(src_ll(q, mem[r])) - lmax);
+          for (int a = 0; a < d; ++a) X[lane][a] = theta_get(P, off + mem[r], k, l, a) - mu[a];
         }
         wave_lds_sync();
         const int nq = nm - q0 < kWave ? nm - q0 : kWave;
-        if (lane < d)
-          for (int rr = 0; rr < nq; ++rr) acc_mu += wst[rr] * X[rr][lane];
+        for (int t = lane; t < d * d; t += kWave) {
+          const int a = t / d, b = t % d;
+          if (b < a) continue;
+          double acc = A[a][b];
+          for (int rr = 0; rr < nq; ++rr) acc += wst[rr] * X[rr][a] * X[rr][b];
+          A[a][b] = acc;
+        }
         wave_lds_sync();
       }
     }
-  }
-  sw = wave_sum(sw);
-  sw2 = wave_sum(sw2);
-  if (!(lmax > -HUGE_VAL) || !(sw * sw > (double)d * sw2)) {      // effective sample size <= d
-    for (int a = lane; a < d; a += kWave) F[a * D + a] = 0.1 * prior_sd(pr, sh.z_max, k, l, a);
-    return;
-  }
-  if (lane < d) mu[lane] = acc_mu / sw;
-  for (int t = lane; t < d * d; t += kWave) A[t / d][t % d] = 0.0;
-  wave_lds_sync();
-  // 4. weighted covariance sum w (theta - mu)(theta - mu)^T, then / (sw - sw2 / sw)
-  for (int q = 0; q < Q; ++q) {
-    const int nm = members(q);
-    const DevParticles &P = q < ar.n_used ? ar.pop : p;
-    const int64_t off = (q < ar.n_used ? (int64_t)q * n_total : 0) + (int64_t)s * N;
-    for (int q0 = 0; q0 < nm; q0 += kWave) {
-      const int r = q0 + lane;
-      if (r < nm) {
-        wst[lane] = exp(log_nu(src_ll(q, mem[r])) - lmax);
-        for (int a = 0; a < d; ++a) X[lane][a] = theta_get(P, off + mem[r], k, l, a) - mu[a];
-      }
-      wave_lds_sync();
-      const int nq = nm - q0 < kWave ? nm - q0 : kWave;
-      for (int t = lane; t < d * d; t += kWave) {
-        const int a = t / d, b = t % d;
-        if (b < a) continue;
-        double acc = A[a][b];
-        for (int rr = 0; rr < nq; ++rr) acc += wst[rr] * X[rr][a] * X[rr][b];
-        A[a][b] = acc;
-      }
-      wave_lds_sync();
+    const double norm = sw - sw2 / sw;      // sum w (1 - sum w~^2)
+    for (int t = lane; t < d * d; t += kWave) {
+      const int a = t / d, b = t % d;
+      if (b >= a) A[a][b] = A[a][b] / norm;
     }
+    wave_lds_sync();
+    for (int t = lane; t < d * d; t += kWave) {
+      const int a = t / d, b = t % d;
+      if (b < a) A[a][b] = A[b][a];
+      V0[a][b] = a == b ? 1.0 : 0.0;
+    }
+    wave_lds_sync();
+    return true;
+  };
+  if (wave == 0) {
+    const bool ok = moments();
+    if (lane == 0) s_ready = ok ? 1 : 0;
   }
-  const double norm = sw - sw2 / sw;      // sum w (1 - sum w~^2)
-  for (int t = lane; t < d * d; t += kWave) {
-    const int a = t / d, b = t % d;
-    if (b >= a) A[a][b] = A[a][b] / norm;
-  }
-  wave_lds_sync();
-  for (int t = lane; t < d * d; t += kWave) {
-    const int a = t / d, b = t % d;
-    if (b < a) A[a][b] = A[b][a];
-    V0[a][b] = a == b ? 1.0 : 0.0;
-  }
-  wave_lds_sync();
-  eigen_factor(A, V0, T, rc, rs, shift, order, d, D, F);
+  __syncthreads();
+  if (!s_ready) return;
+  eigen_factor<kAdaptThreads>(A, V0, T, rc, rs, order, d, D, F);
 }
 
 hipError_t launch_adapt_recycled(const SmcShape &sh, const DevParticles &p, const double *ll, const double *gamma,
                                  const double *log_z, int n_sound, const ArchiveView &ar, const rjsmc_prior &pr,
                                  double *factors, hipStream_t stream) {
-  hipLaunchKernelGGL(adapt_recycled_kernel, dim3((unsigned)(n_sound * sh.n_models)), dim3(kWave), 0, stream, sh, p,
-                     ll, gamma, log_z, ar, pr, factors);
+  hipLaunchKernelGGL(adapt_recycled_kernel, dim3((unsigned)(n_sound * sh.n_models)), dim3(kAdaptThreads), 0, stream,
+                     sh, p, ll, gamma, log_z, ar, pr, factors);
   return hipGetLastError();
 }
 
@@ -1204,13 +1217,23 @@ __device__ bool zca_move(double *th, int &k, int &l, bool birth, int part, doubl
 // `prop`; mask[i] = 1 if the proposal needs a likelihood, 2 if it needs a likelihood and
 // a gradient, 0 if it is rejected outright.
 __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_args a, int move, DevParticles st,
-                                                      DevParticlesW prop, int32_t *mask, const int32_t *type,
+                                                      DevParticlesW prop, int32_t *mask, int32_t *type,
                                                       const double *gamma, DevParticles gcur, int32_t *gvalid,
-                                                      double *lq) {
+                                                      double *lq, const int32_t *active, int draw) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= st.n) return;
   const int64_t snd = st.n_per_sounding > 0 ? i / st.n_per_sounding : 0;
   const int64_t S = st.stride, So = prop.stride;
+  if (draw) {                          // the move type, as draw_types_kernel (no gradient moves)
+    const int k0 = st.kappa[i], l0 = st.lambda[i];
+    int t0 = -1;
+    if ((!active || active[snd]) && k0 >= 0 && k0 <= sh.kc && l0 >= 0 && l0 <= sh.km) {
+      double u0, ua;
+      uniforms(a.seed, (uint32_t)i, (uint32_t)step_of(a), (uint32_t)move, 0u, u0, ua);
+      t0 = draw_type(a, u0);
+    }
+    type[i] = t0;
+  }
   const int t = type[i];
   if (t < 0) {
     mask[i] = 0;
@@ -1505,12 +1528,13 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t stream)
 }
 
 hipError_t launch_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticles &state,
-                          const DevParticlesW &prop, int32_t *mask, const int32_t *type, const double *gamma,
-                          const DevParticles *grad_cur, int32_t *gvalid, double *lq, hipStream_t stream) {
+                          const DevParticlesW &prop, int32_t *mask, int32_t *type, const double *gamma,
+                          const DevParticles *grad_cur, int32_t *gvalid, double *lq, const int32_t *active,
+                          bool draw, hipStream_t stream) {
   const int64_t blocks = (state.n + 255) / 256;
   const DevParticles g = grad_cur ? *grad_cur : DevParticles();
   hipLaunchKernelGGL(propose_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, sh, a, move, state, prop, mask,
-                     type, gamma, g, gvalid, lq);
+                     type, gamma, g, gvalid, lq, active, draw ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -88,14 +88,14 @@ def test_autotune_picks_a_timed_shape(B, uneven, truth_data):
     d = _data(B, truth_data)
     ref = ctx.loglik(dp, d).cpu().numpy()
     best, times = ctx.autotune(dp, d, reps=2)
-    assert len(times) == 12 and all(t > 0 for t in times)
+    assert len(times) == B.TUNING_CANDIDATES and all(t > 0 for t in times)
     k = 2 * B.TILE_SHAPES.index((best["waves_per_block"], best["waves_per_particle"])) + best["layer_sort"]
     assert times[k] == min(times)
     assert ctx.get_tuning() == best
     assert np.array_equal(ctx.loglik(dp, d).cpu().numpy(), ref)
     small = B.Context(W.system(kmax_cond=7, kmax_charg=4), precision="f64")   # no workspace
     best2, times2 = small.autotune(dp, d, reps=1)
-    assert [t < 0 for t in times2] == [False, True] * 6 and best2["layer_sort"] == 0
+    assert [t < 0 for t in times2] == [False, True] * (B.TUNING_CANDIDATES // 2) and best2["layer_sort"] == 0
     ctx.check()
 
 
