@@ -44,6 +44,8 @@ class RJSMCRun:
         self.n = n_sound * n_per_sound
         self.prior = dict(W.PRIOR) if prior is None else prior
         self.alpha, self.n_moves, self.seed = alpha, n_moves, seed
+        self.n_moves0 = n_moves
+        self._run_base = 0          # step-counter offset of the current run (see rerun)
         self.move_prob = move_prob
         self.z_move_sd = z_move_frac * self.prior["z_max"]
         self.rw_scale = rw_scale
@@ -115,7 +117,8 @@ class RJSMCRun:
         value in step_dev when the kernels run) and flips the ping-pong buffers."""
         nxt = 1 - self.cur
         self.ctx.reweight_resample(self.bufs[self.cur], self.lls[self.cur], self.bufs[nxt], self.lls[nxt], self.gamma,
-                                   self.log_z, self.active, self.anc, self.alpha, self.seed, self.step, self.S,
+                                   self.log_z, self.active, self.anc, self.alpha, self.seed, self._run_base + self.step,
+                                   self.S,
                                    step_dev=step_dev)
         self.cur = nxt
         if self.archive is not None:
@@ -123,7 +126,7 @@ class RJSMCRun:
                                     self.factors)
         else:
             self.ctx.adapt(self.state, self.S, self.prior, self.factors)
-        common = dict(seed=self.seed, step=self.step, n_sound=self.S, prior=self.prior, z_move_sd=self.z_move_sd,
+        common = dict(seed=self.seed, step=self._run_base + self.step, n_sound=self.S, prior=self.prior, z_move_sd=self.z_move_sd,
                       rw_scale=self.rw_scale, factors=self.factors, mala_eps=self.mala_eps, step_dev=step_dev,
                       zca_birth=self.zca_birth)
         if self.tune_scale:
@@ -151,7 +154,8 @@ class RJSMCRun:
         graph; the device counter holds the step that a replay runs."""
         torch = self.torch
         if self.step_dev is None:
-            self.step_dev = torch.full((1,), self.step + 1, dtype=torch.int32, device=self.gamma.device)
+            self.step_dev = torch.full((1,), self._run_base + self.step + 1, dtype=torch.int32,
+                                       device=self.gamma.device)
             self.graphs = {}
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
@@ -192,6 +196,40 @@ class RJSMCRun:
 
     def run(self, max_steps=1000):
         self.initialise()
+        while self.step < max_steps:
+            self.advance()
+            if bool((self.gamma >= 1.0).all()):
+                break
+        self.ctx.check()
+        return self
+
+    def rerun(self, prior_seed, max_steps=1000):
+        """Algorithm 1 again on the same buffers for new soundings' worth of work: a fresh
+        prior population drawn with `prior_seed`, gamma, evidence and tallies reset, and
+        the captured step graphs replayed as they are.  The kernels' random counters carry
+        the step, and the device step counter continues from a new base, so the random
+        streams of this run are disjoint from every earlier run's (the captured seed is
+        kept).  Processing soundings one run after another this way captures the step
+        graphs once."""
+        self.gamma.zero_()
+        self.log_z.zero_()
+        self.active.fill_(1)
+        self.stats.zero_()
+        self.n_moves = self.n_moves0
+        self.moves_per_step = []
+        self._stats_prev = None
+        self._run_base += 1 << 16
+        self.step = 0
+        if self.step_dev is not None:
+            self.step_dev.fill_(self._run_base + 1)
+        if self.tune_scale:
+            self.scale.fill_(self.rw_scale)
+            self.stats_sound.zero_()
+        self.ctx.init_prior(self.state, self.prior, prior_seed)
+        self.ctx.loglik(self.state, self.y_obs, out=self.ll)
+        if self.archive is not None:
+            self.archive.n_used = 0
+            self._archive_current()
         while self.step < max_steps:
             self.advance()
             if bool((self.gamma >= 1.0).all()):

@@ -310,6 +310,32 @@ def test_graph_replay_matches_eager(B, truth_data, moves):
     graphed.ctx.check()
 
 
+def test_rerun_reuses_graphs_and_matches_eager(B, truth_data):
+    """A second run on the same buffers (new prior draw, step counters from a new base)
+    replays the step graphs captured by the first run, gives the eager rerun's states
+    and evidence bit for bit, and differs from the first run."""
+    from paper_2109_00661_amd.rjsmc import RJSMCRun
+    y = np.tile(truth_data, (2, 1))
+    runs = []
+    for graph in (False, True):
+        ctx = B.Context(W.system(), precision="f64", max_particles=512)
+        run = RJSMCRun(ctx, 2, 256, y, seed=4, n_moves=2, graph=graph).run()
+        first = run.log_z.cpu().numpy().copy()
+        n_graphs = len(run.graphs) if graph else 0
+        run.rerun(77)
+        assert bool((run.gamma >= 1.0).all())
+        if graph:
+            assert len(run.graphs) >= n_graphs > 0
+            assert int(run.step_dev.item()) == (1 << 16) + run.step + 1
+        runs.append((run, first))
+    (eager, first_e), (graphed, first_g) = runs
+    for k in ("kappa", "lambda_", "phi_b", "phi", "z_cond", "m", "z_charg", "log10_tau", "c"):
+        assert np.array_equal(eager.state[k].cpu().numpy(), graphed.state[k].cpu().numpy()), k
+    assert np.array_equal(eager.log_z.cpu().numpy(), graphed.log_z.cpu().numpy())
+    assert np.array_equal(first_e, first_g)
+    assert not np.array_equal(first_g, graphed.log_z.cpu().numpy())
+
+
 def test_posterior_summary_against_oracle(B, ctx):
     """Model counts (exact), log BFIPD and the depth profiles of three soundings."""
     from oracle import smc
