@@ -190,6 +190,22 @@ def rjsmc_rate(torch, d, n_sound, n_per_sound, seed=0, move_prob=None, graph=Fal
     return out
 
 
+def rjsmc_legs():
+    """The RJSMC measurements of the default run, by name."""
+    from paper_2109_00661_amd.rjsmc import LANGEVIN_MOVES
+    return {
+        "single_sounding_256": lambda torch, d: rjsmc_rate(torch, d, 1, 256),
+        "single_sounding_256_tuned_graph": lambda torch, d: rjsmc_rate(torch, d, 1, 256, graph=True, tune=True),
+        "batched_64x256_rw": lambda torch, d: rjsmc_rate(torch, d, 64, 256, graph=True, tune=True),
+        "batched_64x256_langevin": lambda torch, d: rjsmc_rate(torch, d, 64, 256, move_prob=LANGEVIN_MOVES,
+                                                               graph=True, tune=True),
+        "batched_64x256_adaptive_sweeps_tuned_scale": lambda torch, d: rjsmc_rate(
+            torch, d, 64, 256, graph=True, tune=True, adapt_c=0.05, r_max=40, tune_scale=True),
+        "uneven_512x1024_rw": lambda torch, d: rjsmc_rate(torch, d, 512, 1024, graph=True, kmax=(7, 4), noise=True,
+                                                          tune=True),
+    }
+
+
 def accuracy_comparison(torch, d, sizes=(256, 512, 1024), reps=32, adapt_c=0.01, r_max=40):
     """Random-walk against gradient-informed (Langevin) within-model moves on the same
     GPU: `reps` replicate runs of the synthetic sounding (batched) for each particle count,
@@ -318,6 +334,8 @@ def main():
                     help="also compare random-walk and Langevin moves at several particle counts (minutes)")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the 65,536-particle forward+loglik launches (for profiling)")
+    ap.add_argument("--rjsmc-leg", default=None,
+                    help="run only this RJSMC leg (e.g. single_sounding_256_tuned_graph) and print it (profiling)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before timing, as the "
                          "reference for hardware byte counters")
@@ -330,6 +348,13 @@ def main():
     import torch
     from paper_2109_00661_amd import binding as B
 
+    if args.rjsmc_leg:
+        legs = rjsmc_legs()
+        if args.rjsmc_leg not in legs:
+            print("unknown leg; choose from " + ", ".join(legs), file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps({args.rjsmc_leg: legs[args.rjsmc_leg](torch, synth_data(torch))}), flush=True)
+        return
     system = W.system(kmax_cond=N_LAYERS - 1, kmax_charg=0)
     ctx = B.Context(system, precision="f64")
     d = synth_data(torch)
@@ -372,16 +397,7 @@ def main():
         out["fp32"] = {"evals_per_s": N_PARTICLES / (ms32 * 1e-3), "ms_per_step": ms32}
     if args.extra:
         out["adjoint"] = adjoint_rate(torch, d, max(3, args.steps // 4), 1)
-    from paper_2109_00661_amd.rjsmc import LANGEVIN_MOVES
-    out["rjsmc"] = {"single_sounding_256": rjsmc_rate(torch, d, 1, 256),
-                    "single_sounding_256_tuned_graph": rjsmc_rate(torch, d, 1, 256, graph=True, tune=True),
-                    "batched_64x256_rw": rjsmc_rate(torch, d, 64, 256, graph=True, tune=True),
-                    "batched_64x256_langevin": rjsmc_rate(torch, d, 64, 256, move_prob=LANGEVIN_MOVES, graph=True,
-                                                          tune=True),
-                    "batched_64x256_adaptive_sweeps_tuned_scale": rjsmc_rate(
-                        torch, d, 64, 256, graph=True, tune=True, adapt_c=0.05, r_max=40, tune_scale=True),
-                    "uneven_512x1024_rw": rjsmc_rate(torch, d, 512, 1024, graph=True, kmax=(7, 4), noise=True,
-                                                     tune=True)}
+    out["rjsmc"] = {name: leg(torch, d) for name, leg in rjsmc_legs().items()}
     if args.survey:
         out["survey"] = survey(torch)
     if args.compare:
