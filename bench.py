@@ -334,6 +334,8 @@ def main():
                     help="also compare random-walk and Langevin moves at several particle counts (minutes)")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the 65,536-particle forward+loglik launches (for profiling)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="time only the 65,536-particle log-likelihood gradient launches (for profiling)")
     ap.add_argument("--rjsmc-leg", default=None,
                     help="run only this RJSMC leg (e.g. single_sounding_256_tuned_graph) and print it (profiling)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -348,6 +350,9 @@ def main():
     import torch
     from paper_2109_00661_amd import binding as B
 
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_rate(torch, synth_data(torch), args.steps, args.warmup)}), flush=True)
+        return
     if args.rjsmc_leg:
         legs = rjsmc_legs()
         if args.rjsmc_leg not in legs:
