@@ -1,8 +1,9 @@
 // SMC primitives of adaptive RJSMC (Algorithm 1) for gfx950: prior initialisation,
 // re-weighting with the tempering bisection and evidence update, within-model
-// systematic resampling, gather, per-model proposal adaptation, and the
-// propose / accept halves of the RJ-MCMC mutation (the likelihood of each proposal is
-// evaluated by the forward kernel in between).
+// systematic resampling with the resampled copy, per-model proposal adaptation (also
+// from recycled particles, Section 3.2.5), and the propose / accept halves of the
+// RJ-MCMC mutation, including the adaptive birth of Appendix E.2 (the likelihood of
+// each proposal is evaluated by the forward kernel in between).
 //
 // Weights, temperatures and evidence are FP64.  Resampling thresholds are exact
 // integer arithmetic on weights quantised to 2^-60, so ancestor choices do not depend
