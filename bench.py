@@ -81,6 +81,19 @@ def synth_data(torch):
     return torch.as_tensor(y + s * W.data_noise(1), device="cuda")
 
 
+def copy_calibration(torch, mib):
+    """One plain device-to-device copy of `mib` MiB, whose FETCH_SIZE / WRITE_SIZE
+    readings scale the counters of the kernels profiled in the same run."""
+    if mib <= 0:
+        return
+    src = torch.ones((mib << 20) // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def time_calls(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -291,6 +304,45 @@ def survey(torch):
     return out
 
 
+def reweight_rate(torch, d, steps, warmup, n_sound=2000, n_per_sound=2048):
+    """Re-weight + within-model resampling (with the resampled copy) of survey-sized
+    populations: n_sound soundings of n_per_sound prior particles with their
+    log-likelihoods, each call from gamma = 0 (the two small fills that reset gamma and
+    log Z are inside the timed region).  Algorithmic HBM bytes per particle: the counts,
+    ll and every parameter row read once, the resampled rows, counts, ll and ancestor
+    written once."""
+    from paper_2109_00661_amd import binding as B
+    system = W.system()
+    n = n_sound * n_per_sound
+    ctx = B.Context(system, precision="f64", max_particles=n)
+    kc, km = ctx.kmax_cond, ctx.kmax_charg
+    M = (kc + 1) * (km + 1)
+    p = B.empty_device_population(n, kc, km, n_per_sound)
+    ctx.init_prior(p, W.PRIOR, 11)
+    y = d.reshape(1, -1).repeat(n_sound, 1).contiguous()
+    ll = ctx.loglik(p, y)
+    out = B.empty_device_population(n, kc, km, n_per_sound)
+    ll_out = torch.empty_like(ll)
+    gamma = torch.zeros(n_sound, dtype=torch.float64, device="cuda")
+    log_z = torch.zeros((n_sound, M), dtype=torch.float64, device="cuda")
+    anc = torch.empty(n, dtype=torch.int32, device="cuda")
+
+    def call():
+        gamma.zero_()
+        log_z.zero_()
+        ctx.reweight_resample(p, ll, out, ll_out, gamma, log_z, None, anc, 0.5, 3, 1, n_sound)
+
+    ms, _ = time_calls(call, steps, warmup, torch)
+    ctx.check()
+    rows = 3 + 2 * kc + 2 * km                     # phi_b, log10 tau, c, phi, z, m, zm
+    per_particle = (8 + 8 + 8 * rows) + (8 * rows + 8 + 8 + 4)
+    return {"soundings": n_sound, "particles_per_sounding": n_per_sound, "ms_per_call": ms,
+            "algorithmic_bytes_per_particle": per_particle,
+            "hbm_gb_per_s": per_particle * n / (ms * 1e-3) / 1e9,
+            "hbm_frac_of_8tb_s": per_particle * n / (ms * 1e-3) / 8e12,
+            "gamma_mean": float(gamma.mean().item())}
+
+
 def adjoint_rate(torch, d, steps, warmup):
     """Log-likelihood + gradient evaluations per second for 65,536 decoupled particles
     with 1-8 segments per partition (merged layers up to 15)."""
@@ -334,6 +386,8 @@ def main():
                     help="also compare random-walk and Langevin moves at several particle counts (minutes)")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the 65,536-particle forward+loglik launches (for profiling)")
+    ap.add_argument("--reweight-only", action="store_true",
+                    help="time only re-weight/re-sample on 2,000 x 2,048 particles (for profiling)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="time only the 65,536-particle log-likelihood gradient launches (for profiling)")
     ap.add_argument("--rjsmc-leg", default=None,
@@ -350,6 +404,11 @@ def main():
     import torch
     from paper_2109_00661_amd import binding as B
 
+    if args.reweight_only:
+        copy_calibration(torch, args.copy_calibration_mib)
+        print(json.dumps({"reweight_resample": reweight_rate(torch, synth_data(torch), args.steps, args.warmup)}),
+              flush=True)
+        return
     if args.adjoint_only:
         print(json.dumps({"adjoint": adjoint_rate(torch, synth_data(torch), args.steps, args.warmup)}), flush=True)
         return
@@ -366,14 +425,7 @@ def main():
     p = B.particles_to_device(W.merged_population(N_PARTICLES, N_LAYERS, seed=2, kc=N_LAYERS - 1))
     ll = torch.empty(N_PARTICLES, dtype=torch.float64, device="cuda")
 
-    if args.copy_calibration_mib > 0:
-        nbytes = args.copy_calibration_mib << 20
-        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    copy_calibration(torch, args.copy_calibration_mib)
     ms, wall = time_calls(lambda: ctx.loglik(p, d, out=ll), args.steps, args.warmup, torch)
     ctx.check()
     evals = N_PARTICLES / (ms * 1e-3)
@@ -402,6 +454,7 @@ def main():
         out["fp32"] = {"evals_per_s": N_PARTICLES / (ms32 * 1e-3), "ms_per_step": ms32}
     if args.extra:
         out["adjoint"] = adjoint_rate(torch, d, max(3, args.steps // 4), 1)
+        out["reweight_resample_2000x2048"] = reweight_rate(torch, d, max(3, args.steps // 4), 1)
     out["rjsmc"] = {name: leg(torch, d) for name, leg in rjsmc_legs().items()}
     if args.survey:
         out["survey"] = survey(torch)

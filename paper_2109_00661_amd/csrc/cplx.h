@@ -157,6 +157,24 @@ __device__ __forceinline__ cplx<double> cexp_tab(cplx<double> z, const cplx<doub
   return {e * fma(t.re, cd, -(t.im * sd)), e * fma(t.im, cd, t.re * sd)};
 }
 
+// e^x for x <= 0 with the same reduction, polynomial and table e2 as cexp_tab (its
+// modulus part); x < -1000, and a NaN, give 0.
+__device__ __forceinline__ double exp_tab(double x, const double *e2) {
+  using namespace detail;
+  constexpr double kRound = 0x1.8p52;
+  x = fmax(x, -1000.0);
+  const double kr = fma(x, 256.0 * kInvLn2, kRound);
+  const int ki = __double2loint(kr);
+  const double kx = kr - kRound;
+  double r = fma(kx, -(kLn2Hi / 256.0), x);
+  r = fma(kx, -(kLn2Lo / 256.0), r);
+  double p = fma(r, kInvFact[4], kInvFact[3]);
+  p = fma(p, r, kInvFact[2]);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p * e2[ki & 255], ki >> 8);
+}
+
 // exp(z) for the propagation factors in FP32, Re z <= 0 (Re z < -110 gives 0):
 //   exp(x) = 2^k exp(r),  k = rint(x / ln 2),  r = x - k ln 2,  |r| <= ln(2)/2,
 //   (cos y, sin y) = i^q (cos t, sin t),  q = rint(y 2/pi),  t = y - q pi/2,  |t| <= pi/4,

@@ -555,7 +555,7 @@ extern "C" rjsmc_status rjsmc_reweight_resample(rjsmc_ctx *c, const rjsmc_reweig
   hipError_t e = hipSetDevice(c->device);
   if (e == hipSuccess)
     e = rjsmc::launch_reweight_resample(sh, *a, di, ll_in, writable(dout), ll_out, gamma, log_z, active, anc,
-                                        c->dev.flags, (hipStream_t)stream);
+                                        c->dev.flags, c->dev.exp2t, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "rjsmc_reweight_resample: launch");
   return RJSMC_OK;
 }

@@ -117,7 +117,8 @@ hipError_t launch_init_prior(const DevParticlesW &p, const SmcShape &sh, const r
                              hipStream_t stream);
 hipError_t launch_reweight_resample(const SmcShape &sh, const rjsmc_reweight_args &a, const DevParticles &in,
                                     const double *ll_in, const DevParticlesW &out, double *ll_out, double *gamma,
-                                    double *log_z, int32_t *active, int32_t *anc, int *flags, hipStream_t stream);
+                                    double *log_z, int32_t *active, int32_t *anc, int *flags, const double *exp2t,
+                                    hipStream_t stream);
 hipError_t launch_adapt(const SmcShape &sh, const DevParticles &p, int n_sound, const rjsmc_prior &pr,
                         double *factors, hipStream_t stream);
 

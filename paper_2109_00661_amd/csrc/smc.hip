@@ -11,6 +11,9 @@
 // (its particles, log-likelihoods, model ids and cumulative weights live in LDS).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
+#include "cplx.h"
 #include "rjsmc_internal.h"
 
 namespace rjsmc {
@@ -171,97 +174,189 @@ __device__ __forceinline__ double wave_max(double v) {
 // The temperature search evaluates the TESS at the 2^LV - 1 midpoints that LV successive
 // halvings of the bracket can visit, then takes the same LV decisions: 60 / LV rounds give
 // the 60 halvings of a plain bisection, with its evaluation points and decisions, in a
-// fraction of its sequential rounds.  LV = 3 up to 512 particles per sounding, 2 up to
-// 1194 and 1 above (the exponentials of a round are staged in LDS: (2^LV - 1) N values).
+// fraction of its sequential rounds.
+//
+// Each live model's members (sorted order) are cut into runs of R consecutive members
+// (the model's last run may be shorter), one run per lane, runs in model order across the
+// workgroup; R is the least length whose runs fit the 512 lanes (at most 5 for 2,048
+// members and 128 models).  A lane keeps its run's x values in registers for the whole
+// search; a round is then: the lane's exponentials and their sums, a segmented scan over
+// the lanes of each wave (a model's lanes are contiguous), the carries of models that
+// span waves, and the sum over models of the per-model ESS.  All sums are taken in a
+// fixed order, so every thread obtains the same TESS and takes the same decisions.
 constexpr int kBisectK = 7;
-constexpr int kStageMax = kBisectK * 512;
-// Work items of the sums: up to 64 consecutive members of one model (sorted order).
-constexpr int kMaxItems = kMaxPerSounding / kWave + kMaxModels;
-// (item, candidate) sums: at most (512/64 + 128) x 7, (1194/64 + 128) x 3 or 160 x 1
-constexpr int kPartMax = 1024;
-static_assert((512 / kWave + kMaxModels) * 7 <= kPartMax && (kStageMax / 3 / kWave + 1 + kMaxModels) * 3 <= kPartMax &&
-                  kMaxItems <= kPartMax, "item sums fit");
+constexpr int kRunMax = 5;
+static_assert(kMaxPerSounding + kMaxModels * (kRunMax - 1) <= kRwThreads * kRunMax, "runs of 5 always fit");
 
+template <int KC>
 struct RwShared {
   union {
     double ll[kMaxPerSounding];                       // particle order, until x is formed
-    double w[kStageMax];                              // exponentials of a search round
     uint64_t cum[kMaxPerSounding];                    // cumulative weights, after the search
   } u;
   double x[kMaxPerSounding];        // sorted order: ll - max of the model (-inf: dead model)
-  double part_a[kPartMax], part_b[kPartMax];     // per (item, candidate) sums
+  union {
+    int wc[kRwWaves][kMaxModels];   // per-wave model counts, then running placement offsets
+    int16_t anc_l[kMaxPerSounding]; // ancestor of each particle (index within the sounding)
+  } v;
   int16_t idx[kMaxPerSounding];     // particles sorted by (model, index)
   uint8_t mod[kMaxPerSounding];
-  int cnt[kMaxModels], base[kMaxModels], off[kMaxModels];
-  double mx[kMaxModels], s1[kMaxModels], s2[kMaxModels];
+  int cnt[kMaxModels], base[kMaxModels], rb[kMaxModels + 1];
+  double mx[kMaxModels], s1[kMaxModels];
   uint64_t U[kMaxModels];
-  int16_t item_m[kMaxItems], item_q0[kMaxItems];
-  int item_base[kMaxModels + 1];
-  int n_items;
-  int16_t anc_l[kMaxPerSounding];   // ancestor of each particle (index within the sounding)
-  double tessk[kBisectK];
+  double tail_a[kRwWaves][KC], tail_b[kRwWaves][KC];   // wave-end partial sums (KC candidates)
+  double ess[kMaxModels][KC];                          // per-model ESS (0: no runs)
+  double e2[kExp2N];                // 2^(j/256), the table of exp_tab
+  int run_len;
 };
 
-// TESS at K increments at once (all threads call): sm.tessk[c] = TESS(dg[c]) and
-// sm.s1/s2[m] = sum over model m of w and w^2, w = exp(dg[0] (ll - max_m)).
-//   1. every thread forms exponentials of (candidate, position) pairs;
-//   2. one thread per (item, candidate) adds the item's members in order;
-//   3. one lane per (model, candidate) adds the model's items in order and forms its ESS;
-//      lane c then adds the models in order.
-template <int K>
-__device__ __forceinline__ void eval_tess(RwShared &sm, const double (&dg)[K], int M, int N) {
-  double *W = sm.u.w;
-  for (int t = threadIdx.x; t < K * N; t += kRwThreads) {
-    const int c = K == 1 ? 0 : t / N;
-    // dg[c] as a sum of exact zeros and one term (a select chain would become an
-    // indexed private array)
-    double d = 0.0;
+// A lane's run: model m (-1: no run), nv members with values x, seg the steps of the
+// segmented wave scan (dpp_scan_step) whose source lane holds a run of the same model,
+// fin on the model's last lane, w0 the wave of the model's first lane.
+struct RunLane {
+  int m, nv, seg, w0;
+  bool fin;
+  double x[kRunMax];
+};
+
+template <typename SM>
+__device__ __forceinline__ RunLane run_of_lane(const SM &sm, int M) {
+  RunLane r;
+  const int t = threadIdx.x, lane = t & (kWave - 1);
+  r.m = -1;
+  r.nv = 0;
+  r.seg = 0;
+  r.w0 = 0;
+  r.fin = false;
 #pragma unroll
-    for (int j = 0; j < K; ++j) d += (c == j ? 1.0 : 0.0) * dg[j];
-    W[t] = exp(d * sm.x[t - c * N]);
+  for (int j = 0; j < kRunMax; ++j) r.x[j] = 0.0;
+  if (t >= sm.rb[M]) return r;
+  int lo = 0, hi = M;                 // rb[lo] <= t < rb[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (sm.rb[mid] <= t)
+      lo = mid;
+    else
+      hi = mid;
   }
-  __syncthreads();
-  const int ni = sm.n_items;
-  for (int t = threadIdx.x; t < ni * K; t += kRwThreads) {
-    const int it = K == 1 ? t : t / K, c = t - it * K;
-    const int m = sm.item_m[it];
-    const int p0 = sm.base[m] + sm.item_q0[it];
-    const int rem = sm.cnt[m] - sm.item_q0[it];
-    const int p1 = p0 + (rem < kWave ? rem : kWave);
-    const double *w = W + c * N;
-    double a = 0.0, b = 0.0;
-    for (int pos = p0; pos < p1; ++pos) {
-      const double v = w[pos];
-      a += v;
-      b += v * v;
-    }
-    sm.part_a[t] = a;                 // t = it K + c
-    sm.part_b[t] = b;
-  }
-  __syncthreads();
-  if (threadIdx.x < kWave) {
-    for (int t = threadIdx.x; t < M * K; t += kWave) {
-      const int m = K == 1 ? t : t / K, c = t - m * K;
-      const int i0 = sm.item_base[m], i1 = sm.item_base[m + 1];
-      double A = 0.0, B = 0.0;
-      for (int it = i0; it < i1; ++it) {
-        A += sm.part_a[it * K + c];
-        B += sm.part_b[it * K + c];
+  const int R = sm.run_len;
+  const int m = lo, m0 = sm.rb[m], m1 = sm.rb[m + 1];
+  const int q0 = (t - m0) * R, rem = sm.cnt[m] - q0;
+  r.m = m;
+  r.nv = rem < R ? rem : R;
+  r.fin = t == m1 - 1;
+  r.w0 = m0 / kWave;
+  const int row = lane >> 4, rl = lane & 15, wb = t - lane;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (rl >= (1 << k) && t - (1 << k) >= m0) r.seg |= 1 << k;
+  if ((row == 1 || row == 3) && wb + 16 * row - 1 >= m0) r.seg |= 1 << 4;
+  if (row >= 2 && wb + 31 >= m0) r.seg |= 1 << 5;
+  const double *xs = sm.x + sm.base[m] + q0;
+#pragma unroll
+  for (int j = 0; j < kRunMax; ++j)
+    if (j < r.nv) r.x[j] = xs[j];
+  return r;
+}
+
+// v of another lane by a DPP move (0 where the pattern has no source): CTRL 0x111 + j is
+// lane - 2^j of the same 16-lane row, 0x142 the last lane of the previous row, 0x143
+// lane 31.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Inclusive scan of a and b over the lanes of a wave, restarted where the model changes:
+// row-local steps from lanes -1, -2, -4, -8, then the previous row's last lane (rows 1
+// and 3) and lane 31 (rows 2 and 3); seg bit j says whether step j's source lane holds
+// the same model.  A fixed order of additions, so the sums are reproducible.
+template <int K>
+__device__ __forceinline__ void seg_scan(double (&a)[K], double (&b)[K], int seg) {
+  auto step = [&](auto ctrl, int bit) {
+    constexpr int C = decltype(ctrl)::value;
+    const bool take = (seg >> bit) & 1;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      const double ta = dpp_f64<C>(a[c]), tb = dpp_f64<C>(b[c]);
+      if (take) {
+        a[c] += ta;
+        b[c] += tb;
       }
-      W[c * M + m] = i1 > i0 ? A * A / B : 0.0;   // per-model ESS (the exponentials are spent)
-      if (c == 0) {
-        sm.s1[m] = A;
-        sm.s2[m] = B;
+    }
+  };
+  step(std::integral_constant<int, 0x111>{}, 0);
+  step(std::integral_constant<int, 0x112>{}, 1);
+  step(std::integral_constant<int, 0x114>{}, 2);
+  step(std::integral_constant<int, 0x118>{}, 3);
+  step(std::integral_constant<int, 0x142>{}, 4);
+  step(std::integral_constant<int, 0x143>{}, 5);
+}
+
+// TESS at K increments at once (all threads call, all return the same values); with
+// keep, sm.s1[m] = sum over model m of w at dg[0].  RM bounds the run length.
+template <int K, int RM, typename SM>
+__device__ __forceinline__ void eval_tess(SM &sm, const RunLane &r, const double (&dg)[K], double (&tess)[K],
+                                          int M, bool keep) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  double a[K], b[K];
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    a[c] = 0.0;
+    b[c] = 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < RM; ++j)
+    if (j < r.nv) {
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        const double w = exp_tab(dg[c] * r.x[j], sm.e2);
+        a[c] += w;
+        b[c] = fma(w, w, b[c]);
       }
     }
-    wave_lds_sync();
-    if (threadIdx.x < K) {
-      double t = 0.0;
-      for (int m = 0; m < M; ++m) t += W[threadIdx.x * M + m];
-      sm.tessk[threadIdx.x] = t;
+  seg_scan<K>(a, b, r.seg);
+  if (lane == kWave - 1)
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      sm.tail_a[wave][c] = a[c];
+      sm.tail_b[wave][c] = b[c];
+    }
+  __syncthreads();
+  if (r.fin) {
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      double A = 0.0, B = 0.0;       // earlier waves' parts of the model, in wave order
+      for (int w2 = r.w0; w2 < wave; ++w2) {
+        A += sm.tail_a[w2][c];
+        B += sm.tail_b[w2][c];
+      }
+      A += a[c];
+      B += b[c];
+      sm.ess[r.m][c] = A * A / B;
+      if (keep && c == 0) {
+        sm.s1[r.m] = A;
+      }
     }
   }
   __syncthreads();
+#pragma unroll
+  for (int c = 0; c < K; ++c) tess[c] = 0.0;
+  // models in order, a few loads in flight (absent models add +0)
+  constexpr int G = K == 1 ? 8 : K == 3 ? 4 : 2;
+  for (int m0 = 0; m0 < M; m0 += G) {
+    double v[G][K];
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+#pragma unroll
+      for (int c = 0; c < K; ++c) v[j][c] = m0 + j < M ? sm.ess[m0 + j][c] : 0.0;
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+#pragma unroll
+      for (int c = 0; c < K; ++c) tess[c] += v[j][c];
+  }
 }
 
 // The 2^LV - 1 points that LV halvings of (lo, hi) can visit, in order, each formed from
@@ -286,22 +381,27 @@ __device__ __forceinline__ void nested_midpoints(double (&c)[K], double lo, doub
   }
 }
 
-// 60 halvings of (0, hi) keeping the lower end where TESS >= target.
-template <int LV>
-__device__ __forceinline__ double bisect_increment(RwShared &sm, double hi, double target, int M, int N) {
+// 60 halvings of (0, hi) keeping the lower end where TESS >= target (runs of at most
+// RM members).
+template <int LV, int RM, typename SM>
+__device__ __forceinline__ double bisect_increment(SM &sm, const RunLane &r, double hi, double target,
+                                                  int M) {
   constexpr int K = (1 << LV) - 1;
   double lo = 0.0;
   for (int round = 0; round < 60 / LV; ++round) {
-    double c[K];
+    double c[K], tess[K];
     nested_midpoints<K>(c, lo, hi);
-    eval_tess<K>(sm, c, M, N);
+    eval_tess<K, RM>(sm, r, c, tess, M, false);
     int node = K / 2, step = (K + 1) / 4;
 #pragma unroll
     for (int level = 0; level < LV; ++level) {
-      double cn = 0.0;                      // c[node], kept out of an indexed private array
+      double cn = 0.0, tn = 0.0;            // c[node], tess[node] (no indexed private array)
 #pragma unroll
-      for (int j = 0; j < K; ++j) cn += (node == j ? 1.0 : 0.0) * c[j];
-      if (sm.tessk[node] >= target) {
+      for (int j = 0; j < K; ++j) {
+        cn += (node == j ? 1.0 : 0.0) * c[j];
+        tn += (node == j ? 1.0 : 0.0) * tess[j];
+      }
+      if (tn >= target) {
         lo = cn;
         node += step;
       } else {
@@ -331,33 +431,125 @@ __device__ __forceinline__ uint64_t sys_threshold(uint64_t j, uint64_t U, uint64
   return (q1 << 32) | q2;
 }
 
-// out[i] = in[src] for every row of the population and ll_out[i] = ll_in[src].
-__device__ __forceinline__ void copy_particle(const DevParticles &in, const double *ll_in, const DevParticlesW &out,
-                                              double *ll_out, int64_t i, int64_t src, int rows_c, int rows_m,
-                                              int rows_zm) {
-  const int64_t Si = in.stride, So = out.stride;
-  out.kappa[i] = in.kappa[src];
-  if (out.lambda) out.lambda[i] = in.lambda ? in.lambda[src] : 0;
-  out.phi_b[i] = in.phi_b[src];
-  out.log10_tau[i] = in.log10_tau[src];
-  out.c[i] = in.c[src];
-  ll_out[i] = ll_in[src];
-  for (int r = 0; r < rows_c; ++r) {
-    out.phi[r * So + i] = in.phi[r * Si + src];
-    out.z_cond[r * So + i] = in.z_cond[r * Si + src];
+// Lanes of the wave that hold the same model m (valid lanes only): nbits ballots.
+__device__ __forceinline__ uint64_t same_model_lanes(int m, bool valid, int nbits) {
+  uint64_t same = __ballot(valid);
+  for (int b = 0; b < nbits; ++b) {
+    const bool bit = (m >> b) & 1;
+    const uint64_t ones = __ballot(valid && bit);
+    same &= bit ? ones : ~ones;
   }
-  for (int r = 0; r < rows_m; ++r) out.m[r * So + i] = in.m[r * Si + src];
-  for (int r = 0; r < rows_zm; ++r) out.z_charg[r * So + i] = in.z_charg[r * Si + src];
+  return same;
+}
+
+__device__ __forceinline__ int wave_scan_incl(int v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// out[i] = in[anc_l[i]] for the members i = tid + k * kRwThreads of the sounding, every row
+// of the population, ll, and the global ancestor index.  The loads of a row group are
+// issued before its stores.
+constexpr int kCopyPer = kMaxPerSounding / kRwThreads;
+template <typename SM>
+__device__ __forceinline__ void copy_resampled(const SM &sm, const DevParticles &in,
+                                               const double *__restrict__ ll_in, const DevParticlesW &out,
+                                               double *__restrict__ ll_out, int32_t *__restrict__ anc, int64_t off,
+                                               int N, int rows_c, int rows_m, int rows_zm) {
+  const int tid = threadIdx.x;
+  const int64_t Si = in.stride, So = out.stride;
+  int64_t src[kCopyPer], dst[kCopyPer];
+  bool ok[kCopyPer];
+#pragma unroll
+  for (int k = 0; k < kCopyPer; ++k) {
+    const int i = tid + k * kRwThreads;
+    ok[k] = i < N;
+    dst[k] = off + i;
+    src[k] = off + (ok[k] ? sm.v.anc_l[i] : i);
+  }
+  {
+    int32_t ka[kCopyPer], la[kCopyPer];
+    double pb[kCopyPer], lt[kCopyPer], cc[kCopyPer], lv[kCopyPer];
+#pragma unroll
+    for (int k = 0; k < kCopyPer; ++k)
+      if (ok[k]) {
+        ka[k] = in.kappa[src[k]];
+        la[k] = in.lambda ? in.lambda[src[k]] : 0;
+        pb[k] = in.phi_b[src[k]];
+        lt[k] = in.log10_tau[src[k]];
+        cc[k] = in.c[src[k]];
+        lv[k] = ll_in[src[k]];
+      }
+#pragma unroll
+    for (int k = 0; k < kCopyPer; ++k)
+      if (ok[k]) {
+        anc[dst[k]] = (int32_t)src[k];
+        out.kappa[dst[k]] = ka[k];
+        if (out.lambda) out.lambda[dst[k]] = la[k];
+        out.phi_b[dst[k]] = pb[k];
+        out.log10_tau[dst[k]] = lt[k];
+        out.c[dst[k]] = cc[k];
+        ll_out[dst[k]] = lv[k];
+      }
+  }
+  // the layer rows (phi, z_cond, m, z_charg) as one list of row slots, four at a time
+  const int n_slots = 2 * rows_c + rows_m + rows_zm;
+  auto row_in = [&](int q) -> const double * {
+    if (q < rows_c) return in.phi + q * Si;
+    q -= rows_c;
+    if (q < rows_c) return in.z_cond + q * Si;
+    q -= rows_c;
+    if (q < rows_m) return in.m + q * Si;
+    return in.z_charg + (q - rows_m) * Si;
+  };
+  auto row_out = [&](int q) -> double * {
+    if (q < rows_c) return out.phi + q * So;
+    q -= rows_c;
+    if (q < rows_c) return out.z_cond + q * So;
+    q -= rows_c;
+    if (q < rows_m) return out.m + q * So;
+    return out.z_charg + (q - rows_m) * So;
+  };
+  constexpr int kSlots = 4;
+  for (int q0 = 0; q0 < n_slots; q0 += kSlots) {
+    double v[kSlots][kCopyPer];
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j)
+      if (q0 + j < n_slots) {
+        const double *__restrict__ ri = row_in(q0 + j);
+#pragma unroll
+        for (int k = 0; k < kCopyPer; ++k)
+          if (ok[k]) v[j][k] = ri[src[k]];
+      }
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j)
+      if (q0 + j < n_slots) {
+        double *__restrict__ ro = row_out(q0 + j);
+#pragma unroll
+        for (int k = 0; k < kCopyPer; ++k)
+          if (ok[k]) ro[dst[k]] = v[j][k];
+      }
+  }
 }
 
 // One workgroup per sounding: re-weight, evidence, within-model resampling, and the
-// resampled population written to out (each particle copied from its ancestor).
+// resampled population written to out (each particle copied from its ancestor).  SMALL:
+// at most 512 particles per sounding, so runs are single members and a search round takes
+// three halvings; otherwise one or two (the seven-point rounds need registers that would
+// halve the occupancy of the large-population launch).
+template <bool SMALL>
 __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape sh, rjsmc_reweight_args a,
                                                                        DevParticles in, const double *ll_in,
                                                                        DevParticlesW out, double *ll_out,
                                                                        double *gamma, double *log_z,
-                                                                       int32_t *active, int32_t *anc, int *flags) {
-  __shared__ RwShared sm;
+                                                                       int32_t *active, int32_t *anc, int *flags,
+                                                                       const double *exp2t) {
+  __shared__ RwShared<SMALL ? kBisectK : 3> sm;
   const bool dec = in.layout == RJSMC_LAYOUT_DECOUPLED;
   const int rows_c = sh.kc, rows_m = dec ? sh.km : sh.kc + 1, rows_zm = dec ? sh.km : 0;
   const int s = blockIdx.x;
@@ -367,63 +559,84 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
   const double g0 = gamma[s];
   if (!(g0 < 1.0)) {
-    for (int i = tid; i < N; i += kRwThreads) {
-      anc[off + i] = (int32_t)(off + i);
-      copy_particle(in, ll_in, out, ll_out, off + i, off + i, rows_c, rows_m, rows_zm);
-    }
+    for (int i = tid; i < N; i += kRwThreads) sm.v.anc_l[i] = (int16_t)i;
+    __syncthreads();
+    copy_resampled(sm, in, ll_in, out, ll_out, anc, off, N, rows_c, rows_m, rows_zm);
     if (tid == 0 && active) active[s] = 0;
     return;
   }
+  // counts, models and log-likelihoods (loads first, then the LDS writes)
+  {
+    int kap[kCopyPer], lam[kCopyPer];
+    double llv[kCopyPer];
+#pragma unroll
+    for (int k = 0; k < kCopyPer; ++k) {
+      const int i = tid + k * kRwThreads;
+      if (i < N) {
+        kap[k] = in.kappa[off + i];
+        lam[k] = in.lambda[off + i];
+        llv[k] = ll_in[off + i];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kCopyPer; ++k) {
+      const int i = tid + k * kRwThreads;
+      if (i < N) {
+        const bool okc = kap[k] >= 0 && kap[k] <= sh.kc && lam[k] >= 0 && lam[k] <= sh.km;
+        // a particle with counts outside the capacities is flagged and given -inf weight
+        sm.u.ll[i] = okc ? llv[k] : -HUGE_VAL;
+        if (!okc) atomicOr(flags, kFlagCapacity);
+        sm.mod[i] = (uint8_t)(okc ? kap[k] * (sh.km + 1) + lam[k] : 0);
+      }
+    }
+  }
+  for (int t = tid; t < kRwWaves * kMaxModels; t += kRwThreads) (&sm.v.wc[0][0])[t] = 0;
+  for (int t = tid; t < kExp2N; t += kRwThreads) sm.e2[t] = exp2t[t];
+  for (int t = tid; t < (int)(sizeof(sm.ess) / sizeof(double)); t += kRwThreads) (&sm.ess[0][0])[t] = 0.0;
+  __syncthreads();
+  // stable counting sort by model: wave w takes a contiguous range of 64-particle chunks,
+  // counts its members per model, then places them in order behind the earlier waves'
+  const int nbits = M > 1 ? 32 - __clz(M - 1) : 0;
+  const int n_chunks = (N + kWave - 1) / kWave, cpw = (n_chunks + kRwWaves - 1) / kRwWaves;
+  const int ch0 = wave * cpw, ch1 = min(n_chunks, ch0 + cpw);
+  const uint64_t below = (1ull << lane) - 1;
+  for (int ch = ch0; ch < ch1; ++ch) {
+    const int i = ch * kWave + lane;
+    const bool v = i < N;
+    const int m = v ? sm.mod[i] : 0;
+    const uint64_t same = same_model_lanes(m, v, nbits);
+    if (v && (same & below) == 0) sm.v.wc[wave][m] += __popcll(same);
+  }
+  __syncthreads();
   for (int m = tid; m < M; m += kRwThreads) {
-    sm.cnt[m] = 0;
+    int acc = 0;
+#pragma unroll
+    for (int w = 0; w < kRwWaves; ++w) {
+      const int c = sm.v.wc[w][m];
+      sm.v.wc[w][m] = acc;
+      acc += c;
+    }
+    sm.cnt[m] = acc;
     sm.mx[m] = -HUGE_VAL;
   }
   __syncthreads();
-  for (int i = tid; i < N; i += kRwThreads) {
-    const int kap = in.kappa[off + i], lam = in.lambda[off + i];
-    const bool okc = kap >= 0 && kap <= sh.kc && lam >= 0 && lam <= sh.km;
-    // a particle with counts outside the capacities is flagged and given -inf weight
-    sm.u.ll[i] = okc ? ll_in[off + i] : -HUGE_VAL;
-    if (!okc) atomicOr(flags, kFlagCapacity);
-    const int m = okc ? kap * (sh.km + 1) + lam : 0;
-    sm.mod[i] = (uint8_t)m;
-    atomicAdd(&sm.cnt[m], 1);
+  if (wave == 0) {
+    const int c0 = lane < M ? sm.cnt[lane] : 0, c1 = lane + kWave < M ? sm.cnt[lane + kWave] : 0;
+    const int i0 = wave_scan_incl(c0);
+    const int i1 = wave_scan_incl(c1) + __shfl(i0, kWave - 1);
+    if (lane < M) sm.base[lane] = i0 - c0;
+    if (lane + kWave < M) sm.base[lane + kWave] = i1 - c1;
   }
   __syncthreads();
-  // stable counting sort by model: wave 0 walks 64-particle chunks in order
-  if (wave == 0) {
-    if (lane == 0) {
-      int acc = 0;
-      for (int m = 0; m < M; ++m) {
-        sm.base[m] = acc;
-        sm.off[m] = acc;
-        acc += sm.cnt[m];
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    for (int c0 = 0; c0 < N; c0 += kWave) {
-      const int i = c0 + lane;
-      const int m = i < N ? sm.mod[i] : -1;
-      bool todo = i < N;
-      while (__any(todo)) {
-        const uint64_t pend = __ballot(todo);
-        const int leader = __ffsll((unsigned long long)pend) - 1;
-        const int lm = __shfl(m, leader);
-        const bool mine = todo && m == lm;
-        const uint64_t match = __ballot(mine);
-        const int rank = __popcll(match & ((1ull << lane) - 1));
-        const int basepos = sm.off[lm];
-        if (mine) {
-          sm.idx[basepos + rank] = (int16_t)i;
-          todo = false;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        if (lane == leader) sm.off[lm] = basepos + __popcll(match);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-      }
+  for (int ch = ch0; ch < ch1; ++ch) {
+    const int i = ch * kWave + lane;
+    const bool v = i < N;
+    const int m = v ? sm.mod[i] : 0;
+    const uint64_t same = same_model_lanes(m, v, nbits);
+    if (v) {
+      const int pos = sm.base[m] + sm.v.wc[wave][m] + __popcll(same & below);
+      if (pos >= 0 && pos < N) sm.idx[pos] = (int16_t)i;
+      if ((same & below) == 0) sm.v.wc[wave][m] += __popcll(same);
     }
   }
   __syncthreads();
@@ -447,39 +660,46 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
     const double mx = sm.mx[m];
     sm.x[pos] = mx > -HUGE_VAL ? sm.u.ll[sm.idx[pos]] - mx : -HUGE_VAL;
   }
-  // work items: 64 consecutive members of a model whose maximum is finite
-  if (tid == 0) {
-    int it = 0;
-    for (int m = 0; m < M; ++m) {
-      sm.item_base[m] = it;
-      if (sm.cnt[m] > 0 && sm.mx[m] > -HUGE_VAL)
-        for (int q0 = 0; q0 < sm.cnt[m]; q0 += kWave) {
-          sm.item_m[it] = (int16_t)m;
-          sm.item_q0[it] = (int16_t)q0;
-          ++it;
-        }
+  // run length and the first lane of each live model's runs
+  if (wave == 0) {
+    const int c0 = lane < M && sm.mx[lane] > -HUGE_VAL ? sm.cnt[lane] : 0;
+    const int c1 = lane + kWave < M && sm.mx[lane + kWave] > -HUGE_VAL ? sm.cnt[lane + kWave] : 0;
+    int R = 1;
+    for (; R < kRunMax; ++R) {
+      int tot = (c0 + R - 1) / R + (c1 + R - 1) / R;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) tot += __shfl_xor(tot, o);
+      if (tot <= kRwThreads) break;
     }
-    sm.item_base[M] = it;
-    sm.n_items = it;
+    const int r0 = (c0 + R - 1) / R, r1 = (c1 + R - 1) / R;
+    const int i0 = wave_scan_incl(r0);
+    const int i1 = wave_scan_incl(r1) + __shfl(i0, kWave - 1);
+    if (lane < M) sm.rb[lane] = i0 - r0;
+    if (lane + kWave < M) sm.rb[lane + kWave] = i1 - r1;
+    if (lane == kWave - 1) sm.rb[M] = i1;
+    if (lane == 0) sm.run_len = R;
   }
   __syncthreads();
+  const RunLane run = run_of_lane(sm, M);
   // temperature increment
   const double target = a.alpha_tess * (double)N;
   const double hi = 1.0 - g0;
   const double full_dg[1] = {hi};
-  eval_tess<1>(sm, full_dg, M, N);
-  const bool full = sm.tessk[0] >= target;
+  double t1[1];
+  constexpr int RM = SMALL ? 1 : kRunMax;
+  eval_tess<1, RM>(sm, run, full_dg, t1, M, true);
+  const bool full = t1[0] >= target;
   double dg = hi;
   if (!full) {
-    if (N <= kStageMax / 7)
-      dg = bisect_increment<3>(sm, hi, target, M, N);
-    else if (N <= kStageMax / 3)
-      dg = bisect_increment<2>(sm, hi, target, M, N);
+    if (SMALL)
+      dg = bisect_increment<3, 1>(sm, run, hi, target, M);
+    else if (sm.run_len <= 2)
+      dg = bisect_increment<2, 2>(sm, run, hi, target, M);
     else
-      dg = bisect_increment<1>(sm, hi, target, M, N);
+      dg = bisect_increment<1, kRunMax>(sm, run, hi, target, M);
+    const double chosen[1] = {dg};
+    eval_tess<1, RM>(sm, run, chosen, t1, M, true);   // s1 at the chosen increment
   }
-  const double chosen[1] = {dg};
-  eval_tess<1>(sm, chosen, M, N);   // s1 at the chosen increment
   // evidence, quantised weights and per-model cumulative sums (wave per model)
   for (int m = wave; m < M; m += kRwWaves) {
     const int n = sm.cnt[m];
@@ -500,7 +720,7 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
       const int q = q0 + lane;
       uint64_t v = 0;
       if (q < n && live) {
-        const double w = exp(dg * sm.x[sm.base[m] + q]) * inv;
+        const double w = exp_tab(dg * sm.x[sm.base[m] + q], sm.e2) * inv;
         v = (uint64_t)rint(w * 0x1.0p60);
       }
       // inclusive scan over the wave
@@ -516,7 +736,7 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
   __syncthreads();
   // ancestors: member j of model m takes the first member whose cumulative weight
   // exceeds the j-th systematic threshold
-  for (int i = tid; i < N; i += kRwThreads) sm.anc_l[i] = (int16_t)i;
+  for (int i = tid; i < N; i += kRwThreads) sm.v.anc_l[i] = (int16_t)i;
   __syncthreads();
   for (int pos = tid; pos < N; pos += kRwThreads) {
     const int dest = sm.idx[pos];
@@ -541,15 +761,11 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
       src = sm.idx[b + lo];
       if (src < 0 || src >= N) src = dest;
     }
-    sm.anc_l[dest] = (int16_t)src;
+    sm.v.anc_l[dest] = (int16_t)src;
   }
   __syncthreads();
   // the resampled population, in particle order (coalesced writes)
-  for (int i = tid; i < N; i += kRwThreads) {
-    const int src = sm.anc_l[i];
-    anc[off + i] = (int32_t)(off + src);
-    copy_particle(in, ll_in, out, ll_out, off + i, off + src, rows_c, rows_m, rows_zm);
-  }
+  copy_resampled(sm, in, ll_in, out, ll_out, anc, off, N, rows_c, rows_m, rows_zm);
   if (tid == 0) {
     gamma[s] = full ? 1.0 : g0 + dg;
     if (active) active[s] = 1;
@@ -558,9 +774,15 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
 
 hipError_t launch_reweight_resample(const SmcShape &sh, const rjsmc_reweight_args &a, const DevParticles &in,
                                     const double *ll_in, const DevParticlesW &out, double *ll_out, double *gamma,
-                                    double *log_z, int32_t *active, int32_t *anc, int *flags, hipStream_t stream) {
-  hipLaunchKernelGGL(reweight_resample_kernel, dim3((unsigned)a.n_sound), dim3(kRwThreads), 0, stream, sh, a, in,
-                     ll_in, out, ll_out, gamma, log_z, active, anc, flags);
+                                    double *log_z, int32_t *active, int32_t *anc, int *flags, const double *exp2t,
+                                    hipStream_t stream) {
+  const int64_t nps = in.n_per_sounding > 0 ? in.n_per_sounding : in.n;
+  if (nps <= kRwThreads)
+    hipLaunchKernelGGL(reweight_resample_kernel<true>, dim3((unsigned)a.n_sound), dim3(kRwThreads), 0, stream, sh, a,
+                       in, ll_in, out, ll_out, gamma, log_z, active, anc, flags, exp2t);
+  else
+    hipLaunchKernelGGL(reweight_resample_kernel<false>, dim3((unsigned)a.n_sound), dim3(kRwThreads), 0, stream, sh,
+                       a, in, ll_in, out, ll_out, gamma, log_z, active, anc, flags, exp2t);
   return hipGetLastError();
 }
 
