@@ -452,9 +452,23 @@ __device__ __forceinline__ int wave_scan_incl(int v) {
   return v;
 }
 
+// Element at a 32-bit byte offset from a uniform base (lets the compiler use the
+// scalar-base, vector-offset addressing of global memory instructions).
+template <typename T>
+__device__ __forceinline__ T ld_off(const T *base, uint32_t bytes) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + bytes);
+}
+template <typename T>
+__device__ __forceinline__ void st_off(T *base, uint32_t bytes, T v) {
+  *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + bytes) = v;
+}
+
 // out[i] = in[anc_l[i]] for the members i = tid + k * kRwThreads of the sounding, every row
-// of the population, ll, and the global ancestor index.  The loads of a row group are
-// issued before its stores.
+// of the population, ll, and the global ancestor index.  Rows are addressed from the
+// sounding's first element (a uniform base) with 32-bit byte offsets.  Loads are
+// unconditional (a lane past the sounding reads member 0) and issued in groups before
+// their stores, which are the only predicated accesses, so a group's loads are in flight
+// together.
 constexpr int kCopyPer = kMaxPerSounding / kRwThreads;
 template <typename SM>
 __device__ __forceinline__ void copy_resampled(const SM &sm, const DevParticles &in,
@@ -463,78 +477,72 @@ __device__ __forceinline__ void copy_resampled(const SM &sm, const DevParticles 
                                                int N, int rows_c, int rows_m, int rows_zm) {
   const int tid = threadIdx.x;
   const int64_t Si = in.stride, So = out.stride;
-  int64_t src[kCopyPer], dst[kCopyPer];
+  uint32_t src[kCopyPer], dst[kCopyPer];   // member indices within the sounding
   bool ok[kCopyPer];
 #pragma unroll
   for (int k = 0; k < kCopyPer; ++k) {
     const int i = tid + k * kRwThreads;
     ok[k] = i < N;
-    dst[k] = off + i;
-    src[k] = off + (ok[k] ? sm.v.anc_l[i] : i);
+    dst[k] = ok[k] ? (uint32_t)i : 0u;
+    src[k] = ok[k] ? (uint32_t)sm.v.anc_l[i] : 0u;
   }
   {
     int32_t ka[kCopyPer], la[kCopyPer];
-    double pb[kCopyPer], lt[kCopyPer], cc[kCopyPer], lv[kCopyPer];
+    double lv[kCopyPer];
+#pragma unroll
+    for (int k = 0; k < kCopyPer; ++k) {
+      ka[k] = ld_off(in.kappa + off, src[k] * 4u);
+      la[k] = in.lambda ? ld_off(in.lambda + off, src[k] * 4u) : 0;
+      lv[k] = ld_off(ll_in + off, src[k] * 8u);
+    }
 #pragma unroll
     for (int k = 0; k < kCopyPer; ++k)
       if (ok[k]) {
-        ka[k] = in.kappa[src[k]];
-        la[k] = in.lambda ? in.lambda[src[k]] : 0;
-        pb[k] = in.phi_b[src[k]];
-        lt[k] = in.log10_tau[src[k]];
-        cc[k] = in.c[src[k]];
-        lv[k] = ll_in[src[k]];
+        st_off(anc + off, dst[k] * 4u, (int32_t)(off + src[k]));
+        st_off(out.kappa + off, dst[k] * 4u, ka[k]);
+        if (out.lambda) st_off(out.lambda + off, dst[k] * 4u, la[k]);
+        st_off(ll_out + off, dst[k] * 8u, lv[k]);
       }
+  }
+  {
+    double pb[kCopyPer], lt[kCopyPer], cc[kCopyPer];
+#pragma unroll
+    for (int k = 0; k < kCopyPer; ++k) {
+      pb[k] = ld_off(in.phi_b + off, src[k] * 8u);
+      lt[k] = ld_off(in.log10_tau + off, src[k] * 8u);
+      cc[k] = ld_off(in.c + off, src[k] * 8u);
+    }
 #pragma unroll
     for (int k = 0; k < kCopyPer; ++k)
       if (ok[k]) {
-        anc[dst[k]] = (int32_t)src[k];
-        out.kappa[dst[k]] = ka[k];
-        if (out.lambda) out.lambda[dst[k]] = la[k];
-        out.phi_b[dst[k]] = pb[k];
-        out.log10_tau[dst[k]] = lt[k];
-        out.c[dst[k]] = cc[k];
-        ll_out[dst[k]] = lv[k];
+        st_off(out.phi_b + off, dst[k] * 8u, pb[k]);
+        st_off(out.log10_tau + off, dst[k] * 8u, lt[k]);
+        st_off(out.c + off, dst[k] * 8u, cc[k]);
       }
   }
-  // the layer rows (phi, z_cond, m, z_charg) as one list of row slots, four at a time
-  const int n_slots = 2 * rows_c + rows_m + rows_zm;
-  auto row_in = [&](int q) -> const double * {
-    if (q < rows_c) return in.phi + q * Si;
-    q -= rows_c;
-    if (q < rows_c) return in.z_cond + q * Si;
-    q -= rows_c;
-    if (q < rows_m) return in.m + q * Si;
-    return in.z_charg + (q - rows_m) * Si;
-  };
-  auto row_out = [&](int q) -> double * {
-    if (q < rows_c) return out.phi + q * So;
-    q -= rows_c;
-    if (q < rows_c) return out.z_cond + q * So;
-    q -= rows_c;
-    if (q < rows_m) return out.m + q * So;
-    return out.z_charg + (q - rows_m) * So;
-  };
-  constexpr int kSlots = 4;
-  for (int q0 = 0; q0 < n_slots; q0 += kSlots) {
-    double v[kSlots][kCopyPer];
+  // layer rows of one or two fields, one row of each at a time (more loads in flight
+  // cost the registers of a third workgroup per CU)
+  auto rows_of = [&](const double *ia, const double *ib, double *oa, double *ob, int rows) {
+    for (int r = 0; r < rows; ++r) {
+      double v[2][kCopyPer];
 #pragma unroll
-    for (int j = 0; j < kSlots; ++j)
-      if (q0 + j < n_slots) {
-        const double *__restrict__ ri = row_in(q0 + j);
-#pragma unroll
-        for (int k = 0; k < kCopyPer; ++k)
-          if (ok[k]) v[j][k] = ri[src[k]];
+      for (int k = 0; k < kCopyPer; ++k) {
+        v[0][k] = ld_off(ia + r * Si + off, src[k] * 8u);
+        v[1][k] = ib ? ld_off(ib + r * Si + off, src[k] * 8u) : 0.0;
       }
 #pragma unroll
-    for (int j = 0; j < kSlots; ++j)
-      if (q0 + j < n_slots) {
-        double *__restrict__ ro = row_out(q0 + j);
-#pragma unroll
-        for (int k = 0; k < kCopyPer; ++k)
-          if (ok[k]) ro[dst[k]] = v[j][k];
-      }
-  }
+      for (int k = 0; k < kCopyPer; ++k)
+        if (ok[k]) {
+          st_off(oa + r * So + off, dst[k] * 8u, v[0][k]);
+          if (ob) st_off(ob + r * So + off, dst[k] * 8u, v[1][k]);
+        }
+    }
+  };
+  rows_of(in.phi, in.z_cond, out.phi, out.z_cond, rows_c);
+  if (rows_zm == rows_m)
+    rows_of(in.m, in.z_charg, out.m, out.z_charg, rows_m);
+  else
+    rows_of(in.m, nullptr, out.m, nullptr, rows_m);
 }
 
 // One workgroup per sounding: re-weight, evidence, within-model resampling, and the
