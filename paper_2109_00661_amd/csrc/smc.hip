@@ -171,24 +171,31 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// The temperature search evaluates the TESS at the 2^LV - 1 midpoints that LV successive
-// halvings of the bracket can visit, then takes the same LV decisions: 60 / LV rounds give
-// the 60 halvings of a plain bisection, with its evaluation points and decisions, in a
-// fraction of its sequential rounds.
+// The temperature increment is the lower end of the bracket that 60 halvings of
+// (0, 1 - gamma] leave, each halving keeping the half whose lower end passes the test
+// TESS >= alpha N.  TESS does not increase with the increment (tilting the weights further
+// towards the larger log-likelihoods can only concentrate them), so a midpoint at or below
+// a point that passed also passes, and one at or above a point that failed also fails.
+// The search therefore first narrows a bracket (a, b) around the root with Newton steps
+// on ln TESS in ln(increment), falling back to a geometric halving whenever a step leaves
+// the bracket, then replays the 60 halvings, evaluating TESS only at the midpoints that
+// fall inside the bracket and taking the others from its ends.  Typically a dozen
+// evaluations replace sixty; the replay makes the same decisions as a plain bisection
+// wherever TESS differs from the target by more than its rounding.
 //
 // Each live model's members (sorted order) are cut into runs of R consecutive members
 // (the model's last run may be shorter), one run per lane, runs in model order across the
 // workgroup; R is the least length whose runs fit the 512 lanes (at most 5 for 2,048
 // members and 128 models).  A lane keeps its run's x values in registers for the whole
-// search; a round is then: the lane's exponentials and their sums, a segmented scan over
-// the lanes of each wave (a model's lanes are contiguous), the carries of models that
+// search; an evaluation is then: the lane's exponentials and their sums, a segmented scan
+// over the lanes of each wave (a model's lanes are contiguous), the carries of models that
 // span waves, and the sum over models of the per-model ESS.  All sums are taken in a
 // fixed order, so every thread obtains the same TESS and takes the same decisions.
-constexpr int kBisectK = 7;
+constexpr int kEvalK = 2;        // increments per evaluation at most
 constexpr int kRunMax = 5;
+constexpr int kNewtonMax = 16;
 static_assert(kMaxPerSounding + kMaxModels * (kRunMax - 1) <= kRwThreads * kRunMax, "runs of 5 always fit");
 
-template <int KC>
 struct RwShared {
   union {
     double ll[kMaxPerSounding];                       // particle order, until x is formed
@@ -204,8 +211,8 @@ struct RwShared {
   int cnt[kMaxModels], base[kMaxModels], rb[kMaxModels + 1];
   double mx[kMaxModels], s1[kMaxModels];
   uint64_t U[kMaxModels];
-  double tail_a[kRwWaves][KC], tail_b[kRwWaves][KC];   // wave-end partial sums (KC candidates)
-  double ess[kMaxModels][KC];                          // per-model ESS (0: no runs)
+  double tail[kRwWaves][2 * kEvalK];   // wave-end partial sums of the scanned values
+  double ess[kMaxModels][kEvalK];       // per-model ESS, or ESS and its derivative (0: no runs)
   double e2[kExp2N];                // 2^(j/256), the table of exp_tab
   int run_len;
 };
@@ -269,22 +276,19 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __hiloint2double(hi, lo);
 }
 
-// Inclusive scan of a and b over the lanes of a wave, restarted where the model changes:
+// Inclusive scan of v over the lanes of a wave, restarted where the model changes:
 // row-local steps from lanes -1, -2, -4, -8, then the previous row's last lane (rows 1
 // and 3) and lane 31 (rows 2 and 3); seg bit j says whether step j's source lane holds
 // the same model.  A fixed order of additions, so the sums are reproducible.
-template <int K>
-__device__ __forceinline__ void seg_scan(double (&a)[K], double (&b)[K], int seg) {
+template <int V>
+__device__ __forceinline__ void seg_scan(double (&v)[V], int seg) {
   auto step = [&](auto ctrl, int bit) {
     constexpr int C = decltype(ctrl)::value;
     const bool take = (seg >> bit) & 1;
 #pragma unroll
-    for (int c = 0; c < K; ++c) {
-      const double ta = dpp_f64<C>(a[c]), tb = dpp_f64<C>(b[c]);
-      if (take) {
-        a[c] += ta;
-        b[c] += tb;
-      }
+    for (int q = 0; q < V; ++q) {
+      const double t = dpp_f64<C>(v[q]);
+      if (take) v[q] += t;
     }
   };
   step(std::integral_constant<int, 0x111>{}, 0);
@@ -295,121 +299,170 @@ __device__ __forceinline__ void seg_scan(double (&a)[K], double (&b)[K], int seg
   step(std::integral_constant<int, 0x143>{}, 5);
 }
 
-// TESS at K increments at once (all threads call, all return the same values); with
-// keep, sm.s1[m] = sum over model m of w at dg[0].  RM bounds the run length.
-template <int K, int RM, typename SM>
+// TESS at K increments (all threads call, all return the same values).  With DER (K = 1)
+// also its derivative in the increment, from the per-model sums A = sum w, B = sum w^2,
+// A1 = sum x w, B1 = sum x w^2:  d(A^2/B)/d dg = 2 A (A1 B - A B1) / B^2.  With keep,
+// sm.s1[m] = A of model m at dg[0].  RM bounds the run length.
+template <int K, int RM, bool DER, typename SM>
 __device__ __forceinline__ void eval_tess(SM &sm, const RunLane &r, const double (&dg)[K], double (&tess)[K],
-                                          int M, bool keep) {
+                                          double &dtess, int M, bool keep) {
+  static_assert(K <= kEvalK && (!DER || K == 1), "evaluation shape");
+  constexpr int V = DER ? 4 : 2 * K;     // scanned values: A[K], B[K] (, A1, B1)
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  double a[K], b[K];
+  double v[V];
 #pragma unroll
-  for (int c = 0; c < K; ++c) {
-    a[c] = 0.0;
-    b[c] = 0.0;
-  }
+  for (int q = 0; q < V; ++q) v[q] = 0.0;
 #pragma unroll
   for (int j = 0; j < RM; ++j)
     if (j < r.nv) {
 #pragma unroll
       for (int c = 0; c < K; ++c) {
         const double w = exp_tab(dg[c] * r.x[j], sm.e2);
-        a[c] += w;
-        b[c] = fma(w, w, b[c]);
+        v[c] += w;
+        v[K + c] = fma(w, w, v[K + c]);
+        if (DER) {
+          const double xw = r.x[j] * w;
+          v[2] += xw;
+          v[3] = fma(xw, w, v[3]);
+        }
       }
     }
-  seg_scan<K>(a, b, r.seg);
+  seg_scan<V>(v, r.seg);
   if (lane == kWave - 1)
 #pragma unroll
-    for (int c = 0; c < K; ++c) {
-      sm.tail_a[wave][c] = a[c];
-      sm.tail_b[wave][c] = b[c];
-    }
+    for (int q = 0; q < V; ++q) sm.tail[wave][q] = v[q];
   __syncthreads();
   if (r.fin) {
+    double t[V];                      // earlier waves' parts of the model, in wave order
 #pragma unroll
-    for (int c = 0; c < K; ++c) {
-      double A = 0.0, B = 0.0;       // earlier waves' parts of the model, in wave order
-      for (int w2 = r.w0; w2 < wave; ++w2) {
-        A += sm.tail_a[w2][c];
-        B += sm.tail_b[w2][c];
-      }
-      A += a[c];
-      B += b[c];
-      sm.ess[r.m][c] = A * A / B;
-      if (keep && c == 0) {
-        sm.s1[r.m] = A;
-      }
-    }
+    for (int q = 0; q < V; ++q) t[q] = 0.0;
+    for (int w2 = r.w0; w2 < wave; ++w2)
+#pragma unroll
+      for (int q = 0; q < V; ++q) t[q] += sm.tail[w2][q];
+#pragma unroll
+    for (int q = 0; q < V; ++q) t[q] += v[q];
+#pragma unroll
+    for (int c = 0; c < K; ++c) sm.ess[r.m][c] = t[c] * t[c] / t[K + c];
+    if (DER) sm.ess[r.m][1] = 2.0 * t[0] * (t[2] * t[1] - t[0] * t[3]) / (t[1] * t[1]);
+    if (keep) sm.s1[r.m] = t[0];
   }
   __syncthreads();
+  constexpr int S = DER ? 2 : K;        // summed columns of ess
+  double acc[S];
 #pragma unroll
-  for (int c = 0; c < K; ++c) tess[c] = 0.0;
-  // models in order, a few loads in flight (absent models add +0)
-  constexpr int G = K == 1 ? 8 : K == 3 ? 4 : 2;
-  for (int m0 = 0; m0 < M; m0 += G) {
-    double v[G][K];
+  for (int c = 0; c < S; ++c) acc[c] = 0.0;
+  // models in order, eight loads in flight (absent models add +0)
+  for (int m0 = 0; m0 < M; m0 += 8) {
+    double e[8][S];
 #pragma unroll
-    for (int j = 0; j < G; ++j)
+    for (int j = 0; j < 8; ++j)
 #pragma unroll
-      for (int c = 0; c < K; ++c) v[j][c] = m0 + j < M ? sm.ess[m0 + j][c] : 0.0;
+      for (int c = 0; c < S; ++c) e[j][c] = m0 + j < M ? sm.ess[m0 + j][c] : 0.0;
 #pragma unroll
-    for (int j = 0; j < G; ++j)
+    for (int j = 0; j < 8; ++j)
 #pragma unroll
-      for (int c = 0; c < K; ++c) tess[c] += v[j][c];
+      for (int c = 0; c < S; ++c) acc[c] += e[j][c];
   }
+#pragma unroll
+  for (int c = 0; c < K; ++c) tess[c] = acc[c];
+  dtess = DER ? acc[S - 1] : 0.0;
 }
 
-// The 2^LV - 1 points that LV halvings of (lo, hi) can visit, in order, each formed from
-// its two neighbours exactly as a halving forms it.
-template <int K>
-__device__ __forceinline__ void nested_midpoints(double (&c)[K], double lo, double hi) {
-  static_assert(K == 1 || K == 3 || K == 7, "one, two or three halvings");
-  if constexpr (K == 1) {
-    c[0] = 0.5 * (lo + hi);
-  } else if constexpr (K == 3) {
-    c[1] = 0.5 * (lo + hi);
-    c[0] = 0.5 * (lo + c[1]);
-    c[2] = 0.5 * (c[1] + hi);
-  } else {
-    c[3] = 0.5 * (lo + hi);
-    c[1] = 0.5 * (lo + c[3]);
-    c[5] = 0.5 * (c[3] + hi);
-    c[0] = 0.5 * (lo + c[1]);
-    c[2] = 0.5 * (c[1] + c[3]);
-    c[4] = 0.5 * (c[3] + c[5]);
-    c[6] = 0.5 * (c[5] + hi);
+// ln(f / t) for the Newton steps: the series 2 atanh(s), s = (f - t) / (f + t), when
+// f / t is near 1 (where the steps must be accurate; the terms beyond s^19 are below
+// 1e-19 relative), a single-precision logarithm elsewhere (far from the root a step only
+// needs its direction and rough size; every decision comes from an evaluation).
+__device__ __forceinline__ double ln_ratio(double f, double t) {
+  const double s = (f - t) / (f + t);
+  if (fabs(s) < 0.125) {
+    const double s2 = s * s;
+    double p = 1.0 / 19.0;
+    p = fma(p, s2, 1.0 / 17.0);
+    p = fma(p, s2, 1.0 / 15.0);
+    p = fma(p, s2, 1.0 / 13.0);
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    p = fma(p, s2, 1.0);
+    return 2.0 * s * p;
   }
+  return (double)__logf((float)(f / t));
 }
 
-// 60 halvings of (0, hi) keeping the lower end where TESS >= target (runs of at most
-// RM members).
-template <int LV, int RM, typename SM>
-__device__ __forceinline__ double bisect_increment(SM &sm, const RunLane &r, double hi, double target,
-                                                  int M) {
-  constexpr int K = (1 << LV) - 1;
-  double lo = 0.0;
-  for (int round = 0; round < 60 / LV; ++round) {
-    double c[K], tess[K];
-    nested_midpoints<K>(c, lo, hi);
-    eval_tess<K, RM>(sm, r, c, tess, M, false);
-    int node = K / 2, step = (K + 1) / 4;
-#pragma unroll
-    for (int level = 0; level < LV; ++level) {
-      double cn = 0.0, tn = 0.0;            // c[node], tess[node] (no indexed private array)
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        cn += (node == j ? 1.0 : 0.0) * c[j];
-        tn += (node == j ? 1.0 : 0.0) * tess[j];
-      }
-      if (tn >= target) {
-        lo = cn;
-        node += step;
-      } else {
-        hi = cn;
-        node -= step;
-      }
-      step >>= 1;
+// The increment (see the search description above); full when the whole remaining step
+// 1 - gamma = H passes.  On return sm.s1 holds the per-model weight sums at the increment.
+template <int RM, typename SM>
+__device__ double next_increment(SM &sm, const RunLane &r, double H, double target, int M, bool &full) {
+  double t1[1], dt;
+  {
+    const double d0[1] = {H};
+    eval_tess<1, RM, true>(sm, r, d0, t1, dt, M, true);
+  }
+  full = t1[0] >= target;
+  if (full) return H;
+  double a = 0.0, b = H;                        // TESS(a) >= target (when a > 0), TESS(b) < target
+  // current point: u ~ ln d, TESS f and its derivative df; ua, ub ~ ln a, ln b (the
+  // logarithms only steer the steps: the bracket itself is a, b)
+  const double lnH = (double)__logf((float)H);
+  const double u_min = lnH - 62.0 * 0.69314718055994531;   // below every halving midpoint
+  double u = lnH, d = H, f = t1[0], df = dt, ua = u_min, ub = u;
+  bool converged = false;
+  double step = 0.0;
+  for (int it = 0; it < kNewtonMax && b - a > H * 0x1p-61; ++it) {
+    double un = u - ln_ratio(f, target) * f / (d * df);
+    if (fabs(un - u) < 1e-14) {                 // the root is within |un - u| of the current point
+      converged = true;
+      step = un - u;
+      break;
     }
+    if (!(un > ua && un < ub)) un = 0.5 * (ua + ub);   // outside the bracket, or NaN
+    const double dn = exp_tab(un, sm.e2);      // un < ub <= 0
+    if (!(dn > a && dn < b)) break;             // no representable point left inside
+    const double dd[1] = {dn};
+    eval_tess<1, RM, true>(sm, r, dd, t1, dt, M, false);
+    if (t1[0] >= target) {
+      a = dn;
+      ua = un;
+    } else {
+      b = dn;
+      ub = un;
+    }
+    u = un;
+    d = dn;
+    f = t1[0];
+    df = dt;
+  }
+  if (converged && b - a > H * 0x1p-61) {
+    // tighten the bracket around the converged estimate
+    const double dn = d * (1.0 + step), del = 2.0 * fabs(step) + 0x1p-49;
+    double pd[2] = {dn * (1.0 - del), dn * (1.0 + del)}, tp[2], unused;
+    pd[0] = pd[0] > a ? pd[0] : a;
+    pd[1] = pd[1] < b ? pd[1] : b;
+    eval_tess<2, RM, false>(sm, r, pd, tp, unused, M, false);
+    if (tp[0] >= target && pd[0] > a) a = pd[0];
+    if (tp[1] < target && pd[1] < b) b = pd[1];
+  }
+  // the 60 halvings, evaluating only inside the bracket
+  double lo = 0.0, hi = H;
+  for (int k = 0; k < 60; ++k) {
+    const double c = 0.5 * (lo + hi);
+    bool pass;
+    if (a > 0.0 && c <= a) {
+      pass = true;
+    } else if (c >= b) {
+      pass = false;
+    } else {
+      const double cc[1] = {c};
+      double tc[1], unused;
+      eval_tess<1, RM, false>(sm, r, cc, tc, unused, M, false);
+      pass = tc[0] >= target;
+    }
+    if (pass)
+      lo = c;
+    else
+      hi = c;
   }
   return lo;
 }
@@ -557,7 +610,7 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
                                                                        double *gamma, double *log_z,
                                                                        int32_t *active, int32_t *anc, int *flags,
                                                                        const double *exp2t) {
-  __shared__ RwShared<SMALL ? kBisectK : 3> sm;
+  __shared__ RwShared sm;
   const bool dec = in.layout == RJSMC_LAYOUT_DECOUPLED;
   const int rows_c = sh.kc, rows_m = dec ? sh.km : sh.kc + 1, rows_zm = dec ? sh.km : 0;
   const int s = blockIdx.x;
@@ -692,21 +745,13 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
   // temperature increment
   const double target = a.alpha_tess * (double)N;
   const double hi = 1.0 - g0;
-  const double full_dg[1] = {hi};
-  double t1[1];
   constexpr int RM = SMALL ? 1 : kRunMax;
-  eval_tess<1, RM>(sm, run, full_dg, t1, M, true);
-  const bool full = t1[0] >= target;
-  double dg = hi;
+  bool full;
+  const double dg = next_increment<RM>(sm, run, hi, target, M, full);
   if (!full) {
-    if (SMALL)
-      dg = bisect_increment<3, 1>(sm, run, hi, target, M);
-    else if (sm.run_len <= 2)
-      dg = bisect_increment<2, 2>(sm, run, hi, target, M);
-    else
-      dg = bisect_increment<1, kRunMax>(sm, run, hi, target, M);
     const double chosen[1] = {dg};
-    eval_tess<1, RM>(sm, run, chosen, t1, M, true);   // s1 at the chosen increment
+    double t1[1], unused;
+    eval_tess<1, RM, false>(sm, run, chosen, t1, unused, M, true);   // s1 at the chosen increment
   }
   // evidence, quantised weights and per-model cumulative sums (wave per model)
   for (int m = wave; m < M; m += kRwWaves) {
