@@ -212,7 +212,7 @@ struct RwShared {
   double mx[kMaxModels], s1[kMaxModels];
   uint64_t U[kMaxModels];
   double tail[kRwWaves][2 * kEvalK];   // wave-end partial sums of the scanned values
-  double ess[kMaxModels][kEvalK];       // per-model ESS, or ESS and its derivative (0: no runs)
+  double wess[kRwWaves][kEvalK];        // per-wave sums of the models' ESS (or ESS, derivative)
   double e2[kExp2N];                // 2^(j/256), the table of exp_tab
   int run_len;
 };
@@ -276,6 +276,23 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Sum of v over the lanes of a wave, left in lane 63: the unsegmented form of the scan
+// below (sources outside the pattern read 0).
+template <int V>
+__device__ __forceinline__ void wave_total(double (&v)[V]) {
+  auto step = [&](auto ctrl) {
+    constexpr int C = decltype(ctrl)::value;
+#pragma unroll
+    for (int q = 0; q < V; ++q) v[q] += dpp_f64<C>(v[q]);
+  };
+  step(std::integral_constant<int, 0x111>{});
+  step(std::integral_constant<int, 0x112>{});
+  step(std::integral_constant<int, 0x114>{});
+  step(std::integral_constant<int, 0x118>{});
+  step(std::integral_constant<int, 0x142>{});
+  step(std::integral_constant<int, 0x143>{});
+}
+
 // Inclusive scan of v over the lanes of a wave, restarted where the model changes:
 // row-local steps from lanes -1, -2, -4, -8, then the previous row's last lane (rows 1
 // and 3) and lane 31 (rows 2 and 3); seg bit j says whether step j's source lane holds
@@ -332,6 +349,10 @@ __device__ __forceinline__ void eval_tess(SM &sm, const RunLane &r, const double
 #pragma unroll
     for (int q = 0; q < V; ++q) sm.tail[wave][q] = v[q];
   __syncthreads();
+  constexpr int S = DER ? 2 : K;        // per-model terms: ESS at each increment (, derivative)
+  double e[S];
+#pragma unroll
+  for (int c = 0; c < S; ++c) e[c] = 0.0;
   if (r.fin) {
     double t[V];                      // earlier waves' parts of the model, in wave order
 #pragma unroll
@@ -342,27 +363,24 @@ __device__ __forceinline__ void eval_tess(SM &sm, const RunLane &r, const double
 #pragma unroll
     for (int q = 0; q < V; ++q) t[q] += v[q];
 #pragma unroll
-    for (int c = 0; c < K; ++c) sm.ess[r.m][c] = t[c] * t[c] / t[K + c];
-    if (DER) sm.ess[r.m][1] = 2.0 * t[0] * (t[2] * t[1] - t[0] * t[3]) / (t[1] * t[1]);
+    for (int c = 0; c < K; ++c) e[c] = t[c] * t[c] / t[K + c];
+    if (DER) e[S - 1] = 2.0 * t[0] * (t[2] * t[1] - t[0] * t[3]) / (t[1] * t[1]);
     if (keep) sm.s1[r.m] = t[0];
   }
+  // the models' terms summed over each wave's lanes (models in lane order), then the
+  // waves' sums in wave order
+  wave_total<S>(e);
+  if (lane == kWave - 1)
+#pragma unroll
+    for (int c = 0; c < S; ++c) sm.wess[wave][c] = e[c];
   __syncthreads();
-  constexpr int S = DER ? 2 : K;        // summed columns of ess
   double acc[S];
 #pragma unroll
   for (int c = 0; c < S; ++c) acc[c] = 0.0;
-  // models in order, eight loads in flight (absent models add +0)
-  for (int m0 = 0; m0 < M; m0 += 8) {
-    double e[8][S];
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
+  for (int w2 = 0; w2 < kRwWaves; ++w2)
 #pragma unroll
-      for (int c = 0; c < S; ++c) e[j][c] = m0 + j < M ? sm.ess[m0 + j][c] : 0.0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-#pragma unroll
-      for (int c = 0; c < S; ++c) acc[c] += e[j][c];
-  }
+    for (int c = 0; c < S; ++c) acc[c] += sm.wess[w2][c];
 #pragma unroll
   for (int c = 0; c < K; ++c) tess[c] = acc[c];
   dtess = DER ? acc[S - 1] : 0.0;
@@ -653,7 +671,6 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
   }
   for (int t = tid; t < kRwWaves * kMaxModels; t += kRwThreads) (&sm.v.wc[0][0])[t] = 0;
   for (int t = tid; t < kExp2N; t += kRwThreads) sm.e2[t] = exp2t[t];
-  for (int t = tid; t < (int)(sizeof(sm.ess) / sizeof(double)); t += kRwThreads) (&sm.ess[0][0])[t] = 0.0;
   __syncthreads();
   // stable counting sort by model: wave w takes a contiguous range of 64-particle chunks,
   // counts its members per model, then places them in order behind the earlier waves'
