@@ -176,7 +176,12 @@ def reweight(ll, models, dg, log_z, model_list):
         if nk == 0:
             log_z[k] = -np.inf
             continue
-        x = dg * ll[sel]
+        # a zero-likelihood particle has incremental weight 0 at every increment, the
+        # zero increment included (the limit of 0^dg as dg -> 0+)
+        llk = ll[sel]
+        x = np.full(nk, -np.inf)
+        live = ~np.isneginf(llk)
+        x[live] = dg * llk[live]
         lse = _logsumexp(x)
         log_z[k] = log_z[k] + lse - math.log(nk) if np.isfinite(lse) else -np.inf
         if np.isfinite(lse):

@@ -72,6 +72,11 @@ def test_reweight_resample(B, ctx, n_sound, nps):
         sel = (p["kappa"] == 2) & (np.arange(len(ll)) < nps)
         ll[sel] = -np.inf                                # a dead model in sounding 0
     log_z = np.random.default_rng(1).normal(0, 1, (n_sound, M))
+    _check_reweight(B, ctx, p, ll, gamma, log_z, n_sound, nps)
+
+
+def _check_reweight(B, ctx, p, ll, gamma, log_z, n_sound, nps):
+    from oracle import smc
     g_ref, lz_ref, anc_ref = smc.reweight_resample(ll, p["kappa"], p["lambda_"], KC, KM, gamma, log_z, 0.5, 77, 3,
                                                    nps if n_sound > 1 else None)
     dp = B.particles_to_device(p)
@@ -94,6 +99,31 @@ def test_reweight_resample(B, ctx, n_sound, nps):
     assert np.array_equal(act.cpu().numpy(), (gamma < 1).astype(np.int32))
     _assert_pop_equal(_host(B, out), smc.gather(p, anc_ref))
     assert np.array_equal(ll_out.cpu().numpy(), ll[anc_ref])
+
+
+def test_reweight_resample_skewed_dead_and_full(B, ctx):
+    """Soundings that exercise the temperature search's edge cases: one model holding
+    95% of the members (its runs span six waves, so the per-wave carries chain), fewer
+    live members than alpha N (no increment passes: gamma stays), a nearly flat
+    likelihood (the full step passes), a model of a single member, and a ragged
+    population size."""
+    nps, n_sound = 2000, 4
+    p, ll = _population_with_ll(n_sound, nps, 91)
+    rng = np.random.default_rng(12)
+    s0 = slice(0, nps)
+    big = rng.random(nps) < 0.95
+    p["kappa"][s0][big] = 1
+    p["lambda_"][s0][big] = 2
+    lone = np.nonzero(p["kappa"][s0] * (KM + 1) + p["lambda_"][s0] == 0)[0]
+    p["kappa"][s0][lone[1:]], p["lambda_"][s0][lone[1:]] = 1, 2
+    assert len(lone) >= 1                            # model 0 now has a single member
+    s1 = slice(nps, 2 * nps)
+    ll[s1][40:] = -np.inf                            # 40 live members < 0.5 N: increment 0
+    s2 = slice(2 * nps, 3 * nps)
+    ll[s2] = -1e-3 * rng.random(nps)                 # TESS(1 - gamma) stays above alpha N
+    gamma = np.array([0.0, 0.25, 0.1, 0.9])
+    log_z = np.random.default_rng(2).normal(0, 1, (n_sound, M))
+    _check_reweight(B, ctx, p, ll, gamma, log_z, n_sound, nps)
 
 
 def test_reweight_constant_likelihood_one_step(B, ctx):
