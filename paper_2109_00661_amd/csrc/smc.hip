@@ -901,8 +901,12 @@ __device__ __forceinline__ double prior_sd(const rjsmc_prior &pr, double zmax, i
 }
 
 // ---------------------------------------------------------------------- adaptation ---
-// One wavefront per (sounding, model): member list, mean and covariance in LDS, then the
-// factor of the covariance (eigen_factor).
+// One workgroup per (sounding, model): the member list (first wave, by ballot), the mean
+// (a thread per component) and covariance (a thread per entry), each summed over the
+// members in index order, then the factor of the covariance (eigen_factor).  (Starting
+// the sweeps from the previous step's directions was tried: resampling leaves duplicate
+// members, so those factors often have null directions, and where they did not the
+// sweep count hardly fell.)
 constexpr int kDimMax = 3 + 2 * (kMaxLayers - 1);   // 33
 constexpr int kLd = kDimMax + 1;                    // LDS row stride
 constexpr int kAdaptThreads = 512;                 // workgroup of the adaptation kernels
@@ -914,9 +918,11 @@ constexpr int kAdaptThreads = 512;                 // workgroup of the adaptatio
 //
 // The sweeps use the round-robin (tournament) ordering: a sweep is nn - 1 rounds of nn/2
 // disjoint index pairs (nn = d rounded up to even), so every pair of a round is rotated
-// at once, A <- J^T A J with J the product of the round's rotations.  Each pair's 2x2
-// block is touched by its own rotation only, so its diagonal takes the classical update
-// and its off-diagonal entry is set to zero.
+// at once, A <- J^T A J with J the product of the round's rotations, in one pass over the
+// entries (each reads the four entries of A its row and column pairs touch) together
+// with V <- V J: two barriers per round.  Each pair's 2x2 block is touched by its own
+// rotation only, so its diagonal takes the classical update and its off-diagonal entry
+// is set to zero.
 template <int NT>
 __device__ __forceinline__ void eigen_factor(double (*A)[kLd], double (*V0)[kLd], double (*T)[kDimMax][kLd],
                                              double *rc, double *rs, int *order, int d, int D, double *F) {
@@ -928,17 +934,20 @@ __device__ __forceinline__ void eigen_factor(double (*A)[kLd], double (*V0)[kLd]
       wave_lds_sync();
   };
   __shared__ int partner[kLd];
+  __shared__ int rotated[kLd];
+  __shared__ double dnew[kLd];
   __shared__ double red[2][NT / kWave];
-  double (*Vc)[kLd] = V0;        // current eigenvector estimate
-  double (*Vn)[kLd] = T[1];      // its column-pass buffer
-  double (*B)[kLd] = T[0];       // column-pass buffer of A
+  double (*Ac)[kLd] = A;         // current matrix and eigenvector estimate, and the
+  double (*An)[kLd] = T[0];      // buffers a round writes (swapped after each round)
+  double (*Vc)[kLd] = V0;
+  double (*Vn)[kLd] = T[1];
   const int nn = (d + 1) & ~1, np = nn / 2;
   for (int sweep = 0; sweep < 40; ++sweep) {
     double offn = 0.0, diag = 0.0;
     for (int t = tid; t < d * d; t += NT) {
       const int a = t / d, b = t % d;
-      if (a != b) offn += A[a][b] * A[a][b];
-      else diag += A[a][b] * A[a][b];
+      if (a != b) offn += Ac[a][b] * Ac[a][b];
+      else diag += Ac[a][b] * Ac[a][b];
     }
     offn = wave_sum(offn);
     diag = wave_sum(diag);
@@ -959,25 +968,22 @@ __device__ __forceinline__ void eigen_factor(double (*A)[kLd], double (*V0)[kLd]
     if (!(offn > 1e-30 * diag)) break;
     for (int round = 0; round < nn - 1; ++round) {
       // pair `tid` of this round: (nn-1, round) and ((round + j) mod (nn-1), (round - j) mod (nn-1))
-      int pp = 0, qq = 0;
-      double app = 0.0, aqq = 0.0, apq = 0.0, tt = 0.0;
-      bool rot = false;
       if (tid < np) {
-        int x = tid == 0 ? nn - 1 : (round + tid) % (nn - 1);
-        int y = tid == 0 ? round : (round - tid + (nn - 1)) % (nn - 1);
-        pp = x < y ? x : y;
-        qq = x < y ? y : x;
-        double cth = 1.0, sth = 0.0;
+        const int x = tid == 0 ? nn - 1 : (round + tid) % (nn - 1);
+        const int y = tid == 0 ? round : (round - tid + (nn - 1)) % (nn - 1);
+        const int pp = x < y ? x : y, qq = x < y ? y : x;
         if (qq < d) {
-          apq = A[pp][qq];
-          if (apq != 0.0) {
-            app = A[pp][pp];
-            aqq = A[qq][qq];
+          double cth = 1.0, sth = 0.0;
+          const double apq = Ac[pp][qq];
+          const bool rot = apq != 0.0;
+          if (rot) {
+            const double app = Ac[pp][pp], aqq = Ac[qq][qq];
             const double theta = (aqq - app) / (2.0 * apq);
-            tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
             cth = 1.0 / sqrt(tt * tt + 1.0);
             sth = tt * cth;
-            rot = true;
+            dnew[pp] = app - tt * apq;
+            dnew[qq] = aqq + tt * apq;
           }
           partner[pp] = qq;
           partner[qq] = pp;
@@ -985,42 +991,41 @@ __device__ __forceinline__ void eigen_factor(double (*A)[kLd], double (*V0)[kLd]
           rs[pp] = -sth;
           rc[qq] = cth;
           rs[qq] = sth;
+          rotated[pp] = rot;
+          rotated[qq] = rot;
         } else if (pp < d) {           // paired with the padding index: untouched
           partner[pp] = pp;
           rc[pp] = 1.0;
           rs[pp] = 0.0;
+          rotated[pp] = 0;
         }
       }
       sync();
-      // column pass: B = A J, Vn = Vc J
-      for (int t = tid; t < d * d; t += NT) {
-        const int i = t / d, x = t % d;
-        const int y = partner[x];
-        const double c_ = rc[x], s_ = rs[x];
-        B[i][x] = c_ * A[i][x] + s_ * A[i][y];
-        Vn[i][x] = c_ * Vc[i][x] + s_ * Vc[i][y];
-      }
-      sync();
-      // row pass: A = J^T B
+      // one pass: An = J^T Ac J (a rotated pair's 2x2 block takes the classical update:
+      // its diagonal dnew, its off-diagonal entry 0) and Vn = Vc J
       for (int t = tid; t < d * d; t += NT) {
         const int x = t / d, j = t % d;
-        const int y = partner[x];
-        A[x][j] = rc[x] * B[x][j] + rs[x] * B[y][j];
+        const int yx = partner[x], yj = partner[j];
+        const double cx = rc[x], sx = rs[x], cj = rc[j], sj = rs[j];
+        double v;
+        if (rotated[x] && j == x)
+          v = dnew[x];
+        else if (rotated[x] && j == yx)
+          v = 0.0;
+        else
+          v = cx * (cj * Ac[x][j] + sj * Ac[x][yj]) + sx * (cj * Ac[yx][j] + sj * Ac[yx][yj]);
+        An[x][j] = v;
+        Vn[x][j] = cj * Vc[x][j] + sj * Vc[x][yj];
       }
       sync();
-      if (rot) {
-        A[pp][pp] = app - tt * apq;
-        A[qq][qq] = aqq + tt * apq;
-        A[pp][qq] = 0.0;
-        A[qq][pp] = 0.0;
-      }
-      double (*sw)[kLd] = Vc;
+      double (*sw)[kLd] = Ac;
+      Ac = An;
+      An = sw;
+      sw = Vc;
       Vc = Vn;
       Vn = sw;
-      sync();
     }
   }
-  double (*Ac)[kLd] = A;
   // descending eigenvalue order (stable selection by one thread)
   if (tid == 0) {
     for (int a = 0; a < d; ++a) order[a] = a;
@@ -1050,15 +1055,12 @@ __global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(SmcShape sh, DevPa
   __shared__ int16_t mem[kMaxPerSounding];
   __shared__ double A[kDimMax][kLd];
   __shared__ double V0[kDimMax][kLd];
-  // member staging (64 rows) during the moments; column-pass buffers of A and V after
   __shared__ double T[2][kDimMax][kLd];
   __shared__ double mu[kDimMax];
   __shared__ double rc[kLd], rs[kLd];
-  __shared__ int s_ready;
+  __shared__ int s_nm;
   __shared__ int order[kDimMax];
-  static_assert(kWave * kLd <= 2 * kDimMax * kLd, "staging fits the column-pass buffers");
-  double (*X)[kLd] = reinterpret_cast<double (*)[kLd]>(&T[0][0][0]);
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int M = sh.n_models;
   const int s = blockIdx.x / M, m = blockIdx.x % M;
   const int N = (int)(p.n_per_sounding > 0 ? p.n_per_sounding : p.n);
@@ -1066,9 +1068,8 @@ __global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(SmcShape sh, DevPa
   const int k = m / (sh.km + 1), l = m % (sh.km + 1);
   const int d = 3 + 2 * k + 2 * l, D = sh.dmax;
   double *F = factors + (int64_t)blockIdx.x * D * D;
-  // members, mean and covariance on the first wave; the workgroup then decomposes
-  auto moments = [&]() -> bool {
-    // members in index order
+  // members in index order (first wave, by ballot)
+  if (wave == 0) {
     int nm = 0;
     for (int c0 = 0; c0 < N; c0 += kWave) {
       const int i = c0 + lane;
@@ -1077,62 +1078,39 @@ __global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(SmcShape sh, DevPa
       if (sel) mem[nm + __popcll(b & ((1ull << lane) - 1))] = (int16_t)i;
       nm += __popcll(b);
     }
-    wave_lds_sync();
-    for (int t = lane; t < D * D; t += kWave) F[t] = 0.0;
-    if (nm <= d) {
-      for (int a = lane; a < d; a += kWave) F[a * D + a] = 0.1 * prior_sd(pr, sh.z_max, k, l, a);
-      return false;
-    }
-    // mean: members staged 64 at a time, summed in index order by lane a
-    double acc_mu = 0.0;
-    for (int q0 = 0; q0 < nm; q0 += kWave) {
-      const int q = q0 + lane;
-      if (q < nm)
-        for (int a = 0; a < d; ++a) X[lane][a] = theta_get(p, off + mem[q], k, l, a);
-      wave_lds_sync();
-      const int nq = nm - q0 < kWave ? nm - q0 : kWave;
-      if (lane < d)
-        for (int r = 0; r < nq; ++r) acc_mu += X[r][lane];
-      wave_lds_sync();
-    }
-    if (lane < d) mu[lane] = acc_mu / (double)nm;
-    for (int t = lane; t < d * d; t += kWave) A[t / d][t % d] = 0.0;
-    wave_lds_sync();
-    // covariance: stage 64 centred members at a time
-    for (int q0 = 0; q0 < nm; q0 += kWave) {
-      const int q = q0 + lane;
-      if (q < nm)
-        for (int a = 0; a < d; ++a) X[lane][a] = theta_get(p, off + mem[q], k, l, a) - mu[a];
-      wave_lds_sync();
-      const int nq = nm - q0 < kWave ? nm - q0 : kWave;
-      for (int t = lane; t < d * d; t += kWave) {
-        const int a = t / d, b = t % d;
-        if (b < a) continue;
-        double acc = A[a][b];
-        for (int r = 0; r < nq; ++r) acc += X[r][a] * X[r][b];
-        A[a][b] = acc;
-      }
-      wave_lds_sync();
-    }
-    for (int t = lane; t < d * d; t += kWave) {
-      const int a = t / d, b = t % d;
-      if (b >= a) A[a][b] = A[a][b] / (double)(nm - 1);
-    }
-    wave_lds_sync();
-    for (int t = lane; t < d * d; t += kWave) {
-      const int a = t / d, b = t % d;
-      if (b < a) A[a][b] = A[b][a];
-      V0[a][b] = a == b ? 1.0 : 0.0;
-    }
-    wave_lds_sync();
-    return true;
-  };
-  if (wave == 0) {
-    const bool ok = moments();
-    if (lane == 0) s_ready = ok ? 1 : 0;
+    if (lane == 0) s_nm = nm;
   }
   __syncthreads();
-  if (!s_ready) return;
+  const int nm = s_nm;
+  const bool fallback = nm <= d;
+  // the factor is rewritten whole: zero, or the fallback's prior-scaled diagonal
+  for (int t = tid; t < D * D; t += kAdaptThreads) {
+    const int a = t / D;
+    F[t] = fallback && a < d && t == a * D + a ? 0.1 * prior_sd(pr, sh.z_max, k, l, a) : 0.0;
+  }
+  if (fallback) return;
+  // mean, members in index order (one thread per component)
+  for (int a = tid; a < d; a += kAdaptThreads) {
+    double acc = 0.0;
+    for (int q = 0; q < nm; ++q) acc += theta_get(p, off + mem[q], k, l, a);
+    mu[a] = acc / (double)nm;
+  }
+  __syncthreads();
+  // covariance, one thread per upper-triangle entry
+  for (int t = tid; t < d * d; t += kAdaptThreads) {
+    const int a = t / d, b = t % d;
+    if (b < a) continue;
+    const double ma = mu[a], mb = mu[b];
+    double acc = 0.0;
+    for (int q = 0; q < nm; ++q) {
+      const int64_t i = off + mem[q];
+      acc += (theta_get(p, i, k, l, a) - ma) * (theta_get(p, i, k, l, b) - mb);
+    }
+    A[a][b] = acc / (double)(nm - 1);
+    A[b][a] = A[a][b];
+  }
+  for (int t = tid; t < d * d; t += kAdaptThreads) V0[t / d][t % d] = t / d == t % d ? 1.0 : 0.0;
+  __syncthreads();
   eigen_factor<kAdaptThreads>(A, V0, T, rc, rs, order, d, D, F);
 }
 
