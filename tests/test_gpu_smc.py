@@ -101,13 +101,14 @@ def _check_reweight(B, ctx, p, ll, gamma, log_z, n_sound, nps):
     assert np.array_equal(ll_out.cpu().numpy(), ll[anc_ref])
 
 
-def test_reweight_resample_skewed_dead_and_full(B, ctx):
+@pytest.mark.parametrize("nps", [300, 2000])
+def test_reweight_resample_skewed_dead_and_full(B, ctx, nps):
     """Soundings that exercise the temperature search's edge cases: one model holding
-    95% of the members (its runs span six waves, so the per-wave carries chain), fewer
-    live members than alpha N (no increment passes: gamma stays), a nearly flat
-    likelihood (the full step passes), a model of a single member, and a ragged
-    population size."""
-    nps, n_sound = 2000, 4
+    95% of the members (at 2,000 per sounding its runs span six waves, so the per-wave
+    carries chain), fewer live members than alpha N (no increment passes: gamma stays),
+    a nearly flat likelihood (the full step passes), a model of a single member, and
+    ragged population sizes (both kernel instantiations)."""
+    n_sound = 4
     p, ll = _population_with_ll(n_sound, nps, 91)
     rng = np.random.default_rng(12)
     s0 = slice(0, nps)
@@ -118,7 +119,7 @@ def test_reweight_resample_skewed_dead_and_full(B, ctx):
     p["kappa"][s0][lone[1:]], p["lambda_"][s0][lone[1:]] = 1, 2
     assert len(lone) >= 1                            # model 0 now has a single member
     s1 = slice(nps, 2 * nps)
-    ll[s1][40:] = -np.inf                            # 40 live members < 0.5 N: increment 0
+    ll[s1][nps // 50:] = -np.inf                     # 2% live members < 0.5 N: increment 0
     s2 = slice(2 * nps, 3 * nps)
     ll[s2] = -1e-3 * rng.random(nps)                 # TESS(1 - gamma) stays above alpha N
     gamma = np.array([0.0, 0.25, 0.1, 0.9])
