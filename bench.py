@@ -392,6 +392,8 @@ def main():
                     help="time only the 65,536-particle log-likelihood gradient launches (for profiling)")
     ap.add_argument("--rjsmc-leg", default=None,
                     help="run only this RJSMC leg (e.g. single_sounding_256_tuned_graph) and print it (profiling)")
+    ap.add_argument("--precision", choices=("f64", "f32"), default="f64",
+                    help="precision of the headline forward (f32: the FP32 variant, for its profile)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before timing, as the "
                          "reference for hardware byte counters")
@@ -420,7 +422,7 @@ def main():
         print(json.dumps({args.rjsmc_leg: legs[args.rjsmc_leg](torch, synth_data(torch))}), flush=True)
         return
     system = W.system(kmax_cond=N_LAYERS - 1, kmax_charg=0)
-    ctx = B.Context(system, precision="f64")
+    ctx = B.Context(system, precision=args.precision)
     d = synth_data(torch)
     p = B.particles_to_device(W.merged_population(N_PARTICLES, N_LAYERS, seed=2, kc=N_LAYERS - 1))
     ll = torch.empty(N_PARTICLES, dtype=torch.float64, device="cuda")
@@ -431,18 +433,20 @@ def main():
     evals = N_PARTICLES / (ms * 1e-3)
     flop = nominal_flop_per_eval(N_LAYERS) * N_PARTICLES
     achieved = flop / (ms * 1e-3) / 1e12
+    f32 = args.precision == "f32"
+    peak = FP32_VECTOR_PEAK_TFLOPS if f32 else FP64_VECTOR_PEAK_TFLOPS
     out = {
         "metric": "forward+loglik evals/sec (65k particles, Cole-Cole); RJSMC soundings/sec",
         "value": evals, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": args.precision, "data": "synthetic",
         "config": {"workload": "forward+loglik, 65,536 five-layer Cole-Cole particles from the prior, "
-                               "40 frequencies x 120-point J1 filter x 20 gates, FP64",
+                               "40 frequencies x 120-point J1 filter x 20 gates, " + ("FP32" if f32 else "FP64"),
                    "particles": N_PARTICLES, "layers": N_LAYERS},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None if f32 else measured_traffic(),
                      "traffic_unit": "HBM bytes per launch",
-                     "kernel": "forward_kernel<double,4,1>", "flop_per_launch": flop},
+                     "kernel": "forward_kernel<%s,4,1>" % ("float" if f32 else "double"), "flop_per_launch": flop},
         "wall_s_timed": wall,
     }
     if args.headline_only:
@@ -451,7 +455,9 @@ def main():
     if args.extra:
         ctx32 = B.Context(system, precision="f32")
         ms32, _ = time_calls(lambda: ctx32.loglik(p, d, out=ll), args.steps, args.warmup, torch)
-        out["fp32"] = {"evals_per_s": N_PARTICLES / (ms32 * 1e-3), "ms_per_step": ms32}
+        a32 = flop / (ms32 * 1e-3) / 1e12
+        out["fp32"] = {"evals_per_s": N_PARTICLES / (ms32 * 1e-3), "ms_per_step": ms32,
+                       "nominal_tflops": a32, "frac_of_fp32_peak": a32 / FP32_VECTOR_PEAK_TFLOPS}
     if args.extra:
         out["adjoint"] = adjoint_rate(torch, d, max(3, args.steps // 4), 1)
         out["reweight_resample_2000x2048"] = reweight_rate(torch, d, max(3, args.steps // 4), 1)
