@@ -965,7 +965,7 @@ __device__ __forceinline__ void eigen_factor(double (*A)[kLd], double (*V0)[kLd]
       }
       __syncthreads();
     }
-    if (!(offn > 1e-30 * diag)) break;
+    if (!(offn > 1e-24 * diag)) break;
     for (int round = 0; round < nn - 1; ++round) {
       // pair `tid` of this round: (nn-1, round) and ((round + j) mod (nn-1), (round - j) mod (nn-1))
       if (tid < np) {
@@ -978,9 +978,11 @@ __device__ __forceinline__ void eigen_factor(double (*A)[kLd], double (*V0)[kLd]
           const bool rot = apq != 0.0;
           if (rot) {
             const double app = Ac[pp][pp], aqq = Ac[qq][qq];
-            const double theta = (aqq - app) / (2.0 * apq);
-            const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            cth = 1.0 / sqrt(tt * tt + 1.0);
+            // t = tan of the rotation angle, the smaller root of t^2 + 2 theta t - 1 = 0 with
+            // theta = (aqq - app) / (2 apq), written without forming theta
+            const double dd = aqq - app;
+            const double tt = (dd >= 0.0 ? 2.0 : -2.0) * apq / (fabs(dd) + sqrt(fma(dd, dd, 4.0 * apq * apq)));
+            cth = rsqrt(fma(tt, tt, 1.0));
             sth = tt * cth;
             dnew[pp] = app - tt * apq;
             dnew[qq] = aqq + tt * apq;
