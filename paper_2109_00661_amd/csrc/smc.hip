@@ -1488,7 +1488,11 @@ __device__ bool zca_move(double *th, int &k, int &l, bool birth, int part, doubl
 
 // Proposal of move `move` for every particle (type from draw_types_kernel): written to
 // `prop`; mask[i] = 1 if the proposal needs a likelihood, 2 if it needs a likelihood and
-// a gradient, 0 if it is rejected outright.
+// a gradient, 0 if it is rejected outright.  MALA / ZCA: whether the launch can hold
+// gradient-informed moves / the adaptive birth (without them their branches, and the
+// private arrays they need, are compiled out; a particle drawn for an excluded move is
+// rejected).
+template <bool MALA, bool ZCA>
 __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_args a, int move, DevParticles st,
                                                       DevParticlesW prop, int32_t *mask, int32_t *type,
                                                       const double *gamma, DevParticles gcur, int32_t *gvalid,
@@ -1533,7 +1537,7 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
   const bool jump = t == RJSMC_MOVE_SIGMA_BIRTH || t == RJSMC_MOVE_M_BIRTH || t == RJSMC_MOVE_SIGMA_DEATH ||
                     t == RJSMC_MOVE_M_DEATH;
   if (lq) lq[i] = 0.0;
-  if (a.zca_birth && jump) {
+  if (ZCA && a.zca_birth && jump) {
     const bool birth = t == RJSMC_MOVE_SIGMA_BIRTH || t == RJSMC_MOVE_M_BIRTH;
     const int part = t == RJSMC_MOVE_SIGMA_BIRTH || t == RJSMC_MOVE_SIGMA_DEATH ? 0 : 1;
     if (!birth || (part == 0 ? k < kc : l < km)) {
@@ -1637,7 +1641,7 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
     for (int j = 0; j < l; ++j)
       ok = ok && in_range(mm[j], pr.m_lo, pr.m_hi) && zm[j] > 0.0 && zm[j] < sh.z_max &&
            (j == 0 || zm[j] > zm[j - 1]);
-  } else if (t == RJSMC_MOVE_WITHIN_MALA) {
+  } else if (MALA && t == RJSMC_MOVE_WITHIN_MALA) {
     const int d = 3 + 2 * k + 2 * l, D = sh.dmax;
     const int mdl = k * (km + 1) + l;
     const double *Fm = a.factors + (snd * sh.n_models + mdl) * (int64_t)D * D;   // F[a][r] = Fm[r D + a]
@@ -1806,8 +1810,19 @@ hipError_t launch_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int mo
                           bool draw, hipStream_t stream) {
   const int64_t blocks = (state.n + 255) / 256;
   const DevParticles g = grad_cur ? *grad_cur : DevParticles();
-  hipLaunchKernelGGL(propose_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, sh, a, move, state, prop, mask,
-                     type, gamma, g, gvalid, lq, active, draw ? 1 : 0);
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(256), 0, stream, sh, a, move, state, prop, mask, type,
+                       gamma, g, gvalid, lq, active, draw ? 1 : 0);
+  };
+  const bool mala = grad_cur != nullptr, zca = a.zca_birth != 0;
+  if (mala && zca)
+    go(propose_kernel<true, true>);
+  else if (mala)
+    go(propose_kernel<true, false>);
+  else if (zca)
+    go(propose_kernel<false, true>);
+  else
+    go(propose_kernel<false, false>);
   return hipGetLastError();
 }
 
