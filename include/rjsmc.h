@@ -191,7 +191,10 @@ typedef struct {
 /* Re-weight and re-sample every sounding (Algorithm 1; Section 3.2.1; Appendices C, D):
  *  - the temperature increment dg is 1 - gamma if the total effective sample size
  *    TESS(dg) = sum_k (sum_{i in k} w_i)^2 / sum_{i in k} w_i^2, w_i = exp(dg ll_i), stays
- *    >= alpha N; otherwise 60 bisection steps on (0, 1 - gamma] keep the lower bracket;
+ *    >= alpha N; otherwise 60 bisection steps on (0, 1 - gamma] keep the lower bracket
+ *    (TESS does not increase with dg, so the kernel evaluates it only at the midpoints
+ *    inside a bracket it first narrows by Newton steps; the other decisions follow from
+ *    the bracket ends).  A particle with ll = -inf has weight 0, also when dg = 0;
  *  - log_z[s][k] += logsumexp_{i in k}(dg ll_i) - ln N_k for every populated model;
  *    a model with no member has an empty sum of incremental weights, so its estimate
  *    (a product over steps) is 0 from then on: log_z[s][k] = -inf;
