@@ -618,9 +618,8 @@ __device__ __forceinline__ void copy_resampled(const SM &sm, const DevParticles 
 
 // One workgroup per sounding: re-weight, evidence, within-model resampling, and the
 // resampled population written to out (each particle copied from its ancestor).  SMALL:
-// at most 512 particles per sounding, so runs are single members and a search round takes
-// three halvings; otherwise one or two (the seven-point rounds need registers that would
-// halve the occupancy of the large-population launch).
+// at most 512 particles per sounding, so every run is a single member (the evaluation
+// code is then compiled for runs of one).
 template <bool SMALL>
 __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape sh, rjsmc_reweight_args a,
                                                                        DevParticles in, const double *ll_in,
