@@ -435,7 +435,12 @@ __device__ double next_increment(SM &sm, const RunLane &r, double H, double targ
       step = un - u;
       break;
     }
-    if (!(un > ua && un < ub)) un = 0.5 * (ua + ub);   // outside the bracket, or NaN
+    if (!(un > ua && un < ub)) {                 // outside the bracket, or NaN: before any
+      // point has passed, step 10 below the failing end (increments within e^10 of the
+      // remaining step are the common case), else halve the bracket geometrically
+      const double down = ub - 10.0;
+      un = a == 0.0 && down > 0.5 * (ua + ub) ? down : 0.5 * (ua + ub);
+    }
     const double dn = exp_tab(un, sm.e2);      // un < ub <= 0
     if (!(dn > a && dn < b)) break;             // no representable point left inside
     const double dd[1] = {dn};
