@@ -12,13 +12,14 @@ namespace rjsmc {
 //   R_{l,l+1} = (k2_l - k2_{l+1}) / (u_l + u_{l+1})^2,   R_air = -k2_0 / (lam + u_0)^2,
 //   r_l = (R_{l,l+1} + r_{l+1} E_{l+1}) / (1 + R_{l,l+1} r_{l+1} E_{l+1}),
 //   E_l = exp(-2 u_l h_l),  u_l = sqrt(lam^2 + k2_l), Re u_l > 0,
-// is carried in projective form: with R = A/B (A = k2_l - k2_{l+1}, B = (u_l+u_{l+1})^2)
-// and r = N/D,
-//   N_l = A D_{l+1} + B N_{l+1} E_{l+1},   D_l = B D_{l+1} + A N_{l+1} E_{l+1},
-// so the whole stack needs one real division (Im r = Im(N conj D) / |D|^2) instead of
-// two complex divisions per layer.  No lam - u or u_l - u_{l+1} is ever formed.
-// FP64 keeps N, D unscaled (|D| stays within 1e-140 .. 1e30 for <= 16 layers of this
-// system); FP32 rescales by a power of two every layer.
+// is carried in projective form, r = N/D: the deepest interface starts from
+// N = k2_{L-2} - k2_{L-1}, D = (u_{L-2} + u_{L-1})^2 (R without a difference of nearly
+// equal u), and every interface above takes step_up (R = (u_l - u_{l+1})/(u_l + u_{l+1}),
+// two complex products), so the whole stack needs one real division
+// (Im r = Im(N conj D) / |D|^2) instead of two complex divisions per layer.
+// FP64 keeps N, D unscaled (each step multiplies them by about |u|, so |D| stays far
+// inside the FP64 range for <= 16 layers of this system); FP32 rescales by a power of
+// two every layer.
 template <typename T>
 __device__ __forceinline__ void rescale(cplx<T> &N, cplx<T> &D) {}
 template <>
@@ -29,11 +30,20 @@ __device__ __forceinline__ void rescale<float>(cplx<float> &N, cplx<float> &D) {
   D = {ldexpf(D.re, e), ldexpf(D.im, e)};
 }
 
-// a b + c d with one multiplication and three fused multiply-adds per component.
+// One interface upwards in projective form, with a = u above and b = u below it:
+// R = (a - b) / (a + b), and r_above = (R + r E) / (1 + R r E) for r = N / D becomes
+//   N' = a S - b T,  D' = a S + b T,  S = D + N E,  T = D - N E
+// (the common factor a + b dropped): two complex products instead of four, and neither
+// the interface numerator nor (a + b)^2 is formed.  a - b never appears explicitly; for
+// nearly equal a and b the D-part of N' is the difference of a S and b T, accurate to a
+// rounding of |b D| absolute, i.e. to ~1e-16 in r.
 template <typename T>
-__device__ __forceinline__ cplx<T> cmul2add(cplx<T> a, cplx<T> b, cplx<T> c, cplx<T> d) {
-  return {fma(a.re, b.re, fma(-a.im, b.im, fma(c.re, d.re, -(c.im * d.im)))),
-          fma(a.re, b.im, fma(a.im, b.re, fma(c.re, d.im, c.im * d.re)))};
+__device__ __forceinline__ void step_up(cplx<T> &N, cplx<T> &D, cplx<T> a, cplx<T> b, cplx<T> E) {
+  const cplx<T> NE = N * E;
+  const cplx<T> S = D + NE, Tm = D - NE;
+  const cplx<T> P = a * S, Q = b * Tm;
+  N = P - Q;
+  D = P + Q;
 }
 
 // Propagation factor exp(-2 h u): table-assisted in FP64, polynomial in FP32.
@@ -72,24 +82,13 @@ __device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const cplx<
     for (int l = L - 3; l >= 0; --l) {
       const cplx<T> kl = k2[l];
       const cplx<T> u = csqrt_fast(cplx<T>{lam2 + kl.re, kl.im});
-      const cplx<T> A = dk2[l];
-      const cplx<T> B = csq(u + ub);
       const T hh = h2[l + 1];
-      const cplx<T> NE = N * prop_exp(cplx<T>{hh * ub.re, hh * ub.im}, phase, e2);
-      const cplx<T> Nn = cmul2add(A, D, B, NE);
-      D = cmul2add(B, D, A, NE);
-      N = Nn;
+      step_up(N, D, u, ub, prop_exp(cplx<T>{hh * ub.re, hh * ub.im}, phase, e2));
       rescale(N, D);
       ub = u;
     }
-    const cplx<T> k0 = k2[0];
-    const cplx<T> A0 = {-k0.re, -k0.im};
-    const cplx<T> B0 = csq(cplx<T>{lam + ub.re, ub.im});
     const T hh = h2[0];
-    const cplx<T> NE = N * prop_exp(cplx<T>{hh * ub.re, hh * ub.im}, phase, e2);
-    const cplx<T> Nn = cmul2add(A0, D, B0, NE);
-    D = cmul2add(B0, D, A0, NE);
-    N = Nn;
+    step_up(N, D, cplx<T>{lam, T(0)}, ub, prop_exp(cplx<T>{hh * ub.re, hh * ub.im}, phase, e2));
   }
   return (N.im * D.re - N.re * D.im) * fast_rcp(D.re * D.re + D.im * D.im);
 }
