@@ -3,12 +3,11 @@
 // One wavefront per particle, lanes tiling (frequency, filter abscissa) as in the
 // forward kernel.  Phase A evaluates the forward model to obtain y, ll and
 // w_j = d ll / d Im H(w_j) = sum_g K_gj d ll / d y_g.  Phase B revisits every pair: it runs
-// the reflection recursion bottom-up in the classic form, keeping the generalized
-// reflection coefficients r_l of each layer in a per-lane array (in registers up to 8
-// merged layers; above, runtime layer loops over arrays in the wave's private memory,
-// which keeps the register count low enough for two waves per SIMD), then sweeps
-// top-down through the air interface and
-// every layer, propagating the adjoint of c_k w_j Im r and accumulating, per lane and
+// the projective reflection recursion bottom-up, keeping the state (N_l, D_l) of every
+// interface in a per-lane array (in registers up to 8 merged layers; above, runtime layer
+// loops over arrays in the wave's private memory, which keeps the register count low
+// enough for two waves per SIMD), then sweeps top-down through the surface and every
+// interface, propagating the adjoint of c_k w_j Im r and accumulating, per lane and
 // frequency, the complex adjoints of the layer wavenumbers
 // k2_l = i w mu0 sigma_hat_l and the adjoints of the thicknesses.  The u_l and E_l of the
 // recursion are recomputed in the sweep instead of stored.  Per frequency the adjoints
@@ -40,115 +39,118 @@ __device__ __forceinline__ cplx<double> crcp_fast(cplx<double> b) {
 __device__ __forceinline__ cplx<double> cdiv_fast(cplx<double> a, cplx<double> b) { return a * crcp_fast(b); }
 
 // Adds the adjoints of one (lam, w) pair with seed wt (the weight of Im r) to
-// G[l] (d(wt r)/d k2_l) and H[l] (Im d(wt r)/d h_l); runtime layer loops.
+// G[l] (d(wt r)/d k2_l) and H[l] (Im d(wt r)/d h_l).  The bottom-up pass is the forward's
+// projective recursion (step_up), keeping the state (N_l, D_l) of every interface; the
+// top-down pass applies the adjoint of each step: for N' = a S - b T, D' = a S + b T,
+// S = D + N E, T = D - N E and output adjoints N'~, D'~,
+//   P~ = N'~ + D'~,  Q~ = D'~ - N'~,  a~ += P~ S,  b~ += Q~ T,
+//   S~ = P~ a,  T~ = Q~ b,  D~ = S~ + T~,  N~ = (S~ - T~) E,  E~ = (S~ - T~) N,
+// with E = exp(h2 u) (h2 = -2 h): u~ += E~ h2 E and h~ = -2 u E~ E.  The seed is
+// N~ = wt / D, D~ = -N~ N / D at the surface, and u_l = sqrt(lam^2 + k2_l) gives
+// k2_l~ += u_l~ / (2 u_l).  One complex reciprocal per pair and one per layer; u_l and
+// E_l are recomputed in the top-down pass instead of stored.
 template <int LMAX>
-__device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2, const double *thk, int L,
+__device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2, const double *h2v, int L,
                                              double wt, cplx<double> (&G)[LMAX], double (&H)[LMAX],
                                              const cplx<double> *phase, const double *e2) {
   const double lam2 = lam * lam;
-  cplx<double> rt[LMAX];            // generalized reflection coefficient below interface l
   // Up to 8 layers the layer loops are unrolled over LMAX with a wave-uniform guard, so
-  // rt, G and H stay in registers (measured 9% faster on 1-8 layers); with 16 the
-  // registers would halve the occupancy (measured 27% slower), so the loops stay runtime
-  // loops over arrays in private memory.
+  // the stored states, G and H stay in registers; with 16 the loops stay runtime loops
+  // over arrays in private memory (the registers would halve the occupancy).
   constexpr bool kUnrolled = LMAX <= 8;
-  // ---- bottom-up recursion, classic form
-  {
-    cplx<double> ub = csqrt_fast(cplx<double>{lam2 + k2[L - 1].re, k2[L - 1].im});
-#pragma unroll
-    for (int l = kUnrolled ? LMAX - 2 : L - 2; l >= 0; --l) {
-      if (!kUnrolled || l <= L - 2) {
-        const cplx<double> u = csqrt_fast(cplx<double>{lam2 + k2[l].re, k2[l].im});
-        const cplx<double> R = cdiv_fast(k2[l] - k2[l + 1], csq(u + ub));
-        if (l == L - 2) {
-          rt[l] = R;
-        } else {
-          const double h2 = -2.0 * thk[l + 1];
-          const cplx<double> E = cexp_tab(cplx<double>{h2 * ub.re, h2 * ub.im}, phase, e2);
-          const cplx<double> rho = rt[l + 1] * E;
-          rt[l] = cdiv_fast(R + rho, cplx<double>{1.0, 0.0} + R * rho);
-        }
-        ub = u;
-      }
-    }
-  }
-  // ---- top-down adjoint sweep
-  const cplx<double> one = {1.0, 0.0};
-  cplx<double> ul = csqrt_fast(cplx<double>{lam2 + k2[0].re, k2[0].im});   // u_0
-  const cplx<double> Bair = csq(cplx<double>{lam + ul.re, ul.im});
-  const cplx<double> Aair = {-k2[0].re, -k2[0].im};
-  const cplx<double> Rair = cdiv_fast(Aair, Bair);
-  cplx<double> Rbar_air, rtbar = {0.0, 0.0}, ubar = {0.0, 0.0};
-  const cplx<double> wb = {wt, 0.0};
+  constexpr int NI = LMAX - 1;           // interfaces below the surface
+  cplx<double> Ns[NI], Ds[NI];           // projective reflection state below interface l
+  auto u_of = [&](int l) { return csqrt_fast(cplx<double>{lam2 + k2[l].re, k2[l].im}); };
+  auto half_rcp = [](cplx<double> u) { return crcp_fast(2.0 * u); };
   if (L == 1) {
-    Rbar_air = wb;
-  } else {
-    const double h2 = -2.0 * thk[0];
-    const cplx<double> E = cexp_tab(cplx<double>{h2 * ul.re, h2 * ul.im}, phase, e2);
-    const cplx<double> rho = rt[0] * E;
-    const cplx<double> den = one + Rair * rho;
-    const cplx<double> iden2 = crcp_fast(csq(den));
-    Rbar_air = wb * (one - csq(rho)) * iden2;
-    const cplx<double> rhobar = wb * (one - csq(Rair)) * iden2;
-    rtbar = rhobar * E;
-    const cplx<double> Ebar = rhobar * rt[0];
-    ubar = Ebar * (h2 * E);                                       // dE/du = -2 h E
-    const cplx<double> hb = Ebar * (-2.0 * (ul * E));             // dE/dh = -2 u E
-    H[0] += hb.im;
-  }
-  // R_air = A / B, A = -k2_0, B = (lam + u_0)^2
-  const cplx<double> Abar_air = cdiv_fast(Rbar_air, Bair);
-  const cplx<double> Bbar_air = {-(Rbar_air * Rair).re, -(Rbar_air * Rair).im};
-  cplx<double> kbar = {-Abar_air.re, -Abar_air.im};               // adjoint of k2_0 (partial)
-  ubar = ubar + cdiv_fast(Bbar_air, Bair) * (2.0 * cplx<double>{lam + ul.re, ul.im});
-  if (L == 1) {
-    kbar = kbar + cdiv_fast(ubar, 2.0 * ul);                      // u_0 = sqrt(lam^2 + k2_0)
-    G[0] = G[0] + kbar;
+    // r = -k2_0 / (lam + u_0)^2
+    const cplx<double> u0 = u_of(0);
+    const cplx<double> s = {lam + u0.re, u0.im};
+    const cplx<double> D = csq(s);
+    const cplx<double> iD = crcp_fast(D);
+    const cplx<double> Nb = wt * iD;
+    const cplx<double> r = cplx<double>{-k2[0].re, -k2[0].im} * iD;
+    const cplx<double> Db = {-(Nb * r).re, -(Nb * r).im};
+    const cplx<double> ub = Db * (2.0 * s);
+    G[0] = G[0] + (ub * half_rcp(u0) - Nb);
     return;
   }
+  // ---- bottom-up: the deepest interface, then step_up through every interface above
+  cplx<double> ua = u_of(L - 2);
+  cplx<double> N = k2[L - 2] - k2[L - 1], D = csq(ua + u_of(L - 1));
 #pragma unroll
-  for (int l = 0; l <= (kUnrolled ? LMAX - 2 : L - 2); ++l) {
+  for (int l = kUnrolled ? NI - 1 : L - 2; l >= 0; --l) {
     if (!kUnrolled || l <= L - 2) {
-      const cplx<double> un = csqrt_fast(cplx<double>{lam2 + k2[l + 1].re, k2[l + 1].im});   // u_{l+1}
-      const cplx<double> s = ul + un;
-      const cplx<double> B = csq(s);
-      const cplx<double> A = k2[l] - k2[l + 1];
-      const cplx<double> iB = crcp_fast(B);
-      const cplx<double> R = A * iB;
-      cplx<double> Rbar, rtbar_n = {0.0, 0.0}, ubar_n = {0.0, 0.0};
-      if (l == L - 2) {
-        Rbar = rtbar;
-      } else {
-        const double h2 = -2.0 * thk[l + 1];
-        const cplx<double> E = cexp_tab(cplx<double>{h2 * un.re, h2 * un.im}, phase, e2);
-        const cplx<double> rho = rt[l + 1] * E;
-        const cplx<double> iden2 = crcp_fast(csq(one + R * rho));
-        Rbar = rtbar * (one - csq(rho)) * iden2;
-        const cplx<double> rhobar = rtbar * (one - csq(R)) * iden2;
-        rtbar_n = rhobar * E;
-        const cplx<double> Ebar = rhobar * rt[l + 1];
-        ubar_n = Ebar * (h2 * E);
-        const cplx<double> hb = Ebar * (-2.0 * (un * E));
-        H[l + 1] += hb.im;
+      if (l < L - 2) {
+        const cplx<double> u = u_of(l);
+        const double hh = h2v[l + 1];
+        step_up(N, D, u, ua, cexp_tab(cplx<double>{hh * ua.re, hh * ua.im}, phase, e2));
+        ua = u;
       }
-      // R = A / B
-      const cplx<double> Abar = Rbar * iB;
-      const cplx<double> Bbar = {-(Abar * R).re, -(Abar * R).im};
-      const cplx<double> sb = Bbar * (2.0 * s);                   // B = s^2
-      kbar = kbar + Abar;                                          // A = k2_l - k2_{l+1}
-      ubar = ubar + sb;
-      ubar_n = ubar_n + sb;
-      kbar = kbar + cdiv_fast(ubar, 2.0 * ul);                     // u_l complete
-      G[l] = G[l] + kbar;
-      kbar = {-Abar.re, -Abar.im};                                 // partial adjoint of k2_{l+1}
-      ubar = ubar_n;
-      ul = un;
-      rtbar = rtbar_n;
-      if (l == L - 2) {                                            // basement complete
-        kbar = kbar + cdiv_fast(ubar, 2.0 * ul);
-        G[l + 1] = G[l + 1] + kbar;
-      }
+      Ns[l] = N;
+      Ds[l] = D;
     }
+  }
+  // surface: a = lam, b = u_0
+  const cplx<double> u0 = ua;
+  const cplx<double> E0 = cexp_tab(cplx<double>{h2v[0] * u0.re, h2v[0] * u0.im}, phase, e2);
+  step_up(N, D, cplx<double>{lam, 0.0}, u0, E0);
+  // ---- top-down adjoint
+  const cplx<double> iD = crcp_fast(D);
+  cplx<double> Nb = wt * iD;
+  cplx<double> Db = Nb * (N * iD);
+  Db = {-Db.re, -Db.im};
+  cplx<double> uab;                      // adjoint of u of the layer above the interface
+  {
+    const cplx<double> NE = Ns[0] * E0;
+    const cplx<double> T = Ds[0] - NE;
+    const cplx<double> Pb = Nb + Db, Qb = Db - Nb;
+    const cplx<double> Sb = lam * Pb, Tb = Qb * u0;
+    uab = Qb * T;
+    Db = Sb + Tb;
+    const cplx<double> NEb = Sb - Tb;
+    Nb = NEb * E0;
+    const cplx<double> EbE = (NEb * Ns[0]) * E0;
+    uab = uab + h2v[0] * EbE;
+    H[0] += -2.0 * (EbE * u0).im;
+  }
+  ua = u0;
+#pragma unroll
+  for (int l = 0; l < (kUnrolled ? NI - 1 : L - 2); ++l) {
+    if (!kUnrolled || l < L - 2) {
+      // the step that made state l from state l + 1: a = u_l, b = u_{l+1}, E_{l+1}
+      const cplx<double> ub = u_of(l + 1);
+      const double hh = h2v[l + 1];
+      const cplx<double> E = cexp_tab(cplx<double>{hh * ub.re, hh * ub.im}, phase, e2);
+      const cplx<double> NE = Ns[l + 1] * E;
+      const cplx<double> S = Ds[l + 1] + NE, T = Ds[l + 1] - NE;
+      const cplx<double> Pb = Nb + Db, Qb = Db - Nb;
+      uab = uab + Pb * S;
+      G[l] = G[l] + uab * half_rcp(ua);                            // u_l complete
+      const cplx<double> Sb = Pb * ua, Tb = Qb * ub;
+      Db = Sb + Tb;
+      const cplx<double> NEb = Sb - Tb;
+      Nb = NEb * E;
+      const cplx<double> EbE = (NEb * Ns[l + 1]) * E;
+      uab = Qb * T + hh * EbE;
+      H[l + 1] += -2.0 * (EbE * ub).im;
+      ua = ub;
+    }
+  }
+  // the deepest interface: N = k2_{L-2} - k2_{L-1}, D = (u_{L-2} + u_{L-1})^2
+  const cplx<double> ul = u_of(L - 1);
+  const cplx<double> sb = Db * (2.0 * (ua + ul));
+  const cplx<double> g0 = Nb + (uab + sb) * half_rcp(ua), g1 = sb * half_rcp(ul) - Nb;
+  if (kUnrolled) {
+#pragma unroll
+    for (int l = 0; l < NI; ++l)     // compile-time indices keep G in registers
+      if (l == L - 2) {
+        G[l] = G[l] + g0;
+        G[l + 1] = G[l + 1] + g1;
+      }
+  } else {
+    G[L - 2] = G[L - 2] + g0;
+    G[L - 1] = G[L - 1] + g1;
   }
 }
 
@@ -165,7 +167,6 @@ struct AdjShared {
   double ybar[kWavesA][kMaxGate];
   cplx<double> k2[kWavesA][8][kMaxLayers];
   cplx<double> dk2[kWavesA][8][kMaxLayers];
-  double thk[kWavesA][kMaxLayers];
   double h2[kWavesA][kMaxLayers];
   double slot[kWavesA][8][3 * LMAX + 2];
   double gl[kWavesA][3 * LMAX + 2];
@@ -206,10 +207,7 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
     c = p.c[i];
     log_tau = p.log10_tau[i] * kLn10;
     sincospi(0.5 * c, &spc, &cpc);
-    if (lane < L - 1) {
-      sm.thk[wave][lane] = st->top[lane + 1] - st->top[lane];
-      sm.h2[wave][lane] = -2.0 * (st->top[lane + 1] - st->top[lane]);
-    }
+    if (lane < L - 1) sm.h2[wave][lane] = -2.0 * (st->top[lane + 1] - st->top[lane]);
   }
   const int gl = lane & 7, gw = lane >> 3;
   const int nhg = nhp >> 3;
@@ -314,7 +312,7 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
 #pragma unroll 1
       for (int sidx = 0; sidx < nhg; ++sidx) {
         const int k = gl + 8 * sidx;
-        pair_adjoint<LMAX>(sm.lam[k], sm.k2[wave][gw], sm.thk[wave], L, sm.ck[k] * wj, G, H, sm.phase,
+        pair_adjoint<LMAX>(sm.lam[k], sm.k2[wave][gw], sm.h2[wave], L, sm.ck[k] * wj, G, H, sm.phase,
                            sm.exp2t);
       }
 #pragma unroll

@@ -64,6 +64,24 @@ def test_grad_decoupled_up_to_fifteen_layers(B, K_oracle, truth_data):
     _check_against_oracle(p, ll, g, ll_o, g_o)
 
 
+@pytest.mark.parametrize("kmax", [(2, 1), (4, 3)])
+def test_grad_decoupled_register_path(B, K_oracle, truth_data, kmax):
+    """Capacities of 4 and 8 merged layers (the kernels that keep the per-layer state
+    in registers), every layer count from the half-space up."""
+    from oracle import em
+    kc, km = kmax
+    system = W.system(kmax_cond=kc, kmax_charg=km)
+    ctx = B.Context(system, precision="f64")
+    n = 3 * (kc + 1) * (km + 1)
+    kap = np.tile(np.repeat(np.arange(kc + 1), km + 1), 3)
+    lam = np.tile(np.arange(km + 1), 3 * (kc + 1))
+    p = W.decoupled_population(n, kc, km, seed=17, min_sep=1.0, kappa=kap, lam=lam)
+    ll, g, llp = _grad_gpu(B, ctx, p, truth_data)
+    np.testing.assert_allclose(ll, llp, rtol=1e-12, atol=0)
+    ll_o, g_o = em.loglik_grad(p, system, K_oracle, truth_data)
+    _check_against_oracle(p, ll, g, ll_o, g_o)
+
+
 def test_grad_full_size_sampled(B, K_oracle, truth_data):
     """65,536 decoupled particles with 1-8 segments per partition (the adjoint
     workload); 6 sampled particles against the oracle, all finite."""
