@@ -82,6 +82,30 @@ def test_grad_decoupled_register_path(B, K_oracle, truth_data, kmax):
     _check_against_oracle(p, ll, g, ll_o, g_o)
 
 
+def test_grad_same_particles_under_both_capacities(B, truth_data):
+    """The register path (capacity 8) and the private-memory path (capacity 16) give the
+    same log-likelihood and gradient for the same particles (to rounding)."""
+    kc, km = 4, 3
+    p = W.decoupled_population(200, kc, km, seed=29, min_sep=1.0)
+    wide = W.empty_particles(200, 7, 7)
+    for k, src in p.items():
+        if not isinstance(src, np.ndarray):
+            continue
+        if src.ndim == 2:
+            wide[k][:src.shape[0]] = src
+        else:
+            wide[k][:] = src
+    res = []
+    for (a, b), q in (((kc, km), p), ((7, 7), wide)):
+        ctx = B.Context(W.system(kmax_cond=a, kmax_charg=b), precision="f64")
+        ll, g, _ = _grad_gpu(B, ctx, q, truth_data)
+        res.append((ll, np.concatenate([g[k][:{"phi": kc, "z_cond": kc, "m": km, "z_charg": km}[k]].ravel()
+                                        if g[k].ndim == 2 else g[k] for k in FKEYS])))
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    scale = np.abs(res[0][1]).max()
+    assert np.abs(res[0][1] - res[1][1]).max() <= 1e-12 * scale
+
+
 def test_grad_full_size_sampled(B, K_oracle, truth_data):
     """65,536 decoupled particles with 1-8 segments per partition (the adjoint
     workload); 6 sampled particles against the oracle, all finite."""
