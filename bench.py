@@ -369,8 +369,16 @@ def adjoint_rate(torch, d, steps, warmup):
     ms, _ = time_calls(lambda: ctx.loglik_grad(dp, d), steps, warmup, torch)
     ms_f, _ = time_calls(lambda: ctx.loglik(dp, d), steps, warmup, torch)
     ctx.check()
+    # the default prior (at most 4 conductivity and 3 chargeability interfaces, so at most
+    # 8 merged layers): the register-resident instantiation of the reverse sweep
+    ctx8 = B.Context(W.system(), precision="f64", max_particles=n)
+    p8 = B.empty_device_population(n, ctx8.kmax_cond, ctx8.kmax_charg)
+    ctx8.init_prior(p8, W.PRIOR, 5)
+    ms8, _ = time_calls(lambda: ctx8.loglik_grad(p8, d), steps, warmup, torch)
+    ctx8.check()
     return {"grad_evals_per_s": n / (ms * 1e-3), "ms_per_launch": ms, "forward_ms_same_population": ms_f,
-            "grad_over_forward": ms / ms_f, "mean_merged_layers": float((p["kappa"] + p["lambda_"] + 1).mean())}
+            "grad_over_forward": ms / ms_f, "mean_merged_layers": float((p["kappa"] + p["lambda_"] + 1).mean()),
+            "prior_population_ms_per_launch": ms8}
 
 
 def main():
