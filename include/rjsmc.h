@@ -48,7 +48,7 @@ typedef enum {
  * and the log-likelihood in FP64; outputs are FP64 either way. */
 typedef enum { RJSMC_F64 = 0, RJSMC_F32 = 1 } rjsmc_precision;
 
-/* Particle layouts (paper, Section 2.2 and Fig. 2).
+/* Particle layouts (paper, Section 2.1 and Fig. 2).
  * DECOUPLED: two change-point partitions -- kappa conductivity interfaces and lambda
  *   chargeability interfaces -- merged by a direct sum before the forward model.
  * MERGED: one layered model of L = kappa + 1 layers, each with its own conductivity
@@ -145,8 +145,10 @@ rjsmc_status rjsmc_forward(rjsmc_ctx *ctx, const rjsmc_particles *p, double *res
 rjsmc_status rjsmc_loglik(rjsmc_ctx *ctx, const rjsmc_particles *p, const double *y_obs,
                           double *ll, rjsmc_stream stream);
 
-/* Log-likelihood and its gradient with respect to every continuous parameter of each
- * particle (phi_b, phi, z_cond, m, z_charg, log10_tau, c), by a reverse sweep through
+/* Log-likelihood of Section 2.3.2 and its gradient with respect to every continuous
+ * parameter of the particle vector of Section 2.3.1 (phi_b, phi, z_cond, m, z_charg,
+ * log10_tau, c): the local derivative information of the gradient-informed within-model
+ * proposals that Section 3 cites (Langevin, Riemann-manifold samplers).  By a reverse sweep through
  * the log-likelihood, time transform, Hankel filter, reflection recursion, Cole-Cole
  * terms and the merge.  `grad` has the particle layout and shapes (its count and
  * layout fields are ignored); slots outside each particle's counts are written 0.
@@ -212,7 +214,7 @@ rjsmc_status rjsmc_reweight_resample(rjsmc_ctx *ctx, const rjsmc_reweight_args *
                                      double *log_z, int32_t *active, int32_t *ancestors,
                                      rjsmc_stream stream);
 
-/* Proposal factors of the within-model move (Section 3.2.3).  For every (sounding,
+/* Proposal factors of the within-model move (Section 3.2.2).  For every (sounding,
  * model) with more members than dimensions d = 3 + 2 kappa + 2 lambda:
  * F = U diag(sqrt(Lambda)) from the eigen-decomposition of the members' sample
  * covariance of theta = (phi_b, phi_1..kappa, z_1..kappa, m_1..lambda, zm_1..lambda,
@@ -222,7 +224,7 @@ rjsmc_status rjsmc_reweight_resample(rjsmc_ctx *ctx, const rjsmc_reweight_args *
 rjsmc_status rjsmc_adapt(rjsmc_ctx *ctx, const rjsmc_particles *p, int32_t n_sound,
                          const rjsmc_prior *prior, double *factors, rjsmc_stream stream);
 
-/* Archive of earlier populations for particle recycling (Section 3.2.5).  Slot h holds
+/* Archive of earlier populations for particle recycling (Section 3.2.4).  Slot h holds
  * the population of an earlier step, in the layout of the current one (n = n_sound
  * n_per_sounding particles, soundings contiguous):
  *   particle i of slot h is column h n + i of `pop` (pop.n = n_slots n, pop.stride >=
@@ -248,7 +250,7 @@ rjsmc_status rjsmc_archive_store(rjsmc_ctx *ctx, const rjsmc_particles *p, const
                                  const double *gamma, const double *log_z, int32_t n_sound,
                                  rjsmc_archive *archive, int32_t slot, rjsmc_stream stream);
 
-/* Proposal factors from recycled particles (Section 3.2.5 with Section 3.2.3).  For
+/* Proposal factors from recycled particles (Section 3.2.4 with Section 3.2.2).  For
  * each (sounding s, model k) the members of model k in the current population p (with
  * log-likelihoods ll, temperature gamma[s], evidence log_z[s][k]) and in the archive's
  * used slots are pooled and weighted by the deterministic mixture
@@ -264,7 +266,7 @@ rjsmc_status rjsmc_adapt_recycled(rjsmc_ctx *ctx, const rjsmc_particles *p, cons
                                   const rjsmc_archive *archive, const rjsmc_prior *prior,
                                   double *factors, rjsmc_stream stream);
 
-/* Move types of the RJ-MCMC kernel (Appendix E.1; Section 3.2.3). */
+/* Move types of the RJ-MCMC kernel (Appendix E.1; Section 3.2.2). */
 enum {
   RJSMC_MOVE_SIGMA_BIRTH = 0, RJSMC_MOVE_SIGMA_DEATH = 1, RJSMC_MOVE_SIGMA_MOVE = 2,
   RJSMC_MOVE_M_BIRTH = 3, RJSMC_MOVE_M_DEATH = 4, RJSMC_MOVE_M_MOVE = 5,
@@ -288,7 +290,7 @@ typedef struct {
   int64_t *stats_sound;         /* device [n_sound][2], may be NULL: within-model random-walk
                                    proposals / acceptances per sounding (accumulated) */
   int32_t trial;                /* 0: the sweeps of Algorithm 1.  b >= 1: trial proposals
-                                   (Section 3.2.3) decided and counted but never kept, with
+                                   (Section 3.2.2) decided and counted but never kept, with
                                    random-number move index b * 2^20 + r */
   int32_t zca_birth;            /* 0: a birth draws the new property from its prior.  1: the
                                    adaptive birth and death of Appendix E.2: the new depth
@@ -357,7 +359,7 @@ rjsmc_status rjsmc_summarize(rjsmc_ctx *ctx, const rjsmc_particles *p, const rjs
                              rjsmc_stream stream);
 
 /* One bisection step per sounding on log(scale) of the within-model random walk, from
- * trial proposals at the bracket's midpoint (Section 3.2.3: the step is scaled to reach a
+ * trial proposals at the bracket's midpoint (Section 3.2.2: the step is scaled to reach a
  * target acceptance rate).  init = 1 starts the bracket [log lo0, log hi0]; otherwise a
  * sounding whose trials were accepted at a rate above `target` raises the lower end to
  * the midpoint, else lowers the upper end (no trials: unchanged).  Then scale =
@@ -403,7 +405,9 @@ typedef struct {
 
 /* Sets / reads the tile shape used by rjsmc_forward, rjsmc_loglik and the proposal
  * likelihoods of rjsmc_mutate (default {4, 0, 1}).  RJSMC_E_INVALID for a shape not in
- * the list above. */
+ * the list above, or for one whose workgroup needs more LDS than the device allows
+ * for this system (the shapes that split the filter abscissae among waves stage
+ * 8 n_freq n_hankel bytes of reflection terms per particle). */
 rjsmc_status rjsmc_set_tuning(rjsmc_ctx *ctx, const rjsmc_tuning *tuning);
 rjsmc_status rjsmc_get_tuning(const rjsmc_ctx *ctx, rjsmc_tuning *tuning);
 
@@ -412,7 +416,8 @@ rjsmc_status rjsmc_get_tuning(const rjsmc_ctx *ctx, rjsmc_tuning *tuning);
  * with HIP events on `stream`; keeps the fastest in the context and writes it to *best
  * (may be NULL).  times_ms (host float[RJSMC_TUNING_CANDIDATES], may be NULL) receives
  * the mean launch time of candidate k, or -1 for a candidate that needs more workspace
- * than max_particles.  Synchronizes `stream`.
+ * than max_particles or more LDS than the device allows (it is skipped, not launched).
+ * Synchronizes `stream`.
  * RJSMC_E_INVALID for bad arguments or reps outside 1..1000. */
 rjsmc_status rjsmc_autotune(rjsmc_ctx *ctx, const rjsmc_particles *p, const double *y_obs, double *ll,
                             int32_t reps, rjsmc_tuning *best, float *times_ms, rjsmc_stream stream);

@@ -411,7 +411,6 @@ static hipError_t launch_g(const DevSystem &s, const DevParticles &p, int kc, in
 
 hipError_t launch_loglik_grad(const DevSystem &s, const DevParticles &p, int kc, int km, const double *y_obs,
                               double *ll, const DevGrad &g, hipStream_t stream) {
-  if (s.n_gate > s.n_freq) return hipErrorInvalidValue;     // the ybar staging reuses the Im H slots
   const int lcap = p.layout == RJSMC_LAYOUT_DECOUPLED ? kc + km + 1 : kc + 1;
   if (lcap <= 4) return launch_g<4>(s, p, kc, km, y_obs, ll, g, stream);
   if (lcap <= 8) return launch_g<8>(s, p, kc, km, y_obs, ll, g, stream);

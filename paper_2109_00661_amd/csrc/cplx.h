@@ -58,12 +58,15 @@ __device__ __forceinline__ void sqrt_hrsqrt(double x, double &sq, double &hrs) {
   hrs = fma(h, r, h);
 }
 __device__ __forceinline__ void sqrt_hrsqrt(float x, float &sq, float &hrs) {
+  // the estimate is good to ~2^-23; one Goldschmidt step brings both to about an ulp
   const float y = __builtin_amdgcn_rsqf(x);
-  sq = x * y;
-  hrs = 0.5f * y;
+  const float g = x * y, h = 0.5f * y;
+  const float r = fmaf(-g, h, 0.5f);
+  sq = fmaf(g, r, g);
+  hrs = fmaf(h, r, h);
 }
 
-// 1/x for finite normal x != 0: hardware estimate and two Newton steps.
+// 1/x for finite normal x != 0: hardware estimate and Newton steps (two in FP64).
 __device__ __forceinline__ double fast_rcp(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
@@ -71,7 +74,10 @@ __device__ __forceinline__ double fast_rcp(double x) {
   e = fma(-x, r, 1.0);
   return fma(r, e, r);
 }
-__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fast_rcp(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);   // estimate, then one Newton step
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
 
 // Principal square root for Im z != 0 or Re z > 0 (z never on the closed negative
 // real axis or at 0): both sqrt and its reciprocal from one refined estimate.

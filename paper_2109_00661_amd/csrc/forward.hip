@@ -202,32 +202,57 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
   }
 }
 
+// Dynamic LDS of one workgroup: K [n_gate][n_freq], plus the reflection terms
+// [WPB][n_freq][n_hankel_pad] when the abscissa groups are split among the waves.
+static size_t dynamic_lds(const DevSystem &s, int WPB, int P) {
+  const int nq = (s.n_freq + 7) / 8;
+  const int A = (P > 1 && P > nq) ? P / nq : 1;
+  return sizeof(double) * (s.n_freq * s.n_gate + (A > 1 ? (size_t)WPB * s.n_freq * s.n_hankel_pad : 0));
+}
+
 template <typename T, int WPB, int P>
 static hipError_t launch_t(const DevSystem &s, const DevParticles &p, int kc, int km, double *resp,
                            const double *y_obs, double *ll, const int32_t *perm, hipStream_t stream) {
   const int64_t blocks = (p.n + WPB - 1) / WPB;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  const int nq = (s.n_freq + 7) / 8;
-  const int A = (P > 1 && P > nq) ? P / nq : 1;
-  const size_t dyn =
-      sizeof(double) * (s.n_freq * s.n_gate + (A > 1 ? (size_t)WPB * s.n_freq * s.n_hankel_pad : 0));
-  hipLaunchKernelGGL((forward_kernel<T, WPB, P>), dim3((unsigned)blocks), dim3(kWave * WPB * P), dyn, stream, s, p,
-                     kc, km, resp, y_obs, ll, perm);
+  hipLaunchKernelGGL((forward_kernel<T, WPB, P>), dim3((unsigned)blocks), dim3(kWave * WPB * P), dynamic_lds(s, WPB, P),
+                     stream, s, p, kc, km, resp, y_obs, ll, perm);
   return hipGetLastError();
 }
+
+template <typename T, int WPB, int P>
+static hipError_t lds_t(const DevSystem &s, size_t *bytes) {
+  hipFuncAttributes attr;
+  const hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void *>(&forward_kernel<T, WPB, P>));
+  if (e != hipSuccess) return e;
+  *bytes = attr.sharedSizeBytes + dynamic_lds(s, WPB, P);
+  return hipSuccess;
+}
+
+// Dispatch on the tile shape: F<T, WPB, P>(args...) for the compiled shapes.
+#define RJSMC_TILE_DISPATCH(F, T, w, q, ...)                                  \
+  do {                                                                        \
+    if ((q) == 2 && (w) == 2) return F<T, 2, 2>(__VA_ARGS__);                 \
+    if ((q) == 4 && (w) == 1) return F<T, 1, 4>(__VA_ARGS__);                 \
+    if ((q) == 8 && (w) == 1) return F<T, 1, 8>(__VA_ARGS__);                 \
+    if ((q) == 16 && (w) == 1) return F<T, 1, 16>(__VA_ARGS__);               \
+    if ((q) != 1) return hipErrorInvalidValue;                                \
+    if ((w) == 2) return F<T, 2, 1>(__VA_ARGS__);                             \
+    if ((w) == 8) return F<T, 8, 1>(__VA_ARGS__);                             \
+    if ((w) == 4) return F<T, 4, 1>(__VA_ARGS__);                             \
+    return hipErrorInvalidValue;                                              \
+  } while (0)
 
 template <typename T>
 static hipError_t launch_prec(const ForwardTiles &t, const DevSystem &s, const DevParticles &p, int kc, int km,
                               double *resp, const double *y_obs, double *ll, hipStream_t stream) {
-  const int w = t.waves_per_block, q = t.waves_per_particle;
-  if (q == 2 && w == 2) return launch_t<T, 2, 2>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
-  if (q == 4 && w == 1) return launch_t<T, 1, 4>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
-  if (q == 8 && w == 1) return launch_t<T, 1, 8>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
-  if (q == 16 && w == 1) return launch_t<T, 1, 16>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
-  if (q != 1) return hipErrorInvalidValue;
-  if (w == 2) return launch_t<T, 2, 1>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
-  if (w == 8) return launch_t<T, 8, 1>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
-  return launch_t<T, 4, 1>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);
+  RJSMC_TILE_DISPATCH(launch_t, T, t.waves_per_block, t.waves_per_particle, s, p, kc, km, resp, y_obs, ll, t.perm,
+                      stream);
+}
+
+template <typename T>
+static hipError_t lds_prec(const DevSystem &s, int w, int q, size_t *bytes) {
+  RJSMC_TILE_DISPATCH(lds_t, T, w, q, s, bytes);
 }
 
 hipError_t launch_forward(const DevSystem &s, const DevParticles &p, int kc, int km, int precision,
@@ -235,6 +260,12 @@ hipError_t launch_forward(const DevSystem &s, const DevParticles &p, int kc, int
                           const ForwardTiles &tiles) {
   if (precision == RJSMC_F32) return launch_prec<float>(tiles, s, p, kc, km, resp, y_obs, ll, stream);
   return launch_prec<double>(tiles, s, p, kc, km, resp, y_obs, ll, stream);
+}
+
+hipError_t forward_lds_bytes(const DevSystem &s, int precision, int waves_per_block, int waves_per_particle,
+                             size_t *bytes) {
+  if (precision == RJSMC_F32) return lds_prec<float>(s, waves_per_block, waves_per_particle, bytes);
+  return lds_prec<double>(s, waves_per_block, waves_per_particle, bytes);
 }
 
 // ---- ordering of particles by layer capacity (counting sort, descending capacity)

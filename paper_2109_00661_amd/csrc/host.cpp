@@ -287,6 +287,9 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
   c->tuning.waves_per_block = 4;
   c->tuning.layer_sort = 0;
   c->tuning.waves_per_particle = 1;
+  int lds_limit = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+  c->lds_limit = lds_limit > 0 ? (size_t)lds_limit : 0;
   c->work_n = s->max_particles > 0 ? s->max_particles : 0;
   if (e == hipSuccess && c->work_n > 0) {
     e = hipMalloc((void **)&c->work_mask, sizeof(int32_t) * c->work_n);
@@ -751,11 +754,28 @@ static bool valid_tuning(const rjsmc_tuning &t) {
   return false;
 }
 
+// Whether a workgroup of the tile shape fits the device's LDS for this system: the
+// shapes that split the filter abscissae among waves stage every reflection term in
+// LDS, which long filters and many frequencies can push beyond the limit.
+static bool tuning_fits(const rjsmc_ctx *c, const rjsmc_tuning &t, size_t *need) {
+  size_t bytes = 0;
+  if (rjsmc::forward_lds_bytes(c->dev, c->precision, t.waves_per_block, t.waves_per_particle, &bytes) != hipSuccess)
+    return false;
+  if (need) *need = bytes;
+  return bytes <= c->lds_limit;
+}
+
 extern "C" rjsmc_status rjsmc_set_tuning(rjsmc_ctx *c, const rjsmc_tuning *t) {
   if (!c || !t) return fail(RJSMC_E_INVALID, "rjsmc_set_tuning: NULL argument");
   if (!valid_tuning(*t))
     return fail(RJSMC_E_INVALID, "rjsmc_set_tuning: (%d, %d, %d) is not a compiled tile shape", t->waves_per_block,
                 t->layer_sort, t->waves_per_particle);
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "rjsmc_set_tuning: hipSetDevice");
+  size_t need = 0;
+  if (!tuning_fits(c, *t, &need))
+    return fail(RJSMC_E_INVALID, "rjsmc_set_tuning: (%d, %d, %d) needs %zu bytes of LDS per workgroup, more than %zu",
+                t->waves_per_block, t->layer_sort, t->waves_per_particle, need, c->lds_limit);
   c->tuning = *t;
   return RJSMC_OK;
 }
@@ -786,7 +806,7 @@ extern "C" rjsmc_status rjsmc_autotune(rjsmc_ctx *c, const rjsmc_particles *p, c
   for (int k = 0; k < RJSMC_TUNING_CANDIDATES && e == hipSuccess; ++k) {
     const rjsmc_tuning t = {kShapes[k / 2][0], k % 2, kShapes[k / 2][1]};
     float ms = -1.0f;
-    if (!t.layer_sort || (c->work_perm && dp.n <= c->work_n)) {
+    if ((!t.layer_sort || (c->work_perm && dp.n <= c->work_n)) && tuning_fits(c, t, nullptr)) {
       e = run_forward(c, dp, t, nullptr, y_obs, ll, s);   // warm-up
       if (e == hipSuccess) e = hipEventRecord(ev0, s);
       for (int r = 0; r < reps && e == hipSuccess; ++r) e = run_forward(c, dp, t, nullptr, y_obs, ll, s);

@@ -1,5 +1,5 @@
 // Per-particle merge of the decoupled conductivity and chargeability partitions into one
-// layer stack (paper Section 2.2, Fig. 2: the two change-point profiles are combined by
+// layer stack (paper Section 2.1, Fig. 2: the two change-point profiles are combined by
 // a direct sum).  One wavefront works on one particle; the result lands in LDS.
 #pragma once
 

@@ -14,12 +14,15 @@ namespace rjsmc {
 //   E_l = exp(-2 u_l h_l),  u_l = sqrt(lam^2 + k2_l), Re u_l > 0,
 // is carried in projective form, r = N/D: the deepest interface starts from
 // N = k2_{L-2} - k2_{L-1}, D = (u_{L-2} + u_{L-1})^2 (R without a difference of nearly
-// equal u), and every interface above takes step_up (R = (u_l - u_{l+1})/(u_l + u_{l+1}),
-// two complex products), so the whole stack needs one real division
-// (Im r = Im(N conj D) / |D|^2) instead of two complex divisions per layer.
-// FP64 keeps N, D unscaled (each step multiplies them by about |u|, so |D| stays far
-// inside the FP64 range for <= 16 layers of this system); FP32 rescales by a power of
-// two every layer.
+// equal u), and every interface above takes one projective step, so the whole stack
+// needs one real division (Im r = Im(N conj D) / |D|^2) instead of two complex
+// divisions per layer.  FP64 takes step_up (two complex products; it forms u_l -
+// u_{l+1} implicitly, which costs FP64 nothing measurable); FP32 takes step_ratio,
+// whose interface numerator is the difference of the layer wavenumbers k2_l -
+// k2_{l+1} (exact for equal layers, no cancellation of nearly equal u).  FP64 keeps
+// N, D unscaled (each step multiplies them by about |u|, so |D| stays far inside the
+// FP64 range for <= 16 layers of this system); FP32 rescales by a power of two every
+// layer.
 template <typename T>
 __device__ __forceinline__ void rescale(cplx<T> &N, cplx<T> &D) {}
 template <>
@@ -34,9 +37,11 @@ __device__ __forceinline__ void rescale<float>(cplx<float> &N, cplx<float> &D) {
 // R = (a - b) / (a + b), and r_above = (R + r E) / (1 + R r E) for r = N / D becomes
 //   N' = a S - b T,  D' = a S + b T,  S = D + N E,  T = D - N E
 // (the common factor a + b dropped): two complex products instead of four, and neither
-// the interface numerator nor (a + b)^2 is formed.  a - b never appears explicitly; for
-// nearly equal a and b the D-part of N' is the difference of a S and b T, accurate to a
-// rounding of |b D| absolute, i.e. to ~1e-16 in r.
+// the interface numerator nor (a + b)^2 is formed.  a - b never appears explicitly: for
+// nearly equal a and b (|k2| << lam^2, low frequencies and large lam) the D-part of N'
+// is the difference of a S and b T, accurate only to a rounding of |a D| absolute.  In
+// FP64 that is ~1e-16 of r; in FP32 it would be 6e-8 |a D|, which for k2 / lam^2 ~ 1e-5
+// is a relative error of ~1e-2 in N', so FP32 uses step_ratio instead.
 template <typename T>
 __device__ __forceinline__ void step_up(cplx<T> &N, cplx<T> &D, cplx<T> a, cplx<T> b, cplx<T> E) {
   const cplx<T> NE = N * E;
@@ -44,6 +49,20 @@ __device__ __forceinline__ void step_up(cplx<T> &N, cplx<T> &D, cplx<T> a, cplx<
   const cplx<T> P = a * S, Q = b * Tm;
   N = P - Q;
   D = P + Q;
+}
+
+// The same step with R = dk / B, dk = a^2 - b^2 = k2_above - k2_below (lam^2 cancels
+// exactly) and B = (a + b)^2:
+//   N' = dk D + B N E,  D' = B D + dk N E
+// (the common factor 1 / B dropped).  Every factor is formed without subtracting
+// nearly equal numbers, so each step is accurate to a few roundings relative to its
+// terms whatever the ratio k2 / lam^2.
+template <typename T>
+__device__ __forceinline__ void step_ratio(cplx<T> &N, cplx<T> &D, cplx<T> dk, cplx<T> B, cplx<T> E) {
+  const cplx<T> NE = N * E;
+  const cplx<T> Np = dk * D + B * NE;
+  D = B * D + dk * NE;
+  N = Np;
 }
 
 // Propagation factor exp(-2 h u): table-assisted in FP64, polynomial in FP32.
@@ -63,6 +82,7 @@ __device__ __forceinline__ cplx<float> prop_exp(cplx<float> z, const cplx<double
 template <typename T>
 __device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const cplx<T> *dk2, const T *h2, int L,
                                            const cplx<double> *phase, const double *e2) {
+  constexpr bool kRatio = sizeof(T) == sizeof(float);   // FP32: cancellation-free steps
   const T lam2 = lam * lam;
   const cplx<T> kb = k2[L - 1];
   cplx<T> ub = csqrt_fast(cplx<T>{lam2 + kb.re, kb.im});
@@ -83,12 +103,20 @@ __device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const cplx<
       const cplx<T> kl = k2[l];
       const cplx<T> u = csqrt_fast(cplx<T>{lam2 + kl.re, kl.im});
       const T hh = h2[l + 1];
-      step_up(N, D, u, ub, prop_exp(cplx<T>{hh * ub.re, hh * ub.im}, phase, e2));
+      const cplx<T> E = prop_exp(cplx<T>{hh * ub.re, hh * ub.im}, phase, e2);
+      if (kRatio)
+        step_ratio(N, D, dk2[l], csq(u + ub), E);
+      else
+        step_up(N, D, u, ub, E);
       rescale(N, D);
       ub = u;
     }
     const T hh = h2[0];
-    step_up(N, D, cplx<T>{lam, T(0)}, ub, prop_exp(cplx<T>{hh * ub.re, hh * ub.im}, phase, e2));
+    const cplx<T> E0 = prop_exp(cplx<T>{hh * ub.re, hh * ub.im}, phase, e2);
+    if (kRatio)   // air interface: lam^2 - u_0^2 = -k2_0
+      step_ratio(N, D, cplx<T>{-k2[0].re, -k2[0].im}, csq(cplx<T>{lam + ub.re, ub.im}), E0);
+    else
+      step_up(N, D, cplx<T>{lam, T(0)}, ub, E0);
   }
   return (N.im * D.re - N.re * D.im) * fast_rcp(D.re * D.re + D.im * D.im);
 }

@@ -102,6 +102,10 @@ struct ForwardTiles {
 hipError_t launch_forward(const DevSystem &s, const DevParticles &p, int kmax_cond, int kmax_charg,
                           int precision, double *resp, const double *y_obs, double *ll,
                           hipStream_t stream, const ForwardTiles &tiles);
+// Static plus dynamic LDS bytes of one forward workgroup of the given tile shape for
+// system s (hipErrorInvalidValue for a shape that is not compiled).
+hipError_t forward_lds_bytes(const DevSystem &s, int precision, int waves_per_block, int waves_per_particle,
+                             size_t *bytes);
 // perm[0..n) = particle indices in descending order of layer capacity (kappa + lambda + 1);
 // cnt: 2 kMaxLayers ints of device scratch.
 hipError_t launch_layer_sort(const DevParticles &p, int *cnt, int32_t *perm, hipStream_t stream);
@@ -173,4 +177,5 @@ struct rjsmc_ctx {
   int *work_cnt;        // [2 kMaxLayers] counting-sort scratch
   int64_t work_n;
   rjsmc_tuning tuning;  // forward tile shape
+  size_t lds_limit;     // LDS bytes one workgroup may use on this device
 };

@@ -1,7 +1,7 @@
 // SMC primitives of adaptive RJSMC (Algorithm 1) for gfx950: prior initialisation,
 // re-weighting with the tempering bisection and evidence update, within-model
 // systematic resampling with the resampled copy, per-model proposal adaptation (also
-// from recycled particles, Section 3.2.5), and the propose / accept halves of the
+// from recycled particles, Section 3.2.4), and the propose / accept halves of the
 // RJ-MCMC mutation, including the adaptive birth of Appendix E.2 (the likelihood of
 // each proposal is evaluated by the forward kernel in between).
 //
@@ -1130,7 +1130,7 @@ hipError_t launch_adapt(const SmcShape &sh, const DevParticles &p, int n_sound, 
 // ------------------------------------------------------------- particle recycling ---
 // One wavefront per (sounding, model) pools the model's members of the current
 // population and of the archive's used slots, weighted by the deterministic mixture of
-// the sources (Section 3.2.5):
+// the sources (Section 3.2.4):
 //   log nu = gamma_t ll - log sum_c exp(log N_c - log Z_c + gamma_c ll)
 // over the sources c with N_c > 0 members and a finite log Z_c (L^0 = 1).  Four passes
 // over the sources (member list rebuilt per source): counts, the largest log nu, the

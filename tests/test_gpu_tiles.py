@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-SHAPES = [(w, s, q) for (w, q) in ((2, 1), (4, 1), (8, 1), (2, 2), (1, 4), (1, 8)) for s in (0, 1)]
+SHAPES = [(w, s, q) for (w, q) in ((2, 1), (4, 1), (8, 1), (2, 2), (1, 4), (1, 8), (1, 16)) for s in (0, 1)]
 
 
 @pytest.fixture(scope="module")
@@ -50,6 +50,58 @@ def test_every_shape_bit_identical(B, uneven, truth_data, prec):
         ctx.check()
         assert np.array_equal(y, ref_y), (w, s, q)
         assert np.array_equal(ll, ref_ll), (w, s, q)
+
+
+def _few_frequency_system(kc, km, n_freq=16):
+    """The standard system with fewer frequencies (same band), so that the 4- and
+    8-wave shapes, not only the 16-wave one, split the filter abscissae among waves."""
+    s = dict(W.system(kmax_cond=kc, kmax_charg=km))
+    s["freq_hz"] = 10.0 ** (6.0 * np.arange(n_freq) / (n_freq - 1))
+    return s
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_every_shape_bit_identical_split_abscissae(B, uneven, truth_data, prec):
+    """16 frequencies = 2 groups of 8: (1,4), (1,8) and (1,16) split each group's filter
+    abscissae among 2, 4 and 8 waves and re-sum them in the order of the other shapes."""
+    ctx = B.Context(_few_frequency_system(7, 4), precision=prec, max_particles=2048)
+    dp = B.particles_to_device(W.take(uneven, range(257)))
+    d = _data(B, truth_data)
+    ref_y = ctx.forward(dp).cpu().numpy()
+    ref_ll = ctx.loglik(dp, d).cpu().numpy()
+    ctx.check()
+    assert np.all(np.isfinite(ref_ll))
+    for w, s, q in SHAPES:
+        ctx.set_tuning(w, s, q)
+        y = ctx.forward(dp).cpu().numpy()
+        ll = ctx.loglik(dp, d).cpu().numpy()
+        ctx.check()
+        assert np.array_equal(y, ref_y), (w, s, q)
+        assert np.array_equal(ll, ref_ll), (w, s, q)
+
+
+def test_shape_beyond_lds_rejected_not_launched(B, uneven, truth_data):
+    """With a 256-point filter the 16-wave shape would stage 40 x 256 reflection terms
+    (82 KB) beside its static LDS: set_tuning rejects it, and the autotuner skips it
+    (time -1) and still picks a shape that fits."""
+    s = dict(W.system(kmax_cond=7, kmax_charg=4))
+    b, w = W.hankel_table()
+    s["hankel_b"] = np.exp(np.linspace(np.log(b[0]), np.log(b[-1]), 256))
+    s["hankel_w"] = np.interp(np.log(s["hankel_b"]), np.log(b), w) * (120.0 / 256.0)
+    ctx = B.Context(s, precision="f64", max_particles=2048)
+    with pytest.raises(B.RJSMCError) as e:
+        ctx.set_tuning(1, 0, 16)
+    assert e.value.status == B.RJSMC_E_INVALID and "LDS" in str(e.value)
+    assert ctx.get_tuning() == {"waves_per_block": 4, "layer_sort": 0, "waves_per_particle": 1}
+    dp = B.particles_to_device(W.take(uneven, range(64)))
+    d = _data(B, truth_data)
+    ref = ctx.loglik(dp, d).cpu().numpy()
+    best, times = ctx.autotune(dp, d, reps=1)
+    k16 = 2 * B.TILE_SHAPES.index((1, 16))
+    assert times[k16] < 0 and times[k16 + 1] < 0
+    assert best["waves_per_particle"] != 16
+    assert np.array_equal(ctx.loglik(dp, d).cpu().numpy(), ref)
+    ctx.check()
 
 
 def test_sort_skipped_beyond_workspace(B, uneven, truth_data):
