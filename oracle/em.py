@@ -148,7 +148,7 @@ def _value(p, name, row, i):
 
 
 def merged_stack(p, i, theta=None):
-    """Merged layer stack of particle i (Section 2.2, Fig. 2: the two change-point
+    """Merged layer stack of particle i (Section 2.1, Fig. 2: the two change-point
     profiles are merged by a direct sum).
 
     Returns (sigma_inf[L], m[L], thickness[L-1]) as lists of scalars (or Duals when

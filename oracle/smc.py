@@ -24,12 +24,12 @@ readings where it is silent or loose:
   one depth; all accept with the tempered likelihood ratio (the prior and proposal
   terms cancel).  Proposals beyond the capacity or outside the support are rejected.
   The within-model move steps along one principal direction of the model's particle
-  covariance, scaled by the square root of its eigenvalue (Section 3.2.3).
+  covariance, scaled by the square root of its eigenvalue (Section 3.2.2).
 * The gradient-informed within-model move (the paper cites Langevin proposals as prior
   art, Section 3) is a preconditioned Langevin step theta' = theta + eps^2/2 S grad +
   eps F xi with S = F F^T, grad = gamma grad ll (flat prior inside the support) and a
   Metropolis-Hastings correction with the reverse proposal density.
-* Particle recycling for the proposal adaptation (Section 3.2.5): the members of model
+* Particle recycling for the proposal adaptation (Section 3.2.4): the members of model
   k in the populations of steps l = 0..t (each approximating the model-conditional
   power posterior at gamma_l) are pooled and weighted by the deterministic mixture
   nu = L^gamma_t / sum_l N_{l,k} L^gamma_l / Z_{l,k}, N_{l,k} the number of model-k
@@ -345,7 +345,7 @@ def prior_sd(k, l, pr):
 def proposal_factor(p, members, k, l, pr):
     """Colouring factor F of the within-model proposal for model (k, l): F = U diag(sqrt
     Lambda) from the eigen-decomposition of the sample covariance of the model's
-    members (Section 3.2.3), or 0.1 diag(prior sd) when there are no more members than
+    members (Section 3.2.2), or 0.1 diag(prior sd) when there are no more members than
     dimensions.  F F^T is the unique part; the columns are principal directions."""
     d = 3 + 2 * k + 2 * l
     if len(members) <= d:
@@ -376,7 +376,7 @@ def _tempered(g, ll):
 
 
 def recycled_log_weights(ll, gamma_hist, log_z_hist, count_hist, gamma_t):
-    """Unnormalised log deterministic-mixture weights (Section 3.2.5) of pooled members
+    """Unnormalised log deterministic-mixture weights (Section 3.2.4) of pooled members
     of one model with log-likelihoods `ll`: gamma_t ll - log sum_l N_l exp(gamma_l ll -
     log Z_l) over the steps l whose population holds N_l > 0 members of the model and
     whose evidence estimate log Z_l is finite."""
@@ -643,7 +643,7 @@ def mutate(p, ll, loglik_fn, gamma_of, step, seed, q, pr, kmax_cond, kmax_charg,
     indices: the particles to move (default all); each particle's chain depends only on
     its own state and random counters, so a subset moves exactly as in the full sweep.
     q["rw_scale"] may be a function of the particle index.  trial = b >= 1: trial
-    proposals (Section 3.2.3) that draw from their own counters (move index
+    proposals (Section 3.2.2) that draw from their own counters (move index
     b * TRIAL_STRIDE + r) and are decided but never kept."""
     n = len(ll)
     which = range(n) if indices is None else list(indices)
@@ -721,7 +721,7 @@ class NestedLinearGaussian:
 
 def scale_bisection(log_lo, log_hi, tried, accepted, target):
     """One bisection step on log(scale) of the within-model random walk from trial
-    proposals made at the bracket's midpoint (Section 3.2.3): a higher acceptance than
+    proposals made at the bracket's midpoint (Section 3.2.2): a higher acceptance than
     the target allows a larger step.  Returns (log_lo, log_hi, next scale)."""
     if tried > 0:
         mid = 0.5 * (log_lo + log_hi)
@@ -733,7 +733,7 @@ def scale_bisection(log_lo, log_hi, tried, accepted, target):
 
 
 def mutation_count(acceptance, c, r_max):
-    """Number of mutation sweeps for the next step (Section 3.2.4, after Drovandi and
+    """Number of mutation sweeps for the next step (Section 3.2.3, after Drovandi and
     Pettitt): with p_min the smallest acceptance rate over the proposal types,
     R = ceil(log c / log(1 - p_min)), so that every particle moves with probability at
     least 1 - c under the least-accepted proposal; at least 1, at most r_max (also when
@@ -813,7 +813,7 @@ def posterior_summary(p, kmax_cond, kmax_charg, n_sound, depths):
     pi_T(k | y) / p(k), divided by the same mean over conductive models, with
     pi_T(k | y) = N_k / N (Section 3.2.1) and the uniform model prior p(k).  Profiles:
     at each depth, the mean over particles of log10 sigma_inf(z) and of m(z), and the
-    fraction with m(z) > 0, a property applying from its interface down (Section 2.2).
+    fraction with m(z) > 0, a property applying from its interface down (Section 2.1).
     Returns dict(model_count [S][M], log_bfipd [S], mean_log10_sigma, mean_m,
     p_chargeable [S][n_depth])."""
     n = len(p["kappa"])

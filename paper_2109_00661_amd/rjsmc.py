@@ -17,7 +17,7 @@ RW_ONLY = (0, 0, 0, 0, 0, 0, 1, 0)           # trial proposals of the step-size 
 
 def mutation_count(rates, c, r_max):
     """Sweeps for the next step from the last step's acceptance rates per move type
-    (Section 3.2.4): the least R with (1 - p_min)^R <= c, clamped to 1 .. r_max."""
+    (Section 3.2.3): the least R with (1 - p_min)^R <= c, clamped to 1 .. r_max."""
     p = min(rates)
     if p <= 0.0:
         return int(r_max)
@@ -78,7 +78,7 @@ class RJSMCRun:
             self.stats_sound = torch.zeros((n_sound, 2), dtype=torch.int64, device=device)
         self.moves_per_step = []
         self._stats_prev = None
-        # particle recycling (Section 3.2.5): the proposals adapt to the current population
+        # particle recycling (Section 3.2.4): the proposals adapt to the current population
         # pooled with the populations of up to `recycle` earlier steps (a ring)
         if recycle and graph:
             raise ValueError("particle recycling runs eagerly (the archive slot changes every step)")

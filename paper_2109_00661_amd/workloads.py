@@ -109,6 +109,25 @@ def truth_three_layer_merged():
     return p
 
 
+def near_truth_merged(n, seed=0, kc=4):
+    """Merged-layout particles near the three-layer truth (stand-ins for posterior
+    samples near the mode): particle 0 is the truth itself, the others perturb it by
+    Gaussian draws of sd 0.02 in each log10 sigma, 0.5 m in each interface depth, 0.01
+    in the middle layer's m, 0.02 in log10 tau and 0.01 in c.  Capacity kc >= 2 rows
+    (only three layers are used)."""
+    rng = np.random.default_rng(seed)
+    p = empty_particles(n, kc, 0, LAYOUT_MERGED)
+    jitter = lambda sd, *shape: sd * rng.standard_normal(shape) * (np.arange(n) > 0)
+    p["kappa"][:] = 2
+    p["phi_b"][:] = -2.0 + jitter(0.02, n)
+    p["phi"][:2] = np.array([[-1.0], [-3.0]]) + jitter(0.02, 2, n)
+    p["z_cond"][:2] = np.array([[20.0], [40.0]]) + jitter(0.5, 2, n)
+    p["m"][1] = 0.4 + jitter(0.01, n)
+    p["log10_tau"][:] = -3.0 + jitter(0.02, n)
+    p["c"][:] = 0.5 + jitter(0.01, n)
+    return p
+
+
 def data_noise(seed=1):
     """Standard-normal draws that scale the data noise of the synthetic sounding."""
     return np.random.default_rng(seed).standard_normal(N_GATE)

@@ -1,7 +1,9 @@
 """GPU parity of the reverse-sweep gradient of the log-likelihood.
 
 Against the oracle's forward-mode tangents (a different method): per particle
-|g_gpu - g_oracle| <= 1e-8 max|g_oracle| componentwise.  Against central finite
+|g_gpu - g_oracle| <= 1e-9 max|g_oracle| componentwise (measured up to ~1e-11: the
+device's square roots, exponentials and reciprocals are a few ulps from correctly
+rounded, and the reverse sweep sums in another order).  Against central finite
 differences of the GPU log-likelihood (step 1e-6 max(|x|, 1)): <= 1e-5 max|g|.
 Interfaces are kept at least 1 m apart (the gradient has kinks where a conductivity
 and a chargeability interface cross).
@@ -32,7 +34,7 @@ def _grad_gpu(B, ctx, p, d):
     return ll.cpu().numpy(), {k: v.cpu().numpy() for k, v in g.items()}, ll_plain.cpu().numpy()
 
 
-def _check_against_oracle(p, ll, g, ll_o, g_o, tol=1e-8):
+def _check_against_oracle(p, ll, g, ll_o, g_o, tol=1e-9):
     np.testing.assert_allclose(ll, ll_o, rtol=1e-9, atol=1e-9)
     n = len(ll)
     for i in range(n):
@@ -108,7 +110,7 @@ def test_grad_same_particles_under_both_capacities(B, truth_data):
 
 def test_grad_full_size_sampled(B, K_oracle, truth_data):
     """65,536 decoupled particles with 1-8 segments per partition (the adjoint
-    workload); 6 sampled particles against the oracle, all finite."""
+    workload); 48 sampled particles against the oracle, all finite."""
     from oracle import em
     system = W.system(kmax_cond=7, kmax_charg=7)
     ctx = B.Context(system, precision="f64")
@@ -137,7 +139,7 @@ def test_grad_full_size_sampled(B, K_oracle, truth_data):
         z = np.sort(np.concatenate([[0.0], p["z_cond"][:p["kappa"][i], i], p["z_charg"][:p["lambda_"][i], i]]))
         if np.all(np.diff(z) >= 1.0):
             sel.append(i)
-        if len(sel) == 6:
+        if len(sel) == 48:
             break
     sub = W.take(p, sel)
     ll_o, g_o = em.loglik_grad(sub, system, K_oracle, truth_data)

@@ -357,7 +357,7 @@ def _norm_w(lw):
 
 def test_recycled_factor_of_one_population_is_the_plain_factor():
     """A pool holding only the current population has equal weights: the recycled factor
-    is the factor of the sample covariance (Section 3.2.3)."""
+    is the factor of the sample covariance (Section 3.2.2)."""
     p = smc.init_population(4, 600, PR["kmax_cond"], PR["kmax_charg"], PR)
     models = smc.model_id(p["kappa"], p["lambda_"], PR["kmax_charg"])
     k, l = 2, 1
