@@ -1,0 +1,115 @@
+"""Algorithm 1 on the device (RJSMCRun over the C ABI) against the oracle's driver
+(oracle/algorithm1.py), step by step.
+
+Two soundings of 64 particles, both drivers from the same seed: the device draws the
+prior population itself (bit-identical to the oracle's draw), then every step's
+re-weighting / re-sampling, adaptation and R = 5 mutation sweeps run on the device with
+its ping-pong buffers, the carried log-likelihoods and the step counters, and are
+compared with the oracle's step:
+  temperatures within 1e-12, log-evidence within 1e-11 (relative above 1), ancestors
+  and model counts exact, states and log-likelihoods equal (1e-12 / 1e-9 relative)
+  except for particles whose oracle accept margin gamma (ll' - ll) - ln u (+ proposal
+  terms) came within 1e-8 of zero, and move tallies exact when no such decision
+  occurred.
+Should a near-threshold decision part the two chains, the device population is reset
+to the oracle's (host to device only) before the next step, so that later steps are
+still compared from a common state.  Random-walk moves run through the captured HIP
+step graphs, the Langevin moves eagerly.
+"""
+import numpy as np
+import pytest
+
+from paper_2109_00661_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+PR = W.PRIOR
+FKEYS = ("phi_b", "phi", "z_cond", "m", "z_charg", "log10_tau", "c")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2109_00661_amd import binding
+    return binding
+
+
+def _two_soundings(system, K, truth_data):
+    from oracle import em
+    y = em.forward(W.truth_three_layer(), system, K)[0]
+    s = np.sqrt(em.noise_variance(y, system["eps_an"], system["eps_mn"]))
+    return np.stack([truth_data, y + s * W.data_noise(2)])
+
+
+def _upload(run, pop, ll):
+    st = run.state
+    for k in ("kappa", "lambda_"):
+        st[k].copy_(torch.as_tensor(np.asarray(pop[k], dtype=np.int32)))
+    for k in FKEYS:
+        st[k].copy_(torch.as_tensor(np.asarray(pop[k], dtype=np.float64)))
+    run.ll.copy_(torch.as_tensor(ll))
+
+
+@pytest.mark.parametrize("moves", ["rw", "langevin"])
+def test_algorithm1_against_oracle(B, system, K_oracle, truth_data, moves):
+    from oracle import algorithm1 as A1, smc
+    from paper_2109_00661_amd.rjsmc import RJSMCRun, UNIFORM_MOVES, LANGEVIN_MOVES
+    mp = UNIFORM_MOVES if moves == "rw" else LANGEVIN_MOVES
+    S, N, seed, n_steps = 2, 64, 31, 5
+    y = _two_soundings(system, K_oracle, truth_data)
+    ctx = B.Context(system, precision="f64", max_particles=S * N)
+    run = RJSMCRun(ctx, S, N, y, seed=seed, move_prob=mp, n_moves=5, graph=(moves == "rw"))
+    run.initialise()
+    init = smc.init_population(seed, S * N, PR["kmax_cond"], PR["kmax_charg"], PR)
+    for k in ("kappa", "lambda_") + FKEYS:
+        assert np.array_equal(run.state[k].cpu().numpy(), init[k]), k
+    km = PR["kmax_charg"]
+    report = {"resynced": 0, "flagged": 0}
+    stats_prev = np.zeros((2, 8), dtype=np.int64)
+
+    def on_step(t, rec):
+        nonlocal stats_prev
+        run.advance()
+        ctx.check()
+        assert run.step == t
+        g = run.gamma.cpu().numpy()
+        np.testing.assert_allclose(g, rec["gamma"], rtol=0, atol=1e-12, err_msg="gamma, step %d" % t)
+        lz = run.log_z.cpu().numpy()
+        fin = np.isfinite(rec["log_z"])
+        assert np.array_equal(np.isfinite(lz), fin), t
+        assert np.all(np.abs(lz[fin] - rec["log_z"][fin]) <= 1e-11 * np.maximum(1.0, np.abs(rec["log_z"][fin]))), t
+        assert np.array_equal(run.anc.cpu().numpy(), rec["anc"]), "ancestors, step %d" % t
+        near = sorted({i for i, r, mg in rec["margins"] if abs(mg) < 1e-8})
+        ok = np.setdiff1d(np.arange(S * N), near)
+        got = {k: run.state[k].cpu().numpy() for k in ("kappa", "lambda_") + FKEYS}
+        ll_d = run.ll.cpu().numpy()
+        pop = rec["pop"]
+        for k in ("kappa", "lambda_"):
+            assert np.array_equal(got[k][ok], pop[k][ok]), (k, t)
+        tol = 1e-12 if moves == "rw" else 1e-10
+        for k in FKEYS:
+            np.testing.assert_allclose(got[k][..., ok], pop[k][..., ok], rtol=tol, atol=tol, err_msg="%s step %d" % (k, t))
+        np.testing.assert_allclose(ll_d[ok], rec["ll"][ok], rtol=1e-9, atol=1e-9, err_msg="ll step %d" % t)
+        m_d = smc.model_id(got["kappa"], got["lambda_"], km)
+        m_o = smc.model_id(pop["kappa"], pop["lambda_"], km)
+        st = run.stats.cpu().numpy()
+        if not near:
+            for s in range(S):
+                assert np.array_equal(np.bincount(m_d[s * N:(s + 1) * N], minlength=20),
+                                      np.bincount(m_o[s * N:(s + 1) * N], minlength=20)), t
+            assert np.array_equal(st - stats_prev, rec["stats"]), t
+        stats_prev = st
+        assert rec["stats"][1].sum() > 0
+        report["flagged"] += len(near)
+        if near and not all(np.array_equal(got[k][..., near], pop[k][..., near]) for k in ("kappa", "lambda_") + FKEYS):
+            _upload(run, pop, rec["ll"])       # the chains parted at a rounding-level decision
+            report["resynced"] += 1
+        return None
+
+    g, lz, _, _, steps = A1.run(system, K_oracle, y, S, N, PR, seed, move_prob=mp, n_moves=5, mala_eps=run.mala_eps,
+                                max_steps=n_steps, on_step=on_step)
+    assert steps == n_steps and run.step == n_steps
+    assert np.all(g > 0) and np.all(g < 1)
+    assert report["flagged"] <= 2, report
