@@ -356,11 +356,15 @@ def proposal_factor(p, members, k, l, pr):
 
 def factor_of_covariance(C):
     """F = U diag(sqrt Lambda) of a covariance, eigenvalues descending, each direction
-    signed so that its largest-magnitude component is positive."""
+    signed so that its largest-magnitude component is positive.  Eigenvalues below
+    1e-12 of the largest are taken as zero: the sample covariance of a re-sampled model
+    with fewer distinct members than dimensions is singular, and its null eigenvalues
+    come out as rounding noise of either sign (~1e-16 of the largest)."""
     d = C.shape[0]
     lam_, U = np.linalg.eigh(C)
     order = np.argsort(-lam_, kind="stable")                 # descending eigenvalues
     lam_, U = np.clip(lam_[order], 0.0, None), U[:, order]
+    lam_ = np.where(lam_ > 1e-12 * lam_[0], lam_, 0.0)
     big = np.argmax(np.abs(U), axis=0)                       # largest component positive
     U = U * np.where(U[big, np.arange(d)] < 0, -1.0, 1.0)[None, :]
     return U * np.sqrt(lam_)[None, :]

@@ -1046,9 +1046,13 @@ __device__ __forceinline__ void eigen_factor(double (*A)[kLd], double (*V0)[kLd]
     }
   }
   sync();
+  // eigenvalues below 1e-12 of the largest are the rounding noise of a singular
+  // covariance (a re-sampled model with fewer distinct members than dimensions): zero
+  const double lmax = Ac[order[0]][order[0]];
   for (int r = tid; r < d; r += NT) {
     const int c = order[r];
-    const double ev = Ac[c][c] > 0.0 ? sqrt(Ac[c][c]) : 0.0;
+    const double lc = Ac[c][c];
+    const double ev = (lc > 0.0 && lc > 1e-12 * lmax) ? sqrt(lc) : 0.0;
     int big = 0;
     for (int a = 1; a < d; ++a)
       if (fabs(Vc[a][c]) > fabs(Vc[big][c])) big = a;

