@@ -331,6 +331,25 @@ rjsmc_status rjsmc_mutate(rjsmc_ctx *ctx, const rjsmc_mutate_args *args, rjsmc_p
                           rjsmc_particles *grad_cur, rjsmc_particles *grad_prop, int64_t *stats,
                           rjsmc_stream stream);
 
+/* Allocation-free variant of rjsmc_mutate, for callers that cannot allocate device
+ * memory at the time of the call: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, behaviour and results as
+ * rjsmc_mutate (bit-identical), except that the per-particle scratch of the sweeps
+ * (proposal mask, move type, gradient validity, adaptive-birth correction, evaluation
+ * order) lives in a static device array of the library instead of the context's
+ * workspace, so the context may have been created with max_particles = 0.  That array
+ * holds RJSMC_NOALLOC_MAX_PARTICLES particles (about 6 MiB per GPU, kept until the
+ * process ends); a larger state->n gives RJSMC_E_INVALID before anything is enqueued.
+ * Every call on one GPU uses that GPU's one array: calls that overlap on a GPU (other
+ * streams, other threads, other contexts) race and must be serialised by the caller.
+ * The call allocates nothing, also not on the host side of the runtime. */
+#define RJSMC_NOALLOC_MAX_PARTICLES 262144
+rjsmc_status rjsmc_mutate_noalloc(rjsmc_ctx *ctx, const rjsmc_mutate_args *args, rjsmc_particles *state,
+                                  double *ll, rjsmc_particles *scratch, double *ll_scratch,
+                                  const double *gamma, const int32_t *active, const double *y_obs,
+                                  rjsmc_particles *grad_cur, rjsmc_particles *grad_prop, int64_t *stats,
+                                  rjsmc_stream stream);
+
 /* Posterior summaries of a population (Section 2.3.3 and the case studies), per sounding:
  *  - model_count[s][k]: particles in model k (pi_T(k | y) = count / N, Section 3.2.1);
  *  - log_bfipd[s]: log of the grouped Bayes factor of chargeable (lambda >= 1) versus

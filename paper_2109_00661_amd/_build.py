@@ -10,7 +10,7 @@ LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "librjsmc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["host.cpp", "forward.hip", "adjoint.hip", "smc.hip"]
+SOURCES = ["host.cpp", "forward.hip", "adjoint.hip", "smc.hip", "noalloc.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", os.path.join(ROOT, "include"),
           "-I", CSRC, "-Wall", "-Wno-unused-function",
           # no packed FP32 instructions in any kernel

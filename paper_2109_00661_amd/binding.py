@@ -87,6 +87,7 @@ class Archive(ctypes.Structure):
 
 
 MAX_ARCHIVE = 64
+RJSMC_NOALLOC_MAX_PARTICLES = 262144   # rows of the static scratch of rjsmc_mutate_noalloc
 
 
 class Tuning(ctypes.Structure):
@@ -137,6 +138,11 @@ _SIGS = {
                                     ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Particles),
                                     ctypes.POINTER(Particles), ctypes.c_void_p, ctypes.c_void_p]),
+    "rjsmc_mutate_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MutateArgs), ctypes.POINTER(Particles),
+                                            ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.POINTER(Particles), ctypes.POINTER(Particles), ctypes.c_void_p,
+                                            ctypes.c_void_p]),
     "rjsmc_counter_add": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "rjsmc_scale_bisect": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BisectArgs), ctypes.c_void_p]),
     "rjsmc_summarize": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.POINTER(SummaryArgs),
@@ -383,7 +389,10 @@ class Context:
 
     def mutate(self, state, ll, scratch, ll_scratch, gamma, active, y_obs, stats, *, seed, step, n_moves, n_sound,
                prior, move_prob, z_move_sd, rw_scale, factors, mala_eps=0.0, grad_cur=None, grad_prop=None,
-               stream=None, step_dev=None, rw_scale_dev=None, stats_sound=None, trial=0, zca_birth=False):
+               stream=None, step_dev=None, rw_scale_dev=None, stats_sound=None, trial=0, zca_birth=False,
+               noalloc=False):
+        """rjsmc_mutate, or with noalloc=True rjsmc_mutate_noalloc (the library's static
+        scratch instead of the context's workspace)."""
         a = MutateArgs()
         a.seed, a.step, a.n_moves, a.n_sound = seed, step, n_moves, n_sound
         for t in range(N_MOVES):
@@ -399,9 +408,9 @@ class Context:
         ss, sq = particles_struct(state), particles_struct(scratch)
         gc = ctypes.byref(particles_struct(grad_cur)) if grad_cur is not None else None
         gp = ctypes.byref(particles_struct(grad_prop)) if grad_prop is not None else None
-        _check(lib().rjsmc_mutate(self._ptr, ctypes.byref(a), ctypes.byref(ss), _ptr(ll), ctypes.byref(sq),
-                                  _ptr(ll_scratch), _ptr(gamma), _ptr(active), _ptr(y_obs), gc, gp, _ptr(stats),
-                                  _stream_handle(stream)))
+        fn = lib().rjsmc_mutate_noalloc if noalloc else lib().rjsmc_mutate
+        _check(fn(self._ptr, ctypes.byref(a), ctypes.byref(ss), _ptr(ll), ctypes.byref(sq), _ptr(ll_scratch),
+                  _ptr(gamma), _ptr(active), _ptr(y_obs), gc, gp, _ptr(stats), _stream_handle(stream)))
 
 
 def empty_device_population(n, kmax_cond, kmax_charg, n_per_sounding=0, device="cuda"):

@@ -220,6 +220,9 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
 
   hipError_t e = hipSetDevice(device);
   if (e != hipSuccess) return hip_fail(e, "rjsmc_create: hipSetDevice");
+  // the address of the device's copy of the static scratch of rjsmc_mutate_noalloc (once
+  // per device); a failure is reported by that entry point, the context works without it
+  (void)rjsmc::static_scratch_init(device);
 
   rjsmc_ctx *c = new rjsmc_ctx();
   c->device = device;
@@ -398,26 +401,40 @@ static rjsmc_status check_particles(const rjsmc_ctx *c, const rjsmc_particles *p
   return RJSMC_OK;
 }
 
+// The context's own workspace (empty when it was created with max_particles = 0).
+static rjsmc::MutateWorkspace ctx_workspace(const rjsmc_ctx *c) {
+  rjsmc::MutateWorkspace w;
+  w.mask = c->work_mask;
+  w.type = c->work_type;
+  w.gvalid = c->work_gvalid;
+  w.perm = c->work_perm;
+  w.cnt = c->work_cnt;
+  w.lq = c->work_lq;
+  w.n = c->work_perm ? c->work_n : 0;
+  return w;
+}
+
 // Tile shape of a forward launch over dp from the context's tuning; a layer-capacity
 // order is computed first (on the same stream) when the tuning asks for one and the
 // workspace holds dp.n particles.
-static hipError_t forward_tiles(const rjsmc_ctx *c, const rjsmc::DevParticles &dp, const rjsmc_tuning &t,
+static hipError_t forward_tiles(const rjsmc::DevParticles &dp, const rjsmc_tuning &t, const rjsmc::MutateWorkspace &ws,
                                 hipStream_t stream, rjsmc::ForwardTiles *tiles) {
   tiles->waves_per_block = t.waves_per_block;
   tiles->waves_per_particle = t.waves_per_particle;
   tiles->perm = nullptr;
-  if (t.layer_sort && c->work_perm && dp.n <= c->work_n && dp.n > 0) {
-    const hipError_t e = rjsmc::launch_layer_sort(dp, c->work_cnt, c->work_perm, stream);
+  if (t.layer_sort && ws.perm && dp.n <= ws.n && dp.n > 0) {
+    const hipError_t e = rjsmc::launch_layer_sort(dp, ws.cnt, ws.perm, stream);
     if (e != hipSuccess) return e;
-    tiles->perm = c->work_perm;
+    tiles->perm = ws.perm;
   }
   return hipSuccess;
 }
 
 static hipError_t run_forward(const rjsmc_ctx *c, const rjsmc::DevParticles &dp, const rjsmc_tuning &t, double *resp,
-                              const double *y_obs, double *ll, hipStream_t stream) {
+                              const double *y_obs, double *ll, hipStream_t stream,
+                              const rjsmc::MutateWorkspace *ws = nullptr) {
   rjsmc::ForwardTiles tiles;
-  hipError_t e = forward_tiles(c, dp, t, stream, &tiles);
+  hipError_t e = forward_tiles(dp, t, ws ? *ws : ctx_workspace(c), stream, &tiles);
   if (e == hipSuccess)
     e = rjsmc::launch_forward(c->dev, dp, c->kmax_cond, c->kmax_charg, c->precision, resp, y_obs, ll, stream, tiles);
   return e;
@@ -662,12 +679,13 @@ static rjsmc_status grad_buffer(const rjsmc_ctx *c, const rjsmc_particles *g, co
   return RJSMC_OK;
 }
 
-extern "C" rjsmc_status rjsmc_mutate(rjsmc_ctx *c, const rjsmc_mutate_args *a, rjsmc_particles *state, double *ll,
-                                     rjsmc_particles *scratch, double *ll_scratch, const double *gamma,
-                                     const int32_t *active, const double *y_obs, rjsmc_particles *grad_cur,
-                                     rjsmc_particles *grad_prop, int64_t *stats, rjsmc_stream stream) {
-  const char *who = "rjsmc_mutate";
-  if (!c || !a) return fail(RJSMC_E_INVALID, "%s: NULL argument", who);
+// The sweeps of rjsmc_mutate with the per-particle scratch `ws` (the context's workspace
+// or the static scratch); allocates nothing.
+static rjsmc_status mutate_impl(const char *who, rjsmc_ctx *c, const rjsmc_mutate_args *a, rjsmc_particles *state,
+                                double *ll, rjsmc_particles *scratch, double *ll_scratch, const double *gamma,
+                                const int32_t *active, const double *y_obs, rjsmc_particles *grad_cur,
+                                rjsmc_particles *grad_prop, int64_t *stats, rjsmc_stream stream,
+                                const rjsmc::MutateWorkspace &ws, const char *ws_name) {
   rjsmc::DevParticles ds, dq;
   rjsmc_status st = check_particles(c, state, who, &ds);
   if (st == RJSMC_OK) st = check_particles(c, scratch, who, &dq);
@@ -676,9 +694,8 @@ extern "C" rjsmc_status rjsmc_mutate(rjsmc_ctx *c, const rjsmc_mutate_args *a, r
     return fail(RJSMC_E_INVALID, "%s: DECOUPLED layout only", who);
   if (scratch->n != state->n || scratch->n_per_sounding != state->n_per_sounding)
     return fail(RJSMC_E_INVALID, "%s: scratch and state differ in shape", who);
-  if (state->n > c->work_n)
-    return fail(RJSMC_E_INVALID, "%s: n=%lld exceeds the context's max_particles=%lld", who, (long long)state->n,
-                (long long)c->work_n);
+  if (state->n > ws.n || !ws.mask)
+    return fail(RJSMC_E_INVALID, "%s: n=%lld exceeds %s=%lld", who, (long long)state->n, ws_name, (long long)ws.n);
   if (!ll || !ll_scratch || !gamma || !y_obs) return fail(RJSMC_E_INVALID, "%s: NULL array", who);
   if ((st = check_prior(&a->prior, who)) != RJSMC_OK) return st;
   if ((st = check_soundings(state, a->n_sound, who)) != RJSMC_OK) return st;
@@ -709,38 +726,68 @@ extern "C" rjsmc_status rjsmc_mutate(rjsmc_ctx *c, const rjsmc_mutate_args *a, r
   hipError_t e = hipSetDevice(c->device);
   hipStream_t s = (hipStream_t)stream;
   rjsmc::DevParticles prop1 = dq, prop2 = dq, cur2 = ds;
-  prop1.mask = c->work_mask;
+  prop1.mask = ws.mask;
   prop1.mask_value = 1;
-  prop2.mask = c->work_mask;
+  prop2.mask = ws.mask;
   prop2.mask_value = 2;
-  cur2.mask = c->work_mask;
+  cur2.mask = ws.mask;
   cur2.mask_value = 2;
   if (a->trial < 0 || a->trial > 1000) return fail(RJSMC_E_INVALID, "%s: trial=%d outside 0..1000", who, a->trial);
   // Langevin moves keep each particle's current gradient from sweep to sweep until an
   // accepted move of another type changes the state
-  int32_t *gvalid = mala ? c->work_gvalid : nullptr;
+  int32_t *gvalid = mala ? ws.gvalid : nullptr;
   rjsmc::DevParticlesW gcw_state = mala ? writable(gcd) : rjsmc::DevParticlesW();
   if (e == hipSuccess && gvalid) e = rjsmc::launch_fill_i32(gvalid, ds.n, 0, s);
   for (int r0 = 0; r0 < a->n_moves && e == hipSuccess; ++r0) {
     const int r = a->trial * (1 << 20) + r0;   // random-number move index
     if (mala) {
-      e = rjsmc::launch_draw_types(*a, r, ds, sh.kc, sh.km, c->work_mask, c->work_type, active, gvalid, s);
+      e = rjsmc::launch_draw_types(*a, r, ds, sh.kc, sh.km, ws.mask, ws.type, active, gvalid, s);
       if (e == hipSuccess)   // gradients of the current states of the particles taking a Langevin step
         e = rjsmc::launch_loglik_grad(c->dev, cur2, c->kmax_cond, c->kmax_charg, y_obs, ll_scratch, gcw, s);
     }
     if (e == hipSuccess)   // without gradient moves the proposal kernel draws the types itself
-      e = rjsmc::launch_propose(sh, *a, r, ds, writable(dq), c->work_mask, c->work_type, gamma, mala ? &gcd : nullptr,
-                                gvalid, c->work_lq, active, !mala, s);
+      e = rjsmc::launch_propose(sh, *a, r, ds, writable(dq), ws.mask, ws.type, gamma, mala ? &gcd : nullptr,
+                                gvalid, ws.lq, active, !mala, s);
     if (e == hipSuccess)
-      e = run_forward(c, prop1, c->tuning, nullptr, y_obs, ll_scratch, s);
+      e = run_forward(c, prop1, c->tuning, nullptr, y_obs, ll_scratch, s, &ws);
     if (e == hipSuccess && mala)
       e = rjsmc::launch_loglik_grad(c->dev, prop2, c->kmax_cond, c->kmax_charg, y_obs, ll_scratch, gpw, s);
     if (e == hipSuccess)
-      e = rjsmc::launch_accept(sh, *a, r, writable(ds), ll, dq, ll_scratch, c->work_mask, c->work_type, gamma,
-                               mala ? &gcw_state : nullptr, mala ? &gpd : nullptr, gvalid, stats, c->work_lq, s);
+      e = rjsmc::launch_accept(sh, *a, r, writable(ds), ll, dq, ll_scratch, ws.mask, ws.type, gamma,
+                               mala ? &gcw_state : nullptr, mala ? &gpd : nullptr, gvalid, stats, ws.lq, s);
   }
-  if (e != hipSuccess) return hip_fail(e, "rjsmc_mutate: launch");
+  if (e != hipSuccess) {
+    char what[96];
+    snprintf(what, sizeof what, "%s: launch", who);
+    return hip_fail(e, what);
+  }
   return RJSMC_OK;
+}
+
+extern "C" rjsmc_status rjsmc_mutate(rjsmc_ctx *c, const rjsmc_mutate_args *a, rjsmc_particles *state, double *ll,
+                                     rjsmc_particles *scratch, double *ll_scratch, const double *gamma,
+                                     const int32_t *active, const double *y_obs, rjsmc_particles *grad_cur,
+                                     rjsmc_particles *grad_prop, int64_t *stats, rjsmc_stream stream) {
+  const char *who = "rjsmc_mutate";
+  if (!c || !a) return fail(RJSMC_E_INVALID, "%s: NULL argument", who);
+  const rjsmc::MutateWorkspace ws = ctx_workspace(c);
+  return mutate_impl(who, c, a, state, ll, scratch, ll_scratch, gamma, active, y_obs, grad_cur, grad_prop, stats,
+                     stream, ws, "the context's max_particles");
+}
+
+extern "C" rjsmc_status rjsmc_mutate_noalloc(rjsmc_ctx *c, const rjsmc_mutate_args *a, rjsmc_particles *state,
+                                             double *ll, rjsmc_particles *scratch, double *ll_scratch,
+                                             const double *gamma, const int32_t *active, const double *y_obs,
+                                             rjsmc_particles *grad_cur, rjsmc_particles *grad_prop, int64_t *stats,
+                                             rjsmc_stream stream) {
+  const char *who = "rjsmc_mutate_noalloc";
+  if (!c || !a) return fail(RJSMC_E_INVALID, "%s: NULL argument", who);
+  rjsmc::MutateWorkspace ws;
+  if (!rjsmc::static_scratch(c->device, &ws))
+    return fail(RJSMC_E_DEVICE, "%s: the static scratch of device %d is unavailable: %s", who, c->device,
+                hipGetErrorString(rjsmc::static_scratch_status(c->device)));
+  return mutate_impl(who, c, a, state, ll, scratch, ll_scratch, gamma, active, y_obs, grad_cur, grad_prop, stats,
+                     stream, ws, "RJSMC_NOALLOC_MAX_PARTICLES");
 }
 
 // ---------------------------------------------------------------------------- tuning

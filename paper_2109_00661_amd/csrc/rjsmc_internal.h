@@ -156,6 +156,22 @@ hipError_t launch_accept(const SmcShape &sh, const rjsmc_mutate_args &a, int mov
                          hipStream_t stream);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t stream);
 
+// Per-particle scratch of a mutation sweep (and of a layer-sorted forward launch): the
+// context's workspace, or the library's static device scratch (noalloc.hip).
+struct MutateWorkspace {
+  int32_t *mask = nullptr, *type = nullptr, *gvalid = nullptr, *perm = nullptr;
+  int *cnt = nullptr;       // 2 kMaxLayers counting-sort counters
+  double *lq = nullptr;
+  int64_t n = 0;            // particles it holds
+};
+// Looks up, once per device and with that device current, the address of the static
+// scratch on `device` (hipGetSymbolAddress); later calls return at once.
+hipError_t static_scratch_init(int device);
+// The static scratch of `device` (false if static_scratch_init has not succeeded there).
+bool static_scratch(int device, MutateWorkspace *ws);
+// Why the static scratch of `device` is unavailable (hipSuccess if it is available).
+hipError_t static_scratch_status(int device);
+
 // Host-side construction of the frequency-to-time matrix (host.cpp).
 void build_time_kernel(const double *freq_hz, int n_freq, const double *t_open,
                        const double *t_close, int n_gate, double *K_out);
