@@ -854,3 +854,32 @@ def posterior_summary(p, kmax_cond, kmax_charg, n_sound, depths):
         out["mean_m"].append(m.mean(axis=0))
         out["p_chargeable"].append((m > 0).mean(axis=0))
     return {k: np.array(v) for k, v in out.items()}
+
+
+# ------------------------------------------------------- posterior predictive summaries
+def posterior_predictive(resp, n_sound, d, eps_an, eps_mn):
+    """Summaries of the posterior predictive distribution of each sounding (Section 4.1:
+    posterior predictive checks; Section 4.2: the data standardised to the PPD at each
+    gate).  Replicated data are y~ = y^theta + e with e ~ N(0, Sigma(y^theta)), the
+    noise model of Section 2.3.2, and theta drawn from the final population (equal
+    weights).  Per sounding s and gate g:
+      mean_g = E[y~_g] = (1/N) sum_i y_ig,
+      var_g  = Var[y~_g] = (1/N) sum_i (y_ig - mean_g)^2 + (1/N) sum_i Sigma_gg(theta_i)
+               (law of total variance), sd_g = sqrt(var_g),
+      z_g    = (d_sg - mean_g) / sd_g.
+    resp: [n][n_gate] responses of the population (soundings contiguous); d:
+    [n_sound][n_gate].  Returns (mean, sd, z), each [n_sound][n_gate]."""
+    resp = np.asarray(resp, dtype=np.float64)
+    n, ng = resp.shape
+    N = n // n_sound
+    d = np.asarray(d, dtype=np.float64).reshape(n_sound, ng)
+    mean = np.zeros((n_sound, ng))
+    sd = np.zeros((n_sound, ng))
+    for s in range(n_sound):
+        y = resp[s * N:(s + 1) * N]
+        mu = y.sum(axis=0) / N
+        var_theta = ((y - mu[None, :]) ** 2).sum(axis=0) / N
+        noise = (np.asarray(eps_an)[None, :] ** 2 + (eps_mn * y) ** 2).sum(axis=0) / N
+        mean[s] = mu
+        sd[s] = np.sqrt(var_theta + noise)
+    return mean, sd, (d - mean) / sd

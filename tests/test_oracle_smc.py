@@ -558,3 +558,50 @@ def test_zca_moves_preserve_the_prior_at_zero_temperature(monkeypatch):
     ck2 = np.bincount(p2["kappa"], minlength=5)
     cl2 = np.bincount(p2["lambda_"], minlength=4)
     assert min(stats.chisquare(ck2).pvalue, stats.chisquare(cl2).pvalue) < 1e-6, (ck2, cl2)
+
+
+# ------------------------------------------------------- posterior predictive summaries
+def test_posterior_predictive_identical_particles():
+    """A population of one repeated response: the PPD is the noise model at that
+    response (mean y, sd s(y)), and z is the textbook standardised residual."""
+    from oracle import smc
+    rng = np.random.default_rng(4)
+    y = rng.uniform(-5, 1e4, 20)
+    eps_an, eps_mn = np.full(20, 0.1), 0.03
+    d = y + rng.standard_normal(20)
+    mean, sd, z = smc.posterior_predictive(np.tile(y, (37, 1)), 1, d, eps_an, eps_mn)
+    np.testing.assert_allclose(mean[0], y, rtol=1e-14)
+    np.testing.assert_allclose(sd[0], np.sqrt(eps_an ** 2 + (eps_mn * y) ** 2), rtol=1e-14)
+    np.testing.assert_allclose(z[0], (d - y) / np.sqrt(eps_an ** 2 + (eps_mn * y) ** 2), rtol=1e-12, atol=1e-10)
+
+
+def test_posterior_predictive_two_members_closed_form():
+    from oracle import smc
+    y1, y2 = np.array([3.0, -2.0, 100.0]), np.array([1.0, 2.0, 50.0])
+    eps_an, eps_mn = np.array([0.5, 0.1, 1.0]), 0.1
+    d = np.array([2.5, 0.0, 80.0])
+    mean, sd, z = smc.posterior_predictive(np.stack([y1, y2]), 1, d, eps_an, eps_mn)
+    s1, s2 = eps_an ** 2 + (eps_mn * y1) ** 2, eps_an ** 2 + (eps_mn * y2) ** 2
+    var = ((y1 - y2) / 2) ** 2 + (s1 + s2) / 2
+    np.testing.assert_allclose(mean[0], (y1 + y2) / 2, rtol=1e-15)
+    np.testing.assert_allclose(sd[0], np.sqrt(var), rtol=1e-14)
+    np.testing.assert_allclose(z[0], (d - (y1 + y2) / 2) / np.sqrt(var), rtol=1e-13)
+
+
+def test_posterior_predictive_matches_replicated_data():
+    """Brute force: draw a particle uniformly, then replicated data from the noise model
+    at its response; the sample mean and sd of 400,000 replicates match the summaries
+    within Monte Carlo error (two soundings, soundings kept apart)."""
+    from oracle import smc
+    rng = np.random.default_rng(8)
+    ng, N = 6, 50
+    resp = np.concatenate([rng.normal(10.0, 3.0, (N, ng)), rng.normal(-2.0, 0.5, (N, ng))])
+    eps_an, eps_mn = np.full(ng, 0.3), 0.05
+    d = np.zeros((2, ng))
+    mean, sd, _ = smc.posterior_predictive(resp, 2, d, eps_an, eps_mn)
+    R = 400000
+    for s in range(2):
+        pick = resp[s * N + rng.integers(0, N, R)]
+        rep = pick + rng.standard_normal((R, ng)) * np.sqrt(eps_an ** 2 + (eps_mn * pick) ** 2)
+        assert np.all(np.abs(rep.mean(axis=0) - mean[s]) <= 5 * sd[s] / np.sqrt(R))
+        np.testing.assert_allclose(rep.std(axis=0), sd[s], rtol=0.01)
