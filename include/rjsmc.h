@@ -377,6 +377,29 @@ typedef struct {
 rjsmc_status rjsmc_summarize(rjsmc_ctx *ctx, const rjsmc_particles *p, const rjsmc_summary_args *args,
                              rjsmc_stream stream);
 
+/* Posterior predictive summaries of each sounding's population (Section 4.1: posterior
+ * predictive checks; Section 4.2: the data standardised to the posterior predictive
+ * distribution at each gate).  Replicated data are y~ = y(theta) + e, e ~ N(0, Sigma(y)) with
+ * the noise model of Section 2.3.2 and theta drawn from the population (equal weights, as
+ * after the last mutation of Algorithm 1).  Per sounding s and gate g:
+ *   mean[s][g] = (1/N) sum_i y_ig,
+ *   sd[s][g]   = sqrt((1/N) sum_i (y_ig - mean)^2 + (1/N) sum_i (eps_an_g^2 + (eps_mn y_ig)^2))
+ *                (law of total variance),
+ *   z[s][g]    = (y_obs[s][g] - mean[s][g]) / sd[s][g]   (|z| <= 1 within one sd).
+ * The forward responses of every particle are written to resp first (the forward model
+ * with the context's tile shape); sums run over the sounding's particles in index order.
+ * A particle with an invalid stack has NaN responses, which make its sounding's
+ * summaries NaN.  All pointers are device memory; z may be NULL. */
+typedef struct {
+  int32_t n_sound;
+  const double *y_obs;          /* [n_sound][n_gate] */
+  double *resp;                 /* [n][n_gate], receives the particles' responses */
+  double *mean, *sd, *z;        /* [n_sound][n_gate] */
+} rjsmc_ppd_args;
+
+rjsmc_status rjsmc_posterior_predictive(rjsmc_ctx *ctx, const rjsmc_particles *p, const rjsmc_ppd_args *args,
+                                        rjsmc_stream stream);
+
 /* One bisection step per sounding on log(scale) of the within-model random walk, from
  * trial proposals at the bracket's midpoint (Section 3.2.2: the step is scaled to reach a
  * target acceptance rate).  init = 1 starts the bracket [log lo0, log hi0]; otherwise a

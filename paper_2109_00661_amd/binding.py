@@ -81,6 +81,11 @@ class SummaryArgs(ctypes.Structure):
                 ("mean_log10_sigma", ctypes.c_void_p), ("mean_m", ctypes.c_void_p), ("p_chargeable", ctypes.c_void_p)]
 
 
+class PpdArgs(ctypes.Structure):
+    _fields_ = [("n_sound", ctypes.c_int32), ("y_obs", ctypes.c_void_p), ("resp", ctypes.c_void_p),
+                ("mean", ctypes.c_void_p), ("sd", ctypes.c_void_p), ("z", ctypes.c_void_p)]
+
+
 class Archive(ctypes.Structure):
     _fields_ = [("pop", Particles), ("ll", ctypes.c_void_p), ("gamma", ctypes.c_void_p), ("log_z", ctypes.c_void_p),
                 ("n_slots", ctypes.c_int32), ("n_used", ctypes.c_int32)]
@@ -147,6 +152,8 @@ _SIGS = {
     "rjsmc_scale_bisect": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BisectArgs), ctypes.c_void_p]),
     "rjsmc_summarize": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.POINTER(SummaryArgs),
                                        ctypes.c_void_p]),
+    "rjsmc_posterior_predictive": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.POINTER(PpdArgs),
+                                                  ctypes.c_void_p]),
     "rjsmc_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "rjsmc_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "rjsmc_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Particles), ctypes.c_void_p, ctypes.c_void_p,
@@ -288,6 +295,21 @@ class Context:
                         _ptr(out["p_chargeable"]) if nd else None)
         ps = particles_struct(p)
         _check(lib().rjsmc_summarize(self._ptr, ctypes.byref(ps), ctypes.byref(a), _stream_handle(stream)))
+        return out
+
+    def posterior_predictive(self, p, n_sound, y_obs, stream=None):
+        """Posterior predictive mean, sd and standardised data [S][n_gate] of each
+        sounding's population, and the particles' responses [n][n_gate]."""
+        import torch
+        dev = p["kappa"].device
+        n = int(p["kappa"].shape[0])
+        f = lambda *shape: torch.empty(shape, dtype=torch.float64, device=dev)
+        out = {"resp": f(n, self.n_gate), "mean": f(n_sound, self.n_gate), "sd": f(n_sound, self.n_gate),
+               "z": f(n_sound, self.n_gate)}
+        y = y_obs.reshape(n_sound, self.n_gate).contiguous()
+        a = PpdArgs(n_sound, _ptr(y), _ptr(out["resp"]), _ptr(out["mean"]), _ptr(out["sd"]), _ptr(out["z"]))
+        ps = particles_struct(p)
+        _check(lib().rjsmc_posterior_predictive(self._ptr, ctypes.byref(ps), ctypes.byref(a), _stream_handle(stream)))
         return out
 
     def scale_bisect(self, n_sound, init, target, lo0, hi0, log_lo, log_hi, scale, stats_sound, stream=None):

@@ -902,6 +902,25 @@ extern "C" rjsmc_status rjsmc_summarize(rjsmc_ctx *c, const rjsmc_particles *p, 
   return RJSMC_OK;
 }
 
+extern "C" rjsmc_status rjsmc_posterior_predictive(rjsmc_ctx *c, const rjsmc_particles *p, const rjsmc_ppd_args *a,
+                                                   rjsmc_stream stream) {
+  const char *who = "rjsmc_posterior_predictive";
+  if (!c || !a) return fail(RJSMC_E_INVALID, "%s: NULL argument", who);
+  rjsmc::DevParticles dp;
+  rjsmc_status st = check_particles(c, p, who, &dp);
+  if (st != RJSMC_OK) return st;
+  const int64_t nps = p->n_per_sounding > 0 ? p->n_per_sounding : p->n;
+  if (a->n_sound < 1 || nps * (int64_t)a->n_sound != p->n)
+    return fail(RJSMC_E_INVALID, "%s: n_sound=%d does not tile n=%lld", who, a->n_sound, (long long)p->n);
+  if (!a->y_obs || !a->resp || !a->mean || !a->sd) return fail(RJSMC_E_INVALID, "%s: NULL array", who);
+  hipError_t e = hipSetDevice(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  if (e == hipSuccess) e = run_forward(c, dp, c->tuning, a->resp, nullptr, nullptr, s);
+  if (e == hipSuccess) e = rjsmc::launch_ppd(c->dev, dp, a->n_sound, a->resp, a->y_obs, a->mean, a->sd, a->z, s);
+  if (e != hipSuccess) return hip_fail(e, "rjsmc_posterior_predictive: launch");
+  return RJSMC_OK;
+}
+
 extern "C" rjsmc_status rjsmc_scale_bisect(rjsmc_ctx *c, const rjsmc_bisect_args *a, rjsmc_stream stream) {
   const char *who = "rjsmc_scale_bisect";
   if (!c || !a) return fail(RJSMC_E_INVALID, "%s: NULL argument", who);

@@ -117,6 +117,8 @@ hipError_t launch_loglik_grad(const DevSystem &s, const DevParticles &p, int kma
 hipError_t launch_counter_add(int32_t *counter, int32_t delta, hipStream_t stream);
 hipError_t launch_scale_bisect(const rjsmc_bisect_args &a, hipStream_t stream);
 hipError_t launch_summary(const SmcShape &sh, const DevParticles &p, const rjsmc_summary_args &a, hipStream_t stream);
+hipError_t launch_ppd(const DevSystem &sys, const DevParticles &p, int n_sound, const double *resp,
+                      const double *y_obs, double *mean, double *sd, double *z, hipStream_t stream);
 hipError_t launch_init_prior(const DevParticlesW &p, const SmcShape &sh, const rjsmc_prior &pr, uint64_t seed,
                              hipStream_t stream);
 hipError_t launch_reweight_resample(const SmcShape &sh, const rjsmc_reweight_args &a, const DevParticles &in,

@@ -1920,6 +1920,41 @@ hipError_t launch_summary(const SmcShape &sh, const DevParticles &p, const rjsmc
   return hipGetLastError();
 }
 
+// ------------------------------------------------- posterior predictive summaries ---
+// One thread per (sounding, gate); the sounding's particles are summed in index order
+// (two passes: the mean, then the spread about it and the noise variances).
+__global__ __launch_bounds__(256) void ppd_kernel(int64_t N, int n_sound, int ng, const double *resp,
+                                                  const double *eps_an2, double eps_mn, const double *y_obs,
+                                                  double *mean, double *sd, double *z) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n_sound * ng) return;
+  const int64_t s = t / ng;
+  const int g = (int)(t - s * ng);
+  const double *y = resp + s * N * ng + g;
+  double sum = 0.0;
+  for (int64_t i = 0; i < N; ++i) sum += y[i * ng];
+  const double mu = sum / (double)N;
+  double spread = 0.0, noise = 0.0;
+  for (int64_t i = 0; i < N; ++i) {
+    const double yi = y[i * ng], dy = yi - mu, e = eps_mn * yi;
+    spread += dy * dy;
+    noise += eps_an2[g] + e * e;
+  }
+  const double sdv = sqrt(spread / (double)N + noise / (double)N);
+  mean[t] = mu;
+  sd[t] = sdv;
+  if (z) z[t] = (y_obs[t] - mu) / sdv;
+}
+
+hipError_t launch_ppd(const DevSystem &sys, const DevParticles &p, int n_sound, const double *resp,
+                      const double *y_obs, double *mean, double *sd, double *z, hipStream_t stream) {
+  const int64_t N = p.n_per_sounding > 0 ? p.n_per_sounding : p.n;
+  const int64_t items = (int64_t)n_sound * sys.n_gate;
+  hipLaunchKernelGGL(ppd_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, stream, N, n_sound, sys.n_gate,
+                     resp, sys.eps_an2, sys.eps_mn, y_obs, mean, sd, z);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ step-size bisection ---
 __global__ void scale_bisect_kernel(rjsmc_bisect_args a) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;

@@ -237,6 +237,11 @@ class RJSMCRun:
         self.ctx.check()
         return self
 
+    def posterior_predictive(self):
+        """Posterior predictive mean, sd and standardised data per sounding and gate of the
+        current population (device call)."""
+        return self.ctx.posterior_predictive(self.state, self.S, self.y_obs)
+
     def model_probabilities(self):
         """pi_T(k | y) = N_{T,k} / N per sounding (Section 3.2.1)."""
         k = self.state["kappa"].cpu().numpy() * (self.ctx.kmax_charg + 1) + self.state["lambda_"].cpu().numpy()

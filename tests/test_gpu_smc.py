@@ -654,3 +654,53 @@ def test_rjsmc_run_with_adaptive_birth(B, truth_data):
     for key in ("kappa", "lambda_", "phi_b", "phi", "z_cond", "m", "z_charg", "log10_tau", "c"):
         np.testing.assert_array_equal(a[key], b[key], err_msg=key)
     np.testing.assert_array_equal(runs[0].log_z.cpu().numpy(), runs[1].log_z.cpu().numpy())
+
+
+# ------------------------------------------------------- posterior predictive summaries
+def _ppd_check(B, ctx, system, K, p, n_sound, y):
+    from oracle import em, smc
+    dp = B.particles_to_device(p)
+    out = ctx.posterior_predictive(dp, n_sound, torch.as_tensor(y, device="cuda"))
+    ctx.check()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    resp = em.forward(p, system, K)
+    s = np.sqrt(em.noise_variance(resp, system["eps_an"][None, :], system["eps_mn"]))
+    assert np.all(np.abs(got["resp"] - resp) <= 1e-9 * np.maximum(np.abs(resp), s))
+    mean, sd, z = smc.posterior_predictive(resp, n_sound, y, system["eps_an"], system["eps_mn"])
+    scale = np.abs(resp).reshape(n_sound, -1, resp.shape[1]).mean(axis=1) + sd
+    assert np.all(np.abs(got["mean"] - mean) <= 1e-9 * scale)
+    np.testing.assert_allclose(got["sd"], sd, rtol=1e-9, atol=0)
+    assert np.all(np.abs(got["z"] - z) <= 1e-9 * (scale / sd + np.abs(z)))
+    return got, (mean, sd, z)
+
+
+def test_posterior_predictive_against_oracle(B, system, K_oracle, truth_data):
+    """Two soundings of 1,024 prior particles (every model and depth mix) and a third of
+    particles near the three-layer truth; the device's responses, PPD mean and sd and the
+    standardised data against the oracle's summaries of the oracle's responses."""
+    from oracle import smc
+    ctx = B.Context(system, precision="f64")
+    p = smc.init_population(17, 2048, KC, KM, PR)
+    p["n_per_sounding"] = 1024
+    y = np.stack([truth_data, 0.9 * truth_data])
+    _ppd_check(B, ctx, system, K_oracle, p, 2, y)
+    # near the truth: |z| mostly within a few sd
+    q = W.near_truth_merged(300, seed=3)
+    ctx_m = B.Context(W.system(kmax_cond=4, kmax_charg=0), precision="f64")
+    got, _ = _ppd_check(B, ctx_m, system, K_oracle, q, 1, truth_data[None, :])
+    assert np.median(np.abs(got["z"])) < 2.0
+
+
+def test_posterior_predictive_identical_particles(B, system, truth_data):
+    """A population of copies of one particle: the PPD is the noise model at its response."""
+    ctx = B.Context(system, precision="f64")
+    one = W.truth_three_layer()
+    p = W.take(one, np.zeros(77, dtype=int))
+    dp = B.particles_to_device(p)
+    out = ctx.posterior_predictive(dp, 1, torch.as_tensor(truth_data, device="cuda"))
+    ctx.check()
+    y = out["resp"].cpu().numpy()
+    assert np.all(y == y[0])
+    s = np.sqrt(system["eps_an"] ** 2 + (system["eps_mn"] * y[0]) ** 2)
+    np.testing.assert_allclose(out["mean"].cpu().numpy()[0], y[0], rtol=1e-13)
+    np.testing.assert_allclose(out["sd"].cpu().numpy()[0], s, rtol=1e-13)
