@@ -166,6 +166,10 @@ rjsmc_status rjsmc_loglik_grad(rjsmc_ctx *ctx, const rjsmc_particles *p, const d
  * prior draws use (i, 0, slot, 2^30).  Uniforms are (x + 0.5) 2^-53 for 53-bit x.
  * ---------------------------------------------------------------------------------- */
 
+/* Particles per sounding that the SMC calls accept (the paper's field inversions used
+ * 9,600; Section 4.2). */
+#define RJSMC_MAX_PER_SOUNDING 10240
+
 /* Bounds of the uniform priors (Section 2.3.1); depths are uniform on (0, z_max) of
  * the context and the counts are uniform on 0..kmax of the context. */
 typedef struct {
@@ -206,8 +210,8 @@ typedef struct {
  *  - out / ll_out receive the resampled population (out may not alias in).
  * Soundings with gamma >= 1 are copied unchanged.  active[s] (device, may be NULL) is
  * set to 1 if the sounding was re-weighted, else 0.  ancestors[n] (device) receives the
- * global index of each particle's ancestor.  Requires n_per_sounding <= 2048 and
- * n_models <= 128 (RJSMC_E_UNSUPPORTED otherwise). */
+ * global index of each particle's ancestor.  Requires n_per_sounding <=
+ * RJSMC_MAX_PER_SOUNDING and n_models <= 128 (RJSMC_E_UNSUPPORTED otherwise). */
 rjsmc_status rjsmc_reweight_resample(rjsmc_ctx *ctx, const rjsmc_reweight_args *args,
                                      const rjsmc_particles *in, const double *ll_in,
                                      rjsmc_particles *out, double *ll_out, double *gamma,

@@ -92,6 +92,7 @@ class Archive(ctypes.Structure):
 
 
 MAX_ARCHIVE = 64
+RJSMC_MAX_PER_SOUNDING = 10240           # particles per sounding of the SMC calls
 RJSMC_NOALLOC_MAX_PARTICLES = 262144   # rows of the static scratch of rjsmc_mutate_noalloc
 
 

@@ -534,8 +534,9 @@ static rjsmc_status check_soundings(const rjsmc_particles *p, int32_t n_sound, c
   const int64_t nps = p->n_per_sounding > 0 ? p->n_per_sounding : p->n;
   if (n_sound < 1 || nps * (int64_t)n_sound != p->n)
     return fail(RJSMC_E_INVALID, "%s: n_sound=%d does not tile n=%lld", who, n_sound, (long long)p->n);
-  if (nps > 2048)
-    return fail(RJSMC_E_UNSUPPORTED, "%s: %lld particles per sounding exceed 2048", who, (long long)nps);
+  if (nps > RJSMC_MAX_PER_SOUNDING)
+    return fail(RJSMC_E_UNSUPPORTED, "%s: %lld particles per sounding exceed %d", who, (long long)nps,
+                RJSMC_MAX_PER_SOUNDING);
   return RJSMC_OK;
 }
 

@@ -157,7 +157,8 @@ hipError_t launch_init_prior(const DevParticlesW &p, const SmcShape &sh, const r
 // ----------------------------------------------------------- reweight / resample -----
 constexpr int kRwThreads = 512;
 constexpr int kRwWaves = kRwThreads / kWave;
-constexpr int kMaxPerSounding = 2048;
+constexpr int kMaxPerSounding = 2048;         // register-resident runs (two kernels)
+constexpr int kMaxPerSoundingLarge = RJSMC_MAX_PER_SOUNDING;   // LDS-resident runs
 constexpr int kMaxModels = 128;
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -217,18 +218,49 @@ struct RwShared {
   int run_len;
 };
 
+// Large soundings (up to kMaxPerSoundingLarge = 10,240 members, 13 bytes of LDS each):
+// the log-likelihoods are written straight into sorted order (x holds ll, then ll minus
+// the model's maximum), the cumulative weights overwrite x in place, and the runs are
+// read from LDS at every evaluation instead of being held in registers.
+struct RwSharedLarge {
+  union {
+    double x[kMaxPerSoundingLarge];       // sorted order: ll, then ll - max of the model
+    uint64_t cum[kMaxPerSoundingLarge];   // cumulative weights, after the search
+  } u;
+  union {
+    int wc[kRwWaves][kMaxModels];
+    int16_t anc_l[kMaxPerSoundingLarge];
+  } v;
+  int16_t idx[kMaxPerSoundingLarge];
+  uint8_t mod[kMaxPerSoundingLarge];
+  int cnt[kMaxModels], base[kMaxModels], rb[kMaxModels + 1];
+  double mx[kMaxModels], s1[kMaxModels];
+  uint64_t U[kMaxModels];
+  double tail[kRwWaves][2 * kEvalK];
+  double wess[kRwWaves][kEvalK];
+  double e2[kExp2N];
+  int run_len;
+};
+// sorted-order values of either layout
+__device__ __forceinline__ double *xs_of(RwShared &sm) { return sm.x; }
+__device__ __forceinline__ double *xs_of(RwSharedLarge &sm) { return sm.u.x; }
+__device__ __forceinline__ const double *xs_of(const RwShared &sm) { return sm.x; }
+__device__ __forceinline__ const double *xs_of(const RwSharedLarge &sm) { return sm.u.x; }
+
 // A lane's run: model m (-1: no run), nv members with values x, seg the steps of the
 // segmented wave scan (dpp_scan_step) whose source lane holds a run of the same model,
 // fin on the model's last lane, w0 the wave of the model's first lane.
 struct RunLane {
   int m, nv, seg, w0;
   bool fin;
-  double x[kRunMax];
+  int xoff;                 // offset of the run's first value in sorted order
+  double x[kRunMax];        // the run's values (register-resident runs only)
 };
 
-template <typename SM>
+template <bool LOAD, typename SM>
 __device__ __forceinline__ RunLane run_of_lane(const SM &sm, int M) {
   RunLane r;
+  r.xoff = 0;
   const int t = threadIdx.x, lane = t & (kWave - 1);
   r.m = -1;
   r.nv = 0;
@@ -259,10 +291,13 @@ __device__ __forceinline__ RunLane run_of_lane(const SM &sm, int M) {
     if (rl >= (1 << k) && t - (1 << k) >= m0) r.seg |= 1 << k;
   if ((row == 1 || row == 3) && wb + 16 * row - 1 >= m0) r.seg |= 1 << 4;
   if (row >= 2 && wb + 31 >= m0) r.seg |= 1 << 5;
-  const double *xs = sm.x + sm.base[m] + q0;
+  r.xoff = sm.base[m] + q0;
+  if (LOAD) {
+    const double *xs = xs_of(sm) + r.xoff;
 #pragma unroll
-  for (int j = 0; j < kRunMax; ++j)
-    if (j < r.nv) r.x[j] = xs[j];
+    for (int j = 0; j < kRunMax; ++j)
+      if (j < r.nv) r.x[j] = xs[j];
+  }
   return r;
 }
 
@@ -329,21 +364,27 @@ __device__ __forceinline__ void eval_tess(SM &sm, const RunLane &r, const double
   double v[V];
 #pragma unroll
   for (int q = 0; q < V; ++q) v[q] = 0.0;
+  auto add = [&](double xj) {
 #pragma unroll
-  for (int j = 0; j < RM; ++j)
-    if (j < r.nv) {
-#pragma unroll
-      for (int c = 0; c < K; ++c) {
-        const double w = exp_tab(dg[c] * r.x[j], sm.e2);
-        v[c] += w;
-        v[K + c] = fma(w, w, v[K + c]);
-        if (DER) {
-          const double xw = r.x[j] * w;
-          v[2] += xw;
-          v[3] = fma(xw, w, v[3]);
-        }
+    for (int c = 0; c < K; ++c) {
+      const double w = exp_tab(dg[c] * xj, sm.e2);
+      v[c] += w;
+      v[K + c] = fma(w, w, v[K + c]);
+      if (DER) {
+        const double xw = xj * w;
+        v[2] += xw;
+        v[3] = fma(xw, w, v[3]);
       }
     }
+  };
+  if (RM > 0) {
+#pragma unroll
+    for (int j = 0; j < (RM > 0 ? RM : 1); ++j)
+      if (j < r.nv) add(r.x[j]);
+  } else {                              // runs read from LDS (large soundings)
+    const double *xs = xs_of(sm) + r.xoff;
+    for (int j = 0; j < r.nv; ++j) add(xs[j]);
+  }
   seg_scan<V>(v, r.seg);
   if (lane == kWave - 1)
 #pragma unroll
@@ -490,10 +531,12 @@ __device__ double next_increment(SM &sm, const RunLane &r, double H, double targ
   return lo;
 }
 
-// floor(((j << 53) + U) * T / (n << 53)) for j < n <= 2048, U < 2^53, T < 2^62.
+// floor(((j << 53) + U) * T / (n << 53)) for j < n <= 2^14, U < 2^53, T < 2^61.  A =
+// (j << 53) + U takes up to 67 bits (a_hi, a_lo); A T < n 2^53 T < 2^128.
 __device__ __forceinline__ uint64_t sys_threshold(uint64_t j, uint64_t U, uint64_t T, uint64_t n) {
-  const uint64_t A = (j << 53) + U;
-  const uint64_t lo = A * T, hi = __umul64hi(A, T);
+  const uint64_t a_lo = (j << 53) + U;                      // mod 2^64
+  const uint64_t a_hi = (j >> 11) + (a_lo < U ? 1u : 0u);   // with the carry of the addition
+  const uint64_t lo = a_lo * T, hi = __umul64hi(a_lo, T) + a_hi * T;
   // P1 = floor(A T / 2^53) as (p_hi, p_lo)
   const uint64_t p_lo = (hi << 11) | (lo >> 53);
   const uint64_t p_hi = hi >> 53;
@@ -539,8 +582,8 @@ __device__ __forceinline__ void st_off(T *base, uint32_t bytes, T v) {
   *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + bytes) = v;
 }
 
-// out[i] = in[anc_l[i]] for the members i = tid + k * kRwThreads of the sounding, every row
-// of the population, ll, and the global ancestor index.  Rows are addressed from the
+// out[i] = in[anc_l[i]] for the members i = first + tid + k * kRwThreads of the sounding,
+// every row of the population, ll, and the global ancestor index.  Rows are addressed from the
 // sounding's first element (a uniform base) with 32-bit byte offsets.  Loads are
 // unconditional (a lane past the sounding reads member 0) and issued in groups before
 // their stores, which are the only predicated accesses, so a group's loads are in flight
@@ -550,14 +593,14 @@ template <typename SM>
 __device__ __forceinline__ void copy_resampled(const SM &sm, const DevParticles &in,
                                                const double *__restrict__ ll_in, const DevParticlesW &out,
                                                double *__restrict__ ll_out, int32_t *__restrict__ anc, int64_t off,
-                                               int N, int rows_c, int rows_m, int rows_zm) {
+                                               int N, int rows_c, int rows_m, int rows_zm, int first = 0) {
   const int tid = threadIdx.x;
   const int64_t Si = in.stride, So = out.stride;
   uint32_t src[kCopyPer], dst[kCopyPer];   // member indices within the sounding
   bool ok[kCopyPer];
 #pragma unroll
   for (int k = 0; k < kCopyPer; ++k) {
-    const int i = tid + k * kRwThreads;
+    const int i = first + tid + k * kRwThreads;
     ok[k] = i < N;
     dst[k] = ok[k] ? (uint32_t)i : 0u;
     src[k] = ok[k] ? (uint32_t)sm.v.anc_l[i] : 0u;
@@ -622,17 +665,22 @@ __device__ __forceinline__ void copy_resampled(const SM &sm, const DevParticles 
 }
 
 // One workgroup per sounding: re-weight, evidence, within-model resampling, and the
-// resampled population written to out (each particle copied from its ancestor).  SMALL:
+// resampled population written to out (each particle copied from its ancestor).  KIND 0:
 // at most 512 particles per sounding, so every run is a single member (the evaluation
-// code is then compiled for runs of one).
-template <bool SMALL>
+// code is then compiled for runs of one); KIND 1: at most 2,048, runs of up to five
+// members in registers; KIND 2: at most 10,240, the large layout (runs read from LDS).
+template <int KIND>
 __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape sh, rjsmc_reweight_args a,
                                                                        DevParticles in, const double *ll_in,
                                                                        DevParticlesW out, double *ll_out,
                                                                        double *gamma, double *log_z,
                                                                        int32_t *active, int32_t *anc, int *flags,
                                                                        const double *exp2t) {
-  __shared__ RwShared sm;
+  constexpr bool LARGE = KIND == 2;
+  using SM = typename std::conditional<LARGE, RwSharedLarge, RwShared>::type;
+  constexpr int NMAX = LARGE ? kMaxPerSoundingLarge : kMaxPerSounding;
+  __shared__ SM sm;
+  double *xs = xs_of(sm);
   const bool dec = in.layout == RJSMC_LAYOUT_DECOUPLED;
   const int rows_c = sh.kc, rows_m = dec ? sh.km : sh.kc + 1, rows_zm = dec ? sh.km : 0;
   const int s = blockIdx.x;
@@ -641,33 +689,36 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
   const int M = sh.n_models;
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
   const double g0 = gamma[s];
+  if (N > NMAX) return;                 // the host never launches this (rejected before)
   if (!(g0 < 1.0)) {
     for (int i = tid; i < N; i += kRwThreads) sm.v.anc_l[i] = (int16_t)i;
     __syncthreads();
-    copy_resampled(sm, in, ll_in, out, ll_out, anc, off, N, rows_c, rows_m, rows_zm);
+    for (int first = 0; first < N; first += kCopyPer * kRwThreads)
+      copy_resampled(sm, in, ll_in, out, ll_out, anc, off, N, rows_c, rows_m, rows_zm, first);
     if (tid == 0 && active) active[s] = 0;
     return;
   }
-  // counts, models and log-likelihoods (loads first, then the LDS writes)
-  {
+  // counts, models and log-likelihoods (loads first, then the LDS writes); the large
+  // layout re-reads the log-likelihoods when it places the particles in sorted order
+  for (int first = 0; first < N; first += kCopyPer * kRwThreads) {
     int kap[kCopyPer], lam[kCopyPer];
     double llv[kCopyPer];
 #pragma unroll
     for (int k = 0; k < kCopyPer; ++k) {
-      const int i = tid + k * kRwThreads;
+      const int i = first + tid + k * kRwThreads;
       if (i < N) {
         kap[k] = in.kappa[off + i];
         lam[k] = in.lambda[off + i];
-        llv[k] = ll_in[off + i];
+        if (!LARGE) llv[k] = ll_in[off + i];
       }
     }
 #pragma unroll
     for (int k = 0; k < kCopyPer; ++k) {
-      const int i = tid + k * kRwThreads;
+      const int i = first + tid + k * kRwThreads;
       if (i < N) {
         const bool okc = kap[k] >= 0 && kap[k] <= sh.kc && lam[k] >= 0 && lam[k] <= sh.km;
         // a particle with counts outside the capacities is flagged and given -inf weight
-        sm.u.ll[i] = okc ? llv[k] : -HUGE_VAL;
+        if constexpr (!LARGE) sm.u.ll[i] = okc ? llv[k] : -HUGE_VAL;
         if (!okc) atomicOr(flags, kFlagCapacity);
         sm.mod[i] = (uint8_t)(okc ? kap[k] * (sh.km + 1) + lam[k] : 0);
       }
@@ -715,9 +766,18 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
     const bool v = i < N;
     const int m = v ? sm.mod[i] : 0;
     const uint64_t same = same_model_lanes(m, v, nbits);
+    double llp = 0.0;
+    if (LARGE && v) {                  // the log-likelihood for its sorted position
+      const int kk = in.kappa[off + i], lk = in.lambda[off + i];
+      const bool okc = kk >= 0 && kk <= sh.kc && lk >= 0 && lk <= sh.km;
+      llp = okc ? ll_in[off + i] : -HUGE_VAL;
+    }
     if (v) {
       const int pos = sm.base[m] + sm.v.wc[wave][m] + __popcll(same & below);
-      if (pos >= 0 && pos < N) sm.idx[pos] = (int16_t)i;
+      if (pos >= 0 && pos < N) {
+        sm.idx[pos] = (int16_t)i;
+        if (LARGE) xs[pos] = llp;
+      }
       if ((same & below) == 0) sm.v.wc[wave][m] += __popcll(same);
     }
   }
@@ -726,7 +786,12 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
   for (int m = wave; m < M; m += kRwWaves) {
     const int n = sm.cnt[m];
     double v = -HUGE_VAL;
-    for (int q = lane; q < n; q += kWave) v = fmax(v, sm.u.ll[sm.idx[sm.base[m] + q]]);
+    for (int q = lane; q < n; q += kWave) {
+      if constexpr (LARGE)
+        v = fmax(v, xs[sm.base[m] + q]);
+      else
+        v = fmax(v, sm.u.ll[sm.idx[sm.base[m] + q]]);
+    }
     v = wave_max(v);
     if (lane == 0) {
       sm.mx[m] = v;
@@ -740,14 +805,19 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
   for (int pos = tid; pos < N; pos += kRwThreads) {
     const int m = sm.mod[sm.idx[pos]];
     const double mx = sm.mx[m];
-    sm.x[pos] = mx > -HUGE_VAL ? sm.u.ll[sm.idx[pos]] - mx : -HUGE_VAL;
+    double llv;
+    if constexpr (LARGE)
+      llv = xs[pos];
+    else
+      llv = sm.u.ll[sm.idx[pos]];
+    xs[pos] = mx > -HUGE_VAL ? llv - mx : -HUGE_VAL;
   }
   // run length and the first lane of each live model's runs
   if (wave == 0) {
     const int c0 = lane < M && sm.mx[lane] > -HUGE_VAL ? sm.cnt[lane] : 0;
     const int c1 = lane + kWave < M && sm.mx[lane + kWave] > -HUGE_VAL ? sm.cnt[lane + kWave] : 0;
     int R = 1;
-    for (; R < kRunMax; ++R) {
+    for (; R < (LARGE ? NMAX : kRunMax); ++R) {
       int tot = (c0 + R - 1) / R + (c1 + R - 1) / R;
 #pragma unroll
       for (int o = 1; o < kWave; o <<= 1) tot += __shfl_xor(tot, o);
@@ -762,11 +832,11 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
     if (lane == 0) sm.run_len = R;
   }
   __syncthreads();
-  const RunLane run = run_of_lane(sm, M);
+  constexpr int RM = KIND == 0 ? 1 : (KIND == 1 ? kRunMax : 0);   // 0: runs read from LDS
+  const RunLane run = run_of_lane<RM != 0>(sm, M);
   // temperature increment
   const double target = a.alpha_tess * (double)N;
   const double hi = 1.0 - g0;
-  constexpr int RM = SMALL ? 1 : kRunMax;
   bool full;
   const double dg = next_increment<RM>(sm, run, hi, target, M, full);
   if (!full) {
@@ -794,7 +864,7 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
       const int q = q0 + lane;
       uint64_t v = 0;
       if (q < n && live) {
-        const double w = exp_tab(dg * sm.x[sm.base[m] + q], sm.e2) * inv;
+        const double w = exp_tab(dg * xs[sm.base[m] + q], sm.e2) * inv;
         v = (uint64_t)rint(w * 0x1.0p60);
       }
       // inclusive scan over the wave
@@ -839,7 +909,8 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
   }
   __syncthreads();
   // the resampled population, in particle order (coalesced writes)
-  copy_resampled(sm, in, ll_in, out, ll_out, anc, off, N, rows_c, rows_m, rows_zm);
+  for (int first = 0; first < N; first += kCopyPer * kRwThreads)
+    copy_resampled(sm, in, ll_in, out, ll_out, anc, off, N, rows_c, rows_m, rows_zm, first);
   if (tid == 0) {
     gamma[s] = full ? 1.0 : g0 + dg;
     if (active) active[s] = 1;
@@ -851,12 +922,17 @@ hipError_t launch_reweight_resample(const SmcShape &sh, const rjsmc_reweight_arg
                                     double *log_z, int32_t *active, int32_t *anc, int *flags, const double *exp2t,
                                     hipStream_t stream) {
   const int64_t nps = in.n_per_sounding > 0 ? in.n_per_sounding : in.n;
+  if (nps > kMaxPerSoundingLarge || sh.n_models > kMaxModels) return hipErrorInvalidValue;
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3((unsigned)a.n_sound), dim3(kRwThreads), 0, stream, sh, a, in, ll_in, out, ll_out,
+                       gamma, log_z, active, anc, flags, exp2t);
+  };
   if (nps <= kRwThreads)
-    hipLaunchKernelGGL(reweight_resample_kernel<true>, dim3((unsigned)a.n_sound), dim3(kRwThreads), 0, stream, sh, a,
-                       in, ll_in, out, ll_out, gamma, log_z, active, anc, flags, exp2t);
+    go(reweight_resample_kernel<0>);
+  else if (nps <= kMaxPerSounding)
+    go(reweight_resample_kernel<1>);
   else
-    hipLaunchKernelGGL(reweight_resample_kernel<false>, dim3((unsigned)a.n_sound), dim3(kRwThreads), 0, stream, sh,
-                       a, in, ll_in, out, ll_out, gamma, log_z, active, anc, flags, exp2t);
+    go(reweight_resample_kernel<2>);
   return hipGetLastError();
 }
 
@@ -1062,7 +1138,7 @@ __device__ __forceinline__ void eigen_factor(double (*A)[kLd], double (*V0)[kLd]
 }
 
 __global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(SmcShape sh, DevParticles p, rjsmc_prior pr, double *factors) {
-  __shared__ int16_t mem[kMaxPerSounding];
+  __shared__ int16_t mem[kMaxPerSoundingLarge];
   __shared__ double A[kDimMax][kLd];
   __shared__ double V0[kDimMax][kLd];
   __shared__ double T[2][kDimMax][kLd];
@@ -1142,7 +1218,7 @@ hipError_t launch_adapt(const SmcShape &sh, const DevParticles &p, int n_sound, 
 __global__ __launch_bounds__(kAdaptThreads) void adapt_recycled_kernel(SmcShape sh, DevParticles p, const double *ll,
                                                                const double *gamma, const double *log_z,
                                                                ArchiveView ar, rjsmc_prior pr, double *factors) {
-  __shared__ int16_t mem[kMaxPerSounding];
+  __shared__ int16_t mem[kMaxPerSoundingLarge];
   __shared__ double A[kDimMax][kLd];
   __shared__ double V0[kDimMax][kLd];
   __shared__ double T[2][kDimMax][kLd];

@@ -61,7 +61,8 @@ def _population_with_ll(n_sound, nps, seed, ll_kind="heavy"):
     return p, ll
 
 
-@pytest.mark.parametrize("n_sound,nps", [(1, 256), (3, 1024), (2, 2048), (4, 100)])
+@pytest.mark.parametrize("n_sound,nps", [(1, 256), (3, 1024), (2, 2048), (4, 100), (3, 4097), (2, 9600),
+                                          (1, 10240)])
 def test_reweight_resample(B, ctx, n_sound, nps):
     from oracle import smc
     p, ll = _population_with_ll(n_sound, nps, 31 + nps)
@@ -101,7 +102,7 @@ def _check_reweight(B, ctx, p, ll, gamma, log_z, n_sound, nps):
     assert np.array_equal(ll_out.cpu().numpy(), ll[anc_ref])
 
 
-@pytest.mark.parametrize("nps", [300, 2000])
+@pytest.mark.parametrize("nps", [300, 2000, 9600])
 def test_reweight_resample_skewed_dead_and_full(B, ctx, nps):
     """Soundings that exercise the temperature search's edge cases: one model holding
     95% of the members (at 2,000 per sounding its runs span six waves, so the per-wave
@@ -125,6 +126,19 @@ def test_reweight_resample_skewed_dead_and_full(B, ctx, nps):
     gamma = np.array([0.0, 0.25, 0.1, 0.9])
     log_z = np.random.default_rng(2).normal(0, 1, (n_sound, M))
     _check_reweight(B, ctx, p, ll, gamma, log_z, n_sound, nps)
+
+
+def test_reweight_rejects_more_than_the_per_sounding_limit(B, ctx):
+    n = B.RJSMC_MAX_PER_SOUNDING + 1
+    p = B.empty_device_population(n, KC, KM)
+    out = B.empty_device_population(n, KC, KM)
+    ll = torch.zeros(n, dtype=torch.float64, device="cuda")
+    g = torch.zeros(1, dtype=torch.float64, device="cuda")
+    lz = torch.zeros((1, M), dtype=torch.float64, device="cuda")
+    anc = torch.empty(n, dtype=torch.int32, device="cuda")
+    with pytest.raises(B.RJSMCError) as e:
+        ctx.reweight_resample(p, ll, out, torch.empty_like(ll), g, lz, None, anc, 0.5, 1, 1, 1)
+    assert e.value.status == B.RJSMC_E_UNSUPPORTED
 
 
 def test_reweight_constant_likelihood_one_step(B, ctx):
