@@ -291,8 +291,9 @@ typedef struct {
   const int32_t *step_dev;      /* device, may be NULL: when set, t is read from *step_dev */
   const double *rw_scale_dev;   /* device [n_sound], may be NULL: per-sounding within-model
                                    step (overrides rw_scale) */
-  int64_t *stats_sound;         /* device [n_sound][2], may be NULL: within-model random-walk
-                                   proposals / acceptances per sounding (accumulated) */
+  int64_t *stats_sound;         /* device [n_sound][2], may be NULL: within-model (random-walk
+                                   or gradient-informed) proposals / acceptances per sounding
+                                   (accumulated) */
   int32_t trial;                /* 0: the sweeps of Algorithm 1.  b >= 1: trial proposals
                                    (Section 3.2.2) decided and counted but never kept, with
                                    random-number move index b * 2^20 + r */
@@ -310,6 +311,10 @@ typedef struct {
                                    death, which inverts the map with the same S and is
                                    rejected unless the recovered state is in the support
                                    with u_d at index r) */
+  const double *mala_eps_dev;   /* device [n_sound], may be NULL: per-sounding step of the
+                                   gradient-informed move (overrides mala_eps), e.g. bisected
+                                   from trial proposals toward a target acceptance as the
+                                   random-walk scale is (Section 3.2.2) */
 } rjsmc_mutate_args;
 
 /* n_moves RJ-MCMC sweeps (Algorithm 1, mutation) targeting L^gamma(sounding) x prior.

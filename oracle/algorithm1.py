@@ -40,7 +40,8 @@ def _copy(p):
 def gradient_vector(system, K, d, p, i):
     """(ll, d ll / d theta) of particle i for data d, the gradient in the order of the
     paper's parameter vector (Section 2.3.1), by the oracle's forward-mode tangents."""
-    one = {k: (np.ascontiguousarray(v[..., [i]]) if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+    one = {k: np.ascontiguousarray(v[..., [i]]) for k, v in p.items() if isinstance(v, np.ndarray)}
+    one["layout"] = p["layout"]
     ll, g = em.loglik_grad(one, system, K, d)
     names = em.particle_params(one, 0)
     return ll[0], np.array([g[n][0] if r is None else g[n][r, 0] for n, r in names])

@@ -646,7 +646,7 @@ def mutate(p, ll, loglik_fn, gamma_of, step, seed, q, pr, kmax_cond, kmax_charg,
     (proposed, accepted) counts and the accept margins gamma (ll' - ll) - ln u.
     indices: the particles to move (default all); each particle's chain depends only on
     its own state and random counters, so a subset moves exactly as in the full sweep.
-    q["rw_scale"] may be a function of the particle index.  trial = b >= 1: trial
+    q["rw_scale"] and q["mala_eps"] may be functions of the particle index.  trial = b >= 1: trial
     proposals (Section 3.2.2) that draw from their own counters (move index
     b * TRIAL_STRIDE + r) and are decided but never kept."""
     n = len(ll)
@@ -669,13 +669,14 @@ def mutate(p, ll, loglik_fn, gamma_of, step, seed, q, pr, kmax_cond, kmax_charg,
                 theta = param_vector(p, i)
                 _, g0 = grad_fn(p, i)
                 xi = mala_normals(seed, i, step, mv, len(theta))
-                th_new = mala_propose(theta, g0, gamma_of(i), F, q["mala_eps"], xi)
+                eps = q["mala_eps"](i) if callable(q["mala_eps"]) else q["mala_eps"]
+                th_new = mala_propose(theta, g0, gamma_of(i), F, eps, xi)
                 if not in_support(th_new, k_, l_, pr):
                     margins.append((i, r, np.inf))
                     continue
                 set_param_vector(p, i, th_new)
                 ll_new, g1 = grad_fn(p, i)
-                extra = mala_log_q_ratio(xi, g0, g1, gamma_of(i), F, q["mala_eps"])
+                extra = mala_log_q_ratio(xi, g0, g1, gamma_of(i), F, eps)
             else:
                 apply_state(p, i, new)
                 ll_new = loglik_fn(p, i)

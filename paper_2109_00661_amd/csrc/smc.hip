@@ -1733,7 +1733,7 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
     double th[kDimMax], xi[kDimMax], cr[kDimMax];
     for (int q = 0; q < d; ++q) th[q] = theta_get(st, i, k, l, q);
     mala_normals(a, i, move, d, xi);
-    const double eps = a.mala_eps;
+    const double eps = a.mala_eps_dev ? a.mala_eps_dev[snd] : a.mala_eps;
     for (int r = 0; r < d; ++r) {          // cr = eps^2/2 F^T (gamma grad) + eps xi
       double sr = 0.0;
       for (int q = 0; q < d; ++q) sr += Fm[r * D + q] * (gam * theta_get(gcur, i, k, l, q));
@@ -1799,13 +1799,14 @@ __global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_a
       const int d = 3 + 2 * k + 2 * l, D = sh.dmax;
       const double *Fm = a.factors + (snd * sh.n_models + (k * (sh.km + 1) + l)) * (int64_t)D * D;
       const double gam = gamma[snd];
+      const double eps = a.mala_eps_dev ? a.mala_eps_dev[snd] : a.mala_eps;
       double xi[kDimMax];
       mala_normals(a, i, move, d, xi);
       for (int r = 0; r < d; ++r) {
         double sr = 0.0;
         for (int q = 0; q < d; ++q)
           sr += Fm[r * D + q] * (gam * (theta_get(readonly(gcur), i, k, l, q) + theta_get(gprop, i, k, l, q)));
-        const double v = xi[r] + 0.5 * a.mala_eps * sr;
+        const double v = xi[r] + 0.5 * eps * sr;
         extra += -0.5 * v * v + 0.5 * xi[r] * xi[r];
       }
     }
@@ -1853,7 +1854,8 @@ __global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_a
       }
     }
   }
-  if (a.stats_sound && t == RJSMC_MOVE_WITHIN_RW) {   // every drawn random-walk proposal counts
+  if (a.stats_sound && (t == RJSMC_MOVE_WITHIN_RW || t == RJSMC_MOVE_WITHIN_MALA)) {
+    // every drawn within-model proposal counts, also one that leaves the support
     const int64_t snd = st.n_per_sounding > 0 ? i / st.n_per_sounding : 0;
     atomicAdd((unsigned long long *)&a.stats_sound[2 * snd], 1ull);
     if (acc) atomicAdd((unsigned long long *)&a.stats_sound[2 * snd + 1], 1ull);

@@ -13,6 +13,7 @@ from . import workloads as W
 UNIFORM_MOVES = (1, 1, 1, 1, 1, 1, 1, 0)     # birth/death/move x2 partitions + within-model RW
 LANGEVIN_MOVES = (1, 1, 1, 1, 1, 1, 0, 1)    # the within-model move is the gradient-informed one
 RW_ONLY = (0, 0, 0, 0, 0, 0, 1, 0)           # trial proposals of the step-size bisection
+MALA_ONLY = (0, 0, 0, 0, 0, 0, 0, 1)         # trial proposals of the Langevin step bisection
 
 
 def mutation_count(rates, c, r_max):
@@ -35,8 +36,8 @@ class RJSMCRun:
 
     def __init__(self, ctx, n_sound, n_per_sound, y_obs, *, prior=None, alpha=0.5, n_moves=5, seed=0,
                  move_prob=UNIFORM_MOVES, z_move_frac=0.05, rw_scale=2.38, mala_eps=0.8, device="cuda",
-                 graph=False, adapt_c=None, r_max=100, tune_scale=False, scale_target=0.44, n_bisect=6,
-                 scale_bracket=(0.05, 20.0), recycle=0, zca_birth=False):
+                 graph=False, adapt_c=None, r_max=100, tune_scale=False, scale_target=None, n_bisect=6,
+                 scale_bracket=None, recycle=0, zca_birth=False):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -69,12 +70,22 @@ class RJSMCRun:
             self.grads = [B.empty_device_population(self.n, kc, km, nps, device) for _ in range(2)]
         self.step = 0
         self.adapt_c, self.r_max = adapt_c, r_max
+        # bisection of the within-model step on trial proposals (Section 3.2.2): the random
+        # walk's scale toward acceptance 0.44, or, when the within-model move is the
+        # gradient-informed one, the Langevin step toward 0.574 (the optimal acceptance of
+        # Langevin proposals in high dimension, Roberts & Rosenthal 1998)
+        self.tune_langevin = move_prob[B.N_MOVES - 1] > 0 and move_prob[B.N_MOVES - 2] == 0
+        if scale_target is None:
+            scale_target = 0.574 if self.tune_langevin else 0.44
+        if scale_bracket is None:
+            scale_bracket = (0.02, 4.0) if self.tune_langevin else (0.05, 20.0)
         self.tune_scale, self.scale_target, self.n_bisect, self.scale_bracket = (tune_scale, scale_target, n_bisect,
                                                                                  scale_bracket)
+        self.scale0 = mala_eps if self.tune_langevin else rw_scale
         if tune_scale:
             self.log_lo = torch.zeros(n_sound, dtype=torch.float64, device=device)
             self.log_hi = torch.zeros(n_sound, dtype=torch.float64, device=device)
-            self.scale = torch.full((n_sound,), rw_scale, dtype=torch.float64, device=device)
+            self.scale = torch.full((n_sound,), self.scale0, dtype=torch.float64, device=device)
             self.stats_sound = torch.zeros((n_sound, 2), dtype=torch.int64, device=device)
         self.moves_per_step = []
         self._stats_prev = None
@@ -129,21 +140,23 @@ class RJSMCRun:
         common = dict(seed=self.seed, step=self._run_base + self.step, n_sound=self.S, prior=self.prior, z_move_sd=self.z_move_sd,
                       rw_scale=self.rw_scale, factors=self.factors, mala_eps=self.mala_eps, step_dev=step_dev,
                       zca_birth=self.zca_birth)
+        grads = dict(grad_cur=self.grads[0] if self.grads else None, grad_prop=self.grads[1] if self.grads else None)
+        lang = self.tune_scale and self.tune_langevin
+        tuned = dict(rw_scale_dev=self.scale if self.tune_scale and not lang else None,
+                     mala_eps_dev=self.scale if lang else None)
         if self.tune_scale:
-            # bisection on the random-walk scale from trial proposals (never kept)
+            # bisection on the within-model step from trial proposals (never kept)
             bis = dict(target=self.scale_target, lo0=self.scale_bracket[0], hi0=self.scale_bracket[1],
                        log_lo=self.log_lo, log_hi=self.log_hi, scale=self.scale, stats_sound=self.stats_sound)
             self.ctx.scale_bisect(self.S, 1, **bis)
             for b in range(1, self.n_bisect + 1):
                 self.ctx.mutate(self.state, self.ll, self.bufs[1 - self.cur], self.lls[1 - self.cur], self.gamma,
-                                self.active, self.y_obs, None, n_moves=1, move_prob=RW_ONLY, rw_scale_dev=self.scale,
-                                stats_sound=self.stats_sound, trial=b, **common)
+                                self.active, self.y_obs, None, n_moves=1, move_prob=MALA_ONLY if lang else RW_ONLY,
+                                stats_sound=self.stats_sound, trial=b, **tuned, **grads, **common)
                 self.ctx.scale_bisect(self.S, 0, **bis)
         self.ctx.mutate(self.state, self.ll, self.bufs[1 - self.cur], self.lls[1 - self.cur], self.gamma, self.active,
-                        self.y_obs, self.stats, n_moves=self.n_moves, move_prob=self.move_prob,
-                        grad_cur=self.grads[0] if self.grads else None,
-                        grad_prop=self.grads[1] if self.grads else None,
-                        rw_scale_dev=self.scale if self.tune_scale else None, **common)
+                        self.y_obs, self.stats, n_moves=self.n_moves, move_prob=self.move_prob, **tuned, **grads,
+                        **common)
         if self.archive is not None:
             self._archive_current()
         if step_dev is not None:
@@ -223,7 +236,7 @@ class RJSMCRun:
         if self.step_dev is not None:
             self.step_dev.fill_(self._run_base + 1)
         if self.tune_scale:
-            self.scale.fill_(self.rw_scale)
+            self.scale.fill_(self.scale0)
             self.stats_sound.zero_()
         self.ctx.init_prior(self.state, self.prior, prior_seed)
         self.ctx.loglik(self.state, self.y_obs, out=self.ll)

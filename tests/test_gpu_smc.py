@@ -511,6 +511,70 @@ def test_tuned_scale_run_graph_and_eager(B, truth_data):
     assert np.all((sc > 0.05) & (sc < 20.0))
 
 
+def test_trial_langevin_mutation_against_oracle(B, ctx, system, K_oracle, truth_data):
+    """Trial gradient-informed proposals with per-sounding Langevin steps (the tuning of
+    the Langevin step): population and log-likelihoods untouched, per-sounding counts of
+    proposals and acceptances equal to the oracle's decisions."""
+    from oracle import algorithm1 as A1, em, smc
+    S, nps, trial, seed, step = 2, 24, 2, 57, 8
+    n = S * nps
+    p = smc.init_population(63, n, KC, KM, PR)
+    p["n_per_sounding"] = nps
+    ll0 = em.loglik(p, system, K_oracle, truth_data)
+    eps = np.array([0.15, 0.9])
+    fdev, fhost = _device_factors(p, nps, S, 10)
+    q = dict(move_prob=np.array([0, 0, 0, 0, 0, 0, 0, 1], float), z_move_sd=0.05 * PR["z_max"], rw_scale=2.38,
+             mala_eps=lambda i: eps[i // nps])
+    po = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+    llo = ll0.copy()
+    models = lambda i: smc.model_id(int(po["kappa"][i]), int(po["lambda_"][i]), KM)
+    _, margins = smc.mutate(po, llo, lambda pp, i: em.loglik(pp, system, K_oracle, truth_data, [i])[0],
+                            lambda i: 0.05, step, seed, q, PR, KC, KM, lambda i: fhost[(i // nps, models(i))], 1,
+                            grad_fn=lambda pp, i: A1.gradient_vector(system, K_oracle, truth_data, pp, i), trial=trial)
+    dp = B.particles_to_device(p)
+    ll_d = torch.as_tensor(ll0, device="cuda")
+    stats_sound = torch.zeros((S, 2), dtype=torch.int64, device="cuda")
+    ctx.mutate(dp, ll_d, B.empty_device_population(n, KC, KM, nps), torch.empty_like(ll_d),
+               torch.full((S,), 0.05, dtype=torch.float64, device="cuda"), None,
+               torch.as_tensor(np.tile(truth_data, (S, 1)), device="cuda"), None, seed=seed, step=step, n_moves=1,
+               n_sound=S, prior=PR, move_prob=q["move_prob"], z_move_sd=q["z_move_sd"], rw_scale=2.38, mala_eps=9.9,
+               factors=torch.as_tensor(fdev, device="cuda"), mala_eps_dev=torch.as_tensor(eps, device="cuda"),
+               grad_cur=B.empty_device_population(n, KC, KM, nps), grad_prop=B.empty_device_population(n, KC, KM, nps),
+               stats_sound=stats_sound, trial=trial)
+    ctx.check()
+    _assert_pop_equal(_host(B, dp), p)
+    assert np.array_equal(ll_d.cpu().numpy(), ll0)
+    assert not [mg for _, _, mg in margins if abs(mg) < 1e-7]
+    acc = np.zeros(S, dtype=np.int64)
+    for i, _, mg in margins:
+        acc[i // nps] += 0 < mg < np.inf
+    got = stats_sound.cpu().numpy()
+    assert np.array_equal(got[:, 0], [nps, nps]) and np.array_equal(got[:, 1], acc)
+    assert acc[0] > acc[1]                           # the smaller step is accepted more often
+
+
+def test_tuned_langevin_run_graph_and_eager(B, truth_data):
+    """Langevin within-model moves with the per-sounding step bisected on trial
+    proposals toward acceptance 0.574: replayed step graphs equal the eager calls."""
+    from paper_2109_00661_amd.rjsmc import RJSMCRun, LANGEVIN_MOVES
+    y = np.tile(truth_data, (2, 1))
+    runs = []
+    for graph in (False, True):
+        ctx = B.Context(W.system(), precision="f64", max_particles=256)
+        run = RJSMCRun(ctx, 2, 128, y, seed=23, graph=graph, tune_scale=True, n_bisect=4, move_prob=LANGEVIN_MOVES)
+        run.initialise()
+        for _ in range(3):
+            run.advance()
+        ctx.check()
+        runs.append(run)
+    a, b = runs
+    assert a.tune_langevin and a.scale_target == 0.574
+    for k in ("ll", "log_z", "gamma", "scale", "stats"):
+        assert np.array_equal(getattr(a, k).cpu().numpy(), getattr(b, k).cpu().numpy()), k
+    sc = a.scale.cpu().numpy()
+    assert np.all((sc > 0.02) & (sc < 4.0)) and not np.all(sc == a.scale0)
+
+
 # ------------------------------------------------------------------- particle recycling
 def _recycle_case(B, ctx, n_sound, nps, n_used, seed):
     """Archive of n_used earlier populations plus a current one, with random
