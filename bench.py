@@ -6,7 +6,7 @@ each a five-layer Cole-Cole model drawn from the prior ranges, with the 40-frequ
 over the whole batch; inputs are resident in HBM before the timed region.
 
 Prints one JSON line.  Options: --steps K --warmup W --gpus N (only 1 is supported)
---no-cpu (skip the CPU oracle baseline) --extra (also time FP32 and the other calls).
+--no-cpu (skip the CPU oracle baseline) --quick (skip the survey and the move comparison).
 """
 import argparse
 import json
@@ -110,23 +110,106 @@ def time_calls(fn, steps, warmup, torch):
     return start.elapsed_time(end) / steps, wall
 
 
-def cpu_baseline(system, d_np, budget_s=15.0):
-    """The oracle as it stands, on a bounded sample of the same workload."""
+# ------------------------------------------------------------------ CPU baseline (oracle)
+_ORACLE = {}
+
+
+def _oracle_setup():
+    """The oracle's system, K and synthetic data (the three-layer truth through the
+    oracle's forward model plus the seeded noise), computed once per process."""
+    if not _ORACLE:
+        import warnings
+        from oracle import em
+        system = W.system(kmax_cond=N_LAYERS - 1, kmax_charg=0)
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            K = em.make_K(system)
+        y = em.forward(W.truth_three_layer_merged(), system, K)[0]
+        d = y + np.sqrt(em.noise_variance(y, system["eps_an"], system["eps_mn"])) * W.data_noise(1)
+        _ORACLE.update(system=system, K=K, d=d, pop=W.merged_population(N_PARTICLES, N_LAYERS, seed=2,
+                                                                        kc=N_LAYERS - 1))
+    return _ORACLE
+
+
+def _oracle_chunk(bounds):
+    """Forward + log-likelihood of particles [lo, hi) of the headline batch by the oracle."""
+    from oracle import em
+    o = _oracle_setup()
+    lo, hi = bounds
+    em.loglik(o["pop"], o["system"], o["K"], o["d"], range(lo, hi))
+    return hi - lo
+
+
+def cpu_host():
+    """Host CPU model and the number of cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    share = int(os.environ.get("OMP_NUM_THREADS", avail) or avail)
+    return model, avail, max(1, min(avail, share))
+
+
+def cpu_baseline(budget_s=6.0, repeats=3):
+    """The oracle as it stands, timed on the host: forward + log-likelihood evaluations of
+    the headline batch's particles on one thread and on a process pool over the host's
+    cores (median of `repeats` runs of about `budget_s` each, on consecutive particles of
+    the same batch), and complete Algorithm-1 steps of one 256-particle sounding
+    extrapolated to a whole run.  Run before the GPU is touched (the pool forks)."""
+    import multiprocessing as mp
+    model, avail, workers = cpu_host()
+    _oracle_setup()
+    chunk = 32
+    one, start = [], 0
+    for _ in range(repeats):
+        n, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            n += _oracle_chunk((start + n, start + n + chunk))
+        one.append(n / (time.perf_counter() - t0))
+        start += n
+    many = []
+    with mp.get_context("fork").Pool(workers) as pool:
+        pool.map(_oracle_chunk, [(0, 1)] * workers)            # warm the workers
+        for _ in range(repeats):
+            n_jobs = max(workers, int(np.median(one) * budget_s * workers * 0.9) // chunk)
+            jobs = [((q * chunk) % N_PARTICLES, (q * chunk) % N_PARTICLES + chunk) for q in range(n_jobs)]
+            t0 = time.perf_counter()
+            n = sum(pool.map(_oracle_chunk, jobs, chunksize=1))
+            many.append(n / (time.perf_counter() - t0))
+    out = dict(value=float(np.median(many)), unit="evals/s", cores=workers, kind="oracle",
+               sample="forward+loglik (numpy FP64) of consecutive particles of the 65,536-particle batch, "
+                      "median of %d runs of ~%.0f s on a pool of %d processes; one thread: %.0f evals/s"
+                      % (repeats, budget_s, workers, float(np.median(one))),
+               one_thread_evals_per_s=float(np.median(one)), all_cores_evals_per_s=float(np.median(many)),
+               runs_one_thread=one, runs_all_cores=many, cpu_model=model, nproc=avail)
+    out["rjsmc"] = cpu_rjsmc_steps()
+    return out
+
+
+def cpu_rjsmc_steps(n_steps=2, n_per_sound=256):
+    """The oracle's Algorithm 1 on one 256-particle sounding (R = 5, alpha = 0.5) for
+    n_steps steps on one thread; the soundings/s figure assumes the step count of the
+    GPU run of the same sounding (filled in by the caller)."""
+    from oracle import algorithm1 as A1
     import warnings
     from oracle import em
+    system = W.system()
     with warnings.catch_warnings():
         warnings.simplefilter("ignore")
         K = em.make_K(system)
-    p = W.merged_population(N_PARTICLES, N_LAYERS, seed=2, kc=N_LAYERS - 1)
-    n_done = 0
+    y = em.forward(W.truth_three_layer(), system, K)[0]
+    d = y + np.sqrt(em.noise_variance(y, system["eps_an"], system["eps_mn"])) * W.data_noise(1)
     t0 = time.perf_counter()
-    chunk = 64
-    while time.perf_counter() - t0 < budget_s and n_done < N_PARTICLES:
-        em.loglik(p, system, K, d_np, range(n_done, min(n_done + chunk, N_PARTICLES)))
-        n_done = min(n_done + chunk, N_PARTICLES)
+    A1.run(system, K, d[None, :], 1, n_per_sound, W.PRIOR, 0, max_steps=n_steps)
     dt = time.perf_counter() - t0
-    return dict(value=n_done / dt, unit="evals/s", cores=1, kind="oracle",
-                sample="first %d of the 65,536 particles (numpy FP64, one thread), %.1f s" % (n_done, dt))
+    return {"particles_per_sounding": n_per_sound, "steps_timed": n_steps, "seconds": dt,
+            "seconds_per_step": dt / n_steps, "cores": 1}
 
 
 def rjsmc_rate(torch, d, n_sound, n_per_sound, seed=0, move_prob=None, graph=False, kmax=None, noise=False,
@@ -198,6 +281,14 @@ def rjsmc_rate(torch, d, n_sound, n_per_sound, seed=0, move_prob=None, graph=Fal
             lz.shape[1])
         out["log_evidence_mean"] = float(np.mean(lpy))
         out["log_evidence_sd"] = float(np.std(lpy))
+        # the same marginal evidence from the replicate's most populated model k*:
+        # p(y) = p(k*) Z_k* / pi(k* | y), with pi(k* | y) = N_k* / N (Section 3.2.1)
+        ks = np.argmax(probs, axis=1)
+        lz_ks = lz[np.arange(n_sound), ks]
+        lpy_pop = lz_ks - np.log(lz.shape[1]) - np.log(probs[np.arange(n_sound), ks])
+        fin2 = np.isfinite(lpy_pop)
+        out["log_evidence_pop_mean"] = float(np.mean(lpy_pop[fin2])) if fin2.any() else None
+        out["log_evidence_pop_sd"] = float(np.std(lpy_pop[fin2])) if fin2.any() else None
         out["p_best_model_mean"] = float(np.mean(probs[:, best]))
         out["p_best_model_sd"] = float(np.std(probs[:, best]))
     return out
@@ -219,31 +310,56 @@ def rjsmc_legs():
     }
 
 
-def accuracy_comparison(torch, d, sizes=(256, 512, 1024), reps=32, adapt_c=0.01, r_max=40):
+def accuracy_comparison(torch, d, sizes=(1024, 4096), reps=16, adapt_c=0.01, r_max=40, extras=False):
     """Random-walk against gradient-informed (Langevin) within-model moves on the same
-    GPU: `reps` replicate runs of the synthetic sounding (batched) for each particle count,
-    with the adaptive number of sweeps (c = 0.01: every particle moves with probability
-    0.99) and tuned tiles; then the random walk at 512 particles with the adaptive birth
-    and with particle recycling (8 populations, eager).  The spread over replicates of
-    the marginal log-evidence and of the best model's posterior probability measures
-    accuracy; soundings/s the cost."""
+    GPU, as a cost-versus-accuracy curve: `reps` replicate runs of the synthetic sounding
+    (batched) for each particle count, with the adaptive number of sweeps (c = 0.01:
+    every particle moves with probability 0.99, at most 40 sweeps), each within-model step
+    bisected on trial proposals (random-walk scale toward acceptance 0.44, Langevin step
+    toward 0.574), tuned tiles and step graphs.  Accuracy is the spread over replicates of
+    the marginal log-evidence (from the most populated model's evidence and its posterior
+    probability, and from the sum over models), of the best model's log-evidence and of
+    its posterior probability; cost is soundings/s.  `at_equal_accuracy` gives, for the
+    spread both samplers reach, each one's cheapest configuration that reaches it.
+    extras: also the random walk at 512 particles with the adaptive birth and with
+    particle recycling (8 populations, eager)."""
     from paper_2109_00661_amd.rjsmc import UNIFORM_MOVES, LANGEVIN_MOVES
     rows = []
-    cases = [(name, mp, n, True, {}) for name, mp in (("random_walk", UNIFORM_MOVES), ("langevin", LANGEVIN_MOVES))
-             for n in sizes]
-    # the paper's adaptive machinery on the random-walk sampler at 512 particles
-    cases += [("random_walk_adaptive_birth", UNIFORM_MOVES, 512, True, {"zca_birth": True}),
-              ("random_walk_recycling_8", UNIFORM_MOVES, 512, False, {"recycle": 8})]
+    cases = [(name, mp, n, True, {}) for n in sizes
+             for name, mp in (("random_walk", UNIFORM_MOVES), ("langevin", LANGEVIN_MOVES))]
+    if extras:
+        cases += [("random_walk_adaptive_birth", UNIFORM_MOVES, 512, True, {"zca_birth": True}),
+                  ("random_walk_recycling_8", UNIFORM_MOVES, 512, False, {"recycle": 8})]
     for name, mp, n, graph, extra in cases:
         r = rjsmc_rate(torch, d, reps, n, move_prob=mp, graph=graph, tune=True, adapt_c=adapt_c, r_max=r_max,
-                       **extra)
-        row = {"moves": name, "particles_per_sounding": n, "graph": graph}
-        row.update({k: r[k] for k in ("soundings_per_s", "steps", "sweeps_per_step_mean", "acceptance",
-                                      "log_evidence_mean", "log_evidence_sd", "best_model", "p_best_model_mean",
-                                      "p_best_model_sd", "ll_max_median")})
+                       tune_scale=True, **extra)
+        row = {"moves": name, "particles_per_sounding": n, "replicates": reps, "graph": graph}
+        row.update({k: r.get(k) for k in ("soundings_per_s", "steps", "sweeps_per_step_mean", "acceptance",
+                                          "log_evidence_pop_mean", "log_evidence_pop_sd", "log_evidence_mean",
+                                          "log_evidence_sd", "log_z_best_sd", "best_model", "p_best_model_mean",
+                                          "p_best_model_sd", "p_chargeable_mean", "p_chargeable_sd",
+                                          "ll_max_median")})
         print(json.dumps(row), file=sys.stderr, flush=True)
         rows.append(row)
-    return rows
+    equal = {}
+    for measure in ("log_evidence_pop_sd", "p_best_model_sd"):
+        best = {}
+        for m in ("random_walk", "langevin"):
+            vals = [r[measure] for r in rows if r["moves"] == m and r[measure] is not None]
+            best[m] = min(vals) if vals else None
+        if None in best.values():
+            continue
+        target = max(best.values())                     # a spread both samplers reach
+        pick = {}
+        for m in ("random_walk", "langevin"):
+            ok = [r for r in rows if r["moves"] == m and r[measure] is not None and r[measure] <= target]
+            r = max(ok, key=lambda r: r["soundings_per_s"])
+            pick[m] = {"particles_per_sounding": r["particles_per_sounding"], "soundings_per_s": r["soundings_per_s"],
+                       measure: r[measure]}
+        equal[measure] = {"common_spread": target, **pick,
+                          "random_walk_over_langevin": pick["random_walk"]["soundings_per_s"]
+                          / pick["langevin"]["soundings_per_s"]}
+    return {"rows": rows, "at_equal_accuracy": equal}
 
 
 def survey_run(torch, precision, move_prob, n_per_sound=2048, seed=0):
@@ -272,6 +388,8 @@ def survey_run(torch, precision, move_prob, n_per_sound=2048, seed=0):
     dt = time.perf_counter() - t0
     summ = ctx.summarize(run.state, S)
     lb = summ["log_bfipd"].cpu().numpy()
+    # posterior predictive check: the data standardised to each station's PPD
+    zs = np.abs(run.posterior_predictive()["z"].cpu().numpy())
     lz = run.log_z.cpu().numpy()
     km = ctx.kmax_charg
     true_model = truth["kappa"] * (km + 1) + truth["lambda_"]
@@ -285,14 +403,17 @@ def survey_run(torch, precision, move_prob, n_per_sound=2048, seed=0):
             "log_bfipd_median_body": float(np.median(lb[body])),
             "log_bfipd_median_outside": float(np.median(lb[~body])),
             "log_z_true_model_finite": int(np.isfinite(lz_true).sum()),
+            "ppd_abs_z_median": float(np.median(zs)), "ppd_frac_within_1sd": float(np.mean(zs <= 1.0)),
+            "ppd_frac_within_3sd": float(np.mean(zs <= 3.0)),
             "_log_bfipd": lb, "_log_z_true": lz_true}
 
 
-def survey(torch):
+def survey(torch, langevin=False):
     from paper_2109_00661_amd.rjsmc import UNIFORM_MOVES, LANGEVIN_MOVES
     runs = {"fp64_rw": survey_run(torch, "f64", UNIFORM_MOVES),
-            "fp32_forward_rw": survey_run(torch, "f32", UNIFORM_MOVES),
-            "fp64_langevin": survey_run(torch, "f64", LANGEVIN_MOVES)}
+            "fp32_forward_rw": survey_run(torch, "f32", UNIFORM_MOVES)}
+    if langevin:
+        runs["fp64_langevin"] = survey_run(torch, "f64", LANGEVIN_MOVES)
     a, b = runs["fp64_rw"]["_log_bfipd"], runs["fp32_forward_rw"]["_log_bfipd"]
     fin = np.isfinite(a) & np.isfinite(b)
     za, zb = runs["fp64_rw"]["_log_z_true"], runs["fp32_forward_rw"]["_log_z_true"]
@@ -387,11 +508,15 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extra", action="store_true")
+    ap.add_argument("--extra", action="store_true", help="(the extra legs now run by default)")
+    ap.add_argument("--quick", action="store_true",
+                    help="skip the synthetic survey and the random-walk / Langevin comparison")
     ap.add_argument("--survey", action="store_true",
-                    help="also run the 2,000-sounding synthetic survey (FP64, FP32-forward, Langevin; minutes)")
+                    help="the synthetic survey also with Langevin moves (FP64 and FP32-forward random walk run "
+                         "by default)")
     ap.add_argument("--compare", action="store_true",
-                    help="also compare random-walk and Langevin moves at several particle counts (minutes)")
+                    help="the random-walk / Langevin comparison at 512 to 9,600 particles per sounding and with "
+                         "the adaptive birth and recycling (1,024 and 4,096 run by default; minutes)")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the 65,536-particle forward+loglik launches (for profiling)")
     ap.add_argument("--reweight-only", action="store_true",
@@ -410,6 +535,10 @@ def main():
         print("bench.py measures one GPU: the hot path runs on a single MI355X; "
               "multi-GPU sharding by sounding is a design note only.", file=sys.stderr)
         sys.exit(2)
+
+    # the CPU baseline first: its process pool forks, which must happen before the GPU is used
+    profiling_leg = args.reweight_only or args.adjoint_only or args.rjsmc_leg or args.headline_only
+    cpu = None if (args.no_cpu or profiling_leg) else cpu_baseline()
 
     import torch
     from paper_2109_00661_amd import binding as B
@@ -460,22 +589,37 @@ def main():
     if args.headline_only:
         print(json.dumps(out), flush=True)
         return
-    if args.extra:
-        ctx32 = B.Context(system, precision="f32")
-        ms32, _ = time_calls(lambda: ctx32.loglik(p, d, out=ll), args.steps, args.warmup, torch)
-        a32 = flop / (ms32 * 1e-3) / 1e12
-        out["fp32"] = {"evals_per_s": N_PARTICLES / (ms32 * 1e-3), "ms_per_step": ms32,
-                       "nominal_tflops": a32, "frac_of_fp32_peak": a32 / FP32_VECTOR_PEAK_TFLOPS}
-    if args.extra:
-        out["adjoint"] = adjoint_rate(torch, d, max(3, args.steps // 4), 1)
-        out["reweight_resample_2000x2048"] = reweight_rate(torch, d, max(3, args.steps // 4), 1)
-    out["rjsmc"] = {name: leg(torch, d) for name, leg in rjsmc_legs().items()}
-    if args.survey:
-        out["survey"] = survey(torch)
-    if args.compare:
-        out["moves_accuracy_comparison"] = accuracy_comparison(torch, d)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(system, d.cpu().numpy())
+    progress = lambda what: print("[bench] %s" % what, file=sys.stderr, flush=True)
+    ctx32 = B.Context(system, precision="f32")
+    ms32, _ = time_calls(lambda: ctx32.loglik(p, d, out=ll), args.steps, args.warmup, torch)
+    a32 = flop / (ms32 * 1e-3) / 1e12
+    out["fp32"] = {"evals_per_s": N_PARTICLES / (ms32 * 1e-3), "ms_per_step": ms32,
+                   "nominal_tflops": a32, "frac_of_fp32_peak": a32 / FP32_VECTOR_PEAK_TFLOPS}
+    progress("adjoint")
+    out["adjoint"] = adjoint_rate(torch, d, max(3, args.steps // 4), 1)
+    progress("reweight/resample 2,000 x 2,048")
+    out["reweight_resample_2000x2048"] = reweight_rate(torch, d, max(3, args.steps // 4), 1)
+    out["rjsmc"] = {}
+    for name, leg in rjsmc_legs().items():
+        progress("rjsmc " + name)
+        out["rjsmc"][name] = leg(torch, d)
+    if not args.quick:
+        progress("survey 2,000 x 2,048")
+        out["survey"] = survey(torch, langevin=args.survey)
+        progress("random walk vs Langevin")
+        out["moves_accuracy_comparison"] = (accuracy_comparison(torch, d, sizes=(512, 1024, 2048, 4096, 9600),
+                                                                extras=True)
+                                            if args.compare else accuracy_comparison(torch, d))
+    if cpu is not None:
+        # the oracle's RJSMC rate: its seconds per step times the GPU run's step count
+        ref = out["rjsmc"].get("single_sounding_256")
+        if ref:
+            cpu["rjsmc"]["steps_assumed"] = ref["steps"]
+            cpu["rjsmc"]["soundings_per_s"] = 1.0 / (cpu["rjsmc"]["seconds_per_step"] * ref["steps"])
+            cpu["rjsmc"]["extrapolation"] = ("seconds per Algorithm-1 step of the first %d steps x the %d steps of "
+                                             "the GPU run of the same sounding" % (cpu["rjsmc"]["steps_timed"],
+                                                                                    ref["steps"]))
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 
