@@ -26,6 +26,7 @@ namespace rjsmc {
 
 namespace {
 constexpr int kWavesA = 2;                               // particles per block
+constexpr int64_t kBucketMin = 4096;   // fewer particles: one launch (the sort costs more than it saves)
 constexpr double kMu0A = 1.25663706143591729539e-06;
 constexpr double kTwoPiA = 6.28318530717958647692;
 constexpr double kLn10 = 2.302585092994045684;
@@ -52,7 +53,7 @@ __device__ __forceinline__ cplx<double> cdiv_fast(cplx<double> a, cplx<double> b
 template <int LMAX>
 __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2, const double *h2v, int L,
                                              double wt, cplx<double> (&G)[LMAX], double (&H)[LMAX],
-                                             const cplx<double> *phase, const double *e2) {
+                                             const cplx<double> *phase, const double *e2, double &imr) {
   const double lam2 = lam * lam;
   // Up to 8 layers the layer loops are unrolled over LMAX with a wave-uniform guard, so
   // the stored states, G and H stay in registers; with 16 the loops stay runtime loops
@@ -67,9 +68,13 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
     const cplx<double> u0 = u_of(0);
     const cplx<double> s = {lam + u0.re, u0.im};
     const cplx<double> D = csq(s);
-    const cplx<double> iD = crcp_fast(D);
+    const cplx<double> N = {-k2[0].re, -k2[0].im};
+    // Im r as the forward model forms it: Im(N conj D) / |D|^2
+    const double inv = fast_rcp(D.re * D.re + D.im * D.im);
+    imr = (N.im * D.re - N.re * D.im) * inv;
+    const cplx<double> iD = {D.re * inv, -D.im * inv};
     const cplx<double> Nb = wt * iD;
-    const cplx<double> r = cplx<double>{-k2[0].re, -k2[0].im} * iD;
+    const cplx<double> r = N * iD;
     const cplx<double> Db = {-(Nb * r).re, -(Nb * r).im};
     const cplx<double> ub = Db * (2.0 * s);
     G[0] = G[0] + (ub * half_rcp(u0) - Nb);
@@ -96,9 +101,12 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
   const cplx<double> E0 = cexp_tab(cplx<double>{h2v[0] * u0.re, h2v[0] * u0.im}, phase, e2);
   step_up(N, D, cplx<double>{lam, 0.0}, u0, E0);
   // ---- top-down adjoint
-  const cplx<double> iD = crcp_fast(D);
+  const double inv = fast_rcp(D.re * D.re + D.im * D.im);
+  imr = (N.im * D.re - N.re * D.im) * inv;   // Im r as the forward model forms it
+  const cplx<double> iD = {D.re * inv, -D.im * inv};
+  const cplx<double> rs = N * iD;        // the reflection coefficient at the surface
   cplx<double> Nb = wt * iD;
-  cplx<double> Db = Nb * (N * iD);
+  cplx<double> Db = Nb * rs;
   Db = {-Db.re, -Db.im};
   cplx<double> uab;                      // adjoint of u of the layer above the interface
   {
@@ -154,10 +162,15 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
   }
 }
 
-// Gradient slots per frequency group: [layer sigma (LMAX)][layer m (LMAX)][thickness
-// (LMAX)][log10 tau][c].
+// Single pass.  The reverse sweep of a (lam, w) pair is linear in its seed, and the
+// pair's bottom-up recursion already gives Im r_TE, so every pair is visited once: the
+// sweep is seeded with the filter coefficient c_k alone, giving per frequency the
+// derivatives of Im H(w_j) with respect to the layer wavenumbers and thicknesses; these
+// are mapped through the Cole-Cole terms to a per-frequency slot vector u_j (LDS), and
+// Im H(w_j) is summed on the way.  Once the likelihood is known, the gradient is
+// sum_j wbar_j u_j with wbar_j = d ll / d Im H(w_j).  K is read from global memory (L2).
 template <int LMAX>
-struct AdjShared {
+struct AdjShared1 {
   double lam[kMaxHankel], ck[kMaxHankel], omega[kMaxFreq], eps2[kMaxGate];
   cplx<double> phase[kPhaseN];
   double exp2t[kExp2N];
@@ -166,42 +179,48 @@ struct AdjShared {
   double imh[kWavesA][kMaxFreq];
   double ybar[kWavesA][kMaxGate];
   cplx<double> k2[kWavesA][8][kMaxLayers];
-  cplx<double> dk2[kWavesA][8][kMaxLayers];
   double h2[kWavesA][kMaxLayers];
-  double slot[kWavesA][8][3 * LMAX + 2];
   double gl[kWavesA][3 * LMAX + 2];
   double ll[kWavesA];
 };
 
+// perm != nullptr: slot j evaluates particle perm[j] for the slots from *first (0 when
+// first is NULL) up to *last (device counters of the capacity sort); otherwise slot j is
+// particle j (workgroups renumbered XCD-contiguous).
 template <int LMAX>
-__global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem s, DevParticles p, int kc, int km,
-                                                                       const double *y_obs, double *ll, DevGrad g) {
-  __shared__ AdjShared<LMAX> sm;
-  extern __shared__ double sK[];   // [n_gate][n_freq], dynamic
+__global__ __launch_bounds__(kWave * kWavesA) void loglik_grad1_kernel(DevSystem s, DevParticles p, int kc, int km,
+                                                                        const double *y_obs, double *ll, DevGrad g,
+                                                                        const int32_t *perm, const int *first,
+                                                                        const int *last) {
+  __shared__ AdjShared1<LMAX> sm;
+  constexpr int NS = 3 * LMAX + 2;
+  extern __shared__ double su[];   // [kWavesA][n_freq][NS] per-frequency slot vectors, dynamic
   const int nf = s.n_freq, ng = s.n_gate, nhp = s.n_hankel_pad;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesA + wave;
+  int64_t i;
+  if (perm) {
+    const int64_t lo = first ? *first : 0, hi = *last;
+    const int64_t slot = lo + (int64_t)blockIdx.x * kWavesA + wave;
+    i = slot < hi && slot < p.n ? (int64_t)perm[slot] : p.n;
+  } else {
+    i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kWavesA + wave;
+  }
   const bool valid = i < p.n;
   const bool skip = valid && p.mask && p.mask[i] != p.mask_value;   // left untouched
-  // a masked launch (the Langevin proposals of a sweep) leaves most workgroups without
-  // work: they leave before staging the tables
   if (!__syncthreads_or(valid && !skip)) return;
   for (int t = threadIdx.x; t < nhp; t += blockDim.x) {
     sm.lam[t] = s.lam[t];
     sm.ck[t] = s.ck[t];
   }
   for (int t = threadIdx.x; t < nf; t += blockDim.x) sm.omega[t] = s.omega[t];
-  for (int t = threadIdx.x; t < nf * ng; t += blockDim.x) sK[t] = s.K[t];
   for (int t = threadIdx.x; t < ng; t += blockDim.x) sm.eps2[t] = s.eps_an2[t];
   for (int t = threadIdx.x; t < kPhaseN; t += blockDim.x)
     sm.phase[t] = cplx<double>{s.phase[2 * t], s.phase[2 * t + 1]};
   for (int t = threadIdx.x; t < kExp2N; t += blockDim.x) sm.exp2t[t] = s.exp2t[t];
   LayerStack *st = &sm.stack[wave];
-  constexpr int NS = 3 * LMAX + 2;
-  for (int t = lane; t < 8 * NS; t += kWave) sm.slot[wave][t / NS][t % NS] = 0.0;
+  double *uw = su + (size_t)wave * nf * NS;
   __syncthreads();
   const int L = merge_particle(p, i, valid && !skip, kc, km, LMAX, st, s.flags);
-
   double c = 0.0, log_tau = 0.0, spc = 0.0, cpc = 1.0;
   if (L > 0) {
     c = p.c[i];
@@ -212,75 +231,6 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
   const int gl = lane & 7, gw = lane >> 3;
   const int nhg = nhp >> 3;
   const int nq = (nf + 7) >> 3;
-  // ---- phase A: forward model
-#pragma unroll 1
-  for (int q = 0; q < nq; ++q) {
-    const int jf = gw + 8 * q;
-    const bool act = L > 0 && jf < nf;
-    if (act) {
-      const double w = sm.omega[jf];
-      const double pw = exp(c * (log(w) + log_tau));
-      const cplx<double> qcc = crcp(cplx<double>{1.0 + pw * cpc, pw * spc});
-      const double wmu = w * kMu0A;
-      auto k2_of = [&](int l) {
-        const double sg = st->sig[l], mg = st->m[l];
-        const cplx<double> sh = {sg * (1.0 - mg * qcc.re), sg * (-(mg * qcc.im))};
-        return cplx<double>{-(wmu * sh.im), wmu * sh.re};
-      };
-      for (int l = gl; l < L; l += 8) {
-        const cplx<double> kl = k2_of(l);
-        sm.k2[wave][gw][l] = kl;
-        if (l + 1 < L) sm.dk2[wave][gw][l] = kl - k2_of(l + 1);
-      }
-    }
-    wave_lds_sync();
-    if (act) {
-      double acc = 0.0;
-#pragma unroll 1
-      for (int sidx = 0; sidx < nhg; ++sidx) {
-        const int k = gl + 8 * sidx;
-        acc += sm.ck[k] * reflection_im<double>(sm.lam[k], sm.k2[wave][gw], sm.dk2[wave][gw], sm.h2[wave], L,
-                                      sm.phase, sm.exp2t);
-      }
-      acc += __shfl_xor(acc, 1);
-      acc += __shfl_xor(acc, 2);
-      acc += __shfl_xor(acc, 4);
-      if (gl == 0) sm.imh[wave][jf] = acc;
-    }
-    wave_lds_sync();
-  }
-  // ---- gates, log-likelihood and its adjoint with respect to the gate responses
-  if (L > 0) {
-    double term = 0.0, ybar = 0.0;
-    if (lane < ng) {
-      double y = 0.0;
-      for (int j = 0; j < nf; ++j) y += sK[lane * nf + j] * sm.imh[wave][j];
-      const int64_t snd = p.n_per_sounding > 0 ? i / p.n_per_sounding : 0;
-      const double d = y_obs[snd * ng + lane];
-      const double e = s.eps_mn * y;
-      const double s2 = sm.eps2[lane] + e * e;
-      const double r = d - y;
-      term = r * r / s2 + log(kTwoPiA * s2);
-      // d ll / d y = r/s2 + (r^2/s2^2 - 1/s2) eps_mn^2 y
-      ybar = r / s2 + (r * r / (s2 * s2) - 1.0 / s2) * s.eps_mn * s.eps_mn * y;
-      sm.ybar[wave][lane] = ybar;
-    }
-    term += __shfl_xor(term, 1);
-    term += __shfl_xor(term, 2);
-    term += __shfl_xor(term, 4);
-    term += __shfl_xor(term, 8);
-    term += __shfl_xor(term, 16);
-    term += __shfl_xor(term, 32);
-    if (lane == 0) sm.ll[wave] = -0.5 * term;
-  }
-  wave_lds_sync();
-  if (L > 0 && lane < nf) {
-    double acc = 0.0;
-    for (int gg = 0; gg < ng; ++gg) acc += sK[gg * nf + lane] * sm.ybar[wave][gg];
-    sm.wbar[wave][lane] = acc;
-  }
-  wave_lds_sync();
-  // ---- phase B: reverse sweep per pair
 #pragma unroll 1
   for (int q = 0; q < nq; ++q) {
     const int jf = gw + 8 * q;
@@ -308,13 +258,17 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
         G[l] = {0.0, 0.0};
         H[l] = 0.0;
       }
-      const double wj = sm.wbar[wave][jf];
+      double acc = 0.0;
 #pragma unroll 1
       for (int sidx = 0; sidx < nhg; ++sidx) {
         const int k = gl + 8 * sidx;
-        pair_adjoint<LMAX>(sm.lam[k], sm.k2[wave][gw], sm.h2[wave], L, sm.ck[k] * wj, G, H, sm.phase,
-                           sm.exp2t);
+        double imr;
+        pair_adjoint<LMAX>(sm.lam[k], sm.k2[wave][gw], sm.h2[wave], L, sm.ck[k], G, H, sm.phase, sm.exp2t, imr);
+        acc = __builtin_fma(sm.ck[k], imr, acc);
       }
+      acc += __shfl_xor(acc, 1);
+      acc += __shfl_xor(acc, 2);
+      acc += __shfl_xor(acc, 4);
 #pragma unroll
       for (int l = 0; l < LMAX; ++l) {
 #pragma unroll
@@ -325,39 +279,72 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
         }
       }
       if (gl == 0) {
-        // Cole-Cole chain: k2 = i w mu0 sigma (1 - m q), q = 1/(1 + z), z = (i w tau)^c
+        sm.imh[wave][jf] = acc;
+        // Cole-Cole chain of this frequency: k2 = i w mu0 sigma (1 - m q), q = 1/(1 + z),
+        // z = (i w tau)^c; slot vector [log10 sigma (LMAX)][m (LMAX)][thickness (LMAX)][tau][c]
         const cplx<double> iwm = {0.0, w * kMu0A};
         cplx<double> Gq = {0.0, 0.0};
-        double *sl = sm.slot[wave][gw];
+        double *sl = uw + (size_t)jf * NS;
 #pragma unroll
         for (int l = 0; l < LMAX; ++l) {
+          double a0 = 0.0, a1 = 0.0, a2 = 0.0;
           if (l < L) {
             const double sg = st->sig[l], mg = st->m[l];
             const cplx<double> dsig = iwm * (cplx<double>{1.0, 0.0} - mg * qcc);
-            sl[l] += (G[l] * dsig).im * kLn10 * sg;                       // d / d log10 sigma
-            sl[LMAX + l] += (G[l] * (iwm * (-sg * qcc))).im;              // d / d m
+            a0 = (G[l] * dsig).im * kLn10 * sg;
+            a1 = (G[l] * (iwm * (-sg * qcc))).im;
             Gq = Gq + G[l] * (iwm * cplx<double>{-sg * mg, 0.0});
-            sl[2 * LMAX + l] += H[l];                                     // d / d thickness
+            a2 = H[l];
           }
+          sl[l] = a0;
+          sl[LMAX + l] = a1;
+          sl[2 * LMAX + l] = a2;
         }
-        const cplx<double> Gz = Gq * cplx<double>{-(csq(qcc)).re, -(csq(qcc)).im};   // dq/dz = -q^2
-        sl[3 * LMAX] += (Gz * (c * kLn10 * zc)).im;                                   // dz/dlog10 tau
-        sl[3 * LMAX + 1] += (Gz * (zc * cplx<double>{log(w) + log_tau, kHalfPi})).im; // dz/dc
+        const cplx<double> Gz = Gq * cplx<double>{-(csq(qcc)).re, -(csq(qcc)).im};
+        sl[3 * LMAX] = (Gz * (c * kLn10 * zc)).im;
+        sl[3 * LMAX + 1] = (Gz * (zc * cplx<double>{log(w) + log_tau, kHalfPi})).im;
       }
     }
     wave_lds_sync();
   }
-  // ---- merged-layer gradients -> particle parameters
+  // gates, log-likelihood and wbar_j = sum_g K_gj d ll / d y_g
+  if (L > 0) {
+    double term = 0.0;
+    if (lane < ng) {
+      double y = 0.0;
+      for (int j = 0; j < nf; ++j) y += s.K[lane * nf + j] * sm.imh[wave][j];
+      const int64_t snd = p.n_per_sounding > 0 ? i / p.n_per_sounding : 0;
+      const double d = y_obs[snd * ng + lane];
+      const double e = s.eps_mn * y;
+      const double s2 = sm.eps2[lane] + e * e;
+      const double r = d - y;
+      term = r * r / s2 + log(kTwoPiA * s2);
+      sm.ybar[wave][lane] = r / s2 + (r * r / (s2 * s2) - 1.0 / s2) * s.eps_mn * s.eps_mn * y;
+    }
+    term += __shfl_xor(term, 1);
+    term += __shfl_xor(term, 2);
+    term += __shfl_xor(term, 4);
+    term += __shfl_xor(term, 8);
+    term += __shfl_xor(term, 16);
+    term += __shfl_xor(term, 32);
+    if (lane == 0) sm.ll[wave] = -0.5 * term;
+  }
+  wave_lds_sync();
+  if (L > 0 && lane < nf) {
+    double acc = 0.0;
+    for (int gg = 0; gg < ng; ++gg) acc += s.K[gg * nf + lane] * sm.ybar[wave][gg];
+    sm.wbar[wave][lane] = acc;
+  }
+  wave_lds_sync();
   if (L > 0) {
     for (int t = lane; t < NS; t += kWave) {
       double acc = 0.0;
-      for (int gq = 0; gq < 8; ++gq) acc += sm.slot[wave][gq][t];
+      for (int j = 0; j < nf; ++j) acc += sm.wbar[wave][j] * uw[(size_t)j * NS + t];
       sm.gl[wave][t] = acc;
     }
   }
   wave_lds_sync();
   if (valid && !skip && lane == 0) {
-    // one lane zeroes the particle's gradient slots and routes the merged-layer gradients
     const int64_t S = p.stride;
     const bool dec = p.layout == RJSMC_LAYOUT_DECOUPLED;
     const int rows_m = dec ? km : kc + 1;
@@ -383,7 +370,6 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
         const int sm_ = st->src_m[l];
         if (sm_ >= 0) g.m[sm_ * S + i] += gv[LMAX + l];
         if (l >= 1) {
-          // top_l moves the thickness of layer l-1 (+) and of layer l (-) unless l is the basement
           const double dz = gv[2 * LMAX + l - 1] - (l <= L - 2 ? gv[2 * LMAX + l] : 0.0);
           const int src = st->src_top[l];
           if (src >= kMaxLayers)
@@ -400,21 +386,37 @@ __global__ __launch_bounds__(kWave * kWavesA) void loglik_grad_kernel(DevSystem 
 }
 
 template <int LMAX>
-static hipError_t launch_g(const DevSystem &s, const DevParticles &p, int kc, int km, const double *y_obs, double *ll,
-                           const DevGrad &g, hipStream_t stream) {
-  const int64_t blocks = (p.n + kWavesA - 1) / kWavesA;
-  const size_t dyn = sizeof(double) * s.n_freq * s.n_gate;
-  hipLaunchKernelGGL((loglik_grad_kernel<LMAX>), dim3((unsigned)blocks), dim3(kWave * kWavesA), dyn, stream, s, p,
-                     kc, km, y_obs, ll, g);
+static hipError_t launch_g1(const DevSystem &s, const DevParticles &p, int kc, int km, const double *y_obs,
+                            double *ll, const DevGrad &g, hipStream_t stream, const int32_t *perm, const int *first,
+                            const int *last) {
+  const int64_t blocks = (p.n + kWavesA - 1) / kWavesA;   // every slot range fits
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const size_t dyn = sizeof(double) * kWavesA * s.n_freq * (3 * LMAX + 2);
+  hipLaunchKernelGGL((loglik_grad1_kernel<LMAX>), dim3((unsigned)blocks), dim3(kWave * kWavesA), dyn, stream, s, p,
+                     kc, km, y_obs, ll, g, perm, first, last);
   return hipGetLastError();
 }
 
+// Particles are evaluated by the instantiation whose layer capacity covers them: with
+// a workspace for an evaluation order (ws) and more than 8 layers of capacity, the
+// particles are ordered by descending capacity kappa + lambda + 1 on the device (the
+// counting sort of the forward's tile shapes), those above 8 layers go to the 16-layer
+// instantiation (per-lane state in private memory) and the others to the 8-layer one
+// (state in registers); otherwise one launch covers all of them.
 hipError_t launch_loglik_grad(const DevSystem &s, const DevParticles &p, int kc, int km, const double *y_obs,
-                              double *ll, const DevGrad &g, hipStream_t stream) {
+                              double *ll, const DevGrad &g, hipStream_t stream, const MutateWorkspace *ws) {
   const int lcap = p.layout == RJSMC_LAYOUT_DECOUPLED ? kc + km + 1 : kc + 1;
-  if (lcap <= 4) return launch_g<4>(s, p, kc, km, y_obs, ll, g, stream);
-  if (lcap <= 8) return launch_g<8>(s, p, kc, km, y_obs, ll, g, stream);
-  return launch_g<16>(s, p, kc, km, y_obs, ll, g, stream);
+  if (lcap <= 4) return launch_g1<4>(s, p, kc, km, y_obs, ll, g, stream, nullptr, nullptr, nullptr);
+  if (lcap <= 8) return launch_g1<8>(s, p, kc, km, y_obs, ll, g, stream, nullptr, nullptr, nullptr);
+  if (!ws || !ws->perm || p.n > ws->n || p.n < kBucketMin)
+    return launch_g1<16>(s, p, kc, km, y_obs, ll, g, stream, nullptr, nullptr, nullptr);
+  hipError_t e = launch_layer_sort(p, ws->cnt, ws->perm, stream);
+  // after the sort, cnt[kMaxLayers + b] is the end of bin b (bin b: capacity kMaxLayers - b)
+  const int *end_deep = ws->cnt + kMaxLayers + (kMaxLayers - 9);   // capacities 16 .. 9
+  const int *end_all = ws->cnt + kMaxLayers + (kMaxLayers - 1);    // every particle
+  if (e == hipSuccess) e = launch_g1<16>(s, p, kc, km, y_obs, ll, g, stream, ws->perm, nullptr, end_deep);
+  if (e == hipSuccess) e = launch_g1<8>(s, p, kc, km, y_obs, ll, g, stream, ws->perm, end_deep, end_all);
+  return e;
 }
 
 }  // namespace rjsmc

@@ -482,10 +482,11 @@ extern "C" rjsmc_status rjsmc_loglik_grad(rjsmc_ctx *c, const rjsmc_particles *p
       (dec && c->kmax_charg && !grad->z_charg))
     return fail(RJSMC_E_INVALID, "rjsmc_loglik_grad: NULL gradient array");
   rjsmc::DevGrad g{grad->phi_b, grad->phi, grad->z_cond, grad->m, grad->z_charg, grad->log10_tau, grad->c};
+  const rjsmc::MutateWorkspace ws = ctx_workspace(c);   // the evaluation order, when it holds n
   hipError_t e = hipSetDevice(c->device);
   if (e == hipSuccess)
-    e = rjsmc::launch_loglik_grad(c->dev, dp, c->kmax_cond, c->kmax_charg, y_obs, ll, g,
-                                  (hipStream_t)stream);
+    e = rjsmc::launch_loglik_grad(c->dev, dp, c->kmax_cond, c->kmax_charg, y_obs, ll, g, (hipStream_t)stream,
+                                  &ws);
   if (e != hipSuccess) return hip_fail(e, "rjsmc_loglik_grad: launch");
   return RJSMC_OK;
 }
@@ -744,7 +745,7 @@ static rjsmc_status mutate_impl(const char *who, rjsmc_ctx *c, const rjsmc_mutat
     if (mala) {
       e = rjsmc::launch_draw_types(*a, r, ds, sh.kc, sh.km, ws.mask, ws.type, active, gvalid, s);
       if (e == hipSuccess)   // gradients of the current states of the particles taking a Langevin step
-        e = rjsmc::launch_loglik_grad(c->dev, cur2, c->kmax_cond, c->kmax_charg, y_obs, ll_scratch, gcw, s);
+        e = rjsmc::launch_loglik_grad(c->dev, cur2, c->kmax_cond, c->kmax_charg, y_obs, ll_scratch, gcw, s, &ws);
     }
     if (e == hipSuccess)   // without gradient moves the proposal kernel draws the types itself
       e = rjsmc::launch_propose(sh, *a, r, ds, writable(dq), ws.mask, ws.type, gamma, mala ? &gcd : nullptr,
@@ -752,7 +753,7 @@ static rjsmc_status mutate_impl(const char *who, rjsmc_ctx *c, const rjsmc_mutat
     if (e == hipSuccess)
       e = run_forward(c, prop1, c->tuning, nullptr, y_obs, ll_scratch, s, &ws);
     if (e == hipSuccess && mala)
-      e = rjsmc::launch_loglik_grad(c->dev, prop2, c->kmax_cond, c->kmax_charg, y_obs, ll_scratch, gpw, s);
+      e = rjsmc::launch_loglik_grad(c->dev, prop2, c->kmax_cond, c->kmax_charg, y_obs, ll_scratch, gpw, s, &ws);
     if (e == hipSuccess)
       e = rjsmc::launch_accept(sh, *a, r, writable(ds), ll, dq, ll_scratch, ws.mask, ws.type, gamma,
                                mala ? &gcw_state : nullptr, mala ? &gpd : nullptr, gvalid, stats, ws.lq, s);

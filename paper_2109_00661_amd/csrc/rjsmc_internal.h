@@ -109,9 +109,12 @@ hipError_t forward_lds_bytes(const DevSystem &s, int precision, int waves_per_bl
 // perm[0..n) = particle indices in descending order of layer capacity (kappa + lambda + 1);
 // cnt: 2 kMaxLayers ints of device scratch.
 hipError_t launch_layer_sort(const DevParticles &p, int *cnt, int32_t *perm, hipStream_t stream);
+struct MutateWorkspace;
+// ws (may be NULL): an evaluation-order workspace, with which particles of a context of
+// more than 8 layers' capacity are split by their own capacity between instantiations.
 hipError_t launch_loglik_grad(const DevSystem &s, const DevParticles &p, int kmax_cond,
                               int kmax_charg, const double *y_obs, double *ll, const DevGrad &g,
-                              hipStream_t stream);
+                              hipStream_t stream, const MutateWorkspace *ws = nullptr);
 
 // SMC launchers (smc.hip).
 hipError_t launch_counter_add(int32_t *counter, int32_t delta, hipStream_t stream);
