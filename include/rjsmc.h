@@ -315,6 +315,14 @@ typedef struct {
                                    gradient-informed move (overrides mala_eps), e.g. bisected
                                    from trial proposals toward a target acceptance as the
                                    random-walk scale is (Section 3.2.2) */
+  int32_t keep_gradients;       /* 0: the gradients of the current states are recomputed when
+                                   a gradient-informed move needs them (validity cleared at the
+                                   call's start).  1: the gradients in grad_cur, and which of
+                                   them are valid, carry over from the previous rjsmc_mutate
+                                   call on this context; the caller guarantees that neither the
+                                   states nor grad_cur changed in between (e.g. successive trial
+                                   calls, which never change the states, and the call after
+                                   them) */
 } rjsmc_mutate_args;
 
 /* n_moves RJ-MCMC sweeps (Algorithm 1, mutation) targeting L^gamma(sounding) x prior.

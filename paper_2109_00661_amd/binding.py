@@ -66,7 +66,8 @@ class MutateArgs(ctypes.Structure):
                 ("z_move_sd", ctypes.c_double), ("rw_scale", ctypes.c_double), ("mala_eps", ctypes.c_double),
                 ("factors", ctypes.c_void_p), ("prior", Prior), ("step_dev", ctypes.c_void_p),
                 ("rw_scale_dev", ctypes.c_void_p), ("stats_sound", ctypes.c_void_p), ("trial", ctypes.c_int32),
-                ("zca_birth", ctypes.c_int32), ("mala_eps_dev", ctypes.c_void_p)]
+                ("zca_birth", ctypes.c_int32), ("mala_eps_dev", ctypes.c_void_p),
+                ("keep_gradients", ctypes.c_int32)]
 
 
 class BisectArgs(ctypes.Structure):
@@ -413,7 +414,7 @@ class Context:
     def mutate(self, state, ll, scratch, ll_scratch, gamma, active, y_obs, stats, *, seed, step, n_moves, n_sound,
                prior, move_prob, z_move_sd, rw_scale, factors, mala_eps=0.0, grad_cur=None, grad_prop=None,
                stream=None, step_dev=None, rw_scale_dev=None, stats_sound=None, trial=0, zca_birth=False,
-               noalloc=False, mala_eps_dev=None):
+               noalloc=False, mala_eps_dev=None, keep_gradients=False):
         """rjsmc_mutate, or with noalloc=True rjsmc_mutate_noalloc (the library's static
         scratch instead of the context's workspace)."""
         a = MutateArgs()
@@ -429,6 +430,7 @@ class Context:
         a.trial = int(trial)
         a.zca_birth = 1 if zca_birth else 0
         a.mala_eps_dev = _ptr(mala_eps_dev) if mala_eps_dev is not None else None
+        a.keep_gradients = 1 if keep_gradients else 0
         ss, sq = particles_struct(state), particles_struct(scratch)
         gc = ctypes.byref(particles_struct(grad_cur)) if grad_cur is not None else None
         gp = ctypes.byref(particles_struct(grad_prop)) if grad_prop is not None else None

@@ -739,7 +739,9 @@ static rjsmc_status mutate_impl(const char *who, rjsmc_ctx *c, const rjsmc_mutat
   // accepted move of another type changes the state
   int32_t *gvalid = mala ? ws.gvalid : nullptr;
   rjsmc::DevParticlesW gcw_state = mala ? writable(gcd) : rjsmc::DevParticlesW();
-  if (e == hipSuccess && gvalid) e = rjsmc::launch_fill_i32(gvalid, ds.n, 0, s);
+  if (a->keep_gradients != 0 && a->keep_gradients != 1)
+    return fail(RJSMC_E_INVALID, "%s: keep_gradients must be 0 or 1", who);
+  if (e == hipSuccess && gvalid && !a->keep_gradients) e = rjsmc::launch_fill_i32(gvalid, ds.n, 0, s);
   for (int r0 = 0; r0 < a->n_moves && e == hipSuccess; ++r0) {
     const int r = a->trial * (1 << 20) + r0;   // random-number move index
     if (mala) {

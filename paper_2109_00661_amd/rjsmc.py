@@ -150,13 +150,16 @@ class RJSMCRun:
                        log_lo=self.log_lo, log_hi=self.log_hi, scale=self.scale, stats_sound=self.stats_sound)
             self.ctx.scale_bisect(self.S, 1, **bis)
             for b in range(1, self.n_bisect + 1):
+                # trial sweeps never change the states: the current-state gradients of the
+                # first Langevin trial serve the later ones and the sweeps that follow
                 self.ctx.mutate(self.state, self.ll, self.bufs[1 - self.cur], self.lls[1 - self.cur], self.gamma,
                                 self.active, self.y_obs, None, n_moves=1, move_prob=MALA_ONLY if lang else RW_ONLY,
-                                stats_sound=self.stats_sound, trial=b, **tuned, **grads, **common)
+                                stats_sound=self.stats_sound, trial=b, keep_gradients=lang and b > 1, **tuned,
+                                **grads, **common)
                 self.ctx.scale_bisect(self.S, 0, **bis)
         self.ctx.mutate(self.state, self.ll, self.bufs[1 - self.cur], self.lls[1 - self.cur], self.gamma, self.active,
-                        self.y_obs, self.stats, n_moves=self.n_moves, move_prob=self.move_prob, **tuned, **grads,
-                        **common)
+                        self.y_obs, self.stats, n_moves=self.n_moves, move_prob=self.move_prob,
+                        keep_gradients=lang and self.n_bisect > 0, **tuned, **grads, **common)
         if self.archive is not None:
             self._archive_current()
         if step_dev is not None:

@@ -553,6 +553,48 @@ def test_trial_langevin_mutation_against_oracle(B, ctx, system, K_oracle, truth_
     assert acc[0] > acc[1]                           # the smaller step is accepted more often
 
 
+def test_keep_gradients_across_trials(B, system, truth_data):
+    """Trial Langevin sweeps then the real sweeps, with the current-state gradients kept
+    from call to call (keep_gradients) or recomputed in every call: bit-identical states,
+    log-likelihoods, gradients and tallies."""
+    from oracle import smc
+    S, nps = 2, 96
+    n = S * nps
+    outs = []
+    for keep in (False, True):
+        ctx = B.Context(system, precision="f64", max_particles=n)
+        p = smc.init_population(71, n, KC, KM, PR)
+        p["n_per_sounding"] = nps
+        dp = B.particles_to_device(p)
+        y = torch.as_tensor(np.tile(truth_data, (S, 1)), device="cuda")
+        ll = ctx.loglik(dp, y)
+        fdev, _ = _device_factors(p, nps, S, 12)
+        F = torch.as_tensor(fdev, device="cuda")
+        g = torch.tensor([0.02, 0.2], dtype=torch.float64, device="cuda")
+        eps = torch.tensor([0.3, 0.7], dtype=torch.float64, device="cuda")
+        st_s = torch.zeros((S, 2), dtype=torch.int64, device="cuda")
+        stats = torch.zeros((2, 8), dtype=torch.int64, device="cuda")
+        gc, gp = B.empty_device_population(n, KC, KM, nps), B.empty_device_population(n, KC, KM, nps)
+        scratch = B.empty_device_population(n, KC, KM, nps)
+        kw = dict(seed=5, step=3, n_sound=S, prior=PR, z_move_sd=15.0, rw_scale=2.38, factors=F, mala_eps=0.5,
+                  mala_eps_dev=eps, grad_cur=gc, grad_prop=gp)
+        for b in (1, 2, 3):
+            ctx.mutate(dp, ll, scratch, torch.empty_like(ll), g, None, y, None, n_moves=1,
+                       move_prob=(0, 0, 0, 0, 0, 0, 0, 1), stats_sound=st_s, trial=b, keep_gradients=keep and b > 1,
+                       **kw)
+        ctx.mutate(dp, ll, scratch, torch.empty_like(ll), g, None, y, stats, n_moves=3,
+                   move_prob=(1, 1, 1, 1, 1, 1, 0, 1), keep_gradients=keep, **kw)
+        ctx.check()
+        outs.append(({k: dp[k].cpu().numpy() for k in ("kappa", "lambda_", "phi_b", "phi", "z_cond", "m",
+                                                           "z_charg", "log10_tau", "c")},
+                     ll.cpu().numpy(), st_s.cpu().numpy(), stats.cpu().numpy()))
+    (a, lla, sa, ta), (b_, llb, sb, tb) = outs
+    for k in a:
+        assert np.array_equal(a[k], b_[k]), k
+    assert np.array_equal(lla, llb) and np.array_equal(sa, sb) and np.array_equal(ta, tb)
+    assert ta[0, 7] > 0 and sa[:, 0].sum() == 3 * n
+
+
 def test_tuned_langevin_run_graph_and_eager(B, truth_data):
     """Langevin within-model moves with the per-sounding step bisected on trial
     proposals toward acceptance 0.574: replayed step graphs equal the eager calls."""
