@@ -1137,16 +1137,56 @@ __device__ __forceinline__ void eigen_factor(double (*A)[kLd], double (*V0)[kLd]
   }
 }
 
+// Members of model (k, l) in sounding `off`, in index order, into mem; returns their
+// count (all threads).  Each wave ballots a contiguous range of 64-particle chunks, the
+// waves' counts are summed in wave order, then each wave places its members.
+__device__ __forceinline__ int model_members(const DevParticles &p, int64_t off, int N, int k, int l,
+                                             int16_t *mem, int *wcount) {
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  constexpr int NW = kAdaptThreads / kWave;
+  const int n_chunks = (N + kWave - 1) / kWave, cpw = (n_chunks + NW - 1) / NW;
+  const int ch0 = wave * cpw, ch1 = min(n_chunks, ch0 + cpw);
+  int cnt = 0;
+  for (int ch = ch0; ch < ch1; ++ch) {
+    const int i = ch * kWave + lane;
+    cnt += __popcll(__ballot(i < N && p.kappa[off + i] == k && p.lambda[off + i] == l));
+  }
+  if (lane == 0) wcount[wave] = cnt;
+  __syncthreads();
+  int base = 0, total = 0;
+  for (int w = 0; w < NW; ++w) {
+    base += w < wave ? wcount[w] : 0;
+    total += wcount[w];
+  }
+  for (int ch = ch0; ch < ch1; ++ch) {
+    const int i = ch * kWave + lane;
+    const bool sel = i < N && p.kappa[off + i] == k && p.lambda[off + i] == l;
+    const uint64_t bl = __ballot(sel);
+    if (sel) mem[base + __popcll(bl & ((1ull << lane) - 1))] = (int16_t)i;
+    base += __popcll(bl);
+  }
+  __syncthreads();
+  return total;
+}
+
+// Moments and factor of one (sounding, model).  The members' parameter vectors are staged
+// in LDS a chunk at a time by all threads (the chunk buffer is the eigen-solver's matrix
+// storage, unused until then), the mean (a thread per component) and the covariance (a
+// thread per upper-triangle entry) are summed over the members in index order, and the
+// workgroup runs the Jacobi sweeps.
 __global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(SmcShape sh, DevParticles p, rjsmc_prior pr, double *factors) {
   __shared__ int16_t mem[kMaxPerSoundingLarge];
-  __shared__ double A[kDimMax][kLd];
-  __shared__ double V0[kDimMax][kLd];
-  __shared__ double T[2][kDimMax][kLd];
+  __shared__ double AVT[4][kDimMax][kLd];    // A, V0, T[2] of the eigen solver; first the staged chunks
   __shared__ double mu[kDimMax];
   __shared__ double rc[kLd], rs[kLd];
-  __shared__ int s_nm;
+  __shared__ int wcount[kAdaptThreads / kWave];
   __shared__ int order[kDimMax];
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  double (*A)[kLd] = AVT[0];
+  double (*V0)[kLd] = AVT[1];
+  double (*T)[kDimMax][kLd] = AVT + 2;
+  double *stage = &AVT[0][0][0];
+  constexpr int kStage = 4 * kDimMax * kLd;
+  const int tid = threadIdx.x;
   const int M = sh.n_models;
   const int s = blockIdx.x / M, m = blockIdx.x % M;
   const int N = (int)(p.n_per_sounding > 0 ? p.n_per_sounding : p.n);
@@ -1154,20 +1194,7 @@ __global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(SmcShape sh, DevPa
   const int k = m / (sh.km + 1), l = m % (sh.km + 1);
   const int d = 3 + 2 * k + 2 * l, D = sh.dmax;
   double *F = factors + (int64_t)blockIdx.x * D * D;
-  // members in index order (first wave, by ballot)
-  if (wave == 0) {
-    int nm = 0;
-    for (int c0 = 0; c0 < N; c0 += kWave) {
-      const int i = c0 + lane;
-      const bool sel = i < N && p.kappa[off + i] == k && p.lambda[off + i] == l;
-      const uint64_t b = __ballot(sel);
-      if (sel) mem[nm + __popcll(b & ((1ull << lane) - 1))] = (int16_t)i;
-      nm += __popcll(b);
-    }
-    if (lane == 0) s_nm = nm;
-  }
-  __syncthreads();
-  const int nm = s_nm;
+  const int nm = model_members(p, off, N, k, l, mem, wcount);
   const bool fallback = nm <= d;
   // the factor is rewritten whole: zero, or the fallback's prior-scaled diagonal
   for (int t = tid; t < D * D; t += kAdaptThreads) {
@@ -1175,24 +1202,62 @@ __global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(SmcShape sh, DevPa
     F[t] = fallback && a < d && t == a * D + a ? 0.1 * prior_sd(pr, sh.z_max, k, l, a) : 0.0;
   }
   if (fallback) return;
-  // mean, members in index order (one thread per component)
-  for (int a = tid; a < d; a += kAdaptThreads) {
-    double acc = 0.0;
-    for (int q = 0; q < nm; ++q) acc += theta_get(p, off + mem[q], k, l, a);
-    mu[a] = acc / (double)nm;
-  }
-  __syncthreads();
-  // covariance, one thread per upper-triangle entry
-  for (int t = tid; t < d * d; t += kAdaptThreads) {
-    const int a = t / d, b = t % d;
-    if (b < a) continue;
-    const double ma = mu[a], mb = mu[b];
-    double acc = 0.0;
-    for (int q = 0; q < nm; ++q) {
-      const int64_t i = off + mem[q];
-      acc += (theta_get(p, i, k, l, a) - ma) * (theta_get(p, i, k, l, b) - mb);
+  const int C = kStage / d;                    // members per staged chunk
+  auto stage_chunk = [&](int q0, int nq) {     // stage[q * d + a] = theta_a of member q0 + q
+    for (int t = tid; t < nq * d; t += kAdaptThreads) {
+      const int q = t / d, a = t - q * d;
+      stage[t] = theta_get(p, off + mem[q0 + q], k, l, a);
     }
-    A[a][b] = acc / (double)(nm - 1);
+  };
+  // mean (a thread per component, members in index order)
+  double acc_m = 0.0;
+  for (int q0 = 0; q0 < nm; q0 += C) {
+    const int nq = min(C, nm - q0);
+    __syncthreads();
+    stage_chunk(q0, nq);
+    __syncthreads();
+    if (tid < d)
+      for (int q = 0; q < nq; ++q) acc_m += stage[q * d + tid];
+  }
+  if (tid < d) mu[tid] = acc_m / (double)nm;
+  __syncthreads();
+  // covariance (a thread per upper-triangle entry, members in index order); one staged
+  // chunk when the members fit, else the chunks again
+  const int ne = d * (d + 1) / 2;
+  int ea[2] = {0, 0}, eb[2] = {0, 0};
+  double acc_c[2] = {0.0, 0.0};
+  for (int r = 0; r < 2; ++r) {
+    int t = tid + r * kAdaptThreads, a = 0;
+    if (t < ne) {
+      while (t >= d - a) {                     // row a of the upper triangle holds d - a entries
+        t -= d - a;
+        ++a;
+      }
+      ea[r] = a;
+      eb[r] = a + t;
+    }
+  }
+  for (int q0 = 0; q0 < nm; q0 += C) {
+    const int nq = min(C, nm - q0);
+    if (q0 > 0 || nm > C) {                    // (a single chunk is still staged from the mean)
+      __syncthreads();
+      stage_chunk(q0, nq);
+      __syncthreads();
+    }
+    for (int r = 0; r < 2; ++r) {
+      if (tid + r * kAdaptThreads >= ne) continue;
+      const int a = ea[r], b = eb[r];
+      const double ma = mu[a], mb = mu[b];
+      double acc = acc_c[r];
+      for (int q = 0; q < nq; ++q) acc += (stage[q * d + a] - ma) * (stage[q * d + b] - mb);
+      acc_c[r] = acc;
+    }
+  }
+  __syncthreads();                             // the staged chunk is no longer read
+  for (int r = 0; r < 2; ++r) {
+    if (tid + r * kAdaptThreads >= ne) continue;
+    const int a = ea[r], b = eb[r];
+    A[a][b] = acc_c[r] / (double)(nm - 1);
     A[b][a] = A[a][b];
   }
   for (int t = tid; t < d * d; t += kAdaptThreads) V0[t / d][t % d] = t / d == t % d ? 1.0 : 0.0;
