@@ -994,112 +994,219 @@ constexpr int kAdaptThreads = 512;                 // workgroup of the adaptatio
 // Jacobi eigen-decomposition of the symmetric d x d matrix A (LDS, overwritten; V0 holds
 // the identity, T two spare d x d buffers) and the factor F = U diag(sqrt Lambda) into
 // F[r D + a] (direction r), eigenvalues descending, each direction signed so that its
-// largest-magnitude component is positive.  One wavefront.
+// largest-magnitude component is positive.
 //
 // The sweeps use the round-robin (tournament) ordering: a sweep is nn - 1 rounds of nn/2
-// disjoint index pairs (nn = d rounded up to even), so every pair of a round is rotated
-// at once, A <- J^T A J with J the product of the round's rotations, in one pass over the
-// entries (each reads the four entries of A its row and column pairs touch) together
-// with V <- V J: two barriers per round.  Each pair's 2x2 block is touched by its own
-// rotation only, so its diagonal takes the classical update and its off-diagonal entry
-// is set to zero.
+// disjoint index pairs (nn = d rounded up to even, the padding index nn - 1 when d is
+// odd): in round r index nn - 1 meets r and every other index i meets (2r - i) mod
+// (nn - 1).  Every pair of a round is rotated at once, A <- J^T A J with J the product of
+// the round's rotations, together with V <- V J; each pair's 2x2 block is touched by its
+// own rotation only, so its diagonal takes the classical update and its off-diagonal
+// entry is set to zero.  A round is one pass and one barrier (the matrices ping-pong
+// between two buffers), pipelined: waves 1.. apply round r's rotations (read from a
+// two-slot table) to the strictly upper entries of A (mirrored) and to V, while lane i
+// of wave 0 owns index i: it keeps i's rotation and new diagonal in registers, writes
+// that diagonal, and forms the rotation of i's pair in round r + 1 from the pair's 2x2
+// block after round r (its partner's state by lane exchange, the off-diagonal entry by
+// the same expression as the other waves), so that both lanes of a pair derive the same
+// rotation.  The rotations of the first round are formed before the sweeps.
+__device__ __forceinline__ double jacobi_entry(double cx, double sx, double cj, double sj, double axj, double axy,
+                                               double ayj, double ayy) {
+  // entry (x, j) of J^T A J: cx (cj a_xj + sj a_x,yj) + sx (cj a_yx,j + sj a_yx,yj), fused
+  // the same way wherever it is evaluated
+  return fma(cx, fma(cj, axj, sj * axy), sx * fma(cj, ayj, sj * ayy));
+}
+
+// Rotation of the pair (p, q), p < q, from its 2x2 block: c, s with J[p][p] = J[q][q] = c,
+// J[p][q] = s = -J[q][p], and the rotated diagonal entries (identity if apq = 0).  The
+// angle phi is the smaller solution, t = tan phi the smaller root of t^2 + 2 theta t - 1 = 0
+// with theta = (aqq - app) / (2 apq).  With rho = 1 / sqrt((aqq - app)^2 + 4 apq^2),
+// cos 2phi = |aqq - app| rho and h = cos^2 phi = (1 + cos 2phi) / 2 lies in [1/2, 1], so
+// with q = 1 / sqrt(h): c = h q, |t| = |apq| rho / h = |apq| rho q^2, s = t c (two
+// reciprocal square roots, no division).
+__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double &c, double &s,
+                                                double &dp, double &dq) {
+  c = 1.0;
+  s = 0.0;
+  dp = app;
+  dq = aqq;
+  if (apq == 0.0) return;
+  const double dd = aqq - app;
+  const double rho = rsqrt(fma(dd, dd, 4.0 * apq * apq));
+  const double h = fma(0.5 * fabs(dd), rho, 0.5);
+  const double q = rsqrt(h);
+  const double at = fabs(apq) * rho * (q * q);
+  const double tt = (dd >= 0.0) == (apq >= 0.0) ? at : -at;
+  c = h * q;
+  s = tt * c;
+  dp = app - tt * apq;
+  dq = aqq + tt * apq;
+}
+
 template <int NT>
 __device__ __forceinline__ void eigen_factor(double (*A)[kLd], double (*V0)[kLd], double (*T)[kDimMax][kLd],
-                                             double *rc, double *rs, int *order, int d, int D, double *F) {
+                                             int *order, int d, int D, double *F) {
+  static_assert(NT >= 2 * kWave, "the pipelined rounds need wave 0 and at least one more wave");
+  static_assert(kDimMax <= kWave, "wave 0 holds one index per lane");
+  constexpr int kBulk = NT - kWave;             // threads of waves 1..
+  constexpr int kItems = (kDimMax * (kDimMax - 1) / 2 + kDimMax * kDimMax + kBulk - 1) / kBulk;
+  constexpr int NW = NT / kWave;
   const int tid = threadIdx.x;
-  auto sync = [] {
-    if (NT > kWave)
-      __syncthreads();
-    else
-      wave_lds_sync();
-  };
-  __shared__ int partner[kLd];
-  __shared__ int rotated[kLd];
-  __shared__ double dnew[kLd];
-  __shared__ double red[2][NT / kWave];
+  __shared__ double red[2][2][NW];              // per sweep parity: the waves' off-diagonal and diagonal sums
+  __shared__ double2 rot_cs[2][kDimMax + 1];    // per index i of a round: (J[i][i], J[partner][i]); slot kDimMax: (1, 0)
   double (*Ac)[kLd] = A;         // current matrix and eigenvector estimate, and the
   double (*An)[kLd] = T[0];      // buffers a round writes (swapped after each round)
   double (*Vc)[kLd] = V0;
   double (*Vn)[kLd] = T[1];
-  const int nn = (d + 1) & ~1, np = nn / 2;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    double offn = 0.0, diag = 0.0;
-    for (int t = tid; t < d * d; t += NT) {
-      const int a = t / d, b = t % d;
-      if (a != b) offn += Ac[a][b] * Ac[a][b];
-      else diag += Ac[a][b] * Ac[a][b];
-    }
+  const int nn = (d + 1) & ~1, nr = nn - 1;
+  // partner of index i in round r; an index paired with the padding index is its own
+  auto partner = [nr, d](int i, int r) {
+    int y = 2 * r - i;
+    y += y < 0 ? nr : 0;
+    y -= y >= nr ? nr : 0;
+    y = i == r ? nr : y;
+    y = i == nr ? r : y;
+    return y < d ? y : i;
+  };
+  // the waves' sums of squares of the off-diagonal and diagonal entries, added in wave
+  // order (all threads; slot `sl` of red, one barrier)
+  auto converged = [&](double offn, double diag, int sl) {
     offn = wave_sum(offn);
     diag = wave_sum(diag);
-    if (NT > kWave) {                  // the waves' sums, added in wave order
-      if ((tid & (kWave - 1)) == 0) {
-        red[0][tid / kWave] = offn;
-        red[1][tid / kWave] = diag;
+    if ((tid & (kWave - 1)) == 0) {
+      red[sl][0][tid / kWave] = offn;
+      red[sl][1][tid / kWave] = diag;
+    }
+    __syncthreads();
+    offn = 0.0;
+    diag = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      offn += red[sl][0][w];
+      diag += red[sl][1][w];
+    }
+    return !(offn > 1e-24 * diag);
+  };
+  // the bulk threads' items: strictly upper entries of A, then the entries of V
+  const int nA = d * (d - 1) / 2, nItems = nA + d * d;
+  int ix[kItems], ij[kItems];
+#pragma unroll
+  for (int e = 0; e < kItems; ++e) {
+    int t = tid - kWave + e * kBulk;
+    ix[e] = -1;
+    ij[e] = 0;
+    if (tid < kWave || t >= nItems) continue;
+    if (t < nA) {
+      int a = 0;
+      while (t >= d - 1 - a) {         // row a of the strict upper triangle holds d - 1 - a entries
+        t -= d - 1 - a;
+        ++a;
       }
-      __syncthreads();
+      ix[e] = a;
+      ij[e] = a + 1 + t;
+    } else {
+      t -= nA;
+      ix[e] = kDimMax + t / d;         // V entry, row offset by kDimMax
+      ij[e] = t % d;
+    }
+  }
+  // wave 0, lane i: index i's rotation (c, s) and its diagonal after the round in progress
+  // (a pair that is not rotated has s = 0)
+  double my_c = 1.0, my_s = 0.0, my_dn = 0.0;
+  double offn = 0.0, diag = 0.0;
+  if (tid < d) {
+    const int y = partner(tid, 0);
+    my_dn = Ac[tid][tid];
+    diag = my_dn * my_dn;
+    if (y != tid) {
+      const int p = min(tid, y), q = max(tid, y);
+      double c, sn, dp, dq;
+      jacobi_rotation(Ac[p][p], Ac[q][q], Ac[p][q], c, sn, dp, dq);
+      my_c = c;
+      my_s = tid == p ? -sn : sn;
+      my_dn = tid == p ? dp : dq;
+    }
+    rot_cs[0][tid] = make_double2(my_c, my_s);
+  }
+  if (tid < 2) rot_cs[tid][kDimMax] = make_double2(1.0, 0.0);   // the identity, for the rows of V
+#pragma unroll
+  for (int e = 0; e < kItems; ++e)
+    if (ix[e] >= 0 && ix[e] < kDimMax) offn += 2.0 * Ac[ix[e]][ij[e]] * Ac[ix[e]][ij[e]];
+  bool done = converged(offn, diag, 1);
+  int g = 0;                           // rounds done (table slot of the next round: g & 1)
+  for (int sweep = 0; sweep < 40 && !done; ++sweep) {
+    for (int round = 0; round < nr; ++round, ++g) {
+      const int sl = g & 1;
+      const bool last = round + 1 == nr; // this round's result is tested for convergence
       offn = 0.0;
       diag = 0.0;
-      for (int w = 0; w < NT / kWave; ++w) {
-        offn += red[0][w];
-        diag += red[1][w];
-      }
-      __syncthreads();
-    }
-    if (!(offn > 1e-24 * diag)) break;
-    for (int round = 0; round < nn - 1; ++round) {
-      // pair `tid` of this round: (nn-1, round) and ((round + j) mod (nn-1), (round - j) mod (nn-1))
-      if (tid < np) {
-        const int x = tid == 0 ? nn - 1 : (round + tid) % (nn - 1);
-        const int y = tid == 0 ? round : (round - tid + (nn - 1)) % (nn - 1);
-        const int pp = x < y ? x : y, qq = x < y ? y : x;
-        if (qq < d) {
-          double cth = 1.0, sth = 0.0;
-          const double apq = Ac[pp][qq];
-          const bool rot = apq != 0.0;
-          if (rot) {
-            const double app = Ac[pp][pp], aqq = Ac[qq][qq];
-            // t = tan of the rotation angle, the smaller root of t^2 + 2 theta t - 1 = 0 with
-            // theta = (aqq - app) / (2 apq), written without forming theta
-            const double dd = aqq - app;
-            const double tt = (dd >= 0.0 ? 2.0 : -2.0) * apq / (fabs(dd) + sqrt(fma(dd, dd, 4.0 * apq * apq)));
-            cth = rsqrt(fma(tt, tt, 1.0));
-            sth = tt * cth;
-            dnew[pp] = app - tt * apq;
-            dnew[qq] = aqq + tt * apq;
+      if (tid < kWave) {
+        // the partner in the next round, the 2x2 block's entries before this round (all
+        // loads ahead of this round's stores), and the partner's state in this round by
+        // lane exchange (every lane of the wave takes part)
+        const int r1 = last ? 0 : round + 1;
+        const int i = tid < d ? tid : 0;
+        const int y1 = partner(i, r1);
+        const bool low = i < y1;
+        const int p = low ? i : y1, q = low ? y1 : i;
+        const int yp = partner(p, round), yq = partner(q, round);
+        const double m0 = Ac[p][q], m1 = Ac[p][yq], m2 = Ac[yp][q], m3 = Ac[yp][yq];
+        const double c_y = __shfl(my_c, y1), s_y = __shfl(my_s, y1), dn_y = __shfl(my_dn, y1);
+        if (tid < d) {
+          const double dn_now = my_dn;
+          double c = 1.0, sn = 0.0, dp = my_dn, dq = my_dn;
+          if (y1 != i) {
+            const double cp = low ? my_c : c_y, sp = low ? my_s : s_y;
+            const double cq = low ? c_y : my_c, sq = low ? s_y : my_s;
+            double apq = jacobi_entry(cp, sp, cq, sq, m0, m1, m2, m3);
+            apq = q == yp ? 0.0 : apq;   // (p, q) rotated in this round as well (only when nn = 2)
+            jacobi_rotation(low ? my_dn : dn_y, low ? dn_y : my_dn, apq, c, sn, dp, dq);
           }
-          partner[pp] = qq;
-          partner[qq] = pp;
-          rc[pp] = cth;
-          rs[pp] = -sth;
-          rc[qq] = cth;
-          rs[qq] = sth;
-          rotated[pp] = rot;
-          rotated[qq] = rot;
-        } else if (pp < d) {           // paired with the padding index: untouched
-          partner[pp] = pp;
-          rc[pp] = 1.0;
-          rs[pp] = 0.0;
-          rotated[pp] = 0;
+          my_c = c;
+          my_s = low ? -sn : sn;
+          my_dn = low ? dp : dq;
+          An[i][i] = dn_now;
+          diag = dn_now * dn_now;
+          rot_cs[sl ^ 1][i] = make_double2(my_c, my_s);
+        }
+      } else {
+        // all loads of the thread's items, then the entries and the stores; a V entry is
+        // the same expression with the identity for its row (table slot kDimMax)
+        double2 lx[kItems], lj[kItems];
+        double m0[kItems], m1[kItems], m2[kItems], m3[kItems];
+#pragma unroll
+        for (int e = 0; e < kItems; ++e) {
+          const int x = ix[e], j = ij[e];
+          if (x < 0) continue;
+          const bool isA = x < kDimMax;
+          const int r = isA ? x : x - kDimMax;
+          const int yj = partner(j, round), yx = isA ? partner(x, round) : r;
+          double (*M)[kLd] = isA ? Ac : Vc;
+          lx[e] = rot_cs[sl][isA ? x : kDimMax];
+          lj[e] = rot_cs[sl][j];
+          m0[e] = M[r][j];
+          m1[e] = M[r][yj];
+          m2[e] = M[yx][j];
+          m3[e] = M[yx][yj];
+        }
+#pragma unroll
+        for (int e = 0; e < kItems; ++e) {
+          const int x = ix[e], j = ij[e];
+          if (x < 0) continue;
+          const double v = jacobi_entry(lx[e].x, lx[e].y, lj[e].x, lj[e].y, m0[e], m1[e], m2[e], m3[e]);
+          if (x < kDimMax) {           // A entry (x < j), mirrored; a pair of this round: 0
+            const double a = j == partner(x, round) ? 0.0 : v;
+            An[x][j] = a;
+            An[j][x] = a;
+            offn += 2.0 * a * a;
+          } else {                     // V entry (x - kDimMax, j)
+            Vn[x - kDimMax][j] = v;
+          }
         }
       }
-      sync();
-      // one pass: An = J^T Ac J (a rotated pair's 2x2 block takes the classical update:
-      // its diagonal dnew, its off-diagonal entry 0) and Vn = Vc J
-      for (int t = tid; t < d * d; t += NT) {
-        const int x = t / d, j = t % d;
-        const int yx = partner[x], yj = partner[j];
-        const double cx = rc[x], sx = rs[x], cj = rc[j], sj = rs[j];
-        double v;
-        if (rotated[x] && j == x)
-          v = dnew[x];
-        else if (rotated[x] && j == yx)
-          v = 0.0;
-        else
-          v = cx * (cj * Ac[x][j] + sj * Ac[x][yj]) + sx * (cj * Ac[yx][j] + sj * Ac[yx][yj]);
-        An[x][j] = v;
-        Vn[x][j] = cj * Vc[x][j] + sj * Vc[x][yj];
-      }
-      sync();
+      if (last)
+        done = converged(offn, diag, sweep & 1);   // (its barrier ends the round)
+      else
+        __syncthreads();
       double (*sw)[kLd] = Ac;
       Ac = An;
       An = sw;
@@ -1121,7 +1228,7 @@ __device__ __forceinline__ void eigen_factor(double (*A)[kLd], double (*V0)[kLd]
       order[b] = v;
     }
   }
-  sync();
+  __syncthreads();
   // eigenvalues below 1e-12 of the largest are the rounding noise of a singular
   // covariance (a re-sampled model with fewer distinct members than dimensions): zero
   const double lmax = Ac[order[0]][order[0]];
@@ -1178,7 +1285,6 @@ __global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(SmcShape sh, DevPa
   __shared__ int16_t mem[kMaxPerSoundingLarge];
   __shared__ double AVT[4][kDimMax][kLd];    // A, V0, T[2] of the eigen solver; first the staged chunks
   __shared__ double mu[kDimMax];
-  __shared__ double rc[kLd], rs[kLd];
   __shared__ int wcount[kAdaptThreads / kWave];
   __shared__ int order[kDimMax];
   double (*A)[kLd] = AVT[0];
@@ -1262,7 +1368,7 @@ __global__ __launch_bounds__(kAdaptThreads) void adapt_kernel(SmcShape sh, DevPa
   }
   for (int t = tid; t < d * d; t += kAdaptThreads) V0[t / d][t % d] = t / d == t % d ? 1.0 : 0.0;
   __syncthreads();
-  eigen_factor<kAdaptThreads>(A, V0, T, rc, rs, order, d, D, F);
+  eigen_factor<kAdaptThreads>(A, V0, T, order, d, D, F);
 }
 
 hipError_t launch_adapt(const SmcShape &sh, const DevParticles &p, int n_sound, const rjsmc_prior &pr,
@@ -1288,7 +1394,6 @@ __global__ __launch_bounds__(kAdaptThreads) void adapt_recycled_kernel(SmcShape 
   __shared__ double V0[kDimMax][kLd];
   __shared__ double T[2][kDimMax][kLd];
   __shared__ double mu[kDimMax];
-  __shared__ double rc[kLd], rs[kLd];
   __shared__ int s_ready;
   __shared__ int order[kDimMax];
   __shared__ double wst[kWave];
@@ -1434,7 +1539,7 @@ __global__ __launch_bounds__(kAdaptThreads) void adapt_recycled_kernel(SmcShape 
   }
   __syncthreads();
   if (!s_ready) return;
-  eigen_factor<kAdaptThreads>(A, V0, T, rc, rs, order, d, D, F);
+  eigen_factor<kAdaptThreads>(A, V0, T, order, d, D, F);
 }
 
 hipError_t launch_adapt_recycled(const SmcShape &sh, const DevParticles &p, const double *ll, const double *gamma,
