@@ -1740,6 +1740,13 @@ __device__ bool zca_move(double *th, int &k, int &l, bool birth, int part, doubl
   return true;
 }
 
+// One thread's column of an LDS array laid out [entry][thread].
+struct LdsColumn {
+  double *p;
+  int stride;
+  __device__ double &operator[](int j) const { return p[(int64_t)j * stride]; }
+};
+
 // Proposal of move `move` for every particle (type from draw_types_kernel): written to
 // `prop`; mask[i] = 1 if the proposal needs a likelihood, 2 if it needs a likelihood and
 // a gradient, 0 if it is rejected outright.  MALA / ZCA: whether the launch can hold
@@ -1777,7 +1784,13 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
   uniforms(a.seed, (uint32_t)i, (uint32_t)step_of(a), (uint32_t)move, 1u, u1, u2);
   uniforms(a.seed, (uint32_t)i, (uint32_t)step_of(a), (uint32_t)move, 2u, u3, u4);
   int k = st.kappa[i], l = st.lambda[i];
-  double zc[kMaxLayers], ph[kMaxLayers], zm[kMaxLayers], mm[kMaxLayers];
+  // the layer arrays in LDS (one column per thread): private arrays indexed at run time
+  // would live in scratch memory
+  extern __shared__ double prop_lds[];
+  const int T = blockDim.x;
+  double *lds0 = prop_lds + threadIdx.x;
+  const LdsColumn zc{lds0, T}, ph{lds0 + (int64_t)kc * T, T}, zm{lds0 + (int64_t)2 * kc * T, T},
+      mm{lds0 + (int64_t)(2 * kc + km) * T, T};
   for (int j = 0; j < k; ++j) {
     zc[j] = st.z_cond[j * S + i];
     ph[j] = st.phi[j * S + i];
@@ -1827,7 +1840,7 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
   } else if (t == RJSMC_MOVE_SIGMA_BIRTH || t == RJSMC_MOVE_M_BIRTH) {
     const bool sig = t == RJSMC_MOVE_SIGMA_BIRTH;
     int &n = sig ? k : l;
-    double *z = sig ? zc : zm, *v = sig ? ph : mm;
+    const LdsColumn z = sig ? zc : zm, v = sig ? ph : mm;
     if (n < (sig ? kc : km)) {
       const double zn = sh.z_max * u1;
       const double vn = sig ? affine(pr.phi_lo, pr.phi_hi, u2) : affine(pr.m_lo, pr.m_hi, u2);
@@ -1845,7 +1858,7 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
   } else if (t == RJSMC_MOVE_SIGMA_DEATH || t == RJSMC_MOVE_M_DEATH) {
     const bool sig = t == RJSMC_MOVE_SIGMA_DEATH;
     int &n = sig ? k : l;
-    double *z = sig ? zc : zm, *v = sig ? ph : mm;
+    const LdsColumn z = sig ? zc : zm, v = sig ? ph : mm;
     if (n > 0) {
       int j = (int)(u1 * (double)n);
       j = j > n - 1 ? n - 1 : j;
@@ -1859,7 +1872,7 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
   } else if (t == RJSMC_MOVE_SIGMA_MOVE || t == RJSMC_MOVE_M_MOVE) {
     const bool sig = t == RJSMC_MOVE_SIGMA_MOVE;
     const int n = sig ? k : l;
-    double *z = sig ? zc : zm;
+    const LdsColumn z = sig ? zc : zm;
     if (n > 0) {
       int j = (int)(u1 * (double)n);
       j = j > n - 1 ? n - 1 : j;
@@ -2064,11 +2077,17 @@ hipError_t launch_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int mo
                           const DevParticlesW &prop, int32_t *mask, int32_t *type, const double *gamma,
                           const DevParticles *grad_cur, int32_t *gvalid, double *lq, const int32_t *active,
                           bool draw, hipStream_t stream) {
-  const int64_t blocks = (state.n + 255) / 256;
+  // the four layer arrays of each thread in LDS; 256 threads per workgroup (as the kernels
+  // before and after it, so that a small population stays on one compute unit and its L2)
+  // unless the arrays of the largest capacities need fewer
+  const size_t per_thread = sizeof(double) * (size_t)(2 * sh.kc + 2 * sh.km);
+  const int kThreads = per_thread * 256 <= 64 * 1024 ? 256 : kWave;
+  const int64_t blocks = (state.n + kThreads - 1) / kThreads;
+  const size_t lds = per_thread * kThreads;
   const DevParticles g = grad_cur ? *grad_cur : DevParticles();
   auto go = [&](auto kernel) {
-    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(256), 0, stream, sh, a, move, state, prop, mask, type,
-                       gamma, g, gvalid, lq, active, draw ? 1 : 0);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kThreads), lds, stream, sh, a, move, state, prop, mask,
+                       type, gamma, g, gvalid, lq, active, draw ? 1 : 0);
   };
   const bool mala = grad_cur != nullptr, zca = a.zca_birth != 0;
   if (mala && zca)
