@@ -1,20 +1,22 @@
 // Log-likelihood and its gradient (reverse sweep) for gfx950.
 //
 // One wavefront per particle, lanes tiling (frequency, filter abscissa) as in the
-// forward kernel.  Phase A evaluates the forward model to obtain y, ll and
-// w_j = d ll / d Im H(w_j) = sum_g K_gj d ll / d y_g.  Phase B revisits every pair: it runs
-// the projective reflection recursion bottom-up, keeping the state (N_l, D_l) of every
-// interface in a per-lane array (in registers up to 8 merged layers; above, runtime layer
-// loops over arrays in the wave's private memory, which keeps the register count low
-// enough for two waves per SIMD), then sweeps top-down through the surface and every
-// interface, propagating the adjoint of c_k w_j Im r and accumulating, per lane and
-// frequency, the complex adjoints of the layer wavenumbers
-// k2_l = i w mu0 sigma_hat_l and the adjoints of the thicknesses.  The u_l and E_l of the
-// recursion are recomputed in the sweep instead of stored.  Per frequency the adjoints
-// are mapped through the Cole-Cole terms to (log10 sigma_inf, m) of each merged layer and
-// to (log10 tau, c); after all frequencies the merged-layer gradients are routed back to
-// the particle's parameters through the merge (an interface moves the thickness above
-// and below it).
+// forward kernel, and every (frequency, abscissa) pair visited once.  Per pair the lane
+// runs the projective reflection recursion bottom-up, keeping the state (N_l, D_l) of
+// every interface in a per-lane array (in registers up to 8 merged layers; above, runtime
+// layer loops over arrays in the wave's private memory, which keeps the register count
+// low enough for two waves per SIMD); the same recursion gives Im r_TE for the Hankel sum.
+// It then sweeps top-down through the surface and every interface, propagating the
+// adjoint of c_k Im r (the reverse sweep is linear in its seed, so the filter coefficient
+// alone seeds it) and accumulating, per lane and frequency, the complex adjoints of the
+// layer wavenumbers k2_l = i w mu0 sigma_hat_l and the adjoints of the thicknesses.  The
+// u_l and E_l of the recursion are recomputed in the sweep instead of stored.  Per
+// frequency these derivatives of Im H(w_j) are mapped through the Cole-Cole terms to a
+// slot vector over (log10 sigma_inf, m) of each merged layer, the thicknesses and
+// (log10 tau, c), parked in LDS; once the gates and the likelihood are formed, the
+// gradient is sum_j wbar_j u_j with wbar_j = d ll / d Im H(w_j) = sum_g K_gj d ll / d y_g,
+// and the merged-layer gradients are routed back to the particle's parameters through the
+// merge (an interface moves the thickness above and below it).
 #include <hip/hip_runtime.h>
 
 #include "cplx.h"

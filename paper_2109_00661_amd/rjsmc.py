@@ -259,7 +259,7 @@ class RJSMCRun:
         return self.ctx.posterior_predictive(self.state, self.S, self.y_obs)
 
     def model_probabilities(self):
-        """pi_T(k | y) = N_{T,k} / N per sounding (Section 3.2.1)."""
-        k = self.state["kappa"].cpu().numpy() * (self.ctx.kmax_charg + 1) + self.state["lambda_"].cpu().numpy()
-        k = k.reshape(self.S, self.N)
-        return np.stack([np.bincount(row, minlength=self.M) / self.N for row in k])
+        """pi_T(k | y) = N_{T,k} / N per sounding (Section 3.2.1), from the model counts of
+        the device summary (rjsmc_summarize)."""
+        counts = self.ctx.summarize(self.state, self.S)["model_count"]
+        return counts.cpu().numpy().astype(np.float64) / self.N
