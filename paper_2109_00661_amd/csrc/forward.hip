@@ -326,9 +326,54 @@ __global__ __launch_bounds__(256) void sort_scatter_kernel(DevParticles p, int *
     todo &= ~same;
   }
 }
+
+// The whole sort in one workgroup, for small populations (where the four launches above
+// are latency, not work): every thread loads the bins of its particles first (at most
+// kSortRounds, in registers), counts them with LDS atomics, and after the scan places
+// each particle at the slot an LDS atomic on its bin's cursor returns; the same counts and
+// bin ends in cnt.
+constexpr int kSortThreads = 1024;
+constexpr int kSortRounds = 32;
+constexpr int64_t kSortOneBlockMax = (int64_t)kSortThreads * kSortRounds;
+__global__ __launch_bounds__(kSortThreads) void sort_block_kernel(DevParticles p, int *cnt, int32_t *perm) {
+  __shared__ int hist[kCapBins], cur[kCapBins];
+  if (threadIdx.x < kCapBins) hist[threadIdx.x] = 0;
+  const int64_t n = p.n;
+  int bins[kSortRounds];
+#pragma unroll
+  for (int k = 0; k < kSortRounds; ++k) {
+    const int64_t i = (int64_t)k * kSortThreads + threadIdx.x;
+    bins[k] = i < n ? cap_bin(p, i) : -1;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSortRounds; ++k)
+    if (bins[k] >= 0) atomicAdd(&hist[bins[k]], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int b = 0; b < kCapBins; ++b) {
+      cur[b] = acc;
+      acc += hist[b];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSortRounds; ++k)
+    if (bins[k] >= 0) perm[atomicAdd(&cur[bins[k]], 1)] = (int32_t)((int64_t)k * kSortThreads + threadIdx.x);
+  __syncthreads();
+  if (threadIdx.x < kCapBins) {
+    cnt[threadIdx.x] = hist[threadIdx.x];
+    cnt[kCapBins + threadIdx.x] = cur[threadIdx.x];   // the end of each bin
+  }
+}
 }  // namespace
 
 hipError_t launch_layer_sort(const DevParticles &p, int *cnt, int32_t *perm, hipStream_t stream) {
+  if (p.n <= kSortOneBlockMax) {
+    hipLaunchKernelGGL(sort_block_kernel, dim3(1), dim3(kSortThreads), 0, stream, p, cnt, perm);
+    return hipGetLastError();
+  }
   const int64_t blocks = (p.n + 255) / 256;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(sort_zero_kernel, dim3(1), dim3(64), 0, stream, cnt);
