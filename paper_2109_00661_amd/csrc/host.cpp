@@ -742,8 +742,24 @@ static rjsmc_status mutate_impl(const char *who, rjsmc_ctx *c, const rjsmc_mutat
   if (a->keep_gradients != 0 && a->keep_gradients != 1)
     return fail(RJSMC_E_INVALID, "%s: keep_gradients must be 0 or 1", who);
   if (e == hipSuccess && gvalid && !a->keep_gradients) e = rjsmc::launch_fill_i32(gvalid, ds.n, 0, s);
+  // without gradient moves, the decision of a sweep and the proposal of the next share a
+  // launch (both per particle)
+  const bool fuse = !mala;
   for (int r0 = 0; r0 < a->n_moves && e == hipSuccess; ++r0) {
     const int r = a->trial * (1 << 20) + r0;   // random-number move index
+    if (fuse) {
+      if (r0 == 0)
+        e = rjsmc::launch_propose(sh, *a, r, ds, writable(dq), ws.mask, ws.type, gamma, nullptr, nullptr, ws.lq,
+                                  active, true, s);
+      else
+        e = rjsmc::launch_accept_propose(sh, *a, r - 1, r, writable(ds), ll, writable(dq), ll_scratch, ws.mask,
+                                         ws.type, gamma, stats, ws.lq, active, s);
+      if (e == hipSuccess) e = run_forward(c, prop1, c->tuning, nullptr, y_obs, ll_scratch, s, &ws);
+      if (e == hipSuccess && r0 + 1 == a->n_moves)
+        e = rjsmc::launch_accept(sh, *a, r, writable(ds), ll, dq, ll_scratch, ws.mask, ws.type, gamma, nullptr,
+                                 nullptr, nullptr, stats, ws.lq, s);
+      continue;
+    }
     if (mala) {
       e = rjsmc::launch_draw_types(*a, r, ds, sh.kc, sh.km, ws.mask, ws.type, active, gvalid, s);
       if (e == hipSuccess)   // gradients of the current states of the particles taking a Langevin step

@@ -154,6 +154,11 @@ hipError_t launch_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int mo
                           const DevParticlesW &prop, int32_t *mask, int32_t *type, const double *gamma,
                           const DevParticles *grad_cur, int32_t *gvalid, double *lq, const int32_t *active,
                           bool draw, hipStream_t stream);
+// Decision of sweep move_prev and proposal of sweep move in one launch (no gradient moves).
+hipError_t launch_accept_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int move_prev, int move,
+                                 const DevParticlesW &state, double *ll, const DevParticlesW &prop,
+                                 const double *ll_prop, int32_t *mask, int32_t *type, const double *gamma,
+                                 int64_t *stats, double *lq, const int32_t *active, hipStream_t stream);
 hipError_t launch_accept(const SmcShape &sh, const rjsmc_mutate_args &a, int move, const DevParticlesW &state,
                          double *ll, const DevParticles &prop, const double *ll_prop, const int32_t *mask,
                          const int32_t *type, const double *gamma, const DevParticlesW *grad_cur,

@@ -938,7 +938,7 @@ hipError_t launch_reweight_resample(const SmcShape &sh, const rjsmc_reweight_arg
 
 // ---------------------------------------------------------------- parameter vectors --
 // theta = (phi_b, phi_1..k, z_1..k, m_1..l, zm_1..l, log10 tau, c) of a decoupled particle.
-__device__ __forceinline__ DevParticles readonly(const DevParticlesW &w) {
+__host__ __device__ __forceinline__ DevParticles readonly(const DevParticlesW &w) {
   DevParticles r;
   r.n = w.n;
   r.stride = w.stride;
@@ -1754,11 +1754,10 @@ struct LdsColumn {
 // private arrays they need, are compiled out; a particle drawn for an excluded move is
 // rejected).
 template <bool MALA, bool ZCA>
-__global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_args a, int move, DevParticles st,
-                                                      DevParticlesW prop, int32_t *mask, int32_t *type,
-                                                      const double *gamma, DevParticles gcur, int32_t *gvalid,
-                                                      double *lq, const int32_t *active, int draw) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void propose_particle(int64_t i, const SmcShape &sh, const rjsmc_mutate_args &a, int move,
+                                                 const DevParticles &st, const DevParticlesW &prop, int32_t *mask,
+                                                 int32_t *type, const double *gamma, const DevParticles &gcur,
+                                                 int32_t *gvalid, double *lq, const int32_t *active, int draw) {
   if (i >= st.n) return;
   const int64_t snd = st.n_per_sounding > 0 ? i / st.n_per_sounding : 0;
   const int64_t S = st.stride, So = prop.stride;
@@ -1840,7 +1839,7 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
   } else if (t == RJSMC_MOVE_SIGMA_BIRTH || t == RJSMC_MOVE_M_BIRTH) {
     const bool sig = t == RJSMC_MOVE_SIGMA_BIRTH;
     int &n = sig ? k : l;
-    const LdsColumn z = sig ? zc : zm, v = sig ? ph : mm;
+    const LdsColumn z{sig ? zc.p : zm.p, T}, v{sig ? ph.p : mm.p, T};
     if (n < (sig ? kc : km)) {
       const double zn = sh.z_max * u1;
       const double vn = sig ? affine(pr.phi_lo, pr.phi_hi, u2) : affine(pr.m_lo, pr.m_hi, u2);
@@ -1858,7 +1857,7 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
   } else if (t == RJSMC_MOVE_SIGMA_DEATH || t == RJSMC_MOVE_M_DEATH) {
     const bool sig = t == RJSMC_MOVE_SIGMA_DEATH;
     int &n = sig ? k : l;
-    const LdsColumn z = sig ? zc : zm, v = sig ? ph : mm;
+    const LdsColumn z{sig ? zc.p : zm.p, T}, v{sig ? ph.p : mm.p, T};
     if (n > 0) {
       int j = (int)(u1 * (double)n);
       j = j > n - 1 ? n - 1 : j;
@@ -1872,7 +1871,7 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
   } else if (t == RJSMC_MOVE_SIGMA_MOVE || t == RJSMC_MOVE_M_MOVE) {
     const bool sig = t == RJSMC_MOVE_SIGMA_MOVE;
     const int n = sig ? k : l;
-    const LdsColumn z = sig ? zc : zm;
+    const LdsColumn z{sig ? zc.p : zm.p, T};
     if (n > 0) {
       int j = (int)(u1 * (double)n);
       j = j > n - 1 ? n - 1 : j;
@@ -1961,13 +1960,23 @@ __global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_
   }
 }
 
-// Metropolis-Hastings decision: accept when ln u < gamma (ll' - ll).
-__global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_args a, int move, DevParticlesW st,
-                                                     double *ll, DevParticles prop, const double *ll_prop,
-                                                     const int32_t *mask, const int32_t *type, const double *gamma,
-                                                     DevParticlesW gcur, DevParticles gprop, int32_t *gvalid,
-                                                     int64_t *stats, const double *lq) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <bool MALA, bool ZCA>
+__global__ __launch_bounds__(256) void propose_kernel(SmcShape sh, rjsmc_mutate_args a, int move, DevParticles st,
+                                                      DevParticlesW prop, int32_t *mask, int32_t *type,
+                                                      const double *gamma, DevParticles gcur, int32_t *gvalid,
+                                                      double *lq, const int32_t *active, int draw) {
+  propose_particle<MALA, ZCA>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, sh, a, move, st, prop, mask, type, gamma,
+                              gcur, gvalid, lq, active, draw);
+}
+
+// Metropolis-Hastings decision: accept when ln u < gamma (ll' - ll).  Every thread of a
+// wave takes part (the tallies are wave ballots).
+__device__ __forceinline__ void accept_particle(int64_t i, const SmcShape &sh, const rjsmc_mutate_args &a, int move,
+                                                const DevParticlesW &st, double *ll, const DevParticles &prop,
+                                                const double *ll_prop, const int32_t *mask, const int32_t *type,
+                                                const double *gamma, const DevParticlesW &gcur,
+                                                const DevParticles &gprop, int32_t *gvalid, int64_t *stats,
+                                                const double *lq) {
   const bool in = i < st.n;
   const int t = in ? type[i] : -1;
   bool acc = false;
@@ -2054,6 +2063,32 @@ __global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_a
   }
 }
 
+__global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_args a, int move, DevParticlesW st,
+                                                     double *ll, DevParticles prop, const double *ll_prop,
+                                                     const int32_t *mask, const int32_t *type, const double *gamma,
+                                                     DevParticlesW gcur, DevParticles gprop, int32_t *gvalid,
+                                                     int64_t *stats, const double *lq) {
+  accept_particle((int64_t)blockIdx.x * blockDim.x + threadIdx.x, sh, a, move, st, ll, prop, ll_prop, mask, type, gamma,
+                  gcur, gprop, gvalid, stats, lq);
+}
+
+// The decision of sweep move_prev, then the proposal of sweep move, for every particle:
+// both read and write only the particle's own state, proposal, move type, mask and
+// correction (each read before it is rewritten), so one launch serves the two.  Sweeps
+// without gradient-informed moves only.
+template <bool ZCA>
+__global__ __launch_bounds__(256) void accept_propose_kernel(SmcShape sh, rjsmc_mutate_args a, int move_prev, int move,
+                                                             DevParticlesW st_w, DevParticles st_r, double *ll,
+                                                             DevParticles prop_r, DevParticlesW prop_w,
+                                                             const double *ll_prop, int32_t *mask, int32_t *type,
+                                                             const double *gamma, int64_t *stats, double *lq,
+                                                             const int32_t *active) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  accept_particle(i, sh, a, move_prev, st_w, ll, prop_r, ll_prop, mask, type, gamma, DevParticlesW(), DevParticles(),
+                  nullptr, stats, lq);
+  propose_particle<false, ZCA>(i, sh, a, move, st_r, prop_w, mask, type, gamma, DevParticles(), nullptr, lq, active, 1);
+}
+
 hipError_t launch_draw_types(const rjsmc_mutate_args &a, int move, const DevParticles &state, int kc, int km,
                              int32_t *mask, int32_t *type, const int32_t *active, const int32_t *gvalid,
                              hipStream_t stream) {
@@ -2098,6 +2133,26 @@ hipError_t launch_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int mo
     go(propose_kernel<false, true>);
   else
     go(propose_kernel<false, false>);
+  return hipGetLastError();
+}
+
+hipError_t launch_accept_propose(const SmcShape &sh, const rjsmc_mutate_args &a, int move_prev, int move,
+                                 const DevParticlesW &state, double *ll, const DevParticlesW &prop,
+                                 const double *ll_prop, int32_t *mask, int32_t *type, const double *gamma,
+                                 int64_t *stats, double *lq, const int32_t *active, hipStream_t stream) {
+  // the proposal's launch shape and LDS (launch_propose)
+  const size_t per_thread = sizeof(double) * (size_t)(2 * sh.kc + 2 * sh.km);
+  const int kThreads = per_thread * 256 <= 64 * 1024 ? 256 : kWave;
+  const int64_t blocks = (state.n + kThreads - 1) / kThreads;
+  const size_t lds = per_thread * kThreads;
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kThreads), lds, stream, sh, a, move_prev, move, state,
+                       readonly(state), ll, readonly(prop), prop, ll_prop, mask, type, gamma, stats, lq, active);
+  };
+  if (a.zca_birth)
+    go(accept_propose_kernel<true>);
+  else
+    go(accept_propose_kernel<false>);
   return hipGetLastError();
 }
 

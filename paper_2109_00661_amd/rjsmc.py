@@ -59,6 +59,8 @@ class RJSMCRun:
         self.lls = [torch.empty(self.n, dtype=torch.float64, device=device) for _ in range(2)]
         self.cur = 0
         self.gamma = torch.zeros(n_sound, dtype=torch.float64, device=device)
+        # host copy of gamma for the end-of-loop test (pinned, one copy per step)
+        self._gamma_host = torch.empty(n_sound, dtype=torch.float64, pin_memory=torch.cuda.is_available())
         self.log_z = torch.zeros((n_sound, self.M), dtype=torch.float64, device=device)
         self.active = torch.ones(n_sound, dtype=torch.int32, device=device)
         self.anc = torch.empty(self.n, dtype=torch.int32, device=device)
@@ -210,11 +212,16 @@ class RJSMCRun:
         if self.adapt_c is not None:
             self._adapt_sweeps()
 
+    def finished(self):
+        """Whether every sounding has reached gamma = 1 (one device-to-host copy)."""
+        self._gamma_host.copy_(self.gamma)
+        return bool((self._gamma_host.numpy() >= 1.0).all())
+
     def run(self, max_steps=1000):
         self.initialise()
         while self.step < max_steps:
             self.advance()
-            if bool((self.gamma >= 1.0).all()):
+            if self.finished():
                 break
         self.ctx.check()
         return self
@@ -248,7 +255,7 @@ class RJSMCRun:
             self._archive_current()
         while self.step < max_steps:
             self.advance()
-            if bool((self.gamma >= 1.0).all()):
+            if self.finished():
                 break
         self.ctx.check()
         return self
