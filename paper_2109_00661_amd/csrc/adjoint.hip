@@ -57,10 +57,11 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
                                              double wt, cplx<double> (&G)[LMAX], double (&H)[LMAX],
                                              const cplx<double> *phase, const double *e2, double &imr) {
   const double lam2 = lam * lam;
-  // Up to 8 layers the layer loops are unrolled over LMAX with a wave-uniform guard, so
-  // the stored states, G and H stay in registers; with 16 the loops stay runtime loops
-  // over arrays in private memory (the registers would halve the occupancy).
-  constexpr bool kUnrolled = LMAX <= 8;
+  // Up to 12 layers the layer loops are unrolled over LMAX with a wave-uniform guard, so
+  // the stored states, G and H stay in registers (at 12, 256 VGPRs and 60 AGPRs: one wave
+  // per SIMD, still faster than the private-memory arrays); with 16 the loops stay
+  // runtime loops over arrays in private memory (the registers would not fit).
+  constexpr bool kUnrolled = LMAX <= 12;
   constexpr int NI = LMAX - 1;           // interfaces below the surface
   cplx<double> Ns[NI], Ds[NI];           // projective reflection state below interface l
   auto u_of = [&](int l) { return csqrt_fast(cplx<double>{lam2 + k2[l].re, k2[l].im}); };
@@ -402,22 +403,28 @@ static hipError_t launch_g1(const DevSystem &s, const DevParticles &p, int kc, i
 // Particles are evaluated by the instantiation whose layer capacity covers them: with
 // a workspace for an evaluation order (ws) and more than 8 layers of capacity, the
 // particles are ordered by descending capacity kappa + lambda + 1 on the device (the
-// counting sort of the forward's tile shapes), those above 8 layers go to the 16-layer
-// instantiation (per-lane state in private memory) and the others to the 8-layer one
-// (state in registers); otherwise one launch covers all of them.
+// counting sort of the forward's tile shapes); those above 12 layers go to the 16-layer
+// instantiation (per-lane state in private memory), those of 9 to 12 to the 12-layer one
+// and the others to the 8-layer one (state in registers); otherwise one launch of the
+// smallest instantiation that covers the context's capacity.
 hipError_t launch_loglik_grad(const DevSystem &s, const DevParticles &p, int kc, int km, const double *y_obs,
                               double *ll, const DevGrad &g, hipStream_t stream, const MutateWorkspace *ws) {
   const int lcap = p.layout == RJSMC_LAYOUT_DECOUPLED ? kc + km + 1 : kc + 1;
   if (lcap <= 4) return launch_g1<4>(s, p, kc, km, y_obs, ll, g, stream, nullptr, nullptr, nullptr);
   if (lcap <= 8) return launch_g1<8>(s, p, kc, km, y_obs, ll, g, stream, nullptr, nullptr, nullptr);
-  if (!ws || !ws->perm || p.n > ws->n || p.n < kBucketMin)
+  if (!ws || !ws->perm || p.n > ws->n || p.n < kBucketMin) {
+    if (lcap <= 12) return launch_g1<12>(s, p, kc, km, y_obs, ll, g, stream, nullptr, nullptr, nullptr);
     return launch_g1<16>(s, p, kc, km, y_obs, ll, g, stream, nullptr, nullptr, nullptr);
+  }
   hipError_t e = launch_layer_sort(p, ws->cnt, ws->perm, stream);
   // after the sort, cnt[kMaxLayers + b] is the end of bin b (bin b: capacity kMaxLayers - b)
-  const int *end_deep = ws->cnt + kMaxLayers + (kMaxLayers - 9);   // capacities 16 .. 9
-  const int *end_all = ws->cnt + kMaxLayers + (kMaxLayers - 1);    // every particle
-  if (e == hipSuccess) e = launch_g1<16>(s, p, kc, km, y_obs, ll, g, stream, ws->perm, nullptr, end_deep);
-  if (e == hipSuccess) e = launch_g1<8>(s, p, kc, km, y_obs, ll, g, stream, ws->perm, end_deep, end_all);
+  const int *end_13 = ws->cnt + kMaxLayers + (kMaxLayers - 13);   // capacities 16 .. 13
+  const int *end_9 = ws->cnt + kMaxLayers + (kMaxLayers - 9);     // capacities 12 .. 9
+  const int *end_all = ws->cnt + kMaxLayers + (kMaxLayers - 1);   // every particle
+  if (e == hipSuccess && lcap > 12)
+    e = launch_g1<16>(s, p, kc, km, y_obs, ll, g, stream, ws->perm, nullptr, end_13);
+  if (e == hipSuccess) e = launch_g1<12>(s, p, kc, km, y_obs, ll, g, stream, ws->perm, lcap > 12 ? end_13 : nullptr, end_9);
+  if (e == hipSuccess) e = launch_g1<8>(s, p, kc, km, y_obs, ll, g, stream, ws->perm, end_9, end_all);
   return e;
 }
 

@@ -74,9 +74,9 @@ def test_grad_decoupled_up_to_fifteen_layers(B, K_oracle, truth_data):
     _check_against_oracle(p, ll, g, ll_o, g_o)
 
 
-@pytest.mark.parametrize("kmax", [(2, 1), (4, 3)])
+@pytest.mark.parametrize("kmax", [(2, 1), (4, 3), (6, 5)])
 def test_grad_decoupled_register_path(B, K_oracle, truth_data, kmax):
-    """Capacities of 4 and 8 merged layers (the kernels that keep the per-layer state
+    """Capacities of 4, 8 and 12 merged layers (the kernels that keep the per-layer state
     in registers), every layer count from the half-space up."""
     from oracle import em
     kc, km = kmax
@@ -158,9 +158,9 @@ def test_grad_full_size_sampled(B, K_oracle, truth_data):
 
 def test_grad_bucketed_equals_single_launch(B, truth_data):
     """A context with a workspace evaluates particles of up to 8 merged layers with the
-    register instantiation and deeper ones with the 16-layer one; without a workspace one
-    16-layer launch covers all.  Same values to rounding (the two instantiations run the
-    same arithmetic in differently unrolled code), deeper particles bit-identical."""
+    8-layer instantiation, of 9 to 12 with the 12-layer one and deeper ones with the
+    16-layer one; without a workspace one 16-layer launch covers all.  Same values to
+    rounding (the instantiations run the same arithmetic in differently unrolled code)."""
     system = W.system(kmax_cond=7, kmax_charg=7)
     p = W.prior_population(9000, 7, 7, seed=31)
     res = []
@@ -170,9 +170,9 @@ def test_grad_bucketed_equals_single_launch(B, truth_data):
         res.append((ll, g))
     (ll0, g0), (ll1, g1) = res
     np.testing.assert_allclose(ll1, ll0, rtol=LL_CONSISTENCY, atol=0)
-    deep = p["kappa"] + p["lambda_"] + 1 > 8
-    assert deep.any() and (~deep).any()
-    assert np.array_equal(ll1[deep], ll0[deep])
+    cap = p["kappa"] + p["lambda_"] + 1
+    assert (cap > 12).any() and ((cap > 8) & (cap <= 12)).any() and (cap <= 8).any()
+    assert np.array_equal(ll1[cap > 12], ll0[cap > 12])
     scale = np.max([np.abs(g0[k]).max(axis=0) if g0[k].ndim == 2 else np.abs(g0[k]) for k in FKEYS], axis=0)
     for k in FKEYS:
         assert np.all(np.abs(g1[k] - g0[k]) <= 1e-12 * scale), k
