@@ -467,8 +467,8 @@ def reweight_rate(torch, d, steps, warmup, n_sound=2000, n_per_sound=2048):
 def adjoint_rate(torch, d, steps, warmup):
     """Log-likelihood + gradient evaluations per second for 65,536 decoupled particles
     with 1-8 segments per partition (merged layers up to 15).  The context holds a
-    workspace for the batch, so particles of up to 8 merged layers take the register
-    instantiation and the deeper ones the 16-layer one."""
+    workspace for the batch, so particles are split by their merged-layer count among the
+    8-, 12- and 16-layer instantiations."""
     from paper_2109_00661_amd import binding as B
     system = W.system(kmax_cond=7, kmax_charg=7)
     ctx = B.Context(system, precision="f64", max_particles=N_PARTICLES)

@@ -3,9 +3,9 @@
 // One wavefront per particle, lanes tiling (frequency, filter abscissa) as in the
 // forward kernel, and every (frequency, abscissa) pair visited once.  Per pair the lane
 // runs the projective reflection recursion bottom-up, keeping the state (N_l, D_l) of
-// every interface in a per-lane array (in registers up to 8 merged layers; above, runtime
-// layer loops over arrays in the wave's private memory, which keeps the register count
-// low enough for two waves per SIMD); the same recursion gives Im r_TE for the Hankel sum.
+// every interface in a per-lane array held in registers (the layer loops unrolled over
+// the instantiation's capacity: 4, 8, 12 or 16 merged layers, the deeper two with AGPRs
+// and one wave per SIMD); the same recursion gives Im r_TE for the Hankel sum.
 // It then sweeps top-down through the surface and every interface, propagating the
 // adjoint of c_k Im r (the reverse sweep is linear in its seed, so the filter coefficient
 // alone seeds it) and accumulating, per lane and frequency, the complex adjoints of the
@@ -57,11 +57,9 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
                                              double wt, cplx<double> (&G)[LMAX], double (&H)[LMAX],
                                              const cplx<double> *phase, const double *e2, double &imr) {
   const double lam2 = lam * lam;
-  // Up to 12 layers the layer loops are unrolled over LMAX with a wave-uniform guard, so
-  // the stored states, G and H stay in registers (at 12, 256 VGPRs and 60 AGPRs: one wave
-  // per SIMD, still faster than the private-memory arrays); with 16 the loops stay
-  // runtime loops over arrays in private memory (the registers would not fit).
-  constexpr bool kUnrolled = LMAX <= 12;
+  // The layer loops are unrolled over LMAX with a wave-uniform guard, so the stored
+  // states, G and H stay in registers (at 12 and 16 layers with AGPRs as well, one wave
+  // per SIMD: still faster than keeping them in private memory with two).
   constexpr int NI = LMAX - 1;           // interfaces below the surface
   cplx<double> Ns[NI], Ds[NI];           // projective reflection state below interface l
   auto u_of = [&](int l) { return csqrt_fast(cplx<double>{lam2 + k2[l].re, k2[l].im}); };
@@ -87,8 +85,8 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
   cplx<double> ua = u_of(L - 2);
   cplx<double> N = k2[L - 2] - k2[L - 1], D = csq(ua + u_of(L - 1));
 #pragma unroll
-  for (int l = kUnrolled ? NI - 1 : L - 2; l >= 0; --l) {
-    if (!kUnrolled || l <= L - 2) {
+  for (int l = NI - 1; l >= 0; --l) {
+    if (l <= L - 2) {
       if (l < L - 2) {
         const cplx<double> u = u_of(l);
         const double hh = h2v[l + 1];
@@ -127,8 +125,8 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
   }
   ua = u0;
 #pragma unroll
-  for (int l = 0; l < (kUnrolled ? NI - 1 : L - 2); ++l) {
-    if (!kUnrolled || l < L - 2) {
+  for (int l = 0; l < NI - 1; ++l) {
+    if (l < L - 2) {
       // the step that made state l from state l + 1: a = u_l, b = u_{l+1}, E_{l+1}
       const cplx<double> ub = u_of(l + 1);
       const double hh = h2v[l + 1];
@@ -152,17 +150,12 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
   const cplx<double> ul = u_of(L - 1);
   const cplx<double> sb = Db * (2.0 * (ua + ul));
   const cplx<double> g0 = Nb + (uab + sb) * half_rcp(ua), g1 = sb * half_rcp(ul) - Nb;
-  if (kUnrolled) {
 #pragma unroll
-    for (int l = 0; l < NI; ++l)     // compile-time indices keep G in registers
-      if (l == L - 2) {
-        G[l] = G[l] + g0;
-        G[l + 1] = G[l + 1] + g1;
-      }
-  } else {
-    G[L - 2] = G[L - 2] + g0;
-    G[L - 1] = G[L - 1] + g1;
-  }
+  for (int l = 0; l < NI; ++l)       // compile-time indices keep G in registers
+    if (l == L - 2) {
+      G[l] = G[l] + g0;
+      G[l + 1] = G[l + 1] + g1;
+    }
 }
 
 // Single pass.  The reverse sweep of a (lam, w) pair is linear in its seed, and the
@@ -404,9 +397,9 @@ static hipError_t launch_g1(const DevSystem &s, const DevParticles &p, int kc, i
 // a workspace for an evaluation order (ws) and more than 8 layers of capacity, the
 // particles are ordered by descending capacity kappa + lambda + 1 on the device (the
 // counting sort of the forward's tile shapes); those above 12 layers go to the 16-layer
-// instantiation (per-lane state in private memory), those of 9 to 12 to the 12-layer one
-// and the others to the 8-layer one (state in registers); otherwise one launch of the
-// smallest instantiation that covers the context's capacity.
+// instantiation, those of 9 to 12 to the 12-layer one and the others to the 8-layer one
+// (each unrolled over its own capacity); otherwise one launch of the smallest
+// instantiation that covers the context's capacity.
 hipError_t launch_loglik_grad(const DevSystem &s, const DevParticles &p, int kc, int km, const double *y_obs,
                               double *ll, const DevGrad &g, hipStream_t stream, const MutateWorkspace *ws) {
   const int lcap = p.layout == RJSMC_LAYOUT_DECOUPLED ? kc + km + 1 : kc + 1;

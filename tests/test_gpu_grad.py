@@ -76,8 +76,8 @@ def test_grad_decoupled_up_to_fifteen_layers(B, K_oracle, truth_data):
 
 @pytest.mark.parametrize("kmax", [(2, 1), (4, 3), (6, 5)])
 def test_grad_decoupled_register_path(B, K_oracle, truth_data, kmax):
-    """Capacities of 4, 8 and 12 merged layers (the kernels that keep the per-layer state
-    in registers), every layer count from the half-space up."""
+    """Capacities of 4, 8 and 12 merged layers (one launch of the smallest instantiation
+    that covers the context), every layer count from the half-space up."""
     from oracle import em
     kc, km = kmax
     system = W.system(kmax_cond=kc, kmax_charg=km)
@@ -93,8 +93,9 @@ def test_grad_decoupled_register_path(B, K_oracle, truth_data, kmax):
 
 
 def test_grad_same_particles_under_both_capacities(B, truth_data):
-    """The register path (capacity 8) and the private-memory path (capacity 16) give the
-    same log-likelihood and gradient for the same particles (to rounding)."""
+    """The 8-layer instantiation and the 16-layer one (a capacity-15 context without a
+    workspace) give the same log-likelihood and gradient for the same particles (to
+    rounding)."""
     kc, km = 4, 3
     p = W.decoupled_population(200, kc, km, seed=29, min_sep=1.0)
     wide = W.empty_particles(200, 7, 7)
@@ -119,7 +120,7 @@ def test_grad_same_particles_under_both_capacities(B, truth_data):
 def test_grad_full_size_sampled(B, K_oracle, truth_data):
     """65,536 decoupled particles with 1-8 segments per partition (the adjoint
     workload, in the benchmark's launch: a context with a workspace, so the particles are
-    split by their own layer count between the 8- and 16-layer instantiations); 48
+    split by their own layer count among the 8-, 12- and 16-layer instantiations); 48
     sampled particles against the oracle, all finite."""
     from oracle import em
     system = W.system(kmax_cond=7, kmax_charg=7)
