@@ -447,20 +447,29 @@ rjsmc_status rjsmc_counter_add(rjsmc_ctx *ctx, int32_t *counter, int32_t delta, 
  * identical for every shape).
  * ---------------------------------------------------------------------------------- */
 typedef struct {
-  int32_t waves_per_block;    /* particles per workgroup */
+  int32_t waves_per_block;    /* particles per workgroup (spread shape: waves per workgroup) */
   int32_t layer_sort;         /* 1: evaluate particles in descending order of layer capacity
                                  (kappa + lambda + 1), computed on the device before each
                                  launch; used only when n <= max_particles of the context */
   int32_t waves_per_particle; /* wavefronts sharing one particle's frequency groups (more
-                                 than one shortens the latency of small batches) */
+                                 than one shortens the latency of small batches); 0: spread */
 } rjsmc_tuning;
 
 /* The tile shapes, as (waves_per_block, waves_per_particle):
- *   (2,1) (4,1) (8,1) (2,2) (1,4) (1,8) (1,16),
+ *   (2,1) (4,1) (8,1) (2,2) (1,4) (1,8) (1,16) (16,0),
  * each with layer_sort 0 and 1: candidate k = 2 * shape index + layer_sort.  With more
  * waves per particle than groups of 8 frequencies, each group's filter abscissae are
- * split among the waves as well (the sums keep the same order). */
-#define RJSMC_TUNING_CANDIDATES 14
+ * split among the waves as well (the sums keep the same order).
+ * (16,0) is the spread evaluation, for small populations whose particles differ in depth:
+ * each particle's reflection terms are cut into units of 64 (8 frequencies x 8 filter
+ * abscissae) weighted by its layer capacity, the units are dealt in runs of equal weight
+ * to the waves of one 16-wave workgroup per compute unit, and a second launch adds the
+ * stored terms in the order of the other shapes.  FP64 contexts only (rjsmc_set_tuning
+ * rejects it in an FP32 context, the autotuner skips it).  It needs a context workspace
+ * (max_particles > 0; 8 ceil(n_freq/8) n_hankel_pad doubles per particle are allocated for
+ * min(max_particles, 2048) particles); a launch over more particles than that, or from
+ * rjsmc_mutate_noalloc, takes the shape (4,1) instead. */
+#define RJSMC_TUNING_CANDIDATES 16
 
 /* Sets / reads the tile shape used by rjsmc_forward, rjsmc_loglik and the proposal
  * likelihoods of rjsmc_mutate (default {4, 0, 1}).  RJSMC_E_INVALID for a shape not in

@@ -102,8 +102,9 @@ class Tuning(ctypes.Structure):
                 ("waves_per_particle", ctypes.c_int32)]
 
 
-TUNING_CANDIDATES = 14
-TILE_SHAPES = ((2, 1), (4, 1), (8, 1), (2, 2), (1, 4), (1, 8), (1, 16))   # (waves_per_block, waves_per_particle)
+TUNING_CANDIDATES = 16
+# (waves_per_block, waves_per_particle); (16, 0) is the spread evaluation
+TILE_SHAPES = ((2, 1), (4, 1), (8, 1), (2, 2), (1, 4), (1, 8), (1, 16), (16, 0))
 
 
 def make_prior(pr):

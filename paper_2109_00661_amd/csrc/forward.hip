@@ -28,6 +28,100 @@ __device__ __forceinline__ T to(double x) {
   return static_cast<T>(x);
 }
 
+// Per-particle Cole-Cole constants: (i w tau)^c = (w tau)^c (cos(pi c/2) + i sin(pi c/2)).
+struct ColeCole {
+  double c, log_tau, spc, cpc;
+};
+__device__ __forceinline__ ColeCole cole_cole(const DevParticles &p, int64_t i) {
+  ColeCole cc;
+  cc.c = p.c[i];
+  cc.log_tau = p.log10_tau[i] * 2.302585092994045684;
+  sincospi(0.5 * cc.c, &cc.spc, &cc.cpc);
+  return cc;
+}
+
+// h2[l] = -2 h_l for the L - 1 finite layers (lane l).
+template <typename T>
+__device__ __forceinline__ void stage_h2(const LayerStack *st, int L, T *h2, int lane) {
+  if (lane < L - 1) h2[lane] = T(-2) * to<T>(st->top[lane + 1] - st->top[lane]);
+}
+
+// Layer wavenumbers of one particle at angular frequency w (logw = log w, from the
+// workgroup's table): k2[l] = i w mu0 sigma_inf_l (1 - m_l q_cc) with q_cc = 1 / (1 +
+// (i w tau)^c), and the interface numerators dk2[l] = k2[l] - k2[l+1].  k2_freq holds the
+// per-frequency factors, k2_layer forms one layer's value from them; every kernel builds
+// its tables from these two, so the values are the same bits whoever forms them.
+template <typename T>
+struct K2Freq {
+  T wmu;
+  cplx<T> qt;
+};
+template <typename T>
+__device__ __forceinline__ K2Freq<T> k2_freq(double w, double logw, const ColeCole &cc) {
+  const double wtc = exp(cc.c * (logw + cc.log_tau));
+  const cplx<double> qcc = crcp(cplx<double>{1.0 + wtc * cc.cpc, wtc * cc.spc});
+  return K2Freq<T>{to<T>(w * kMu0), cplx<T>{to<T>(qcc.re), to<T>(qcc.im)}};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> k2_layer(const LayerStack *st, int l, const K2Freq<T> &kf) {
+  const T sg = to<T>(st->sig[l]), mg = to<T>(st->m[l]);
+  const cplx<T> sh = {sg * (T(1) - mg * kf.qt.re), sg * (-(mg * kf.qt.im))};
+  return cplx<T>{-(kf.wmu * sh.im), kf.wmu * sh.re};
+}
+
+// The table of one frequency, by the 8 lanes gl of a frequency group (layers gl, gl + 8).
+template <typename T>
+__device__ __forceinline__ void stage_k2(const LayerStack *st, int L, double w, double logw, const ColeCole &cc,
+                                         int gl, cplx<T> *k2, cplx<T> *dk2) {
+  const K2Freq<T> kf = k2_freq<T>(w, logw, cc);
+  for (int l = gl; l < L; l += 8) {
+    const cplx<T> kl = k2_layer<T>(st, l, kf);
+    k2[l] = kl;
+    if (l + 1 < L) dk2[l] = kl - k2_layer<T>(st, l + 1, kf);
+  }
+}
+
+// Gate responses of particle i from its Im H values (imh[0..n_freq), LDS) and its
+// log-likelihood, by one whole wave: lane g < n_gate forms gate g, the wave adds the
+// likelihood terms.
+__device__ __forceinline__ void gates_loglik(const DevSystem &s, const DevParticles &p, int64_t i, const double *K,
+                                             const double *imh, const double *eps2, double *resp,
+                                             const double *y_obs, double *ll, int lane) {
+  const int nf = s.n_freq, ng = s.n_gate;
+  double term = 0.0;
+  if (lane < ng) {
+    double y = 0.0;
+    for (int j = 0; j < nf; ++j) y += K[lane * nf + j] * imh[j];
+    if (resp) resp[i * ng + lane] = y;
+    if (ll) {
+      const int64_t snd = p.n_per_sounding > 0 ? i / p.n_per_sounding : 0;
+      const double d = y_obs[snd * ng + lane];
+      const double e = s.eps_mn * y;
+      const double s2 = eps2[lane] + e * e;
+      const double r = d - y;
+      term = r * r / s2 + log(kTwoPi * s2);
+    }
+  }
+  if (ll) {
+    term += __shfl_xor(term, 1);
+    term += __shfl_xor(term, 2);
+    term += __shfl_xor(term, 4);
+    term += __shfl_xor(term, 8);
+    term += __shfl_xor(term, 16);
+    term += __shfl_xor(term, 32);
+    if (lane == 0) {
+      const double v = -0.5 * term;
+      ll[i] = (v == v && v != HUGE_VAL) ? v : -HUGE_VAL;   // NaN or +inf -> -inf
+    }
+  }
+}
+
+// An invalid particle: NaN responses, -inf log-likelihood.
+__device__ __forceinline__ void invalid_outputs(const DevSystem &s, int64_t i, double *resp, double *ll, int lane) {
+  if (resp && lane < s.n_gate) resp[i * s.n_gate + lane] = __builtin_nan("");
+  if (ll && lane == 0) ll[i] = -HUGE_VAL;
+}
+
 // resp != nullptr: write gate responses.  ll != nullptr: write the log-likelihood.
 // WPB particles per workgroup, P waves per particle: wave q0 of a particle takes the
 // frequency groups q0, q0 + P, ... (P = 1: the whole particle; P > 1 shortens the
@@ -44,6 +138,7 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
   __shared__ double s_lam[kMaxHankel];
   __shared__ double s_ck[kMaxHankel];
   __shared__ double s_omega[kMaxFreq];
+  __shared__ double s_logw[kMaxFreq];
   __shared__ double s_eps2[kMaxGate];
   __shared__ cplx<double> s_phase[kPhaseN];
   __shared__ double s_exp2[kExp2N];
@@ -69,7 +164,10 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
     s_lam[t] = s.lam[t];
     s_ck[t] = s.ck[t];
   }
-  for (int t = threadIdx.x; t < nf; t += blockDim.x) s_omega[t] = s.omega[t];
+  for (int t = threadIdx.x; t < nf; t += blockDim.x) {
+    s_omega[t] = s.omega[t];
+    s_logw[t] = log(s.omega[t]);
+  }
   for (int t = threadIdx.x; t < nf * ng; t += blockDim.x) s_K[t] = s.K[t];
   for (int t = threadIdx.x; t < ng; t += blockDim.x) s_eps2[t] = s.eps_an2[t];
   for (int t = threadIdx.x; t < kPhaseN; t += blockDim.x)
@@ -79,13 +177,10 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
   __syncthreads();
   const int L = merge_particle(p, i, valid && !skip, kc, km, LMAX, st, s.flags);
 
-  // per-particle Cole-Cole constants: (i w tau)^c = (w tau)^c (cos(pi c/2) + i sin(pi c/2))
-  double c = 0.0, log_tau = 0.0, spc = 0.0, cpc = 1.0;
+  ColeCole cc{0.0, 0.0, 0.0, 1.0};
   if (L > 0) {
-    c = p.c[i];
-    log_tau = p.log10_tau[i] * 2.302585092994045684;
-    sincospi(0.5 * c, &spc, &cpc);
-    if (lane < L - 1) s_h2[wave][lane] = T(-2) * to<T>(st->top[lane + 1] - st->top[lane]);
+    cc = cole_cole(p, i);
+    stage_h2<T>(st, L, s_h2[wave], lane);
   }
   const int gl = lane & 7, gw = lane >> 3;
   const int nhg = nhp >> 3;
@@ -102,24 +197,7 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
     const int q = A == 1 ? u : u / A, part = u - q * A;
     const int jf = gw + 8 * q;
     const bool act = L > 0 && jf < nf;
-    if (act) {
-      const double w = s_omega[jf];
-      // q_cc = 1 / (1 + (i w tau)^c); k2 = i w mu0 sigma_inf (1 - m q_cc)
-      const double pw = exp(c * (log(w) + log_tau));
-      const cplx<double> qcc = crcp(cplx<double>{1.0 + pw * cpc, pw * spc});
-      const T wmu = to<T>(w * kMu0);
-      const cplx<T> qt = {to<T>(qcc.re), to<T>(qcc.im)};
-      auto k2_of = [&](int l) {
-        const T sg = to<T>(st->sig[l]), mg = to<T>(st->m[l]);
-        const cplx<T> sh = {sg * (T(1) - mg * qt.re), sg * (-(mg * qt.im))};
-        return cplx<T>{-(wmu * sh.im), wmu * sh.re};
-      };
-      for (int l = gl; l < L; l += 8) {
-        const cplx<T> kl = k2_of(l);
-        s_k2[wave][gw][l] = kl;
-        if (l + 1 < L) s_dk2[wave][gw][l] = kl - k2_of(l + 1);
-      }
-    }
+    if (act) stage_k2<T>(st, L, s_omega[jf], s_logw[jf], cc, gl, s_k2[wave][gw], s_dk2[wave][gw]);
     wave_lds_sync();
     if (act && A == 1) {
       double acc = 0.0;
@@ -168,38 +246,345 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
     }
     wave_lds_sync();
   }
-  if (L > 0) {
-    double term = 0.0;
-    if (lane < ng) {
-      double y = 0.0;
-      for (int j = 0; j < nf; ++j) y += s_K[lane * nf + j] * s_imh[pw][j];
-      if (resp) resp[i * ng + lane] = y;
-      if (ll) {
-        const int64_t snd = p.n_per_sounding > 0 ? i / p.n_per_sounding : 0;
-        const double d = y_obs[snd * ng + lane];
-        const double e = s.eps_mn * y;
-        const double s2 = s_eps2[lane] + e * e;
-        const double r = d - y;
-        term = r * r / s2 + log(kTwoPi * s2);
-      }
-    }
-    if (ll) {
-      term += __shfl_xor(term, 1);
-      term += __shfl_xor(term, 2);
-      term += __shfl_xor(term, 4);
-      term += __shfl_xor(term, 8);
-      term += __shfl_xor(term, 16);
-      term += __shfl_xor(term, 32);
-      if (lane == 0) {
-        const double v = -0.5 * term;
-        ll[i] = (v == v && v != HUGE_VAL) ? v : -HUGE_VAL;   // NaN or +inf -> -inf
-      }
-    }
-  } else if (valid && !skip) {
-    // invalid particle: NaN responses, -inf log-likelihood
-    if (resp && lane < ng) resp[i * ng + lane] = __builtin_nan("");
-    if (ll && lane == 0) ll[i] = -HUGE_VAL;
+  if (L > 0)
+    gates_loglik(s, p, i, s_K, s_imh[pw], s_eps2, resp, y_obs, ll, lane);
+  else if (valid && !skip)
+    invalid_outputs(s, i, resp, ll, lane);
+}
+
+// ---- spread evaluation (FP64): a launch's work dealt evenly over the compute units
+// With one particle per workgroup a small population ends when its deepest particle does,
+// on one compute unit.  Here a particle's reflection terms are cut into units (frequency
+// chunk q, abscissa step s: the 64 terms of frequencies gw + 8q at abscissae gl + 8s, one
+// per lane); unit j = q n_hg + s of the particle in slot r weighs its layer capacity + 1,
+// and the units, slot-major, are cut into ranges of equal weight, one per workgroup of a
+// grid with one workgroup per compute unit.  A deep particle's units so spread over more
+// compute units than a shallow one's.  A workgroup merges the few particles of its range
+// (kSpreadStage at a time) and builds their wavenumber tables in LDS together; then its
+// waves claim the range's units one at a time from an LDS counter, so that every SIMD
+// stays busy until the range is done.  spread_terms_kernel writes the terms to rim in
+// [slot][q][s][lane] order; spread_finish_kernel adds them in the order of forward_kernel
+// and applies the gates and the likelihood, so the results are the same bits.
+constexpr int kSpreadWaves = 16;                         // waves per workgroup
+constexpr int kSpreadMaxN = 2 * kWave * kSpreadWaves;   // particles per launch (two per thread)
+constexpr int kSpreadStage = 4;                          // particles staged at once
+
+// Weight of the particle in a slot: 0 if masked out, else its layer capacity (clamped to
+// 1..kMaxLayers, so that invalid counts stay bounded) + 1.  Its counts are kept for the
+// merge.
+__device__ __forceinline__ int spread_weight(const DevParticles &p, int64_t i, int *kap, int *lam) {
+  *kap = p.kappa[i];
+  *lam = p.layout == RJSMC_LAYOUT_DECOUPLED ? p.lambda[i] : 0;
+  if (p.mask && p.mask[i] != p.mask_value) return 0;
+  int cap = *kap + *lam + 1;
+  cap = cap < 1 ? 1 : (cap > kMaxLayers ? kMaxLayers : cap);
+  return cap + 1;
+}
+
+// v[k] for a small index k known only at run time (held in scalar registers, no
+// indexed access).
+__device__ __forceinline__ int pick4(int k, int v0, int v1, int v2, int v3) {
+  return k == 0 ? v0 : (k == 1 ? v1 : (k == 2 ? v2 : v3));
+}
+
+// Dynamic LDS of spread_terms_kernel: the staged particles' k2 and dk2 tables.
+template <typename T>
+static size_t spread_table_bytes(const DevSystem &s) {
+  return 2 * sizeof(cplx<T>) * kSpreadStage * s.n_freq * kMaxLayers;
+}
+
+// rim_layers[r] = L of the particle in slot r (0: invalid), written by the workgroup that
+// holds the slot's first unit (masked slots are not written).
+template <typename T>
+__global__ __launch_bounds__(kWave * kSpreadWaves, 1) void spread_terms_kernel(
+    DevSystem s, DevParticles p, int kc, int km, const int32_t *perm, double *rim, int32_t *rim_layers) {
+  constexpr int LMAX = kMaxLayers;
+  constexpr int KP = kSpreadStage;
+  static_assert(KP == 4, "pick4 holds the staged set");
+  __shared__ double s_lam[kMaxHankel];
+  __shared__ double s_omega[kMaxFreq];
+  __shared__ double s_logw[kMaxFreq];
+  __shared__ cplx<double> s_phase[kPhaseN];
+  __shared__ double s_exp2[kExp2N];
+  __shared__ int s_pref[kSpreadMaxN + 1];   // s_pref[r] = weight of slots 0..r-1
+  __shared__ int s_kap[kSpreadMaxN], s_lmb[kSpreadMaxN];   // counts of slot r
+  __shared__ int s_wsum[kSpreadWaves];
+  __shared__ LayerStack s_stack[KP];
+  __shared__ ColeCole s_cc[KP];
+  __shared__ T s_h2[KP][LMAX];
+  __shared__ int s_L[KP];
+  __shared__ int s_next;
+  extern __shared__ double s_tab[];   // k2 [KP][n_freq][LMAX], then dk2 alike
+  const int nf = s.n_freq, nhp = s.n_hankel_pad;
+  cplx<T> *const s_k2 = reinterpret_cast<cplx<T> *>(s_tab);
+  cplx<T> *const s_dk2 = s_k2 + KP * nf * LMAX;
+
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int n = (int)p.n;   // 1..kSpreadMaxN (the host checks)
+  for (int t = threadIdx.x; t < nhp; t += blockDim.x) s_lam[t] = s.lam[t];
+  for (int t = threadIdx.x; t < nf; t += blockDim.x) {
+    s_omega[t] = s.omega[t];
+    s_logw[t] = log(s.omega[t]);
   }
+  for (int t = threadIdx.x; t < kPhaseN; t += blockDim.x)
+    s_phase[t] = cplx<double>{s.phase[2 * t], s.phase[2 * t + 1]};
+  for (int t = threadIdx.x; t < kExp2N; t += blockDim.x) s_exp2[t] = s.exp2t[t];
+  if (threadIdx.x == 0) s_next = 0;
+  // prefix sums of the slot weights: thread t holds slots 2t and 2t + 1
+  const int r0 = 2 * (int)threadIdx.x;
+  int k0 = 0, l0 = 0, k1 = 0, l1 = 0;
+  const int w0 = r0 < n ? spread_weight(p, perm ? (int64_t)perm[r0] : r0, &k0, &l0) : 0;
+  const int w1 = r0 + 1 < n ? spread_weight(p, perm ? (int64_t)perm[r0 + 1] : r0 + 1, &k1, &l1) : 0;
+  int x = w0 + w1;
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == kWave - 1) s_wsum[wave] = x;
+  if (r0 < n) {
+    s_kap[r0] = k0;
+    s_lmb[r0] = l0;
+  }
+  if (r0 + 1 < n) {
+    s_kap[r0 + 1] = k1;
+    s_lmb[r0 + 1] = l1;
+  }
+  __syncthreads();
+  for (int v = 0; v < wave; ++v) x += s_wsum[v];
+  if (r0 < n) s_pref[r0 + 1] = x - w1;
+  if (r0 + 1 < n) s_pref[r0 + 2] = x;
+  if (threadIdx.x == 0) s_pref[0] = 0;
+  __syncthreads();
+
+  // this workgroup's range: the units whose weight offset lies in [lo, hi).  Every wave
+  // derives the same bounds and staged sets; readfirstlane keeps the values it reads from
+  // LDS in scalar registers.
+  auto uni = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+  const int nq = (nf + 7) >> 3, nhg = nhp >> 3, U = nq * nhg;
+  const int64_t total = (int64_t)U * uni(s_pref[n]);
+  const int64_t G = gridDim.x;
+  const int64_t lo = ((int64_t)blockIdx.x * total + G - 1) / G;
+  const int64_t hi = (((int64_t)blockIdx.x + 1) * total + G - 1) / G;
+  if (lo >= hi) return;   // workgroup-uniform: an empty range
+  // The slot holding offset x: the first r with U s_pref[r + 1] > x (its weight is > 0),
+  // by a 64-way search in two rounds (n <= 64 x 32): the first segment of 32 slots whose
+  // last slot qualifies, then the first qualifying slot in it (slots beyond n - 1 test
+  // slot n - 1, which qualifies for x < total).
+  auto slot_of = [&](int64_t x) {
+    const int c1 = min(32 * lane + 31, n - 1);
+    const uint64_t m1 = __ballot((int64_t)U * s_pref[c1 + 1] > x);
+    const int seg = 32 * __builtin_ctzll(m1);
+    const int c2 = min(seg + (lane & 31), n - 1);
+    const uint64_t m2 = __ballot((int64_t)U * s_pref[c2 + 1] > x);
+    return uni(seg + __builtin_ctzll(m2));
+  };
+  // first slot and its first unit in the range; last slot and its units below hi
+  const int r_first = slot_of(lo), r_last = slot_of(hi - 1);
+  int j_first, j_last;
+  {
+    const int pf = uni(s_pref[r_first]), wf = uni(s_pref[r_first + 1]) - pf;
+    j_first = (int)((lo - (int64_t)U * pf + wf - 1) / wf);   // may be U: no unit of it in range
+    const int pl = uni(s_pref[r_last]), wl = uni(s_pref[r_last + 1]) - pl;
+    const int64_t je = (hi - (int64_t)U * pl + wl - 1) / wl;
+    j_last = je < U ? (int)je : U;
+  }
+
+  const int gl = lane & 7, gw = lane >> 3;
+  int rr = r_first;   // the next slot to consider
+  for (;;) {
+    // the staged set: the next (at most KP) slots of [rr, r_last] with units in the range,
+    // found with one ballot over 64 slots (every wave finds the same set)
+    uint64_t m = 0;
+    for (;;) {
+      const int slot = rr + lane;
+      bool has = false;
+      if (slot <= r_last && s_pref[slot + 1] > s_pref[slot]) {
+        const int a = slot == r_first ? j_first : 0, b = slot == r_last ? j_last : U;
+        has = a < b;
+      }
+      m = __ballot(has);
+      if (m != 0 || rr + kWave > r_last) break;
+      rr += kWave;
+    }
+    if (m == 0) break;   // workgroup-uniform: the range is done
+    int sl[KP], ja[KP], cu[KP + 1], np = 0;
+    cu[0] = 0;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      sl[k] = 0;
+      ja[k] = 0;
+      cu[k + 1] = cu[k];
+      if (m != 0) {
+        const int slot = rr + __builtin_ctzll(m);
+        m &= m - 1;
+        const int a = slot == r_first ? j_first : 0, b = slot == r_last ? j_last : U;
+        sl[k] = slot;
+        ja[k] = a;
+        cu[k + 1] = cu[k] + (b - a);
+        np = k + 1;
+      }
+    }
+    rr = sl[np - 1] + 1;
+    // wave w < np merges staged particle w
+    if (wave < np) {
+      const int rw = pick4(wave, sl[0], sl[1], sl[2], sl[3]);
+      const int64_t i = perm ? (int64_t)perm[rw] : rw;
+      LayerStack *st = &s_stack[wave];
+      const int L = merge_counts(p, i, true, uni(s_kap[rw]), uni(s_lmb[rw]), kc, km, LMAX, st, s.flags);
+      if (L > 0) {
+        const ColeCole cc = cole_cole(p, i);
+        if (lane == 0) s_cc[wave] = cc;
+        stage_h2<T>(st, L, s_h2[wave], lane);
+      }
+      if (lane == 0) {
+        s_L[wave] = L;
+        if (pick4(wave, ja[0], ja[1], ja[2], ja[3]) == 0) rim_layers[rw] = L;
+      }
+    }
+    __syncthreads();
+    // wavenumber tables of the frequency chunks the staged units need, one (particle,
+    // frequency) pair per thread
+    for (int t = threadIdx.x; t < np * nf; t += blockDim.x) {
+      const int sp = t / nf, f = t - sp * nf;
+      const int L = s_L[sp];
+      const int a = pick4(sp, ja[0], ja[1], ja[2], ja[3]);
+      const int b = a + pick4(sp, cu[1], cu[2], cu[3], cu[4]) - pick4(sp, cu[0], cu[1], cu[2], cu[3]);
+      const int qa = a / nhg, qb = (b - 1) / nhg;
+      if (L > 0 && f >= 8 * qa && f < 8 * qb + 8) {
+        const LayerStack *st = &s_stack[sp];
+        const K2Freq<T> kf = k2_freq<T>(s_omega[f], s_logw[f], s_cc[sp]);
+        cplx<T> *k2 = s_k2 + (sp * nf + f) * LMAX, *dk2 = s_dk2 + (sp * nf + f) * LMAX;
+        cplx<T> kl = k2_layer<T>(st, 0, kf);
+        for (int l = 0; l < L; ++l) {
+          k2[l] = kl;
+          if (l + 1 < L) {
+            const cplx<T> kn = k2_layer<T>(st, l + 1, kf);
+            dk2[l] = kl - kn;
+            kl = kn;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // the staged units, claimed one at a time by whichever wave is free
+    const int nu = cu[np];
+    for (;;) {
+      int u = 0;
+      if (lane == 0) u = atomicAdd(&s_next, 1);
+      u = __builtin_amdgcn_readfirstlane(u);
+      if (u >= nu) break;
+      const int sp = (u >= cu[1]) + (u >= cu[2]) + (u >= cu[3]);
+      const int L = uni(s_L[sp]);
+      if (L == 0) continue;   // invalid particle: no terms
+      const int jj = pick4(sp, ja[0], ja[1], ja[2], ja[3]) + u - pick4(sp, cu[0], cu[1], cu[2], cu[3]);
+      const int q = jj / nhg, sidx = jj - q * nhg;
+      const int jf = gw + 8 * q;
+      double v = 0.0;
+      if (jf < nf)
+        v = static_cast<double>(reflection_im<T>(to<T>(s_lam[gl + 8 * sidx]), s_k2 + (sp * nf + jf) * LMAX,
+                                                 s_dk2 + (sp * nf + jf) * LMAX, s_h2[sp], L, s_phase, s_exp2));
+      rim[(((int64_t)pick4(sp, sl[0], sl[1], sl[2], sl[3]) * nq + q) * nhg + sidx) * kWave + lane] = v;
+    }
+    __syncthreads();   // every claimed unit is done before the set is restaged
+    if (threadIdx.x == 0) s_next = 0;
+  }
+}
+
+// The evaluation is compiled for FP64 only: in FP32 the compiler contracts a few products
+// of the recursion into FMAs differently here than in forward_kernel, so the terms would
+// differ from the other shapes' in their last bits.
+
+// One workgroup of n_q waves per slot: wave q adds chunk q's terms over the abscissae in
+// the order of forward_kernel, then the first wave applies the gates and the likelihood.
+__global__ __launch_bounds__(kWave * kMaxFreq / 8) void spread_finish_kernel(
+    DevSystem s, DevParticles p, const int32_t *perm, const double *rim, const int32_t *rim_layers, double *resp,
+    const double *y_obs, double *ll) {
+  __shared__ double s_ck[kMaxHankel];
+  __shared__ double s_eps2[kMaxGate];
+  __shared__ double s_imh[kMaxFreq];
+  extern __shared__ double s_K[];   // [n_gate][n_freq], dynamic
+  const int nf = s.n_freq, ng = s.n_gate, nhp = s.n_hankel_pad;
+  const int r = blockIdx.x;
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int gl = lane & 7, gw = lane >> 3;
+  const int nq = (nf + 7) >> 3, nhg = nhp >> 3;
+  const int jf = gw + 8 * wave;
+  // every global load of the workgroup is issued before the first wait: the first batch
+  // of this wave's terms (read whatever the slot holds; used only for a valid particle),
+  // the slot's layer count and particle, and the tables
+  constexpr int kBatch = 16;   // terms in flight before the dependent sums
+  const double *src = rim + ((int64_t)r * nq + wave) * nhg * kWave + lane;
+  double v[kBatch];
+#pragma unroll
+  for (int t = 0; t < kBatch; ++t) v[t] = t < nhg ? src[(int64_t)t * kWave] : 0.0;
+  const int L = rim_layers[r];
+  const int64_t i = perm ? (int64_t)perm[r] : r;
+  for (int t = threadIdx.x; t < nhp; t += blockDim.x) s_ck[t] = s.ck[t];
+  for (int t = threadIdx.x; t < nf * ng; t += blockDim.x) s_K[t] = s.K[t];
+  for (int t = threadIdx.x; t < ng; t += blockDim.x) s_eps2[t] = s.eps_an2[t];
+  if (p.mask && p.mask[i] != p.mask_value) return;   // workgroup-uniform
+  __syncthreads();
+  if (L > 0) {
+    double acc = 0.0;
+    for (int s0 = 0; s0 < nhg; s0 += kBatch) {
+      if (s0 > 0) {
+#pragma unroll
+        for (int t = 0; t < kBatch; ++t) v[t] = s0 + t < nhg ? src[(int64_t)(s0 + t) * kWave] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < kBatch; ++t)
+        if (s0 + t < nhg) acc = __builtin_fma(s_ck[gl + 8 * (s0 + t)], v[t], acc);
+    }
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    acc += __shfl_xor(acc, 4);
+    if (gl == 0 && jf < nf) s_imh[jf] = acc;
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  if (L > 0)
+    gates_loglik(s, p, i, s_K, s_imh, s_eps2, resp, y_obs, ll, lane);
+  else
+    invalid_outputs(s, i, resp, ll, lane);
+}
+
+template <typename T>
+static hipError_t launch_spread(const DevSystem &s, const DevParticles &p, int kc, int km, double *resp,
+                                const double *y_obs, double *ll, const ForwardTiles &t, hipStream_t stream) {
+  const int nq = (s.n_freq + 7) / 8;
+  hipLaunchKernelGGL(spread_terms_kernel<T>, dim3((unsigned)t.n_cu), dim3(kWave * kSpreadWaves),
+                     spread_table_bytes<T>(s), stream, s, p, kc, km, t.perm, t.rim, t.rim_layers);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(spread_finish_kernel, dim3((unsigned)p.n), dim3(kWave * nq),
+                     sizeof(double) * s.n_freq * s.n_gate, stream, s, p, t.perm, t.rim, t.rim_layers, resp, y_obs,
+                     ll);
+  return hipGetLastError();
+}
+
+// Whether a launch over n particles can take the spread evaluation with these tiles.
+static bool spread_ok(const ForwardTiles &t, int64_t n) {
+  return t.rim && t.rim_layers && t.n_cu > 0 && n <= t.rim_n && n <= kSpreadMaxN;
+}
+
+int64_t spread_rim_doubles(const DevSystem &s, int64_t n) {
+  return n * ((s.n_freq + 7) / 8) * (s.n_hankel_pad / 8) * kWave;
+}
+
+int64_t spread_max_particles() { return kSpreadMaxN; }
+
+template <typename T>
+static hipError_t spread_lds(const DevSystem &s, size_t *bytes) {
+  hipFuncAttributes a1, a2;
+  hipError_t e = hipFuncGetAttributes(&a1, reinterpret_cast<const void *>(&spread_terms_kernel<T>));
+  if (e == hipSuccess) e = hipFuncGetAttributes(&a2, reinterpret_cast<const void *>(&spread_finish_kernel));
+  if (e != hipSuccess) return e;
+  const size_t b1 = a1.sharedSizeBytes + spread_table_bytes<T>(s);
+  const size_t b2 = a2.sharedSizeBytes + sizeof(double) * s.n_freq * s.n_gate;
+  *bytes = b1 > b2 ? b1 : b2;
+  return hipSuccess;
 }
 
 // Dynamic LDS of one workgroup: K [n_gate][n_freq], plus the reflection terms
@@ -246,12 +631,20 @@ static hipError_t lds_t(const DevSystem &s, size_t *bytes) {
 template <typename T>
 static hipError_t launch_prec(const ForwardTiles &t, const DevSystem &s, const DevParticles &p, int kc, int km,
                               double *resp, const double *y_obs, double *ll, hipStream_t stream) {
+  if (t.waves_per_particle == 0 && t.waves_per_block == kSpreadWaves) {
+    if (p.n == 0) return hipSuccess;
+    if (sizeof(T) == sizeof(double) && spread_ok(t, p.n))
+      return launch_spread<double>(s, p, kc, km, resp, y_obs, ll, t, stream);
+    return launch_t<T, 4, 1>(s, p, kc, km, resp, y_obs, ll, t.perm, stream);   // beyond the workspace
+  }
   RJSMC_TILE_DISPATCH(launch_t, T, t.waves_per_block, t.waves_per_particle, s, p, kc, km, resp, y_obs, ll, t.perm,
                       stream);
 }
 
 template <typename T>
 static hipError_t lds_prec(const DevSystem &s, int w, int q, size_t *bytes) {
+  if (q == 0 && w == kSpreadWaves)   // FP64 only: not compiled for FP32
+    return sizeof(T) == sizeof(double) ? spread_lds<double>(s, bytes) : hipErrorInvalidValue;
   RJSMC_TILE_DISPATCH(lds_t, T, w, q, s, bytes);
 }
 

@@ -287,12 +287,18 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
   c->work_cnt = nullptr;
   c->work_gvalid = nullptr;
   c->work_lq = nullptr;
+  c->work_rim = nullptr;
+  c->work_rim_layers = nullptr;
+  c->work_rim_n = 0;
   c->tuning.waves_per_block = 4;
   c->tuning.layer_sort = 0;
   c->tuning.waves_per_particle = 1;
   int lds_limit = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
   c->lds_limit = lds_limit > 0 ? (size_t)lds_limit : 0;
+  int n_cu = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
+  c->n_cu = n_cu > 0 ? n_cu : 0;
   c->work_n = s->max_particles > 0 ? s->max_particles : 0;
   if (e == hipSuccess && c->work_n > 0) {
     e = hipMalloc((void **)&c->work_mask, sizeof(int32_t) * c->work_n);
@@ -301,6 +307,10 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
     if (e == hipSuccess) e = hipMalloc((void **)&c->work_gvalid, sizeof(int32_t) * c->work_n);
     if (e == hipSuccess) e = hipMalloc((void **)&c->work_lq, sizeof(double) * c->work_n);
     if (e == hipSuccess) e = hipMalloc((void **)&c->work_cnt, sizeof(int) * 2 * rjsmc::kMaxLayers);
+    c->work_rim_n = std::min<int64_t>(c->work_n, rjsmc::spread_max_particles());
+    if (e == hipSuccess)
+      e = hipMalloc((void **)&c->work_rim, sizeof(double) * rjsmc::spread_rim_doubles(d, c->work_rim_n));
+    if (e == hipSuccess) e = hipMalloc((void **)&c->work_rim_layers, sizeof(int32_t) * c->work_rim_n);
   }
   if (e != hipSuccess) {
     if (c->work_mask) (void)hipFree(c->work_mask);
@@ -309,6 +319,8 @@ extern "C" rjsmc_status rjsmc_create(const rjsmc_system *s, int device, rjsmc_ct
     if (c->work_cnt) (void)hipFree(c->work_cnt);
     if (c->work_gvalid) (void)hipFree(c->work_gvalid);
     if (c->work_lq) (void)hipFree(c->work_lq);
+    if (c->work_rim) (void)hipFree(c->work_rim);
+    if (c->work_rim_layers) (void)hipFree(c->work_rim_layers);
     free_dev(d);
     delete[] c->K_host;
     delete c;
@@ -327,6 +339,8 @@ extern "C" void rjsmc_destroy(rjsmc_ctx *c) {
   if (c->work_cnt) (void)hipFree(c->work_cnt);
   if (c->work_gvalid) (void)hipFree(c->work_gvalid);
   if (c->work_lq) (void)hipFree(c->work_lq);
+  if (c->work_rim) (void)hipFree(c->work_rim);
+  if (c->work_rim_layers) (void)hipFree(c->work_rim_layers);
   free_dev(c->dev);
   delete[] c->K_host;
   delete c;
@@ -411,17 +425,24 @@ static rjsmc::MutateWorkspace ctx_workspace(const rjsmc_ctx *c) {
   w.cnt = c->work_cnt;
   w.lq = c->work_lq;
   w.n = c->work_perm ? c->work_n : 0;
+  w.rim = c->work_rim;
+  w.rim_layers = c->work_rim_layers;
+  w.rim_n = c->work_rim ? c->work_rim_n : 0;
   return w;
 }
 
 // Tile shape of a forward launch over dp from the context's tuning; a layer-capacity
 // order is computed first (on the same stream) when the tuning asks for one and the
 // workspace holds dp.n particles.
-static hipError_t forward_tiles(const rjsmc::DevParticles &dp, const rjsmc_tuning &t, const rjsmc::MutateWorkspace &ws,
-                                hipStream_t stream, rjsmc::ForwardTiles *tiles) {
+static hipError_t forward_tiles(const rjsmc_ctx *c, const rjsmc::DevParticles &dp, const rjsmc_tuning &t,
+                                const rjsmc::MutateWorkspace &ws, hipStream_t stream, rjsmc::ForwardTiles *tiles) {
   tiles->waves_per_block = t.waves_per_block;
   tiles->waves_per_particle = t.waves_per_particle;
   tiles->perm = nullptr;
+  tiles->n_cu = c->n_cu;
+  tiles->rim = ws.rim;
+  tiles->rim_layers = ws.rim_layers;
+  tiles->rim_n = ws.rim ? ws.rim_n : 0;
   if (t.layer_sort && ws.perm && dp.n <= ws.n && dp.n > 0) {
     const hipError_t e = rjsmc::launch_layer_sort(dp, ws.cnt, ws.perm, stream);
     if (e != hipSuccess) return e;
@@ -434,7 +455,7 @@ static hipError_t run_forward(const rjsmc_ctx *c, const rjsmc::DevParticles &dp,
                               const double *y_obs, double *ll, hipStream_t stream,
                               const rjsmc::MutateWorkspace *ws = nullptr) {
   rjsmc::ForwardTiles tiles;
-  hipError_t e = forward_tiles(dp, t, ws ? *ws : ctx_workspace(c), stream, &tiles);
+  hipError_t e = forward_tiles(c, dp, t, ws ? *ws : ctx_workspace(c), stream, &tiles);
   if (e == hipSuccess)
     e = rjsmc::launch_forward(c->dev, dp, c->kmax_cond, c->kmax_charg, c->precision, resp, y_obs, ll, stream, tiles);
   return e;
@@ -812,7 +833,8 @@ extern "C" rjsmc_status rjsmc_mutate_noalloc(rjsmc_ctx *c, const rjsmc_mutate_ar
 
 // ---------------------------------------------------------------------------- tuning
 // (waves_per_block, waves_per_particle) of the compiled tile shapes.
-static const int kShapes[RJSMC_TUNING_CANDIDATES / 2][2] = {{2, 1}, {4, 1}, {8, 1}, {2, 2}, {1, 4}, {1, 8}, {1, 16}};
+static const int kShapes[RJSMC_TUNING_CANDIDATES / 2][2] = {{2, 1}, {4, 1}, {8, 1}, {2, 2},
+                                                            {1, 4}, {1, 8}, {1, 16}, {16, 0}};
 
 static bool valid_tuning(const rjsmc_tuning &t) {
   if (t.layer_sort != 0 && t.layer_sort != 1) return false;
@@ -837,6 +859,9 @@ extern "C" rjsmc_status rjsmc_set_tuning(rjsmc_ctx *c, const rjsmc_tuning *t) {
   if (!valid_tuning(*t))
     return fail(RJSMC_E_INVALID, "rjsmc_set_tuning: (%d, %d, %d) is not a compiled tile shape", t->waves_per_block,
                 t->layer_sort, t->waves_per_particle);
+  if (t->waves_per_particle == 0 && c->precision != RJSMC_F64)
+    return fail(RJSMC_E_INVALID, "rjsmc_set_tuning: the spread evaluation (%d, %d, 0) runs in FP64 contexts only",
+                t->waves_per_block, t->layer_sort);
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(e, "rjsmc_set_tuning: hipSetDevice");
   size_t need = 0;
@@ -873,7 +898,10 @@ extern "C" rjsmc_status rjsmc_autotune(rjsmc_ctx *c, const rjsmc_particles *p, c
   for (int k = 0; k < RJSMC_TUNING_CANDIDATES && e == hipSuccess; ++k) {
     const rjsmc_tuning t = {kShapes[k / 2][0], k % 2, kShapes[k / 2][1]};
     float ms = -1.0f;
-    if ((!t.layer_sort || (c->work_perm && dp.n <= c->work_n)) && tuning_fits(c, t, nullptr)) {
+    const bool spread = t.waves_per_particle == 0;
+    const bool spread_ok = c->precision == RJSMC_F64 && c->work_rim && dp.n <= c->work_rim_n;
+    if ((!t.layer_sort || (c->work_perm && dp.n <= c->work_n)) && (!spread || spread_ok) &&
+        tuning_fits(c, t, nullptr)) {
       e = run_forward(c, dp, t, nullptr, y_obs, ll, s);   // warm-up
       if (e == hipSuccess) e = hipEventRecord(ev0, s);
       for (int r = 0; r < reps && e == hipSuccess; ++r) e = run_forward(c, dp, t, nullptr, y_obs, ll, s);

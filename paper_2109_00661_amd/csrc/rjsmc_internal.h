@@ -94,9 +94,20 @@ struct DevGrad {
 // order (a permutation of the particle indices).
 struct ForwardTiles {
   int waves_per_block = 4;     // particles per workgroup
-  int waves_per_particle = 1;  // waves sharing one particle's frequency groups
+  int waves_per_particle = 1;  // waves sharing one particle's frequency groups; 0: spread
   const int32_t *perm = nullptr;
+  // spread evaluation (waves_per_particle 0, waves_per_block 16): one workgroup per compute
+  // unit, reflection terms in rim ([rim_n] slots of spread_rim_doubles(s, 1)) and layer
+  // counts in rim_layers; a launch beyond rim_n particles takes the (4, 1) shape instead
+  int n_cu = 0;
+  double *rim = nullptr;
+  int32_t *rim_layers = nullptr;
+  int64_t rim_n = 0;
 };
+// Doubles of reflection terms the spread evaluation stores for n particles, and the most
+// particles one spread launch takes.
+int64_t spread_rim_doubles(const DevSystem &s, int64_t n);
+int64_t spread_max_particles();
 
 // Kernel launchers (forward.hip / adjoint.hip).  Return the launch's hipError_t.
 hipError_t launch_forward(const DevSystem &s, const DevParticles &p, int kmax_cond, int kmax_charg,
@@ -173,6 +184,9 @@ struct MutateWorkspace {
   int *cnt = nullptr;       // 2 kMaxLayers counting-sort counters
   double *lq = nullptr;
   int64_t n = 0;            // particles it holds
+  double *rim = nullptr;    // spread evaluation terms for rim_n particles (may be absent)
+  int32_t *rim_layers = nullptr;
+  int64_t rim_n = 0;
 };
 // Looks up, once per device and with that device current, the address of the static
 // scratch on `device` (hipGetSymbolAddress); later calls return at once.
@@ -202,6 +216,10 @@ struct rjsmc_ctx {
   int32_t *work_perm;   // [work_n] evaluation order by layer capacity
   int *work_cnt;        // [2 kMaxLayers] counting-sort scratch
   int64_t work_n;
+  double *work_rim;         // [work_rim_n] slots of spread evaluation terms
+  int32_t *work_rim_layers; // [work_rim_n] layer counts of the spread evaluation
+  int64_t work_rim_n;       // min(work_n, the spread launch limit)
   rjsmc_tuning tuning;  // forward tile shape
   size_t lds_limit;     // LDS bytes one workgroup may use on this device
+  int n_cu;             // compute units of the device
 };

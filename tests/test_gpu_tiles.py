@@ -11,7 +11,13 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-SHAPES = [(w, s, q) for (w, q) in ((2, 1), (4, 1), (8, 1), (2, 2), (1, 4), (1, 8), (1, 16)) for s in (0, 1)]
+SHAPES = [(w, s, q) for (w, q) in ((2, 1), (4, 1), (8, 1), (2, 2), (1, 4), (1, 8), (1, 16), (16, 0))
+          for s in (0, 1)]
+
+
+def _shapes(prec):
+    """The spread evaluation (16, 0) is compiled for FP64 only."""
+    return [sh for sh in SHAPES if prec == "f64" or sh[2] != 0]
 
 
 @pytest.fixture(scope="module")
@@ -43,7 +49,7 @@ def test_every_shape_bit_identical(B, uneven, truth_data, prec):
     ref_ll = ctx.loglik(dp, d).cpu().numpy()
     ctx.check()
     assert np.all(np.isfinite(ref_ll))
-    for w, s, q in SHAPES:
+    for w, s, q in _shapes(prec):
         ctx.set_tuning(w, s, q)
         y = ctx.forward(dp).cpu().numpy()
         ll = ctx.loglik(dp, d).cpu().numpy()
@@ -71,7 +77,7 @@ def test_every_shape_bit_identical_split_abscissae(B, uneven, truth_data, prec):
     ref_ll = ctx.loglik(dp, d).cpu().numpy()
     ctx.check()
     assert np.all(np.isfinite(ref_ll))
-    for w, s, q in SHAPES:
+    for w, s, q in _shapes(prec):
         ctx.set_tuning(w, s, q)
         y = ctx.forward(dp).cpu().numpy()
         ll = ctx.loglik(dp, d).cpu().numpy()
@@ -120,7 +126,7 @@ def test_masked_mutation_under_sorted_shape(B, truth_data):
     multi-wave shapes give the same chain as the default shape."""
     from paper_2109_00661_amd.rjsmc import RJSMCRun
     runs = []
-    for shape in ((4, 0, 1), (8, 1, 1), (1, 1, 8)):
+    for shape in ((4, 0, 1), (8, 1, 1), (1, 1, 8), (16, 0, 0)):
         ctx = B.Context(W.system(), precision="f64", max_particles=512)
         ctx.set_tuning(*shape)
         run = RJSMCRun(ctx, 2, 256, np.tile(truth_data, (2, 1)), seed=5)
@@ -147,13 +153,86 @@ def test_autotune_picks_a_timed_shape(B, uneven, truth_data):
     assert np.array_equal(ctx.loglik(dp, d).cpu().numpy(), ref)
     small = B.Context(W.system(kmax_cond=7, kmax_charg=4), precision="f64")   # no workspace
     best2, times2 = small.autotune(dp, d, reps=1)
-    assert [t < 0 for t in times2] == [False, True] * (B.TUNING_CANDIDATES // 2) and best2["layer_sort"] == 0
+    # without a workspace neither the sorted shapes nor the spread evaluation are timed
+    assert [t < 0 for t in times2] == [False, True] * (B.TUNING_CANDIDATES // 2 - 1) + [True, True]
+    assert best2["layer_sort"] == 0 and best2["waves_per_particle"] != 0
     ctx.check()
 
 
-def test_bad_tuning_rejected(B):
+def test_bad_tuning_rejected(B, uneven, truth_data):
     ctx = B.Context(W.system(), precision="f64")
-    for w, s, q in ((3, 0, 1), (4, 2, 1), (0, 0, 1), (4, 0, 2), (1, 0, 5)):
+    for w, s, q in ((3, 0, 1), (4, 2, 1), (0, 0, 1), (4, 0, 2), (1, 0, 5), (8, 0, 0), (16, 2, 0)):
         with pytest.raises(B.RJSMCError):
             ctx.set_tuning(w, s, q)
     assert ctx.get_tuning() == {"waves_per_block": 4, "layer_sort": 0, "waves_per_particle": 1}
+    # the spread evaluation in an FP32 context: rejected, and skipped by the autotuner
+    c32 = B.Context(W.system(kmax_cond=7, kmax_charg=4), precision="f32", max_particles=2048)
+    with pytest.raises(B.RJSMCError) as e:
+        c32.set_tuning(16, 0, 0)
+    assert e.value.status == B.RJSMC_E_INVALID and "FP64" in str(e.value)
+    dp = B.particles_to_device(W.take(uneven, range(100)))
+    best, times = c32.autotune(dp, _data(B, truth_data), reps=1)
+    assert times[-2] < 0 and times[-1] < 0 and all(t > 0 for t in times[:-2])
+    assert best["waves_per_particle"] != 0
+
+
+def test_spread_edge_cases(B, system, K_oracle, truth_data):
+    """The spread evaluation (16, 0): a single particle (its 75 units on as many waves of
+    a grid of thousands), invalid particles between valid ones (NaN responses, -inf
+    log-likelihood, flags raised), the 2048-particle launch limit and one particle beyond
+    it (the (4, 1) shape instead), each bit-identical to the default shape; the single
+    particle and a deep/shallow mix also against the oracle."""
+    from oracle import em
+    ctx = B.Context(W.system(kmax_cond=7, kmax_charg=4), precision="f64", max_particles=4096)
+    d = _data(B, truth_data)
+
+    def both(p, shape):
+        dp = B.particles_to_device(p)
+        ctx.set_tuning(*shape)
+        return ctx.forward(dp).cpu().numpy(), ctx.loglik(dp, d).cpu().numpy()
+
+    def same(p, check_flags=True):
+        ref = both(p, (4, 0, 1))
+        if check_flags:
+            ctx.check()
+        for shape in ((16, 0, 0), (16, 1, 0)):
+            got = both(p, shape)
+            if check_flags:
+                ctx.check()
+            assert np.array_equal(got[0], ref[0], equal_nan=True), shape
+            assert np.array_equal(got[1], ref[1]), shape
+        return ref
+
+    # one particle; a mix of the deepest and the shallowest particles the capacity allows
+    one = W.decoupled_population(1, 7, 4, seed=31, min_sep=1.0, kappa=7, lam=4)
+    kap, lam = np.arange(37) % 8, np.arange(37) % 5
+    kap[::3], lam[::3] = 0, 0
+    kap[1::3], lam[1::3] = 7, 4
+    mix = W.decoupled_population(37, 7, 4, seed=32, min_sep=1.0, kappa=kap, lam=lam)
+    sysw = W.system(kmax_cond=7, kmax_charg=4)
+    for p in (one, mix):
+        y, ll = same(p)
+        y_o = em.forward(p, sysw, K_oracle)
+        s = np.sqrt(em.noise_variance(y_o, sysw["eps_an"][None, :], sysw["eps_mn"]))
+        assert (np.abs(y - y_o) / np.maximum(np.abs(y_o), s)).max() <= 1e-9
+
+    # invalid particles: unsorted interfaces (slot 2), a count beyond the capacity (slot 5)
+    bad = W.decoupled_population(9, 7, 4, seed=33, min_sep=1.0, kappa=np.full(9, 3))
+    bad["z_cond"][0, 2], bad["z_cond"][1, 2] = 120.0, 60.0
+    bad["kappa"][5] = 9
+    ctx.set_tuning(16, 0, 0)
+    y, ll = both(bad, (16, 0, 0))
+    with pytest.raises(B.RJSMCError):
+        ctx.check()
+    ctx.check()                                          # flags were cleared
+    assert np.isnan(y[[2, 5]]).all() and (ll[[2, 5]] == -np.inf).all()
+    assert np.isfinite(y[[0, 1, 3, 4, 6, 7, 8]]).all()
+    ref = both(bad, (4, 0, 1))
+    with pytest.raises(B.RJSMCError):
+        ctx.check()
+    assert np.array_equal(y, ref[0], equal_nan=True) and np.array_equal(ll, ref[1])
+
+    # the launch limit, and one particle beyond it
+    big = W.decoupled_population(2049, 7, 4, seed=34, min_sep=1.0)
+    same(W.take(big, range(2048)))
+    same(big)
