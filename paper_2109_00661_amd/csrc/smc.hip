@@ -1747,22 +1747,94 @@ struct LdsColumn {
   __device__ double &operator[](int j) const { return p[(int64_t)j * stride]; }
 };
 
+// Rows [0, n) of two row-major particle arrays (row j of particle i at a[j S + i]) into
+// two LDS columns.  The loads go out in batches of kRowBatch rows, before the batch's
+// stores: the compiler cannot move a global load above an LDS store through a generic
+// pointer, so a plain row loop would wait out one load latency per row.
+constexpr int kRowBatch = 8;
+__device__ __forceinline__ void load_rows2(const double *a, const double *b, int64_t S, int64_t i, int n,
+                                           const LdsColumn &da, const LdsColumn &db) {
+  for (int j0 = 0; j0 < n; j0 += kRowBatch) {
+    double va[kRowBatch], vb[kRowBatch];
+#pragma unroll
+    for (int t = 0; t < kRowBatch; ++t) {
+      va[t] = j0 + t < n ? a[(int64_t)(j0 + t) * S + i] : 0.0;
+      vb[t] = j0 + t < n ? b[(int64_t)(j0 + t) * S + i] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < kRowBatch; ++t)
+      if (j0 + t < n) {
+        da[j0 + t] = va[t];
+        db[j0 + t] = vb[t];
+      }
+  }
+}
+
+// x[j] += step fx[j] and y[j] += step fy[j] (madd_rn) for j < n over two LDS columns, the
+// factor entries (global) loaded in batches before the updates.
+__device__ __forceinline__ void madd_rows2(const LdsColumn &x, const LdsColumn &y, const double *fx, const double *fy,
+                                           int n, double step) {
+  for (int j0 = 0; j0 < n; j0 += kRowBatch) {
+    double vx[kRowBatch], vy[kRowBatch];
+#pragma unroll
+    for (int t = 0; t < kRowBatch; ++t) {
+      vx[t] = j0 + t < n ? fx[j0 + t] : 0.0;
+      vy[t] = j0 + t < n ? fy[j0 + t] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < kRowBatch; ++t)
+      if (j0 + t < n) {
+        x[j0 + t] = madd_rn(x[j0 + t], step, vx[t]);
+        y[j0 + t] = madd_rn(y[j0 + t], step, vy[t]);
+      }
+  }
+}
+
+// Rows [0, n) of two row-major arrays copied from (sa, sb; stride Ss) to (da, db; stride
+// Sd) for particle i, loads batched before stores as above.
+__device__ __forceinline__ void copy_rows2(double *da, double *db, int64_t Sd, const double *sa, const double *sb,
+                                           int64_t Ss, int64_t i, int n) {
+  for (int j0 = 0; j0 < n; j0 += kRowBatch) {
+    double va[kRowBatch], vb[kRowBatch];
+#pragma unroll
+    for (int t = 0; t < kRowBatch; ++t) {
+      va[t] = j0 + t < n ? sa[(int64_t)(j0 + t) * Ss + i] : 0.0;
+      vb[t] = j0 + t < n ? sb[(int64_t)(j0 + t) * Ss + i] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < kRowBatch; ++t)
+      if (j0 + t < n) {
+        da[(int64_t)(j0 + t) * Sd + i] = va[t];
+        db[(int64_t)(j0 + t) * Sd + i] = vb[t];
+      }
+  }
+}
+
 // Proposal of move `move` for every particle (type from draw_types_kernel): written to
 // `prop`; mask[i] = 1 if the proposal needs a likelihood, 2 if it needs a likelihood and
 // a gradient, 0 if it is rejected outright.  MALA / ZCA: whether the launch can hold
 // gradient-informed moves / the adaptive birth (without them their branches, and the
 // private arrays they need, are compiled out; a particle drawn for an excluded move is
 // rejected).
+// A particle's state held by the caller: counts and scalars in registers, layer rows
+// already in the thread's LDS columns (the proposal's layout).
+struct StateRegs {
+  int k, l;
+  double phb, lt, cc;
+};
+
 template <bool MALA, bool ZCA>
 __device__ __forceinline__ void propose_particle(int64_t i, const SmcShape &sh, const rjsmc_mutate_args &a, int move,
                                                  const DevParticles &st, const DevParticlesW &prop, int32_t *mask,
                                                  int32_t *type, const double *gamma, const DevParticles &gcur,
-                                                 int32_t *gvalid, double *lq, const int32_t *active, int draw) {
+                                                 int32_t *gvalid, double *lq, const int32_t *active, int draw,
+                                                 const StateRegs *pre = nullptr) {
   if (i >= st.n) return;
   const int64_t snd = st.n_per_sounding > 0 ? i / st.n_per_sounding : 0;
   const int64_t S = st.stride, So = prop.stride;
+  int t;
   if (draw) {                          // the move type, as draw_types_kernel (no gradient moves)
-    const int k0 = st.kappa[i], l0 = st.lambda[i];
+    const int k0 = pre ? pre->k : st.kappa[i], l0 = pre ? pre->l : st.lambda[i];
     int t0 = -1;
     if ((!active || active[snd]) && k0 >= 0 && k0 <= sh.kc && l0 >= 0 && l0 <= sh.km) {
       double u0, ua;
@@ -1770,8 +1842,10 @@ __device__ __forceinline__ void propose_particle(int64_t i, const SmcShape &sh, 
       t0 = draw_type(a, u0);
     }
     type[i] = t0;
+    t = t0;
+  } else {
+    t = type[i];
   }
-  const int t = type[i];
   if (t < 0) {
     mask[i] = 0;
     return;
@@ -1782,7 +1856,7 @@ __device__ __forceinline__ void propose_particle(int64_t i, const SmcShape &sh, 
   double u1, u2, u3, u4;
   uniforms(a.seed, (uint32_t)i, (uint32_t)step_of(a), (uint32_t)move, 1u, u1, u2);
   uniforms(a.seed, (uint32_t)i, (uint32_t)step_of(a), (uint32_t)move, 2u, u3, u4);
-  int k = st.kappa[i], l = st.lambda[i];
+  int k = pre ? pre->k : st.kappa[i], l = pre ? pre->l : st.lambda[i];
   // the layer arrays in LDS (one column per thread): private arrays indexed at run time
   // would live in scratch memory
   extern __shared__ double prop_lds[];
@@ -1790,18 +1864,25 @@ __device__ __forceinline__ void propose_particle(int64_t i, const SmcShape &sh, 
   double *lds0 = prop_lds + threadIdx.x;
   const LdsColumn zc{lds0, T}, ph{lds0 + (int64_t)kc * T, T}, zm{lds0 + (int64_t)2 * kc * T, T},
       mm{lds0 + (int64_t)(2 * kc + km) * T, T};
-  for (int j = 0; j < k; ++j) {
-    zc[j] = st.z_cond[j * S + i];
-    ph[j] = st.phi[j * S + i];
+  double phb, lt, cc;
+  if (pre) {
+    phb = pre->phb;
+    lt = pre->lt;
+    cc = pre->cc;
+  } else {
+    phb = st.phi_b[i];
+    lt = st.log10_tau[i];
+    cc = st.c[i];
+    load_rows2(st.z_cond, st.phi, S, i, k, zc, ph);
+    load_rows2(st.z_charg, st.m, S, i, l, zm, mm);
   }
-  for (int j = 0; j < l; ++j) {
-    zm[j] = st.z_charg[j * S + i];
-    mm[j] = st.m[j * S + i];
-  }
-  double phb = st.phi_b[i], lt = st.log10_tau[i], cc = st.c[i];
   bool ok = false;
   const bool jump = t == RJSMC_MOVE_SIGMA_BIRTH || t == RJSMC_MOVE_M_BIRTH || t == RJSMC_MOVE_SIGMA_DEATH ||
                     t == RJSMC_MOVE_M_DEATH;
+  // the standard normal of the moves that take one, formed once before the branches (a
+  // wave runs the branches of all its lanes' move types one after another, and the
+  // logarithm and cosine are its longest chain)
+  const double nz = normal0(u2, u3);
   if (lq) lq[i] = 0.0;
   if (ZCA && a.zca_birth && jump) {
     const bool birth = t == RJSMC_MOVE_SIGMA_BIRTH || t == RJSMC_MOVE_M_BIRTH;
@@ -1816,7 +1897,7 @@ __device__ __forceinline__ void propose_particle(int64_t i, const SmcShape &sh, 
       for (int j = 0; j < l; ++j) th[q++] = zm[j];
       th[q++] = lt;
       th[q++] = cc;
-      if (zca_move(th, k, l, birth, part, u1, normal0(u2, u3), a, sh, snd, corr)) {
+      if (zca_move(th, k, l, birth, part, u1, nz, a, sh, snd, corr)) {
         q = 0;
         phb = th[q++];
         for (int j = 0; j < k; ++j) ph[j] = th[q++];
@@ -1875,7 +1956,7 @@ __device__ __forceinline__ void propose_particle(int64_t i, const SmcShape &sh, 
     if (n > 0) {
       int j = (int)(u1 * (double)n);
       j = j > n - 1 ? n - 1 : j;
-      const double zn = madd_rn(z[j], a.z_move_sd, normal0(u2, u3));
+      const double zn = madd_rn(z[j], a.z_move_sd, nz);
       const double lo = j > 0 ? z[j - 1] : 0.0;
       const double hi = j + 1 < n ? z[j + 1] : sh.z_max;
       if (lo < zn && zn < hi && zn > 0.0) {
@@ -1889,16 +1970,15 @@ __device__ __forceinline__ void propose_particle(int64_t i, const SmcShape &sh, 
     r = r > d - 1 ? d - 1 : r;
     const int mdl = k * (km + 1) + l;
     const double *Fr = a.factors + ((snd * sh.n_models + mdl) * (int64_t)sh.dmax + r) * sh.dmax;
-    const double step = (a.rw_scale_dev ? a.rw_scale_dev[snd] : a.rw_scale) * normal0(u2, u3);
-    // theta' = theta + step F[:, r] in parameter-vector order
-    int q = 0;
-    phb = madd_rn(phb, step, Fr[q++]);
-    for (int j = 0; j < k; ++j) ph[j] = madd_rn(ph[j], step, Fr[q++]);
-    for (int j = 0; j < k; ++j) zc[j] = madd_rn(zc[j], step, Fr[q++]);
-    for (int j = 0; j < l; ++j) mm[j] = madd_rn(mm[j], step, Fr[q++]);
-    for (int j = 0; j < l; ++j) zm[j] = madd_rn(zm[j], step, Fr[q++]);
-    lt = madd_rn(lt, step, Fr[q++]);
-    cc = madd_rn(cc, step, Fr[q++]);
+    const double step = (a.rw_scale_dev ? a.rw_scale_dev[snd] : a.rw_scale) * nz;
+    // theta' = theta + step F[:, r] in parameter-vector order (phi_b, phi, z_cond, m,
+    // z_charg, log10 tau, c); the entries are loaded together, not one per update
+    const double f0 = Fr[0], fa = Fr[d - 2], fb = Fr[d - 1];
+    madd_rows2(ph, zc, Fr + 1, Fr + 1 + k, k, step);
+    madd_rows2(mm, zm, Fr + 1 + 2 * k, Fr + 1 + 2 * k + l, l, step);
+    phb = madd_rn(phb, step, f0);
+    lt = madd_rn(lt, step, fa);
+    cc = madd_rn(cc, step, fb);
     ok = in_range(phb, pr.phi_lo, pr.phi_hi) && in_range(lt, pr.ltau_lo, pr.ltau_hi) &&
          in_range(cc, pr.c_lo, pr.c_hi);
     for (int j = 0; j < k; ++j)
@@ -2010,19 +2090,15 @@ __device__ __forceinline__ void accept_particle(int64_t i, const SmcShape &sh, c
     acc = margin > 0.0;
     if (acc && a.trial == 0) {
       const int64_t S = st.stride, Sp = prop.stride;
-      st.kappa[i] = prop.kappa[i];
-      st.lambda[i] = prop.lambda[i];
-      st.phi_b[i] = prop.phi_b[i];
-      st.log10_tau[i] = prop.log10_tau[i];
-      st.c[i] = prop.c[i];
-      for (int j = 0; j < sh.kc; ++j) {
-        st.z_cond[j * S + i] = prop.z_cond[j * Sp + i];
-        st.phi[j * S + i] = prop.phi[j * Sp + i];
-      }
-      for (int j = 0; j < sh.km; ++j) {
-        st.z_charg[j * S + i] = prop.z_charg[j * Sp + i];
-        st.m[j * S + i] = prop.m[j * Sp + i];
-      }
+      const int pk = prop.kappa[i], pl = prop.lambda[i];
+      const double pb = prop.phi_b[i], pt = prop.log10_tau[i], pc = prop.c[i];
+      st.kappa[i] = pk;
+      st.lambda[i] = pl;
+      st.phi_b[i] = pb;
+      st.log10_tau[i] = pt;
+      st.c[i] = pc;
+      copy_rows2(st.z_cond, st.phi, S, prop.z_cond, prop.phi, Sp, i, sh.kc);
+      copy_rows2(st.z_charg, st.m, S, prop.z_charg, prop.m, Sp, i, sh.km);
       ll[i] = ll_prop[i];
       if (gvalid) {
         // a Langevin proposal brings its own gradient; any other accepted move leaves the
@@ -2075,7 +2151,12 @@ __global__ __launch_bounds__(256) void accept_kernel(SmcShape sh, rjsmc_mutate_a
 // The decision of sweep move_prev, then the proposal of sweep move, for every particle:
 // both read and write only the particle's own state, proposal, move type, mask and
 // correction (each read before it is rewritten), so one launch serves the two.  Sweeps
-// without gradient-informed moves only.
+// without gradient-informed moves only.  The decision is accept_particle's; the launch
+// loads everything either step reads in one round, before the decision: the current
+// state (scalars in registers, layer rows, all rows up to the capacities, into the
+// proposal's LDS columns), the decision's inputs, and, for an evaluated proposal, the
+// proposal itself, so that an accepted one is copied from registers and the next
+// proposal starts from whichever state survives without reading it back.
 template <bool ZCA>
 __global__ __launch_bounds__(256) void accept_propose_kernel(SmcShape sh, rjsmc_mutate_args a, int move_prev, int move,
                                                              DevParticlesW st_w, DevParticles st_r, double *ll,
@@ -2084,9 +2165,119 @@ __global__ __launch_bounds__(256) void accept_propose_kernel(SmcShape sh, rjsmc_
                                                              const double *gamma, int64_t *stats, double *lq,
                                                              const int32_t *active) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  accept_particle(i, sh, a, move_prev, st_w, ll, prop_r, ll_prop, mask, type, gamma, DevParticlesW(), DevParticles(),
-                  nullptr, stats, lq);
-  propose_particle<false, ZCA>(i, sh, a, move, st_r, prop_w, mask, type, gamma, DevParticles(), nullptr, lq, active, 1);
+  const bool in = i < st_r.n;
+  const int kc = sh.kc, km = sh.km;
+  const int64_t S = st_r.stride, Sp = prop_r.stride;
+  const int64_t snd = in && st_r.n_per_sounding > 0 ? i / st_r.n_per_sounding : 0;
+  extern __shared__ double prop_lds[];
+  const int T = blockDim.x;
+  double *lds0 = prop_lds + threadIdx.x;
+  const LdsColumn zc{lds0, T}, ph{lds0 + (int64_t)kc * T, T}, zm{lds0 + (int64_t)2 * kc * T, T},
+      mm{lds0 + (int64_t)(2 * kc + km) * T, T};
+  StateRegs s0{0, 0, 0.0, 0.0, 0.0};
+  int t = -1, mk = 0;
+  double llp = 0.0, llc = 0.0, gm = 0.0, lqv = 0.0;
+  if (in) {
+    t = type[i];
+    mk = mask[i];
+    llp = ll_prop[i];
+    llc = ll[i];
+    gm = gamma[snd];
+    if (ZCA && lq) lqv = lq[i];
+    s0.k = st_r.kappa[i];
+    s0.l = st_r.lambda[i];
+    s0.phb = st_r.phi_b[i];
+    s0.lt = st_r.log10_tau[i];
+    s0.cc = st_r.c[i];
+    load_rows2(st_r.z_cond, st_r.phi, S, i, kc, zc, ph);
+    load_rows2(st_r.z_charg, st_r.m, S, i, km, zm, mm);
+  }
+  bool acc = false;
+  if (in && t >= 0 && mk) {
+    const bool copy = a.trial == 0;
+    // the proposal (the next state if accepted), the first kRowBatch rows in registers
+    int pk = 0, pl = 0;
+    double pb = 0.0, pt = 0.0, pc = 0.0;
+    double rz[kRowBatch], rp[kRowBatch], rzm[kRowBatch], rmm[kRowBatch];
+    if (copy) {
+      pk = prop_r.kappa[i];
+      pl = prop_r.lambda[i];
+      pb = prop_r.phi_b[i];
+      pt = prop_r.log10_tau[i];
+      pc = prop_r.c[i];
+#pragma unroll
+      for (int j = 0; j < kRowBatch; ++j) {
+        rz[j] = j < kc ? prop_r.z_cond[(int64_t)j * Sp + i] : 0.0;
+        rp[j] = j < kc ? prop_r.phi[(int64_t)j * Sp + i] : 0.0;
+        rzm[j] = j < km ? prop_r.z_charg[(int64_t)j * Sp + i] : 0.0;
+        rmm[j] = j < km ? prop_r.m[(int64_t)j * Sp + i] : 0.0;
+      }
+    }
+    double u0, ua;
+    uniforms(a.seed, (uint32_t)i, (uint32_t)step_of(a), (uint32_t)move_prev, 0u, u0, ua);
+    double extra = 0.0;
+    if (ZCA && a.zca_birth && lq &&
+        (t == RJSMC_MOVE_SIGMA_BIRTH || t == RJSMC_MOVE_M_BIRTH || t == RJSMC_MOVE_SIGMA_DEATH ||
+         t == RJSMC_MOVE_M_DEATH))
+      extra += lqv;                       // adaptive birth / death: proposal and Jacobian terms
+    const double margin = gm * (llp - llc) + extra - log(ua);
+    acc = margin > 0.0;
+    if (acc && copy) {
+      st_w.kappa[i] = pk;
+      st_w.lambda[i] = pl;
+      st_w.phi_b[i] = pb;
+      st_w.log10_tau[i] = pt;
+      st_w.c[i] = pc;
+#pragma unroll
+      for (int j = 0; j < kRowBatch; ++j) {
+        if (j < kc) {
+          st_w.z_cond[(int64_t)j * S + i] = rz[j];
+          st_w.phi[(int64_t)j * S + i] = rp[j];
+          zc[j] = rz[j];
+          ph[j] = rp[j];
+        }
+        if (j < km) {
+          st_w.z_charg[(int64_t)j * S + i] = rzm[j];
+          st_w.m[(int64_t)j * S + i] = rmm[j];
+          zm[j] = rzm[j];
+          mm[j] = rmm[j];
+        }
+      }
+      // rows beyond the first batch (capacities above kRowBatch)
+      for (int j = kRowBatch; j < kc; ++j) {
+        const double z = prop_r.z_cond[(int64_t)j * Sp + i], v = prop_r.phi[(int64_t)j * Sp + i];
+        st_w.z_cond[(int64_t)j * S + i] = z;
+        st_w.phi[(int64_t)j * S + i] = v;
+        zc[j] = z;
+        ph[j] = v;
+      }
+      for (int j = kRowBatch; j < km; ++j) {
+        const double z = prop_r.z_charg[(int64_t)j * Sp + i], v = prop_r.m[(int64_t)j * Sp + i];
+        st_w.z_charg[(int64_t)j * S + i] = z;
+        st_w.m[(int64_t)j * S + i] = v;
+        zm[j] = z;
+        mm[j] = v;
+      }
+      ll[i] = llp;
+      s0 = StateRegs{pk, pl, pb, pt, pc};
+    }
+  }
+  if (a.stats_sound && (t == RJSMC_MOVE_WITHIN_RW || t == RJSMC_MOVE_WITHIN_MALA)) {
+    // every drawn within-model proposal counts, also one that leaves the support
+    atomicAdd((unsigned long long *)&a.stats_sound[2 * snd], 1ull);
+    if (acc) atomicAdd((unsigned long long *)&a.stats_sound[2 * snd + 1], 1ull);
+  }
+  if (stats) {
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int q = 0; q < RJSMC_N_MOVES; ++q) {
+      const int np = __popcll(__ballot(t == q));
+      const int na = __popcll(__ballot(t == q && acc));
+      if (lane == 0 && np) atomicAdd((unsigned long long *)&stats[q], (unsigned long long)np);
+      if (lane == 0 && na) atomicAdd((unsigned long long *)&stats[RJSMC_N_MOVES + q], (unsigned long long)na);
+    }
+  }
+  propose_particle<false, ZCA>(i, sh, a, move, st_r, prop_w, mask, type, gamma, DevParticles(), nullptr, lq, active, 1,
+                               &s0);
 }
 
 hipError_t launch_draw_types(const rjsmc_mutate_args &a, int move, const DevParticles &state, int kc, int km,
