@@ -260,14 +260,16 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
 // and the units, slot-major, are cut into ranges of equal weight, one per workgroup of a
 // grid with one workgroup per compute unit.  A deep particle's units so spread over more
 // compute units than a shallow one's.  A workgroup merges the few particles of its range
-// (kSpreadStage at a time) and builds their wavenumber tables in LDS together; then its
+// (as many as fit a pool of kSpreadPool layer tables, at most kSpreadStage at a time) and
+// builds their wavenumber tables in LDS together; then its
 // waves claim the range's units one at a time from an LDS counter, so that every SIMD
 // stays busy until the range is done.  spread_terms_kernel writes the terms to rim in
 // [slot][q][s][lane] order; spread_finish_kernel adds them in the order of forward_kernel
 // and applies the gates and the likelihood, so the results are the same bits.
 constexpr int kSpreadWaves = 16;                         // waves per workgroup
 constexpr int kSpreadMaxN = 2 * kWave * kSpreadWaves;   // particles per launch (two per thread)
-constexpr int kSpreadStage = 4;                          // particles staged at once
+constexpr int kSpreadStage = 8;                          // particles staged at once, at most
+constexpr int kSpreadPool = 64;                          // layer capacities staged at once, at most
 
 // Weight of the particle in a slot: 0 if masked out, else its layer capacity (clamped to
 // 1..kMaxLayers, so that invalid counts stay bounded) + 1.  Its counts are kept for the
@@ -281,16 +283,13 @@ __device__ __forceinline__ int spread_weight(const DevParticles &p, int64_t i, i
   return cap + 1;
 }
 
-// v[k] for a small index k known only at run time (held in scalar registers, no
-// indexed access).
-__device__ __forceinline__ int pick4(int k, int v0, int v1, int v2, int v3) {
-  return k == 0 ? v0 : (k == 1 ? v1 : (k == 2 ? v2 : v3));
-}
 
-// Dynamic LDS of spread_terms_kernel: the staged particles' k2 and dk2 tables.
+
+// Dynamic LDS of spread_terms_kernel: the staged particles' k2 and dk2 tables, each
+// particle's [n_freq][capacity] behind the previous one's.
 template <typename T>
 static size_t spread_table_bytes(const DevSystem &s) {
-  return 2 * sizeof(cplx<T>) * kSpreadStage * s.n_freq * kMaxLayers;
+  return 2 * sizeof(cplx<T>) * kSpreadPool * s.n_freq;
 }
 
 // rim_layers[r] = L of the particle in slot r (0: invalid), written by the workgroup that
@@ -300,7 +299,7 @@ __global__ __launch_bounds__(kWave * kSpreadWaves, 1) void spread_terms_kernel(
     DevSystem s, DevParticles p, int kc, int km, const int32_t *perm, double *rim, int32_t *rim_layers) {
   constexpr int LMAX = kMaxLayers;
   constexpr int KP = kSpreadStage;
-  static_assert(KP == 4, "pick4 holds the staged set");
+  static_assert(kSpreadPool >= kMaxLayers, "one particle of any capacity fits the pool");
   __shared__ double s_lam[kMaxHankel];
   __shared__ double s_omega[kMaxFreq];
   __shared__ double s_logw[kMaxFreq];
@@ -313,11 +312,14 @@ __global__ __launch_bounds__(kWave * kSpreadWaves, 1) void spread_terms_kernel(
   __shared__ ColeCole s_cc[KP];
   __shared__ T s_h2[KP][LMAX];
   __shared__ int s_L[KP];
+  // staged set: slot, first unit, first claim (entry np: the claims in all), table offset
+  // and capacity
+  __shared__ int s_sl[KP], s_ja[KP], s_cu[KP + 1], s_off[KP], s_cap[KP], s_np;
   __shared__ int s_next;
-  extern __shared__ double s_tab[];   // k2 [KP][n_freq][LMAX], then dk2 alike
+  extern __shared__ double s_tab[];   // k2 pool [kSpreadPool n_freq], then dk2 alike
   const int nf = s.n_freq, nhp = s.n_hankel_pad;
   cplx<T> *const s_k2 = reinterpret_cast<cplx<T> *>(s_tab);
-  cplx<T> *const s_dk2 = s_k2 + KP * nf * LMAX;
+  cplx<T> *const s_dk2 = s_k2 + kSpreadPool * nf;
 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x & (kWave - 1);
@@ -393,8 +395,8 @@ __global__ __launch_bounds__(kWave * kSpreadWaves, 1) void spread_terms_kernel(
   const int gl = lane & 7, gw = lane >> 3;
   int rr = r_first;   // the next slot to consider
   for (;;) {
-    // the staged set: the next (at most KP) slots of [rr, r_last] with units in the range,
-    // found with one ballot over 64 slots (every wave finds the same set)
+    // the staged set: the next slots of [rr, r_last] with units in the range, found with
+    // one ballot over 64 slots (every wave finds the same), as many as the pool takes
     uint64_t m = 0;
     for (;;) {
       const int slot = rr + lane;
@@ -408,27 +410,33 @@ __global__ __launch_bounds__(kWave * kSpreadWaves, 1) void spread_terms_kernel(
       rr += kWave;
     }
     if (m == 0) break;   // workgroup-uniform: the range is done
-    int sl[KP], ja[KP], cu[KP + 1], np = 0;
-    cu[0] = 0;
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      sl[k] = 0;
-      ja[k] = 0;
-      cu[k + 1] = cu[k];
-      if (m != 0) {
+    if (threadIdx.x == 0) {
+      int np = 0, cu = 0, off = 0;
+      while (m != 0 && np < KP) {
         const int slot = rr + __builtin_ctzll(m);
+        int cap = s_kap[slot] + s_lmb[slot] + 1;
+        cap = cap < 1 ? 1 : (cap > LMAX ? LMAX : cap);   // the merge rejects counts beyond LMAX
+        if (off + cap > kSpreadPool) break;
         m &= m - 1;
         const int a = slot == r_first ? j_first : 0, b = slot == r_last ? j_last : U;
-        sl[k] = slot;
-        ja[k] = a;
-        cu[k + 1] = cu[k] + (b - a);
-        np = k + 1;
+        s_sl[np] = slot;
+        s_ja[np] = a;
+        s_cu[np] = cu;
+        s_off[np] = off * nf;
+        s_cap[np] = cap;
+        cu += b - a;
+        off += cap;
+        ++np;
       }
+      s_cu[np] = cu;
+      s_np = np;
     }
-    rr = sl[np - 1] + 1;
+    __syncthreads();
+    const int np = uni(s_np);
+    rr = uni(s_sl[np - 1]) + 1;
     // wave w < np merges staged particle w
     if (wave < np) {
-      const int rw = pick4(wave, sl[0], sl[1], sl[2], sl[3]);
+      const int rw = uni(s_sl[wave]);
       const int64_t i = perm ? (int64_t)perm[rw] : rw;
       LayerStack *st = &s_stack[wave];
       const int L = merge_counts(p, i, true, uni(s_kap[rw]), uni(s_lmb[rw]), kc, km, LMAX, st, s.flags);
@@ -439,22 +447,23 @@ __global__ __launch_bounds__(kWave * kSpreadWaves, 1) void spread_terms_kernel(
       }
       if (lane == 0) {
         s_L[wave] = L;
-        if (pick4(wave, ja[0], ja[1], ja[2], ja[3]) == 0) rim_layers[rw] = L;
+        if (s_ja[wave] == 0) rim_layers[rw] = L;
       }
     }
     __syncthreads();
     // wavenumber tables of the frequency chunks the staged units need, one (particle,
-    // frequency) pair per thread
+    // frequency) pair per thread; particle sp's table of frequency f at s_off[sp] +
+    // f s_cap[sp] (L <= capacity)
     for (int t = threadIdx.x; t < np * nf; t += blockDim.x) {
       const int sp = t / nf, f = t - sp * nf;
       const int L = s_L[sp];
-      const int a = pick4(sp, ja[0], ja[1], ja[2], ja[3]);
-      const int b = a + pick4(sp, cu[1], cu[2], cu[3], cu[4]) - pick4(sp, cu[0], cu[1], cu[2], cu[3]);
+      const int a = s_ja[sp], b = a + s_cu[sp + 1] - s_cu[sp];
       const int qa = a / nhg, qb = (b - 1) / nhg;
       if (L > 0 && f >= 8 * qa && f < 8 * qb + 8) {
         const LayerStack *st = &s_stack[sp];
         const K2Freq<T> kf = k2_freq<T>(s_omega[f], s_logw[f], s_cc[sp]);
-        cplx<T> *k2 = s_k2 + (sp * nf + f) * LMAX, *dk2 = s_dk2 + (sp * nf + f) * LMAX;
+        const int o = s_off[sp] + f * s_cap[sp];
+        cplx<T> *k2 = s_k2 + o, *dk2 = s_dk2 + o;
         cplx<T> kl = k2_layer<T>(st, 0, kf);
         for (int l = 0; l < L; ++l) {
           k2[l] = kl;
@@ -468,23 +477,25 @@ __global__ __launch_bounds__(kWave * kSpreadWaves, 1) void spread_terms_kernel(
     }
     __syncthreads();
     // the staged units, claimed one at a time by whichever wave is free
-    const int nu = cu[np];
+    const int nu = uni(s_cu[np]);
     for (;;) {
       int u = 0;
       if (lane == 0) u = atomicAdd(&s_next, 1);
       u = __builtin_amdgcn_readfirstlane(u);
       if (u >= nu) break;
-      const int sp = (u >= cu[1]) + (u >= cu[2]) + (u >= cu[3]);
+      int sp = 0;
+      while (sp + 1 < np && u >= uni(s_cu[sp + 1])) ++sp;
       const int L = uni(s_L[sp]);
       if (L == 0) continue;   // invalid particle: no terms
-      const int jj = pick4(sp, ja[0], ja[1], ja[2], ja[3]) + u - pick4(sp, cu[0], cu[1], cu[2], cu[3]);
+      const int jj = uni(s_ja[sp]) + u - uni(s_cu[sp]);
       const int q = jj / nhg, sidx = jj - q * nhg;
       const int jf = gw + 8 * q;
+      const int o = uni(s_off[sp]) + jf * uni(s_cap[sp]);
       double v = 0.0;
       if (jf < nf)
-        v = static_cast<double>(reflection_im<T>(to<T>(s_lam[gl + 8 * sidx]), s_k2 + (sp * nf + jf) * LMAX,
-                                                 s_dk2 + (sp * nf + jf) * LMAX, s_h2[sp], L, s_phase, s_exp2));
-      rim[(((int64_t)pick4(sp, sl[0], sl[1], sl[2], sl[3]) * nq + q) * nhg + sidx) * kWave + lane] = v;
+        v = static_cast<double>(reflection_im<T>(to<T>(s_lam[gl + 8 * sidx]), s_k2 + o, s_dk2 + o, s_h2[sp], L,
+                                                 s_phase, s_exp2));
+      rim[(((int64_t)uni(s_sl[sp]) * nq + q) * nhg + sidx) * kWave + lane] = v;
     }
     __syncthreads();   // every claimed unit is done before the set is restaged
     if (threadIdx.x == 0) s_next = 0;
