@@ -589,33 +589,35 @@ __device__ __forceinline__ void st_off(T *base, uint32_t bytes, T v) {
 // their stores, which are the only predicated accesses, so a group's loads are in flight
 // together.
 constexpr int kCopyPer = kMaxPerSounding / kRwThreads;
-template <typename SM>
+// CP members per thread (first + tid + k kRwThreads, k < CP), RB layer rows per batch of
+// loads.
+template <int CP, int RB, typename SM>
 __device__ __forceinline__ void copy_resampled(const SM &sm, const DevParticles &in,
                                                const double *__restrict__ ll_in, const DevParticlesW &out,
                                                double *__restrict__ ll_out, int32_t *__restrict__ anc, int64_t off,
                                                int N, int rows_c, int rows_m, int rows_zm, int first = 0) {
   const int tid = threadIdx.x;
   const int64_t Si = in.stride, So = out.stride;
-  uint32_t src[kCopyPer], dst[kCopyPer];   // member indices within the sounding
-  bool ok[kCopyPer];
+  uint32_t src[CP], dst[CP];   // member indices within the sounding
+  bool ok[CP];
 #pragma unroll
-  for (int k = 0; k < kCopyPer; ++k) {
+  for (int k = 0; k < CP; ++k) {
     const int i = first + tid + k * kRwThreads;
     ok[k] = i < N;
     dst[k] = ok[k] ? (uint32_t)i : 0u;
     src[k] = ok[k] ? (uint32_t)sm.v.anc_l[i] : 0u;
   }
   {
-    int32_t ka[kCopyPer], la[kCopyPer];
-    double lv[kCopyPer];
+    int32_t ka[CP], la[CP];
+    double lv[CP];
 #pragma unroll
-    for (int k = 0; k < kCopyPer; ++k) {
+    for (int k = 0; k < CP; ++k) {
       ka[k] = ld_off(in.kappa + off, src[k] * 4u);
       la[k] = in.lambda ? ld_off(in.lambda + off, src[k] * 4u) : 0;
       lv[k] = ld_off(ll_in + off, src[k] * 8u);
     }
 #pragma unroll
-    for (int k = 0; k < kCopyPer; ++k)
+    for (int k = 0; k < CP; ++k)
       if (ok[k]) {
         st_off(anc + off, dst[k] * 4u, (int32_t)(off + src[k]));
         st_off(out.kappa + off, dst[k] * 4u, ka[k]);
@@ -624,37 +626,47 @@ __device__ __forceinline__ void copy_resampled(const SM &sm, const DevParticles 
       }
   }
   {
-    double pb[kCopyPer], lt[kCopyPer], cc[kCopyPer];
+    double pb[CP], lt[CP], cc[CP];
 #pragma unroll
-    for (int k = 0; k < kCopyPer; ++k) {
+    for (int k = 0; k < CP; ++k) {
       pb[k] = ld_off(in.phi_b + off, src[k] * 8u);
       lt[k] = ld_off(in.log10_tau + off, src[k] * 8u);
       cc[k] = ld_off(in.c + off, src[k] * 8u);
     }
 #pragma unroll
-    for (int k = 0; k < kCopyPer; ++k)
+    for (int k = 0; k < CP; ++k)
       if (ok[k]) {
         st_off(out.phi_b + off, dst[k] * 8u, pb[k]);
         st_off(out.log10_tau + off, dst[k] * 8u, lt[k]);
         st_off(out.c + off, dst[k] * 8u, cc[k]);
       }
   }
-  // layer rows of one or two fields, one row of each at a time (more loads in flight
-  // cost the registers of a third workgroup per CU)
+  // layer rows of one or two fields, RB rows of each per batch of loads (with four members
+  // per thread more loads in flight would cost the registers of a third workgroup per CU;
+  // with one, a sounding's copy is a chain of load round trips that batches shorten)
   auto rows_of = [&](const double *ia, const double *ib, double *oa, double *ob, int rows) {
-    for (int r = 0; r < rows; ++r) {
-      double v[2][kCopyPer];
+    for (int r0 = 0; r0 < rows; r0 += RB) {
+      double v[RB][2][CP];
 #pragma unroll
-      for (int k = 0; k < kCopyPer; ++k) {
-        v[0][k] = ld_off(ia + r * Si + off, src[k] * 8u);
-        v[1][k] = ib ? ld_off(ib + r * Si + off, src[k] * 8u) : 0.0;
+      for (int b = 0; b < RB; ++b) {
+        const int r = r0 + b;
+#pragma unroll
+        for (int k = 0; k < CP; ++k) {
+          v[b][0][k] = r < rows ? ld_off(ia + r * Si + off, src[k] * 8u) : 0.0;
+          v[b][1][k] = ib && r < rows ? ld_off(ib + r * Si + off, src[k] * 8u) : 0.0;
+        }
       }
 #pragma unroll
-      for (int k = 0; k < kCopyPer; ++k)
-        if (ok[k]) {
-          st_off(oa + r * So + off, dst[k] * 8u, v[0][k]);
-          if (ob) st_off(ob + r * So + off, dst[k] * 8u, v[1][k]);
-        }
+      for (int b = 0; b < RB; ++b) {
+        const int r = r0 + b;
+        if (r >= rows) continue;
+#pragma unroll
+        for (int k = 0; k < CP; ++k)
+          if (ok[k]) {
+            st_off(oa + r * So + off, dst[k] * 8u, v[b][0][k]);
+            if (ob) st_off(ob + r * So + off, dst[k] * 8u, v[b][1][k]);
+          }
+      }
     }
   };
   rows_of(in.phi, in.z_cond, out.phi, out.z_cond, rows_c);
@@ -677,6 +689,9 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
                                                                        int32_t *active, int32_t *anc, int *flags,
                                                                        const double *exp2t) {
   constexpr bool LARGE = KIND == 2;
+  // the copy: one member per thread and 8 rows per batch of loads for at most kRwThreads
+  // members (KIND 0), else four members per thread, one row per batch
+  constexpr int kCP = KIND == 0 ? 1 : kCopyPer, kRB = KIND == 0 ? 8 : 1;
   using SM = typename std::conditional<LARGE, RwSharedLarge, RwShared>::type;
   constexpr int NMAX = LARGE ? kMaxPerSoundingLarge : kMaxPerSounding;
   __shared__ SM sm;
@@ -693,8 +708,8 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
   if (!(g0 < 1.0)) {
     for (int i = tid; i < N; i += kRwThreads) sm.v.anc_l[i] = (int16_t)i;
     __syncthreads();
-    for (int first = 0; first < N; first += kCopyPer * kRwThreads)
-      copy_resampled(sm, in, ll_in, out, ll_out, anc, off, N, rows_c, rows_m, rows_zm, first);
+    for (int first = 0; first < N; first += kCP * kRwThreads)
+      copy_resampled<kCP, kRB>(sm, in, ll_in, out, ll_out, anc, off, N, rows_c, rows_m, rows_zm, first);
     if (tid == 0 && active) active[s] = 0;
     return;
   }
@@ -909,8 +924,8 @@ __global__ __launch_bounds__(kRwThreads) void reweight_resample_kernel(SmcShape 
   }
   __syncthreads();
   // the resampled population, in particle order (coalesced writes)
-  for (int first = 0; first < N; first += kCopyPer * kRwThreads)
-    copy_resampled(sm, in, ll_in, out, ll_out, anc, off, N, rows_c, rows_m, rows_zm, first);
+  for (int first = 0; first < N; first += kCP * kRwThreads)
+    copy_resampled<kCP, kRB>(sm, in, ll_in, out, ll_out, anc, off, N, rows_c, rows_m, rows_zm, first);
   if (tid == 0) {
     gamma[s] = full ? 1.0 : g0 + dg;
     if (active) active[s] = 1;
