@@ -1898,6 +1898,21 @@ __device__ __forceinline__ void propose_particle(int64_t i, const SmcShape &sh, 
   // wave runs the branches of all its lanes' move types one after another, and the
   // logarithm and cosine are its longest chain)
   const double nz = normal0(u2, u3);
+  // the random-walk move's factor column and scale, requested before the branches (their
+  // loads are in flight while the wave runs the other move types' branches)
+  const double *Fr = nullptr;
+  double rw_scale = 0.0, f0 = 0.0, fa = 0.0, fb = 0.0;
+  if (t == RJSMC_MOVE_WITHIN_RW) {
+    const int d = 3 + 2 * k + 2 * l;
+    int r = (int)(u1 * (double)d);
+    r = r > d - 1 ? d - 1 : r;
+    const int mdl = k * (km + 1) + l;
+    Fr = a.factors + ((snd * sh.n_models + mdl) * (int64_t)sh.dmax + r) * sh.dmax;
+    rw_scale = a.rw_scale_dev ? a.rw_scale_dev[snd] : a.rw_scale;
+    f0 = Fr[0];
+    fa = Fr[d - 2];
+    fb = Fr[d - 1];
+  }
   if (lq) lq[i] = 0.0;
   if (ZCA && a.zca_birth && jump) {
     const bool birth = t == RJSMC_MOVE_SIGMA_BIRTH || t == RJSMC_MOVE_M_BIRTH;
@@ -1980,15 +1995,9 @@ __device__ __forceinline__ void propose_particle(int64_t i, const SmcShape &sh, 
       }
     }
   } else if (t == RJSMC_MOVE_WITHIN_RW) {
-    const int d = 3 + 2 * k + 2 * l;
-    int r = (int)(u1 * (double)d);
-    r = r > d - 1 ? d - 1 : r;
-    const int mdl = k * (km + 1) + l;
-    const double *Fr = a.factors + ((snd * sh.n_models + mdl) * (int64_t)sh.dmax + r) * sh.dmax;
-    const double step = (a.rw_scale_dev ? a.rw_scale_dev[snd] : a.rw_scale) * nz;
+    const double step = rw_scale * nz;
     // theta' = theta + step F[:, r] in parameter-vector order (phi_b, phi, z_cond, m,
-    // z_charg, log10 tau, c); the entries are loaded together, not one per update
-    const double f0 = Fr[0], fa = Fr[d - 2], fb = Fr[d - 1];
+    // z_charg, log10 tau, c); the layer entries are loaded together, not one per update
     madd_rows2(ph, zc, Fr + 1, Fr + 1 + k, k, step);
     madd_rows2(mm, zm, Fr + 1 + 2 * k, Fr + 1 + 2 * k + l, l, step);
     phb = madd_rn(phb, step, f0);
