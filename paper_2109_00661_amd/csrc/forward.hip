@@ -11,6 +11,9 @@
 // shared tables in LDS its waves run independently (wave-level syncs only), so a
 // particle with few layers does not wait for a deeper neighbour.  The kernel is bound
 // by FP64 (or FP32) vector ALU work: ~24,000 layer steps per particle for 5 layers.
+// Small populations can take the spread evaluation instead (spread_terms_kernel and
+// spread_finish_kernel below): the reflection terms of all particles dealt over every
+// compute unit in ranges of equal work, then summed in the same order.
 #include <hip/hip_runtime.h>
 
 #include "cplx.h"
@@ -261,9 +264,9 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
 // grid with one workgroup per compute unit.  A deep particle's units so spread over more
 // compute units than a shallow one's.  A workgroup merges the few particles of its range
 // (as many as fit a pool of kSpreadPool layer tables, at most kSpreadStage at a time) and
-// builds their wavenumber tables in LDS together; then its
-// waves claim the range's units one at a time from an LDS counter, so that every SIMD
-// stays busy until the range is done.  spread_terms_kernel writes the terms to rim in
+// builds their wavenumber tables in LDS together; then its waves claim the range's units
+// one at a time from an LDS counter, so that every SIMD stays busy until the range is
+// done.  spread_terms_kernel writes the terms to rim in
 // [slot][q][s][lane] order; spread_finish_kernel adds them in the order of forward_kernel
 // and applies the gates and the likelihood, so the results are the same bits.
 constexpr int kSpreadWaves = 16;                         // waves per workgroup
@@ -282,8 +285,6 @@ __device__ __forceinline__ int spread_weight(const DevParticles &p, int64_t i, i
   cap = cap < 1 ? 1 : (cap > kMaxLayers ? kMaxLayers : cap);
   return cap + 1;
 }
-
-
 
 // Dynamic LDS of spread_terms_kernel: the staged particles' k2 and dk2 tables, each
 // particle's [n_freq][capacity] behind the previous one's.
