@@ -4,8 +4,8 @@
 // forward kernel, and every (frequency, abscissa) pair visited once.  Per pair the lane
 // runs the projective reflection recursion bottom-up, keeping the state (N_l, D_l) of
 // every interface in a per-lane array held in registers (the layer loops unrolled over
-// the instantiation's capacity: 4, 8, 12 or 16 merged layers; at 16 with AGPRs and one
-// wave per SIMD); the same recursion gives Im r_TE for the Hankel sum.
+// the instantiation's capacity: 4, 8, 12 or 16 merged layers; at 12 and 16 a few values
+// spill at two waves per SIMD); the same recursion gives Im r_TE for the Hankel sum.
 // It then sweeps top-down through the surface and every interface, propagating the
 // adjoint of c_k Im r (the reverse sweep is linear in its seed, so the filter coefficient
 // alone seeds it) and accumulating, per lane and frequency, the complex adjoints of the
@@ -58,8 +58,8 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
                                              const cplx<double> *phase, const double *e2, double &imr) {
   const double lam2 = lam * lam;
   // The layer loops are unrolled over LMAX with a wave-uniform guard, so the stored
-  // states, G and H stay in registers (at 16 layers with AGPRs as well, one wave per SIMD:
-  // still faster than keeping them in private memory with two).
+  // states, G and H stay in registers (at 12 and 16 layers some of them spill at two
+  // waves per SIMD: still faster than indexing them in private memory).
   constexpr int NI = LMAX - 1;           // interfaces below the surface
   cplx<double> Ns[NI], Ds[NI];           // projective reflection state below interface l
   auto u_of = [&](int l) { return csqrt_fast(cplx<double>{lam2 + k2[l].re, k2[l].im}); };
@@ -184,10 +184,11 @@ struct AdjShared1 {
 // first is NULL) up to *last (device counters of the capacity sort); otherwise slot j is
 // particle j (workgroups renumbered XCD-contiguous).
 template <int LMAX>
-// The 12-layer instantiation is held to two waves per SIMD (a few registers spill to
-// private memory; 3% faster than one wave per SIMD without spills); the 16-layer one
-// would spill far more and keeps one.
-__global__ __launch_bounds__(kWave * kWavesA) __attribute__((amdgpu_waves_per_eu(LMAX == 12 ? 2 : 1))) void loglik_grad1_kernel(DevSystem s, DevParticles p, int kc, int km,
+// The 12- and 16-layer instantiations are held to two waves per SIMD: some registers
+// spill to private memory (132 and 372 bytes per lane), and both still run faster than at
+// one wave per SIMD without spills (3% and 1.8% of the whole launch).  The 8-layer one
+// fits two waves without spills; held to three (320 bytes of spills) it was 5% slower.
+__global__ __launch_bounds__(kWave * kWavesA) __attribute__((amdgpu_waves_per_eu(LMAX >= 12 ? 2 : 1))) void loglik_grad1_kernel(DevSystem s, DevParticles p, int kc, int km,
                                                                         const double *y_obs, double *ll, DevGrad g,
                                                                         const int32_t *perm, const int *first,
                                                                         const int *last) {
