@@ -236,3 +236,28 @@ def test_spread_edge_cases(B, system, K_oracle, truth_data):
     big = W.decoupled_population(2049, 7, 4, seed=34, min_sep=1.0)
     same(W.take(big, range(2048)))
     same(big)
+
+
+def test_spread_merged_layout_and_no_chargeability(B, truth_data):
+    """The spread evaluation on merged-layout particles of mixed depth, and in a context
+    without chargeability interfaces: bit-identical to the default shape."""
+    d = _data(B, truth_data)
+
+    def same(ctx, p):
+        dp = B.particles_to_device(p)
+        out = []
+        for shape in ((4, 0, 1), (16, 0, 0), (16, 1, 0)):
+            ctx.set_tuning(*shape)
+            out.append((ctx.forward(dp).cpu().numpy(), ctx.loglik(dp, d).cpu().numpy()))
+            ctx.check()
+        assert np.all(np.isfinite(out[0][1]))
+        for y, ll in out[1:]:
+            assert np.array_equal(y, out[0][0]) and np.array_equal(ll, out[0][1])
+
+    merged = W.merged_population(300, 5, seed=41, kc=4)
+    merged["kappa"][::3] = 0                              # half-spaces among five-layer models
+    merged["kappa"][1::3] = 2
+    same(B.Context(W.system(), precision="f64", max_particles=512), merged)
+    no_ip = W.decoupled_population(200, 6, 0, seed=42, min_sep=1.0)
+    no_ip["m"] = np.zeros((1, 200))                       # the ABI takes a non-null m array
+    same(B.Context(W.system(kmax_cond=6, kmax_charg=0), precision="f64", max_particles=512), no_ip)
