@@ -12,11 +12,13 @@
 // layer wavenumbers k2_l = i w mu0 sigma_hat_l and the adjoints of the thicknesses.  The
 // u_l and E_l of the recursion are recomputed in the sweep instead of stored.  Per
 // frequency these derivatives of Im H(w_j) are mapped through the Cole-Cole terms to a
-// slot vector over (log10 sigma_inf, m) of each merged layer, the thicknesses and
-// (log10 tau, c), parked in LDS; once the gates and the likelihood are formed, the
-// gradient is sum_j wbar_j u_j with wbar_j = d ll / d Im H(w_j) = sum_g K_gj d ll / d y_g,
-// and the merged-layer gradients are routed back to the particle's parameters through the
-// merge (an interface moves the thickness above and below it).
+// slot vector u_j over (log10 sigma_inf, m) of each merged layer, the thicknesses and
+// (log10 tau, c), kept in LDS (as they are, or folded into the gates' sums
+// V_g = sum_j K_gj u_j); once the gates and the likelihood are formed, the gradient is
+// sum_j wbar_j u_j = sum_g ybar_g V_g with ybar_g = d ll / d y_g and
+// wbar_j = sum_g K_gj ybar_g, and the merged-layer gradients are routed back to the
+// particle's parameters through the merge (an interface moves the thickness above and
+// below it).
 #include <hip/hip_runtime.h>
 
 #include "cplx.h"
@@ -41,6 +43,20 @@ __device__ __forceinline__ cplx<double> crcp_fast(cplx<double> b) {
 }
 __device__ __forceinline__ cplx<double> cdiv_fast(cplx<double> a, cplx<double> b) { return a * crcp_fast(b); }
 
+// u = sqrt(z), the principal root as csqrt_fast forms it, and hm = 1/(2|z|), so that
+// 1/(2u) = conj(u) hm (|u|^2 = |z|): the refined reciprocal square root of |z|^2 that
+// gives |z| gives hm as well.
+__device__ __forceinline__ cplx<double> csqrt_hm(cplx<double> z, double &hm) {
+  double mag;
+  sqrt_hrsqrt(z.re * z.re + z.im * z.im, mag, hm);
+  const double w = 0.5 * (mag + fabs(z.re));
+  double t, ht;
+  sqrt_hrsqrt(w, t, ht);
+  const double o = z.im * ht;   // Im z / (2 t)
+  const bool right = z.re >= 0.0;
+  return {right ? t : fabs(o), right ? o : copysign(t, z.im)};
+}
+
 // Adds the adjoints of one (lam, w) pair with seed wt (the weight of Im r) to
 // G[l] (d(wt r)/d k2_l) and H[l] (Im d(wt r)/d h_l).  The bottom-up pass is the forward's
 // projective recursion (step_up), keeping the state (N_l, D_l) of every interface; the
@@ -50,8 +66,11 @@ __device__ __forceinline__ cplx<double> cdiv_fast(cplx<double> a, cplx<double> b
 //   S~ = P~ a,  T~ = Q~ b,  D~ = S~ + T~,  N~ = (S~ - T~) E,  E~ = (S~ - T~) N,
 // with E = exp(h2 u) (h2 = -2 h): u~ += E~ h2 E and h~ = -2 u E~ E.  The seed is
 // N~ = wt / D, D~ = -N~ N / D at the surface, and u_l = sqrt(lam^2 + k2_l) gives
-// k2_l~ += u_l~ / (2 u_l).  One complex reciprocal per pair and one per layer; u_l and
-// E_l are recomputed in the top-down pass instead of stored.
+// k2_l~ += u_l~ / (2 u_l).  One complex reciprocal per pair, and 1/(2 u_l) per layer:
+// the 12- and 16-layer instantiations take it from the square root's own 1/(2|u_l|^2)
+// (two products; 3% faster there), the smaller ones form a complex reciprocal at the
+// point of use (one register pair fewer through the sweep keeps them within 256 VGPRs
+// unspilled).  u_l and E_l are recomputed in the top-down pass instead of stored.
 template <int LMAX>
 __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2, const double *h2v, int L,
                                              double wt, cplx<double> (&G)[LMAX], double (&H)[LMAX],
@@ -62,11 +81,16 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
   // waves per SIMD: still faster than indexing them in private memory).
   constexpr int NI = LMAX - 1;           // interfaces below the surface
   cplx<double> Ns[NI], Ds[NI];           // projective reflection state below interface l
+  constexpr bool kHm = LMAX >= 12;
   auto u_of = [&](int l) { return csqrt_fast(cplx<double>{lam2 + k2[l].re, k2[l].im}); };
-  auto half_rcp = [](cplx<double> u) { return crcp_fast(2.0 * u); };
+  auto u_hm = [&](int l, double &hm) { return csqrt_hm(cplx<double>{lam2 + k2[l].re, k2[l].im}, hm); };
+  auto half_rcp = [](cplx<double> u, double hm) {   // 1/(2u); hm is unused (dead) unless kHm
+    return kHm ? cplx<double>{u.re * hm, -u.im * hm} : crcp_fast(2.0 * u);
+  };
   if (L == 1) {
     // r = -k2_0 / (lam + u_0)^2
-    const cplx<double> u0 = u_of(0);
+    double hm0;
+    const cplx<double> u0 = u_hm(0, hm0);
     const cplx<double> s = {lam + u0.re, u0.im};
     const cplx<double> D = csq(s);
     const cplx<double> N = {-k2[0].re, -k2[0].im};
@@ -78,7 +102,7 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
     const cplx<double> r = N * iD;
     const cplx<double> Db = {-(Nb * r).re, -(Nb * r).im};
     const cplx<double> ub = Db * (2.0 * s);
-    G[0] = G[0] + (ub * half_rcp(u0) - Nb);
+    G[0] = G[0] + (ub * half_rcp(u0, hm0) - Nb);
     return;
   }
   // ---- bottom-up: the deepest interface, then step_up through every interface above
@@ -124,18 +148,20 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
     H[0] += -2.0 * (EbE * u0).im;
   }
   ua = u0;
+  double hma = 0.5 * fast_rcp(u0.re * u0.re + u0.im * u0.im);   // 1/(2|u_l|^2) (kHm)
 #pragma unroll
   for (int l = 0; l < NI - 1; ++l) {
     if (l < L - 2) {
       // the step that made state l from state l + 1: a = u_l, b = u_{l+1}, E_{l+1}
-      const cplx<double> ub = u_of(l + 1);
+      double hmb;
+      const cplx<double> ub = u_hm(l + 1, hmb);
       const double hh = h2v[l + 1];
       const cplx<double> E = cexp_tab(cplx<double>{hh * ub.re, hh * ub.im}, phase, e2);
       const cplx<double> NE = Ns[l + 1] * E;
       const cplx<double> S = Ds[l + 1] + NE, T = Ds[l + 1] - NE;
       const cplx<double> Pb = Nb + Db, Qb = Db - Nb;
       uab = uab + Pb * S;
-      G[l] = G[l] + uab * half_rcp(ua);                            // u_l complete
+      G[l] = G[l] + uab * half_rcp(ua, hma);                       // u_l complete
       const cplx<double> Sb = Pb * ua, Tb = Qb * ub;
       Db = Sb + Tb;
       const cplx<double> NEb = Sb - Tb;
@@ -144,12 +170,14 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
       uab = Qb * T + hh * EbE;
       H[l + 1] += -2.0 * (EbE * ub).im;
       ua = ub;
+      hma = hmb;
     }
   }
   // the deepest interface: N = k2_{L-2} - k2_{L-1}, D = (u_{L-2} + u_{L-1})^2
-  const cplx<double> ul = u_of(L - 1);
+  double hml;
+  const cplx<double> ul = u_hm(L - 1, hml);
   const cplx<double> sb = Db * (2.0 * (ua + ul));
-  const cplx<double> g0 = Nb + (uab + sb) * half_rcp(ua), g1 = sb * half_rcp(ul) - Nb;
+  const cplx<double> g0 = Nb + (uab + sb) * half_rcp(ua, hma), g1 = sb * half_rcp(ul, hml) - Nb;
 #pragma unroll
   for (int l = 0; l < NI; ++l)       // compile-time indices keep G in registers
     if (l == L - 2) {
@@ -162,19 +190,24 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
 // pair's bottom-up recursion already gives Im r_TE, so every pair is visited once: the
 // sweep is seeded with the filter coefficient c_k alone, giving per frequency the
 // derivatives of Im H(w_j) with respect to the layer wavenumbers and thicknesses; these
-// are mapped through the Cole-Cole terms to a per-frequency slot vector u_j (LDS), and
+// are mapped through the Cole-Cole terms to a per-frequency slot vector u_j, and
 // Im H(w_j) is summed on the way.  Once the likelihood is known, the gradient is
-// sum_j wbar_j u_j with wbar_j = d ll / d Im H(w_j).  K is read from global memory (L2).
+// sum_j wbar_j u_j with wbar_j = d ll / d Im H(w_j) = sum_g K_gj ybar_g.  The 4- and
+// 8-layer instantiations park every u_j in LDS and form wbar; the 12- and 16-layer ones
+// fold each round's eight u_j into V_g = sum_j K_gj u_j (the gradient is then
+// sum_g ybar_g V_g), which for fewer gates than frequencies takes less LDS: with 20 gates
+// and 40 frequencies a 16-layer workgroup needs 39 KB instead of 52, so four of them (two
+// waves per SIMD) fit a compute unit's 160 KB instead of three.  K is read from global
+// memory (L2; the fold's K_gj are wave-uniform).
 template <int LMAX>
 struct AdjShared1 {
-  double lam[kMaxHankel], ck[kMaxHankel], omega[kMaxFreq], eps2[kMaxGate];
+  double omega[kMaxFreq], eps2[kMaxGate];
   cplx<double> phase[kPhaseN];
   double exp2t[kExp2N];
   LayerStack stack[kWavesA];
-  double wbar[kWavesA][kMaxFreq];
-  double imh[kWavesA][kMaxFreq];
+  double imh[kWavesA][kMaxFreq];   // Im H(w_j), then wbar_j (4 and 8 layers)
   double ybar[kWavesA][kMaxGate];
-  cplx<double> k2[kWavesA][8][kMaxLayers];
+  cplx<double> k2[kWavesA][8][LMAX];
   double h2[kWavesA][kMaxLayers];
   double gl[kWavesA][3 * LMAX + 2];
   double ll[kWavesA];
@@ -185,17 +218,22 @@ struct AdjShared1 {
 // particle j (workgroups renumbered XCD-contiguous).
 template <int LMAX>
 // The 12- and 16-layer instantiations are held to two waves per SIMD: some registers
-// spill to private memory (132 and 372 bytes per lane), and both still run faster than at
-// one wave per SIMD without spills (3% and 1.8% of the whole launch).  The 8-layer one
-// fits two waves without spills; held to three (320 bytes of spills) it was 5% slower.
+// spill to private memory (176 and 400 bytes per lane), and both still run faster than at
+// one wave per SIMD without spills.  The 8-layer one fits two waves without spills
+// unconstrained; the same attribute on it (the allocation differs) was 6% slower, and
+// held to three waves per SIMD (320 bytes of spills) 5% slower.
 __global__ __launch_bounds__(kWave * kWavesA) __attribute__((amdgpu_waves_per_eu(LMAX >= 12 ? 2 : 1))) void loglik_grad1_kernel(DevSystem s, DevParticles p, int kc, int km,
                                                                         const double *y_obs, double *ll, DevGrad g,
                                                                         const int32_t *perm, const int *first,
                                                                         const int *last) {
   __shared__ AdjShared1<LMAX> sm;
   constexpr int NS = 3 * LMAX + 2;
-  extern __shared__ double su[];   // [kWavesA][n_freq][NS] per-frequency slot vectors, dynamic
+  constexpr bool kByGate = LMAX >= 12;
+  // dynamic: the filter's abscissae and coefficients [2][n_hankel_pad], then per wave
+  // u_j [n_freq][NS] (4 and 8 layers) or V [n_gate][NS] and the round's u_j [8][NS]
+  extern __shared__ double su[];
   const int nf = s.n_freq, ng = s.n_gate, nhp = s.n_hankel_pad;
+  double *lam_s = su, *ck_s = su + nhp;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   int64_t i;
   if (perm) {
@@ -209,8 +247,8 @@ __global__ __launch_bounds__(kWave * kWavesA) __attribute__((amdgpu_waves_per_eu
   const bool skip = valid && p.mask && p.mask[i] != p.mask_value;   // left untouched
   if (!__syncthreads_or(valid && !skip)) return;
   for (int t = threadIdx.x; t < nhp; t += blockDim.x) {
-    sm.lam[t] = s.lam[t];
-    sm.ck[t] = s.ck[t];
+    lam_s[t] = s.lam[t];
+    ck_s[t] = s.ck[t];
   }
   for (int t = threadIdx.x; t < nf; t += blockDim.x) sm.omega[t] = s.omega[t];
   for (int t = threadIdx.x; t < ng; t += blockDim.x) sm.eps2[t] = s.eps_an2[t];
@@ -218,7 +256,12 @@ __global__ __launch_bounds__(kWave * kWavesA) __attribute__((amdgpu_waves_per_eu
     sm.phase[t] = cplx<double>{s.phase[2 * t], s.phase[2 * t + 1]};
   for (int t = threadIdx.x; t < kExp2N; t += blockDim.x) sm.exp2t[t] = s.exp2t[t];
   LayerStack *st = &sm.stack[wave];
-  double *uw = su + (size_t)wave * nf * NS;
+  double *uw = su + 2 * (size_t)nhp + (size_t)wave * (kByGate ? ng + 8 : nf) * NS;
+  double *vw = uw;   // V (kByGate)
+  if (kByGate) {
+    uw += (size_t)ng * NS;
+    for (int t = lane; t < ng * NS; t += kWave) vw[t] = 0.0;
+  }
   __syncthreads();
   const int L = merge_particle(p, i, valid && !skip, kc, km, LMAX, st, s.flags);
   double c = 0.0, log_tau = 0.0, spc = 0.0, cpc = 1.0;
@@ -263,8 +306,8 @@ __global__ __launch_bounds__(kWave * kWavesA) __attribute__((amdgpu_waves_per_eu
       for (int sidx = 0; sidx < nhg; ++sidx) {
         const int k = gl + 8 * sidx;
         double imr;
-        pair_adjoint<LMAX>(sm.lam[k], sm.k2[wave][gw], sm.h2[wave], L, sm.ck[k], G, H, sm.phase, sm.exp2t, imr);
-        acc = __builtin_fma(sm.ck[k], imr, acc);
+        pair_adjoint<LMAX>(lam_s[k], sm.k2[wave][gw], sm.h2[wave], L, ck_s[k], G, H, sm.phase, sm.exp2t, imr);
+        acc = __builtin_fma(ck_s[k], imr, acc);
       }
       acc += __shfl_xor(acc, 1);
       acc += __shfl_xor(acc, 2);
@@ -284,7 +327,7 @@ __global__ __launch_bounds__(kWave * kWavesA) __attribute__((amdgpu_waves_per_eu
         // z = (i w tau)^c; slot vector [log10 sigma (LMAX)][m (LMAX)][thickness (LMAX)][tau][c]
         const cplx<double> iwm = {0.0, w * kMu0A};
         cplx<double> Gq = {0.0, 0.0};
-        double *sl = uw + (size_t)jf * NS;
+        double *sl = uw + (size_t)(kByGate ? gw : jf) * NS;
 #pragma unroll
         for (int l = 0; l < LMAX; ++l) {
           double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -306,8 +349,27 @@ __global__ __launch_bounds__(kWave * kWavesA) __attribute__((amdgpu_waves_per_eu
       }
     }
     wave_lds_sync();
+    if constexpr (kByGate) {
+      // fold the round's u_j into V: lane t owns slot t of every gate's row; the round's
+      // frequencies are added in order
+      if (L > 0 && lane < NS) {
+        const int nj = min(8, nf - 8 * q);
+        double uv[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) uv[r] = r < nj ? uw[r * NS + lane] : 0.0;
+        for (int gg = 0; gg < ng; ++gg) {
+          const double *kr = s.K + (size_t)gg * nf + 8 * q;
+          double a = vw[gg * NS + lane];
+#pragma unroll
+          for (int r = 0; r < 8; ++r)
+            if (r < nj) a = fma(kr[r], uv[r], a);
+          vw[gg * NS + lane] = a;
+        }
+      }
+      wave_lds_sync();
+    }
   }
-  // gates, log-likelihood and wbar_j = sum_g K_gj d ll / d y_g
+  // gates, the log-likelihood and ybar_g = d ll / d y_g
   if (L > 0) {
     double term = 0.0;
     if (lane < ng) {
@@ -330,17 +392,28 @@ __global__ __launch_bounds__(kWave * kWavesA) __attribute__((amdgpu_waves_per_eu
     if (lane == 0) sm.ll[wave] = -0.5 * term;
   }
   wave_lds_sync();
-  if (L > 0 && lane < nf) {
-    double acc = 0.0;
-    for (int gg = 0; gg < ng; ++gg) acc += s.K[gg * nf + lane] * sm.ybar[wave][gg];
-    sm.wbar[wave][lane] = acc;
-  }
-  wave_lds_sync();
-  if (L > 0) {
-    for (int t = lane; t < NS; t += kWave) {
+  if constexpr (kByGate) {
+    if (L > 0) {
+      for (int t = lane; t < NS; t += kWave) {
+        double acc = 0.0;
+        for (int gg = 0; gg < ng; ++gg) acc += sm.ybar[wave][gg] * vw[(size_t)gg * NS + t];
+        sm.gl[wave][t] = acc;
+      }
+    }
+  } else {
+    // wbar_j overwrites Im H(w_j), which every gate has read before the last sync
+    if (L > 0 && lane < nf) {
       double acc = 0.0;
-      for (int j = 0; j < nf; ++j) acc += sm.wbar[wave][j] * uw[(size_t)j * NS + t];
-      sm.gl[wave][t] = acc;
+      for (int gg = 0; gg < ng; ++gg) acc += s.K[gg * nf + lane] * sm.ybar[wave][gg];
+      sm.imh[wave][lane] = acc;
+    }
+    wave_lds_sync();
+    if (L > 0) {
+      for (int t = lane; t < NS; t += kWave) {
+        double acc = 0.0;
+        for (int j = 0; j < nf; ++j) acc += sm.imh[wave][j] * uw[(size_t)j * NS + t];
+        sm.gl[wave][t] = acc;
+      }
     }
   }
   wave_lds_sync();
@@ -391,7 +464,8 @@ static hipError_t launch_g1(const DevSystem &s, const DevParticles &p, int kc, i
                             const int *last) {
   const int64_t blocks = (p.n + kWavesA - 1) / kWavesA;   // every slot range fits
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  const size_t dyn = sizeof(double) * kWavesA * s.n_freq * (3 * LMAX + 2);
+  const size_t per_wave = LMAX >= 12 ? s.n_gate + 8 : s.n_freq;   // slot-vector rows
+  const size_t dyn = sizeof(double) * (2 * (size_t)s.n_hankel_pad + kWavesA * per_wave * (3 * LMAX + 2));
   hipLaunchKernelGGL((loglik_grad1_kernel<LMAX>), dim3((unsigned)blocks), dim3(kWave * kWavesA), dyn, stream, s, p,
                      kc, km, y_obs, ll, g, perm, first, last);
   return hipGetLastError();

@@ -32,6 +32,8 @@ def B():
 # last-bit difference of Im H by up to ~1e4 for particles that fit the data very badly
 # (|ll| ~ 1e12): measured up to 1.8e-11 relative; each is within ~1e-12 of the oracle.
 LL_CONSISTENCY = 1e-10
+# two instantiations whose final contraction sums in a different order
+GRAD_BUCKET_RTOL = 1e-10
 
 
 def _grad_gpu(B, ctx, p, d):
@@ -160,8 +162,12 @@ def test_grad_full_size_sampled(B, K_oracle, truth_data):
 def test_grad_bucketed_equals_single_launch(B, truth_data):
     """A context with a workspace evaluates particles of up to 8 merged layers with the
     8-layer instantiation, of 9 to 12 with the 12-layer one and deeper ones with the
-    16-layer one; without a workspace one 16-layer launch covers all.  Same values to
-    rounding (the instantiations run the same arithmetic in differently unrolled code)."""
+    16-layer one; without a workspace one 16-layer launch covers all.  The deep particles
+    run the same code either way (identical results); the 12- and 16-layer instantiations
+    run the same arithmetic in differently unrolled code (same values to rounding); the
+    8-layer one keeps every frequency's slot vector and forms 1/(2u) by a complex
+    reciprocal, where the 16-layer one folds the slot vectors into the gates' sums and
+    takes 1/(2u) from the square root, so its gradients differ in summation order."""
     system = W.system(kmax_cond=7, kmax_charg=7)
     p = W.prior_population(9000, 7, 7, seed=31)
     res = []
@@ -175,8 +181,16 @@ def test_grad_bucketed_equals_single_launch(B, truth_data):
     assert (cap > 12).any() and ((cap > 8) & (cap <= 12)).any() and (cap <= 8).any()
     assert np.array_equal(ll1[cap > 12], ll0[cap > 12])
     scale = np.max([np.abs(g0[k]).max(axis=0) if g0[k].ndim == 2 else np.abs(g0[k]) for k in FKEYS], axis=0)
+    deep, mid, shallow = cap > 12, (cap > 8) & (cap <= 12), cap <= 8
     for k in FKEYS:
-        assert np.all(np.abs(g1[k] - g0[k]) <= 1e-12 * scale), k
+        assert np.array_equal(g1[k][..., deep], g0[k][..., deep]), k
+    rel = {k: np.abs(g1[k] - g0[k]) / scale for k in FKEYS}
+    r_mid = max(float(rel[k][..., mid].max()) for k in FKEYS)
+    r_shallow = max(float(rel[k][..., shallow].max()) for k in FKEYS)
+    print("bucketed vs single launch, relative to the largest component: 9-12 layers %.2e, "
+          "<= 8 layers %.2e" % (r_mid, r_shallow))
+    assert r_mid <= 1e-12
+    assert r_shallow <= GRAD_BUCKET_RTOL
 
 
 def test_grad_against_central_differences(B, system, truth_data):
