@@ -45,17 +45,19 @@ __device__ __forceinline__ cplx<T> crcp(cplx<T> b) {
   return {b.re * inv, -b.im * inv};
 }
 
-// sqrt(x) and 1/(2 sqrt(x)) for x > 0 (finite, normal): hardware reciprocal-square-root
-// estimate refined by two Goldschmidt steps (relative error a few ulp).
+// sqrt(x) and 1/(2 sqrt(x)) for x > 0 (finite, normal) from the hardware reciprocal-
+// square-root estimate y = (1 + e)/sqrt(x) (|e| < 2^-24): with g = x y, h = y/2 and
+// r = 1/2 - g h, 1 + e = (1 - 2r)^(1/2), so sqrt(x) = g (1 - 2r)^(-1/2) and
+// 1/(2 sqrt(x)) = h (1 - 2r)^(-1/2), the factor taken to second order in r,
+// 1 + r + 3r^2/2 (one Goldschmidt step of third order; the remainder 5r^3/2 is below
+// 2^-70): relative error within about an ulp.
 __device__ __forceinline__ void sqrt_hrsqrt(double x, double &sq, double &hrs) {
   const double y = __builtin_amdgcn_rsq(x);
-  double g = x * y, h = 0.5 * y;
-  double r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  h = fma(h, r, h);
-  r = fma(-g, h, 0.5);
-  sq = fma(g, r, g);
-  hrs = fma(h, r, h);
+  const double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  const double q = r * fma(r, 1.5, 1.0);
+  sq = fma(g, q, g);
+  hrs = fma(h, q, h);
 }
 __device__ __forceinline__ void sqrt_hrsqrt(float x, float &sq, float &hrs) {
   // the estimate is good to ~2^-23; one Goldschmidt step brings both to about an ulp
