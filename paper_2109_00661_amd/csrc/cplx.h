@@ -138,8 +138,23 @@ constexpr double kInvFact[7] = {1.0, 1.0, 1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0, 1.0 
 // j are rounded by adding 1.5 2^52, which leaves them as integers in the low word.
 // Re z < -1000 gives 0; a NaN real part is clamped too (the recursion still propagates
 // it through u), a NaN imaginary part gives NaN.
+// 1/6 and 1/24, the two constants the polynomials below share.  Each of three polynomial
+// steps has two constants that are not inline operands, and an instruction takes at most
+// one from a scalar register, so the other is copied into a vector register at every
+// evaluation unless it already lives in one: exp_consts() puts both there, opaque to the
+// compiler, so that a loop of evaluations keeps them (two registers pairs) instead.
+struct ExpConsts {
+  double c6, c24;
+};
+__device__ __forceinline__ ExpConsts exp_consts() {
+  double c6 = detail::kInvFact[3], c24 = detail::kInvFact[4];
+  asm volatile("" : "+v"(c6), "+v"(c24));
+  return {c6, c24};
+}
+
 __device__ __forceinline__ cplx<double> cexp_tab(cplx<double> z, const cplx<double> *phase,
-                                                 const double *e2) {
+                                                 const double *e2,
+                                                 ExpConsts kc = {detail::kInvFact[3], detail::kInvFact[4]}) {
   using namespace detail;
   constexpr double kRound = 0x1.8p52;
   const double x = fmax(z.re, -1000.0);
@@ -147,7 +162,7 @@ __device__ __forceinline__ cplx<double> cexp_tab(cplx<double> z, const cplx<doub
   const int ki = __double2loint(kr);
   const double kx = kr - kRound;
   const double r = fma(kx, -(kLn2Hi / 256.0), x);
-  double p = fma(r, kInvFact[4], kInvFact[3]);
+  double p = fma(r, kInvFact[4], kc.c6);
   p = fma(p, r, kInvFact[2]);
   p = fma(p, r, 1.0);
   p = fma(p, r, 1.0);
@@ -158,8 +173,8 @@ __device__ __forceinline__ cplx<double> cexp_tab(cplx<double> z, const cplx<doub
   const double jy = jr - kRound;
   const double d = fma(jy, -(kPio2A / 64.0), z.im);
   const double x2 = -(d * d);
-  const double sd = fma(d * x2, fma(x2, kInvFact[5], kInvFact[3]), d);
-  double C = fma(x2, kInvFact[6], kInvFact[4]);
+  const double sd = fma(d * x2, fma(x2, kInvFact[5], kc.c6), d);
+  double C = fma(x2, kInvFact[6], kc.c24);
   C = fma(C, x2, kInvFact[2]);
   const double cd = fma(x2, C, 1.0);
   const cplx<double> t = phase[ji & 255];

@@ -178,7 +178,9 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
   for (int t = threadIdx.x; t < kExp2N; t += blockDim.x) s_exp2[t] = s.exp2t[t];
   LayerStack *st = &s_stack[wave];
   __syncthreads();
-  const int L = merge_particle(p, i, valid && !skip, kc, km, LMAX, st, s.flags);
+  // the wave's particle is one, so its merged-layer count is wave-uniform: held in a
+  // scalar register, the layer loops count in scalar instructions
+  const int L = __builtin_amdgcn_readfirstlane(merge_particle(p, i, valid && !skip, kc, km, LMAX, st, s.flags));
 
   ColeCole cc{0.0, 0.0, 0.0, 1.0};
   if (L > 0) {
@@ -188,6 +190,7 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
   const int gl = lane & 7, gw = lane >> 3;
   const int nhg = nhp >> 3;
   const int nq = (nf + 7) >> 3;
+  const ExpConsts ek = exp_consts();
   // With more waves per particle than frequency chunks, each chunk's abscissa groups are
   // split into A parts (work unit = chunk x part); the parts store their reflection
   // terms and the particle's first wave adds them in the order of the A == 1 path, so
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
       for (int sidx = 0; sidx < nhg; ++sidx) {
         const int k = gl + 8 * sidx;
         const T rim = reflection_im<T>(to<T>(s_lam[k]), s_k2[wave][gw], s_dk2[wave][gw], s_h2[wave], L,
-                                         s_phase, s_exp2);
+                                         s_phase, s_exp2, ek);
         acc = __builtin_fma(s_ck[k], static_cast<double>(rim), acc);
       }
       // reduce over the 8 abscissa groups (lane bits 0..2); all 8 lanes of a group
@@ -223,7 +226,7 @@ __global__ __launch_bounds__(kWave * WPB * P, 16 / (WPB * P) > 0 ? 16 / (WPB * P
         const int k = gl + 8 * sidx;
         s_rim[jf * nhp + k] = static_cast<double>(reflection_im<T>(to<T>(s_lam[k]), s_k2[wave][gw],
                                                                    s_dk2[wave][gw], s_h2[wave], L, s_phase,
-                                                                   s_exp2));
+                                                                   s_exp2, ek));
       }
     }
     wave_lds_sync();
@@ -479,6 +482,7 @@ __global__ __launch_bounds__(kWave * kSpreadWaves, 1) void spread_terms_kernel(
     __syncthreads();
     // the staged units, claimed one at a time by whichever wave is free
     const int nu = uni(s_cu[np]);
+    const ExpConsts ek = exp_consts();
     for (;;) {
       int u = 0;
       if (lane == 0) u = atomicAdd(&s_next, 1);
@@ -495,7 +499,7 @@ __global__ __launch_bounds__(kWave * kSpreadWaves, 1) void spread_terms_kernel(
       double v = 0.0;
       if (jf < nf)
         v = static_cast<double>(reflection_im<T>(to<T>(s_lam[gl + 8 * sidx]), s_k2 + o, s_dk2 + o, s_h2[sp], L,
-                                                 s_phase, s_exp2));
+                                                 s_phase, s_exp2, ek));
       rim[(((int64_t)uni(s_sl[sp]) * nq + q) * nhg + sidx) * kWave + lane] = v;
     }
     __syncthreads();   // every claimed unit is done before the set is restaged

@@ -67,10 +67,10 @@ __device__ __forceinline__ void step_ratio(cplx<T> &N, cplx<T> &D, cplx<T> dk, c
 
 // Propagation factor exp(-2 h u): table-assisted in FP64, polynomial in FP32.
 __device__ __forceinline__ cplx<double> prop_exp(cplx<double> z, const cplx<double> *phase,
-                                                 const double *e2) {
-  return cexp_tab(z, phase, e2);
+                                                 const double *e2, ExpConsts kc) {
+  return cexp_tab(z, phase, e2, kc);
 }
-__device__ __forceinline__ cplx<float> prop_exp(cplx<float> z, const cplx<double> *, const double *) {
+__device__ __forceinline__ cplx<float> prop_exp(cplx<float> z, const cplx<double> *, const double *, ExpConsts) {
   return cexp(z);
 }
 
@@ -78,10 +78,11 @@ __device__ __forceinline__ cplx<float> prop_exp(cplx<float> z, const cplx<double
 // numerators dk2[l] = k2[l] - k2[l+1] (l < L-1) and h2[l] = -2 h_l (l < L-1).  The layer
 // loop is a runtime loop (unrolled by two, which removes the register rotation of the
 // carried u and stays within 128 VGPRs) whose carried state is N, D and u_{l+1}.  phase / e2 are the
-// LDS copies of the exponential's tables (used in FP64).
+// LDS copies of the exponential's tables and kc its polynomial constants from exp_consts()
+// (used in FP64).
 template <typename T>
 __device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const cplx<T> *dk2, const T *h2, int L,
-                                           const cplx<double> *phase, const double *e2) {
+                                           const cplx<double> *phase, const double *e2, ExpConsts kc) {
   constexpr bool kRatio = sizeof(T) == sizeof(float);   // FP32: cancellation-free steps
   const T lam2 = lam * lam;
   const cplx<T> kb = k2[L - 1];
@@ -103,7 +104,7 @@ __device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const cplx<
       const cplx<T> kl = k2[l];
       const cplx<T> u = csqrt_fast(cplx<T>{lam2 + kl.re, kl.im});
       const T hh = h2[l + 1];
-      const cplx<T> E = prop_exp(cplx<T>{hh * ub.re, hh * ub.im}, phase, e2);
+      const cplx<T> E = prop_exp(cplx<T>{hh * ub.re, hh * ub.im}, phase, e2, kc);
       if (kRatio)
         step_ratio(N, D, dk2[l], csq(u + ub), E);
       else
@@ -112,7 +113,7 @@ __device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const cplx<
       ub = u;
     }
     const T hh = h2[0];
-    const cplx<T> E0 = prop_exp(cplx<T>{hh * ub.re, hh * ub.im}, phase, e2);
+    const cplx<T> E0 = prop_exp(cplx<T>{hh * ub.re, hh * ub.im}, phase, e2, kc);
     if (kRatio)   // air interface: lam^2 - u_0^2 = -k2_0
       step_ratio(N, D, cplx<T>{-k2[0].re, -k2[0].im}, csq(cplx<T>{lam + ub.re, ub.im}), E0);
     else
