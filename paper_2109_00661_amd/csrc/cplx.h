@@ -46,17 +46,18 @@ __device__ __forceinline__ cplx<T> crcp(cplx<T> b) {
 }
 
 // sqrt(x) and 1/(2 sqrt(x)) for x > 0 (finite, normal) from the hardware reciprocal-
-// square-root estimate y = (1 + e)/sqrt(x) (|e| < 2^-24): with g = x y, h = y/2 and
-// r = 1/2 - g h, 1 + e = (1 - 2r)^(1/2), so sqrt(x) = g (1 - 2r)^(-1/2) and
-// 1/(2 sqrt(x)) = h (1 - 2r)^(-1/2), the factor taken to second order in r,
-// 1 + r + 3r^2/2 (one Goldschmidt step of third order; the remainder 5r^3/2 is below
-// 2^-70): relative error within about an ulp.
+// square-root estimate y = (1 + e)/sqrt(x) (|e| < 2^-24): with g = x y and
+// v = 1 - g y = 1 - (1 + e)^2, sqrt(x) = g (1 - v)^(-1/2) and 1/(2 sqrt(x)) =
+// (y/2) (1 - v)^(-1/2), the factor taken to second order in v, 1 + v/2 + 3v^2/8 (one
+// Goldschmidt step of third order; the remainder 5v^3/16 is below 2^-70): relative error
+// within about an ulp.  Without hrs (unused) it costs five operations besides the estimate.
 __device__ __forceinline__ void sqrt_hrsqrt(double x, double &sq, double &hrs) {
   const double y = __builtin_amdgcn_rsq(x);
-  const double g = x * y, h = 0.5 * y;
-  const double r = fma(-g, h, 0.5);
-  const double q = r * fma(r, 1.5, 1.0);
+  const double g = x * y;
+  const double v = fma(-g, y, 1.0);
+  const double q = v * fma(v, 0.375, 0.5);
   sq = fma(g, q, g);
+  const double h = 0.5 * y;
   hrs = fma(h, q, h);
 }
 __device__ __forceinline__ void sqrt_hrsqrt(float x, float &sq, float &hrs) {
@@ -90,9 +91,9 @@ __device__ __forceinline__ cplx<T> csqrt_fast(cplx<T> z) {
   const T w = T(0.5) * (mag + fabs(z.re));
   T t, ht;
   sqrt_hrsqrt(w, t, ht);
-  const T o = z.im * ht;   // Im z / (2 t)
+  const T oa = fabs(z.im) * ht;   // |Im z| / (2 t)
   const bool right = z.re >= T(0);
-  return {right ? t : fabs(o), right ? o : copysign(t, z.im)};
+  return {right ? t : oa, copysign(right ? oa : t, z.im)};
 }
 
 // Principal square root (Re >= 0), branch cut on the negative real axis.
