@@ -1032,13 +1032,23 @@ __device__ __forceinline__ double jacobi_entry(double cx, double sx, double cj, 
   return fma(cx, fma(cj, axj, sj * axy), sx * fma(cj, ayj, sj * ayy));
 }
 
+// 1/sqrt(x) for finite normal x > 0: the hardware estimate y and one third-order step,
+// y (1 - v)^(-1/2) ~ y (1 + v/2 + 3v^2/8) with v = 1 - x y^2 (remainder below 2^-70).
+__device__ __forceinline__ double rsqrt_fast(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double v = fma(-(x * y), y, 1.0);
+  return fma(y * v, fma(v, 0.375, 0.5), y);
+}
+
 // Rotation of the pair (p, q), p < q, from its 2x2 block: c, s with J[p][p] = J[q][q] = c,
 // J[p][q] = s = -J[q][p], and the rotated diagonal entries (identity if apq = 0).  The
 // angle phi is the smaller solution, t = tan phi the smaller root of t^2 + 2 theta t - 1 = 0
 // with theta = (aqq - app) / (2 apq).  With rho = 1 / sqrt((aqq - app)^2 + 4 apq^2),
 // cos 2phi = |aqq - app| rho and h = cos^2 phi = (1 + cos 2phi) / 2 lies in [1/2, 1], so
-// with q = 1 / sqrt(h): c = h q, |t| = |apq| rho / h = |apq| rho q^2, s = t c (two
-// reciprocal square roots, no division).
+// with q = 1 / sqrt(h): c = h q, |s| = |t| c = |apq| rho q (h q^2 = 1), and
+// |t apq| = apq^2 rho q^2, the sign of t being that of (aqq - app) apq (two reciprocal
+// square roots, no division; after q, one product for c and s and a product and a fused
+// multiply-add for the diagonal: the chain that bounds a round).
 __device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double &c, double &s,
                                                 double &dp, double &dq) {
   c = 1.0;
@@ -1047,15 +1057,16 @@ __device__ __forceinline__ void jacobi_rotation(double app, double aqq, double a
   dq = aqq;
   if (apq == 0.0) return;
   const double dd = aqq - app;
-  const double rho = rsqrt(fma(dd, dd, 4.0 * apq * apq));
+  const double rho = rsqrt_fast(fma(dd, dd, 4.0 * apq * apq));
   const double h = fma(0.5 * fabs(dd), rho, 0.5);
-  const double q = rsqrt(h);
-  const double at = fabs(apq) * rho * (q * q);
-  const double tt = (dd >= 0.0) == (apq >= 0.0) ? at : -at;
+  const double q = rsqrt_fast(h);
+  const double ar = fabs(apq) * rho;
+  const double w = dd >= 0.0 ? -(fabs(apq) * ar) : fabs(apq) * ar;   // -t apq / q^2
+  const double q2 = q * q;
   c = h * q;
-  s = tt * c;
-  dp = app - tt * apq;
-  dq = aqq + tt * apq;
+  s = (dd >= 0.0) == (apq >= 0.0) ? ar * q : -(ar * q);
+  dp = fma(w, q2, app);
+  dq = fma(-w, q2, aqq);
 }
 
 template <int NT>
