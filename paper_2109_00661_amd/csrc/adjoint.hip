@@ -218,7 +218,7 @@ struct AdjShared1 {
 // particle j (workgroups renumbered XCD-contiguous).
 template <int LMAX>
 // The 12- and 16-layer instantiations are held to two waves per SIMD: some registers
-// spill to private memory (176 and 400 bytes per lane), and both still run faster than at
+// spill to private memory (192 and 408 bytes per lane), and both still run faster than at
 // one wave per SIMD without spills.  The 8-layer one fits two waves without spills
 // unconstrained; the same attribute on it (the allocation differs) was 6% slower, and
 // held to three waves per SIMD (320 bytes of spills) 5% slower.

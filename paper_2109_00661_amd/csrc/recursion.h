@@ -50,6 +50,17 @@ __device__ __forceinline__ void step_up(cplx<T> &N, cplx<T> &D, cplx<T> a, cplx<
   N = P - Q;
   D = P + Q;
 }
+// The same step at the air interface, where a = lam is real (two products fewer: a zero
+// imaginary part would still be multiplied out, since 0 x is not folded without
+// fast-math; the results are the same).
+template <typename T>
+__device__ __forceinline__ void step_up(cplx<T> &N, cplx<T> &D, T a, cplx<T> b, cplx<T> E) {
+  const cplx<T> NE = N * E;
+  const cplx<T> S = D + NE, Tm = D - NE;
+  const cplx<T> P = a * S, Q = b * Tm;
+  N = P - Q;
+  D = P + Q;
+}
 
 // The same step with R = dk / B, dk = a^2 - b^2 = k2_above - k2_below (lam^2 cancels
 // exactly) and B = (a + b)^2:
@@ -117,7 +128,7 @@ __device__ __forceinline__ T reflection_im(T lam, const cplx<T> *k2, const cplx<
     if (kRatio)   // air interface: lam^2 - u_0^2 = -k2_0
       step_ratio(N, D, cplx<T>{-k2[0].re, -k2[0].im}, csq(cplx<T>{lam + ub.re, ub.im}), E0);
     else
-      step_up(N, D, cplx<T>{lam, T(0)}, ub, E0);
+      step_up(N, D, lam, ub, E0);
   }
   return (N.im * D.re - N.re * D.im) * fast_rcp(D.re * D.re + D.im * D.im);
 }
