@@ -124,26 +124,11 @@ constexpr double kPio2A = 0x1.921fb54442d18p+0;
 constexpr double kInvFact[7] = {1.0, 1.0, 1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0};
 }  // namespace detail
 
-// exp(z) for the propagation factors in FP64, Re z <= 0, with two tables in LDS:
-// phase[j] = (cos, sin)(j pi/128) and e2[j] = 2^(j/256), j = 0..255.  With
-//   k = round(256 x / ln 2), r = x - k ln2/256 (|r| <= ln2/512),
-//   j = round(128 y / pi),   d = y - j pi/128  (|d| <= pi/256),
-//   exp(x + iy) = 2^floor(k/256) e2[k mod 256] e^r phase[j mod 256] (cos d + i sin d),
-// and Taylor polynomials of degree 4 (e^r), 5 (sin d) and 6 (cos d), whose remainders
-// are below 4e-17, 9e-18 and 2e-20.  ln 2 and pi/2 enter the reductions as one double
-// each: their rounding errors (2.3e-17 and 6.1e-17), times k/256 and j/64, put r and d
-// off by at most 3.4e-17 |x| and 3.9e-17 |y|, so the relative error of exp(z) is a few
-// ulp plus 4e-17 (|x| + |y|): a few ulp while |z| is of order one, 1.6e-15 at |z| = 40,
-// where a propagation factor exp(-2 h u) is below 3e-7 (|Im u| <= 2.5 Re u for every
-// Cole-Cole layer with m <= 1, so |y| <= 2.5 |x|), and 4e-14 at the clamp below.  k and
-// j are rounded by adding 1.5 2^52, which leaves them as integers in the low word.
-// Re z < -1000 gives 0; a NaN real part is clamped too (the recursion still propagates
-// it through u), a NaN imaginary part gives NaN.
-// 1/6 and 1/24, the two constants the polynomials below share.  Each of three polynomial
+// 1/6 and 1/24, the two constants the polynomials of cexp_tab share.  Each of three polynomial
 // steps has two constants that are not inline operands, and an instruction takes at most
 // one from a scalar register, so the other is copied into a vector register at every
 // evaluation unless it already lives in one: exp_consts() puts both there, opaque to the
-// compiler, so that a loop of evaluations keeps them (two registers pairs) instead.
+// compiler, so that a loop of evaluations keeps them (two register pairs) instead.
 struct ExpConsts {
   double c6, c24;
 };
@@ -153,6 +138,23 @@ __device__ __forceinline__ ExpConsts exp_consts() {
   return {c6, c24};
 }
 
+// exp(z) for the propagation factors in FP64, Re z <= 0, with two tables in LDS:
+// phase[j] = (cos, sin)(j pi/128) and e2[j] = 2^(j/256), j = 0..255.  With
+//   k = round(256 x / ln 2), r = x - k ln2/256 (|r| <= ln2/512),
+//   j = round(128 y / pi),   d = y - j pi/128  (|d| <= pi/256),
+//   exp(x + iy) = 2^floor(k/256) e2[k mod 256] e^r phase[j mod 256] (cos d + i sin d),
+// and Taylor polynomials of degree 4 (e^r), 5 (sin d) and 6 (cos d), whose remainders
+// are below 4e-17, 9e-18 and 2e-20.  ln 2 and pi/2 enter the reductions as one double
+// each: their rounding errors (2.3e-17 and 6.1e-17), times k/256 and j/64, put r and d
+// off by at most 3.4e-17 |x| and 3.9e-17 |y|, so the relative error of exp(z) is a few
+// ulp plus 4e-17 (|x| + |y|) <= 6e-17 |z|: a few ulp while |z| is of order one, 2.3e-15
+// at |z| = 40, where a propagation factor exp(-2 h u) is below 4e-7 (|Im u| <= 2.5 Re u
+// for every Cole-Cole layer with m <= 1, so |y| <= 2.5 |x|), and 1.4e-13 at the clamp
+// below (|x| = 1000, |y| <= 2500), where it is below e^-1000.  k and
+// j are rounded by adding 1.5 2^52, which leaves them as integers in the low word.
+// Re z < -1000 gives 0; a NaN real part is clamped too (the recursion still propagates
+// it through u), a NaN imaginary part gives NaN.  kc: the shared polynomial constants
+// (from exp_consts() where the call sits in a loop).
 __device__ __forceinline__ cplx<double> cexp_tab(cplx<double> z, const cplx<double> *phase,
                                                  const double *e2,
                                                  ExpConsts kc = {detail::kInvFact[3], detail::kInvFact[4]}) {
