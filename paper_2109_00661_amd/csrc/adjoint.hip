@@ -3,8 +3,9 @@
 // One wavefront per particle, lanes tiling (frequency, filter abscissa) as in the
 // forward kernel, and every (frequency, abscissa) pair visited once.  Per pair the lane
 // runs the projective reflection recursion bottom-up, keeping the state (N_l, D_l) of
-// every interface in a per-lane array held in registers (the layer loops unrolled over
-// the instantiation's capacity: 4, 8, 12 or 16 merged layers; at 12 and 16 a few values
+// every interface (of every even one at 12 and 16 layers, the odd ones rebuilt on the
+// way back) in a per-lane array held in registers (the layer loops unrolled over the
+// instantiation's capacity: 4, 8, 12 or 16 merged layers; at 12 and 16 a few values
 // spill at two waves per SIMD); the same recursion gives Im r_TE for the Hankel sum.
 // It then sweeps top-down through the surface and every interface, propagating the
 // adjoint of c_k Im r (the reverse sweep is linear in its seed, so the filter coefficient
@@ -59,14 +60,18 @@ __device__ __forceinline__ cplx<double> csqrt_hm(cplx<double> z, double &hm) {
 
 // Adds the adjoints of one (lam, w) pair with seed wt (the weight of Im r) to
 // G[l] (d(wt r)/d k2_l) and H[l] (Im d(wt r)/d h_l).  The bottom-up pass is the forward's
-// projective recursion (step_up), keeping the state (N_l, D_l) of every interface; the
+// projective recursion (step_up), keeping the state (N_l, D_l) of the interfaces; the
 // top-down pass applies the adjoint of each step: for N' = a S - b T, D' = a S + b T,
 // S = D + N E, T = D - N E and output adjoints N'~, D'~,
 //   P~ = N'~ + D'~,  Q~ = D'~ - N'~,  a~ += P~ S,  b~ += Q~ T,
 //   S~ = P~ a,  T~ = Q~ b,  D~ = S~ + T~,  N~ = (S~ - T~) E,  E~ = (S~ - T~) N,
 // with E = exp(h2 u) (h2 = -2 h): u~ += E~ h2 E and h~ = -2 u E~ E.  The seed is
 // N~ = wt / D, D~ = -N~ N / D at the surface, and u_l = sqrt(lam^2 + k2_l) gives
-// k2_l~ += u_l~ / (2 u_l).  One complex reciprocal per pair, and 1/(2 u_l) per layer:
+// k2_l~ += u_l~ / (2 u_l).  The 12- and 16-layer instantiations keep the states of the
+// even interfaces only and rebuild an odd one, when the top-down pass reaches it, by one
+// step up from the state below it (the u and E of that step are the next step's, so
+// they are formed once): half the registers for the states, for one step up per two
+// layers.  One complex reciprocal per pair, and 1/(2 u_l) per layer:
 // the 12- and 16-layer instantiations take it from the square root's own 1/(2|u_l|^2)
 // (two products; 3% faster there), the smaller ones form a complex reciprocal at the
 // point of use (one register pair fewer through the sweep keeps them within 256 VGPRs
@@ -82,6 +87,7 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
   constexpr int NI = LMAX - 1;           // interfaces below the surface
   cplx<double> Ns[NI], Ds[NI];           // projective reflection state below interface l
   constexpr bool kHm = LMAX >= 12;
+  constexpr bool kCkpt = LMAX >= 12;     // interface states of even interfaces only
   auto u_of = [&](int l) { return csqrt_fast(cplx<double>{lam2 + k2[l].re, k2[l].im}); };
   auto u_hm = [&](int l, double &hm) { return csqrt_hm(cplx<double>{lam2 + k2[l].re, k2[l].im}, hm); };
   auto half_rcp = [](cplx<double> u, double hm) {   // 1/(2u); hm is unused (dead) unless kHm
@@ -117,8 +123,10 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
         step_up(N, D, u, ua, cexp_tab(cplx<double>{hh * ua.re, hh * ua.im}, phase, e2));
         ua = u;
       }
-      Ns[l] = N;
-      Ds[l] = D;
+      if (!kCkpt || (l & 1) == 0) {   // checkpointed: the even interfaces only
+        Ns[l] = N;
+        Ds[l] = D;
+      }
     }
   }
   // surface: a = lam, b = u_0
@@ -149,16 +157,44 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
   }
   ua = u0;
   double hma = 0.5 * fast_rcp(u0.re * u0.re + u0.im * u0.im);   // 1/(2|u_l|^2) (kHm)
+  // checkpointed: u, 1/(2|u|^2) and E of the layer below an odd interface, formed while
+  // rebuilding that interface's state and taken over by the next step
+  cplx<double> cu = {0.0, 0.0}, cE = {0.0, 0.0};
+  double chm = 0.0;
 #pragma unroll
   for (int l = 0; l < NI - 1; ++l) {
     if (l < L - 2) {
       // the step that made state l from state l + 1: a = u_l, b = u_{l+1}, E_{l+1}
       double hmb;
-      const cplx<double> ub = u_hm(l + 1, hmb);
+      cplx<double> ub, E;
       const double hh = h2v[l + 1];
-      const cplx<double> E = cexp_tab(cplx<double>{hh * ub.re, hh * ub.im}, phase, e2);
-      const cplx<double> NE = Ns[l + 1] * E;
-      const cplx<double> S = Ds[l + 1] + NE, T = Ds[l + 1] - NE;
+      if (kCkpt && (l & 1)) {
+        ub = cu;
+        hmb = chm;
+        E = cE;
+      } else {
+        ub = u_hm(l + 1, hmb);
+        E = cexp_tab(cplx<double>{hh * ub.re, hh * ub.im}, phase, e2);
+      }
+      cplx<double> N1, D1;               // the state below interface l + 1
+      if (!kCkpt || ((l + 1) & 1) == 0) {
+        N1 = Ns[l + 1];
+        D1 = Ds[l + 1];
+      } else {
+        cu = u_hm(l + 2, chm);
+        if (l + 1 < L - 2) {             // one step up from the stored state below
+          const double h2 = h2v[l + 2];
+          cE = cexp_tab(cplx<double>{h2 * cu.re, h2 * cu.im}, phase, e2);
+          N1 = Ns[l + 2];
+          D1 = Ds[l + 2];
+          step_up(N1, D1, ub, cu, cE);
+        } else {                         // the deepest interface
+          N1 = k2[l + 1] - k2[l + 2];
+          D1 = csq(ub + cu);
+        }
+      }
+      const cplx<double> NE = N1 * E;
+      const cplx<double> S = D1 + NE, T = D1 - NE;
       const cplx<double> Pb = Nb + Db, Qb = Db - Nb;
       uab = uab + Pb * S;
       G[l] = G[l] + uab * half_rcp(ua, hma);                       // u_l complete
@@ -166,7 +202,7 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
       Db = Sb + Tb;
       const cplx<double> NEb = Sb - Tb;
       Nb = NEb * E;
-      const cplx<double> EbE = (NEb * Ns[l + 1]) * E;
+      const cplx<double> EbE = (NEb * N1) * E;
       uab = Qb * T + hh * EbE;
       H[l + 1] += -2.0 * (EbE * ub).im;
       ua = ub;
@@ -175,7 +211,13 @@ __device__ __forceinline__ void pair_adjoint(double lam, const cplx<double> *k2,
   }
   // the deepest interface: N = k2_{L-2} - k2_{L-1}, D = (u_{L-2} + u_{L-1})^2
   double hml;
-  const cplx<double> ul = u_hm(L - 1, hml);
+  cplx<double> ul;
+  if (kCkpt && (L & 1)) {                // L - 2 odd: formed with the deepest state
+    ul = cu;
+    hml = chm;
+  } else {
+    ul = u_hm(L - 1, hml);
+  }
   const cplx<double> sb = Db * (2.0 * (ua + ul));
   const cplx<double> g0 = Nb + (uab + sb) * half_rcp(ua, hma), g1 = sb * half_rcp(ul, hml) - Nb;
 #pragma unroll
@@ -218,8 +260,9 @@ struct AdjShared1 {
 // particle j (workgroups renumbered XCD-contiguous).
 template <int LMAX>
 // The 12- and 16-layer instantiations are held to two waves per SIMD: some registers
-// spill to private memory (192 and 408 bytes per lane), and both still run faster than at
-// one wave per SIMD without spills.  The 8-layer one fits two waves without spills
+// spill to private memory (160 and 320 bytes per lane, with the checkpointed interface
+// states; 192 and 408 with every state kept), and both still run faster than at one wave
+// per SIMD without spills.  The 8-layer one fits two waves without spills
 // unconstrained; the same attribute on it (the allocation differs) was 6% slower, and
 // held to three waves per SIMD (320 bytes of spills) 5% slower.
 __global__ __launch_bounds__(kWave * kWavesA) __attribute__((amdgpu_waves_per_eu(LMAX >= 12 ? 2 : 1))) void loglik_grad1_kernel(DevSystem s, DevParticles p, int kc, int km,
