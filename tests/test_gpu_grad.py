@@ -66,11 +66,15 @@ def test_grad_merged_five_layer(B, system, K_oracle, truth_data):
 
 
 def test_grad_decoupled_up_to_fifteen_layers(B, K_oracle, truth_data):
+    """The 16-layer instantiation (a capacity-15 context without a workspace: one launch)
+    on every merged-layer count from the half-space to 15 layers, odd and even (its
+    top-down pass rebuilds the odd interfaces' states)."""
     from oracle import em
     system = W.system(kmax_cond=7, kmax_charg=7)
     ctx = B.Context(system, precision="f64")
-    p = W.decoupled_population(13, 7, 7, seed=3, min_sep=1.0)
-    p["kappa"][0], p["lambda_"][0] = 0, 0                 # half-space
+    nl = np.arange(1, 16)                                  # merged layers 1 .. 15
+    kap = np.minimum(nl - 1, 7)
+    p = W.decoupled_population(15, 7, 7, seed=3, min_sep=1.0, kappa=kap, lam=nl - 1 - kap)
     ll, g, llp = _grad_gpu(B, ctx, p, truth_data)
     np.testing.assert_allclose(ll, llp, rtol=LL_CONSISTENCY, atol=0)
     ll_o, g_o = em.loglik_grad(p, system, K_oracle, truth_data)
