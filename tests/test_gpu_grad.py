@@ -99,6 +99,51 @@ def test_grad_decoupled_register_path(B, K_oracle, truth_data, kmax):
     _check_against_oracle(p, ll, g, ll_o, g_o)
 
 
+def _largest_system():
+    """64 frequencies, a 256-point filter and 32 gates, the largest sizes the context
+    accepts (the filter is the 120-point table resampled; any table serves parity)."""
+    s = W.system(kmax_cond=7, kmax_charg=7)
+    s["freq_hz"] = 10.0 ** (6.0 * np.arange(64) / 63)
+    ng = 32
+    centres = 10.0 ** (-5.0 + 3.0 * np.arange(ng) / (ng - 1))
+    half = 10.0 ** (1.5 / (ng - 1))
+    s["gate_open_s"], s["gate_close_s"] = centres / half, centres * half
+    s["eps_an"] = np.full(ng, s["eps_an"][0])
+    b, w = s["hankel_b"], s["hankel_w"]
+    b2 = np.geomspace(b.min(), b.max(), 256)
+    s["hankel_b"], s["hankel_w"] = b2, np.interp(np.log(b2), np.log(b), w) * (len(b) / 256.0)
+    return s
+
+
+def test_grad_largest_system(B):
+    """The largest system: the 16-layer instantiation folds each round's eight slot
+    vectors into 32 gates' sums over eight rounds of frequencies, and the 8-layer one
+    keeps all 64 frequencies' slot vectors (its largest LDS), both against the oracle."""
+    import warnings
+    from oracle import em
+    s = _largest_system()
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        K = em.make_K(s)
+    d = em.forward(W.truth_three_layer(), s, K)[0]
+    nl = np.array([15, 14, 9, 8, 3, 1])
+    kap = np.minimum(nl - 1, 7)
+    p = W.decoupled_population(6, 7, 7, seed=5, min_sep=1.0, kappa=kap, lam=nl - 1 - kap)
+    ll_o, g_o = em.loglik_grad(p, s, K, d)
+    ctx = B.Context(s, precision="f64")                   # capacity 15: the 16-layer one
+    ll, g, llp = _grad_gpu(B, ctx, p, d)
+    np.testing.assert_allclose(ll, llp, rtol=LL_CONSISTENCY, atol=0)
+    _check_against_oracle(p, ll, g, ll_o, g_o)
+    # up to 8 merged layers in a capacity-8 context: the 8-layer instantiation
+    s8 = dict(s, kmax_cond=4, kmax_charg=3)
+    q = W.decoupled_population(4, 4, 3, seed=6, min_sep=1.0, kappa=np.array([4, 3, 1, 0]),
+                               lam=np.array([3, 1, 2, 0]))
+    ll_o, g_o = em.loglik_grad(q, s8, K, d)
+    ll, g, llp = _grad_gpu(B, B.Context(s8, precision="f64"), q, d)
+    np.testing.assert_allclose(ll, llp, rtol=LL_CONSISTENCY, atol=0)
+    _check_against_oracle(q, ll, g, ll_o, g_o)
+
+
 def test_grad_same_particles_under_both_capacities(B, truth_data):
     """The 8-layer instantiation and the 16-layer one (a capacity-15 context without a
     workspace) give the same log-likelihood and gradient for the same particles (to
